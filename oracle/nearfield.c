@@ -1,0 +1,224 @@
+/*
+ * Near-field fixture of the oracle (TEST INFRASTRUCTURE ONLY).
+ *
+ * The weak-form path evaluates regular (vertex-disjoint) triangle pairs only;
+ * the paper hands identical and adjacent pairs to a separate singular scheme
+ * (Section 3.2.3).  The closed-form checks on the unit sphere (the sum of the
+ * single-layer matrix, its spectrum, the double-layer identity) need every
+ * pair, so this file supplies a semi-analytic P0 value for near pairs:
+ *
+ *   inner integral over the flat trial triangle in closed form,
+ *     single layer:  int_T 1/|x-y| dy          (potential of a uniform flat
+ *                    triangle, Wilton et al. 1984 / Graglia 1993),
+ *     double layer:  int_T (x-y).n_y/|x-y|^3 dy = -Omega(x), Omega the signed
+ *                    solid angle of Van Oosterom & Strackee (1983),
+ *   outer integral over the test triangle with the 6-point rule applied on
+ *   4^L congruent sub-triangles.
+ *
+ * It is never compared against the product; it only serves the closed-form
+ * pins of the oracle's regular entries.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#include "orc_internal.h"
+
+static const double NF_PI = 3.14159265358979323846264338327950288;
+
+static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* int_T 1/|x - y| dy for the flat triangle (v0, v1, v2). */
+double orc_tri_potential(const double *v0, const double *v1, const double *v2, const double *x)
+{
+    const double *v[3] = {v0, v1, v2};
+    double e1[3], e2[3], N[3], n[3], xv0[3], rho[3];
+    sub3(v1, v0, e1);
+    sub3(v2, v0, e2);
+    cross3(e1, e2, N);
+    double nn = sqrt(dot3(N, N));
+    for (int d = 0; d < 3; ++d) n[d] = N[d] / nn;
+    sub3(x, v0, xv0);
+    double h = dot3(xv0, n);
+    double ah = fabs(h);
+    for (int d = 0; d < 3; ++d) rho[d] = x[d] - h * n[d];
+    double sum = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double *pm = v[i], *pp = v[(i + 1) % 3];
+        double s[3], m[3], a[3], b[3];
+        sub3(pp, pm, s);
+        double L = sqrt(dot3(s, s));
+        for (int d = 0; d < 3; ++d) s[d] /= L;
+        cross3(s, n, m); /* in-plane outward normal of the edge */
+        sub3(pp, rho, a);
+        sub3(pm, rho, b);
+        double lp = dot3(a, s), lm = dot3(b, s);
+        double t0 = dot3(b, m);
+        double R0sq = t0 * t0 + h * h;
+        double Rp = sqrt(R0sq + lp * lp), Rm = sqrt(R0sq + lm * lm);
+        if (fabs(t0) > 0.0) {
+            double lg;
+            if (lp + lm >= 0.0)
+                lg = log((Rp + lp) / (Rm + lm));
+            else
+                lg = log((Rm - lm) / (Rp - lp));
+            sum += t0 * lg;
+        }
+        if (ah > 0.0)
+            sum -= ah * (atan(t0 * lp / (R0sq + ah * Rp)) - atan(t0 * lm / (R0sq + ah * Rm)));
+    }
+    return sum;
+}
+
+/* Signed solid angle of the triangle seen from x; positive when x lies on the
+ * side opposite to (v1-v0) x (v2-v0). */
+double orc_tri_solid_angle(const double *v0, const double *v1, const double *v2, const double *x)
+{
+    double a[3], b[3], c[3], bc[3];
+    sub3(v0, x, a);
+    sub3(v1, x, b);
+    sub3(v2, x, c);
+    double la = sqrt(dot3(a, a)), lb = sqrt(dot3(b, b)), lc = sqrt(dot3(c, c));
+    cross3(b, c, bc);
+    double num = dot3(a, bc);
+    double den = la * lb * lc + dot3(a, b) * lc + dot3(a, c) * lb + dot3(b, c) * la;
+    return 2.0 * atan2(num, den);
+}
+
+/* 6-point rule on 4^level congruent sub-triangles of the reference triangle.
+ * Returns the number of points (6 * 4^level); weights sum to 1/2. */
+int orc_subdivided_rule(int level, double *xi, double *eta, double *w)
+{
+    double qx[6], qe[6], qw[6];
+    orc_rule(6, qx, qe, qw);
+    int ntri = 1;
+    for (int l = 0; l < level; ++l) ntri *= 4;
+    double *T = (double *)malloc(sizeof(double) * 6 * ntri);
+    double *U = (double *)malloc(sizeof(double) * 6 * ntri);
+    T[0] = 0; T[1] = 0; T[2] = 1; T[3] = 0; T[4] = 0; T[5] = 1;
+    int cur = 1;
+    for (int l = 0; l < level; ++l) {
+        for (int t = 0; t < cur; ++t) {
+            double *P = T + 6 * t;
+            double m01[2] = {0.5 * (P[0] + P[2]), 0.5 * (P[1] + P[3])};
+            double m12[2] = {0.5 * (P[2] + P[4]), 0.5 * (P[3] + P[5])};
+            double m20[2] = {0.5 * (P[4] + P[0]), 0.5 * (P[5] + P[1])};
+            double sub[4][6] = {
+                {P[0], P[1], m01[0], m01[1], m20[0], m20[1]},
+                {m01[0], m01[1], P[2], P[3], m12[0], m12[1]},
+                {m20[0], m20[1], m12[0], m12[1], P[4], P[5]},
+                {m12[0], m12[1], m20[0], m20[1], m01[0], m01[1]},
+            };
+            memcpy(U + 24 * t, sub, sizeof(sub));
+        }
+        cur *= 4;
+        double *tmp = T; T = U; U = tmp;
+    }
+    double scale = 1.0 / (double)ntri;
+    int k = 0;
+    for (int t = 0; t < ntri; ++t) {
+        double *P = T + 6 * t;
+        for (int p = 0; p < 6; ++p, ++k) {
+            xi[k] = P[0] + qx[p] * (P[2] - P[0]) + qe[p] * (P[4] - P[0]);
+            eta[k] = P[1] + qx[p] * (P[3] - P[1]) + qe[p] * (P[5] - P[1]);
+            w[k] = qw[p] * scale;
+        }
+    }
+    free(T);
+    free(U);
+    return 6 * ntri;
+}
+
+/* Semi-analytic P0 entry for one pair (test i, trial j), Laplace single or
+ * double layer.  xi/eta/w: an outer rule on the reference triangle. */
+static double nf_entry(const orc_mesh *m, int op, int64_t i, int64_t j, int npts,
+                       const double *xi, const double *eta, const double *w)
+{
+    const double *a = m->xyz + 3 * m->tri[3 * i], *b = m->xyz + 3 * m->tri[3 * i + 1],
+                 *c = m->xyz + 3 * m->tri[3 * i + 2];
+    const double *u0 = m->xyz + 3 * m->tri[3 * j], *u1 = m->xyz + 3 * m->tri[3 * j + 1],
+                 *u2 = m->xyz + 3 * m->tri[3 * j + 2];
+    double s = 0.0;
+    for (int p = 0; p < npts; ++p) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = a[d] + xi[p] * (b[d] - a[d]) + eta[p] * (c[d] - a[d]);
+        double inner;
+        if (op == ORC_LAPLACE_SLP) {
+            inner = orc_tri_potential(u0, u1, u2, x) / (4.0 * NF_PI);
+        } else {
+            /* (x - y).n_y vanishes identically when x lies in the plane of the
+             * trial triangle (the identical pair, coplanar neighbours); the
+             * solid-angle formula would return the one-sided limit +-2 pi. */
+            double xu[3];
+            sub3(x, u0, xu);
+            double hgt = dot3(xu, m->n + 3 * j);
+            double scale = sqrt(m->J[j]);
+            inner = fabs(hgt) <= 1e-12 * scale ? 0.0 : -orc_tri_solid_angle(u0, u1, u2, x) / (4.0 * NF_PI);
+        }
+        s += w[p] * inner;
+    }
+    return m->J[i] * s;
+}
+
+double orc_nearfield_entry(const orc_mesh *m, int op, int64_t i, int64_t j, int level)
+{
+    int np = 6;
+    for (int l = 0; l < level; ++l) np *= 4;
+    double *xi = (double *)malloc(sizeof(double) * np * 3);
+    double *eta = xi + np, *w = xi + 2 * np;
+    orc_subdivided_rule(level, xi, eta, w);
+    double v = nf_entry(m, op, i, j, np, xi, eta, w);
+    free(xi);
+    return v;
+}
+
+/* Full nt x nt P0 matrix of the Laplace single (op 0) or double (op 1) layer:
+ * pairs whose centroids are closer than near_dist, or that share a vertex,
+ * take the semi-analytic value; all other pairs the regular oracle value.
+ * Row-major output. */
+int orc_p0_matrix_with_nearfield(const orc_mesh *m, int op, double near_dist, int level, double *out)
+{
+    if (op != ORC_LAPLACE_SLP && op != ORC_LAPLACE_DLP) return ORC_E_ARG;
+    int np = 6;
+    for (int l = 0; l < level; ++l) np *= 4;
+    double *xi = (double *)malloc(sizeof(double) * np * 3);
+    double *eta = xi + np, *w = xi + 2 * np;
+    orc_subdivided_rule(level, xi, eta, w);
+    const int64_t nt = m->nt;
+    double *cen = (double *)malloc(sizeof(double) * 3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int d = 0; d < 3; ++d)
+            cen[3 * t + d] = (m->xyz[3 * m->tri[3 * t] + d] + m->xyz[3 * m->tri[3 * t + 1] + d] +
+                              m->xyz[3 * m->tri[3 * t + 2] + d]) / 3.0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t i = 0; i < nt; ++i) {
+        for (int64_t j = 0; j < nt; ++j) {
+            double dd[3];
+            sub3(cen + 3 * i, cen + 3 * j, dd);
+            double dist = sqrt(dot3(dd, dd));
+            if (dist < near_dist || orc_adjacent(m, i, j)) {
+                out[i * nt + j] = nf_entry(m, op, i, j, np, xi, eta, w);
+            } else {
+                double re, im;
+                orc_pair(m, op, 0.0, i, j, -1, -1, &re, &im);
+                out[i * nt + j] = re;
+            }
+        }
+    }
+    free(cen);
+    free(xi);
+    return ORC_OK;
+}

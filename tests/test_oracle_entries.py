@@ -1,0 +1,276 @@
+"""Pins of the oracle's Galerkin entries (Eqs. slp, dlp over regular pairs).
+
+Independent references used here:
+  * brute force: a tensor Gauss-Legendre rule on the Duffy-collapsed square
+    (numpy, 20 points per direction), i.e. a different discretisation of the
+    same 4-D integral; the oracle's 6-point result must converge to it as the
+    separation grows, at the rate of a degree-4 rule;
+  * the far-field limit A_ij -> |T_i| |T_j| K(c_i, c_j);
+  * invariants: symmetry of the single layer, the P1/P0 partition of unity,
+    scaling, rigid motions, the near-pair policy.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+RNG = np.random.Generator(np.random.PCG64(3))
+
+
+def gl01(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def duffy_points(a, b, c, n=20):
+    """Points, weights (including the area Jacobian) and barycentric coords."""
+    u, wu = gl01(n)
+    v, wv = gl01(n)
+    U, V = np.meshgrid(u, v, indexing="ij")
+    W = np.outer(wu, wv) * (1.0 - U)
+    xi = U.ravel()
+    eta = ((1.0 - U) * V).ravel()
+    J = np.linalg.norm(np.cross(b - a, c - a))
+    pts = a + xi[:, None] * (b - a) + eta[:, None] * (c - a)
+    lam = np.stack([1.0 - xi - eta, xi, eta], axis=1)
+    return pts, J * W.ravel(), lam
+
+
+def brute_pair(op, k, A, B, a_loc=None, b_loc=None, n=20):
+    """int_A int_B psi(x) K(x,y) phi(y) by the Duffy/Gauss-Legendre rule."""
+    xp, xw, xl = duffy_points(*A, n=n)
+    yp, yw, yl = duffy_points(*B, n=n)
+    if a_loc is not None:
+        xw = xw * xl[:, a_loc]
+    if b_loc is not None:
+        yw = yw * yl[:, b_loc]
+    ny = np.cross(B[1] - B[0], B[2] - B[0])
+    ny /= np.linalg.norm(ny)
+    d = xp[:, None, :] - yp[None, :, :]
+    r = np.linalg.norm(d, axis=2)
+    g = np.exp(1j * k * r) / (4 * math.pi * r)
+    if op in (O.LAPLACE_DLP, O.HELMHOLTZ_DLP):
+        g = g * (1.0 - 1j * k * r) * (d @ ny) / (r * r)
+    val = np.einsum("i,ij,j->", xw, g, yw)
+    return val if op in (O.HELMHOLTZ_SLP, O.HELMHOLTZ_DLP) else val.real
+
+
+def two_triangle_mesh(A, B):
+    xyz = np.vstack([A, B])
+    tri = np.array([[0, 1, 2], [3, 4, 5]], dtype=np.int32)
+    return xyz, tri
+
+
+def rotation(rng):
+    q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    return q
+
+
+T1 = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.3, 0.8, 0.0]])
+T2_LOCAL = np.array([[0.0, 0.0, 0.0], [0.7, 0.1, 0.2], [0.1, 0.9, -0.4]])
+DIR = np.array([0.6, -0.48, 0.64])
+
+
+def placed_pair(d):
+    B = T2_LOCAL + d * DIR
+    return T1, B
+
+
+@pytest.mark.parametrize("op", [O.LAPLACE_SLP, O.LAPLACE_DLP])
+def test_far_field_limit_laplace(op):
+    errs = []
+    for d in (40.0, 80.0, 160.0):
+        A, B = placed_pair(d)
+        errs.append(abs(entry(op, 0.0, A, B) / centroid_value(op, 0.0, A, B) - 1.0))
+    assert errs[0] < 2e-3
+    # second-order approach to the centroid limit
+    assert errs[1] < errs[0] / 3.0 and errs[2] < errs[1] / 3.0
+
+
+@pytest.mark.parametrize("op", [O.HELMHOLTZ_SLP, O.HELMHOLTZ_DLP])
+def test_far_field_limit_helmholtz(op):
+    """Small triangles (k h = 0.017) far apart (k d ~ 68): the entry tends to
+    the centroid value, phase exp(+i k |c_i - c_j|) included."""
+    k = 1.7
+    for d in (40.0, 55.0):
+        A = T1 * 0.01
+        B = T2_LOCAL * 0.01 + d * DIR
+        e = entry(op, k, A, B)
+        c = centroid_value(op, k, A, B)
+        assert abs(e / c - 1.0) < 1e-3
+        # the opposite time convention is far off
+        assert abs(np.conj(e) / c - 1.0) > 0.1
+
+
+def entry(op, k, A, B):
+    m = O.OracleMesh(*two_triangle_mesh(A, B), 6)
+    return m.entries(op, O.P0, k, [0], [1])[0, 0]
+
+
+def centroid_value(op, k, A, B):
+    cA, cB = A.mean(0), B.mean(0)
+    areaA = 0.5 * np.linalg.norm(np.cross(A[1] - A[0], A[2] - A[0]))
+    nB = np.cross(B[1] - B[0], B[2] - B[0])
+    areaB = 0.5 * np.linalg.norm(nB)
+    return areaA * areaB * O.kernel(op, k, cA, cB, nB / np.linalg.norm(nB))
+
+
+@pytest.mark.parametrize("op", [O.LAPLACE_SLP, O.LAPLACE_DLP])
+def test_brute_force_convergence_laplace(op):
+    errs = []
+    for d in (2.0, 4.0, 8.0, 16.0, 32.0):
+        A, B = placed_pair(d)
+        ref = brute_pair(op, 0.0, A, B)
+        errs.append(abs(entry(op, 0.0, A, B) - ref) / abs(ref))
+    # degree-4 tensor rule: the relative error falls ~2^5 per doubling of d
+    assert errs[-1] < 1e-10
+    for e0, e1 in zip(errs[1:], errs[2:]):
+        assert e1 < e0 / 16.0
+
+
+@pytest.mark.parametrize("op", [O.HELMHOLTZ_SLP, O.HELMHOLTZ_DLP])
+def test_brute_force_helmholtz(op):
+    """At k h ~ 2 the 6-point rule errs by ~3e-5 at any distance; a wrong
+    phase sign or a dropped (1 - i k r) factor errs by O(1)."""
+    k = 2.0
+    for d in (4.0, 8.0):
+        A, B = placed_pair(d)
+        ref = brute_pair(op, k, A, B)
+        got = entry(op, k, A, B)
+        assert abs(got - ref) < 1e-4 * abs(ref)
+        assert abs(np.conj(got) - ref) > 0.05 * abs(ref)
+        if op == O.HELMHOLTZ_DLP:
+            ny = np.cross(B[1] - B[0], B[2] - B[0])
+            # the same integrand without the (1 - i k r) factor
+            xp, xw, _ = duffy_points(*A)
+            yp, yw, _ = duffy_points(*B)
+            d_ = xp[:, None, :] - yp[None, :, :]
+            r = np.linalg.norm(d_, axis=2)
+            alt = np.einsum("i,ij,j->", xw, np.exp(1j * k * r) * (d_ @ (ny / np.linalg.norm(ny))) / (4 * math.pi * r ** 3), yw)
+            assert abs(got - alt) > 0.05 * abs(ref)
+
+
+def p1_brute(op, k, xyz, tri, m, I, J, rotate_test_basis=False):
+    ref = 0.0
+    for tA in np.flatnonzero((tri == I).any(1)):
+        for tB in np.flatnonzero((tri == J).any(1)):
+            if m.adjacent(int(tA), int(tB)):
+                continue
+            a_loc = int(np.flatnonzero(tri[tA] == I)[0])
+            if rotate_test_basis:
+                a_loc = (a_loc + 1) % 3
+            b_loc = int(np.flatnonzero(tri[tB] == J)[0])
+            ref = ref + brute_pair(op, k, xyz[tri[tA]], xyz[tri[tB]], a_loc, b_loc)
+    return ref
+
+
+@pytest.mark.parametrize("op,k", [(O.LAPLACE_SLP, 0.0), (O.LAPLACE_DLP, 0.0), (O.HELMHOLTZ_SLP, 1.3),
+                                  (O.HELMHOLTZ_DLP, 1.3)])
+def test_p1_entries_brute_force(op, k, ico):
+    """P1 entries between a vertex and vertices 3-5 edges away on a level-2
+    icosphere: within the 6-point rule's error of the brute-force integral,
+    and far from the value with the test hat function moved to another
+    corner of each triangle."""
+    xyz, tri = ico(2)
+    m = O.OracleMesh(xyz, tri, 6)
+    I = 0
+    dist = np.linalg.norm(xyz - xyz[I], axis=1)
+    Js = [int(j) for j in np.argsort(dist) if 0.8 < dist[j] < 1.6][:4]
+    assert Js
+    got = m.entries(op, O.P1, k, [I], Js)[0]
+    for J, g in zip(Js, got):
+        ref = p1_brute(op, k, xyz, tri, m, I, J)
+        assert abs(g - ref) <= 2e-4 * abs(ref), (J, g, ref)
+        wrong = p1_brute(op, k, xyz, tri, m, I, J, rotate_test_basis=True)
+        assert abs(wrong - ref) > 5e-3 * abs(ref)
+
+
+@pytest.mark.parametrize("op,k", [(O.LAPLACE_SLP, 0.0), (O.HELMHOLTZ_SLP, 3.0)])
+def test_single_layer_symmetric(op, k, ico):
+    xyz, tri = ico(2)
+    m = O.OracleMesh(xyz, tri, 6)
+    idx = np.arange(m.nt)
+    A = m.entries(op, O.P0, k, idx, idx)
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+    idx = np.arange(m.nv)
+    A = m.entries(op, O.P1, k, idx, idx)
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+
+
+@pytest.mark.parametrize("op", [O.LAPLACE_SLP, O.LAPLACE_DLP, O.HELMHOLTZ_DLP])
+def test_p1_partition_of_unity(op, ico):
+    """Hat functions sum to one on every triangle, so the sum of all P1
+    entries equals the sum of all P0 entries over the same regular pairs."""
+    xyz, tri = ico(1)
+    m = O.OracleMesh(xyz, tri, 6)
+    k = 2.5 if op == O.HELMHOLTZ_DLP else 0.0
+    p0 = m.entries(op, O.P0, k, np.arange(m.nt), np.arange(m.nt))
+    p1 = m.entries(op, O.P1, k, np.arange(m.nv), np.arange(m.nv))
+    assert abs(p1.sum() - p0.sum()) <= 1e-13 * np.abs(p0).sum()
+
+
+@pytest.mark.parametrize("space", [O.P0, O.P1])
+def test_scaling_laws(space, ico):
+    xyz, tri = ico(1)
+    s = 2.5
+    m1 = O.OracleMesh(xyz, tri, 6)
+    m2 = O.OracleMesh(s * xyz, tri, 6)
+    n = m1.nt if space == O.P0 else m1.nv
+    idx = np.arange(n)
+    for op, power in [(O.LAPLACE_SLP, 3), (O.LAPLACE_DLP, 2)]:
+        a = m1.entries(op, space, 0.0, idx, idx)
+        b = m2.entries(op, space, 0.0, idx, idx)
+        assert np.abs(b - s ** power * a).max() <= 1e-13 * np.abs(b).max()
+    # Helmholtz: (s mesh, k/s) = s^3 (mesh, k)
+    a = m1.entries(O.HELMHOLTZ_SLP, space, 4.0, idx, idx)
+    b = m2.entries(O.HELMHOLTZ_SLP, space, 4.0 / s, idx, idx)
+    assert np.abs(b - s ** 3 * a).max() <= 1e-13 * np.abs(b).max()
+
+
+def test_rigid_motion_invariance(ico):
+    xyz, tri = ico(1)
+    R = rotation(RNG)
+    moved = xyz @ R.T + np.array([1e3, -2e3, 5e2])
+    m1 = O.OracleMesh(xyz, tri, 6)
+    m2 = O.OracleMesh(moved, tri, 6)
+    idx = np.arange(m1.nt)
+    for op, k in [(O.LAPLACE_SLP, 0.0), (O.LAPLACE_DLP, 0.0), (O.HELMHOLTZ_DLP, 3.0)]:
+        a = m1.entries(op, O.P0, k, idx, idx)
+        b = m2.entries(op, O.P0, k, idx, idx)
+        assert np.abs(b - a).max() <= 1e-9 * np.abs(a).max()
+
+
+def test_near_policy(ico):
+    xyz, tri = ico(1)
+    m = O.OracleMesh(xyz, tri, 6)
+    nbr = [t for t in range(m.nt) if t != 0 and m.adjacent(0, t)]
+    far = [t for t in range(m.nt) if not m.adjacent(0, t)]
+    with pytest.raises(O.NearFieldError):
+        m.entries(O.LAPLACE_SLP, O.P0, 0.0, [0], [nbr[0]], near=O.NEAR_ERROR)
+    with pytest.raises(O.NearFieldError):
+        m.entries(O.LAPLACE_SLP, O.P0, 0.0, [0], [0], near=O.NEAR_ERROR)
+    a = m.entries(O.LAPLACE_SLP, O.P0, 0.0, [0], nbr + far[:3], near=O.NEAR_SKIP)
+    assert (a[0, :len(nbr)] == 0).all() and (a[0, len(nbr):] > 0).all()
+    b = m.entries(O.LAPLACE_SLP, O.P0, 0.0, [0], far[:3], near=O.NEAR_ERROR)
+    assert np.array_equal(a[0, len(nbr):], b[0])
+
+
+def test_icosphere_level3_regular_pair_count(ico):
+    """1280 triangles: 16,580 ordered pairs share a vertex (self included),
+    so a full dense request has 1,621,820 regular entries."""
+    xyz, tri = ico(3)
+    m = O.OracleMesh(xyz, tri, 6)
+    idx = np.arange(m.nt)
+    A = m.entries(O.LAPLACE_SLP, O.P0, 0.0, idx, idx)
+    assert int((A != 0).sum()) == 1621820
+    # the count of vertex-sharing pairs from the mesh alone
+    share = np.zeros((m.nt, m.nt), dtype=bool)
+    for k in range(3):
+        for l in range(3):
+            share |= tri[:, k][:, None] == tri[:, l][None, :]
+    assert int(share.sum()) == 16580
+    assert np.array_equal(share, A == 0)
