@@ -1,0 +1,267 @@
+/*
+ * bem.h - C ABI of libbem: Galerkin boundary-element weak-form entries on an
+ * AMD Instinct MI355X (gfx950), the adaptive cross approximation (ACA) that
+ * consumes them, and the H-matrix assembly built on both.
+ *
+ * What is computed (Vater, Betcke, Dilba, "Simple and efficient GPU
+ * parallelization of existing H-Matrix accelerated BEM code", Section 2):
+ *
+ *   single layer, Eq. (slp):  A_ij = int_Gi int_Gj psi_i(x) g(x,y)     phi_j(y)
+ *   double layer, Eq. (dlp):  A_ij = int_Gi int_Gj psi_i(x) dg/dn_y    phi_j(y)
+ *   g(x,y) = exp(i k |x-y|) / (4 pi |x-y|)   (Helmholtz; Laplace is k = 0)
+ *
+ * Row i is the test function psi_i (variable x), column j the trial function
+ * phi_j (variable y); n_y is the unit normal of the trial triangle.  Basis
+ * functions: P0 (one dof per triangle, the indicator of the triangle) or P1
+ * (one dof per vertex, the continuous piecewise-linear hat function).
+ * Both integrals use the same symmetric Gauss rule per triangle (Section
+ * 3.2.1: the 6-point rule of degree 4; the 4-point rule of degree 3 is the
+ * other choice), tensorised over each pair of triangles.  Only regular pairs
+ * are integrated: triangles that share no vertex (Section 3.2.3 leaves
+ * identical, edge- and vertex-adjacent pairs to a singular scheme).  A pair
+ * that shares a vertex either contributes zero (BEM_NEAR_SKIP) or fails the
+ * whole call (BEM_NEAR_ERROR).
+ *
+ * Conventions for every call
+ *   - Indices are 0-based int32 dof ids: triangle ids for P0, vertex ids for
+ *     P1.  Duplicated indices are allowed.
+ *   - Outputs are row-major nrows x ncols.  Element type by (operator,
+ *     precision): Laplace FP64 -> double, Laplace FP32 -> float, Helmholtz
+ *     FP64 -> complex double, Helmholtz FP32 -> complex float; complex values
+ *     are interleaved (re, im).
+ *   - k must be 0 for Laplace and real, finite and > 0 for Helmholtz.
+ *   - Meshes must be welded (shared vertices share an index) and
+ *     outward-oriented: the normal of triangle (a,b,c) points along
+ *     (b-a) x (c-a); the double-layer sign depends on it.
+ *   - The caller owns every buffer passed in; the library copies what it
+ *     keeps.  Outputs are written only when the call returns BEM_OK.
+ *   - Every entry point is thread-safe; many host threads may call
+ *     concurrently (that is how ACA workers use the library).
+ *   - On failure a negative status is returned and bem_last_error() gives a
+ *     message (per calling thread).
+ *   - The library runs on the HIP device that is current when the first
+ *     mesh is created (device 0 by default).
+ */
+#ifndef BEM_H
+#define BEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define BEM_OK 0
+#define BEM_E_ARG (-1)        /* invalid argument (index out of range, bad k, ...) */
+#define BEM_E_OOM (-2)        /* host or device allocation failed / request too large */
+#define BEM_E_DEVICE (-3)     /* HIP runtime error */
+#define BEM_E_NEARFIELD (-4)  /* a contributing pair shares a vertex under BEM_NEAR_ERROR */
+#define BEM_E_BUSY (-5)       /* object still in use by requests in flight */
+#define BEM_E_CANCELLED (-6)  /* request cancelled (server shut down) */
+#define BEM_E_TIMEOUT (-7)    /* wait timed out; the request is still pending */
+#define BEM_E_INTERNAL (-8)   /* internal inconsistency */
+
+typedef enum { BEM_LAPLACE_SLP = 0, BEM_LAPLACE_DLP = 1, BEM_HELMHOLTZ_SLP = 2, BEM_HELMHOLTZ_DLP = 3 } bem_op;
+typedef enum { BEM_P0 = 0, BEM_P1 = 1 } bem_space;
+/* BEM_FP64: plain FP64 quadrature.  BEM_FP32: FP32 quadrature with
+ * compensated (TwoSum) accumulation, centroid-relative geometry and, for
+ * Helmholtz, the phase k r reduced to a turn in FP64. */
+typedef enum { BEM_FP64 = 0, BEM_FP32 = 1 } bem_prec;
+typedef enum { BEM_NEAR_ERROR = 0, BEM_NEAR_SKIP = 1 } bem_near;
+
+typedef struct bem_mesh bem_mesh;
+typedef struct bem_ticket bem_ticket;
+typedef struct bem_hmat bem_hmat;
+
+/* Returns a message describing the last failure on the calling thread. */
+const char *bem_last_error(void);
+
+/* ---- meshes ------------------------------------------------------------ */
+/* Upload a triangle mesh and precompute its geometry on the device
+ * (Section 3.2.1: the grid is copied to the device whole, normals,
+ * Jacobians and quadrature points are computed there and kept resident).
+ *   xyz: nv x 3 vertex coordinates (host, row-major); tri: nt x 3 vertex ids
+ *   (host, row-major, counter-clockwise seen from outside);
+ *   quad_points: 6 (degree-4 rule) or 4 (degree-3 rule).
+ * Errors: BEM_E_ARG (index out of range, degenerate triangle, bad
+ * quad_points), BEM_E_OOM, BEM_E_DEVICE.  *out receives the handle. */
+int bem_mesh_create(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
+                    int quad_points, bem_mesh **out);
+
+/* Release a mesh.  BEM_E_BUSY while requests on it are in flight. */
+int bem_mesh_destroy(bem_mesh *mesh);
+
+typedef struct {
+    int64_t nv, nt;
+    int32_t quad_points;
+    int32_t max_star;          /* largest number of triangles around a vertex */
+    double mean_jacobian;      /* mean of |(b-a) x (c-a)| */
+    double mean_edge;          /* mean edge length */
+    size_t device_bytes;       /* resident device memory of the mesh */
+} bem_mesh_info_t;
+int bem_mesh_info(const bem_mesh *mesh, bem_mesh_info_t *info);
+
+/* ---- weak-form entries ------------------------------------------------- */
+/* A[rows, cols] of operator op on space `space` (test and trial spaces are
+ * the same), evaluated on the device; blocks until the result is in `out`
+ * (host memory, nrows*ncols elements of the type given above).
+ * nrows == 0 or ncols == 0 returns BEM_OK and writes nothing.
+ * Errors: BEM_E_ARG (index out of range, bad k/op/space/prec),
+ * BEM_E_NEARFIELD (BEM_NEAR_ERROR and a contributing pair shares a vertex;
+ * out untouched), BEM_E_OOM (request larger than the server arena),
+ * BEM_E_DEVICE. */
+int bem_eval_entries(bem_mesh *mesh, bem_op op, bem_space space, double k,
+                     const int32_t *rows, int64_t nrows, const int32_t *cols, int64_t ncols,
+                     bem_prec prec, bem_near near, void *out);
+
+/* Same request, submitted to the device request server without waiting.
+ * rows/cols are copied before the call returns; `out` (host memory) must
+ * stay valid until the ticket completes.  Requests submitted by any thread
+ * are admitted by memory, fused into shared kernel launches and overlap on
+ * the device.  The ticket must be released with bem_ticket_free. */
+int bem_submit(bem_mesh *mesh, bem_op op, bem_space space, double k,
+               const int32_t *rows, int64_t nrows, const int32_t *cols, int64_t ncols,
+               bem_prec prec, bem_near near, void *out, bem_ticket **ticket);
+
+/* Wait up to timeout_s seconds (negative: forever).  Returns the request's
+ * status (BEM_OK, BEM_E_NEARFIELD, ...) or BEM_E_TIMEOUT if still pending. */
+int bem_ticket_wait(bem_ticket *ticket, double timeout_s);
+
+/* Submit/complete timestamps of a finished request, seconds on the
+ * library's monotonic clock. */
+int bem_ticket_times(const bem_ticket *ticket, double *t_submit, double *t_done);
+
+/* Release a ticket; waits for the request first if it is still pending. */
+int bem_ticket_free(bem_ticket *ticket);
+
+/* Same request with the result written to device memory `dev_out` on the
+ * caller's HIP stream `stream` (hipStream_t; NULL = null stream), without
+ * host synchronisation.  rows/cols are host arrays, expanded and staged
+ * through pinned memory by the library; the call returns once the work is
+ * enqueued, and dev_out is complete when the stream reaches that point.
+ * Workspace comes from the stream-ordered allocator on the same stream.
+ * Under BEM_NEAR_ERROR the adjacency check runs on the host before anything
+ * is enqueued (BEM_E_NEARFIELD, nothing enqueued). */
+int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
+                           const int32_t *rows, int64_t nrows, const int32_t *cols, int64_t ncols,
+                           bem_prec prec, bem_near near, void *dev_out, void *stream);
+
+/* ---- request server ---------------------------------------------------- */
+/* Size the server before first use: arena_bytes of device memory (and the
+ * same amount of pinned host staging) hold the batches in flight;
+ * max_batch_requests bounds how many requests one fused launch takes.
+ * BEM_E_BUSY once the server is running. */
+int bem_server_config(size_t arena_bytes, int max_batch_requests);
+
+typedef struct {
+    int64_t requests;        /* completed requests */
+    int64_t entries;         /* completed entries */
+    int64_t batches;         /* fused launches */
+    int64_t kernel_evals;    /* pair-quadrature kernel evaluations (Q^2 per regular pair) */
+    double latency_p50;      /* seconds, submit -> completion, over the window */
+    double latency_p99;
+    double latency_max;
+    double busy_seconds;     /* wall time with at least one batch on the device */
+    double kernel_seconds;   /* sum of entry-kernel durations measured with HIP events */
+    double kernel_seconds_p1_reduce;
+    int64_t kernel_launches; /* entry-kernel launches timed */
+} bem_server_stats_t;
+
+/* Statistics since the last reset; reset != 0 clears them afterwards. */
+int bem_server_stats(bem_server_stats_t *stats, int reset);
+
+/* ---- adaptive cross approximation --------------------------------------- */
+typedef struct {
+    double tol;          /* relative stopping tolerance: ||u_k|| ||v_k|| <= tol ||S_k||_F */
+    int32_t max_rank;    /* upper bound on the rank */
+    double zero_abs;     /* a residual row with max |entry| <= zero_abs vanishes; < 0: derived
+                            from the block geometry */
+} bem_aca_params;
+
+/* ACA on the block A[rows, cols] (Algorithm "ACA", Section 2.1): rows and
+ * columns of the block are evaluated on the device through the request
+ * server (precision `prec`), pivots and residual updates run in FP64 on the
+ * host.  Output A ~= U V^T with U column-major m x max_rank and V
+ * column-major n x max_rank (double, or complex double for Helmholtz);
+ * columns >= *rank are left untouched.  *entries_evaluated counts the
+ * entries requested from the device.  Every pair must be regular
+ * (BEM_E_NEARFIELD otherwise). */
+int bem_aca_block(bem_mesh *mesh, bem_op op, bem_space space, double k,
+                  const int32_t *rows, int64_t m, const int32_t *cols, int64_t n,
+                  const bem_aca_params *params, bem_prec prec,
+                  void *U, void *V, int32_t *rank, int64_t *entries_evaluated);
+
+/* ACA on caller-supplied entries (no device involved): get_row(ctx, i, out)
+ * writes block row i (n values), get_col(ctx, j, out) block column j (m
+ * values), as double or interleaved complex double (is_complex != 0).  Same
+ * algorithm and outputs as bem_aca_block. */
+typedef void (*bem_row_fn)(void *ctx, int64_t i, double *out);
+typedef void (*bem_col_fn)(void *ctx, int64_t j, double *out);
+int bem_aca_callback(int64_t m, int64_t n, int is_complex, bem_row_fn get_row, bem_col_fn get_col,
+                     void *ctx, const bem_aca_params *params, void *U, void *V, int32_t *rank);
+
+/* ---- cluster tree, block tree, H-matrix --------------------------------- */
+/* Geometric partition (Section 2.1): a cluster tree over the dof points,
+ * split at the midpoint of the longest bounding-box side (median split when
+ * one side would be empty), and the block tree from (root, root) whose
+ * leaves are admissible when dist > 0 and min(diam) <= eta dist on the
+ * clusters' support boxes, dense when either cluster is a leaf.
+ * Host-only.  Writes up to max_blocks leaves as (row cluster, col cluster,
+ * admissible) triples and the dof ranges of every cluster: cluster c holds
+ * dofs perm[cl_begin[c] .. cl_end[c]).  Sizes are returned in *nblocks and
+ * *nclusters; when a capacity is too small nothing else is written and
+ * BEM_E_ARG is returned with the needed sizes. */
+int bem_partition(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, bem_space space,
+                  int32_t leaf_size, double eta,
+                  int32_t *perm, int32_t *cl_begin, int32_t *cl_end, int64_t max_clusters,
+                  int32_t *blocks /* 3 x max_blocks */, int64_t max_blocks,
+                  int64_t *nclusters, int64_t *nblocks);
+
+typedef struct {
+    int32_t leaf_size;      /* 100 */
+    double eta;             /* 1.0 */
+    double aca_tol;         /* 1e-5 */
+    int32_t max_rank;       /* 200 */
+    int32_t n_workers;      /* host ACA worker threads */
+    int32_t blocks_per_worker; /* ACA blocks each worker keeps in flight */
+    bem_prec prec;          /* precision of the device entries */
+    int32_t dense_mode;     /* 0: dense leaves left empty; 1: their regular part (BEM_NEAR_SKIP) */
+} bem_hmat_params;
+
+/* Fill every admissible leaf of the block tree by ACA (all rows and columns
+ * on the device) and, if dense_mode == 1, every dense leaf by its regular
+ * part.  The caller gets an H-matrix handle. */
+int bem_hmat_assemble(bem_mesh *mesh, bem_op op, bem_space space, double k,
+                      const bem_hmat_params *params, bem_hmat **out);
+
+/* y = H x (host vectors of length ndof, double or interleaved complex
+ * double). */
+int bem_hmat_matvec(const bem_hmat *h, const void *x, void *y);
+
+typedef struct {
+    int64_t ndof;
+    int64_t admissible_blocks, dense_blocks;
+    int64_t aca_entries;       /* entries requested by ACA */
+    int64_t dense_entries;     /* entries of dense leaves evaluated */
+    int64_t aca_requests;      /* row and column requests */
+    int64_t rank_sum;
+    int32_t rank_max;
+    size_t bytes;              /* storage of U, V and dense leaves */
+    double seconds;            /* wall time of the assembly */
+} bem_hmat_stats;
+int bem_hmat_stats_get(const bem_hmat *h, bem_hmat_stats *stats);
+
+/* Dense reconstruction of block b (leaf order as bem_hmat_block_info):
+ * out is rows x cols row-major in the block's local dof order. */
+int bem_hmat_block_info(const bem_hmat *h, int64_t b, int32_t *admissible, int64_t *m, int64_t *n,
+                        int32_t *rank, const int32_t **rows, const int32_t **cols);
+int bem_hmat_block_dense(const bem_hmat *h, int64_t b, void *out);
+int bem_hmat_destroy(bem_hmat *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BEM_H */

@@ -1,0 +1,159 @@
+// Adaptive cross approximation as a resumable state machine (host, FP64).
+//
+// Algorithm "ACA" of Section 2.1: pick a row i_k, form the residual row
+// v~ = a_{i_k,:} - sum_l (u_l)_{i_k} v_l, pick the column j_k of its largest
+// modulus, scale v_k = v~ / v~_{j_k}, form the residual column
+// u_k = a_{:,j_k} - sum_l (v_l)_{j_k} u_l, and repeat; the block is U V^T.
+// Choices the paper leaves open:
+//   * row pivots: first local row, then the unused row where |u_k| is
+//     largest (ties: lowest index);
+//   * a residual row with max |v~| <= zero_abs vanishes: it is marked used
+//     and the lowest unused row is tried next;
+//   * stop when ||u_k|| ||v_k|| <= tol ||S_k||_F, with ||S_k||_F updated by
+//     ||S_k||^2 = ||S_{k-1}||^2 + 2 Re sum_{l<k} (u_l^H u_k)(v_l^H v_k)
+//                + ||u_k||^2 ||v_k||^2,
+//     or when every row is used, or k reaches min(m, n, max_rank).
+// The state machine asks for one block row or column at a time, so one host
+// thread can keep many blocks in flight on the device.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+namespace bem {
+
+inline double abs2(double x) { return x * x; }
+inline double abs2(const std::complex<double> &x) { return x.real() * x.real() + x.imag() * x.imag(); }
+inline double re_of(double x) { return x; }
+inline double re_of(const std::complex<double> &x) { return x.real(); }
+inline double conj_of(double x) { return x; }
+inline std::complex<double> conj_of(const std::complex<double> &x) { return std::conj(x); }
+
+template <typename T>
+struct AcaCore {
+    enum Phase { NEED_ROW = 0, NEED_COL = 1, DONE = 2 };
+    int64_t m = 0, n = 0;
+    double tol = 1e-5, zero_abs = 0.0;
+    int max_rank = 0, limit = 0;
+    std::vector<T> U, V;   // column l of U at U[l*m], of V at V[l*n]
+    std::vector<T> v;      // current residual row
+    std::vector<char> used;
+    int64_t nused = 0;
+    int k = 0;
+    double norm2 = 0.0;
+    int64_t i = 0, j = 0;
+    Phase phase = NEED_ROW;
+
+    void init(int64_t m_, int64_t n_, double tol_, int max_rank_, double zero_abs_)
+    {
+        m = m_;
+        n = n_;
+        tol = tol_;
+        max_rank = max_rank_;
+        zero_abs = zero_abs_;
+        limit = (int)std::min<int64_t>(std::min<int64_t>(m, n), max_rank);
+        U.clear();
+        V.clear();
+        used.assign(m, 0);
+        nused = 0;
+        k = 0;
+        norm2 = 0.0;
+        i = 0;
+        j = 0;
+        phase = (m > 0 && n > 0 && limit > 0) ? NEED_ROW : DONE;
+    }
+
+    // Raw block row i (length n).
+    void consume_row(const T *row)
+    {
+        v.assign(row, row + n);
+        for (int l = 0; l < k; ++l) {
+            const T ul = U[(size_t)l * m + i];
+            const T *vl = &V[(size_t)l * n];
+            for (int64_t c = 0; c < n; ++c) v[c] = v[c] - ul * vl[c];
+        }
+        if (!used[i]) {
+            used[i] = 1;
+            ++nused;
+        }
+        double amax2 = -1.0;
+        int64_t jm = 0;
+        for (int64_t c = 0; c < n; ++c) {
+            const double a = abs2(v[c]);
+            if (a > amax2) {
+                amax2 = a;
+                jm = c;
+            }
+        }
+        if (!(std::sqrt(amax2) > zero_abs)) {
+            if (nused == m) {
+                phase = DONE;
+                return;
+            }
+            for (int64_t r = 0; r < m; ++r)
+                if (!used[r]) {
+                    i = r;
+                    break;
+                }
+            phase = NEED_ROW;
+            return;
+        }
+        j = jm;
+        const T piv = v[j];
+        for (int64_t c = 0; c < n; ++c) v[c] = v[c] / piv;
+        phase = NEED_COL;
+    }
+
+    // Raw block column j (length m).
+    void consume_col(const T *col)
+    {
+        std::vector<T> u(col, col + m);
+        for (int l = 0; l < k; ++l) {
+            const T vl = V[(size_t)l * n + j];
+            const T *ul = &U[(size_t)l * m];
+            for (int64_t r = 0; r < m; ++r) u[r] = u[r] - vl * ul[r];
+        }
+        double cross = 0.0;
+        for (int l = 0; l < k; ++l) {
+            T du = T(0), dv = T(0);
+            const T *ul = &U[(size_t)l * m];
+            const T *vl = &V[(size_t)l * n];
+            for (int64_t r = 0; r < m; ++r) du += conj_of(ul[r]) * u[r];
+            for (int64_t c = 0; c < n; ++c) dv += conj_of(vl[c]) * v[c];
+            cross += re_of(du * dv);
+        }
+        double su = 0.0, sv = 0.0;
+        for (int64_t r = 0; r < m; ++r) su += abs2(u[r]);
+        for (int64_t c = 0; c < n; ++c) sv += abs2(v[c]);
+        const double nu = std::sqrt(su), nv = std::sqrt(sv);
+        norm2 = norm2 + 2.0 * cross + (nu * nv) * (nu * nv);
+        U.insert(U.end(), u.begin(), u.end());
+        V.insert(V.end(), v.begin(), v.end());
+        ++k;
+        if (nu * nv <= tol * std::sqrt(std::max(norm2, 0.0))) {
+            phase = DONE;
+            return;
+        }
+        if (nused == m || k >= limit) {
+            phase = DONE;
+            return;
+        }
+        double best = -1.0;
+        int64_t ib = 0;
+        for (int64_t r = 0; r < m; ++r) {
+            if (used[r]) continue;
+            const double a = abs2(u[r]);
+            if (a > best) {
+                best = a;
+                ib = r;
+            }
+        }
+        i = ib;
+        phase = NEED_ROW;
+    }
+};
+
+}  // namespace bem

@@ -1,0 +1,349 @@
+// extern "C" entry points of libbem (declared in include/bem.h).
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "bem_internal.hpp"
+#include "tree.hpp"
+
+namespace bem {
+const char *last_error();
+int mesh_create_impl(const double *, int64_t, const int32_t *, int64_t, int, bem_mesh **);
+int mesh_destroy_impl(bem_mesh *);
+int server_configure(size_t, int);
+int server_stats(bem_server_stats_t *, int);
+int aca_block(bem_mesh *, int, int, double, const int32_t *, int64_t, const int32_t *, int64_t, const bem_aca_params *,
+              int, void *, void *, int32_t *, int64_t *);
+int aca_callback(int64_t, int64_t, int, bem_row_fn, bem_col_fn, void *, const bem_aca_params *, void *, void *,
+                 int32_t *);
+int hmat_assemble(bem_mesh *, int, int, double, const bem_hmat_params *, bem_hmat **);
+int hmat_matvec(const bem_hmat *, const void *, void *);
+int hmat_block_info(const bem_hmat *, int64_t, int32_t *, int64_t *, int64_t *, int32_t *, const int32_t **,
+                    const int32_t **);
+int hmat_block_dense(const bem_hmat *, int64_t, void *);
+int hmat_stats(const bem_hmat *, bem_hmat_stats *);
+int hmat_destroy(bem_hmat *);
+}  // namespace bem
+
+using namespace bem;
+
+struct bem_ticket {
+    Request req;
+};
+
+namespace {
+
+int fill_request(Request &r, bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows, int64_t nrows,
+                 const int32_t *cols, int64_t ncols, bem_prec prec, bem_near near)
+{
+    if (!mesh) return fail(BEM_E_ARG, "null mesh");
+    if (nrows < 0 || ncols < 0) return fail(BEM_E_ARG, "negative request size");
+    if ((nrows > 0 && !rows) || (ncols > 0 && !cols)) return fail(BEM_E_ARG, "null index array");
+    r.mesh = mesh;
+    r.op = op;
+    r.space = space;
+    r.prec = prec;
+    r.near = near;
+    r.k = k;
+    r.nrows = nrows;
+    r.ncols = ncols;
+    r.rows.assign(rows, rows + nrows);
+    r.cols.assign(cols, cols + ncols);
+    return expand_request(r);
+}
+
+// Pinned staging buffers of the async path.  A buffer is freed once the
+// event recorded after its copy has completed; completed buffers are
+// reclaimed on later calls (or immediately when no event could be recorded).
+std::mutex g_stage_mu;
+std::vector<std::pair<hipEvent_t, char *>> g_stage_pending;
+
+void reclaim_stages(bool all)
+{
+    std::lock_guard<std::mutex> g(g_stage_mu);
+    auto it = g_stage_pending.begin();
+    while (it != g_stage_pending.end()) {
+        if (all ? hipEventSynchronize(it->first) == hipSuccess : hipEventQuery(it->first) == hipSuccess) {
+            (void)hipEventDestroy(it->first);
+            (void)hipHostFree(it->second);
+            it = g_stage_pending.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+char *pinned_stage(size_t bytes)
+{
+    reclaim_stages(false);
+    char *p = nullptr;
+    if (hipHostMalloc((void **)&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+    return p;
+}
+
+void pinned_release(char *p, hipEvent_t after)
+{
+    if (!after) {
+        // nothing was enqueued that reads p
+        (void)hipHostFree(p);
+        return;
+    }
+    std::lock_guard<std::mutex> g(g_stage_mu);
+    g_stage_pending.push_back({after, p});
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bem_last_error(void) { return bem::last_error(); }
+
+int bem_mesh_create(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, int quad_points, bem_mesh **out)
+{
+    return mesh_create_impl(xyz, nv, tri, nt, quad_points, out);
+}
+
+int bem_mesh_destroy(bem_mesh *mesh) { return mesh_destroy_impl(mesh); }
+
+int bem_mesh_info(const bem_mesh *m, bem_mesh_info_t *info)
+{
+    if (!m || !info) return fail(BEM_E_ARG, "null argument");
+    info->nv = m->nv;
+    info->nt = m->nt;
+    info->quad_points = m->q;
+    info->max_star = m->max_star;
+    info->mean_jacobian = m->mean_J;
+    info->mean_edge = m->mean_edge;
+    info->device_bytes = m->dev_bytes;
+    return BEM_OK;
+}
+
+int bem_eval_entries(bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows, int64_t nrows,
+                     const int32_t *cols, int64_t ncols, bem_prec prec, bem_near near, void *out)
+{
+    Request *r = new (std::nothrow) Request();
+    if (!r) return fail(BEM_E_OOM, "host allocation failed");
+    int rc = fill_request(*r, mesh, op, space, k, rows, nrows, cols, ncols, prec, near);
+    if (rc == BEM_OK && r->entries() > 0) {
+        if (!out) {
+            rc = fail(BEM_E_ARG, "null output");
+        } else {
+            r->out_host = out;
+            rc = server_submit(r);
+            if (rc == BEM_OK) {
+                rc = server_wait(r, -1.0);
+                if (rc == BEM_E_NEARFIELD) fail(rc, "a contributing triangle pair shares a vertex");
+            }
+        }
+    }
+    delete r;
+    return rc;
+}
+
+int bem_submit(bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows, int64_t nrows,
+               const int32_t *cols, int64_t ncols, bem_prec prec, bem_near near, void *out, bem_ticket **ticket)
+{
+    if (!ticket) return fail(BEM_E_ARG, "null ticket");
+    bem_ticket *t = new (std::nothrow) bem_ticket();
+    if (!t) return fail(BEM_E_OOM, "host allocation failed");
+    Request &r = t->req;
+    int rc = fill_request(r, mesh, op, space, k, rows, nrows, cols, ncols, prec, near);
+    if (rc == BEM_OK) {
+        if (r.entries() == 0) {
+            r.done = true;
+            r.status = BEM_OK;
+            r.t_submit = r.t_done = now_seconds();
+        } else if (!out) {
+            rc = fail(BEM_E_ARG, "null output");
+        } else {
+            r.out_host = out;
+            rc = server_submit(&r);
+        }
+    }
+    if (rc != BEM_OK) {
+        delete t;
+        return rc;
+    }
+    *ticket = t;
+    return BEM_OK;
+}
+
+int bem_ticket_wait(bem_ticket *t, double timeout_s)
+{
+    if (!t) return fail(BEM_E_ARG, "null ticket");
+    const int rc = server_wait(&t->req, timeout_s);
+    if (rc == BEM_E_NEARFIELD) fail(rc, "a contributing triangle pair shares a vertex");
+    return rc;
+}
+
+int bem_ticket_times(const bem_ticket *t, double *t_submit, double *t_done)
+{
+    if (!t) return fail(BEM_E_ARG, "null ticket");
+    if (t_submit) *t_submit = t->req.t_submit;
+    if (t_done) *t_done = t->req.t_done;
+    return BEM_OK;
+}
+
+int bem_ticket_free(bem_ticket *t)
+{
+    if (!t) return BEM_OK;
+    (void)server_wait(&t->req, -1.0);
+    delete t;
+    return BEM_OK;
+}
+
+int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows, int64_t nrows,
+                           const int32_t *cols, int64_t ncols, bem_prec prec, bem_near near, void *dev_out,
+                           void *stream)
+{
+    Request r;
+    int rc = fill_request(r, mesh, op, space, k, rows, nrows, cols, ncols, prec, near);
+    if (rc != BEM_OK) return rc;
+    if (r.entries() == 0) return BEM_OK;
+    if (!dev_out) return fail(BEM_E_ARG, "null output");
+    if (near == BEM_NEAR_ERROR) {
+        // host-side check: nothing may be enqueued for a failing request
+        if (space == BEM_P0) {
+            for (int32_t a : r.rows)
+                for (int32_t b : r.cols)
+                    if (mesh->adjacent(a, b)) return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
+        } else {
+            for (size_t f = 0; f + 1 < r.fix.size(); ++f)
+                for (int32_t s = r.fix[f]; s < r.fix[f + 1]; ++s)
+                    for (int32_t t : r.lane)
+                        if (mesh->adjacent(r.fstar[s] >> 2, t))
+                            return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
+        }
+    }
+    std::vector<Tile> tiles;
+    std::vector<RTile> rtiles;
+    make_tiles(r, 0, tiles, rtiles);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t off_req = off;
+    off = al(off + sizeof(ReqDev));
+    const size_t off_t = off;
+    off = al(off + sizeof(Tile) * tiles.size());
+    const size_t off_rt = off;
+    off = al(off + sizeof(RTile) * rtiles.size());
+    const size_t off_in = off;
+    off = al(off + r.in_bytes);
+    const size_t off_status = off;
+    off = al(off + 256);
+    const size_t in_total = off;
+    const size_t off_part = off;
+    off = al(off + r.part_bytes);
+    // descriptors go through pinned staging that is released once the copy
+    // has completed (checked on later calls), so nothing here waits
+    char *host = pinned_stage(in_total);
+    if (!host) return fail(BEM_E_OOM, "pinned staging allocation failed");
+    std::memset(host, 0, in_total);
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = nullptr;
+    hipError_t e = hipMallocAsync((void **)&ws, off, s);
+    if (e != hipSuccess) {
+        pinned_release(host, nullptr);
+        return fail(BEM_E_DEVICE, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
+    ReqDev d;
+    place_request(r, host, ws, off_in, 0, off_part, off_status, d);
+    d.out = dev_out;
+    std::memcpy(host + off_req, &d, sizeof(ReqDev));
+    std::memcpy(host + off_t, tiles.data(), sizeof(Tile) * tiles.size());
+    std::memcpy(host + off_rt, rtiles.data(), sizeof(RTile) * rtiles.size());
+    e = hipMemcpyAsync(ws, host, in_total, hipMemcpyHostToDevice, s);
+    hipEvent_t ev = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, s);
+    pinned_release(host, e == hipSuccess ? ev : nullptr);
+    if (e != hipSuccess) return fail(BEM_E_DEVICE, std::string("staging copy: ") + hipGetErrorString(e));
+    Variant v{r.op, r.space, r.prec, mesh->q, r.rowfix};
+    BEM_HIP_TRY(launch_entries(v, (const ReqDev *)(ws + off_req), (const Tile *)(ws + off_t), (int)tiles.size(), s));
+    if (space == BEM_P1)
+        BEM_HIP_TRY(launch_p1_reduce(r.prec, is_complex_op(r.op), (const ReqDev *)(ws + off_req),
+                                     (const RTile *)(ws + off_rt), (int)rtiles.size(), s));
+    BEM_HIP_TRY(hipFreeAsync(ws, s));
+    return BEM_OK;
+}
+
+int bem_server_config(size_t arena_bytes, int max_batch_requests)
+{
+    return server_configure(arena_bytes, max_batch_requests);
+}
+
+int bem_server_stats(bem_server_stats_t *stats, int reset)
+{
+    if (!stats) return fail(BEM_E_ARG, "null argument");
+    return server_stats(stats, reset);
+}
+
+int bem_aca_block(bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows, int64_t m,
+                  const int32_t *cols, int64_t n, const bem_aca_params *params, bem_prec prec, void *U, void *V,
+                  int32_t *rank, int64_t *entries_evaluated)
+{
+    return aca_block(mesh, op, space, k, rows, m, cols, n, params, prec, U, V, rank, entries_evaluated);
+}
+
+int bem_aca_callback(int64_t m, int64_t n, int is_complex, bem_row_fn get_row, bem_col_fn get_col, void *ctx,
+                     const bem_aca_params *params, void *U, void *V, int32_t *rank)
+{
+    return aca_callback(m, n, is_complex, get_row, get_col, ctx, params, U, V, rank);
+}
+
+int bem_partition(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, bem_space space, int32_t leaf_size,
+                  double eta, int32_t *perm, int32_t *cl_begin, int32_t *cl_end, int64_t max_clusters, int32_t *blocks,
+                  int64_t max_blocks, int64_t *nclusters, int64_t *nblocks)
+{
+    if (!xyz || !tri || nv < 1 || nt < 1 || leaf_size < 1 || !(eta > 0) || !nclusters || !nblocks)
+        return fail(BEM_E_ARG, "bad partition arguments");
+    if (space != BEM_P0 && space != BEM_P1) return fail(BEM_E_ARG, "unknown space");
+    for (int64_t i = 0; i < 3 * nt; ++i)
+        if (tri[i] < 0 || tri[i] >= nv) return fail(BEM_E_ARG, "triangle vertex index out of range");
+    bem_mesh m;
+    m.nv = nv;
+    m.nt = nt;
+    m.xyz.assign(xyz, xyz + 3 * nv);
+    m.tri.assign(tri, tri + 3 * nt);
+    std::vector<double> pts, slo, shi;
+    dof_geometry(m, space, pts, slo, shi);
+    Partition P;
+    build_partition(pts, slo, shi, leaf_size, eta, P);
+    *nclusters = (int64_t)P.nodes.size();
+    *nblocks = (int64_t)P.blocks.size();
+    if ((int64_t)P.nodes.size() > max_clusters || (int64_t)P.blocks.size() > max_blocks)
+        return fail(BEM_E_ARG, "capacity too small");
+    if (perm) std::copy(P.perm.begin(), P.perm.end(), perm);
+    for (size_t c = 0; c < P.nodes.size(); ++c) {
+        if (cl_begin) cl_begin[c] = (int32_t)P.nodes[c].begin;
+        if (cl_end) cl_end[c] = (int32_t)P.nodes[c].end;
+    }
+    if (blocks)
+        for (size_t b = 0; b < P.blocks.size(); ++b) {
+            blocks[3 * b] = P.blocks[b].tau;
+            blocks[3 * b + 1] = P.blocks[b].sigma;
+            blocks[3 * b + 2] = P.blocks[b].admissible;
+        }
+    return BEM_OK;
+}
+
+int bem_hmat_assemble(bem_mesh *mesh, bem_op op, bem_space space, double k, const bem_hmat_params *params,
+                      bem_hmat **out)
+{
+    return hmat_assemble(mesh, op, space, k, params, out);
+}
+
+int bem_hmat_matvec(const bem_hmat *h, const void *x, void *y) { return hmat_matvec(h, x, y); }
+
+int bem_hmat_stats_get(const bem_hmat *h, bem_hmat_stats *stats) { return hmat_stats(h, stats); }
+
+int bem_hmat_block_info(const bem_hmat *h, int64_t b, int32_t *admissible, int64_t *m, int64_t *n, int32_t *rank,
+                        const int32_t **rows, const int32_t **cols)
+{
+    return hmat_block_info(h, b, admissible, m, n, rank, rows, cols);
+}
+
+int bem_hmat_block_dense(const bem_hmat *h, int64_t b, void *out) { return hmat_block_dense(h, b, out); }
+
+int bem_hmat_destroy(bem_hmat *h) { return hmat_destroy(h); }
+
+}  // extern "C"

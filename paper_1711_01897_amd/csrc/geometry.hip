@@ -1,0 +1,70 @@
+// Per-triangle geometry, computed once on the device when a mesh is created
+// and kept resident (Section 3.2.1: normals, Jacobians and global quadrature
+// points are precomputed on the device and laid out for coalesced access).
+#include "bem_internal.hpp"
+#include "quad_rules.hpp"
+
+namespace bem {
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_geometry(const double *__restrict__ xyz, const int32_t *__restrict__ tri,
+                                                  int64_t nt, float *__restrict__ g32, double *__restrict__ g64,
+                                                  int4 *__restrict__ vtx, int32_t *__restrict__ bad)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int i0 = tri[3 * t], i1 = tri[3 * t + 1], i2 = tri[3 * t + 2];
+    const double a[3] = {xyz[3 * i0], xyz[3 * i0 + 1], xyz[3 * i0 + 2]};
+    const double b[3] = {xyz[3 * i1], xyz[3 * i1 + 1], xyz[3 * i1 + 2]};
+    const double c[3] = {xyz[3 * i2], xyz[3 * i2 + 1], xyz[3 * i2 + 2]};
+    double e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) {
+        e1[d] = b[d] - a[d];
+        e2[d] = c[d] - a[d];
+    }
+    const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double J = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+    if (!(J > 0.0)) atomicOr(bad, 1);
+    const double inv = 1.0 / J;
+    double cen[3];
+    for (int d = 0; d < 3; ++d) cen[d] = ((a[d] + b[d]) + c[d]) / 3.0;
+
+    double *r64 = g64 + t * kGeo64Stride;
+    float *r32 = g32 + t * kGeo32Stride;
+    for (int d = 0; d < 3; ++d) {
+        r64[d] = N[d] * inv;
+        const float hi = (float)cen[d];
+        r32[d] = hi;
+        r32[4 + d] = (float)(cen[d] - (double)hi);
+        r32[8 + d] = (float)(N[d] * inv);
+    }
+    r64[3] = J;
+    r32[3] = (float)J;
+    r32[7] = 0.0f;
+    r32[11] = 0.0f;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        for (int d = 0; d < 3; ++d) {
+            const double x = a[d] + rule::Rule<Q>::l1[p] * e1[d] + rule::Rule<Q>::l2[p] * e2[d];
+            r64[4 + 3 * p + d] = x;
+            r32[12 + 3 * p + d] = (float)(x - cen[d]);
+        }
+    }
+    for (int i = 4 + 3 * Q; i < kGeo64Stride; ++i) r64[i] = 0.0;
+    for (int i = 12 + 3 * Q; i < kGeo32Stride; ++i) r32[i] = 0.0f;
+    vtx[t] = make_int4(i0, i1, i2, 0);
+}
+
+hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, int q, float *g32, double *g64,
+                           int4 *vtx, int32_t *bad, hipStream_t s)
+{
+    const int block = 256;
+    const unsigned grid = (unsigned)((nt + block - 1) / block);
+    if (q == 6)
+        hipLaunchKernelGGL(k_geometry<6>, dim3(grid), dim3(block), 0, s, xyz, tri, nt, g32, g64, vtx, bad);
+    else
+        hipLaunchKernelGGL(k_geometry<4>, dim3(grid), dim3(block), 0, s, xyz, tri, nt, g32, g64, vtx, bad);
+    return hipGetLastError();
+}
+
+}  // namespace bem

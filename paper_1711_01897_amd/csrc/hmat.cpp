@@ -1,0 +1,647 @@
+// ACA on device-evaluated rows and columns, and H-matrix assembly.
+//
+// Section 4 of the paper gives every admissible block to one CPU thread that
+// runs ACA and sends each row and column it needs to the GPU.  Here a small
+// pool of worker threads each keeps several blocks in flight as resumable
+// ACA state machines: a worker submits the next row or column request of
+// every block it holds to the request server, and while those requests run
+// (fused with the other workers' requests) it consumes finished ones, so
+// the device sees large batches of uneven requests while pivoting and
+// residual updates stay on the host in FP64.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <deque>
+#include <thread>
+
+#include "aca.hpp"
+#include "bem_internal.hpp"
+#include "tree.hpp"
+
+using cd = std::complex<double>;
+
+struct bem_hmat {
+    int op = 0, space = 0;
+    bool cplx = false;
+    int64_t ndof = 0;
+    bem::Partition part;
+    struct Leaf {
+        int adm = 0;
+        std::vector<int32_t> rows, cols;
+        int rank = 0;
+        std::vector<double> U, V, D;   // complex values interleaved
+    };
+    std::vector<Leaf> leaves;
+    bem_hmat_stats st{};
+};
+
+namespace bem {
+
+namespace {
+
+double vanish_scale(const bem_mesh &m, int op, int space, double k, double dist)
+{
+    const double d = dist > 0.0 ? dist : m.mean_edge;
+    const double J2 = m.mean_J * m.mean_J * (space == BEM_P0 ? 0.25 : 1.0);
+    const double inv4pi = 0.0795774715459476678844418816862571;
+    if (op == BEM_LAPLACE_SLP || op == BEM_HELMHOLTZ_SLP) return J2 * inv4pi / d;
+    return J2 * inv4pi * (1.0 + (op == BEM_HELMHOLTZ_DLP ? k * d : 0.0)) / (d * d);
+}
+
+double default_zero_abs(const bem_mesh &m, int op, int space, double k, int prec, double dist)
+{
+    return (prec == BEM_FP32 ? 1e-6 : 1e-12) * vanish_scale(m, op, space, k, dist);
+}
+
+// support box of a dof list
+void support_box(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, double *lo, double *hi)
+{
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = INFINITY;
+        hi[d] = -INFINITY;
+    }
+    auto add_tri = [&](int64_t t) {
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d) {
+                const double x = m.xyz[3 * m.tri[3 * t + k] + d];
+                lo[d] = std::min(lo[d], x);
+                hi[d] = std::max(hi[d], x);
+            }
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        if (space == BEM_P0) {
+            add_tri(dofs[i]);
+        } else {
+            for (int64_t s = m.star_ptr[dofs[i]]; s < m.star_ptr[dofs[i] + 1]; ++s) add_tri(m.star[s] >> 2);
+        }
+    }
+}
+
+double box_distance(const double *alo, const double *ahi, const double *blo, const double *bhi)
+{
+    double g[3];
+    for (int k = 0; k < 3; ++k) g[k] = std::max(0.0, std::max(alo[k] - bhi[k], blo[k] - ahi[k]));
+    return std::sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+}
+
+template <typename T>
+void to_scalar(const void *src, int prec, int64_t n, T *dst);
+
+template <>
+void to_scalar<double>(const void *src, int prec, int64_t n, double *dst)
+{
+    if (prec == BEM_FP32) {
+        const float *s = (const float *)src;
+        for (int64_t i = 0; i < n; ++i) dst[i] = s[i];
+    } else {
+        std::memcpy(dst, src, sizeof(double) * n);
+    }
+}
+
+template <>
+void to_scalar<cd>(const void *src, int prec, int64_t n, cd *dst)
+{
+    if (prec == BEM_FP32) {
+        const float *s = (const float *)src;
+        for (int64_t i = 0; i < n; ++i) dst[i] = cd(s[2 * i], s[2 * i + 1]);
+    } else {
+        const double *s = (const double *)src;
+        for (int64_t i = 0; i < n; ++i) dst[i] = cd(s[2 * i], s[2 * i + 1]);
+    }
+}
+
+template <typename T>
+void store_cols(const std::vector<T> &src, int k, int64_t len, int64_t cap, void *dst);
+
+template <>
+void store_cols<double>(const std::vector<double> &src, int k, int64_t len, int64_t cap, void *dst)
+{
+    (void)cap;
+    std::memcpy(dst, src.data(), sizeof(double) * len * k);
+}
+
+template <>
+void store_cols<cd>(const std::vector<cd> &src, int k, int64_t len, int64_t cap, void *dst)
+{
+    (void)cap;
+    std::memcpy(dst, src.data(), sizeof(cd) * len * k);
+}
+
+// Completion queue of one worker.
+struct DoneQueue {
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request *> q;
+    static void push(Request *r, void *ctx)
+    {
+        DoneQueue *d = (DoneQueue *)ctx;
+        {
+            std::lock_guard<std::mutex> g(d->mu);
+            d->q.push_back(r);
+        }
+        d->cv.notify_one();
+    }
+    Request *pop()
+    {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return !q.empty(); });
+        Request *r = q.front();
+        q.pop_front();
+        return r;
+    }
+};
+
+struct Job {
+    int64_t leaf;
+    int adm;
+};
+
+template <typename T>
+struct Slot {
+    int64_t leaf = -1;
+    bool adm = false;
+    AcaCore<T> core;
+    Request req;
+    std::vector<char> out;
+    std::vector<T> buf;
+    bool busy = false;
+};
+
+struct AssemblyCtx {
+    bem_mesh *mesh;
+    int op, space, prec;
+    double k, tol;
+    int max_rank;
+    bem_hmat *h;
+    std::vector<Job> jobs;
+    std::atomic<int64_t> next{0};
+    std::atomic<int> error{0};
+    std::mutex err_mu;
+    std::string err_msg;
+    std::atomic<int64_t> aca_entries{0}, dense_entries{0}, requests{0};
+};
+
+template <typename T>
+int submit_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq)
+{
+    bem_hmat::Leaf &L = C.h->leaves[s.leaf];
+    Request &r = s.req;
+    r.mesh = C.mesh;
+    r.op = C.op;
+    r.space = C.space;
+    r.prec = C.prec;
+    r.k = C.k;
+    if (!s.adm) {
+        r.near = BEM_NEAR_SKIP;
+        r.rows = L.rows;
+        r.cols = L.cols;
+    } else {
+        r.near = BEM_NEAR_ERROR;
+        if (s.core.phase == AcaCore<T>::NEED_ROW) {
+            r.rows.assign(1, L.rows[s.core.i]);
+            r.cols = L.cols;
+        } else {
+            r.rows = L.rows;
+            r.cols.assign(1, L.cols[s.core.j]);
+        }
+    }
+    r.nrows = (int64_t)r.rows.size();
+    r.ncols = (int64_t)r.cols.size();
+    int rc = expand_request(r);
+    if (rc != BEM_OK) return rc;
+    s.out.resize((size_t)r.entries() * r.elem_bytes);
+    r.out_host = s.out.data();
+    r.on_done = &DoneQueue::push;
+    r.cb_ctx = &dq;
+    r.done = false;
+    r.status = 0;
+    C.requests.fetch_add(1);
+    if (s.adm)
+        C.aca_entries.fetch_add(r.entries());
+    else
+        C.dense_entries.fetch_add(r.entries());
+    return server_submit(&r);
+}
+
+template <typename T>
+void worker(AssemblyCtx &C, int per_worker)
+{
+    DoneQueue dq;
+    std::vector<Slot<T>> slots(per_worker);
+    int active = 0;
+    bool exhausted = false;
+    for (;;) {
+        for (auto &s : slots) {
+            if (s.busy || exhausted || C.error.load()) continue;
+            const int64_t j = C.next.fetch_add(1);
+            if (j >= (int64_t)C.jobs.size()) {
+                exhausted = true;
+                break;
+            }
+            s.leaf = C.jobs[j].leaf;
+            s.adm = C.jobs[j].adm != 0;
+            bem_hmat::Leaf &L = C.h->leaves[s.leaf];
+            if (s.adm) {
+                const Cluster &a = C.h->part.nodes[C.h->part.blocks[s.leaf].tau];
+                const Cluster &b = C.h->part.nodes[C.h->part.blocks[s.leaf].sigma];
+                s.core.init((int64_t)L.rows.size(), (int64_t)L.cols.size(), C.tol, C.max_rank,
+                            default_zero_abs(*C.mesh, C.op, C.space, C.k, C.prec, support_distance(a, b)));
+            }
+            const int rc = submit_slot(C, s, dq);
+            if (rc != BEM_OK) {
+                std::lock_guard<std::mutex> g(C.err_mu);
+                C.error = rc;
+                C.err_msg = std::string("submit: ") + bem_last_error();
+                break;
+            }
+            s.busy = true;
+            ++active;
+        }
+        if (active == 0) return;
+        Request *r = dq.pop();
+        Slot<T> *s = nullptr;
+        for (auto &x : slots)
+            if (&x.req == r) s = &x;
+        if (r->status != BEM_OK) {
+            std::lock_guard<std::mutex> g(C.err_mu);
+            C.error = r->status;
+            C.err_msg = "device request failed";
+            s->busy = false;
+            --active;
+            continue;
+        }
+        bem_hmat::Leaf &L = C.h->leaves[s->leaf];
+        const int64_t cnt = r->entries();
+        s->buf.resize(cnt);
+        to_scalar<T>(s->out.data(), C.prec, cnt, s->buf.data());
+        bool finished = false;
+        if (!s->adm) {
+            L.D.resize((size_t)cnt * (sizeof(T) / sizeof(double)));
+            std::memcpy(L.D.data(), s->buf.data(), sizeof(T) * cnt);
+            finished = true;
+        } else {
+            if (s->core.phase == AcaCore<T>::NEED_ROW)
+                s->core.consume_row(s->buf.data());
+            else
+                s->core.consume_col(s->buf.data());
+            if (s->core.phase == AcaCore<T>::DONE) {
+                L.rank = s->core.k;
+                const size_t f = sizeof(T) / sizeof(double);
+                L.U.resize(s->core.U.size() * f);
+                L.V.resize(s->core.V.size() * f);
+                std::memcpy(L.U.data(), s->core.U.data(), sizeof(T) * s->core.U.size());
+                std::memcpy(L.V.data(), s->core.V.data(), sizeof(T) * s->core.V.size());
+                finished = true;
+            }
+        }
+        if (finished || C.error.load()) {
+            s->busy = false;
+            --active;
+            continue;
+        }
+        const int rc = submit_slot(C, *s, dq);
+        if (rc != BEM_OK) {
+            std::lock_guard<std::mutex> g(C.err_mu);
+            C.error = rc;
+            C.err_msg = std::string("submit: ") + bem_last_error();
+            s->busy = false;
+            --active;
+        }
+    }
+}
+
+template <typename T>
+int aca_block_impl(bem_mesh *mesh, int op, int space, double k, const int32_t *rows, int64_t m, const int32_t *cols,
+                   int64_t n, const bem_aca_params *p, int prec, void *U, void *V, int32_t *rank, int64_t *entries)
+{
+    double zero_abs = p->zero_abs;
+    if (zero_abs < 0) {
+        double alo[3], ahi[3], blo[3], bhi[3];
+        support_box(*mesh, space, rows, m, alo, ahi);
+        support_box(*mesh, space, cols, n, blo, bhi);
+        zero_abs = default_zero_abs(*mesh, op, space, k, prec, box_distance(alo, ahi, blo, bhi));
+    }
+    AcaCore<T> core;
+    core.init(m, n, p->tol, p->max_rank, zero_abs);
+    Request r;
+    std::vector<char> out;
+    std::vector<T> buf;
+    int64_t count = 0;
+    while (core.phase != AcaCore<T>::DONE) {
+        r.mesh = mesh;
+        r.op = op;
+        r.space = space;
+        r.prec = prec;
+        r.k = k;
+        r.near = BEM_NEAR_ERROR;
+        if (core.phase == AcaCore<T>::NEED_ROW) {
+            r.rows.assign(1, rows[core.i]);
+            r.cols.assign(cols, cols + n);
+        } else {
+            r.rows.assign(rows, rows + m);
+            r.cols.assign(1, cols[core.j]);
+        }
+        r.nrows = (int64_t)r.rows.size();
+        r.ncols = (int64_t)r.cols.size();
+        int rc = expand_request(r);
+        if (rc != BEM_OK) return rc;
+        out.resize((size_t)r.entries() * r.elem_bytes);
+        r.out_host = out.data();
+        r.on_done = nullptr;
+        rc = server_submit(&r);
+        if (rc != BEM_OK) return rc;
+        rc = server_wait(&r, -1.0);
+        if (rc != BEM_OK) return rc == BEM_E_NEARFIELD ? fail(rc, "block contains a vertex-sharing pair") : rc;
+        count += r.entries();
+        buf.resize(r.entries());
+        to_scalar<T>(out.data(), prec, r.entries(), buf.data());
+        if (core.phase == AcaCore<T>::NEED_ROW)
+            core.consume_row(buf.data());
+        else
+            core.consume_col(buf.data());
+    }
+    store_cols<T>(core.U, core.k, m, p->max_rank, U);
+    store_cols<T>(core.V, core.k, n, p->max_rank, V);
+    *rank = core.k;
+    if (entries) *entries = count;
+    return BEM_OK;
+}
+
+}  // namespace
+
+int aca_block(bem_mesh *mesh, int op, int space, double k, const int32_t *rows, int64_t m, const int32_t *cols,
+              int64_t n, const bem_aca_params *p, int prec, void *U, void *V, int32_t *rank, int64_t *entries)
+{
+    if (!mesh || !p || !U || !V || !rank) return fail(BEM_E_ARG, "null argument");
+    if (m <= 0 || n <= 0 || (m > 0 && !rows) || (n > 0 && !cols)) return fail(BEM_E_ARG, "empty block");
+    if (p->max_rank < 1 || !(p->tol >= 0.0)) return fail(BEM_E_ARG, "bad ACA parameters");
+    if (is_complex_op(op))
+        return aca_block_impl<cd>(mesh, op, space, k, rows, m, cols, n, p, prec, U, V, rank, entries);
+    return aca_block_impl<double>(mesh, op, space, k, rows, m, cols, n, p, prec, U, V, rank, entries);
+}
+
+int aca_callback(int64_t m, int64_t n, int is_complex, bem_row_fn get_row, bem_col_fn get_col, void *ctx,
+                 const bem_aca_params *p, void *U, void *V, int32_t *rank)
+{
+    if (!get_row || !get_col || !p || !U || !V || !rank || m <= 0 || n <= 0 || p->max_rank < 1)
+        return fail(BEM_E_ARG, "bad ACA arguments");
+    const double zero_abs = p->zero_abs < 0 ? 0.0 : p->zero_abs;
+    if (is_complex) {
+        AcaCore<cd> core;
+        core.init(m, n, p->tol, p->max_rank, zero_abs);
+        std::vector<cd> buf;
+        while (core.phase != AcaCore<cd>::DONE) {
+            if (core.phase == AcaCore<cd>::NEED_ROW) {
+                buf.assign(n, cd(0));
+                get_row(ctx, core.i, reinterpret_cast<double *>(buf.data()));
+                core.consume_row(buf.data());
+            } else {
+                buf.assign(m, cd(0));
+                get_col(ctx, core.j, reinterpret_cast<double *>(buf.data()));
+                core.consume_col(buf.data());
+            }
+        }
+        store_cols<cd>(core.U, core.k, m, p->max_rank, U);
+        store_cols<cd>(core.V, core.k, n, p->max_rank, V);
+        *rank = core.k;
+    } else {
+        AcaCore<double> core;
+        core.init(m, n, p->tol, p->max_rank, zero_abs);
+        std::vector<double> buf;
+        while (core.phase != AcaCore<double>::DONE) {
+            if (core.phase == AcaCore<double>::NEED_ROW) {
+                buf.assign(n, 0.0);
+                get_row(ctx, core.i, buf.data());
+                core.consume_row(buf.data());
+            } else {
+                buf.assign(m, 0.0);
+                get_col(ctx, core.j, buf.data());
+                core.consume_col(buf.data());
+            }
+        }
+        store_cols<double>(core.U, core.k, m, p->max_rank, U);
+        store_cols<double>(core.V, core.k, n, p->max_rank, V);
+        *rank = core.k;
+    }
+    return BEM_OK;
+}
+
+int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_params *p, bem_hmat **out)
+{
+    if (!mesh || !p || !out) return fail(BEM_E_ARG, "null argument");
+    if (p->leaf_size < 1 || !(p->eta > 0) || p->max_rank < 1 || !(p->aca_tol >= 0))
+        return fail(BEM_E_ARG, "bad H-matrix parameters");
+    {
+        // validate op/k/space/prec once with an empty request
+        Request probe;
+        probe.mesh = mesh;
+        probe.op = op;
+        probe.space = space;
+        probe.prec = p->prec;
+        probe.k = k;
+        probe.near = BEM_NEAR_SKIP;
+        const int rc = expand_request(probe);
+        if (rc != BEM_OK) return rc;
+    }
+    const double t0 = now_seconds();
+    bem_hmat *h = new bem_hmat();
+    h->op = op;
+    h->space = space;
+    h->cplx = is_complex_op(op);
+    h->ndof = space == BEM_P0 ? mesh->nt : mesh->nv;
+    std::vector<double> pts, slo, shi;
+    dof_geometry(*mesh, space, pts, slo, shi);
+    build_partition(pts, slo, shi, p->leaf_size, p->eta, h->part);
+    const auto &P = h->part;
+    h->leaves.resize(P.blocks.size());
+    AssemblyCtx C;
+    C.mesh = mesh;
+    C.op = op;
+    C.space = space;
+    C.prec = p->prec;
+    C.k = k;
+    C.tol = p->aca_tol;
+    C.max_rank = p->max_rank;
+    C.h = h;
+    for (size_t b = 0; b < P.blocks.size(); ++b) {
+        const Cluster &a = P.nodes[P.blocks[b].tau], &c = P.nodes[P.blocks[b].sigma];
+        auto &L = h->leaves[b];
+        L.adm = P.blocks[b].admissible;
+        L.rows.assign(P.perm.begin() + a.begin, P.perm.begin() + a.end);
+        L.cols.assign(P.perm.begin() + c.begin, P.perm.begin() + c.end);
+        if (L.adm || p->dense_mode == 1) C.jobs.push_back(Job{(int64_t)b, L.adm});
+    }
+    // largest blocks first
+    std::stable_sort(C.jobs.begin(), C.jobs.end(), [&](const Job &x, const Job &y) {
+        const auto &a = h->leaves[x.leaf], &b = h->leaves[y.leaf];
+        const int64_t cx = x.adm ? (int64_t)(a.rows.size() + a.cols.size()) * 16 : (int64_t)(a.rows.size() * a.cols.size());
+        const int64_t cy = y.adm ? (int64_t)(b.rows.size() + b.cols.size()) * 16 : (int64_t)(b.rows.size() * b.cols.size());
+        return cx > cy;
+    });
+    const int nw = std::max(1, p->n_workers);
+    const int per = std::max(1, p->blocks_per_worker);
+    std::vector<std::thread> th;
+    for (int w = 0; w < nw; ++w) {
+        if (h->cplx)
+            th.emplace_back([&] { worker<cd>(C, per); });
+        else
+            th.emplace_back([&] { worker<double>(C, per); });
+    }
+    for (auto &t : th) t.join();
+    if (C.error.load() != 0) {
+        const int code = C.error.load();
+        std::string msg = C.err_msg;
+        delete h;
+        return fail(code, "H-matrix assembly: " + msg);
+    }
+    bem_hmat_stats &s = h->st;
+    s.ndof = h->ndof;
+    s.aca_entries = C.aca_entries.load();
+    s.dense_entries = C.dense_entries.load();
+    s.aca_requests = C.requests.load();
+    size_t bytes = 0;
+    for (auto &L : h->leaves) {
+        if (L.adm) {
+            s.admissible_blocks++;
+            s.rank_sum += L.rank;
+            s.rank_max = std::max(s.rank_max, L.rank);
+        } else {
+            s.dense_blocks++;
+        }
+        bytes += sizeof(double) * (L.U.size() + L.V.size() + L.D.size());
+    }
+    s.bytes = bytes;
+    s.seconds = now_seconds() - t0;
+    *out = h;
+    return BEM_OK;
+}
+
+int hmat_matvec(const bem_hmat *h, const void *xv, void *yv)
+{
+    if (!h || !xv || !yv) return fail(BEM_E_ARG, "null argument");
+    const int64_t n = h->ndof;
+    const int f = h->cplx ? 2 : 1;
+    const double *x = (const double *)xv;
+    const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::vector<double>> acc(nth, std::vector<double>((size_t)n * f, 0.0));
+    auto run = [&](int tid) {
+        std::vector<double> &y = acc[tid];
+        std::vector<cd> tmp;
+        for (size_t b = tid; b < h->leaves.size(); b += nth) {
+            const auto &L = h->leaves[b];
+            const int64_t m = (int64_t)L.rows.size(), nc = (int64_t)L.cols.size();
+            if (h->cplx) {
+                const cd *X = reinterpret_cast<const cd *>(x);
+                cd *Y = reinterpret_cast<cd *>(y.data());
+                if (L.adm) {
+                    const cd *U = reinterpret_cast<const cd *>(L.U.data());
+                    const cd *V = reinterpret_cast<const cd *>(L.V.data());
+                    tmp.assign(L.rank, cd(0));
+                    for (int l = 0; l < L.rank; ++l)
+                        for (int64_t c = 0; c < nc; ++c) tmp[l] += V[(size_t)l * nc + c] * X[L.cols[c]];
+                    for (int l = 0; l < L.rank; ++l)
+                        for (int64_t r = 0; r < m; ++r) Y[L.rows[r]] += U[(size_t)l * m + r] * tmp[l];
+                } else if (!L.D.empty()) {
+                    const cd *D = reinterpret_cast<const cd *>(L.D.data());
+                    for (int64_t r = 0; r < m; ++r) {
+                        cd s = 0;
+                        for (int64_t c = 0; c < nc; ++c) s += D[r * nc + c] * X[L.cols[c]];
+                        Y[L.rows[r]] += s;
+                    }
+                }
+            } else {
+                if (L.adm) {
+                    std::vector<double> t(L.rank, 0.0);
+                    for (int l = 0; l < L.rank; ++l)
+                        for (int64_t c = 0; c < nc; ++c) t[l] += L.V[(size_t)l * nc + c] * x[L.cols[c]];
+                    for (int l = 0; l < L.rank; ++l)
+                        for (int64_t r = 0; r < m; ++r) y[L.rows[r]] += L.U[(size_t)l * m + r] * t[l];
+                } else if (!L.D.empty()) {
+                    for (int64_t r = 0; r < m; ++r) {
+                        double s = 0;
+                        for (int64_t c = 0; c < nc; ++c) s += L.D[r * nc + c] * x[L.cols[c]];
+                        y[L.rows[r]] += s;
+                    }
+                }
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) th.emplace_back(run, t);
+    for (auto &t : th) t.join();
+    double *y = (double *)yv;
+    for (int64_t i = 0; i < n * f; ++i) {
+        double s = 0.0;
+        for (int t = 0; t < nth; ++t) s += acc[t][i];
+        y[i] = s;
+    }
+    return BEM_OK;
+}
+
+int hmat_block_info(const bem_hmat *h, int64_t b, int32_t *adm, int64_t *m, int64_t *n, int32_t *rank,
+                    const int32_t **rows, const int32_t **cols)
+{
+    if (!h || b < 0 || b >= (int64_t)h->leaves.size()) return fail(BEM_E_ARG, "block index out of range");
+    const auto &L = h->leaves[b];
+    if (adm) *adm = L.adm;
+    if (m) *m = (int64_t)L.rows.size();
+    if (n) *n = (int64_t)L.cols.size();
+    if (rank) *rank = L.rank;
+    if (rows) *rows = L.rows.data();
+    if (cols) *cols = L.cols.data();
+    return BEM_OK;
+}
+
+int hmat_block_dense(const bem_hmat *h, int64_t b, void *outv)
+{
+    if (!h || !outv || b < 0 || b >= (int64_t)h->leaves.size()) return fail(BEM_E_ARG, "bad block");
+    const auto &L = h->leaves[b];
+    const int64_t m = (int64_t)L.rows.size(), n = (int64_t)L.cols.size();
+    if (h->cplx) {
+        cd *out = (cd *)outv;
+        if (L.adm) {
+            const cd *U = reinterpret_cast<const cd *>(L.U.data());
+            const cd *V = reinterpret_cast<const cd *>(L.V.data());
+            for (int64_t r = 0; r < m; ++r)
+                for (int64_t c = 0; c < n; ++c) {
+                    cd s = 0;
+                    for (int l = 0; l < L.rank; ++l) s += U[(size_t)l * m + r] * V[(size_t)l * n + c];
+                    out[r * n + c] = s;
+                }
+        } else if (!L.D.empty()) {
+            std::memcpy(out, L.D.data(), sizeof(cd) * m * n);
+        } else {
+            std::fill(out, out + m * n, cd(0));
+        }
+    } else {
+        double *out = (double *)outv;
+        if (L.adm) {
+            for (int64_t r = 0; r < m; ++r)
+                for (int64_t c = 0; c < n; ++c) {
+                    double s = 0;
+                    for (int l = 0; l < L.rank; ++l) s += L.U[(size_t)l * m + r] * L.V[(size_t)l * n + c];
+                    out[r * n + c] = s;
+                }
+        } else if (!L.D.empty()) {
+            std::memcpy(out, L.D.data(), sizeof(double) * m * n);
+        } else {
+            std::fill(out, out + m * n, 0.0);
+        }
+    }
+    return BEM_OK;
+}
+
+int hmat_stats(const bem_hmat *h, bem_hmat_stats *s)
+{
+    if (!h || !s) return fail(BEM_E_ARG, "null argument");
+    *s = h->st;
+    return BEM_OK;
+}
+
+int hmat_destroy(bem_hmat *h)
+{
+    delete h;
+    return BEM_OK;
+}
+
+}  // namespace bem

@@ -1,0 +1,347 @@
+// Mesh residency and request expansion (host side).
+//
+// A request A[rows, cols] becomes work for the entry kernels:
+//  * P0 (dof = triangle): entry (i, j) is the single triangle pair (T_i, T_j).
+//    The longer of the two index lists runs across the lanes of a tile, the
+//    other one is the tile's fixed side.
+//  * P1 (dof = vertex, hat functions, Section 2): entry (I, J) sums over the
+//    triangles m around I and n around J.  With the column side on the lanes,
+//    the lane list is the set of distinct triangles around the requested
+//    columns (ascending), every lane triangle serving each of its requested
+//    vertices; the fixed side of a tile is the star of one row vertex.  A
+//    segment list maps every requested column to its (lane triangle, local
+//    vertex) partial sums in ascending triangle order, which fixes the order
+//    of the final per-entry sum.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "bem_internal.hpp"
+
+namespace bem {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+const char *last_error() { return g_last_error.c_str(); }
+
+double now_seconds()
+{
+    using clk = std::chrono::steady_clock;
+    return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+bool is_complex_op(int op) { return op == BEM_HELMHOLTZ_SLP || op == BEM_HELMHOLTZ_DLP; }
+
+size_t out_elem_bytes(int op, int prec)
+{
+    const size_t real = prec == BEM_FP32 ? 4 : 8;
+    return is_complex_op(op) ? 2 * real : real;
+}
+
+namespace {
+
+// Distinct triangles around a list of vertices, ascending; slot_of maps a
+// triangle to its position.  Scratch is per thread.
+struct StarScratch {
+    std::vector<int32_t> slot_of;
+    std::vector<uint32_t> stamp;
+    uint32_t gen = 0;
+    void prepare(int64_t nt)
+    {
+        if ((int64_t)stamp.size() < nt) {
+            stamp.assign(nt, 0);
+            slot_of.assign(nt, -1);
+            gen = 0;
+        }
+        if (++gen == 0) {
+            std::fill(stamp.begin(), stamp.end(), 0);
+            gen = 1;
+        }
+    }
+};
+thread_local StarScratch g_scratch;
+
+void expand_p1_side(const bem_mesh &m, const std::vector<int32_t> &lane_dofs, const std::vector<int32_t> &fix_dofs,
+                    Request &r)
+{
+    StarScratch &sc = g_scratch;
+    sc.prepare(m.nt);
+    std::vector<int32_t> &lane = r.lane;
+    lane.clear();
+    for (int32_t v : lane_dofs)
+        for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) {
+            const int32_t t = m.star[s] >> 2;
+            if (sc.stamp[t] != sc.gen) {
+                sc.stamp[t] = sc.gen;
+                lane.push_back(t);
+            }
+        }
+    std::sort(lane.begin(), lane.end());
+    for (size_t i = 0; i < lane.size(); ++i) sc.slot_of[lane[i]] = (int32_t)i;
+    r.seg_ptr.resize(lane_dofs.size() + 1);
+    r.seg.clear();
+    r.seg_ptr[0] = 0;
+    for (size_t c = 0; c < lane_dofs.size(); ++c) {
+        const int32_t v = lane_dofs[c];
+        for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) {
+            const int32_t pk = m.star[s];
+            r.seg.push_back((sc.slot_of[pk >> 2] << 2) | (pk & 3));
+        }
+        r.seg_ptr[c + 1] = (int32_t)r.seg.size();
+    }
+    r.fix.resize(fix_dofs.size() + 1);
+    r.fstar.clear();
+    r.fix[0] = 0;
+    for (size_t f = 0; f < fix_dofs.size(); ++f) {
+        const int32_t v = fix_dofs[f];
+        for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) r.fstar.push_back(m.star[s]);
+        r.fix[f + 1] = (int32_t)r.fstar.size();
+    }
+    r.nlane = (int64_t)lane.size();
+    r.nfix = (int64_t)fix_dofs.size();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int expand_request(Request &r)
+{
+    const bem_mesh &m = *r.mesh;
+    if (r.op < 0 || r.op > 3) return fail(BEM_E_ARG, "unknown operator");
+    if (r.space != BEM_P0 && r.space != BEM_P1) return fail(BEM_E_ARG, "unknown space");
+    if (r.prec != BEM_FP32 && r.prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
+    if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP) return fail(BEM_E_ARG, "unknown near-field policy");
+    if (is_complex_op(r.op)) {
+        if (!(std::isfinite(r.k) && r.k > 0.0)) return fail(BEM_E_ARG, "Helmholtz needs a finite wavenumber k > 0");
+    } else if (r.k != 0.0) {
+        return fail(BEM_E_ARG, "Laplace needs k = 0");
+    }
+    const int64_t ndof = r.space == BEM_P0 ? m.nt : m.nv;
+    for (int32_t v : r.rows)
+        if (v < 0 || v >= ndof) return fail(BEM_E_ARG, "row index out of range");
+    for (int32_t v : r.cols)
+        if (v < 0 || v >= ndof) return fail(BEM_E_ARG, "column index out of range");
+    if (r.nrows > INT32_MAX || r.ncols > INT32_MAX) return fail(BEM_E_ARG, "request dimension too large");
+
+    r.elem_bytes = out_elem_bytes(r.op, r.prec);
+    r.rowfix = r.ncols >= r.nrows ? 1 : 0;
+    const std::vector<int32_t> &fix_dofs = r.rowfix ? r.rows : r.cols;
+    const std::vector<int32_t> &lane_dofs = r.rowfix ? r.cols : r.rows;
+    const int64_t q2 = (int64_t)m.q * m.q;
+    if (r.space == BEM_P0) {
+        r.fix = fix_dofs;
+        r.lane = lane_dofs;
+        r.fstar.clear();
+        r.seg.clear();
+        r.seg_ptr.clear();
+        r.nfix = (int64_t)fix_dofs.size();
+        r.nlane = (int64_t)lane_dofs.size();
+        r.part_elem_bytes = 0;
+        r.part_bytes = 0;
+        r.evals = r.nfix * r.nlane * q2;
+        r.ntiles = r.nfix * ((r.nlane + kTileLanes - 1) / kTileLanes);
+        r.nrtiles = 0;
+    } else {
+        expand_p1_side(m, lane_dofs, fix_dofs, r);
+        const size_t real = r.prec == BEM_FP32 ? 8 : 8;  // (hi, lo) float pair or one double
+        r.part_elem_bytes = is_complex_op(r.op) ? 2 * real : real;
+        r.part_bytes = (size_t)r.nfix * r.nlane * 3 * r.part_elem_bytes;
+        r.evals = (int64_t)r.fstar.size() * r.nlane * q2;
+        r.ntiles = r.nfix * ((r.nlane + kTileLanes - 1) / kTileLanes);
+        r.nrtiles = (r.entries() + kReduceBlock - 1) / kReduceBlock;
+    }
+    r.in_bytes = align256(4 * (r.fix.size() + r.fstar.size() + r.lane.size() + r.seg_ptr.size() + r.seg.size()));
+    r.out_bytes = align256((size_t)r.entries() * r.elem_bytes);
+    r.part_bytes = align256(r.part_bytes);
+    return BEM_OK;
+}
+
+size_t request_bytes(const Request &r)
+{
+    return sizeof(ReqDev) + 256 + r.in_bytes + r.out_bytes + r.part_bytes + (size_t)r.ntiles * sizeof(Tile) +
+           (size_t)r.nrtiles * sizeof(RTile) + 64;
+}
+
+void place_request(Request &r, char *host_base, char *dev_base, size_t off_in, size_t off_out, size_t off_part,
+                   size_t off_status, ReqDev &d)
+{
+    const bem_mesh &m = *r.mesh;
+    r.off_in = off_in;
+    r.off_out = off_out;
+    r.off_part = off_part;
+    r.off_status = off_status;
+    char *h = host_base + off_in;
+    char *dv = dev_base + off_in;
+    auto put = [&](const std::vector<int32_t> &v) -> const int32_t * {
+        if (v.empty()) return nullptr;
+        std::memcpy(h, v.data(), 4 * v.size());
+        const int32_t *dp = reinterpret_cast<const int32_t *>(dv);
+        h += 4 * v.size();
+        dv += 4 * v.size();
+        return dp;
+    };
+    d.g32 = m.d_g32;
+    d.g64 = m.d_g64;
+    d.vtx = m.d_vtx;
+    d.fix = put(r.fix);
+    d.fstar = put(r.fstar);
+    d.lane = put(r.lane);
+    d.seg_ptr = put(r.seg_ptr);
+    d.seg = put(r.seg);
+    d.part = r.part_bytes ? dev_base + off_part : nullptr;
+    d.out = dev_base + off_out;
+    d.status = reinterpret_cast<int32_t *>(dev_base + off_status);
+    if (r.rowfix) {
+        d.sf = r.ncols;
+        d.sl = 1;
+    } else {
+        d.sf = 1;
+        d.sl = r.ncols;
+    }
+    d.nrows = (int32_t)r.nrows;
+    d.ncols = (int32_t)r.ncols;
+    d.nlane = (int32_t)r.nlane;
+    d.rowfix = r.rowfix;
+    d.near_error = r.near == BEM_NEAR_ERROR ? 1 : 0;
+    d.pad0 = 0;
+    d.k = r.k;
+    d.kk = r.k / (2.0 * 3.14159265358979323846);
+}
+
+void make_tiles(const Request &r, int32_t req_index, std::vector<Tile> &tiles, std::vector<RTile> &rtiles)
+{
+    for (int64_t f = 0; f < r.nfix; ++f)
+        for (int64_t l0 = 0; l0 < r.nlane; l0 += kTileLanes) {
+            Tile t;
+            t.req = req_index;
+            t.fixed = (int32_t)f;
+            t.lane0 = (int32_t)l0;
+            t.nlanes = (int32_t)std::min<int64_t>(kTileLanes, r.nlane - l0);
+            tiles.push_back(t);
+        }
+    if (r.space == BEM_P1) {
+        const int64_t n = r.entries();
+        for (int64_t e0 = 0; e0 < n; e0 += kReduceBlock) {
+            RTile t;
+            t.req = req_index;
+            t.count = (int32_t)std::min<int64_t>(kReduceBlock, n - e0);
+            t.e0 = e0;
+            rtiles.push_back(t);
+        }
+    }
+}
+
+}  // namespace bem
+
+// ---------------------------------------------------------------------------
+// Mesh creation / destruction.
+using namespace bem;
+
+namespace bem {
+int mesh_create_impl(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, int q, bem_mesh **out)
+{
+    if (!xyz || !tri || !out) return fail(BEM_E_ARG, "null pointer");
+    if (nv < 3 || nt < 1) return fail(BEM_E_ARG, "mesh needs at least 3 vertices and 1 triangle");
+    if (q != 4 && q != 6) return fail(BEM_E_ARG, "quad_points must be 4 or 6");
+    if (nt > (INT32_MAX >> 2) || nv > INT32_MAX) return fail(BEM_E_ARG, "mesh too large for 32-bit indices");
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(xyz[i])) return fail(BEM_E_ARG, "non-finite vertex coordinate");
+    for (int64_t i = 0; i < 3 * nt; ++i)
+        if (tri[i] < 0 || tri[i] >= nv) return fail(BEM_E_ARG, "triangle vertex index out of range");
+    for (int64_t t = 0; t < nt; ++t)
+        if (tri[3 * t] == tri[3 * t + 1] || tri[3 * t] == tri[3 * t + 2] || tri[3 * t + 1] == tri[3 * t + 2])
+            return fail(BEM_E_ARG, "triangle with a repeated vertex");
+
+    bem_mesh *m = new (std::nothrow) bem_mesh();
+    if (!m) return fail(BEM_E_OOM, "host allocation failed");
+    m->nv = nv;
+    m->nt = nt;
+    m->q = q;
+    m->xyz.assign(xyz, xyz + 3 * nv);
+    m->tri.assign(tri, tri + 3 * nt);
+    m->star_ptr.assign(nv + 1, 0);
+    for (int64_t i = 0; i < 3 * nt; ++i) m->star_ptr[tri[i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) m->star_ptr[v + 1] += m->star_ptr[v];
+    m->star.resize(3 * nt);
+    {
+        std::vector<int64_t> fill(m->star_ptr.begin(), m->star_ptr.end() - 1);
+        for (int64_t t = 0; t < nt; ++t)
+            for (int k = 0; k < 3; ++k) m->star[fill[tri[3 * t + k]]++] = (int32_t)((t << 2) | k);
+    }
+    for (int64_t v = 0; v < nv; ++v) m->max_star = std::max<int>(m->max_star, (int)(m->star_ptr[v + 1] - m->star_ptr[v]));
+    double sj = 0.0, se = 0.0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const double *a = &xyz[3 * tri[3 * t]], *b = &xyz[3 * tri[3 * t + 1]], *c = &xyz[3 * tri[3 * t + 2]];
+        double e1[3], e2[3];
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = b[d] - a[d];
+            e2[d] = c[d] - a[d];
+        }
+        const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        sj += std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        double e3[3] = {c[0] - b[0], c[1] - b[1], c[2] - b[2]};
+        se += std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]) + std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]) +
+              std::sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2]);
+    }
+    m->mean_J = sj / nt;
+    m->mean_edge = se / (3.0 * nt);
+
+    hipError_t e = hipGetDevice(&m->device);
+    double *d_xyz = nullptr;
+    int32_t *d_tri = nullptr, *d_bad = nullptr;
+    const size_t b32 = sizeof(float) * kGeo32Stride * nt, b64 = sizeof(double) * kGeo64Stride * nt,
+                 bv = sizeof(int4) * nt;
+    int rc = BEM_OK;
+    int32_t bad = 0;
+    if (e == hipSuccess) e = hipMalloc(&m->d_g32, b32);
+    if (e == hipSuccess) e = hipMalloc(&m->d_g64, b64);
+    if (e == hipSuccess) e = hipMalloc(&m->d_vtx, bv);
+    if (e == hipSuccess) e = hipMalloc(&d_xyz, sizeof(double) * 3 * nv);
+    if (e == hipSuccess) e = hipMalloc(&d_tri, sizeof(int32_t) * 3 * nt);
+    if (e == hipSuccess) e = hipMalloc(&d_bad, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(d_xyz, xyz, sizeof(double) * 3 * nv, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_tri, tri, sizeof(int32_t) * 3 * nt, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_bad, &bad, sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_geometry(d_xyz, d_tri, nt, q, m->d_g32, m->d_g64, m->d_vtx, d_bad, 0);
+    if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (d_xyz) (void)hipFree(d_xyz);
+    if (d_tri) (void)hipFree(d_tri);
+    if (d_bad) (void)hipFree(d_bad);
+    if (e != hipSuccess)
+        rc = fail(e == hipErrorOutOfMemory ? BEM_E_OOM : BEM_E_DEVICE, std::string("mesh upload: ") + hipGetErrorString(e));
+    else if (bad)
+        rc = fail(BEM_E_ARG, "degenerate triangle (zero area)");
+    if (rc != BEM_OK) {
+        if (m->d_g32) (void)hipFree(m->d_g32);
+        if (m->d_g64) (void)hipFree(m->d_g64);
+        if (m->d_vtx) (void)hipFree(m->d_vtx);
+        delete m;
+        return rc;
+    }
+    m->dev_bytes = b32 + b64 + bv;
+    *out = m;
+    return BEM_OK;
+}
+
+int mesh_destroy_impl(bem_mesh *m)
+{
+    if (!m) return fail(BEM_E_ARG, "null mesh");
+    if (m->inflight.load() != 0) return fail(BEM_E_BUSY, "requests on this mesh are still in flight");
+    (void)hipFree(m->d_g32);
+    (void)hipFree(m->d_g64);
+    (void)hipFree(m->d_vtx);
+    delete m;
+    return BEM_OK;
+}
+}  // namespace bem

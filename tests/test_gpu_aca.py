@@ -1,0 +1,86 @@
+"""GPU: ACA on device-evaluated rows/columns and H-matrix assembly.
+
+ACA factors are not unique once FP32 entries move a pivot, so the checks
+compare reconstructions: against the dense oracle block (error within a
+small multiple of the tolerance), against the oracle's own ACA on FP64
+entries (same pivots, same product), and ranks of FP32 vs FP64 entries.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import oracle.aca as OA
+from paper_1711_01897_amd import bem, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sphere4():
+    xyz, tri = inputs.icosphere(4)
+    return xyz, tri, bem.mesh_create(xyz, tri, 6), O.OracleMesh(xyz, tri, 6)
+
+
+def largest_admissible(xyz, tri, space, leaf, count):
+    perm, ranges, blocks = bem.partition(xyz, tri, space, leaf, 1.0)
+    adm = [(perm[ranges[t, 0]:ranges[t, 1]], perm[ranges[s, 0]:ranges[s, 1]]) for t, s, ok in blocks if ok]
+    adm.sort(key=lambda p: -(p[0].size * p[1].size))
+    return adm[:count]
+
+
+@pytest.mark.parametrize("op,space,k", [(bem.LAPLACE_SLP, bem.P1, 0.0), (bem.LAPLACE_DLP, bem.P1, 0.0),
+                                        (bem.HELMHOLTZ_SLP, bem.P0, 6.0)])
+def test_aca_block_against_dense_and_oracle_aca(sphere4, op, space, k):
+    xyz, tri, mesh, om = sphere4
+    for rows, cols in largest_admissible(xyz, tri, space, 40, 3):
+        D = om.entries(op, space, k, rows, cols, near=O.NEAR_ERROR)
+        za = 1e-13 * np.abs(D).max()
+        U, V, ent = bem.aca_block(mesh, op, space, k, rows, cols, tol=1e-6, max_rank=120, prec=bem.FP64,
+                                  zero_abs=za)
+        err = np.linalg.norm(D - U @ V.T) / np.linalg.norm(D)
+        assert err <= 1e-5, err
+        Uo, Vo, piv, _ = OA.aca(lambda i: D[i], lambda j: D[:, j], rows.size, cols.size, 1e-6, 120, za,
+                                dtype=D.dtype)
+        assert U.shape[1] == Uo.shape[1]
+        assert np.abs(U @ V.T - Uo @ Vo.T).max() <= 1e-9 * np.abs(D).max()
+        assert ent == U.shape[1] * (rows.size + cols.size)
+        # FP32 entries with compensated accumulation: same accuracy class
+        U32, V32, _ = bem.aca_block(mesh, op, space, k, rows, cols, tol=1e-5, max_rank=120, prec=bem.FP32)
+        err32 = np.linalg.norm(D - U32 @ V32.T) / np.linalg.norm(D)
+        assert err32 <= 1e-4, err32
+        U64, _, _ = bem.aca_block(mesh, op, space, k, rows, cols, tol=1e-5, max_rank=120, prec=bem.FP64)
+        assert U32.shape[1] <= int(1.2 * U64.shape[1]) + 1
+
+
+def test_aca_block_rejects_near_pairs(sphere4):
+    xyz, tri, mesh, om = sphere4
+    with pytest.raises(bem.NearFieldError):
+        bem.aca_block(mesh, bem.LAPLACE_SLP, bem.P0, 0.0, np.arange(30), np.arange(20, 60))
+
+
+@pytest.mark.parametrize("op,space,k,prec", [(bem.LAPLACE_SLP, bem.P1, 0.0, bem.FP32),
+                                             (bem.LAPLACE_DLP, bem.P1, 0.0, bem.FP64),
+                                             (bem.HELMHOLTZ_SLP, bem.P0, 4.0, bem.FP32)])
+def test_hmat_matvec_against_dense(op, space, k, prec):
+    xyz, tri = inputs.icosphere(3)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    H = bem.hmat_assemble(mesh, op, space, k, leaf_size=32, eta=1.0, aca_tol=1e-6, max_rank=100, n_workers=4,
+                          blocks_per_worker=8, prec=prec, dense_mode=1)
+    st = H.stats()
+    n = st["ndof"]
+    A = om.entries(op, space, k, np.arange(n), np.arange(n), near=O.NEAR_SKIP)
+    rng = np.random.Generator(np.random.PCG64(3))
+    x = rng.normal(size=n) + (1j * rng.normal(size=n) if np.iscomplexobj(A) else 0)
+    y = H.matvec(x)
+    err = np.linalg.norm(y - A @ x) / np.linalg.norm(A @ x)
+    print(st, err)
+    assert err <= 2e-5
+    assert st["admissible_blocks"] > 0 and st["dense_blocks"] > 0
+    # every block reconstructs its part of the dense matrix
+    for b in range(0, st["admissible_blocks"] + st["dense_blocks"], 7):
+        adm, rows, cols, rank, dense = H.block(b)
+        ref = A[np.ix_(rows, cols)]
+        assert np.abs(dense - ref).max() <= 1e-4 * max(np.abs(ref).max(), 1e-300)
+    H.destroy()
+    mesh.destroy()
