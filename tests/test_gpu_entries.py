@@ -154,7 +154,7 @@ def test_argument_errors_and_edge_cases(sphere2):
     assert bem.eval_entries(mesh, bem.HELMHOLTZ_DLP, bem.P1, 2.0, [3], []).shape == (1, 0)
     # duplicated indices give duplicated rows and columns
     rows = np.array([40, 40, 41], dtype=np.int32)
-    cols = np.array([100, 200, 100, 300], dtype=np.int32)
+    cols = np.array([100, 150, 100, 160], dtype=np.int32)
     for space in (bem.P0, bem.P1):
         got = bem.eval_entries(mesh, bem.LAPLACE_DLP, space, 0.0, rows, cols)
         assert np.array_equal(got[0], got[1]) and np.array_equal(got[:, 0], got[:, 2])
