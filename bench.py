@@ -1,0 +1,262 @@
+"""Benchmark: H-matrix (ACA) assembly of the Laplace single- and double-layer
+operators, P1, on the level-6 icosphere (81,920 triangles, 40,962 vertices),
+leaf size 100, eta = 1, ACA tolerance 1e-5, every ACA row and column
+evaluated on the GPU through the request server.
+
+One step = both assemblies with FP32 (compensated) entries.  The timed steps
+give `value` = ACA entries evaluated per second of wall time (whole job:
+tree, host ACA in FP64, batching, device kernels, copies).  The same
+assembly with plain FP64 entries is timed beside it.  The request latencies
+(submit -> completion) of the timed steps give p50/p99.
+
+The roofline object is for the dominant kernel (largest summed duration):
+algorithmic flops per launch / mean launch duration, both from the server's
+HIP events around each launch on its stream.  `cpu_baseline` times the FP64
+oracle on a bounded sample of the same ACA row requests on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic flops per kernel evaluation (one pair of quadrature points):
+# d = x - y (3), r^2 (1 mul + 2 fma = 5), 1/r (1), weighted accumulation
+# (fma = 2) -> 11; double layer + r^-3 (2 mul) -> 13; P1 adds the three
+# basis-weighted accumulations, 3 fma per point of the outer loop, i.e.
+# 1 flop per evaluation with 6 points -> 12 / 14.  Helmholtz adds r (1),
+# the FP64 phase (mul, round, subtract: 3), sin and cos (2) and the complex
+# accumulation (1 mul + 2 fma: 5) -> 21 / 27 (P0), +1 for P1.
+FLOPS_PER_EVAL = {(0, 0): 11, (1, 0): 13, (2, 0): 21, (3, 0): 27,
+                  (0, 1): 12, (1, 1): 14, (2, 1): 22, (3, 1): 28}
+# Non-packed FP32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
+PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9
+PEAK_FP32_PACKED = 2 * PEAK_FP32_VALU
+KERNEL_NAMES = {0: "k_p0", 1: "k_p1"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_icosphere6_p1.json")
+
+
+def kernel_source_hash():
+    with open(os.path.join(ROOT, "paper_1711_01897_amd", "csrc", "entries.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workers", type=int, default=12)
+    ap.add_argument("--blocks-per-worker", type=int, default=64)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
+    return ap.parse_args()
+
+
+def copy_calibration(nbytes):
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "dispatches": 5}))
+
+
+def assemble_step(bem, mesh, prec, args):
+    out = {"entries": 0, "requests": 0, "rank_sum": 0, "rank_max": 0, "blocks": 0, "phases": {}}
+    for op in (bem.LAPLACE_SLP, bem.LAPLACE_DLP):
+        H = bem.hmat_assemble(mesh, op, bem.P1, 0.0, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200,
+                              n_workers=args.workers, blocks_per_worker=args.blocks_per_worker, prec=prec,
+                              dense_mode=0)
+        st = H.stats()
+        out["entries"] += st["aca_entries"]
+        out["requests"] += st["aca_requests"]
+        out["rank_sum"] += st["rank_sum"]
+        out["rank_max"] = max(out["rank_max"], st["rank_max"])
+        out["blocks"] += st["admissible_blocks"]
+        for key in ("seconds", "partition_seconds", "setup_seconds", "aca_seconds", "worker_busy_seconds"):
+            out["phases"][key] = out["phases"].get(key, 0.0) + st[key]
+        H.destroy()
+    return out
+
+
+def timed(bem, mesh, prec, steps, warmup, args):
+    import torch
+    for _ in range(warmup):
+        assemble_step(bem, mesh, prec, args)
+    bem.server_stats(reset=True)
+    bem.server_kernel_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot = {"entries": 0, "requests": 0, "rank_sum": 0, "rank_max": 0, "blocks": 0, "phases": {}}
+    for _ in range(steps):
+        s = assemble_step(bem, mesh, prec, args)
+        for k in ("entries", "requests", "rank_sum", "blocks"):
+            tot[k] += s[k]
+        for k, v in s["phases"].items():
+            tot["phases"][k] = tot["phases"].get(k, 0.0) + v / steps
+        tot["rank_max"] = max(tot["rank_max"], s["rank_max"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return dt, tot, bem.server_stats(), bem.server_kernel_stats()
+
+
+def roofline(kstats):
+    main = [k for k in kstats if not k["reduce"]]
+    if not main:
+        return None, None
+    dom = max(main, key=lambda k: k["seconds"])
+    flops = dom["pair_evals"] * FLOPS_PER_EVAL[(dom["op"], dom["space"])]
+    per_launch = flops / dom["launches"]
+    mean_s = dom["seconds"] / dom["launches"]
+    achieved = per_launch / mean_s / 1e12
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("kernel_source_hash") == kernel_source_hash():
+            traffic = t.get("bytes_per_launch")
+    name = "%s_f%s<op=%d,Q=%d,rowfix=%d>" % (KERNEL_NAMES[dom["space"]], "32" if dom["prec"] == 1 else "64",
+                                            dom["op"], dom["quad_points"], dom["rowfix"])
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_VALU / 1e12, 1),
+            "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_VALU, 4), "traffic": traffic,
+            "kernel": name, "launches": dom["launches"], "mean_launch_us": round(mean_s * 1e6, 2),
+            "flops_per_launch": per_launch, "flops_per_eval": FLOPS_PER_EVAL[(dom["op"], dom["space"])],
+            "frac_of_packed_fp32_peak": round(achieved * 1e12 / PEAK_FP32_PACKED, 4)}
+    return roof, dom
+
+
+def cpu_baseline(bem, inputs, mesh, xyz, tri, seconds):
+    """FP64 oracle on a seeded sample of the benchmark's ACA row/column
+    requests (single layer, P1), all host threads; stops after `seconds`.
+    Also returns the largest FP32-vs-oracle normwise error on that sample."""
+    import numpy as np
+    import oracle
+
+    om = oracle.OracleMesh(xyz, tri, 6)
+    perm, ranges, blocks = bem.partition(xyz, tri, bem.P1, 100, 1.0)
+    adm = blocks[blocks[:, 2] == 1]
+    rng = inputs.rng(inputs.SEED_SAMPLING)
+    entries = 0
+    spent = 0.0
+    nreq = 0
+    worst = 0.0
+    while spent < seconds:
+        b = adm[int(rng.integers(adm.shape[0]))]
+        rows = perm[ranges[b[0], 0]:ranges[b[0], 1]]
+        cols = perm[ranges[b[1], 0]:ranges[b[1], 1]]
+        op = oracle.LAPLACE_SLP if nreq % 2 == 0 else oracle.LAPLACE_DLP
+        if nreq % 4 < 2:
+            r, c = rows[int(rng.integers(rows.size)):][:1], cols
+        else:
+            r, c = rows, cols[int(rng.integers(cols.size)):][:1]
+        t0 = time.perf_counter()
+        ref = om.entries(op, oracle.P1, 0.0, r, c)
+        spent += time.perf_counter() - t0
+        entries += ref.size
+        nreq += 1
+        got = bem.eval_entries(mesh, op, bem.P1, 0.0, r, c, prec=bem.FP32, near=bem.NEAR_ERROR)
+        worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    return {"value": entries / spent, "unit": "entries/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{nreq} ACA row/column requests (Laplace SLP and DLP, P1) of seeded admissible blocks of "
+                      f"the same partition, {entries} entries, {spent:.1f} s"}, worst
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the workload has no multi-GPU path in this build "
+              "(blocks would be routed to independent per-GPU servers).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    from paper_1711_01897_amd import bem, inputs
+
+    xyz, tri = inputs.icosphere(6)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    print(f"[bench] mesh {tri.shape[0]} triangles / {xyz.shape[0]} vertices resident", file=sys.stderr, flush=True)
+
+    dt, tot, sst, kst = timed(bem, mesh, bem.FP32, args.steps, args.warmup, args)
+    print(f"[bench] fp32: {args.steps} steps in {dt:.3f} s, {tot['entries']} entries", file=sys.stderr, flush=True)
+    roof, dom = roofline(kst)
+
+    fp64 = None
+    if not args.no_fp64:
+        dt64, tot64, sst64, kst64 = timed(bem, mesh, bem.FP64, 1, 0, args)
+        fp64 = {"value": tot64["entries"] / dt64, "unit": "entries/s", "seconds_per_step": dt64,
+                "latency_p50_ms": sst64["latency_p50"] * 1e3, "latency_p99_ms": sst64["latency_p99"] * 1e3,
+                "rank_sum": tot64["rank_sum"]}
+        print(f"[bench] fp64: 1 step in {dt64:.3f} s", file=sys.stderr, flush=True)
+
+    cpu = None
+    worst = None
+    if not args.no_cpu_baseline:
+        cpu, worst = cpu_baseline(bem, inputs, mesh, xyz, tri, args.cpu_seconds)
+        print(f"[bench] cpu baseline {cpu['value']:.3e} entries/s on {cpu['cores']} threads", file=sys.stderr,
+              flush=True)
+
+    value = tot["entries"] / dt
+    line = {
+        "metric": "weak-form entries/sec FP32 vs FP64 at stated rel err; p50/p99 ACA request latency",
+        "value": value,
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "icosphere level 6 (81920 triangles, 40962 vertices), Laplace single+double layer, P1, "
+                        "6-point rule, H-matrix leaf 100, eta 1.0, ACA tol 1e-5, every ACA row/column on the GPU "
+                        "through the request server, FP32 compensated entries",
+            "aca_entries_per_step": tot["entries"] // args.steps,
+            "aca_requests_per_step": tot["requests"] // args.steps,
+            "admissible_blocks_per_step": tot["blocks"] // args.steps,
+            "mean_rank": tot["rank_sum"] / max(1, tot["blocks"]),
+            "max_rank": tot["rank_max"],
+            "workers": args.workers,
+            "blocks_per_worker": args.blocks_per_worker,
+        },
+        "latency_p50_ms": sst["latency_p50"] * 1e3,
+        "latency_p99_ms": sst["latency_p99"] * 1e3,
+        "fused_launch_batches": sst["batches"],
+        "requests_per_batch": sst["requests"] / max(1, sst["batches"]),
+        "assembly_seconds_per_step": tot["phases"],
+        "server_seconds_per_step": {"dispatch": sst["dispatch_seconds"] / args.steps,
+                                    "complete": sst["complete_seconds"] / args.steps,
+                                    "event_wait": sst["wait_seconds"] / args.steps,
+                                    "entry_kernels": sst["kernel_seconds"] / args.steps,
+                                    "p1_reduce_kernels": sst["kernel_seconds_p1_reduce"] / args.steps},
+        "kernel_busy_fraction": sst["kernel_seconds"] / dt if dt > 0 else None,
+        "fp64": fp64,
+        "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
+        "max_rel_err_sampled": worst,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -167,10 +167,31 @@ typedef struct {
     double kernel_seconds;   /* sum of entry-kernel durations measured with HIP events */
     double kernel_seconds_p1_reduce;
     int64_t kernel_launches; /* entry-kernel launches timed */
+    double dispatch_seconds; /* host time spent staging and enqueueing batches */
+    double complete_seconds; /* host time spent completing batches (after their event) */
+    double wait_seconds;     /* completion-thread time spent waiting for batch events */
 } bem_server_stats_t;
 
 /* Statistics since the last reset; reset != 0 clears them afterwards. */
 int bem_server_stats(bem_server_stats_t *stats, int reset);
+
+/* Per kernel variant: launches, durations (HIP events recorded around each
+ * launch on the server's stream) and the work those launches covered. */
+typedef struct {
+    int32_t op, space, prec, quad_points;
+    int32_t rowfix;            /* 1: the test side is fixed per tile (lanes run over trial triangles) */
+    int32_t reduce;            /* 1: P1 per-entry reduction launch (op/space/q not meaningful) */
+    int64_t launches;
+    int64_t entries;           /* entries of the requests these launches served */
+    int64_t pair_evals;        /* Q^2 x (fixed, lane) triangle pairs; vertex-sharing pairs, which are
+                                  skipped, are included (there are none in admissible blocks) */
+    int64_t triangle_loads;    /* lane-triangle geometry records gathered (one per lane per tile) */
+    double seconds;            /* summed launch durations */
+} bem_kernel_stats_t;
+
+/* Copies up to max_entries variant records into out, sets *count to the
+ * number of variants recorded; reset != 0 clears them afterwards. */
+int bem_server_kernel_stats(bem_kernel_stats_t *out, int max_entries, int *count, int reset);
 
 /* ---- adaptive cross approximation --------------------------------------- */
 typedef struct {
@@ -250,6 +271,10 @@ typedef struct {
     int32_t rank_max;
     size_t bytes;              /* storage of U, V and dense leaves */
     double seconds;            /* wall time of the assembly */
+    double partition_seconds;  /* cluster and block tree */
+    double setup_seconds;      /* lane sets of the clusters (host expansion + upload), leaf lists */
+    double aca_seconds;        /* worker phase: ACA and dense leaves */
+    double worker_busy_seconds;/* summed over workers: time spent outside waits */
 } bem_hmat_stats;
 int bem_hmat_stats_get(const bem_hmat *h, bem_hmat_stats *stats);
 

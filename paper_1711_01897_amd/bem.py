@@ -29,7 +29,7 @@ _NAMES = {E_ARG: "BEM_E_ARG", E_OOM: "BEM_E_OOM", E_DEVICE: "BEM_E_DEVICE", E_NE
 EXPORTS = [
     "bem_last_error", "bem_mesh_create", "bem_mesh_destroy", "bem_mesh_info", "bem_eval_entries", "bem_submit",
     "bem_ticket_wait", "bem_ticket_times", "bem_ticket_free", "bem_eval_entries_async", "bem_server_config",
-    "bem_server_stats", "bem_aca_block", "bem_aca_callback", "bem_partition", "bem_hmat_assemble",
+    "bem_server_stats", "bem_server_kernel_stats", "bem_aca_block", "bem_aca_callback", "bem_partition", "bem_hmat_assemble",
     "bem_hmat_matvec", "bem_hmat_stats_get", "bem_hmat_block_info", "bem_hmat_block_dense", "bem_hmat_destroy",
 ]
 
@@ -61,7 +61,16 @@ class ServerStats(ctypes.Structure):
                 ("kernel_evals", ctypes.c_int64), ("latency_p50", ctypes.c_double),
                 ("latency_p99", ctypes.c_double), ("latency_max", ctypes.c_double),
                 ("busy_seconds", ctypes.c_double), ("kernel_seconds", ctypes.c_double),
-                ("kernel_seconds_p1_reduce", ctypes.c_double), ("kernel_launches", ctypes.c_int64)]
+                ("kernel_seconds_p1_reduce", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
+                ("dispatch_seconds", ctypes.c_double), ("complete_seconds", ctypes.c_double),
+                ("wait_seconds", ctypes.c_double)]
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("space", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("quad_points", ctypes.c_int32), ("rowfix", ctypes.c_int32), ("reduce", ctypes.c_int32),
+                ("launches", ctypes.c_int64), ("entries", ctypes.c_int64), ("pair_evals", ctypes.c_int64),
+                ("triangle_loads", ctypes.c_int64), ("seconds", ctypes.c_double)]
 
 
 class AcaParams(ctypes.Structure):
@@ -78,7 +87,9 @@ class HmatStats(ctypes.Structure):
     _fields_ = [("ndof", ctypes.c_int64), ("admissible_blocks", ctypes.c_int64), ("dense_blocks", ctypes.c_int64),
                 ("aca_entries", ctypes.c_int64), ("dense_entries", ctypes.c_int64), ("aca_requests", ctypes.c_int64),
                 ("rank_sum", ctypes.c_int64), ("rank_max", ctypes.c_int32), ("bytes", ctypes.c_size_t),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("partition_seconds", ctypes.c_double),
+                ("setup_seconds", ctypes.c_double), ("aca_seconds", ctypes.c_double),
+                ("worker_busy_seconds", ctypes.c_double)]
 
 
 ROW_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int64, _dp)
@@ -114,6 +125,8 @@ def lib():
     L.bem_eval_entries_async.argtypes = entry_args + [_p, _p]
     L.bem_server_config.argtypes = [ctypes.c_size_t, ctypes.c_int]
     L.bem_server_stats.argtypes = [ctypes.POINTER(ServerStats), ctypes.c_int]
+    L.bem_server_kernel_stats.argtypes = [ctypes.POINTER(KernelStats), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.c_int]
     L.bem_aca_block.argtypes = [_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, _i32p, ctypes.c_int64, _i32p,
                                 ctypes.c_int64, ctypes.POINTER(AcaParams), ctypes.c_int, _p, _p, _i32p, _i64p]
     L.bem_aca_callback.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ROW_FN, COL_FN, _p,
@@ -261,6 +274,13 @@ def server_stats(reset: bool = False) -> dict:
     s = ServerStats()
     _check(lib().bem_server_stats(ctypes.byref(s), 1 if reset else 0))
     return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+
+def server_kernel_stats(reset: bool = False) -> list:
+    arr = (KernelStats * 256)()
+    n = ctypes.c_int()
+    _check(lib().bem_server_kernel_stats(arr, 256, ctypes.byref(n), 1 if reset else 0))
+    return [{f: getattr(arr[i], f) for f, _ in KernelStats._fields_} for i in range(min(n.value, 256))]
 
 
 # ---------------------------------------------------------------------------

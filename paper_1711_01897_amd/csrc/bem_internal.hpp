@@ -56,9 +56,9 @@ struct ReqDev {
     int64_t sf, sl;            // P0: out index = fixed_pos * sf + lane_pos * sl
     int32_t nrows, ncols;
     int32_t nlane;             // lane-side item count
+    int32_t nfix;              // fixed-side positions
     int32_t rowfix;
     int32_t near_error;
-    int32_t pad0;
     double k;                  // wavenumber
     double kk;                 // k / (2 pi): phase in turns per unit length
 };
@@ -89,8 +89,25 @@ struct Variant {
 };
 
 // Launchers (entries.hip).  Return hipSuccess or the launch error.
-hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const Tile *tiles, int ntiles, hipStream_t s);
-hipError_t launch_p1_reduce(int prec, bool cplx, const ReqDev *reqs, const RTile *tiles, int ntiles, hipStream_t s);
+// Tile tables are built on the device from per-group request lists and
+// exclusive prefix sums of per-request tile counts (gpre has ng + 1 entries).
+hipError_t launch_build_tiles(const ReqDev *reqs, const int32_t *greq, const int64_t *gpre, int ng, int64_t ntiles,
+                              Tile *tiles, hipStream_t s);
+hipError_t launch_build_rtiles(const ReqDev *reqs, const int32_t *greq, const int64_t *gpre, int ng, int64_t ntiles,
+                               RTile *tiles, hipStream_t s);
+// All groups of a batch in one launch: group g covers global tiles
+// [tile0, tile0 + ntiles) and writes Tile (kind 0) or RTile (kind 1) records.
+struct GroupDesc {
+    int64_t tile0, ntiles;
+    const int32_t *greq;
+    const int64_t *gpre;
+    void *tiles;
+    int32_t ng, kind;
+};
+hipError_t launch_build_all(const ReqDev *reqs, const GroupDesc *groups, int ngroups, int64_t total, hipStream_t s);
+hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const Tile *tiles, int64_t ntiles, hipStream_t s);
+hipError_t launch_p1_reduce(int prec, bool cplx, const ReqDev *reqs, const RTile *tiles, int64_t ntiles,
+                            hipStream_t s);
 hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, int q, float *g32, double *g64,
                            int4 *vtx, int32_t *bad, hipStream_t s);
 
@@ -139,6 +156,26 @@ struct bem_mesh {
 namespace bem {
 
 // ---------------------------------------------------------------------------
+// Lane side of a request: the triangles the lanes run over and, for P1, the
+// map from each requested lane-side dof to its (triangle, local vertex)
+// partial sums.  Computed once per dof list; device-resident copies are
+// shared by every request of an H-matrix block.
+struct LaneSet {
+    int64_t ndof = 0;                 // lane-side output positions
+    std::vector<int32_t> lane;        // P0: the dofs themselves; P1: distinct triangles, ascending
+    std::vector<int32_t> seg_ptr;     // P1: ndof + 1
+    std::vector<int32_t> seg;         // P1: packed (slot << 2 | local vertex)
+    size_t ints() const { return lane.size() + seg_ptr.size() + seg.size(); }
+};
+
+struct LaneRef {                      // device pointers of a resident LaneSet
+    const int32_t *lane = nullptr, *seg_ptr = nullptr, *seg = nullptr;
+    int64_t ndof = 0, nlane = 0, nseg = 0;
+};
+
+void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, LaneSet &ls);
+
+// ---------------------------------------------------------------------------
 // A request on its way through the server.
 struct Request {
     bem_mesh *mesh = nullptr;
@@ -146,15 +183,20 @@ struct Request {
     double k = 0.0;
     int64_t nrows = 0, ncols = 0;
     std::vector<int32_t> rows, cols;
-    void *out_host = nullptr;   // destination (host)
+    void *out_host = nullptr;   // destination (host); null with borrow = true
+    bool borrow = false;        // completion hands out a pointer into pinned staging instead
+    const void *result = nullptr;
+    void *batch = nullptr;      // batch holding a borrowed result
 
     // expansion
     int rowfix = 1;
-    std::vector<int32_t> fix, fstar, lane, seg_ptr, seg;
+    std::vector<int32_t> fix, fstar;   // fixed side
+    LaneSet own;                       // lane side, when not external
+    const LaneRef *ext = nullptr;      // device-resident lane side
     int64_t nfix = 0, nlane = 0;
     size_t elem_bytes = 0, part_elem_bytes = 0;
     size_t in_bytes = 0, out_bytes = 0, part_bytes = 0;
-    int64_t evals = 0;          // Q^2 x regular pairs (upper bound for P1 before adjacency)
+    int64_t evals = 0;          // Q^2 x (fixed, lane) triangle pairs, vertex-sharing pairs included
     int64_t ntiles = 0, nrtiles = 0;
 
     // completion
@@ -163,11 +205,15 @@ struct Request {
     bool done = false;
     int status = 0;
     double t_submit = 0.0, t_done = 0.0;
-    void (*on_done)(Request *, void *) = nullptr;
+    // Completion callback, called from the server's completion thread with all
+    // finished requests of one batch that share (on_done, cb_ctx); requests
+    // with a callback are not signalled through cv.
+    void (*on_done)(Request **, size_t, void *) = nullptr;
     void *cb_ctx = nullptr;
+    int64_t tag = 0;            // caller's bookkeeping
 
     // placement inside a batch
-    size_t off_in = 0, off_out = 0, off_part = 0, off_status = 0;
+    size_t off_out = 0, off_status = 0;
 
     int64_t entries() const { return nrows * ncols; }
 };
@@ -177,20 +223,25 @@ size_t out_elem_bytes(int op, int prec);
 
 // Validate and expand a request (host; runs on the submitting thread).
 int expand_request(Request &r);
+// Fast path for requests whose lane side is a resident LaneRef and whose
+// fixed side is a single dof known to be valid (H-matrix blocks).
+void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext);
 
-// Total device bytes a request needs inside a batch (inputs, outputs, partials).
+// Device bytes a request needs inside a batch (inputs, outputs, partials, tiles).
 size_t request_bytes(const Request &r);
 
+// Writes the request's inputs at host_base + off (staging) and fills its
+// descriptor with device addresses at dev_base + off; returns the bytes used.
+size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d);
+void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_part, size_t off_status,
+                       ReqDev &d);
+
 // Server
-int server_submit(Request *r);            // takes ownership until done
+int server_submit(Request *r);
+int server_submit_many(Request *const *rs, size_t n);
 int server_wait(Request *r, double timeout_s);
+void server_release(Request *r);           // return a borrowed result
 int server_ensure_started();
 bool server_running();
-
-// Fill ReqDev pointers for a request placed at `base` (device) and write its
-// inputs to `host_base` (staging).  Used by the server and the async path.
-void place_request(Request &r, char *host_base, char *dev_base, size_t off_in, size_t off_out,
-                   size_t off_part, size_t off_status, ReqDev &d);
-void make_tiles(const Request &r, int32_t req_index, std::vector<Tile> &tiles, std::vector<RTile> &rtiles);
 
 }  // namespace bem

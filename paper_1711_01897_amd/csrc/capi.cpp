@@ -12,6 +12,7 @@ int mesh_create_impl(const double *, int64_t, const int32_t *, int64_t, int, bem
 int mesh_destroy_impl(bem_mesh *);
 int server_configure(size_t, int);
 int server_stats(bem_server_stats_t *, int);
+int server_kernel_stats(bem_kernel_stats_t *, int, int *, int);
 int aca_block(bem_mesh *, int, int, double, const int32_t *, int64_t, const int32_t *, int64_t, const bem_aca_params *,
               int, void *, void *, int32_t *, int64_t *);
 int aca_callback(int64_t, int64_t, int, bem_row_fn, bem_col_fn, void *, const bem_aca_params *, void *, void *,
@@ -210,29 +211,35 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
         } else {
             for (size_t f = 0; f + 1 < r.fix.size(); ++f)
                 for (int32_t s = r.fix[f]; s < r.fix[f + 1]; ++s)
-                    for (int32_t t : r.lane)
+                    for (int32_t t : r.own.lane)
                         if (mesh->adjacent(r.fstar[s] >> 2, t))
                             return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
         }
     }
-    std::vector<Tile> tiles;
-    std::vector<RTile> rtiles;
-    make_tiles(r, 0, tiles, rtiles);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    // layout: descriptor | tile groups | inputs | status || partials | tiles | reduction tiles
     size_t off = 0;
     const size_t off_req = off;
     off = al(off + sizeof(ReqDev));
-    const size_t off_t = off;
-    off = al(off + sizeof(Tile) * tiles.size());
-    const size_t off_rt = off;
-    off = al(off + sizeof(RTile) * rtiles.size());
+    const size_t off_g = off;
+    off = al(off + 4);
+    const size_t off_gp = off;
+    off = al(off + 16);
+    const size_t off_rg = off;
+    off = al(off + 4);
+    const size_t off_rgp = off;
+    off = al(off + 16);
     const size_t off_in = off;
     off = al(off + r.in_bytes);
     const size_t off_status = off;
-    off = al(off + 256);
+    off = al(off + 4);
     const size_t in_total = off;
     const size_t off_part = off;
     off = al(off + r.part_bytes);
+    const size_t off_t = off;
+    off = al(off + sizeof(Tile) * (size_t)r.ntiles);
+    const size_t off_rt = off;
+    off = al(off + sizeof(RTile) * (size_t)r.nrtiles);
     // descriptors go through pinned staging that is released once the copy
     // has completed (checked on later calls), so nothing here waits
     char *host = pinned_stage(in_total);
@@ -246,22 +253,29 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
         return fail(BEM_E_DEVICE, std::string("hipMallocAsync: ") + hipGetErrorString(e));
     }
     ReqDev d;
-    place_request(r, host, ws, off_in, 0, off_part, off_status, d);
+    stage_request_inputs(r, host, ws, off_in, d);
+    finish_descriptor(r, ws, 0, off_part, off_status, d);
     d.out = dev_out;
     std::memcpy(host + off_req, &d, sizeof(ReqDev));
-    std::memcpy(host + off_t, tiles.data(), sizeof(Tile) * tiles.size());
-    std::memcpy(host + off_rt, rtiles.data(), sizeof(RTile) * rtiles.size());
+    const int64_t gp[2] = {0, r.ntiles}, rgp[2] = {0, r.nrtiles};
+    std::memcpy(host + off_gp, gp, sizeof(gp));
+    std::memcpy(host + off_rgp, rgp, sizeof(rgp));
     e = hipMemcpyAsync(ws, host, in_total, hipMemcpyHostToDevice, s);
     hipEvent_t ev = nullptr;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(ev, s);
     pinned_release(host, e == hipSuccess ? ev : nullptr);
     if (e != hipSuccess) return fail(BEM_E_DEVICE, std::string("staging copy: ") + hipGetErrorString(e));
+    const ReqDev *dreq = (const ReqDev *)(ws + off_req);
+    BEM_HIP_TRY(launch_build_tiles(dreq, (const int32_t *)(ws + off_g), (const int64_t *)(ws + off_gp), 1, r.ntiles,
+                                   (Tile *)(ws + off_t), s));
     Variant v{r.op, r.space, r.prec, mesh->q, r.rowfix};
-    BEM_HIP_TRY(launch_entries(v, (const ReqDev *)(ws + off_req), (const Tile *)(ws + off_t), (int)tiles.size(), s));
-    if (space == BEM_P1)
-        BEM_HIP_TRY(launch_p1_reduce(r.prec, is_complex_op(r.op), (const ReqDev *)(ws + off_req),
-                                     (const RTile *)(ws + off_rt), (int)rtiles.size(), s));
+    BEM_HIP_TRY(launch_entries(v, dreq, (const Tile *)(ws + off_t), r.ntiles, s));
+    if (space == BEM_P1) {
+        BEM_HIP_TRY(launch_build_rtiles(dreq, (const int32_t *)(ws + off_rg), (const int64_t *)(ws + off_rgp), 1,
+                                        r.nrtiles, (RTile *)(ws + off_rt), s));
+        BEM_HIP_TRY(launch_p1_reduce(r.prec, is_complex_op(r.op), dreq, (const RTile *)(ws + off_rt), r.nrtiles, s));
+    }
     BEM_HIP_TRY(hipFreeAsync(ws, s));
     return BEM_OK;
 }
@@ -275,6 +289,12 @@ int bem_server_stats(bem_server_stats_t *stats, int reset)
 {
     if (!stats) return fail(BEM_E_ARG, "null argument");
     return server_stats(stats, reset);
+}
+
+int bem_server_kernel_stats(bem_kernel_stats_t *out, int max_entries, int *count, int reset)
+{
+    if (max_entries < 0 || !count) return fail(BEM_E_ARG, "bad arguments");
+    return server_kernel_stats(out, max_entries, count, reset);
 }
 
 int bem_aca_block(bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows, int64_t m,

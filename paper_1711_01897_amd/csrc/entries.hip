@@ -333,11 +333,11 @@ __device__ __forceinline__ void pair_p1_f64(const double *T, const double *S, in
 // Kernels.
 template <int OP, int Q, bool ROWFIX>
 __global__ __launch_bounds__(256) void k_p0_f32(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
-                                                int ntiles)
+                                                int64_t ntiles)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWavesPerBlock + wave;
+    const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     if (t >= ntiles) return;
     const Tile tl = tiles[t];
     const ReqDev &R = reqs[tl.req];
@@ -370,11 +370,11 @@ __global__ __launch_bounds__(256) void k_p0_f32(const ReqDev *__restrict__ reqs,
 
 template <int OP, int Q, bool ROWFIX>
 __global__ __launch_bounds__(256) void k_p0_f64(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
-                                                int ntiles)
+                                                int64_t ntiles)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWavesPerBlock + wave;
+    const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     if (t >= ntiles) return;
     const Tile tl = tiles[t];
     const ReqDev &R = reqs[tl.req];
@@ -409,11 +409,11 @@ __global__ __launch_bounds__(256) void k_p0_f64(const ReqDev *__restrict__ reqs,
 // compensated partial sums (one per local vertex of the lane triangle).
 template <int OP, int Q, bool ROWFIX>
 __global__ __launch_bounds__(256) void k_p1_f32(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
-                                                int ntiles)
+                                                int64_t ntiles)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWavesPerBlock + wave;
+    const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     if (t >= ntiles) return;
     const Tile tl = tiles[t];
     const ReqDev &R = reqs[tl.req];
@@ -460,11 +460,11 @@ __global__ __launch_bounds__(256) void k_p1_f32(const ReqDev *__restrict__ reqs,
 
 template <int OP, int Q, bool ROWFIX>
 __global__ __launch_bounds__(256) void k_p1_f64(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
-                                                int ntiles)
+                                                int64_t ntiles)
 {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWavesPerBlock + wave;
+    const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
     if (t >= ntiles) return;
     const Tile tl = tiles[t];
     const ReqDev &R = reqs[tl.req];
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(256) void k_p1_f64(const ReqDev *__restrict__ reqs,
 // (ascending lane triangle), compensated in FP32.
 template <bool CPLX>
 __global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f32(const ReqDev *__restrict__ reqs,
-                                                               const RTile *__restrict__ tiles, int ntiles)
+                                                               const RTile *__restrict__ tiles, int64_t ntiles)
 {
     const RTile tl = tiles[blockIdx.x];
     if ((int)threadIdx.x >= tl.count) return;
@@ -547,7 +547,7 @@ __global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f32(const ReqDev *__
 
 template <bool CPLX>
 __global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f64(const ReqDev *__restrict__ reqs,
-                                                               const RTile *__restrict__ tiles, int ntiles)
+                                                               const RTile *__restrict__ tiles, int64_t ntiles)
 {
     const RTile tl = tiles[blockIdx.x];
     if ((int)threadIdx.x >= tl.count) return;
@@ -576,8 +576,111 @@ __global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f64(const ReqDev *__
 }
 
 // ---------------------------------------------------------------------------
+// Tile tables.  Thread t finds its request by binary search in the group's
+// exclusive prefix of per-request tile counts and writes the tile record.
+__global__ __launch_bounds__(256) void k_build_tiles(const ReqDev *__restrict__ reqs, const int32_t *__restrict__ greq,
+                                                     const int64_t *__restrict__ gpre, int ng, int64_t ntiles,
+                                                     Tile *__restrict__ tiles)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int lo = 0, hi = ng;  // gpre[lo] <= t < gpre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (gpre[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int r = greq[lo];
+    const ReqDev &R = reqs[r];
+    const int64_t u = t - gpre[lo];
+    const int ntl = (R.nlane + kTileLanes - 1) / kTileLanes;
+    const int f = (int)(u / ntl);
+    const int c = (int)(u - (int64_t)f * ntl);
+    Tile tl;
+    tl.req = r;
+    tl.fixed = f;
+    tl.lane0 = c * kTileLanes;
+    tl.nlanes = min(kTileLanes, R.nlane - c * kTileLanes);
+    tiles[t] = tl;
+}
+
+__global__ __launch_bounds__(256) void k_build_rtiles(const ReqDev *__restrict__ reqs,
+                                                      const int32_t *__restrict__ greq,
+                                                      const int64_t *__restrict__ gpre, int ng, int64_t ntiles,
+                                                      RTile *__restrict__ tiles)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    int lo = 0, hi = ng;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (gpre[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int r = greq[lo];
+    const ReqDev &R = reqs[r];
+    const int64_t u = t - gpre[lo];
+    const int64_t n = (int64_t)R.nrows * R.ncols;
+    RTile tl;
+    tl.req = r;
+    tl.e0 = u * kReduceBlock;
+    tl.count = (int32_t)min((int64_t)kReduceBlock, n - tl.e0);
+    tiles[t] = tl;
+}
+
+__global__ __launch_bounds__(256) void k_build_all(const ReqDev *__restrict__ reqs,
+                                                   const GroupDesc *__restrict__ groups, int ngroups, int64_t total)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    int glo = 0, ghi = ngroups;  // groups[glo].tile0 <= t < groups[ghi].tile0
+    while (ghi - glo > 1) {
+        const int mid = (glo + ghi) >> 1;
+        if (groups[mid].tile0 <= t)
+            glo = mid;
+        else
+            ghi = mid;
+    }
+    const GroupDesc &G = groups[glo];
+    const int64_t tt = t - G.tile0;
+    int lo = 0, hi = G.ng;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (G.gpre[mid] <= tt)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int r = G.greq[lo];
+    const ReqDev &R = reqs[r];
+    const int64_t u = tt - G.gpre[lo];
+    if (G.kind == 0) {
+        const int ntl = (R.nlane + kTileLanes - 1) / kTileLanes;
+        const int f = (int)(u / ntl);
+        const int c = (int)(u - (int64_t)f * ntl);
+        Tile tl;
+        tl.req = r;
+        tl.fixed = f;
+        tl.lane0 = c * kTileLanes;
+        tl.nlanes = min(kTileLanes, R.nlane - c * kTileLanes);
+        reinterpret_cast<Tile *>(G.tiles)[tt] = tl;
+    } else {
+        const int64_t n = (int64_t)R.nrows * R.ncols;
+        RTile tl;
+        tl.req = r;
+        tl.e0 = u * kReduceBlock;
+        tl.count = (int32_t)min((int64_t)kReduceBlock, n - tl.e0);
+        reinterpret_cast<RTile *>(G.tiles)[tt] = tl;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Dispatch.
-typedef void (*EntryKernel)(const ReqDev *, const Tile *, int);
+typedef void (*EntryKernel)(const ReqDev *, const Tile *, int64_t);
 
 template <int OP, int Q, bool RF>
 EntryKernel pick(int space, int prec)
@@ -610,7 +713,33 @@ EntryKernel select_kernel(const Variant &v)
 
 }  // namespace
 
-hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const Tile *tiles, int ntiles, hipStream_t s)
+hipError_t launch_build_tiles(const ReqDev *reqs, const int32_t *greq, const int64_t *gpre, int ng, int64_t ntiles,
+                              Tile *tiles, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((ntiles + 255) / 256);
+    hipLaunchKernelGGL(k_build_tiles, dim3(grid), dim3(256), 0, s, reqs, greq, gpre, ng, ntiles, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_all(const ReqDev *reqs, const GroupDesc *groups, int ngroups, int64_t total, hipStream_t s)
+{
+    if (total <= 0 || ngroups <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL(k_build_all, dim3(grid), dim3(256), 0, s, reqs, groups, ngroups, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_rtiles(const ReqDev *reqs, const int32_t *greq, const int64_t *gpre, int ng, int64_t ntiles,
+                               RTile *tiles, hipStream_t s)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((ntiles + 255) / 256);
+    hipLaunchKernelGGL(k_build_rtiles, dim3(grid), dim3(256), 0, s, reqs, greq, gpre, ng, ntiles, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const Tile *tiles, int64_t ntiles, hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
@@ -618,7 +747,8 @@ hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const Tile *tile
     return hipGetLastError();
 }
 
-hipError_t launch_p1_reduce(int prec, bool cplx, const ReqDev *reqs, const RTile *tiles, int ntiles, hipStream_t s)
+hipError_t launch_p1_reduce(int prec, bool cplx, const ReqDev *reqs, const RTile *tiles, int64_t ntiles,
+                            hipStream_t s)
 {
     if (ntiles <= 0) return hipSuccess;
     if (prec == BEM_FP32) {

@@ -15,6 +15,7 @@
 #include <thread>
 
 #include "aca.hpp"
+#include <unordered_map>
 #include "bem_internal.hpp"
 #include "tree.hpp"
 
@@ -127,27 +128,83 @@ void store_cols<cd>(const std::vector<cd> &src, int k, int64_t len, int64_t cap,
     std::memcpy(dst, src.data(), sizeof(cd) * len * k);
 }
 
+// Lane sets of several dof lists, expanded on the host (in parallel) and
+// uploaded to the device in one buffer.
+struct ResidentLanes {
+    int32_t *dev = nullptr;
+    std::vector<LaneRef> refs;
+    ResidentLanes() = default;
+    ResidentLanes(const ResidentLanes &) = delete;
+    ~ResidentLanes()
+    {
+        if (dev) (void)hipFree(dev);
+    }
+};
+
+int make_resident(const bem_mesh &m, int space, const std::vector<std::pair<const int32_t *, int64_t>> &lists,
+                  ResidentLanes &out)
+{
+    const size_t n = lists.size();
+    std::vector<LaneSet> sets(n);
+    const unsigned nth = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t)
+        th.emplace_back([&, t] {
+            for (size_t i = t; i < n; i += nth)
+                if (lists[i].first) build_lane_set(m, space, lists[i].first, lists[i].second, sets[i]);
+        });
+    for (auto &x : th) x.join();
+    size_t total = 0;
+    for (auto &ls : sets) total += ls.ints();
+    std::vector<int32_t> host(std::max<size_t>(total, 1));
+    out.refs.assign(n, LaneRef());
+    std::vector<size_t> at(n);
+    size_t pos = 0;
+    for (size_t i = 0; i < n; ++i) {
+        at[i] = pos;
+        const LaneSet &ls = sets[i];
+        std::copy(ls.lane.begin(), ls.lane.end(), host.begin() + pos);
+        pos += ls.lane.size();
+        std::copy(ls.seg_ptr.begin(), ls.seg_ptr.end(), host.begin() + pos);
+        pos += ls.seg_ptr.size();
+        std::copy(ls.seg.begin(), ls.seg.end(), host.begin() + pos);
+        pos += ls.seg.size();
+    }
+    BEM_HIP_TRY(hipMalloc(&out.dev, sizeof(int32_t) * host.size()));
+    BEM_HIP_TRY(hipMemcpy(out.dev, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice));
+    for (size_t i = 0; i < n; ++i) {
+        const LaneSet &ls = sets[i];
+        LaneRef &r = out.refs[i];
+        r.ndof = ls.ndof;
+        r.nlane = (int64_t)ls.lane.size();
+        r.nseg = (int64_t)ls.seg.size();
+        r.lane = out.dev + at[i];
+        r.seg_ptr = ls.seg_ptr.empty() ? nullptr : out.dev + at[i] + ls.lane.size();
+        r.seg = ls.seg.empty() ? nullptr : out.dev + at[i] + ls.lane.size() + ls.seg_ptr.size();
+    }
+    return BEM_OK;
+}
+
 // Completion queue of one worker.
 struct DoneQueue {
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Request *> q;
-    static void push(Request *r, void *ctx)
+    std::vector<Request *> q;
+    static void push(Request **rs, size_t n, void *ctx)
     {
         DoneQueue *d = (DoneQueue *)ctx;
         {
             std::lock_guard<std::mutex> g(d->mu);
-            d->q.push_back(r);
+            d->q.insert(d->q.end(), rs, rs + n);
         }
         d->cv.notify_one();
     }
-    Request *pop()
+    void pop_all(std::vector<Request *> &out)
     {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait(lk, [&] { return !q.empty(); });
-        Request *r = q.front();
-        q.pop_front();
-        return r;
+        out.swap(q);
+        q.clear();
     }
 };
 
@@ -162,7 +219,6 @@ struct Slot {
     bool adm = false;
     AcaCore<T> core;
     Request req;
-    std::vector<char> out;
     std::vector<T> buf;
     bool busy = false;
 };
@@ -173,16 +229,28 @@ struct AssemblyCtx {
     double k, tol;
     int max_rank;
     bem_hmat *h;
+    const std::vector<LaneRef> *lanes;  // per cluster id
     std::vector<Job> jobs;
     std::atomic<int64_t> next{0};
     std::atomic<int> error{0};
     std::mutex err_mu;
     std::string err_msg;
     std::atomic<int64_t> aca_entries{0}, dense_entries{0}, requests{0};
+    std::mutex busy_mu;
+    double busy = 0.0;
+
+    void set_error(int code, const std::string &msg)
+    {
+        std::lock_guard<std::mutex> g(err_mu);
+        if (!error.load()) {
+            error = code;
+            err_msg = msg;
+        }
+    }
 };
 
 template <typename T>
-int submit_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq)
+int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag)
 {
     bem_hmat::Leaf &L = C.h->leaves[s.leaf];
     Request &r = s.req;
@@ -191,36 +259,31 @@ int submit_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq)
     r.space = C.space;
     r.prec = C.prec;
     r.k = C.k;
+    r.borrow = true;
+    r.out_host = nullptr;
+    r.on_done = &DoneQueue::push;
+    r.cb_ctx = &dq;
+    r.tag = tag;
     if (!s.adm) {
         r.near = BEM_NEAR_SKIP;
         r.rows = L.rows;
         r.cols = L.cols;
+        r.nrows = (int64_t)r.rows.size();
+        r.ncols = (int64_t)r.cols.size();
+        const int rc = expand_request(r);
+        if (rc != BEM_OK) return rc;
+        C.dense_entries.fetch_add(r.entries());
     } else {
         r.near = BEM_NEAR_ERROR;
-        if (s.core.phase == AcaCore<T>::NEED_ROW) {
-            r.rows.assign(1, L.rows[s.core.i]);
-            r.cols = L.cols;
-        } else {
-            r.rows = L.rows;
-            r.cols.assign(1, L.cols[s.core.j]);
-        }
-    }
-    r.nrows = (int64_t)r.rows.size();
-    r.ncols = (int64_t)r.cols.size();
-    int rc = expand_request(r);
-    if (rc != BEM_OK) return rc;
-    s.out.resize((size_t)r.entries() * r.elem_bytes);
-    r.out_host = s.out.data();
-    r.on_done = &DoneQueue::push;
-    r.cb_ctx = &dq;
-    r.done = false;
-    r.status = 0;
-    C.requests.fetch_add(1);
-    if (s.adm)
+        const Block &bk = C.h->part.blocks[s.leaf];
+        if (s.core.phase == AcaCore<T>::NEED_ROW)
+            expand_single_fixed(r, L.rows[s.core.i], 1, &(*C.lanes)[bk.sigma]);
+        else
+            expand_single_fixed(r, L.cols[s.core.j], 0, &(*C.lanes)[bk.tau]);
         C.aca_entries.fetch_add(r.entries());
-    else
-        C.dense_entries.fetch_add(r.entries());
-    return server_submit(&r);
+    }
+    C.requests.fetch_add(1);
+    return BEM_OK;
 }
 
 template <typename T>
@@ -228,92 +291,135 @@ void worker(AssemblyCtx &C, int per_worker)
 {
     DoneQueue dq;
     std::vector<Slot<T>> slots(per_worker);
+    std::vector<Request *> submit, done;
     int active = 0;
     bool exhausted = false;
-    for (;;) {
-        for (auto &s : slots) {
-            if (s.busy || exhausted || C.error.load()) continue;
-            const int64_t j = C.next.fetch_add(1);
-            if (j >= (int64_t)C.jobs.size()) {
-                exhausted = true;
-                break;
-            }
-            s.leaf = C.jobs[j].leaf;
-            s.adm = C.jobs[j].adm != 0;
-            bem_hmat::Leaf &L = C.h->leaves[s.leaf];
-            if (s.adm) {
-                const Cluster &a = C.h->part.nodes[C.h->part.blocks[s.leaf].tau];
-                const Cluster &b = C.h->part.nodes[C.h->part.blocks[s.leaf].sigma];
-                s.core.init((int64_t)L.rows.size(), (int64_t)L.cols.size(), C.tol, C.max_rank,
-                            default_zero_abs(*C.mesh, C.op, C.space, C.k, C.prec, support_distance(a, b)));
-            }
-            const int rc = submit_slot(C, s, dq);
-            if (rc != BEM_OK) {
-                std::lock_guard<std::mutex> g(C.err_mu);
-                C.error = rc;
-                C.err_msg = std::string("submit: ") + bem_last_error();
-                break;
-            }
-            s.busy = true;
-            ++active;
+    auto start_job = [&](int64_t si) -> bool {
+        Slot<T> &s = slots[si];
+        if (exhausted || C.error.load()) return false;
+        const int64_t j = C.next.fetch_add(1);
+        if (j >= (int64_t)C.jobs.size()) {
+            exhausted = true;
+            return false;
         }
-        if (active == 0) return;
-        Request *r = dq.pop();
-        Slot<T> *s = nullptr;
-        for (auto &x : slots)
-            if (&x.req == r) s = &x;
-        if (r->status != BEM_OK) {
-            std::lock_guard<std::mutex> g(C.err_mu);
-            C.error = r->status;
-            C.err_msg = "device request failed";
-            s->busy = false;
-            --active;
-            continue;
+        s.leaf = C.jobs[j].leaf;
+        s.adm = C.jobs[j].adm != 0;
+        if (s.adm) {
+            const bem_hmat::Leaf &L = C.h->leaves[s.leaf];
+            const Block &bk = C.h->part.blocks[s.leaf];
+            const Cluster &a = C.h->part.nodes[bk.tau];
+            const Cluster &b = C.h->part.nodes[bk.sigma];
+            s.core.init((int64_t)L.rows.size(), (int64_t)L.cols.size(), C.tol, C.max_rank,
+                        default_zero_abs(*C.mesh, C.op, C.space, C.k, C.prec, support_distance(a, b)));
         }
-        bem_hmat::Leaf &L = C.h->leaves[s->leaf];
-        const int64_t cnt = r->entries();
-        s->buf.resize(cnt);
-        to_scalar<T>(s->out.data(), C.prec, cnt, s->buf.data());
-        bool finished = false;
-        if (!s->adm) {
-            L.D.resize((size_t)cnt * (sizeof(T) / sizeof(double)));
-            std::memcpy(L.D.data(), s->buf.data(), sizeof(T) * cnt);
-            finished = true;
-        } else {
-            if (s->core.phase == AcaCore<T>::NEED_ROW)
-                s->core.consume_row(s->buf.data());
-            else
-                s->core.consume_col(s->buf.data());
-            if (s->core.phase == AcaCore<T>::DONE) {
-                L.rank = s->core.k;
-                const size_t f = sizeof(T) / sizeof(double);
-                L.U.resize(s->core.U.size() * f);
-                L.V.resize(s->core.V.size() * f);
-                std::memcpy(L.U.data(), s->core.U.data(), sizeof(T) * s->core.U.size());
-                std::memcpy(L.V.data(), s->core.V.data(), sizeof(T) * s->core.V.size());
-                finished = true;
-            }
-        }
-        if (finished || C.error.load()) {
-            s->busy = false;
-            --active;
-            continue;
-        }
-        const int rc = submit_slot(C, *s, dq);
+        const int rc = prepare_slot(C, s, dq, si);
         if (rc != BEM_OK) {
-            std::lock_guard<std::mutex> g(C.err_mu);
-            C.error = rc;
-            C.err_msg = std::string("submit: ") + bem_last_error();
-            s->busy = false;
-            --active;
+            C.set_error(rc, std::string("request: ") + bem_last_error());
+            return false;
         }
+        s.busy = true;
+        ++active;
+        submit.push_back(&s.req);
+        return true;
+    };
+    auto flush = [&]() {
+        if (submit.empty()) return;
+        const int rc = server_submit_many(submit.data(), submit.size());
+        if (rc != BEM_OK) {
+            C.set_error(rc, std::string("submit: ") + bem_last_error());
+            // nothing was queued: these requests will never complete
+            for (Request *r : submit) {
+                slots[r->tag].busy = false;
+                --active;
+            }
+        }
+        submit.clear();
+    };
+    double busy = 0.0;
+    double tb = now_seconds();
+    for (int64_t si = 0; si < per_worker; ++si)
+        if (!start_job(si)) break;
+    flush();
+    while (active > 0) {
+        busy += now_seconds() - tb;
+        dq.pop_all(done);
+        tb = now_seconds();
+        for (Request *r : done) {
+            Slot<T> &s = slots[r->tag];
+            bool finished = false;
+            if (r->status != BEM_OK) {
+                C.set_error(r->status, r->status == BEM_E_NEARFIELD ? "admissible block met a vertex-sharing pair"
+                                                                    : "device request failed");
+                finished = true;
+            } else {
+                bem_hmat::Leaf &L = C.h->leaves[s.leaf];
+                const int64_t cnt = r->entries();
+                s.buf.resize(cnt);
+                to_scalar<T>(r->result, C.prec, cnt, s.buf.data());
+                server_release(r);
+                if (!s.adm) {
+                    L.D.resize((size_t)cnt * (sizeof(T) / sizeof(double)));
+                    std::memcpy(L.D.data(), s.buf.data(), sizeof(T) * cnt);
+                    finished = true;
+                } else {
+                    if (s.core.phase == AcaCore<T>::NEED_ROW)
+                        s.core.consume_row(s.buf.data());
+                    else
+                        s.core.consume_col(s.buf.data());
+                    if (s.core.phase == AcaCore<T>::DONE) {
+                        L.rank = s.core.k;
+                        const size_t f = sizeof(T) / sizeof(double);
+                        L.U.resize(s.core.U.size() * f);
+                        L.V.resize(s.core.V.size() * f);
+                        std::memcpy(L.U.data(), s.core.U.data(), sizeof(T) * s.core.U.size());
+                        std::memcpy(L.V.data(), s.core.V.data(), sizeof(T) * s.core.V.size());
+                        finished = true;
+                    }
+                }
+            }
+            if (r->batch) server_release(r);
+            if (finished || C.error.load()) {
+                s.busy = false;
+                --active;
+                if (!C.error.load()) start_job(r->tag);
+                continue;
+            }
+            const int rc = prepare_slot(C, s, dq, r->tag);
+            if (rc != BEM_OK) {
+                C.set_error(rc, std::string("request: ") + bem_last_error());
+                s.busy = false;
+                --active;
+                continue;
+            }
+            submit.push_back(&s.req);
+        }
+        done.clear();
+        flush();
     }
+    busy += now_seconds() - tb;
+    std::lock_guard<std::mutex> g(C.busy_mu);
+    C.busy += busy;
 }
 
 template <typename T>
 int aca_block_impl(bem_mesh *mesh, int op, int space, double k, const int32_t *rows, int64_t m, const int32_t *cols,
                    int64_t n, const bem_aca_params *p, int prec, void *U, void *V, int32_t *rank, int64_t *entries)
 {
+    {
+        Request probe;
+        probe.mesh = mesh;
+        probe.op = op;
+        probe.space = space;
+        probe.prec = prec;
+        probe.k = k;
+        probe.near = BEM_NEAR_ERROR;
+        probe.rows.assign(rows, rows + m);
+        probe.cols.assign(cols, cols + n);
+        probe.nrows = 0;
+        probe.ncols = 0;
+        const int rc = expand_request(probe);  // validates indices, op, k
+        if (rc != BEM_OK) return rc;
+    }
     double zero_abs = p->zero_abs;
     if (zero_abs < 0) {
         double alo[3], ahi[3], blo[3], bhi[3];
@@ -321,6 +427,9 @@ int aca_block_impl(bem_mesh *mesh, int op, int space, double k, const int32_t *r
         support_box(*mesh, space, cols, n, blo, bhi);
         zero_abs = default_zero_abs(*mesh, op, space, k, prec, box_distance(alo, ahi, blo, bhi));
     }
+    ResidentLanes lanes;
+    int rc = make_resident(*mesh, space, {{rows, m}, {cols, n}}, lanes);
+    if (rc != BEM_OK) return rc;
     AcaCore<T> core;
     core.init(m, n, p->tol, p->max_rank, zero_abs);
     Request r;
@@ -334,17 +443,10 @@ int aca_block_impl(bem_mesh *mesh, int op, int space, double k, const int32_t *r
         r.prec = prec;
         r.k = k;
         r.near = BEM_NEAR_ERROR;
-        if (core.phase == AcaCore<T>::NEED_ROW) {
-            r.rows.assign(1, rows[core.i]);
-            r.cols.assign(cols, cols + n);
-        } else {
-            r.rows.assign(rows, rows + m);
-            r.cols.assign(1, cols[core.j]);
-        }
-        r.nrows = (int64_t)r.rows.size();
-        r.ncols = (int64_t)r.cols.size();
-        int rc = expand_request(r);
-        if (rc != BEM_OK) return rc;
+        if (core.phase == AcaCore<T>::NEED_ROW)
+            expand_single_fixed(r, rows[core.i], 1, &lanes.refs[1]);
+        else
+            expand_single_fixed(r, cols[core.j], 0, &lanes.refs[0]);
         out.resize((size_t)r.entries() * r.elem_bytes);
         r.out_host = out.data();
         r.on_done = nullptr;
@@ -452,6 +554,7 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
     std::vector<double> pts, slo, shi;
     dof_geometry(*mesh, space, pts, slo, shi);
     build_partition(pts, slo, shi, p->leaf_size, p->eta, h->part);
+    const double t_part = now_seconds();
     const auto &P = h->part;
     h->leaves.resize(P.blocks.size());
     AssemblyCtx C;
@@ -463,6 +566,22 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
     C.tol = p->aca_tol;
     C.max_rank = p->max_rank;
     C.h = h;
+    std::vector<std::pair<const int32_t *, int64_t>> lists(P.nodes.size(), {nullptr, 0});
+    for (const Block &bk : P.blocks)
+        if (bk.admissible)
+            for (int cid : {bk.tau, bk.sigma}) {
+                const Cluster &cl = P.nodes[cid];
+                lists[cid] = {P.perm.data() + cl.begin, cl.end - cl.begin};
+            }
+    ResidentLanes lanes;
+    {
+        const int rc = make_resident(*mesh, space, lists, lanes);
+        if (rc != BEM_OK) {
+            delete h;
+            return rc;
+        }
+    }
+    C.lanes = &lanes.refs;
     for (size_t b = 0; b < P.blocks.size(); ++b) {
         const Cluster &a = P.nodes[P.blocks[b].tau], &c = P.nodes[P.blocks[b].sigma];
         auto &L = h->leaves[b];
@@ -478,6 +597,7 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
         const int64_t cy = y.adm ? (int64_t)(b.rows.size() + b.cols.size()) * 16 : (int64_t)(b.rows.size() * b.cols.size());
         return cx > cy;
     });
+    const double t_setup = now_seconds();
     const int nw = std::max(1, p->n_workers);
     const int per = std::max(1, p->blocks_per_worker);
     std::vector<std::thread> th;
@@ -488,6 +608,7 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
             th.emplace_back([&] { worker<double>(C, per); });
     }
     for (auto &t : th) t.join();
+    const double t_aca = now_seconds();
     if (C.error.load() != 0) {
         const int code = C.error.load();
         std::string msg = C.err_msg;
@@ -512,6 +633,10 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
     }
     s.bytes = bytes;
     s.seconds = now_seconds() - t0;
+    s.partition_seconds = t_part - t0;
+    s.setup_seconds = t_setup - t_part;
+    s.aca_seconds = t_aca - t_setup;
+    s.worker_busy_seconds = C.busy;
     *out = h;
     return BEM_OK;
 }

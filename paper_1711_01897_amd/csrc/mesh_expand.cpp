@@ -50,8 +50,7 @@ size_t out_elem_bytes(int op, int prec)
 
 namespace {
 
-// Distinct triangles around a list of vertices, ascending; slot_of maps a
-// triangle to its position.  Scratch is per thread.
+// Per-thread scratch mapping triangles to lane slots.
 struct StarScratch {
     std::vector<int32_t> slot_of;
     std::vector<uint32_t> stamp;
@@ -71,49 +70,86 @@ struct StarScratch {
 };
 thread_local StarScratch g_scratch;
 
-void expand_p1_side(const bem_mesh &m, const std::vector<int32_t> &lane_dofs, const std::vector<int32_t> &fix_dofs,
-                    Request &r)
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+void expand_fixed(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, Request &r)
 {
+    r.fix.clear();
+    r.fstar.clear();
+    if (space == BEM_P0) {
+        r.fix.assign(dofs, dofs + n);
+    } else {
+        r.fix.resize(n + 1);
+        r.fix[0] = 0;
+        for (int64_t f = 0; f < n; ++f) {
+            const int32_t v = dofs[f];
+            for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) r.fstar.push_back(m.star[s]);
+            r.fix[f + 1] = (int32_t)r.fstar.size();
+        }
+    }
+    r.nfix = n;
+}
+
+void finalize_sizes(Request &r)
+{
+    const bem_mesh &m = *r.mesh;
+    const int64_t q2 = (int64_t)m.q * m.q;
+    r.elem_bytes = out_elem_bytes(r.op, r.prec);
+    if (r.space == BEM_P0) {
+        r.part_elem_bytes = 0;
+        r.part_bytes = 0;
+        r.evals = r.nfix * r.nlane * q2;
+        r.nrtiles = 0;
+    } else {
+        // (hi, lo) float pair or one double per real component
+        r.part_elem_bytes = is_complex_op(r.op) ? 16 : 8;
+        r.part_bytes = align16((size_t)r.nfix * r.nlane * 3 * r.part_elem_bytes);
+        r.evals = (int64_t)r.fstar.size() * r.nlane * q2;
+        r.nrtiles = (r.entries() + kReduceBlock - 1) / kReduceBlock;
+    }
+    r.ntiles = r.nfix * ((r.nlane + kTileLanes - 1) / kTileLanes);
+    const size_t own = r.ext ? 0 : r.own.ints();
+    r.in_bytes = align16(4 * (r.fix.size() + r.fstar.size() + own));
+    r.out_bytes = align16((size_t)r.entries() * r.elem_bytes);
+}
+
+}  // namespace
+
+void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, LaneSet &ls)
+{
+    ls.ndof = n;
+    ls.lane.clear();
+    ls.seg_ptr.clear();
+    ls.seg.clear();
+    if (space == BEM_P0) {
+        ls.lane.assign(dofs, dofs + n);
+        return;
+    }
     StarScratch &sc = g_scratch;
     sc.prepare(m.nt);
-    std::vector<int32_t> &lane = r.lane;
-    lane.clear();
-    for (int32_t v : lane_dofs)
+    for (int64_t c = 0; c < n; ++c) {
+        const int32_t v = dofs[c];
         for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) {
             const int32_t t = m.star[s] >> 2;
             if (sc.stamp[t] != sc.gen) {
                 sc.stamp[t] = sc.gen;
-                lane.push_back(t);
+                ls.lane.push_back(t);
             }
         }
-    std::sort(lane.begin(), lane.end());
-    for (size_t i = 0; i < lane.size(); ++i) sc.slot_of[lane[i]] = (int32_t)i;
-    r.seg_ptr.resize(lane_dofs.size() + 1);
-    r.seg.clear();
-    r.seg_ptr[0] = 0;
-    for (size_t c = 0; c < lane_dofs.size(); ++c) {
-        const int32_t v = lane_dofs[c];
+    }
+    std::sort(ls.lane.begin(), ls.lane.end());
+    for (size_t i = 0; i < ls.lane.size(); ++i) sc.slot_of[ls.lane[i]] = (int32_t)i;
+    ls.seg_ptr.resize(n + 1);
+    ls.seg_ptr[0] = 0;
+    for (int64_t c = 0; c < n; ++c) {
+        const int32_t v = dofs[c];
         for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) {
             const int32_t pk = m.star[s];
-            r.seg.push_back((sc.slot_of[pk >> 2] << 2) | (pk & 3));
+            ls.seg.push_back((sc.slot_of[pk >> 2] << 2) | (pk & 3));
         }
-        r.seg_ptr[c + 1] = (int32_t)r.seg.size();
+        ls.seg_ptr[c + 1] = (int32_t)ls.seg.size();
     }
-    r.fix.resize(fix_dofs.size() + 1);
-    r.fstar.clear();
-    r.fix[0] = 0;
-    for (size_t f = 0; f < fix_dofs.size(); ++f) {
-        const int32_t v = fix_dofs[f];
-        for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) r.fstar.push_back(m.star[s]);
-        r.fix[f + 1] = (int32_t)r.fstar.size();
-    }
-    r.nlane = (int64_t)lane.size();
-    r.nfix = (int64_t)fix_dofs.size();
 }
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-}  // namespace
 
 int expand_request(Request &r)
 {
@@ -134,55 +170,49 @@ int expand_request(Request &r)
         if (v < 0 || v >= ndof) return fail(BEM_E_ARG, "column index out of range");
     if (r.nrows > INT32_MAX || r.ncols > INT32_MAX) return fail(BEM_E_ARG, "request dimension too large");
 
-    r.elem_bytes = out_elem_bytes(r.op, r.prec);
+    r.ext = nullptr;
     r.rowfix = r.ncols >= r.nrows ? 1 : 0;
     const std::vector<int32_t> &fix_dofs = r.rowfix ? r.rows : r.cols;
     const std::vector<int32_t> &lane_dofs = r.rowfix ? r.cols : r.rows;
-    const int64_t q2 = (int64_t)m.q * m.q;
-    if (r.space == BEM_P0) {
-        r.fix = fix_dofs;
-        r.lane = lane_dofs;
-        r.fstar.clear();
-        r.seg.clear();
-        r.seg_ptr.clear();
-        r.nfix = (int64_t)fix_dofs.size();
-        r.nlane = (int64_t)lane_dofs.size();
-        r.part_elem_bytes = 0;
-        r.part_bytes = 0;
-        r.evals = r.nfix * r.nlane * q2;
-        r.ntiles = r.nfix * ((r.nlane + kTileLanes - 1) / kTileLanes);
-        r.nrtiles = 0;
-    } else {
-        expand_p1_side(m, lane_dofs, fix_dofs, r);
-        const size_t real = r.prec == BEM_FP32 ? 8 : 8;  // (hi, lo) float pair or one double
-        r.part_elem_bytes = is_complex_op(r.op) ? 2 * real : real;
-        r.part_bytes = (size_t)r.nfix * r.nlane * 3 * r.part_elem_bytes;
-        r.evals = (int64_t)r.fstar.size() * r.nlane * q2;
-        r.ntiles = r.nfix * ((r.nlane + kTileLanes - 1) / kTileLanes);
-        r.nrtiles = (r.entries() + kReduceBlock - 1) / kReduceBlock;
-    }
-    r.in_bytes = align256(4 * (r.fix.size() + r.fstar.size() + r.lane.size() + r.seg_ptr.size() + r.seg.size()));
-    r.out_bytes = align256((size_t)r.entries() * r.elem_bytes);
-    r.part_bytes = align256(r.part_bytes);
+    expand_fixed(m, r.space, fix_dofs.data(), (int64_t)fix_dofs.size(), r);
+    build_lane_set(m, r.space, lane_dofs.data(), (int64_t)lane_dofs.size(), r.own);
+    r.nlane = (int64_t)r.own.lane.size();
+    finalize_sizes(r);
     return BEM_OK;
+}
+
+void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext)
+{
+    r.ext = ext;
+    r.rowfix = rowfix;
+    r.own.lane.clear();
+    r.own.seg_ptr.clear();
+    r.own.seg.clear();
+    expand_fixed(*r.mesh, r.space, &dof, 1, r);
+    r.nlane = ext->nlane;
+    if (rowfix) {
+        r.nrows = 1;
+        r.ncols = ext->ndof;
+    } else {
+        r.nrows = ext->ndof;
+        r.ncols = 1;
+    }
+    finalize_sizes(r);
 }
 
 size_t request_bytes(const Request &r)
 {
-    return sizeof(ReqDev) + 256 + r.in_bytes + r.out_bytes + r.part_bytes + (size_t)r.ntiles * sizeof(Tile) +
-           (size_t)r.nrtiles * sizeof(RTile) + 64;
+    // descriptor, group-table entries (request id + prefix, main and reduce), inputs, status, outputs,
+    // partials, tiles
+    return sizeof(ReqDev) + 2 * (4 + 8) + r.in_bytes + 4 + r.out_bytes + r.part_bytes +
+           (size_t)r.ntiles * sizeof(Tile) + (size_t)r.nrtiles * sizeof(RTile) + 64;
 }
 
-void place_request(Request &r, char *host_base, char *dev_base, size_t off_in, size_t off_out, size_t off_part,
-                   size_t off_status, ReqDev &d)
+size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d)
 {
     const bem_mesh &m = *r.mesh;
-    r.off_in = off_in;
-    r.off_out = off_out;
-    r.off_part = off_part;
-    r.off_status = off_status;
-    char *h = host_base + off_in;
-    char *dv = dev_base + off_in;
+    char *h = host_base + off;
+    char *dv = dev_base + off;
     auto put = [&](const std::vector<int32_t> &v) -> const int32_t * {
         if (v.empty()) return nullptr;
         std::memcpy(h, v.data(), 4 * v.size());
@@ -196,12 +226,15 @@ void place_request(Request &r, char *host_base, char *dev_base, size_t off_in, s
     d.vtx = m.d_vtx;
     d.fix = put(r.fix);
     d.fstar = put(r.fstar);
-    d.lane = put(r.lane);
-    d.seg_ptr = put(r.seg_ptr);
-    d.seg = put(r.seg);
-    d.part = r.part_bytes ? dev_base + off_part : nullptr;
-    d.out = dev_base + off_out;
-    d.status = reinterpret_cast<int32_t *>(dev_base + off_status);
+    if (r.ext) {
+        d.lane = r.ext->lane;
+        d.seg_ptr = r.ext->seg_ptr;
+        d.seg = r.ext->seg;
+    } else {
+        d.lane = put(r.own.lane);
+        d.seg_ptr = put(r.own.seg_ptr);
+        d.seg = put(r.own.seg);
+    }
     if (r.rowfix) {
         d.sf = r.ncols;
         d.sl = 1;
@@ -212,34 +245,20 @@ void place_request(Request &r, char *host_base, char *dev_base, size_t off_in, s
     d.nrows = (int32_t)r.nrows;
     d.ncols = (int32_t)r.ncols;
     d.nlane = (int32_t)r.nlane;
+    d.nfix = (int32_t)r.nfix;
     d.rowfix = r.rowfix;
     d.near_error = r.near == BEM_NEAR_ERROR ? 1 : 0;
-    d.pad0 = 0;
     d.k = r.k;
     d.kk = r.k / (2.0 * 3.14159265358979323846);
+    return r.in_bytes;
 }
 
-void make_tiles(const Request &r, int32_t req_index, std::vector<Tile> &tiles, std::vector<RTile> &rtiles)
+void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_part, size_t off_status,
+                       ReqDev &d)
 {
-    for (int64_t f = 0; f < r.nfix; ++f)
-        for (int64_t l0 = 0; l0 < r.nlane; l0 += kTileLanes) {
-            Tile t;
-            t.req = req_index;
-            t.fixed = (int32_t)f;
-            t.lane0 = (int32_t)l0;
-            t.nlanes = (int32_t)std::min<int64_t>(kTileLanes, r.nlane - l0);
-            tiles.push_back(t);
-        }
-    if (r.space == BEM_P1) {
-        const int64_t n = r.entries();
-        for (int64_t e0 = 0; e0 < n; e0 += kReduceBlock) {
-            RTile t;
-            t.req = req_index;
-            t.count = (int32_t)std::min<int64_t>(kReduceBlock, n - e0);
-            t.e0 = e0;
-            rtiles.push_back(t);
-        }
-    }
+    d.out = dev_base + off_out;
+    d.part = r.part_bytes ? dev_base + off_part : nullptr;
+    d.status = reinterpret_cast<int32_t *>(dev_base + off_status);
 }
 
 }  // namespace bem
