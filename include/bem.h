@@ -164,9 +164,11 @@ typedef struct {
     double latency_p99;
     double latency_max;
     double busy_seconds;     /* wall time with at least one batch on the device */
-    double kernel_seconds;   /* sum of entry-kernel durations measured with HIP events */
+    double kernel_seconds;   /* entry-kernel launch durations (HIP events), summed over the timed
+                                batches and scaled to all batches */
     double kernel_seconds_p1_reduce;
-    int64_t kernel_launches; /* entry-kernel launches timed */
+    int64_t kernel_launches; /* launches timed: every launch of one batch in four is bracketed by
+                                HIP events, so kernel_seconds covers that sample */
     double dispatch_seconds; /* host time spent staging and enqueueing batches */
     double complete_seconds; /* host time spent completing batches (after their event) */
     double wait_seconds;     /* completion-thread time spent waiting for batch events */
@@ -176,7 +178,8 @@ typedef struct {
 int bem_server_stats(bem_server_stats_t *stats, int reset);
 
 /* Per kernel variant: launches, durations (HIP events recorded around each
- * launch on the server's stream) and the work those launches covered. */
+ * launch on the batch's stream, for one batch in four) and the work those
+ * timed launches covered. */
 typedef struct {
     int32_t op, space, prec, quad_points;
     int32_t rowfix;            /* 1: the test side is fixed per tile (lanes run over trial triangles) */

@@ -18,14 +18,14 @@ LIB = os.path.join(HERE, "libbem.so")
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
 DEVICE_SOURCES = ["entries.hip", "geometry.hip"]
-HOST_SOURCES = ["mesh_expand.cpp", "server.cpp", "hmat.cpp", "tree.cpp", "capi.cpp"]
+HOST_SOURCES = ["mesh_expand.cpp", "server.cpp", "hmat.cpp", "tree.cpp", "capi.cpp", "aca_kernels.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-Wall",
           "-Wno-unused-result"]
 DEVICE_FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-munsafe-fp-atomics"]
-HOST_FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",
-              "-packed-fp32-ops"]
+HOST_FLAGS = ["-x", "hip", "--offload-arch=" + ARCH, "-ffp-contract=off", "-fcx-limited-range", "-Xclang",
+              "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def _compile(src, flags, verbose):

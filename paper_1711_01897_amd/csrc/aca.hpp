@@ -25,6 +25,15 @@
 
 namespace bem {
 
+// Vector kernels of the residual updates (defined in aca_kernels.cpp with an
+// AVX2 clone selected at run time):  y -= a x,  sum conj(x) y,  sum |x|^2.
+void aca_axpy(double *y, const double *x, double a, int64_t n);
+void aca_axpy(std::complex<double> *y, const std::complex<double> *x, std::complex<double> a, int64_t n);
+double aca_dot(const double *x, const double *y, int64_t n);
+std::complex<double> aca_dot(const std::complex<double> *x, const std::complex<double> *y, int64_t n);
+double aca_norm2(const double *x, int64_t n);
+double aca_norm2(const std::complex<double> *x, int64_t n);
+
 inline double abs2(double x) { return x * x; }
 inline double abs2(const std::complex<double> &x) { return x.real() * x.real() + x.imag() * x.imag(); }
 inline double re_of(double x) { return x; }
@@ -40,6 +49,7 @@ struct AcaCore {
     int max_rank = 0, limit = 0;
     std::vector<T> U, V;   // column l of U at U[l*m], of V at V[l*n]
     std::vector<T> v;      // current residual row
+    std::vector<T> u;      // current residual column
     std::vector<char> used;
     int64_t nused = 0;
     int k = 0;
@@ -57,6 +67,8 @@ struct AcaCore {
         limit = (int)std::min<int64_t>(std::min<int64_t>(m, n), max_rank);
         U.clear();
         V.clear();
+        U.reserve((size_t)m * 16);
+        V.reserve((size_t)n * 16);
         used.assign(m, 0);
         nused = 0;
         k = 0;
@@ -70,11 +82,7 @@ struct AcaCore {
     void consume_row(const T *row)
     {
         v.assign(row, row + n);
-        for (int l = 0; l < k; ++l) {
-            const T ul = U[(size_t)l * m + i];
-            const T *vl = &V[(size_t)l * n];
-            for (int64_t c = 0; c < n; ++c) v[c] = v[c] - ul * vl[c];
-        }
+        for (int l = 0; l < k; ++l) aca_axpy(v.data(), &V[(size_t)l * n], U[(size_t)l * m + i], n);
         if (!used[i]) {
             used[i] = 1;
             ++nused;
@@ -110,24 +118,15 @@ struct AcaCore {
     // Raw block column j (length m).
     void consume_col(const T *col)
     {
-        std::vector<T> u(col, col + m);
-        for (int l = 0; l < k; ++l) {
-            const T vl = V[(size_t)l * n + j];
-            const T *ul = &U[(size_t)l * m];
-            for (int64_t r = 0; r < m; ++r) u[r] = u[r] - vl * ul[r];
-        }
+        u.assign(col, col + m);
+        for (int l = 0; l < k; ++l) aca_axpy(u.data(), &U[(size_t)l * m], V[(size_t)l * n + j], m);
         double cross = 0.0;
         for (int l = 0; l < k; ++l) {
-            T du = T(0), dv = T(0);
-            const T *ul = &U[(size_t)l * m];
-            const T *vl = &V[(size_t)l * n];
-            for (int64_t r = 0; r < m; ++r) du += conj_of(ul[r]) * u[r];
-            for (int64_t c = 0; c < n; ++c) dv += conj_of(vl[c]) * v[c];
+            const T du = aca_dot(&U[(size_t)l * m], u.data(), m);
+            const T dv = aca_dot(&V[(size_t)l * n], v.data(), n);
             cross += re_of(du * dv);
         }
-        double su = 0.0, sv = 0.0;
-        for (int64_t r = 0; r < m; ++r) su += abs2(u[r]);
-        for (int64_t c = 0; c < n; ++c) sv += abs2(v[c]);
+        const double su = aca_norm2(u.data(), m), sv = aca_norm2(v.data(), n);
         const double nu = std::sqrt(su), nv = std::sqrt(sv);
         norm2 = norm2 + 2.0 * cross + (nu * nv) * (nu * nv);
         U.insert(U.end(), u.begin(), u.end());

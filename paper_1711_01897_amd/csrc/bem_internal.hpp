@@ -53,12 +53,15 @@ struct ReqDev {
     void *part;                // P1: per (fixed pos, lane slot, local vertex) partial sums
     void *out;                 // final output, row-major nrows x ncols
     int32_t *status;           // bit 0: a vertex-sharing pair was met under BEM_NEAR_ERROR
+    int32_t *counter;          // P1 with fused reduction: tiles finished so far (zeroed); else null
     int64_t sf, sl;            // P0: out index = fixed_pos * sf + lane_pos * sl
     int32_t nrows, ncols;
     int32_t nlane;             // lane-side item count
     int32_t nfix;              // fixed-side positions
     int32_t rowfix;
     int32_t near_error;
+    int32_t ntiles_req;        // entry tiles of this request (fused reduction: the last one reduces)
+    int32_t pad0;
     double k;                  // wavenumber
     double kk;                 // k / (2 pi): phase in turns per unit length
 };
@@ -198,6 +201,8 @@ struct Request {
     size_t in_bytes = 0, out_bytes = 0, part_bytes = 0;
     int64_t evals = 0;          // Q^2 x (fixed, lane) triangle pairs, vertex-sharing pairs included
     int64_t ntiles = 0, nrtiles = 0;
+    bool fuse_reduce = false;   // P1: the request's last entry tile performs the per-entry reduction
+    size_t batch_bytes = 0;     // request_bytes(), cached at expansion
 
     // completion
     std::mutex mu;
@@ -233,8 +238,14 @@ size_t request_bytes(const Request &r);
 // Writes the request's inputs at host_base + off (staging) and fills its
 // descriptor with device addresses at dev_base + off; returns the bytes used.
 size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d);
+// off_status addresses two int32 per request: status word, then the arrival
+// counter of the fused P1 reduction.
 void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_part, size_t off_status,
                        ReqDev &d);
+// P1 requests with at most this many entries reduce inside the entry kernel
+// (last-arriving tile); 0 = always a separate reduction launch.  Set by the
+// BEM_FUSE_REDUCE_MAX environment variable, read once.
+int64_t fuse_reduce_max_entries();
 
 // Server
 int server_submit(Request *r);

@@ -232,7 +232,7 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     const size_t off_in = off;
     off = al(off + r.in_bytes);
     const size_t off_status = off;
-    off = al(off + 4);
+    off = al(off + 8);
     const size_t in_total = off;
     const size_t off_part = off;
     off = al(off + r.part_bytes);
@@ -271,7 +271,7 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
                                    (Tile *)(ws + off_t), s));
     Variant v{r.op, r.space, r.prec, mesh->q, r.rowfix};
     BEM_HIP_TRY(launch_entries(v, dreq, (const Tile *)(ws + off_t), r.ntiles, s));
-    if (space == BEM_P1) {
+    if (space == BEM_P1 && r.nrtiles > 0) {
         BEM_HIP_TRY(launch_build_rtiles(dreq, (const int32_t *)(ws + off_rg), (const int64_t *)(ws + off_rgp), 1,
                                         r.nrtiles, (RTile *)(ws + off_rt), s));
         BEM_HIP_TRY(launch_p1_reduce(r.prec, is_complex_op(r.op), dreq, (const RTile *)(ws + off_rt), r.nrtiles, s));

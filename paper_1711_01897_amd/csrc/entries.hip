@@ -208,28 +208,34 @@ template <int OP, int Q>
 __device__ __forceinline__ void pair_p1_testfix_f32(const float *T, int a, const float *S, float kf, double kk,
                                                     float *vr, float *vi)
 {
+    // x_p - y_q = a_p - o_q with a_p the test point relative to the trial
+    // centroid; r^2 = (|a_p|^2 + |o_q|^2) + (-2 a_p) . o_q costs one add and
+    // three fma per point pair.
     const float dcx = (T[0] - S[0]) + (T[4] - S[4]);
     const float dcy = (T[1] - S[1]) + (T[5] - S[5]);
     const float dcz = (T[2] - S[2]) + (T[6] - S[6]);
-    float ax[Q], ay[Q], az[Q], wa[Q];
+    float mx[Q], my[Q], mz[Q], A[Q], wa[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) {
-        ax[p] = dcx + T[12 + 3 * p];
-        ay[p] = dcy + T[13 + 3 * p];
-        az[p] = dcz + T[14 + 3 * p];
+        const float ax = dcx + T[12 + 3 * p], ay = dcy + T[13 + 3 * p], az = dcz + T[14 + 3 * p];
+        mx[p] = -2.0f * ax;
+        my[p] = -2.0f * ay;
+        mz[p] = -2.0f * az;
+        A[p] = fmaf(ax, ax, fmaf(ay, ay, az * az));
         const float l = (float)(a == 0 ? rule::Rule<Q>::l0[p] : (a == 1 ? rule::Rule<Q>::l1[p] : rule::Rule<Q>::l2[p]));
         wa[p] = (float)rule::Rule<Q>::w[p] * l;
-        if constexpr (is_dlp<OP>()) wa[p] *= fmaf(ax[p], S[8], fmaf(ay[p], S[9], az[p] * S[10]));
+        if constexpr (is_dlp<OP>()) wa[p] *= fmaf(ax, S[8], fmaf(ay, S[9], az * S[10]));
     }
 #pragma unroll
     for (int e = 0; e < 3; ++e) vr[e] = vi[e] = 0.f;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
+        const float ox = S[12 + 3 * q], oy = S[13 + 3 * q], oz = S[14 + 3 * q];
+        const float B = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
         float tr = 0.f, ti = 0.f;
 #pragma unroll
         for (int p = 0; p < Q; ++p) {
-            const float dx = ax[p] - S[12 + 3 * q], dy = ay[p] - S[13 + 3 * q], dz = az[p] - S[14 + 3 * q];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float r2 = fmaf(mx[p], ox, fmaf(my[p], oy, fmaf(mz[p], oz, A[p] + B)));
             kern_f32<OP>(r2, wa[p], kf, kk, tr, ti);
         }
 #pragma unroll
@@ -250,22 +256,24 @@ __device__ __forceinline__ void pair_p1_trialfix_f32(const float *T, const float
     const float dcx = (T[0] - S[0]) + (T[4] - S[4]);
     const float dcy = (T[1] - S[1]) + (T[5] - S[5]);
     const float dcz = (T[2] - S[2]) + (T[6] - S[6]);
-    float wb[Q];
+    float wb[Q], B[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const float l = (float)(b == 0 ? rule::Rule<Q>::l0[q] : (b == 1 ? rule::Rule<Q>::l1[q] : rule::Rule<Q>::l2[q]));
         wb[q] = (float)rule::Rule<Q>::w[q] * l;
+        B[q] = fmaf(S[12 + 3 * q], S[12 + 3 * q], fmaf(S[13 + 3 * q], S[13 + 3 * q], S[14 + 3 * q] * S[14 + 3 * q]));
     }
 #pragma unroll
     for (int e = 0; e < 3; ++e) vr[e] = vi[e] = 0.f;
 #pragma unroll
     for (int p = 0; p < Q; ++p) {
         const float ax = dcx + T[12 + 3 * p], ay = dcy + T[13 + 3 * p], az = dcz + T[14 + 3 * p];
+        const float mx = -2.0f * ax, my = -2.0f * ay, mz = -2.0f * az;
+        const float A = fmaf(ax, ax, fmaf(ay, ay, az * az));
         float tr = 0.f, ti = 0.f;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const float dx = ax - S[12 + 3 * q], dy = ay - S[13 + 3 * q], dz = az - S[14 + 3 * q];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const float r2 = fmaf(mx, S[12 + 3 * q], fmaf(my, S[13 + 3 * q], fmaf(mz, S[14 + 3 * q], A + B[q])));
             kern_f32<OP>(r2, wb[q], kf, kk, tr, ti);
         }
         if constexpr (is_dlp<OP>()) {
@@ -405,6 +413,103 @@ __global__ __launch_bounds__(256) void k_p0_f64(const ReqDev *__restrict__ reqs,
     }
 }
 
+// Per-entry reduction of P1 partials in the fixed order of the segment list
+// (ascending lane triangle), compensated in FP32.
+template <bool CPLX>
+__device__ __forceinline__ void reduce_entry_f32(const ReqDev &R, int64_t idx)
+{
+    const int64_t r = idx / R.ncols, c = idx - r * R.ncols;
+    const int64_t f = R.rowfix ? r : c;
+    const int64_t op = R.rowfix ? c : r;
+    const int s0 = R.seg_ptr[op], s1 = R.seg_ptr[op + 1];
+    float hr = 0.f, lr = 0.f, hi = 0.f, li = 0.f;
+    for (int s = s0; s < s1; ++s) {
+        const int pk = R.seg[s];
+        const int64_t at = (f * R.nlane + (pk >> 2)) * 3 + (pk & 3);
+        if constexpr (CPLX) {
+            const float4 v = reinterpret_cast<const float4 *>(R.part)[at];
+            two_sum_acc(hr, lr, v.x);
+            lr += v.y;
+            two_sum_acc(hi, li, v.z);
+            li += v.w;
+        } else {
+            const float2 v = reinterpret_cast<const float2 *>(R.part)[at];
+            two_sum_acc(hr, lr, v.x);
+            lr += v.y;
+        }
+    }
+    if constexpr (CPLX)
+        reinterpret_cast<float2 *>(R.out)[idx] = make_float2(hr + lr, hi + li);
+    else
+        reinterpret_cast<float *>(R.out)[idx] = hr + lr;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f32(const ReqDev *__restrict__ reqs,
+                                                               const RTile *__restrict__ tiles, int64_t ntiles)
+{
+    const RTile tl = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= tl.count) return;
+    reduce_entry_f32<CPLX>(reqs[tl.req], tl.e0 + threadIdx.x);
+}
+
+template <bool CPLX>
+__device__ __forceinline__ void reduce_entry_f64(const ReqDev &R, int64_t idx)
+{
+    const int64_t r = idx / R.ncols, c = idx - r * R.ncols;
+    const int64_t f = R.rowfix ? r : c;
+    const int64_t op = R.rowfix ? c : r;
+    const int s0 = R.seg_ptr[op], s1 = R.seg_ptr[op + 1];
+    double ar = 0.0, ai = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const int pk = R.seg[s];
+        const int64_t at = (f * R.nlane + (pk >> 2)) * 3 + (pk & 3);
+        if constexpr (CPLX) {
+            const double2 v = reinterpret_cast<const double2 *>(R.part)[at];
+            ar += v.x;
+            ai += v.y;
+        } else {
+            ar += reinterpret_cast<const double *>(R.part)[at];
+        }
+    }
+    if constexpr (CPLX)
+        reinterpret_cast<double2 *>(R.out)[idx] = make_double2(ar, ai);
+    else
+        reinterpret_cast<double *>(R.out)[idx] = ar;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f64(const ReqDev *__restrict__ reqs,
+                                                               const RTile *__restrict__ tiles, int64_t ntiles)
+{
+    const RTile tl = tiles[blockIdx.x];
+    if ((int)threadIdx.x >= tl.count) return;
+    reduce_entry_f64<CPLX>(reqs[tl.req], tl.e0 + threadIdx.x);
+}
+
+// Fused reduction of small P1 requests: after its partials are stored, each
+// tile counts itself in with a device-scope release fence and an atomic;
+// the tile that arrives last (acquire fence) reduces every entry of the
+// request, 64 entries at a time.
+template <bool F32, bool CPLX>
+__device__ __forceinline__ void fused_reduce_tail(const ReqDev &R, int lane)
+{
+    if (!R.counter) return;
+    __threadfence();
+    int last = 0;
+    if (lane == 0) last = atomicAdd(R.counter, 1) == R.ntiles_req - 1 ? 1 : 0;
+    last = __builtin_amdgcn_readfirstlane(last);
+    if (!last) return;
+    __threadfence();
+    const int64_t n = (int64_t)R.nrows * R.ncols;
+    for (int64_t idx = lane; idx < n; idx += 64) {
+        if constexpr (F32)
+            reduce_entry_f32<CPLX>(R, idx);
+        else
+            reduce_entry_f64<CPLX>(R, idx);
+    }
+}
+
 // P1: lane triangle against the fixed vertex star; writes the three
 // compensated partial sums (one per local vertex of the lane triangle).
 template <int OP, int Q, bool ROWFIX>
@@ -456,6 +561,7 @@ __global__ __launch_bounds__(256) void k_p1_f32(const ReqDev *__restrict__ reqs,
                 reinterpret_cast<float2 *>(R.part)[base + e] = make_float2(hr[e], lr[e]);
         }
     }
+    fused_reduce_tail<true, is_cplx<OP>()>(R, lane);
 }
 
 template <int OP, int Q, bool ROWFIX>
@@ -507,72 +613,7 @@ __global__ __launch_bounds__(256) void k_p1_f64(const ReqDev *__restrict__ reqs,
                 reinterpret_cast<double *>(R.part)[base + e] = ar[e];
         }
     }
-}
-
-// Per-entry reduction of P1 partials in the fixed order of the segment list
-// (ascending lane triangle), compensated in FP32.
-template <bool CPLX>
-__global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f32(const ReqDev *__restrict__ reqs,
-                                                               const RTile *__restrict__ tiles, int64_t ntiles)
-{
-    const RTile tl = tiles[blockIdx.x];
-    if ((int)threadIdx.x >= tl.count) return;
-    const ReqDev &R = reqs[tl.req];
-    const int64_t idx = tl.e0 + threadIdx.x;
-    const int64_t r = idx / R.ncols, c = idx - r * R.ncols;
-    const int64_t f = R.rowfix ? r : c;
-    const int64_t op = R.rowfix ? c : r;
-    const int s0 = R.seg_ptr[op], s1 = R.seg_ptr[op + 1];
-    float hr = 0.f, lr = 0.f, hi = 0.f, li = 0.f;
-    for (int s = s0; s < s1; ++s) {
-        const int pk = R.seg[s];
-        const int64_t at = (f * R.nlane + (pk >> 2)) * 3 + (pk & 3);
-        if constexpr (CPLX) {
-            const float4 v = reinterpret_cast<const float4 *>(R.part)[at];
-            two_sum_acc(hr, lr, v.x);
-            lr += v.y;
-            two_sum_acc(hi, li, v.z);
-            li += v.w;
-        } else {
-            const float2 v = reinterpret_cast<const float2 *>(R.part)[at];
-            two_sum_acc(hr, lr, v.x);
-            lr += v.y;
-        }
-    }
-    if constexpr (CPLX)
-        reinterpret_cast<float2 *>(R.out)[idx] = make_float2(hr + lr, hi + li);
-    else
-        reinterpret_cast<float *>(R.out)[idx] = hr + lr;
-}
-
-template <bool CPLX>
-__global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f64(const ReqDev *__restrict__ reqs,
-                                                               const RTile *__restrict__ tiles, int64_t ntiles)
-{
-    const RTile tl = tiles[blockIdx.x];
-    if ((int)threadIdx.x >= tl.count) return;
-    const ReqDev &R = reqs[tl.req];
-    const int64_t idx = tl.e0 + threadIdx.x;
-    const int64_t r = idx / R.ncols, c = idx - r * R.ncols;
-    const int64_t f = R.rowfix ? r : c;
-    const int64_t op = R.rowfix ? c : r;
-    const int s0 = R.seg_ptr[op], s1 = R.seg_ptr[op + 1];
-    double ar = 0.0, ai = 0.0;
-    for (int s = s0; s < s1; ++s) {
-        const int pk = R.seg[s];
-        const int64_t at = (f * R.nlane + (pk >> 2)) * 3 + (pk & 3);
-        if constexpr (CPLX) {
-            const double2 v = reinterpret_cast<const double2 *>(R.part)[at];
-            ar += v.x;
-            ai += v.y;
-        } else {
-            ar += reinterpret_cast<const double *>(R.part)[at];
-        }
-    }
-    if constexpr (CPLX)
-        reinterpret_cast<double2 *>(R.out)[idx] = make_double2(ar, ai);
-    else
-        reinterpret_cast<double *>(R.out)[idx] = ar;
+    fused_reduce_tail<false, is_cplx<OP>()>(R, lane);
 }
 
 // ---------------------------------------------------------------------------

@@ -10,6 +10,8 @@
 // residual updates stay on the host in FP64.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <complex>
 #include <deque>
 #include <thread>
@@ -199,12 +201,18 @@ struct DoneQueue {
         }
         d->cv.notify_one();
     }
-    void pop_all(std::vector<Request *> &out)
+    // Up to `most` finished requests, oldest first.
+    void pop_some(std::vector<Request *> &out, size_t most)
     {
         std::unique_lock<std::mutex> lk(mu);
         cv.wait(lk, [&] { return !q.empty(); });
-        out.swap(q);
-        q.clear();
+        if (q.size() <= most) {
+            out.swap(q);
+            q.clear();
+        } else {
+            out.assign(q.begin(), q.begin() + most);
+            q.erase(q.begin(), q.begin() + most);
+        }
     }
 };
 
@@ -238,6 +246,8 @@ struct AssemblyCtx {
     std::atomic<int64_t> aca_entries{0}, dense_entries{0}, requests{0};
     std::mutex busy_mu;
     double busy = 0.0;
+    double qdelay = 0.0, proc = 0.0;   // completion -> pickup, pickup -> resubmit (summed over requests)
+    int64_t nproc = 0;
 
     void set_error(int code, const std::string &msg)
     {
@@ -335,15 +345,18 @@ void worker(AssemblyCtx &C, int per_worker)
         }
         submit.clear();
     };
-    double busy = 0.0;
+    double busy = 0.0, qd = 0.0, pr = 0.0;
+    int64_t np = 0;
     double tb = now_seconds();
     for (int64_t si = 0; si < per_worker; ++si)
         if (!start_job(si)) break;
     flush();
     while (active > 0) {
         busy += now_seconds() - tb;
-        dq.pop_all(done);
+        dq.pop_some(done, 64);
         tb = now_seconds();
+        for (Request *r : done) qd += tb - r->t_done;
+        np += (int64_t)done.size();
         for (Request *r : done) {
             Slot<T> &s = slots[r->tag];
             bool finished = false;
@@ -393,12 +406,17 @@ void worker(AssemblyCtx &C, int per_worker)
             }
             submit.push_back(&s.req);
         }
+        const size_t nd = done.size();
         done.clear();
         flush();
+        pr += (now_seconds() - tb) * (double)nd;
     }
     busy += now_seconds() - tb;
     std::lock_guard<std::mutex> g(C.busy_mu);
     C.busy += busy;
+    C.qdelay += qd;
+    C.proc += pr;
+    C.nproc += np;
 }
 
 template <typename T>
@@ -637,6 +655,10 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
     s.setup_seconds = t_setup - t_part;
     s.aca_seconds = t_aca - t_setup;
     s.worker_busy_seconds = C.busy;
+    if (std::getenv("BEM_DEBUG_TIMING"))
+        fprintf(stderr, "[bem] assembly %.3fs: partition %.3f setup %.3f aca %.3f; %lld completions, mean pickup delay %.1f us, mean batch-processing span %.1f us\n",
+                s.seconds, s.partition_seconds, s.setup_seconds, s.aca_seconds, (long long)C.nproc,
+                1e6 * C.qdelay / std::max<int64_t>(1, C.nproc), 1e6 * C.proc / std::max<int64_t>(1, C.nproc));
     *out = h;
     return BEM_OK;
 }

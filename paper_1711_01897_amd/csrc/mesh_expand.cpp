@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 
 #include "bem_internal.hpp"
 
@@ -38,6 +39,15 @@ double now_seconds()
 {
     using clk = std::chrono::steady_clock;
     return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+int64_t fuse_reduce_max_entries()
+{
+    static const int64_t v = [] {
+        const char *e = std::getenv("BEM_FUSE_REDUCE_MAX");
+        return e ? std::max<int64_t>(0, std::atoll(e)) : (int64_t)0;
+    }();
+    return v;
 }
 
 bool is_complex_op(int op) { return op == BEM_HELMHOLTZ_SLP || op == BEM_HELMHOLTZ_DLP; }
@@ -108,9 +118,12 @@ void finalize_sizes(Request &r)
         r.nrtiles = (r.entries() + kReduceBlock - 1) / kReduceBlock;
     }
     r.ntiles = r.nfix * ((r.nlane + kTileLanes - 1) / kTileLanes);
+    r.fuse_reduce = r.space == BEM_P1 && r.ntiles > 0 && r.entries() <= fuse_reduce_max_entries();
+    if (r.fuse_reduce) r.nrtiles = 0;
     const size_t own = r.ext ? 0 : r.own.ints();
     r.in_bytes = align16(4 * (r.fix.size() + r.fstar.size() + own));
     r.out_bytes = align16((size_t)r.entries() * r.elem_bytes);
+    r.batch_bytes = request_bytes(r);
 }
 
 }  // namespace
@@ -204,7 +217,7 @@ size_t request_bytes(const Request &r)
 {
     // descriptor, group-table entries (request id + prefix, main and reduce), inputs, status, outputs,
     // partials, tiles
-    return sizeof(ReqDev) + 2 * (4 + 8) + r.in_bytes + 4 + r.out_bytes + r.part_bytes +
+    return sizeof(ReqDev) + 2 * (4 + 8) + r.in_bytes + 8 + r.out_bytes + r.part_bytes +
            (size_t)r.ntiles * sizeof(Tile) + (size_t)r.nrtiles * sizeof(RTile) + 64;
 }
 
@@ -259,6 +272,9 @@ void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t 
     d.out = dev_base + off_out;
     d.part = r.part_bytes ? dev_base + off_part : nullptr;
     d.status = reinterpret_cast<int32_t *>(dev_base + off_status);
+    d.counter = r.fuse_reduce ? reinterpret_cast<int32_t *>(dev_base + off_status) + 1 : nullptr;
+    d.ntiles_req = (int32_t)r.ntiles;
+    d.pad0 = 0;
 }
 
 }  // namespace bem

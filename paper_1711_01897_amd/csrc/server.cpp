@@ -11,10 +11,10 @@
 //  * fusion: all admitted requests of one kernel variant run in one launch,
 //    one wavefront per tile, whatever request the tile belongs to; the tile
 //    tables are built on the device from per-request tile counts;
-//  * overlap: several slots rotate, so the dispatcher stages and enqueues the
-//    next batches (behind the running one, on the same stream) while earlier
-//    ones run or are being consumed; requests that arrive meanwhile wait
-//    only for the next free slot;
+//  * overlap: several slots rotate, each with its own stream, so the
+//    dispatcher stages and enqueues the next batches while earlier ones run
+//    or are being consumed, and consecutive batches overlap on the device;
+//    requests that arrive meanwhile wait only for the next free slot;
 //  * completion: a second thread waits for each batch's event, checks the
 //    near-field flags, copies results to the callers' buffers (or lends the
 //    caller a pointer into the pinned staging until it releases it), wakes
@@ -23,6 +23,7 @@
 // summation order whichever batch it lands in.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <deque>
 #include <map>
 #include <thread>
@@ -33,7 +34,15 @@ namespace bem {
 
 namespace {
 
-constexpr int kMaxSlots = 8;
+constexpr int kMaxSlots = 16;
+constexpr int kTimedEvery = 4;
+
+int env_int(const char *name, int dflt, int lo, int hi)
+{
+    const char *e = std::getenv(name);
+    if (!e) return dflt;
+    return std::max(lo, std::min(hi, std::atoi(e)));
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -60,22 +69,25 @@ struct Batch {
     double t_launch = 0.0;
     int64_t entries = 0, evals = 0;
     std::atomic<int> refs{1};     // completion thread + borrowed results
+    bool timed = false;           // per-launch events recorded
 };
 
 class Server {
 public:
     size_t arena_bytes = size_t(1) << 30;
     int max_batch = 16384;
-    int nslots = 4;
+    int nslots = 8;     // BEM_SERVER_SLOTS
+    int nstreams = 8;   // BEM_SERVER_STREAMS (slot s uses stream s % nstreams), default one per slot
 
     std::mutex mu;
-    std::condition_variable cv;
+    std::condition_variable cv;    // dispatcher: pending requests, free slots
+    std::condition_variable cvc;   // completer: batches in flight
     std::deque<Request *> pending;
     std::deque<Batch *> inflight;
     bool slot_busy[kMaxSlots] = {};
     bool started = false, stop = false;
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t streams[kMaxSlots] = {};
     char *d_arena = nullptr, *h_stage = nullptr;
     size_t slot_bytes = 0;
     std::thread dispatcher, completer;
@@ -84,17 +96,21 @@ public:
 
     // statistics
     std::mutex stat_mu;
-    int64_t n_requests = 0, n_entries = 0, n_batches = 0, n_evals = 0, n_launches = 0;
+    int64_t n_requests = 0, n_entries = 0, n_batches = 0, n_evals = 0, n_launches = 0, n_timed = 0;
     double busy = 0.0, last_done = 0.0, kernel_s = 0.0, reduce_s = 0.0;
     double dispatch_s = 0.0, complete_s = 0.0, wait_s = 0.0;
     std::vector<float> latencies;
     std::map<std::pair<Variant, int>, KStat> kstats;
+    std::vector<int> group_members[64], rgroup_members[4];   // dispatcher scratch
+    int64_t batch_counter = 0;
 
     int start()
     {
         if (started) return BEM_OK;
+        nslots = env_int("BEM_SERVER_SLOTS", nslots, 2, kMaxSlots);
+        nstreams = env_int("BEM_SERVER_STREAMS", nslots, 1, nslots);
         hipError_t e = hipGetDevice(&device);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
+        for (int i = 0; i < nstreams && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipMalloc(&d_arena, arena_bytes);
         if (e == hipSuccess) e = hipHostMalloc(&h_stage, arena_bytes, hipHostMallocDefault);
         if (e != hipSuccess) {
@@ -165,7 +181,7 @@ public:
 
     // batch-level slack: alignment of sections and group tables
     static constexpr size_t kSlack = size_t(1) << 17;
-    bool fits(const Request *r) const { return request_bytes(*r) + kSlack <= slot_bytes; }
+    bool fits(const Request *r) const { return r->batch_bytes + kSlack <= slot_bytes; }
 
     int submit_many(Request *const *rs, size_t n)
     {
@@ -188,7 +204,7 @@ public:
                 pending.push_back(r);
             }
         }
-        cv.notify_all();
+        cv.notify_one();
         return BEM_OK;
     }
 
@@ -219,7 +235,7 @@ public:
                 size_t bytes = kSlack;
                 while (!pending.empty() && (int)take.size() < max_batch) {
                     Request *r = pending.front();
-                    const size_t rb = request_bytes(*r);
+                    const size_t rb = r->batch_bytes;
                     if (!take.empty() && bytes + rb > slot_bytes) break;
                     take.push_back(r);
                     bytes += rb;
@@ -238,7 +254,7 @@ public:
                 std::lock_guard<std::mutex> g(mu);
                 inflight.push_back(b);
             }
-            cv.notify_all();
+            cvc.notify_one();
         }
     }
 
@@ -249,18 +265,32 @@ public:
         b->reqs = take;
         char *hb = h_stage + (size_t)slot * slot_bytes;
         char *db = d_arena + (size_t)slot * slot_bytes;
+        hipStream_t stream = streams[slot % nstreams];
         const int n = (int)take.size();
 
-        // kernel variant groups (entry launches) and reduction groups
-        std::map<Variant, std::vector<int>> groups;
-        std::map<std::pair<int, int>, std::vector<int>> rgroups;
+        // kernel variant groups (entry launches) and reduction groups, indexed
+        // by (op, space, prec, rule, fixed side) and (prec, complex)
+        for (auto &g : group_members) g.clear();
+        for (auto &g : rgroup_members) g.clear();
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
-            if (r.ntiles > 0) groups[Variant{r.op, r.space, r.prec, r.mesh->q, r.rowfix}].push_back(i);
-            if (r.nrtiles > 0) rgroups[{r.prec, is_complex_op(r.op) ? 1 : 0}].push_back(i);
+            if (r.ntiles > 0)
+                group_members[(((r.op * 2 + r.space) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0)) * 2 + r.rowfix]
+                    .push_back(i);
+            if (r.nrtiles > 0) rgroup_members[r.prec * 2 + (is_complex_op(r.op) ? 1 : 0)].push_back(i);
             b->entries += r.entries();
             b->evals += r.evals;
         }
+        std::vector<std::pair<Variant, const std::vector<int> *>> groups;
+        for (int key = 0; key < 64; ++key) {
+            if (group_members[key].empty()) continue;
+            const int rowfix = key & 1, q = (key >> 1) & 1 ? 6 : 4, prec = (key >> 2) & 1, space = (key >> 3) & 1,
+                      op = key >> 4;
+            groups.push_back({Variant{op, space, prec, q, rowfix}, &group_members[key]});
+        }
+        std::vector<std::pair<std::pair<int, int>, const std::vector<int> *>> rgroups;
+        for (int key = 0; key < 4; ++key)
+            if (!rgroup_members[key].empty()) rgroups.push_back({{key >> 1, key & 1}, &rgroup_members[key]});
 
         // layout: descriptors | group tables | inputs | status | outputs || partials | tiles
         // (offsets first, checked against the slot, then the staging writes)
@@ -269,19 +299,19 @@ public:
             Launch L;
             L.v = g.first;
             L.reduce = false;
-            L.ng = (int)g.second.size();
+            L.ng = (int)g.second->size();
             launches.push_back(L);
         }
         for (auto &g : rgroups) {
             Launch L;
             L.v = Variant{g.first.second ? BEM_HELMHOLTZ_SLP : BEM_LAPLACE_SLP, BEM_P1, g.first.first, 0, 0};
             L.reduce = true;
-            L.ng = (int)g.second.size();
+            L.ng = (int)g.second->size();
             launches.push_back(L);
         }
         std::vector<const std::vector<int> *> members;
-        for (auto &g : groups) members.push_back(&g.second);
-        for (auto &g : rgroups) members.push_back(&g.second);
+        for (auto &g : groups) members.push_back(g.second);
+        for (auto &g : rgroups) members.push_back(g.second);
         size_t off = 0;
         const size_t off_reqs = off;
         off = align256(off + sizeof(ReqDev) * n);
@@ -306,7 +336,7 @@ public:
         const size_t off_in = off;
         for (int i = 0; i < n; ++i) off += take[i]->in_bytes;
         const size_t off_status = align256(off);
-        off = align256(off_status + sizeof(int32_t) * n);
+        off = align256(off_status + 2 * sizeof(int32_t) * n);
         const size_t h2d_end = off;
         std::vector<size_t> out_off(n), part_off(n);
         for (int i = 0; i < n; ++i) {
@@ -352,12 +382,12 @@ public:
         }
         size_t in = off_in;
         for (int i = 0; i < n; ++i) in += stage_request_inputs(*take[i], hb, db, in, hreq[i]);
-        std::memset(hb + off_status, 0, sizeof(int32_t) * n);
+        std::memset(hb + off_status, 0, 2 * sizeof(int32_t) * n);
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
-            finish_descriptor(r, db, out_off[i], part_off[i], off_status + 4 * i, hreq[i]);
+            finish_descriptor(r, db, out_off[i], part_off[i], off_status + 8 * i, hreq[i]);
             r.off_out = out_off[i];
-            r.off_status = off_status + 4 * i;
+            r.off_status = off_status + 8 * i;
         }
         b->launches = launches;
         GroupDesc *gd = reinterpret_cast<GroupDesc *>(hb + off_groups);
@@ -379,8 +409,10 @@ public:
         const ReqDev *dreq = reinterpret_cast<const ReqDev *>(db + off_reqs);
         (void)launch_build_all(dreq, reinterpret_cast<const GroupDesc *>(db + off_groups), (int)b->launches.size(),
                                tile_total, stream);
-        // n + 1 events bracket n consecutive launches
-        if (!b->launches.empty()) {
+        // n + 1 events bracket n consecutive launches, on every kTimedEvery-th
+        // batch (launch durations are sampled; the batch event is always kept)
+        b->timed = (batch_counter++ % kTimedEvery) == 0;
+        if (b->timed && !b->launches.empty()) {
             hipEvent_t e = get_event();
             (void)hipEventRecord(e, stream);
             b->ev.push_back(e);
@@ -391,9 +423,11 @@ public:
                                        reinterpret_cast<const RTile *>(db + L.off_tiles), L.ntiles, stream);
             else
                 (void)launch_entries(L.v, dreq, reinterpret_cast<const Tile *>(db + L.off_tiles), L.ntiles, stream);
-            hipEvent_t e = get_event();
-            (void)hipEventRecord(e, stream);
-            b->ev.push_back(e);
+            if (b->timed) {
+                hipEvent_t e = get_event();
+                (void)hipEventRecord(e, stream);
+                b->ev.push_back(e);
+            }
         }
         (void)hipMemcpyAsync(hb + off_status, db + off_status, d2h_end - off_status, hipMemcpyDeviceToHost, stream);
         b->ev_done = get_event();
@@ -413,7 +447,7 @@ public:
             std::lock_guard<std::mutex> g(mu);
             slot_busy[b->slot] = false;
         }
-        cv.notify_all();
+        cv.notify_one();
         delete b;
     }
 
@@ -424,7 +458,7 @@ public:
             Batch *b = nullptr;
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv.wait(lk, [&] { return !inflight.empty() || (stop && pending.empty()); });
+                cvc.wait(lk, [&] { return !inflight.empty() || (stop && pending.empty()); });
                 if (inflight.empty()) return;
                 b = inflight.front();
                 inflight.pop_front();
@@ -434,27 +468,31 @@ public:
             const double t_done = now_seconds();
             double ks = 0.0, rs = 0.0;
             std::vector<double> dur(b->launches.size(), 0.0);
-            for (size_t i = 0; i < b->launches.size(); ++i) {
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, b->ev[i], b->ev[i + 1]) == hipSuccess) {
-                    dur[i] = ms * 1e-3;
-                    (b->launches[i].reduce ? rs : ks) += ms * 1e-3;
+            if (b->timed)
+                for (size_t i = 0; i < b->launches.size(); ++i) {
+                    float ms = 0.f;
+                    if (hipEventElapsedTime(&ms, b->ev[i], b->ev[i + 1]) == hipSuccess) {
+                        dur[i] = ms * 1e-3;
+                        (b->launches[i].reduce ? rs : ks) += ms * 1e-3;
+                    }
                 }
-            }
             {
                 std::lock_guard<std::mutex> g(stat_mu);
                 n_batches += 1;
                 n_requests += (int64_t)b->reqs.size();
                 n_entries += b->entries;
                 n_evals += b->evals;
-                n_launches += (int64_t)b->launches.size();
-                kernel_s += ks;
-                reduce_s += rs;
+                if (b->timed) {
+                    n_timed += 1;
+                    n_launches += (int64_t)b->launches.size();
+                    kernel_s += ks;
+                    reduce_s += rs;
+                }
                 busy += t_done - std::max(b->t_launch, last_done);
                 last_done = t_done;
                 for (Request *r : b->reqs)
                     if (latencies.size() < (size_t(1) << 24)) latencies.push_back((float)(t_done - r->t_submit));
-                for (size_t i = 0; i < b->launches.size(); ++i) {
+                for (size_t i = 0; b->timed && i < b->launches.size(); ++i) {
                     const Launch &L = b->launches[i];
                     KStat &k = kstats[{L.v, L.reduce ? 1 : 0}];
                     k.launches += 1;
@@ -532,8 +570,10 @@ public:
         s->batches = n_batches;
         s->kernel_evals = n_evals;
         s->busy_seconds = busy;
-        s->kernel_seconds = kernel_s;
-        s->kernel_seconds_p1_reduce = reduce_s;
+        // timed batches are a sample: scale to all batches
+        const double scale = n_timed ? (double)n_batches / (double)n_timed : 0.0;
+        s->kernel_seconds = kernel_s * scale;
+        s->kernel_seconds_p1_reduce = reduce_s * scale;
         s->kernel_launches = n_launches;
         s->dispatch_seconds = dispatch_s;
         s->complete_seconds = complete_s;
@@ -551,7 +591,7 @@ public:
             s->latency_max = *std::max_element(latencies.begin(), latencies.end());
         }
         if (reset) {
-            n_requests = n_entries = n_batches = n_evals = n_launches = 0;
+            n_requests = n_entries = n_batches = n_evals = n_launches = n_timed = 0;
             busy = kernel_s = reduce_s = 0.0;
             dispatch_s = complete_s = wait_s = 0.0;
             latencies.clear();
