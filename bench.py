@@ -53,8 +53,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workers", type=int, default=12)
-    ap.add_argument("--blocks-per-worker", type=int, default=64)
+    ap.add_argument("--workers", type=int, default=14)
+    ap.add_argument("--blocks-per-worker", type=int, default=128)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -113,7 +113,7 @@ def timed(bem, mesh, prec, steps, warmup, args):
 
 
 def roofline(kstats):
-    main = [k for k in kstats if not k["reduce"]]
+    main = list(kstats)
     if not main:
         return None, None
     dom = max(main, key=lambda k: k["seconds"])
@@ -127,8 +127,8 @@ def roofline(kstats):
             t = json.load(f)
         if t.get("kernel_source_hash") == kernel_source_hash():
             traffic = t.get("bytes_per_launch")
-    name = "%s_f%s<op=%d,Q=%d,rowfix=%d>" % (KERNEL_NAMES[dom["space"]], "32" if dom["prec"] == 1 else "64",
-                                            dom["op"], dom["quad_points"], dom["rowfix"])
+    name = "%s_f%s<op=%d,Q=%d>" % (KERNEL_NAMES[dom["space"]], "32" if dom["prec"] == 1 else "64",
+                                   dom["op"], dom["quad_points"])
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_VALU / 1e12, 1),
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_VALU, 4), "traffic": traffic,
             "kernel": name, "launches": dom["launches"], "mean_launch_us": round(mean_s * 1e6, 2),
@@ -244,10 +244,12 @@ def main():
         "requests_per_batch": sst["requests"] / max(1, sst["batches"]),
         "assembly_seconds_per_step": tot["phases"],
         "server_seconds_per_step": {"dispatch": sst["dispatch_seconds"] / args.steps,
+                                    "dispatch_hip_calls": sst["dispatch_hip_seconds"] / args.steps,
                                     "complete": sst["complete_seconds"] / args.steps,
                                     "event_wait": sst["wait_seconds"] / args.steps,
-                                    "entry_kernels": sst["kernel_seconds"] / args.steps,
-                                    "p1_reduce_kernels": sst["kernel_seconds_p1_reduce"] / args.steps},
+                                    "entry_kernels": sst["kernel_seconds"] / args.steps},
+        "request_latency_legs_us": {k: round(sst["mean_%s_seconds" % k] * 1e6, 1)
+                                    for k in ("queue", "stage", "device", "complete")},
         "kernel_busy_fraction": sst["kernel_seconds"] / dt if dt > 0 else None,
         "fp64": fp64,
         "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,

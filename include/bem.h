@@ -166,29 +166,34 @@ typedef struct {
     double busy_seconds;     /* wall time with at least one batch on the device */
     double kernel_seconds;   /* entry-kernel launch durations (HIP events), summed over the timed
                                 batches and scaled to all batches */
-    double kernel_seconds_p1_reduce;
-    int64_t kernel_launches; /* launches timed: every launch of one batch in four is bracketed by
+    int64_t kernel_launches; /* launches timed: every launch of one batch in four carries start/stop
                                 HIP events, so kernel_seconds covers that sample */
     double dispatch_seconds; /* host time spent staging and enqueueing batches */
     double complete_seconds; /* host time spent completing batches (after their event) */
     double wait_seconds;     /* completion-thread time spent waiting for batch events */
+    double dispatch_hip_seconds; /* part of dispatch_seconds spent inside HIP enqueue calls */
+    /* request-weighted means of the four legs of submit -> completion */
+    double mean_queue_seconds;    /* submitted -> taken into a batch */
+    double mean_stage_seconds;    /* taken -> batch enqueued on its stream */
+    double mean_device_seconds;   /* enqueued -> batch event observed complete */
+    double mean_complete_seconds; /* event observed -> request completed (callbacks included) */
 } bem_server_stats_t;
 
 /* Statistics since the last reset; reset != 0 clears them afterwards. */
 int bem_server_stats(bem_server_stats_t *stats, int reset);
 
-/* Per kernel variant: launches, durations (HIP events recorded around each
- * launch on the batch's stream, for one batch in four) and the work those
- * timed launches covered. */
+/* Per kernel variant: launches, durations (start/stop HIP events bound to
+ * each launch's own dispatch, for one batch in four) and the work those
+ * timed launches covered.  One entry launch serves row and column requests
+ * alike. */
 typedef struct {
     int32_t op, space, prec, quad_points;
-    int32_t rowfix;            /* 1: the test side is fixed per tile (lanes run over trial triangles) */
-    int32_t reduce;            /* 1: P1 per-entry reduction launch (op/space/q not meaningful) */
     int64_t launches;
+    int64_t workgroups;        /* 256-thread workgroups of these launches */
     int64_t entries;           /* entries of the requests these launches served */
     int64_t pair_evals;        /* Q^2 x (fixed, lane) triangle pairs; vertex-sharing pairs, which are
                                   skipped, are included (there are none in admissible blocks) */
-    int64_t triangle_loads;    /* lane-triangle geometry records gathered (one per lane per tile) */
+    int64_t triangle_loads;    /* lane-triangle geometry records gathered (one per lane per workgroup) */
     double seconds;            /* summed launch durations */
 } bem_kernel_stats_t;
 

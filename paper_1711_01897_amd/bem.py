@@ -61,15 +61,17 @@ class ServerStats(ctypes.Structure):
                 ("kernel_evals", ctypes.c_int64), ("latency_p50", ctypes.c_double),
                 ("latency_p99", ctypes.c_double), ("latency_max", ctypes.c_double),
                 ("busy_seconds", ctypes.c_double), ("kernel_seconds", ctypes.c_double),
-                ("kernel_seconds_p1_reduce", ctypes.c_double), ("kernel_launches", ctypes.c_int64),
+                ("kernel_launches", ctypes.c_int64),
                 ("dispatch_seconds", ctypes.c_double), ("complete_seconds", ctypes.c_double),
-                ("wait_seconds", ctypes.c_double)]
+                ("wait_seconds", ctypes.c_double), ("dispatch_hip_seconds", ctypes.c_double),
+                ("mean_queue_seconds", ctypes.c_double), ("mean_stage_seconds", ctypes.c_double),
+                ("mean_device_seconds", ctypes.c_double), ("mean_complete_seconds", ctypes.c_double)]
 
 
 class KernelStats(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("space", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("quad_points", ctypes.c_int32), ("rowfix", ctypes.c_int32), ("reduce", ctypes.c_int32),
-                ("launches", ctypes.c_int64), ("entries", ctypes.c_int64), ("pair_evals", ctypes.c_int64),
+                ("quad_points", ctypes.c_int32),
+                ("launches", ctypes.c_int64), ("workgroups", ctypes.c_int64), ("entries", ctypes.c_int64), ("pair_evals", ctypes.c_int64),
                 ("triangle_loads", ctypes.c_int64), ("seconds", ctypes.c_double)]
 
 

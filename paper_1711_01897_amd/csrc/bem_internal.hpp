@@ -15,6 +15,8 @@
 
 namespace bem {
 
+struct Request;
+
 // ---------------------------------------------------------------------------
 // Device layout of one triangle.
 //
@@ -32,15 +34,16 @@ namespace bem {
 //   [0..2] unit normal  [3] J  [4..] absolute quadrature points, point-major.
 constexpr int kGeo32Stride = 32;
 constexpr int kGeo64Stride = 24;
-constexpr int kTileLanes = 64;      // one wavefront per tile
-constexpr int kWavesPerBlock = 4;   // 256-thread workgroups
-constexpr int kReduceBlock = 256;
+constexpr int kBlockLanes = 256;    // lane-side items per workgroup (4 wavefronts)
+constexpr int kStage = 8;           // fixed-side triangles staged in LDS at a time
 
 // One request as the entry kernels see it.
 //
-// "fixed" side: one triangle (P0) or one vertex star (P1) shared by the 64
-// lanes of a tile; "lane" side: one triangle per lane.  rowfix = 1 means the
-// fixed side is the test (row) side.
+// "fixed" side: one triangle (P0) or one vertex star (P1) shared by the
+// lanes of a workgroup; "lane" side: one triangle per lane, grouped in
+// chunks of at most kBlockLanes lanes.  rowfix = 1 means the fixed side is
+// the test (row) side.  Output position (fixed f, lane-side dof d) is
+// out[f * sf + d * sl].
 struct ReqDev {
     const float *g32;
     const double *g64;
@@ -48,69 +51,49 @@ struct ReqDev {
     const int32_t *fix;        // P0: triangle per fixed position; P1: star ranges (nfix + 1)
     const int32_t *fstar;      // P1: packed (triangle << 2 | local vertex) of fixed stars
     const int32_t *lane;       // triangle per lane position
-    const int32_t *seg_ptr;    // P1: per output position on the lane side, range into seg
-    const int32_t *seg;        // P1: packed (lane slot << 2 | local vertex)
-    void *part;                // P1: per (fixed pos, lane slot, local vertex) partial sums
+    const int4 *chunk;         // per chunk: first lane, lanes, first dof, dofs
+    const int32_t *seg_ptr;    // P1: per lane-side dof, range into seg
+    const int32_t *seg;        // P1: packed (lane slot within the chunk << 2 | local vertex)
     void *out;                 // final output, row-major nrows x ncols
-    int32_t *status;           // bit 0: a vertex-sharing pair was met under BEM_NEAR_ERROR
-    int32_t *counter;          // P1 with fused reduction: tiles finished so far (zeroed); else null
-    int64_t sf, sl;            // P0: out index = fixed_pos * sf + lane_pos * sl
+    int32_t *status;           // set to 1: a vertex-sharing pair was met under BEM_NEAR_ERROR
+    int64_t sf, sl;
     int32_t nrows, ncols;
-    int32_t nlane;             // lane-side item count
+    int32_t nlane;             // lane-side items over all chunks
     int32_t nfix;              // fixed-side positions
     int32_t rowfix;
     int32_t near_error;
-    int32_t ntiles_req;        // entry tiles of this request (fused reduction: the last one reduces)
-    int32_t pad0;
     double k;                  // wavenumber
     double kk;                 // k / (2 pi): phase in turns per unit length
 };
 
-struct Tile {        // one wavefront of entry work
+struct EntryBlock {  // one workgroup of entry work
     int32_t req;
     int32_t fixed;   // fixed position
-    int32_t lane0;   // first lane position
-    int32_t nlanes;  // active lanes (<= 64)
+    int32_t chunk;   // lane-side chunk
+    int32_t pad;
 };
 
-struct RTile {       // one workgroup of P1 reduction work
-    int32_t req;
-    int32_t count;   // entries (<= kReduceBlock)
-    int64_t e0;      // first flat output index
-};
-
-// Kernel variant: one compiled instantiation of the entry kernel.
+// Kernel variant: one compiled instantiation of the entry kernel (it serves
+// both fixed sides).
 struct Variant {
-    int op, space, prec, q, rowfix;
+    int op, space, prec, q;
     bool operator<(const Variant &o) const {
         if (op != o.op) return op < o.op;
         if (space != o.space) return space < o.space;
         if (prec != o.prec) return prec < o.prec;
-        if (q != o.q) return q < o.q;
-        return rowfix < o.rowfix;
+        return q < o.q;
     }
 };
 
+// Block table of a request, written by the host: request index `ri` inside
+// its batch, blocks in (fixed, chunk) order; returns the count.
+int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out);
+
 // Launchers (entries.hip).  Return hipSuccess or the launch error.
-// Tile tables are built on the device from per-group request lists and
-// exclusive prefix sums of per-request tile counts (gpre has ng + 1 entries).
-hipError_t launch_build_tiles(const ReqDev *reqs, const int32_t *greq, const int64_t *gpre, int ng, int64_t ntiles,
-                              Tile *tiles, hipStream_t s);
-hipError_t launch_build_rtiles(const ReqDev *reqs, const int32_t *greq, const int64_t *gpre, int ng, int64_t ntiles,
-                               RTile *tiles, hipStream_t s);
-// All groups of a batch in one launch: group g covers global tiles
-// [tile0, tile0 + ntiles) and writes Tile (kind 0) or RTile (kind 1) records.
-struct GroupDesc {
-    int64_t tile0, ntiles;
-    const int32_t *greq;
-    const int64_t *gpre;
-    void *tiles;
-    int32_t ng, kind;
-};
-hipError_t launch_build_all(const ReqDev *reqs, const GroupDesc *groups, int ngroups, int64_t total, hipStream_t s);
-hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const Tile *tiles, int64_t ntiles, hipStream_t s);
-hipError_t launch_p1_reduce(int prec, bool cplx, const ReqDev *reqs, const RTile *tiles, int64_t ntiles,
-                            hipStream_t s);
+// `start`/`stop` (optional) are bound to the kernel's own dispatch, so their
+// elapsed time is the kernel's execution time, not the stream's.
+hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock *blocks, int64_t nblocks, hipStream_t s,
+                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, int q, float *g32, double *g64,
                            int4 *vtx, int32_t *bad, hipStream_t s);
 
@@ -159,21 +142,28 @@ struct bem_mesh {
 namespace bem {
 
 // ---------------------------------------------------------------------------
-// Lane side of a request: the triangles the lanes run over and, for P1, the
-// map from each requested lane-side dof to its (triangle, local vertex)
-// partial sums.  Computed once per dof list; device-resident copies are
-// shared by every request of an H-matrix block.
+// Lane side of a request: the triangles the lanes run over, in chunks of at
+// most kBlockLanes, and, for P1, the map from each requested lane-side dof to
+// its (triangle, local vertex) partial sums.  A P1 chunk holds a run of
+// consecutive lane-side dofs together with every triangle of their stars, so
+// one workgroup finishes those entries on its own (triangles on a chunk
+// border appear in both chunks).  Computed once per dof list; device-resident
+// copies are shared by every request of an H-matrix block.
 struct LaneSet {
     int64_t ndof = 0;                 // lane-side output positions
-    std::vector<int32_t> lane;        // P0: the dofs themselves; P1: distinct triangles, ascending
+    int64_t ndistinct = 0;            // distinct lane triangles (P0: ndof)
+    std::vector<int32_t> lane;        // P0: the dofs themselves; P1: triangles, chunk by chunk
+    std::vector<int32_t> chunk;       // 4 per chunk: first lane, lanes, first dof, dofs
     std::vector<int32_t> seg_ptr;     // P1: ndof + 1
-    std::vector<int32_t> seg;         // P1: packed (slot << 2 | local vertex)
-    size_t ints() const { return lane.size() + seg_ptr.size() + seg.size(); }
+    std::vector<int32_t> seg;         // P1: packed (slot within the chunk << 2 | local vertex)
+    int64_t nchunk() const { return (int64_t)chunk.size() / 4; }
+    size_t ints() const { return chunk.size() + lane.size() + seg_ptr.size() + seg.size(); }
 };
 
 struct LaneRef {                      // device pointers of a resident LaneSet
     const int32_t *lane = nullptr, *seg_ptr = nullptr, *seg = nullptr;
-    int64_t ndof = 0, nlane = 0, nseg = 0;
+    const int4 *chunk = nullptr;
+    int64_t ndof = 0, nlane = 0, nseg = 0, nchunk = 0, ndistinct = 0;
 };
 
 void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, LaneSet &ls);
@@ -196,12 +186,11 @@ struct Request {
     std::vector<int32_t> fix, fstar;   // fixed side
     LaneSet own;                       // lane side, when not external
     const LaneRef *ext = nullptr;      // device-resident lane side
-    int64_t nfix = 0, nlane = 0;
-    size_t elem_bytes = 0, part_elem_bytes = 0;
-    size_t in_bytes = 0, out_bytes = 0, part_bytes = 0;
-    int64_t evals = 0;          // Q^2 x (fixed, lane) triangle pairs, vertex-sharing pairs included
-    int64_t ntiles = 0, nrtiles = 0;
-    bool fuse_reduce = false;   // P1: the request's last entry tile performs the per-entry reduction
+    int64_t nfix = 0, nlane = 0, nchunk = 0, ndistinct = 0;
+    size_t elem_bytes = 0;
+    size_t in_bytes = 0, out_bytes = 0;
+    int64_t evals = 0;          // Q^2 x distinct (fixed, lane) triangle pairs, vertex-sharing pairs included
+    int64_t nblocks = 0;
     size_t batch_bytes = 0;     // request_bytes(), cached at expansion
 
     // completion
@@ -232,20 +221,14 @@ int expand_request(Request &r);
 // fixed side is a single dof known to be valid (H-matrix blocks).
 void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext);
 
-// Device bytes a request needs inside a batch (inputs, outputs, partials, tiles).
+// Device bytes a request needs inside a batch (inputs, outputs, block table).
 size_t request_bytes(const Request &r);
 
 // Writes the request's inputs at host_base + off (staging) and fills its
 // descriptor with device addresses at dev_base + off; returns the bytes used.
 size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d);
-// off_status addresses two int32 per request: status word, then the arrival
-// counter of the fused P1 reduction.
-void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_part, size_t off_status,
-                       ReqDev &d);
-// P1 requests with at most this many entries reduce inside the entry kernel
-// (last-arriving tile); 0 = always a separate reduction launch.  Set by the
-// BEM_FUSE_REDUCE_MAX environment variable, read once.
-int64_t fuse_reduce_max_entries();
+// off_status addresses the request's int32 status word (zeroed by the caller).
+void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_status, ReqDev &d);
 
 // Server
 int server_submit(Request *r);

@@ -217,29 +217,17 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
         }
     }
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    // layout: descriptor | tile groups | inputs | status || partials | tiles | reduction tiles
+    // layout: descriptor | block table | inputs | status
     size_t off = 0;
     const size_t off_req = off;
     off = al(off + sizeof(ReqDev));
-    const size_t off_g = off;
-    off = al(off + 4);
-    const size_t off_gp = off;
-    off = al(off + 16);
-    const size_t off_rg = off;
-    off = al(off + 4);
-    const size_t off_rgp = off;
-    off = al(off + 16);
+    const size_t off_b = off;
+    off = al(off + sizeof(EntryBlock) * (size_t)r.nblocks);
     const size_t off_in = off;
     off = al(off + r.in_bytes);
     const size_t off_status = off;
     off = al(off + 8);
     const size_t in_total = off;
-    const size_t off_part = off;
-    off = al(off + r.part_bytes);
-    const size_t off_t = off;
-    off = al(off + sizeof(Tile) * (size_t)r.ntiles);
-    const size_t off_rt = off;
-    off = al(off + sizeof(RTile) * (size_t)r.nrtiles);
     // descriptors go through pinned staging that is released once the copy
     // has completed (checked on later calls), so nothing here waits
     char *host = pinned_stage(in_total);
@@ -254,12 +242,10 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     }
     ReqDev d;
     stage_request_inputs(r, host, ws, off_in, d);
-    finish_descriptor(r, ws, 0, off_part, off_status, d);
+    finish_descriptor(r, ws, 0, off_status, d);
     d.out = dev_out;
     std::memcpy(host + off_req, &d, sizeof(ReqDev));
-    const int64_t gp[2] = {0, r.ntiles}, rgp[2] = {0, r.nrtiles};
-    std::memcpy(host + off_gp, gp, sizeof(gp));
-    std::memcpy(host + off_rgp, rgp, sizeof(rgp));
+    write_blocks(r, 0, reinterpret_cast<EntryBlock *>(host + off_b));
     e = hipMemcpyAsync(ws, host, in_total, hipMemcpyHostToDevice, s);
     hipEvent_t ev = nullptr;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -267,15 +253,8 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     pinned_release(host, e == hipSuccess ? ev : nullptr);
     if (e != hipSuccess) return fail(BEM_E_DEVICE, std::string("staging copy: ") + hipGetErrorString(e));
     const ReqDev *dreq = (const ReqDev *)(ws + off_req);
-    BEM_HIP_TRY(launch_build_tiles(dreq, (const int32_t *)(ws + off_g), (const int64_t *)(ws + off_gp), 1, r.ntiles,
-                                   (Tile *)(ws + off_t), s));
-    Variant v{r.op, r.space, r.prec, mesh->q, r.rowfix};
-    BEM_HIP_TRY(launch_entries(v, dreq, (const Tile *)(ws + off_t), r.ntiles, s));
-    if (space == BEM_P1 && r.nrtiles > 0) {
-        BEM_HIP_TRY(launch_build_rtiles(dreq, (const int32_t *)(ws + off_rg), (const int64_t *)(ws + off_rgp), 1,
-                                        r.nrtiles, (RTile *)(ws + off_rt), s));
-        BEM_HIP_TRY(launch_p1_reduce(r.prec, is_complex_op(r.op), dreq, (const RTile *)(ws + off_rt), r.nrtiles, s));
-    }
+    Variant v{r.op, r.space, r.prec, mesh->q};
+    BEM_HIP_TRY(launch_entries(v, dreq, (const EntryBlock *)(ws + off_b), r.nblocks, s));
     BEM_HIP_TRY(hipFreeAsync(ws, s));
     return BEM_OK;
 }

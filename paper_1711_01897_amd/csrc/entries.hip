@@ -1,13 +1,17 @@
 // Weak-form entry kernels for gfx950.
 //
-// One wavefront per tile.  A tile pairs one "fixed" item, shared by all 64
-// lanes (a test or trial triangle for P0, the star of a test or trial vertex
-// for P1), with up to 64 "lane" triangles, one per lane.  The fixed item's
-// geometry is wave-uniform; the lane triangles are gathered from the
-// resident per-triangle records (one 128-byte FP32 or 192-byte FP64 record
-// each).  Every lane evaluates the Green's function at all Q x Q pairs of
-// quadrature points (Section 3.3: kernel values at all pairs of Gauss
-// points, then weights times basis values for every pair of local dofs).
+// One 256-thread workgroup (four wavefronts) per block of work.  A block
+// pairs one "fixed" item (a test or trial triangle for P0, the star of a
+// test or trial vertex for P1) with up to 256 "lane" triangles, one per
+// thread.  The lane triangles are gathered from the resident per-triangle
+// records (one 128-byte FP32 or 192-byte FP64 record each); for P1 the
+// fixed star's records are staged once per workgroup in LDS, so the waves
+// read them at LDS latency instead of walking the star through dependent
+// global loads.  Every lane evaluates the Green's function at all Q x Q
+// pairs of quadrature points (Section 3.3: kernel values at all pairs of
+// Gauss points, then weights times basis values for every pair of local
+// dofs).  Test-fixed (row) and trial-fixed (column) requests share one
+// kernel and launch; the side is a workgroup-uniform branch.
 //
 // FP32 path: positions are centroid-relative (bem_internal.hpp), 1/r is the
 // hardware reciprocal square root, the Helmholtz phase k r is formed and
@@ -21,10 +25,12 @@
 //
 // P1 entries are sums over the triangles of two vertex stars (hat basis
 // functions, Section 2); each lane keeps the three partial sums of its lane
-// triangle (one per local vertex) over the fixed star, and a second kernel
-// adds the partials that belong to each requested entry in a fixed order.
-// No atomics touch the results, so results do not depend on which other
-// requests share a launch.
+// triangle (one per local vertex) over the fixed star in LDS, and after a
+// workgroup barrier each entry of the chunk adds the partials that belong to
+// it in a fixed order.  No atomics touch the results, so results do not
+// depend on which other requests share a launch.
+#include <hip/hip_ext.h>
+
 #include "bem_internal.hpp"
 #include "quad_rules.hpp"
 
@@ -339,19 +345,21 @@ __device__ __forceinline__ void pair_p1_f64(const double *T, const double *S, in
 
 // ---------------------------------------------------------------------------
 // Kernels.
+//
+// Workgroup B covers chunk B.chunk of the lane side against fixed position
+// B.fixed; thread t takes lane t of the chunk.  Threads past the end of the
+// chunk repeat its first lane (valid loads) and store nothing; a wavefront
+// with no valid lane skips the arithmetic.
+
 template <int OP, int Q, bool ROWFIX>
-__global__ __launch_bounds__(256) void k_p0_f32(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
-                                                int64_t ntiles)
+__device__ __forceinline__ void p0_body_f32(const ReqDev &R, const EntryBlock &B)
 {
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (t >= ntiles) return;
-    const Tile tl = tiles[t];
-    const ReqDev &R = reqs[tl.req];
-    const bool act = lane < tl.nlanes;
-    const int li = tl.lane0 + (act ? lane : 0);
-    const int tf = R.fix[tl.fixed];
+    const int4 ch = R.chunk[B.chunk];   // first lane, lanes, first dof, dofs
+    const int t = threadIdx.x;
+    if ((t & ~63) >= ch.y) return;
+    const bool act = t < ch.y;
+    const int li = ch.x + (act ? t : 0);
+    const int tf = R.fix[B.fixed];
     const int tn = R.lane[li];
     const int test = ROWFIX ? tf : tn, trial = ROWFIX ? tn : tf;
     const bool adj = share_vertex(R.vtx[test], R.vtx[trial]);
@@ -365,10 +373,10 @@ __global__ __launch_bounds__(256) void k_p0_f32(const ReqDev *__restrict__ reqs,
         vr *= sc;
         vi *= sc;
     } else if (act && R.near_error) {
-        atomicOr(R.status, 1);
+        *R.status = 1;
     }
     if (act) {
-        const int64_t o = (int64_t)tl.fixed * R.sf + (int64_t)li * R.sl;
+        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)(ch.z + t) * R.sl;
         if constexpr (is_cplx<OP>())
             reinterpret_cast<float2 *>(R.out)[o] = make_float2(vr, vi);
         else
@@ -376,19 +384,28 @@ __global__ __launch_bounds__(256) void k_p0_f32(const ReqDev *__restrict__ reqs,
     }
 }
 
-template <int OP, int Q, bool ROWFIX>
-__global__ __launch_bounds__(256) void k_p0_f64(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
-                                                int64_t ntiles)
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void k_p0_f32(const ReqDev *__restrict__ reqs,
+                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks)
 {
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (t >= ntiles) return;
-    const Tile tl = tiles[t];
-    const ReqDev &R = reqs[tl.req];
-    const bool act = lane < tl.nlanes;
-    const int li = tl.lane0 + (act ? lane : 0);
-    const int tf = R.fix[tl.fixed];
+    if ((int64_t)blockIdx.x >= nblocks) return;
+    const EntryBlock B = blocks[blockIdx.x];
+    const ReqDev &R = reqs[B.req];
+    if (R.rowfix)
+        p0_body_f32<OP, Q, true>(R, B);
+    else
+        p0_body_f32<OP, Q, false>(R, B);
+}
+
+template <int OP, int Q, bool ROWFIX>
+__device__ __forceinline__ void p0_body_f64(const ReqDev &R, const EntryBlock &B)
+{
+    const int4 ch = R.chunk[B.chunk];
+    const int t = threadIdx.x;
+    if ((t & ~63) >= ch.y) return;
+    const bool act = t < ch.y;
+    const int li = ch.x + (act ? t : 0);
+    const int tf = R.fix[B.fixed];
     const int tn = R.lane[li];
     const int test = ROWFIX ? tf : tn, trial = ROWFIX ? tn : tf;
     const bool adj = share_vertex(R.vtx[test], R.vtx[trial]);
@@ -402,10 +419,10 @@ __global__ __launch_bounds__(256) void k_p0_f64(const ReqDev *__restrict__ reqs,
         vr *= sc;
         vi *= sc;
     } else if (act && R.near_error) {
-        atomicOr(R.status, 1);
+        *R.status = 1;
     }
     if (act) {
-        const int64_t o = (int64_t)tl.fixed * R.sf + (int64_t)li * R.sl;
+        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)(ch.z + t) * R.sl;
         if constexpr (is_cplx<OP>())
             reinterpret_cast<double2 *>(R.out)[o] = make_double2(vr, vi);
         else
@@ -413,396 +430,252 @@ __global__ __launch_bounds__(256) void k_p0_f64(const ReqDev *__restrict__ reqs,
     }
 }
 
-// Per-entry reduction of P1 partials in the fixed order of the segment list
-// (ascending lane triangle), compensated in FP32.
-template <bool CPLX>
-__device__ __forceinline__ void reduce_entry_f32(const ReqDev &R, int64_t idx)
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void k_p0_f64(const ReqDev *__restrict__ reqs,
+                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks)
 {
-    const int64_t r = idx / R.ncols, c = idx - r * R.ncols;
-    const int64_t f = R.rowfix ? r : c;
-    const int64_t op = R.rowfix ? c : r;
-    const int s0 = R.seg_ptr[op], s1 = R.seg_ptr[op + 1];
-    float hr = 0.f, lr = 0.f, hi = 0.f, li = 0.f;
-    for (int s = s0; s < s1; ++s) {
-        const int pk = R.seg[s];
-        const int64_t at = (f * R.nlane + (pk >> 2)) * 3 + (pk & 3);
-        if constexpr (CPLX) {
-            const float4 v = reinterpret_cast<const float4 *>(R.part)[at];
-            two_sum_acc(hr, lr, v.x);
-            lr += v.y;
-            two_sum_acc(hi, li, v.z);
-            li += v.w;
-        } else {
-            const float2 v = reinterpret_cast<const float2 *>(R.part)[at];
-            two_sum_acc(hr, lr, v.x);
-            lr += v.y;
-        }
-    }
-    if constexpr (CPLX)
-        reinterpret_cast<float2 *>(R.out)[idx] = make_float2(hr + lr, hi + li);
+    if ((int64_t)blockIdx.x >= nblocks) return;
+    const EntryBlock B = blocks[blockIdx.x];
+    const ReqDev &R = reqs[B.req];
+    if (R.rowfix)
+        p0_body_f64<OP, Q, true>(R, B);
     else
-        reinterpret_cast<float *>(R.out)[idx] = hr + lr;
+        p0_body_f64<OP, Q, false>(R, B);
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f32(const ReqDev *__restrict__ reqs,
-                                                               const RTile *__restrict__ tiles, int64_t ntiles)
+// Stages up to kStage triangles of the fixed star, starting at star entry
+// sb, into LDS: W words of geometry per triangle (one word per thread), the
+// vertex ids and the local vertex of the star's dof.  Every thread of the
+// workgroup calls it (it synchronises).
+template <typename R_T, int W>
+__device__ __forceinline__ int stage_star(const ReqDev &R, const R_T *__restrict__ g, int stride, int sb, int s1,
+                                          R_T (*sG)[W], int4 *sV, int *sL)
 {
-    const RTile tl = tiles[blockIdx.x];
-    if ((int)threadIdx.x >= tl.count) return;
-    reduce_entry_f32<CPLX>(reqs[tl.req], tl.e0 + threadIdx.x);
-}
-
-template <bool CPLX>
-__device__ __forceinline__ void reduce_entry_f64(const ReqDev &R, int64_t idx)
-{
-    const int64_t r = idx / R.ncols, c = idx - r * R.ncols;
-    const int64_t f = R.rowfix ? r : c;
-    const int64_t op = R.rowfix ? c : r;
-    const int s0 = R.seg_ptr[op], s1 = R.seg_ptr[op + 1];
-    double ar = 0.0, ai = 0.0;
-    for (int s = s0; s < s1; ++s) {
-        const int pk = R.seg[s];
-        const int64_t at = (f * R.nlane + (pk >> 2)) * 3 + (pk & 3);
-        if constexpr (CPLX) {
-            const double2 v = reinterpret_cast<const double2 *>(R.part)[at];
-            ar += v.x;
-            ai += v.y;
-        } else {
-            ar += reinterpret_cast<const double *>(R.part)[at];
-        }
+    const int t = threadIdx.x;
+    const int ns = min(kStage, s1 - sb);
+    __syncthreads();   // the previous stage has been read
+    if (t < ns * W) {
+        const int k = t / W, w = t - k * W;
+        sG[k][w] = g[(size_t)(R.fstar[sb + k] >> 2) * stride + w];
     }
-    if constexpr (CPLX)
-        reinterpret_cast<double2 *>(R.out)[idx] = make_double2(ar, ai);
-    else
-        reinterpret_cast<double *>(R.out)[idx] = ar;
-}
-
-template <bool CPLX>
-__global__ __launch_bounds__(kReduceBlock) void k_p1_reduce_f64(const ReqDev *__restrict__ reqs,
-                                                               const RTile *__restrict__ tiles, int64_t ntiles)
-{
-    const RTile tl = tiles[blockIdx.x];
-    if ((int)threadIdx.x >= tl.count) return;
-    reduce_entry_f64<CPLX>(reqs[tl.req], tl.e0 + threadIdx.x);
-}
-
-// Fused reduction of small P1 requests: after its partials are stored, each
-// tile counts itself in with a device-scope release fence and an atomic;
-// the tile that arrives last (acquire fence) reduces every entry of the
-// request, 64 entries at a time.
-template <bool F32, bool CPLX>
-__device__ __forceinline__ void fused_reduce_tail(const ReqDev &R, int lane)
-{
-    if (!R.counter) return;
-    __threadfence();
-    int last = 0;
-    if (lane == 0) last = atomicAdd(R.counter, 1) == R.ntiles_req - 1 ? 1 : 0;
-    last = __builtin_amdgcn_readfirstlane(last);
-    if (!last) return;
-    __threadfence();
-    const int64_t n = (int64_t)R.nrows * R.ncols;
-    for (int64_t idx = lane; idx < n; idx += 64) {
-        if constexpr (F32)
-            reduce_entry_f32<CPLX>(R, idx);
-        else
-            reduce_entry_f64<CPLX>(R, idx);
+    if (t < ns) {
+        const int pk = R.fstar[sb + t];
+        sV[t] = R.vtx[pk >> 2];
+        sL[t] = pk & 3;
     }
+    __syncthreads();
+    return ns;
 }
 
-// P1: lane triangle against the fixed vertex star; writes the three
-// compensated partial sums (one per local vertex of the lane triangle).
+// P1, FP32.  Phase 1: lane triangle against the fixed vertex star; the three
+// compensated partial sums (one per local vertex of the lane triangle) go to
+// LDS.  Phase 2: thread j adds, for dof j of the chunk, the partials its
+// segment list names, in order, compensated, and stores the entry.
 template <int OP, int Q, bool ROWFIX>
-__global__ __launch_bounds__(256) void k_p1_f32(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
-                                                int64_t ntiles)
+__device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B, float (*sG)[n32<Q>()], int4 *sV,
+                                            int *sL, float4 (*sP)[3])
 {
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (t >= ntiles) return;
-    const Tile tl = tiles[t];
-    const ReqDev &R = reqs[tl.req];
-    const bool act = lane < tl.nlanes;
-    const int li = tl.lane0 + (act ? lane : 0);
-    const int tn = R.lane[li];
+    const int4 ch = R.chunk[B.chunk];   // first lane, lanes, first dof, dofs
+    const int t = threadIdx.x;
+    const bool wact = (t & ~63) < ch.y;   // wave-uniform
+    const bool act = t < ch.y;
+    const int li = ch.x + (act ? t : 0);
+    const int tn = ch.y > 0 ? R.lane[li] : 0;   // a chunk of dofs without triangles has no lanes
     const int4 vn = R.vtx[tn];
     float L[n32<Q>()];
     load32<Q>(R.g32, tn, L);
     float hr[3] = {0.f, 0.f, 0.f}, lr[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f}, lo[3] = {0.f, 0.f, 0.f};
-    const int s0 = R.fix[tl.fixed], s1 = R.fix[tl.fixed + 1];
-    for (int s = s0; s < s1; ++s) {
-        const int pk = R.fstar[s];
-        const int tf = pk >> 2, loc = pk & 3;
-        if (share_vertex(R.vtx[tf], vn)) {
-            if (act && R.near_error) atomicOr(R.status, 1);
-            continue;
-        }
-        float F[n32<Q>()];
-        load32<Q>(R.g32, tf, F);
-        float vr[3], vi[3];
-        if constexpr (ROWFIX)
-            pair_p1_testfix_f32<OP, Q>(F, loc, L, (float)R.k, R.kk, vr, vi);
-        else
-            pair_p1_trialfix_f32<OP, Q>(L, F, loc, (float)R.k, R.kk, vr, vi);
-        const float sc = F[3] * L[3] * kInv4PiF;
+    const int s0 = R.fix[B.fixed], s1 = R.fix[B.fixed + 1];
+    for (int sb = s0; sb < s1; sb += kStage) {
+        const int ns = stage_star<float, n32<Q>()>(R, R.g32, kGeo32Stride, sb, s1, sG, sV, sL);
+        if (!wact) continue;
+        for (int s = 0; s < ns; ++s) {
+            if (share_vertex(sV[s], vn)) {
+                if (act && R.near_error) *R.status = 1;
+                continue;
+            }
+            float F[n32<Q>()];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            two_sum_acc(hr[e], lr[e], sc * vr[e]);
-            if constexpr (is_cplx<OP>()) two_sum_acc(hi[e], lo[e], sc * vi[e]);
+            for (int i = 0; i < n32<Q>(); ++i) F[i] = sG[s][i];
+            const int loc = sL[s];
+            float vr[3], vi[3];
+            if constexpr (ROWFIX)
+                pair_p1_testfix_f32<OP, Q>(F, loc, L, (float)R.k, R.kk, vr, vi);
+            else
+                pair_p1_trialfix_f32<OP, Q>(L, F, loc, (float)R.k, R.kk, vr, vi);
+            const float sc = F[3] * L[3] * kInv4PiF;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                two_sum_acc(hr[e], lr[e], sc * vr[e]);
+                if constexpr (is_cplx<OP>()) two_sum_acc(hi[e], lo[e], sc * vi[e]);
+            }
         }
     }
     if (act) {
-        const int64_t base = ((int64_t)tl.fixed * R.nlane + li) * 3;
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            if constexpr (is_cplx<OP>())
-                reinterpret_cast<float4 *>(R.part)[base + e] = make_float4(hr[e], lr[e], hi[e], lo[e]);
-            else
-                reinterpret_cast<float2 *>(R.part)[base + e] = make_float2(hr[e], lr[e]);
-        }
+        for (int e = 0; e < 3; ++e) sP[t][e] = make_float4(hr[e], lr[e], hi[e], lo[e]);
     }
-    fused_reduce_tail<true, is_cplx<OP>()>(R, lane);
+    __syncthreads();
+    for (int j = t; j < ch.w; j += kBlockLanes) {
+        const int d = ch.z + j;
+        const int g0 = R.seg_ptr[d], g1 = R.seg_ptr[d + 1];
+        float ar = 0.f, br = 0.f, ai = 0.f, bi = 0.f;
+        for (int g = g0; g < g1; ++g) {
+            const int pk = R.seg[g];
+            const float4 v = sP[pk >> 2][pk & 3];
+            two_sum_acc(ar, br, v.x);
+            br += v.y;
+            if constexpr (is_cplx<OP>()) {
+                two_sum_acc(ai, bi, v.z);
+                bi += v.w;
+            }
+        }
+        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)d * R.sl;
+        if constexpr (is_cplx<OP>())
+            reinterpret_cast<float2 *>(R.out)[o] = make_float2(ar + br, ai + bi);
+        else
+            reinterpret_cast<float *>(R.out)[o] = ar + br;
+    }
 }
 
-template <int OP, int Q, bool ROWFIX>
-__global__ __launch_bounds__(256) void k_p1_f64(const ReqDev *__restrict__ reqs, const Tile *__restrict__ tiles,
-                                                int64_t ntiles)
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void k_p1_f32(const ReqDev *__restrict__ reqs,
+                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks)
 {
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (t >= ntiles) return;
-    const Tile tl = tiles[t];
-    const ReqDev &R = reqs[tl.req];
-    const bool act = lane < tl.nlanes;
-    const int li = tl.lane0 + (act ? lane : 0);
-    const int tn = R.lane[li];
+    __shared__ float sG[kStage][n32<Q>()];
+    __shared__ int4 sV[kStage];
+    __shared__ int sL[kStage];
+    __shared__ float4 sP[kBlockLanes][3];
+    if ((int64_t)blockIdx.x >= nblocks) return;
+    const EntryBlock B = blocks[blockIdx.x];
+    const ReqDev &R = reqs[B.req];
+    if (R.rowfix)
+        p1_body_f32<OP, Q, true>(R, B, sG, sV, sL, sP);
+    else
+        p1_body_f32<OP, Q, false>(R, B, sG, sV, sL, sP);
+}
+
+// P1, FP64: the same two phases with plain FP64 sums.
+template <int OP, int Q, bool ROWFIX>
+__device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B, double (*sG)[n64<Q>()], int4 *sV,
+                                            int *sL, double2 (*sP)[3])
+{
+    const int4 ch = R.chunk[B.chunk];
+    const int t = threadIdx.x;
+    const bool wact = (t & ~63) < ch.y;
+    const bool act = t < ch.y;
+    const int li = ch.x + (act ? t : 0);
+    const int tn = ch.y > 0 ? R.lane[li] : 0;
     const int4 vn = R.vtx[tn];
     double L[n64<Q>()];
     load64<Q>(R.g64, tn, L);
     double ar[3] = {0.0, 0.0, 0.0}, ai[3] = {0.0, 0.0, 0.0};
-    const int s0 = R.fix[tl.fixed], s1 = R.fix[tl.fixed + 1];
-    for (int s = s0; s < s1; ++s) {
-        const int pk = R.fstar[s];
-        const int tf = pk >> 2, loc = pk & 3;
-        if (share_vertex(R.vtx[tf], vn)) {
-            if (act && R.near_error) atomicOr(R.status, 1);
-            continue;
-        }
-        double F[n64<Q>()];
-        load64<Q>(R.g64, tf, F);
-        double vr[3], vi[3];
-        if constexpr (ROWFIX)
-            pair_p1_f64<OP, Q, true>(F, L, loc, R.k, vr, vi);
-        else
-            pair_p1_f64<OP, Q, false>(L, F, loc, R.k, vr, vi);
-        const double sc = F[3] * L[3] * kInv4Pi;
+    const int s0 = R.fix[B.fixed], s1 = R.fix[B.fixed + 1];
+    for (int sb = s0; sb < s1; sb += kStage) {
+        const int ns = stage_star<double, n64<Q>()>(R, R.g64, kGeo64Stride, sb, s1, sG, sV, sL);
+        if (!wact) continue;
+        for (int s = 0; s < ns; ++s) {
+            if (share_vertex(sV[s], vn)) {
+                if (act && R.near_error) *R.status = 1;
+                continue;
+            }
+            double F[n64<Q>()];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            ar[e] += sc * vr[e];
-            ai[e] += sc * vi[e];
+            for (int i = 0; i < n64<Q>(); ++i) F[i] = sG[s][i];
+            const int loc = sL[s];
+            double vr[3], vi[3];
+            if constexpr (ROWFIX)
+                pair_p1_f64<OP, Q, true>(F, L, loc, R.k, vr, vi);
+            else
+                pair_p1_f64<OP, Q, false>(L, F, loc, R.k, vr, vi);
+            const double sc = F[3] * L[3] * kInv4Pi;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                ar[e] += sc * vr[e];
+                ai[e] += sc * vi[e];
+            }
         }
     }
     if (act) {
-        const int64_t base = ((int64_t)tl.fixed * R.nlane + li) * 3;
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-            if constexpr (is_cplx<OP>())
-                reinterpret_cast<double2 *>(R.part)[base + e] = make_double2(ar[e], ai[e]);
-            else
-                reinterpret_cast<double *>(R.part)[base + e] = ar[e];
+        for (int e = 0; e < 3; ++e) sP[t][e] = make_double2(ar[e], ai[e]);
+    }
+    __syncthreads();
+    for (int j = t; j < ch.w; j += kBlockLanes) {
+        const int d = ch.z + j;
+        const int g0 = R.seg_ptr[d], g1 = R.seg_ptr[d + 1];
+        double xr = 0.0, xi = 0.0;
+        for (int g = g0; g < g1; ++g) {
+            const int pk = R.seg[g];
+            const double2 v = sP[pk >> 2][pk & 3];
+            xr += v.x;
+            xi += v.y;
         }
+        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)d * R.sl;
+        if constexpr (is_cplx<OP>())
+            reinterpret_cast<double2 *>(R.out)[o] = make_double2(xr, xi);
+        else
+            reinterpret_cast<double *>(R.out)[o] = xr;
     }
-    fused_reduce_tail<false, is_cplx<OP>()>(R, lane);
 }
 
-// ---------------------------------------------------------------------------
-// Tile tables.  Thread t finds its request by binary search in the group's
-// exclusive prefix of per-request tile counts and writes the tile record.
-__global__ __launch_bounds__(256) void k_build_tiles(const ReqDev *__restrict__ reqs, const int32_t *__restrict__ greq,
-                                                     const int64_t *__restrict__ gpre, int ng, int64_t ntiles,
-                                                     Tile *__restrict__ tiles)
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void k_p1_f64(const ReqDev *__restrict__ reqs,
+                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
-    int lo = 0, hi = ng;  // gpre[lo] <= t < gpre[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (gpre[mid] <= t)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const int r = greq[lo];
-    const ReqDev &R = reqs[r];
-    const int64_t u = t - gpre[lo];
-    const int ntl = (R.nlane + kTileLanes - 1) / kTileLanes;
-    const int f = (int)(u / ntl);
-    const int c = (int)(u - (int64_t)f * ntl);
-    Tile tl;
-    tl.req = r;
-    tl.fixed = f;
-    tl.lane0 = c * kTileLanes;
-    tl.nlanes = min(kTileLanes, R.nlane - c * kTileLanes);
-    tiles[t] = tl;
-}
-
-__global__ __launch_bounds__(256) void k_build_rtiles(const ReqDev *__restrict__ reqs,
-                                                      const int32_t *__restrict__ greq,
-                                                      const int64_t *__restrict__ gpre, int ng, int64_t ntiles,
-                                                      RTile *__restrict__ tiles)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntiles) return;
-    int lo = 0, hi = ng;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (gpre[mid] <= t)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const int r = greq[lo];
-    const ReqDev &R = reqs[r];
-    const int64_t u = t - gpre[lo];
-    const int64_t n = (int64_t)R.nrows * R.ncols;
-    RTile tl;
-    tl.req = r;
-    tl.e0 = u * kReduceBlock;
-    tl.count = (int32_t)min((int64_t)kReduceBlock, n - tl.e0);
-    tiles[t] = tl;
-}
-
-__global__ __launch_bounds__(256) void k_build_all(const ReqDev *__restrict__ reqs,
-                                                   const GroupDesc *__restrict__ groups, int ngroups, int64_t total)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    int glo = 0, ghi = ngroups;  // groups[glo].tile0 <= t < groups[ghi].tile0
-    while (ghi - glo > 1) {
-        const int mid = (glo + ghi) >> 1;
-        if (groups[mid].tile0 <= t)
-            glo = mid;
-        else
-            ghi = mid;
-    }
-    const GroupDesc &G = groups[glo];
-    const int64_t tt = t - G.tile0;
-    int lo = 0, hi = G.ng;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (G.gpre[mid] <= tt)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const int r = G.greq[lo];
-    const ReqDev &R = reqs[r];
-    const int64_t u = tt - G.gpre[lo];
-    if (G.kind == 0) {
-        const int ntl = (R.nlane + kTileLanes - 1) / kTileLanes;
-        const int f = (int)(u / ntl);
-        const int c = (int)(u - (int64_t)f * ntl);
-        Tile tl;
-        tl.req = r;
-        tl.fixed = f;
-        tl.lane0 = c * kTileLanes;
-        tl.nlanes = min(kTileLanes, R.nlane - c * kTileLanes);
-        reinterpret_cast<Tile *>(G.tiles)[tt] = tl;
-    } else {
-        const int64_t n = (int64_t)R.nrows * R.ncols;
-        RTile tl;
-        tl.req = r;
-        tl.e0 = u * kReduceBlock;
-        tl.count = (int32_t)min((int64_t)kReduceBlock, n - tl.e0);
-        reinterpret_cast<RTile *>(G.tiles)[tt] = tl;
-    }
+    __shared__ double sG[kStage][n64<Q>()];
+    __shared__ int4 sV[kStage];
+    __shared__ int sL[kStage];
+    __shared__ double2 sP[kBlockLanes][3];
+    if ((int64_t)blockIdx.x >= nblocks) return;
+    const EntryBlock B = blocks[blockIdx.x];
+    const ReqDev &R = reqs[B.req];
+    if (R.rowfix)
+        p1_body_f64<OP, Q, true>(R, B, sG, sV, sL, sP);
+    else
+        p1_body_f64<OP, Q, false>(R, B, sG, sV, sL, sP);
 }
 
 // ---------------------------------------------------------------------------
 // Dispatch.
-typedef void (*EntryKernel)(const ReqDev *, const Tile *, int64_t);
-
-template <int OP, int Q, bool RF>
-EntryKernel pick(int space, int prec)
-{
-    if (space == BEM_P0) return prec == BEM_FP32 ? k_p0_f32<OP, Q, RF> : k_p0_f64<OP, Q, RF>;
-    return prec == BEM_FP32 ? k_p1_f32<OP, Q, RF> : k_p1_f64<OP, Q, RF>;
-}
+typedef void (*EntryKernel)(const ReqDev *, const EntryBlock *, int64_t);
 
 template <int OP, int Q>
-EntryKernel pick_rf(int space, int prec, int rowfix)
+EntryKernel pick(int space, int prec)
 {
-    return rowfix ? pick<OP, Q, true>(space, prec) : pick<OP, Q, false>(space, prec);
+    if (space == BEM_P0) return prec == BEM_FP32 ? k_p0_f32<OP, Q> : k_p0_f64<OP, Q>;
+    return prec == BEM_FP32 ? k_p1_f32<OP, Q> : k_p1_f64<OP, Q>;
 }
 
 template <int OP>
-EntryKernel pick_q(int space, int prec, int q, int rowfix)
+EntryKernel pick_q(int space, int prec, int q)
 {
-    return q == 6 ? pick_rf<OP, 6>(space, prec, rowfix) : pick_rf<OP, 4>(space, prec, rowfix);
+    return q == 6 ? pick<OP, 6>(space, prec) : pick<OP, 4>(space, prec);
 }
 
 EntryKernel select_kernel(const Variant &v)
 {
     switch (v.op) {
-    case LSLP: return pick_q<LSLP>(v.space, v.prec, v.q, v.rowfix);
-    case LDLP: return pick_q<LDLP>(v.space, v.prec, v.q, v.rowfix);
-    case HSLP: return pick_q<HSLP>(v.space, v.prec, v.q, v.rowfix);
-    default: return pick_q<HDLP>(v.space, v.prec, v.q, v.rowfix);
+    case LSLP: return pick_q<LSLP>(v.space, v.prec, v.q);
+    case LDLP: return pick_q<LDLP>(v.space, v.prec, v.q);
+    case HSLP: return pick_q<HSLP>(v.space, v.prec, v.q);
+    default: return pick_q<HDLP>(v.space, v.prec, v.q);
     }
 }
 
 }  // namespace
 
-hipError_t launch_build_tiles(const ReqDev *reqs, const int32_t *greq, const int64_t *gpre, int ng, int64_t ntiles,
-                              Tile *tiles, hipStream_t s)
+hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock *blocks, int64_t nblocks, hipStream_t s,
+                          hipEvent_t start, hipEvent_t stop)
 {
-    if (ntiles <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((ntiles + 255) / 256);
-    hipLaunchKernelGGL(k_build_tiles, dim3(grid), dim3(256), 0, s, reqs, greq, gpre, ng, ntiles, tiles);
-    return hipGetLastError();
-}
-
-hipError_t launch_build_all(const ReqDev *reqs, const GroupDesc *groups, int ngroups, int64_t total, hipStream_t s)
-{
-    if (total <= 0 || ngroups <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((total + 255) / 256);
-    hipLaunchKernelGGL(k_build_all, dim3(grid), dim3(256), 0, s, reqs, groups, ngroups, total);
-    return hipGetLastError();
-}
-
-hipError_t launch_build_rtiles(const ReqDev *reqs, const int32_t *greq, const int64_t *gpre, int ng, int64_t ntiles,
-                               RTile *tiles, hipStream_t s)
-{
-    if (ntiles <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((ntiles + 255) / 256);
-    hipLaunchKernelGGL(k_build_rtiles, dim3(grid), dim3(256), 0, s, reqs, greq, gpre, ng, ntiles, tiles);
-    return hipGetLastError();
-}
-
-hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const Tile *tiles, int64_t ntiles, hipStream_t s)
-{
-    if (ntiles <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((ntiles + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(select_kernel(v), dim3(grid), dim3(64 * kWavesPerBlock), 0, s, reqs, tiles, ntiles);
-    return hipGetLastError();
-}
-
-hipError_t launch_p1_reduce(int prec, bool cplx, const ReqDev *reqs, const RTile *tiles, int64_t ntiles,
-                            hipStream_t s)
-{
-    if (ntiles <= 0) return hipSuccess;
-    if (prec == BEM_FP32) {
-        if (cplx)
-            hipLaunchKernelGGL(k_p1_reduce_f32<true>, dim3(ntiles), dim3(kReduceBlock), 0, s, reqs, tiles, ntiles);
-        else
-            hipLaunchKernelGGL(k_p1_reduce_f32<false>, dim3(ntiles), dim3(kReduceBlock), 0, s, reqs, tiles, ntiles);
-    } else {
-        if (cplx)
-            hipLaunchKernelGGL(k_p1_reduce_f64<true>, dim3(ntiles), dim3(kReduceBlock), 0, s, reqs, tiles, ntiles);
-        else
-            hipLaunchKernelGGL(k_p1_reduce_f64<false>, dim3(ntiles), dim3(kReduceBlock), 0, s, reqs, tiles, ntiles);
-    }
+    if (nblocks <= 0) return hipSuccess;
+    if (nblocks > INT32_MAX) return hipErrorInvalidValue;
+    const EntryKernel k = select_kernel(v);
+    if (start || stop)
+        hipExtLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kBlockLanes), 0, s, start, stop, 0, reqs, blocks,
+                              nblocks);
+    else
+        hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kBlockLanes), 0, s, reqs, blocks, nblocks);
     return hipGetLastError();
 }
 

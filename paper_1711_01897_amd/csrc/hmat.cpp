@@ -156,33 +156,42 @@ int make_resident(const bem_mesh &m, int space, const std::vector<std::pair<cons
                 if (lists[i].first) build_lane_set(m, space, lists[i].first, lists[i].second, sets[i]);
         });
     for (auto &x : th) x.join();
+    // one int32 buffer: per set, the chunk table (16-byte aligned int4
+    // records), lanes, segment pointers and segments
+    auto pad4 = [](size_t x) { return (x + 3) & ~(size_t)3; };
     size_t total = 0;
-    for (auto &ls : sets) total += ls.ints();
-    std::vector<int32_t> host(std::max<size_t>(total, 1));
+    for (auto &ls : sets) total += pad4(ls.ints());
+    std::vector<int32_t> host(std::max<size_t>(total, 4));
     out.refs.assign(n, LaneRef());
     std::vector<size_t> at(n);
     size_t pos = 0;
     for (size_t i = 0; i < n; ++i) {
         at[i] = pos;
         const LaneSet &ls = sets[i];
-        std::copy(ls.lane.begin(), ls.lane.end(), host.begin() + pos);
-        pos += ls.lane.size();
-        std::copy(ls.seg_ptr.begin(), ls.seg_ptr.end(), host.begin() + pos);
-        pos += ls.seg_ptr.size();
-        std::copy(ls.seg.begin(), ls.seg.end(), host.begin() + pos);
-        pos += ls.seg.size();
+        for (const std::vector<int32_t> *v : {&ls.chunk, &ls.lane, &ls.seg_ptr, &ls.seg}) {
+            std::copy(v->begin(), v->end(), host.begin() + pos);
+            pos += v->size();
+        }
+        pos = pad4(pos);
     }
     BEM_HIP_TRY(hipMalloc(&out.dev, sizeof(int32_t) * host.size()));
     BEM_HIP_TRY(hipMemcpy(out.dev, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice));
     for (size_t i = 0; i < n; ++i) {
         const LaneSet &ls = sets[i];
         LaneRef &r = out.refs[i];
+        const int32_t *base = out.dev + at[i];
         r.ndof = ls.ndof;
         r.nlane = (int64_t)ls.lane.size();
         r.nseg = (int64_t)ls.seg.size();
-        r.lane = out.dev + at[i];
-        r.seg_ptr = ls.seg_ptr.empty() ? nullptr : out.dev + at[i] + ls.lane.size();
-        r.seg = ls.seg.empty() ? nullptr : out.dev + at[i] + ls.lane.size() + ls.seg_ptr.size();
+        r.nchunk = ls.nchunk();
+        r.ndistinct = ls.ndistinct;
+        r.chunk = ls.chunk.empty() ? nullptr : reinterpret_cast<const int4 *>(base);
+        base += ls.chunk.size();
+        r.lane = ls.lane.empty() ? nullptr : base;
+        base += ls.lane.size();
+        r.seg_ptr = ls.seg_ptr.empty() ? nullptr : base;
+        base += ls.seg_ptr.size();
+        r.seg = ls.seg.empty() ? nullptr : base;
     }
     return BEM_OK;
 }

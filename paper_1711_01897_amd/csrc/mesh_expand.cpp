@@ -2,16 +2,17 @@
 //
 // A request A[rows, cols] becomes work for the entry kernels:
 //  * P0 (dof = triangle): entry (i, j) is the single triangle pair (T_i, T_j).
-//    The longer of the two index lists runs across the lanes of a tile, the
-//    other one is the tile's fixed side.
+//    The longer of the two index lists runs across the lanes of a workgroup
+//    (in chunks of 256), the other one is the workgroup's fixed side.
 //  * P1 (dof = vertex, hat functions, Section 2): entry (I, J) sums over the
 //    triangles m around I and n around J.  With the column side on the lanes,
-//    the lane list is the set of distinct triangles around the requested
-//    columns (ascending), every lane triangle serving each of its requested
-//    vertices; the fixed side of a tile is the star of one row vertex.  A
-//    segment list maps every requested column to its (lane triangle, local
-//    vertex) partial sums in ascending triangle order, which fixes the order
-//    of the final per-entry sum.
+//    the requested columns are cut into runs whose stars together hold at
+//    most 256 triangles; each run's triangles form one chunk of lanes, every
+//    lane triangle serving each of its requested vertices in the run, and the
+//    fixed side of a workgroup is the star of one row vertex.  A segment list
+//    maps every requested column to its (lane triangle, local vertex) partial
+//    sums in ascending triangle order, which fixes the order of the final
+//    per-entry sum.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -41,15 +42,6 @@ double now_seconds()
     return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
 }
 
-int64_t fuse_reduce_max_entries()
-{
-    static const int64_t v = [] {
-        const char *e = std::getenv("BEM_FUSE_REDUCE_MAX");
-        return e ? std::max<int64_t>(0, std::atoll(e)) : (int64_t)0;
-    }();
-    return v;
-}
-
 bool is_complex_op(int op) { return op == BEM_HELMHOLTZ_SLP || op == BEM_HELMHOLTZ_DLP; }
 
 size_t out_elem_bytes(int op, int prec)
@@ -72,6 +64,10 @@ struct StarScratch {
             slot_of.assign(nt, -1);
             gen = 0;
         }
+        next_gen();
+    }
+    void next_gen()
+    {
         if (++gen == 0) {
             std::fill(stamp.begin(), stamp.end(), 0);
             gen = 1;
@@ -105,21 +101,9 @@ void finalize_sizes(Request &r)
     const bem_mesh &m = *r.mesh;
     const int64_t q2 = (int64_t)m.q * m.q;
     r.elem_bytes = out_elem_bytes(r.op, r.prec);
-    if (r.space == BEM_P0) {
-        r.part_elem_bytes = 0;
-        r.part_bytes = 0;
-        r.evals = r.nfix * r.nlane * q2;
-        r.nrtiles = 0;
-    } else {
-        // (hi, lo) float pair or one double per real component
-        r.part_elem_bytes = is_complex_op(r.op) ? 16 : 8;
-        r.part_bytes = align16((size_t)r.nfix * r.nlane * 3 * r.part_elem_bytes);
-        r.evals = (int64_t)r.fstar.size() * r.nlane * q2;
-        r.nrtiles = (r.entries() + kReduceBlock - 1) / kReduceBlock;
-    }
-    r.ntiles = r.nfix * ((r.nlane + kTileLanes - 1) / kTileLanes);
-    r.fuse_reduce = r.space == BEM_P1 && r.ntiles > 0 && r.entries() <= fuse_reduce_max_entries();
-    if (r.fuse_reduce) r.nrtiles = 0;
+    const int64_t fixed_tris = r.space == BEM_P0 ? r.nfix : (int64_t)r.fstar.size();
+    r.evals = fixed_tris * r.ndistinct * q2;
+    r.nblocks = r.nfix * r.nchunk;
     const size_t own = r.ext ? 0 : r.own.ints();
     r.in_bytes = align16(4 * (r.fix.size() + r.fstar.size() + own));
     r.out_bytes = align16((size_t)r.entries() * r.elem_bytes);
@@ -132,36 +116,58 @@ void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n
 {
     ls.ndof = n;
     ls.lane.clear();
+    ls.chunk.clear();
     ls.seg_ptr.clear();
     ls.seg.clear();
     if (space == BEM_P0) {
         ls.lane.assign(dofs, dofs + n);
+        ls.ndistinct = n;
+        for (int64_t c0 = 0; c0 < n; c0 += kBlockLanes) {
+            const int32_t len = (int32_t)std::min<int64_t>(kBlockLanes, n - c0);
+            ls.chunk.insert(ls.chunk.end(), {(int32_t)c0, len, (int32_t)c0, len});
+        }
         return;
     }
+    // P1: walk the dofs in order; a dof joins the open chunk while the
+    // union of the chunk's stars stays within kBlockLanes triangles
     StarScratch &sc = g_scratch;
     sc.prepare(m.nt);
+    ls.seg_ptr.resize(n + 1);
+    ls.seg_ptr[0] = 0;
+    int32_t lane0 = 0, count = 0;
+    int64_t dof0 = 0;
+    auto close = [&](int64_t end) {
+        ls.chunk.insert(ls.chunk.end(), {lane0, count, (int32_t)dof0, (int32_t)(end - dof0)});
+        lane0 += count;
+        count = 0;
+        dof0 = end;
+        sc.next_gen();
+    };
     for (int64_t c = 0; c < n; ++c) {
         const int32_t v = dofs[c];
+        int32_t fresh = 0;
+        for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) fresh += sc.stamp[m.star[s] >> 2] != sc.gen;
+        if (count + fresh > kBlockLanes && c > dof0) close(c);
         for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) {
             const int32_t t = m.star[s] >> 2;
             if (sc.stamp[t] != sc.gen) {
                 sc.stamp[t] = sc.gen;
+                sc.slot_of[t] = count++;
                 ls.lane.push_back(t);
             }
-        }
-    }
-    std::sort(ls.lane.begin(), ls.lane.end());
-    for (size_t i = 0; i < ls.lane.size(); ++i) sc.slot_of[ls.lane[i]] = (int32_t)i;
-    ls.seg_ptr.resize(n + 1);
-    ls.seg_ptr[0] = 0;
-    for (int64_t c = 0; c < n; ++c) {
-        const int32_t v = dofs[c];
-        for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) {
-            const int32_t pk = m.star[s];
-            ls.seg.push_back((sc.slot_of[pk >> 2] << 2) | (pk & 3));
+            ls.seg.push_back((sc.slot_of[t] << 2) | (m.star[s] & 3));
         }
         ls.seg_ptr[c + 1] = (int32_t)ls.seg.size();
     }
+    if (n > dof0) close(n);
+    // distinct triangles over all chunks
+    ls.ndistinct = 0;
+    for (int32_t t : ls.lane)
+        if (sc.stamp[t] != sc.gen) {
+            sc.stamp[t] = sc.gen;
+            ++ls.ndistinct;
+        }
+    sc.next_gen();
 }
 
 int expand_request(Request &r)
@@ -190,6 +196,8 @@ int expand_request(Request &r)
     expand_fixed(m, r.space, fix_dofs.data(), (int64_t)fix_dofs.size(), r);
     build_lane_set(m, r.space, lane_dofs.data(), (int64_t)lane_dofs.size(), r.own);
     r.nlane = (int64_t)r.own.lane.size();
+    r.nchunk = r.own.nchunk();
+    r.ndistinct = r.own.ndistinct;
     finalize_sizes(r);
     return BEM_OK;
 }
@@ -199,10 +207,13 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
     r.ext = ext;
     r.rowfix = rowfix;
     r.own.lane.clear();
+    r.own.chunk.clear();
     r.own.seg_ptr.clear();
     r.own.seg.clear();
     expand_fixed(*r.mesh, r.space, &dof, 1, r);
     r.nlane = ext->nlane;
+    r.nchunk = ext->nchunk;
+    r.ndistinct = ext->ndistinct;
     if (rowfix) {
         r.nrows = 1;
         r.ncols = ext->ndof;
@@ -215,10 +226,8 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
 
 size_t request_bytes(const Request &r)
 {
-    // descriptor, group-table entries (request id + prefix, main and reduce), inputs, status, outputs,
-    // partials, tiles
-    return sizeof(ReqDev) + 2 * (4 + 8) + r.in_bytes + 8 + r.out_bytes + r.part_bytes +
-           (size_t)r.ntiles * sizeof(Tile) + (size_t)r.nrtiles * sizeof(RTile) + 64;
+    // descriptor, inputs, status, outputs, block table
+    return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * sizeof(EntryBlock) + 64;
 }
 
 size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d)
@@ -237,17 +246,20 @@ size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t 
     d.g32 = m.d_g32;
     d.g64 = m.d_g64;
     d.vtx = m.d_vtx;
-    d.fix = put(r.fix);
-    d.fstar = put(r.fstar);
+    // the chunk table (int4 records) goes first: the section starts 16-byte aligned
     if (r.ext) {
+        d.chunk = r.ext->chunk;
         d.lane = r.ext->lane;
         d.seg_ptr = r.ext->seg_ptr;
         d.seg = r.ext->seg;
     } else {
+        d.chunk = reinterpret_cast<const int4 *>(put(r.own.chunk));
         d.lane = put(r.own.lane);
         d.seg_ptr = put(r.own.seg_ptr);
         d.seg = put(r.own.seg);
     }
+    d.fix = put(r.fix);
+    d.fstar = put(r.fstar);
     if (r.rowfix) {
         d.sf = r.ncols;
         d.sl = 1;
@@ -266,15 +278,19 @@ size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t 
     return r.in_bytes;
 }
 
-void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_part, size_t off_status,
-                       ReqDev &d)
+void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_status, ReqDev &d)
 {
+    (void)r;
     d.out = dev_base + off_out;
-    d.part = r.part_bytes ? dev_base + off_part : nullptr;
     d.status = reinterpret_cast<int32_t *>(dev_base + off_status);
-    d.counter = r.fuse_reduce ? reinterpret_cast<int32_t *>(dev_base + off_status) + 1 : nullptr;
-    d.ntiles_req = (int32_t)r.ntiles;
-    d.pad0 = 0;
+}
+
+int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
+{
+    int64_t n = 0;
+    for (int32_t f = 0; f < (int32_t)r.nfix; ++f)
+        for (int32_t c = 0; c < (int32_t)r.nchunk; ++c) out[n++] = EntryBlock{ri, f, c, 0};
+    return n;
 }
 
 }  // namespace bem
@@ -315,6 +331,10 @@ int mesh_create_impl(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
             for (int k = 0; k < 3; ++k) m->star[fill[tri[3 * t + k]]++] = (int32_t)((t << 2) | k);
     }
     for (int64_t v = 0; v < nv; ++v) m->max_star = std::max<int>(m->max_star, (int)(m->star_ptr[v + 1] - m->star_ptr[v]));
+    if (m->max_star > kBlockLanes) {
+        delete m;
+        return fail(BEM_E_ARG, "a vertex belongs to more than 256 triangles");
+    }
     double sj = 0.0, se = 0.0;
     for (int64_t t = 0; t < nt; ++t) {
         const double *a = &xyz[3 * tri[3 * t]], *b = &xyz[3 * tri[3 * t + 1]], *c = &xyz[3 * tri[3 * t + 2]];

@@ -6,20 +6,21 @@
 //
 //  * admission: a request is taken into the next batch when a batch slot is
 //    free and the slot's share of the device arena still has room for the
-//    request's inputs, outputs, partial sums and tile tables (admission by
+//    request's inputs, outputs, partial sums and block tables (admission by
 //    memory);
 //  * fusion: all admitted requests of one kernel variant run in one launch,
-//    one wavefront per tile, whatever request the tile belongs to; the tile
-//    tables are built on the device from per-request tile counts;
-//  * overlap: several slots rotate, each with its own stream, so the
-//    dispatcher stages and enqueues the next batches while earlier ones run
-//    or are being consumed, and consecutive batches overlap on the device;
+//    one 256-lane workgroup per (request, fixed item, lane chunk), whatever
+//    request the workgroup belongs to and whichever side is fixed; the block
+//    tables are written on the host while the batch is staged;
+//  * overlap: several slots rotate, each with its own stream; dispatcher
+//    threads stage and enqueue the next batches while earlier ones run or are
+//    being consumed, so consecutive batches overlap on the device and
 //    requests that arrive meanwhile wait only for the next free slot;
-//  * completion: a second thread waits for each batch's event, checks the
-//    near-field flags, copies results to the callers' buffers (or lends the
-//    caller a pointer into the pinned staging until it releases it), wakes
-//    the waiters and records submit-to-completion latency.
-// Each request's result is computed by the same tiles with the same
+//  * completion: completion threads wait for each batch's event, check the
+//    near-field flags, copy results to the callers' buffers (or lend the
+//    caller a pointer into the pinned staging until it releases it), wake
+//    the waiters and record submit-to-completion latency.
+// Each request's result is computed by the same workgroups with the same
 // summation order whichever batch it lands in.
 #include <algorithm>
 #include <cmath>
@@ -35,7 +36,9 @@ namespace bem {
 namespace {
 
 constexpr int kMaxSlots = 16;
+constexpr int kMaxThreads = 4;
 constexpr int kTimedEvery = 4;
+constexpr int kKeys = 32;   // launch groups: (op, space, prec, rule)
 
 int env_int(const char *name, int dflt, int lo, int hi)
 {
@@ -46,17 +49,18 @@ int env_int(const char *name, int dflt, int lo, int hi)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int entry_key(const Request &r) { return ((r.op * 2 + r.space) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0); }
+
 struct Launch {
     Variant v{};
-    bool reduce = false;
-    int ng = 0;                  // requests in the group
-    size_t off_greq = 0, off_gpre = 0, off_tiles = 0;
-    int64_t ntiles = 0;
+    int key = 0;                 // member list of the group
+    size_t off_tab = 0;          // EntryBlock table
+    int64_t count = 0;           // workgroups
     int64_t entries = 0, evals = 0, loads = 0;
 };
 
 struct KStat {
-    int64_t launches = 0, entries = 0, evals = 0, loads = 0;
+    int64_t launches = 0, workgroups = 0, entries = 0, evals = 0, loads = 0;
     double seconds = 0.0;
 };
 
@@ -64,12 +68,20 @@ struct Batch {
     int slot = 0;
     std::vector<Request *> reqs;
     std::vector<Launch> launches;
-    std::vector<hipEvent_t> ev;   // start/stop per entry or reduction launch
+    std::vector<hipEvent_t> ev;   // start/stop per launch (timed batches)
     hipEvent_t ev_done = nullptr;
+    hipError_t enqueue_error = hipSuccess;
     double t_launch = 0.0;
+    double t_hip = 0.0;           // host seconds inside the enqueue calls
+    double t_take = 0.0, t_enq = 0.0, q_sum = 0.0;   // latency legs (q_sum: summed queue waits)
     int64_t entries = 0, evals = 0;
     std::atomic<int> refs{1};     // completion thread + borrowed results
     bool timed = false;           // per-launch events recorded
+};
+
+// Per dispatcher thread: group member lists, reused across batches.
+struct Scratch {
+    std::vector<int> members[kKeys];
 };
 
 class Server {
@@ -78,10 +90,14 @@ public:
     int max_batch = 16384;
     int nslots = 8;     // BEM_SERVER_SLOTS
     int nstreams = 8;   // BEM_SERVER_STREAMS (slot s uses stream s % nstreams), default one per slot
+    int ndisp = 1;      // BEM_SERVER_DISPATCHERS
+    int ncomp = 1;      // BEM_SERVER_COMPLETERS
+    bool host_out = true;    // BEM_SERVER_HOST_OUT: kernels store results and flags straight into pinned staging
+    bool spin = false;       // BEM_SERVER_SPIN: completion threads poll batch events instead of blocking
 
     std::mutex mu;
-    std::condition_variable cv;    // dispatcher: pending requests, free slots
-    std::condition_variable cvc;   // completer: batches in flight
+    std::condition_variable cv;    // dispatchers: pending requests, free slots
+    std::condition_variable cvc;   // completers: batches in flight
     std::deque<Request *> pending;
     std::deque<Batch *> inflight;
     bool slot_busy[kMaxSlots] = {};
@@ -89,30 +105,40 @@ public:
     int device = 0;
     hipStream_t streams[kMaxSlots] = {};
     char *d_arena = nullptr, *h_stage = nullptr;
+    char *h_stage_dev = nullptr;   // device address of h_stage
     size_t slot_bytes = 0;
-    std::thread dispatcher, completer;
+    std::vector<std::thread> threads;
     std::mutex ev_mu;
     std::vector<hipEvent_t> event_pool;
+    std::atomic<int64_t> batch_counter{0};
 
     // statistics
     std::mutex stat_mu;
     int64_t n_requests = 0, n_entries = 0, n_batches = 0, n_evals = 0, n_launches = 0, n_timed = 0;
-    double busy = 0.0, last_done = 0.0, kernel_s = 0.0, reduce_s = 0.0;
-    double dispatch_s = 0.0, complete_s = 0.0, wait_s = 0.0;
+    double busy = 0.0, last_done = 0.0, kernel_s = 0.0;
+    double dispatch_s = 0.0, complete_s = 0.0, wait_s = 0.0, dispatch_hip_s = 0.0;
+    double leg_queue = 0.0, leg_stage = 0.0, leg_device = 0.0, leg_complete = 0.0;   // request-weighted sums
     std::vector<float> latencies;
-    std::map<std::pair<Variant, int>, KStat> kstats;
-    std::vector<int> group_members[64], rgroup_members[4];   // dispatcher scratch
-    int64_t batch_counter = 0;
+    std::map<Variant, KStat> kstats;
 
     int start()
     {
         if (started) return BEM_OK;
         nslots = env_int("BEM_SERVER_SLOTS", nslots, 2, kMaxSlots);
         nstreams = env_int("BEM_SERVER_STREAMS", nslots, 1, nslots);
+        ndisp = env_int("BEM_SERVER_DISPATCHERS", ndisp, 1, kMaxThreads);
+        ncomp = env_int("BEM_SERVER_COMPLETERS", ncomp, 1, kMaxThreads);
+        host_out = env_int("BEM_SERVER_HOST_OUT", host_out ? 1 : 0, 0, 1) != 0;
+        spin = env_int("BEM_SERVER_SPIN", spin ? 1 : 0, 0, 1) != 0;
         hipError_t e = hipGetDevice(&device);
         for (int i = 0; i < nstreams && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipMalloc(&d_arena, arena_bytes);
-        if (e == hipSuccess) e = hipHostMalloc(&h_stage, arena_bytes, hipHostMallocDefault);
+        // with host_out the kernels write into the staging: coherent (uncached
+        // on the device) so results are in host memory once the batch event
+        // completes
+        if (e == hipSuccess)
+            e = hipHostMalloc(&h_stage, arena_bytes, host_out ? hipHostMallocCoherent : hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&h_stage_dev, h_stage, 0);
         if (e != hipSuccess) {
             if (d_arena) (void)hipFree(d_arena);
             d_arena = nullptr;
@@ -121,8 +147,8 @@ public:
         }
         slot_bytes = (arena_bytes / nslots) & ~(size_t)255;
         started = true;
-        dispatcher = std::thread([this] { dispatch_loop(); });
-        completer = std::thread([this] { complete_loop(); });
+        for (int i = 0; i < ndisp; ++i) threads.emplace_back([this] { dispatch_loop(); });
+        for (int i = 0; i < ncomp; ++i) threads.emplace_back([this] { complete_loop(); });
         return BEM_OK;
     }
 
@@ -179,7 +205,7 @@ public:
         }
     }
 
-    // batch-level slack: alignment of sections and group tables
+    // batch-level slack: alignment of sections and tables
     static constexpr size_t kSlack = size_t(1) << 17;
     bool fits(const Request *r) const { return r->batch_bytes + kSlack <= slot_bytes; }
 
@@ -218,9 +244,11 @@ public:
     void dispatch_loop()
     {
         (void)hipSetDevice(device);
+        Scratch sc;
         for (;;) {
             std::vector<Request *> take;
             int slot = -1;
+            bool more = false;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv.wait(lk, [&] { return stop || (!pending.empty() && free_slot() >= 0); });
@@ -242,13 +270,21 @@ public:
                     pending.pop_front();
                 }
                 slot_busy[slot] = true;
+                more = !pending.empty() && free_slot() >= 0;
             }
+            if (more) cv.notify_one();   // another dispatcher can take the rest meanwhile
             const double t0 = now_seconds();
-            Batch *b = build_and_launch(slot, take);
+            double qs = 0.0;
+            for (Request *r : take) qs += t0 - r->t_submit;
+            Batch *b = build_and_launch(slot, take, sc);
             const double t1 = now_seconds();
+            b->t_take = t0;
+            b->t_enq = t1;
+            b->q_sum = qs;
             {
                 std::lock_guard<std::mutex> g(stat_mu);
                 dispatch_s += t1 - t0;
+                dispatch_hip_s += b->t_hip;
             }
             {
                 std::lock_guard<std::mutex> g(mu);
@@ -258,7 +294,7 @@ public:
         }
     }
 
-    Batch *build_and_launch(int slot, std::vector<Request *> &take)
+    Batch *build_and_launch(int slot, std::vector<Request *> &take, Scratch &sc)
     {
         Batch *b = new Batch();
         b->slot = slot;
@@ -268,95 +304,50 @@ public:
         hipStream_t stream = streams[slot % nstreams];
         const int n = (int)take.size();
 
-        // kernel variant groups (entry launches) and reduction groups, indexed
-        // by (op, space, prec, rule, fixed side) and (prec, complex)
-        for (auto &g : group_members) g.clear();
-        for (auto &g : rgroup_members) g.clear();
+        // launch groups by (op, space, prec, rule)
+        for (auto &g : sc.members) g.clear();
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
-            if (r.ntiles > 0)
-                group_members[(((r.op * 2 + r.space) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0)) * 2 + r.rowfix]
-                    .push_back(i);
-            if (r.nrtiles > 0) rgroup_members[r.prec * 2 + (is_complex_op(r.op) ? 1 : 0)].push_back(i);
+            if (r.nblocks > 0) sc.members[entry_key(r)].push_back(i);
             b->entries += r.entries();
             b->evals += r.evals;
         }
-        std::vector<std::pair<Variant, const std::vector<int> *>> groups;
-        for (int key = 0; key < 64; ++key) {
-            if (group_members[key].empty()) continue;
-            const int rowfix = key & 1, q = (key >> 1) & 1 ? 6 : 4, prec = (key >> 2) & 1, space = (key >> 3) & 1,
-                      op = key >> 4;
-            groups.push_back({Variant{op, space, prec, q, rowfix}, &group_members[key]});
-        }
-        std::vector<std::pair<std::pair<int, int>, const std::vector<int> *>> rgroups;
-        for (int key = 0; key < 4; ++key)
-            if (!rgroup_members[key].empty()) rgroups.push_back({{key >> 1, key & 1}, &rgroup_members[key]});
-
-        // layout: descriptors | group tables | inputs | status | outputs || partials | tiles
-        // (offsets first, checked against the slot, then the staging writes)
         std::vector<Launch> launches;
-        for (auto &g : groups) {
+        for (int key = 0; key < kKeys; ++key) {
+            if (sc.members[key].empty()) continue;
             Launch L;
-            L.v = g.first;
-            L.reduce = false;
-            L.ng = (int)g.second->size();
-            launches.push_back(L);
-        }
-        for (auto &g : rgroups) {
-            Launch L;
-            L.v = Variant{g.first.second ? BEM_HELMHOLTZ_SLP : BEM_LAPLACE_SLP, BEM_P1, g.first.first, 0, 0};
-            L.reduce = true;
-            L.ng = (int)g.second->size();
-            launches.push_back(L);
-        }
-        std::vector<const std::vector<int> *> members;
-        for (auto &g : groups) members.push_back(g.second);
-        for (auto &g : rgroups) members.push_back(g.second);
-        size_t off = 0;
-        const size_t off_reqs = off;
-        off = align256(off + sizeof(ReqDev) * n);
-        for (size_t gi = 0; gi < launches.size(); ++gi) {
-            Launch &L = launches[gi];
-            L.off_greq = off;
-            off = align256(off + 4 * (size_t)L.ng);
-            L.off_gpre = off;
-            off = align256(off + 8 * ((size_t)L.ng + 1));
-            for (int i : *members[gi]) {
+            L.key = key;
+            L.v = Variant{key >> 3, (key >> 2) & 1, (key >> 1) & 1, (key & 1) ? 6 : 4};
+            for (int i : sc.members[key]) {
                 const Request &r = *take[i];
-                L.ntiles += L.reduce ? r.nrtiles : r.ntiles;
                 L.entries += r.entries();
-                if (!L.reduce) {
-                    L.evals += r.evals;
-                    L.loads += r.nfix * r.nlane;
-                }
+                L.count += r.nblocks;
+                L.evals += r.evals;
+                L.loads += r.nfix * r.nlane;
             }
+            launches.push_back(L);
         }
-        const size_t off_groups = off;
-        off = align256(off + sizeof(GroupDesc) * launches.size());
+
+        // layout: descriptors | block tables | inputs | status || outputs
+        // (offsets first, checked against the slot, then the staging writes)
+        size_t off = align256(sizeof(ReqDev) * n);
+        for (Launch &L : launches) {
+            L.off_tab = off;
+            off = align256(off + 16 * (size_t)L.count);
+        }
         const size_t off_in = off;
         for (int i = 0; i < n; ++i) off += take[i]->in_bytes;
         const size_t off_status = align256(off);
-        off = align256(off_status + 2 * sizeof(int32_t) * n);
+        off = align256(off_status + sizeof(int32_t) * n);
         const size_t h2d_end = off;
-        std::vector<size_t> out_off(n), part_off(n);
+        std::vector<size_t> out_off(n);
         for (int i = 0; i < n; ++i) {
             out_off[i] = off;
             off += take[i]->out_bytes;
         }
         const size_t d2h_end = off;
-        off = align256(off);
-        for (int i = 0; i < n; ++i) {
-            part_off[i] = off;
-            off += take[i]->part_bytes;
-        }
-        off = align256(off);
-        for (Launch &L : launches) {
-            L.off_tiles = off;
-            off = align256(off + (L.reduce ? sizeof(RTile) : sizeof(Tile)) * (size_t)L.ntiles);
-        }
         if (off > slot_bytes) {
             // admission keeps this from happening; fail the batch rather than overrun the slot
-            b->launches.clear();
             b->t_launch = now_seconds();
             b->ev_done = get_event();
             (void)hipEventRecord(b->ev_done, stream);
@@ -365,73 +356,52 @@ public:
         }
 
         // staging writes
-        ReqDev *hreq = reinterpret_cast<ReqDev *>(hb + off_reqs);
-        for (size_t gi = 0; gi < launches.size(); ++gi) {
-            const Launch &L = launches[gi];
-            int32_t *greq = reinterpret_cast<int32_t *>(hb + L.off_greq);
-            int64_t *gpre = reinterpret_cast<int64_t *>(hb + L.off_gpre);
-            int64_t acc = 0;
-            size_t k = 0;
-            for (int i : *members[gi]) {
-                greq[k] = i;
-                gpre[k] = acc;
-                acc += L.reduce ? take[i]->nrtiles : take[i]->ntiles;
-                ++k;
-            }
-            gpre[k] = acc;
+        static_assert(sizeof(EntryBlock) == 16, "block records are 16 bytes");
+        for (const Launch &L : launches) {
+            EntryBlock *p = reinterpret_cast<EntryBlock *>(hb + L.off_tab);
+            int64_t k = 0;
+            for (int i : sc.members[L.key]) k += write_blocks(*take[i], i, p + k);
         }
+        ReqDev *hreq = reinterpret_cast<ReqDev *>(hb);
         size_t in = off_in;
         for (int i = 0; i < n; ++i) in += stage_request_inputs(*take[i], hb, db, in, hreq[i]);
-        std::memset(hb + off_status, 0, 2 * sizeof(int32_t) * n);
+        std::memset(hb + off_status, 0, sizeof(int32_t) * n);
+        char *ob = host_out ? h_stage_dev + (size_t)slot * slot_bytes : db;   // where results are stored
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
-            finish_descriptor(r, db, out_off[i], part_off[i], off_status + 8 * i, hreq[i]);
+            finish_descriptor(r, ob, out_off[i], off_status + sizeof(int32_t) * i, hreq[i]);
             r.off_out = out_off[i];
-            r.off_status = off_status + 8 * i;
+            r.off_status = off_status + sizeof(int32_t) * i;
         }
-        b->launches = launches;
-        GroupDesc *gd = reinterpret_cast<GroupDesc *>(hb + off_groups);
-        int64_t tile_total = 0;
-        for (size_t gi = 0; gi < launches.size(); ++gi) {
-            const Launch &L = launches[gi];
-            gd[gi].tile0 = tile_total;
-            gd[gi].ntiles = L.ntiles;
-            gd[gi].greq = reinterpret_cast<const int32_t *>(db + L.off_greq);
-            gd[gi].gpre = reinterpret_cast<const int64_t *>(db + L.off_gpre);
-            gd[gi].tiles = db + L.off_tiles;
-            gd[gi].ng = L.ng;
-            gd[gi].kind = L.reduce ? 1 : 0;
-            tile_total += L.ntiles;
-        }
+        b->launches = std::move(launches);
 
+        // enqueue: inputs, launches (every kTimedEvery-th batch with a
+        // start/stop event pair bound to each launch; the batch event is
+        // always kept), statuses and outputs back
         b->t_launch = now_seconds();
-        (void)hipMemcpyAsync(db, hb, h2d_end, hipMemcpyHostToDevice, stream);
-        const ReqDev *dreq = reinterpret_cast<const ReqDev *>(db + off_reqs);
-        (void)launch_build_all(dreq, reinterpret_cast<const GroupDesc *>(db + off_groups), (int)b->launches.size(),
-                               tile_total, stream);
-        // n + 1 events bracket n consecutive launches, on every kTimedEvery-th
-        // batch (launch durations are sampled; the batch event is always kept)
-        b->timed = (batch_counter++ % kTimedEvery) == 0;
-        if (b->timed && !b->launches.empty()) {
-            hipEvent_t e = get_event();
-            (void)hipEventRecord(e, stream);
-            b->ev.push_back(e);
-        }
+        b->t_hip = b->t_launch;
+        auto note = [&](hipError_t e) {
+            if (e != hipSuccess && b->enqueue_error == hipSuccess) b->enqueue_error = e;
+        };
+        note(hipMemcpyAsync(db, hb, h2d_end, hipMemcpyHostToDevice, stream));
+        const ReqDev *dreq = reinterpret_cast<const ReqDev *>(db);
+        b->timed = (batch_counter.fetch_add(1) % kTimedEvery) == 0;
         for (const Launch &L : b->launches) {
-            if (L.reduce)
-                (void)launch_p1_reduce(L.v.prec, is_complex_op(L.v.op), dreq,
-                                       reinterpret_cast<const RTile *>(db + L.off_tiles), L.ntiles, stream);
-            else
-                (void)launch_entries(L.v, dreq, reinterpret_cast<const Tile *>(db + L.off_tiles), L.ntiles, stream);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
             if (b->timed) {
-                hipEvent_t e = get_event();
-                (void)hipEventRecord(e, stream);
-                b->ev.push_back(e);
+                e0 = get_event();
+                e1 = get_event();
+                b->ev.push_back(e0);
+                b->ev.push_back(e1);
             }
+            note(launch_entries(L.v, dreq, reinterpret_cast<const EntryBlock *>(db + L.off_tab), L.count, stream, e0,
+                                e1));
         }
-        (void)hipMemcpyAsync(hb + off_status, db + off_status, d2h_end - off_status, hipMemcpyDeviceToHost, stream);
+        if (!host_out)
+            note(hipMemcpyAsync(hb + off_status, db + off_status, d2h_end - off_status, hipMemcpyDeviceToHost, stream));
         b->ev_done = get_event();
-        (void)hipEventRecord(b->ev_done, stream);
+        note(hipEventRecord(b->ev_done, stream));
+        b->t_hip = now_seconds() - b->t_hip;
         return b;
     }
 
@@ -464,16 +434,22 @@ public:
                 inflight.pop_front();
             }
             const double tw0 = now_seconds();
-            hipError_t e = hipEventSynchronize(b->ev_done);
+            hipError_t e = hipSuccess;
+            if (spin) {
+                while ((e = hipEventQuery(b->ev_done)) == hipErrorNotReady) __builtin_ia32_pause();
+            } else {
+                e = hipEventSynchronize(b->ev_done);
+            }
+            if (e == hipSuccess) e = b->enqueue_error;
             const double t_done = now_seconds();
-            double ks = 0.0, rs = 0.0;
+            double ks = 0.0;
             std::vector<double> dur(b->launches.size(), 0.0);
-            if (b->timed)
+            if (b->timed && e == hipSuccess)
                 for (size_t i = 0; i < b->launches.size(); ++i) {
                     float ms = 0.f;
-                    if (hipEventElapsedTime(&ms, b->ev[i], b->ev[i + 1]) == hipSuccess) {
+                    if (hipEventElapsedTime(&ms, b->ev[2 * i], b->ev[2 * i + 1]) == hipSuccess) {
                         dur[i] = ms * 1e-3;
-                        (b->launches[i].reduce ? rs : ks) += ms * 1e-3;
+                        ks += ms * 1e-3;
                     }
                 }
             {
@@ -486,16 +462,16 @@ public:
                     n_timed += 1;
                     n_launches += (int64_t)b->launches.size();
                     kernel_s += ks;
-                    reduce_s += rs;
                 }
-                busy += t_done - std::max(b->t_launch, last_done);
-                last_done = t_done;
+                busy += std::max(0.0, t_done - std::max(b->t_launch, last_done));
+                last_done = std::max(last_done, t_done);
                 for (Request *r : b->reqs)
                     if (latencies.size() < (size_t(1) << 24)) latencies.push_back((float)(t_done - r->t_submit));
                 for (size_t i = 0; b->timed && i < b->launches.size(); ++i) {
                     const Launch &L = b->launches[i];
-                    KStat &k = kstats[{L.v, L.reduce ? 1 : 0}];
+                    KStat &k = kstats[L.v];
                     k.launches += 1;
+                    k.workgroups += L.count;
                     k.entries += L.entries;
                     k.evals += L.evals;
                     k.loads += L.loads;
@@ -526,12 +502,19 @@ public:
                 sts[i] = st;
             }
             b->refs.fetch_add(lent);  // before any borrower can release
+            const double nreq = (double)reqs.size();
+            const double leg_q = b->q_sum, leg_s = nreq * (b->t_enq - b->t_take), leg_d = nreq * (t_done - b->t_enq);
             finish_all(reqs, sts);
-            release_batch(b);
+            release_batch(b);   // b may be gone from here on
             {
+                const double t_fin = now_seconds();
                 std::lock_guard<std::mutex> g(stat_mu);
                 wait_s += t_done - tw0;
-                complete_s += now_seconds() - t_done;
+                complete_s += t_fin - t_done;
+                leg_queue += leg_q;
+                leg_stage += leg_s;
+                leg_device += leg_d;
+                leg_complete += nreq * (t_fin - t_done);
             }
         }
     }
@@ -543,14 +526,13 @@ public:
         for (auto &kv : kstats) {
             if (i < max && out) {
                 bem_kernel_stats_t &o = out[i];
-                const Variant &v = kv.first.first;
+                const Variant &v = kv.first;
                 o.op = v.op;
                 o.space = v.space;
                 o.prec = v.prec;
                 o.quad_points = v.q;
-                o.rowfix = v.rowfix;
-                o.reduce = kv.first.second;
                 o.launches = kv.second.launches;
+                o.workgroups = kv.second.workgroups;
                 o.entries = kv.second.entries;
                 o.pair_evals = kv.second.evals;
                 o.triangle_loads = kv.second.loads;
@@ -573,11 +555,16 @@ public:
         // timed batches are a sample: scale to all batches
         const double scale = n_timed ? (double)n_batches / (double)n_timed : 0.0;
         s->kernel_seconds = kernel_s * scale;
-        s->kernel_seconds_p1_reduce = reduce_s * scale;
         s->kernel_launches = n_launches;
         s->dispatch_seconds = dispatch_s;
         s->complete_seconds = complete_s;
         s->wait_seconds = wait_s;
+        s->dispatch_hip_seconds = dispatch_hip_s;
+        const double nr = n_requests ? (double)n_requests : 1.0;
+        s->mean_queue_seconds = leg_queue / nr;
+        s->mean_stage_seconds = leg_stage / nr;
+        s->mean_device_seconds = leg_device / nr;
+        s->mean_complete_seconds = leg_complete / nr;
         s->latency_p50 = s->latency_p99 = s->latency_max = 0.0;
         if (!latencies.empty()) {
             std::vector<float> v(latencies);
@@ -592,8 +579,9 @@ public:
         }
         if (reset) {
             n_requests = n_entries = n_batches = n_evals = n_launches = n_timed = 0;
-            busy = kernel_s = reduce_s = 0.0;
-            dispatch_s = complete_s = wait_s = 0.0;
+            busy = kernel_s = 0.0;
+            dispatch_s = complete_s = wait_s = dispatch_hip_s = 0.0;
+            leg_queue = leg_stage = leg_device = leg_complete = 0.0;
             latencies.clear();
         }
     }

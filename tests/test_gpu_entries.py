@@ -233,3 +233,32 @@ def test_full_size_icosphere6_sampled_rows():
             refc = om.entries(op, O.P1, 0.0, rows, cols[:1])
             assert normwise(gotc.astype(np.float64), refc) <= 1e-5
     mesh.destroy()
+
+
+def test_p1_chunk_edge_cases():
+    """P1 lane sides cut into chunks: a dof repeated far more often than a
+    workgroup has threads, a vertex that belongs to no triangle (its entries
+    are zero), and lane lists spanning many chunks, against the oracle."""
+    xyz, tri = inputs.icosphere(2)
+    xyz = np.vstack([xyz, [[5.0, 5.0, 5.0]]])          # vertex 162: in no triangle
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    lone = xyz.shape[0] - 1
+    rows = np.array([0, 77, lone], dtype=np.int32)
+    cols = np.arange(xyz.shape[0], dtype=np.int32)
+    for prec in (bem.FP64, bem.FP32):
+        for op in (bem.LAPLACE_SLP, bem.HELMHOLTZ_DLP):
+            got = bem.eval_entries(mesh, op, bem.P1, K[op], rows, cols, prec=prec, near=bem.NEAR_SKIP)
+            ref = om.entries(op, O.P1, K[op], rows, cols, near=O.NEAR_SKIP)
+            assert np.all(got[2] == 0) and np.all(got[:, lone] == 0)
+            assert normwise(got.astype(ref.dtype), ref) <= tol(op, prec)
+            # the transposed request runs with the row side on the lanes
+            gotT = bem.eval_entries(mesh, op, bem.P1, K[op], cols, rows, prec=prec, near=bem.NEAR_SKIP)
+            refT = om.entries(op, O.P1, K[op], cols, rows, near=O.NEAR_SKIP)
+            assert normwise(gotT.astype(refT.dtype), refT) <= tol(op, prec)
+    # 700 copies of one far dof: one chunk, 700 entries from the same partials
+    rep = np.full(700, 120, dtype=np.int32)
+    got = bem.eval_entries(mesh, bem.LAPLACE_SLP, bem.P1, 0.0, [3], rep, prec=bem.FP32)
+    single = bem.eval_entries(mesh, bem.LAPLACE_SLP, bem.P1, 0.0, [3], [120], prec=bem.FP32)
+    assert np.all(got == single[0, 0])
+    mesh.destroy()
