@@ -60,6 +60,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="only summarise four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of this benchmark and "
+                         "of --copy-calibration) into the traffic record used by the roofline")
+    ap.add_argument("--traffic-kernel", default="k_p1_f32<1, 6>",
+                    help="kernel name fragment of the dominant kernel for --traffic-from")
+    ap.add_argument("--traffic-copy-bytes", type=int, default=256 << 20)
     return ap.parse_args()
 
 
@@ -71,6 +77,52 @@ def copy_calibration(nbytes):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "dispatches": 5}))
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "*counter_collection.csv"))):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return rows
+
+
+def _mean_kib(rows, counter, pick):
+    vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and pick(r["Kernel_Name"])]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for the requested kernel")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic_from(args):
+    """HBM traffic per launch of the dominant kernel from two --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for a device copy of known size."""
+    fdir, wdir, cfdir, cwdir = args.traffic_from
+    frag = args.traffic_kernel
+    is_dom = lambda name: frag in name
+    is_copy = lambda name: "copyBuffer" in name
+    fetch, nf = _mean_kib(_counter_rows(fdir), "FETCH_SIZE", is_dom)
+    write, nw = _mean_kib(_counter_rows(wdir), "WRITE_SIZE", is_dom)
+    # the copy reads and writes args.traffic_copy_bytes; take its largest dispatch
+    cf = max(float(r["Counter_Value"]) for r in _counter_rows(cfdir)
+             if r["Counter_Name"] == "FETCH_SIZE" and is_copy(r["Kernel_Name"]))
+    cw = max(float(r["Counter_Value"]) for r in _counter_rows(cwdir)
+             if r["Counter_Name"] == "WRITE_SIZE" and is_copy(r["Kernel_Name"]))
+    kib = args.traffic_copy_bytes / 1024.0
+    f_fetch, f_write = kib / cf, kib / cw
+    rec = {"kernel": frag, "kernel_source_hash": kernel_source_hash(),
+           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
+           "copy_bytes": args.traffic_copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+           "fetch_factor": f_fetch, "write_factor": f_write,
+           "bytes_per_launch": (fetch * f_fetch + write * f_write) * 1024.0}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def assemble_step(bem, mesh, prec, args):
@@ -119,7 +171,8 @@ def roofline(kstats):
     dom = max(main, key=lambda k: k["seconds"])
     flops = dom["pair_evals"] * FLOPS_PER_EVAL[(dom["op"], dom["space"])]
     per_launch = flops / dom["launches"]
-    mean_s = dom["seconds"] / dom["launches"]
+    mean_s = dom["seconds"] / dom["launches"]            # kernel execution, device clock
+    mean_ev = dom["seconds_events"] / dom["launches"]    # HIP events around the launch
     achieved = per_launch / mean_s / 1e12
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -132,6 +185,7 @@ def roofline(kstats):
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_VALU / 1e12, 1),
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_VALU, 4), "traffic": traffic,
             "kernel": name, "launches": dom["launches"], "mean_launch_us": round(mean_s * 1e6, 2),
+            "mean_launch_us_hip_events": round(mean_ev * 1e6, 2),
             "flops_per_launch": per_launch, "flops_per_eval": FLOPS_PER_EVAL[(dom["op"], dom["space"])],
             "frac_of_packed_fp32_peak": round(achieved * 1e12 / PEAK_FP32_PACKED, 4)}
     return roof, dom
@@ -175,6 +229,9 @@ def cpu_baseline(bem, inputs, mesh, xyz, tri, seconds):
 
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_from(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the workload has no multi-GPU path in this build "
               "(blocks would be routed to independent per-GPU servers).", file=sys.stderr)

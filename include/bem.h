@@ -164,9 +164,9 @@ typedef struct {
     double latency_p99;
     double latency_max;
     double busy_seconds;     /* wall time with at least one batch on the device */
-    double kernel_seconds;   /* entry-kernel launch durations (HIP events), summed over the timed
+    double kernel_seconds;   /* entry-kernel execution times (device clock), summed over the timed
                                 batches and scaled to all batches */
-    int64_t kernel_launches; /* launches timed: every launch of one batch in four carries start/stop
+    int64_t kernel_launches; /* launches timed: every launch of one batch in eight carries start/stop
                                 HIP events, so kernel_seconds covers that sample */
     double dispatch_seconds; /* host time spent staging and enqueueing batches */
     double complete_seconds; /* host time spent completing batches (after their event) */
@@ -182,10 +182,14 @@ typedef struct {
 /* Statistics since the last reset; reset != 0 clears them afterwards. */
 int bem_server_stats(bem_server_stats_t *stats, int reset);
 
-/* Per kernel variant: launches, durations (start/stop HIP events bound to
- * each launch's own dispatch, for one batch in four) and the work those
- * timed launches covered.  One entry launch serves row and column requests
- * alike. */
+/* Per kernel variant, over the launches of one batch in eight: launches,
+ * durations and the work those timed launches covered.  `seconds` is the
+ * kernels' own execution time (earliest wavefront start to latest wavefront
+ * end on the device's constant-rate clock); `seconds_events` is the time
+ * between HIP events recorded around each launch on its stream, which also
+ * holds whatever separates the start event from the kernel's start (host
+ * submission of the launch, other work of the same hardware queue).  One
+ * entry launch serves row and column requests alike. */
 typedef struct {
     int32_t op, space, prec, quad_points;
     int64_t launches;
@@ -194,7 +198,8 @@ typedef struct {
     int64_t pair_evals;        /* Q^2 x (fixed, lane) triangle pairs; vertex-sharing pairs, which are
                                   skipped, are included (there are none in admissible blocks) */
     int64_t triangle_loads;    /* lane-triangle geometry records gathered (one per lane per workgroup) */
-    double seconds;            /* summed launch durations */
+    double seconds;            /* summed kernel execution times (device clock) */
+    double seconds_events;     /* summed HIP-event launch brackets */
 } bem_kernel_stats_t;
 
 /* Copies up to max_entries variant records into out, sets *count to the

@@ -90,10 +90,11 @@ struct Variant {
 int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out);
 
 // Launchers (entries.hip).  Return hipSuccess or the launch error.
-// `start`/`stop` (optional) are bound to the kernel's own dispatch, so their
-// elapsed time is the kernel's execution time, not the stream's.
+// tclock (optional, device memory, 2 * nblocks entries): receives each
+// workgroup's start and end on the device's constant-rate clock.
+// start/stop (optional): HIP events recorded around the launch on its stream.
 hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock *blocks, int64_t nblocks, hipStream_t s,
-                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+                          unsigned long long *tclock = nullptr, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, int q, float *g32, double *g64,
                            int4 *vtx, int32_t *bad, hipStream_t s);
 

@@ -94,6 +94,22 @@ __device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x)
     hi = s;
 }
 
+// Launch timing: with tc set, workgroup b stores the constant-rate device
+// clock at its start in tc[2b] and, once all its wavefronts are done, at its
+// end in tc[2b + 1] (plain stores, one slot per workgroup).
+__device__ __forceinline__ void clock_start(unsigned long long *tc)
+{
+    if (tc && threadIdx.x == 0) tc[2 * blockIdx.x] = (unsigned long long)wall_clock64();
+}
+
+__device__ __forceinline__ void clock_end(unsigned long long *tc)
+{
+    if (tc) {   // workgroup-uniform
+        __syncthreads();
+        if (threadIdx.x == 0) tc[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
+    }
+}
+
 // Green's function factors at one point pair, FP32.  d = x - y, r2 = |d|^2.
 // SLP: accumulates w/r;   DLP: w/r^3 (the (x-y).n_y factor is applied per
 // test point by the caller: the trial offsets lie in the trial plane, so
@@ -386,15 +402,18 @@ __device__ __forceinline__ void p0_body_f32(const ReqDev &R, const EntryBlock &B
 
 template <int OP, int Q>
 __global__ __launch_bounds__(kBlockLanes) void k_p0_f32(const ReqDev *__restrict__ reqs,
-                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks)
+                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks,
+                                                        unsigned long long *tclock)
 {
     if ((int64_t)blockIdx.x >= nblocks) return;
+    clock_start(tclock);
     const EntryBlock B = blocks[blockIdx.x];
     const ReqDev &R = reqs[B.req];
     if (R.rowfix)
         p0_body_f32<OP, Q, true>(R, B);
     else
         p0_body_f32<OP, Q, false>(R, B);
+    clock_end(tclock);
 }
 
 template <int OP, int Q, bool ROWFIX>
@@ -432,15 +451,18 @@ __device__ __forceinline__ void p0_body_f64(const ReqDev &R, const EntryBlock &B
 
 template <int OP, int Q>
 __global__ __launch_bounds__(kBlockLanes) void k_p0_f64(const ReqDev *__restrict__ reqs,
-                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks)
+                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks,
+                                                        unsigned long long *tclock)
 {
     if ((int64_t)blockIdx.x >= nblocks) return;
+    clock_start(tclock);
     const EntryBlock B = blocks[blockIdx.x];
     const ReqDev &R = reqs[B.req];
     if (R.rowfix)
         p0_body_f64<OP, Q, true>(R, B);
     else
         p0_body_f64<OP, Q, false>(R, B);
+    clock_end(tclock);
 }
 
 // Stages up to kStage triangles of the fixed star, starting at star entry
@@ -540,19 +562,22 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
 
 template <int OP, int Q>
 __global__ __launch_bounds__(kBlockLanes) void k_p1_f32(const ReqDev *__restrict__ reqs,
-                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks)
+                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks,
+                                                        unsigned long long *tclock)
 {
     __shared__ float sG[kStage][n32<Q>()];
     __shared__ int4 sV[kStage];
     __shared__ int sL[kStage];
     __shared__ float4 sP[kBlockLanes][3];
     if ((int64_t)blockIdx.x >= nblocks) return;
+    clock_start(tclock);
     const EntryBlock B = blocks[blockIdx.x];
     const ReqDev &R = reqs[B.req];
     if (R.rowfix)
         p1_body_f32<OP, Q, true>(R, B, sG, sV, sL, sP);
     else
         p1_body_f32<OP, Q, false>(R, B, sG, sV, sL, sP);
+    clock_end(tclock);
 }
 
 // P1, FP64: the same two phases with plain FP64 sums.
@@ -621,24 +646,27 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
 
 template <int OP, int Q>
 __global__ __launch_bounds__(kBlockLanes) void k_p1_f64(const ReqDev *__restrict__ reqs,
-                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks)
+                                                        const EntryBlock *__restrict__ blocks, int64_t nblocks,
+                                                        unsigned long long *tclock)
 {
     __shared__ double sG[kStage][n64<Q>()];
     __shared__ int4 sV[kStage];
     __shared__ int sL[kStage];
     __shared__ double2 sP[kBlockLanes][3];
     if ((int64_t)blockIdx.x >= nblocks) return;
+    clock_start(tclock);
     const EntryBlock B = blocks[blockIdx.x];
     const ReqDev &R = reqs[B.req];
     if (R.rowfix)
         p1_body_f64<OP, Q, true>(R, B, sG, sV, sL, sP);
     else
         p1_body_f64<OP, Q, false>(R, B, sG, sV, sL, sP);
+    clock_end(tclock);
 }
 
 // ---------------------------------------------------------------------------
 // Dispatch.
-typedef void (*EntryKernel)(const ReqDev *, const EntryBlock *, int64_t);
+typedef void (*EntryKernel)(const ReqDev *, const EntryBlock *, int64_t, unsigned long long *);
 
 template <int OP, int Q>
 EntryKernel pick(int space, int prec)
@@ -666,16 +694,16 @@ EntryKernel select_kernel(const Variant &v)
 }  // namespace
 
 hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock *blocks, int64_t nblocks, hipStream_t s,
-                          hipEvent_t start, hipEvent_t stop)
+                          unsigned long long *tclock, hipEvent_t start, hipEvent_t stop)
 {
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > INT32_MAX) return hipErrorInvalidValue;
     const EntryKernel k = select_kernel(v);
     if (start || stop)
         hipExtLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kBlockLanes), 0, s, start, stop, 0, reqs, blocks,
-                              nblocks);
+                              nblocks, tclock);
     else
-        hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kBlockLanes), 0, s, reqs, blocks, nblocks);
+        hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kBlockLanes), 0, s, reqs, blocks, nblocks, tclock);
     return hipGetLastError();
 }
 

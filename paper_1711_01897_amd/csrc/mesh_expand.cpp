@@ -226,8 +226,8 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
 
 size_t request_bytes(const Request &r)
 {
-    // descriptor, inputs, status, outputs, block table
-    return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * sizeof(EntryBlock) + 64;
+    // descriptor, inputs, status, outputs, block table, launch-timing records
+    return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * (sizeof(EntryBlock) + 16) + 64;
 }
 
 size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d)

@@ -16,6 +16,10 @@
 //    threads stage and enqueue the next batches while earlier ones run or are
 //    being consumed, so consecutive batches overlap on the device and
 //    requests that arrive meanwhile wait only for the next free slot;
+//  * staging: each slot has pinned host staging and a device arena; the
+//    inputs are copied to the arena in one copy, and the kernels store
+//    results and near-field flags straight into the staging (host-coherent,
+//    uncached on the device), so a batch is one copy and its launches;
 //  * completion: completion threads wait for each batch's event, check the
 //    near-field flags, copy results to the callers' buffers (or lend the
 //    caller a pointer into the pinned staging until it releases it), wake
@@ -24,6 +28,7 @@
 // summation order whichever batch it lands in.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <deque>
 #include <map>
@@ -37,7 +42,7 @@ namespace {
 
 constexpr int kMaxSlots = 16;
 constexpr int kMaxThreads = 4;
-constexpr int kTimedEvery = 4;
+constexpr int kTimedEvery = 8;
 constexpr int kKeys = 32;   // launch groups: (op, space, prec, rule)
 
 int env_int(const char *name, int dflt, int lo, int hi)
@@ -61,7 +66,7 @@ struct Launch {
 
 struct KStat {
     int64_t launches = 0, workgroups = 0, entries = 0, evals = 0, loads = 0;
-    double seconds = 0.0;
+    double seconds = 0.0, seconds_events = 0.0;
 };
 
 struct Batch {
@@ -74,6 +79,7 @@ struct Batch {
     double t_launch = 0.0;
     double t_hip = 0.0;           // host seconds inside the enqueue calls
     double t_take = 0.0, t_enq = 0.0, q_sum = 0.0;   // latency legs (q_sum: summed queue waits)
+    size_t off_clock = 0;         // timed batches: per-launch {start, end} device clock records
     int64_t entries = 0, evals = 0;
     std::atomic<int> refs{1};     // completion thread + borrowed results
     bool timed = false;           // per-launch events recorded
@@ -89,11 +95,11 @@ public:
     size_t arena_bytes = size_t(1) << 30;
     int max_batch = 16384;
     int nslots = 8;     // BEM_SERVER_SLOTS
-    int nstreams = 8;   // BEM_SERVER_STREAMS (slot s uses stream s % nstreams), default one per slot
+    int nstreams = 4;   // BEM_SERVER_STREAMS (slot s uses stream s % nstreams), default one per hardware queue
     int ndisp = 1;      // BEM_SERVER_DISPATCHERS
     int ncomp = 1;      // BEM_SERVER_COMPLETERS
-    bool host_out = true;    // BEM_SERVER_HOST_OUT: kernels store results and flags straight into pinned staging
     bool spin = false;       // BEM_SERVER_SPIN: completion threads poll batch events instead of blocking
+    bool log_launches = false;   // BEM_DEBUG_LAUNCHES: print each timed launch (grid, duration) to stderr
 
     std::mutex mu;
     std::condition_variable cv;    // dispatchers: pending requests, free slots
@@ -111,6 +117,7 @@ public:
     std::mutex ev_mu;
     std::vector<hipEvent_t> event_pool;
     std::atomic<int64_t> batch_counter{0};
+    double clock_hz = 1e8;   // device constant-rate clock
 
     // statistics
     std::mutex stat_mu;
@@ -125,19 +132,25 @@ public:
     {
         if (started) return BEM_OK;
         nslots = env_int("BEM_SERVER_SLOTS", nslots, 2, kMaxSlots);
-        nstreams = env_int("BEM_SERVER_STREAMS", nslots, 1, nslots);
+        // one stream per hardware queue: streams that share a queue run
+        // their packets in one order, so more streams than queues only
+        // serialise batches behind each other
+        const int hwq = env_int("GPU_MAX_HW_QUEUES", 4, 1, kMaxSlots);
+        nstreams = env_int("BEM_SERVER_STREAMS", std::min(nslots, hwq), 1, nslots);
         ndisp = env_int("BEM_SERVER_DISPATCHERS", ndisp, 1, kMaxThreads);
         ncomp = env_int("BEM_SERVER_COMPLETERS", ncomp, 1, kMaxThreads);
-        host_out = env_int("BEM_SERVER_HOST_OUT", host_out ? 1 : 0, 0, 1) != 0;
         spin = env_int("BEM_SERVER_SPIN", spin ? 1 : 0, 0, 1) != 0;
+        log_launches = env_int("BEM_DEBUG_LAUNCHES", 0, 0, 1) != 0;
         hipError_t e = hipGetDevice(&device);
+        int khz = 0;
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
+        clock_hz = khz > 0 ? 1e3 * khz : 1e8;
         for (int i = 0; i < nstreams && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&streams[i], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipMalloc(&d_arena, arena_bytes);
-        // with host_out the kernels write into the staging: coherent (uncached
-        // on the device) so results are in host memory once the batch event
-        // completes
-        if (e == hipSuccess)
-            e = hipHostMalloc(&h_stage, arena_bytes, host_out ? hipHostMallocCoherent : hipHostMallocDefault);
+        // inputs are staged here and copied to the device arena; the kernels
+        // store results and flags straight into it, uncached (coherent), so
+        // they are in host memory once the batch event completes
+        if (e == hipSuccess) e = hipHostMalloc(&h_stage, arena_bytes, hipHostMallocCoherent);
         if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&h_stage_dev, h_stage, 0);
         if (e != hipSuccess) {
             if (d_arena) (void)hipFree(d_arena);
@@ -152,6 +165,10 @@ public:
         return BEM_OK;
     }
 
+    // Events skip the system-scope fence (a device cache writeback and
+    // invalidation per event): results reach the host through uncached
+    // stores to coherent memory, which precede the batch event's signal, and
+    // timing events must not charge such cache work to the timed kernel.
     hipEvent_t get_event()
     {
         std::lock_guard<std::mutex> g(ev_mu);
@@ -161,7 +178,7 @@ public:
             return e;
         }
         hipEvent_t e = nullptr;
-        (void)hipEventCreate(&e);
+        (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
         return e;
     }
 
@@ -300,6 +317,7 @@ public:
         b->slot = slot;
         b->reqs = take;
         char *hb = h_stage + (size_t)slot * slot_bytes;
+        char *hd = h_stage_dev + (size_t)slot * slot_bytes;   // the slot's staging, device address
         char *db = d_arena + (size_t)slot * slot_bytes;
         hipStream_t stream = streams[slot % nstreams];
         const int n = (int)take.size();
@@ -328,7 +346,8 @@ public:
             launches.push_back(L);
         }
 
-        // layout: descriptors | block tables | inputs | status || outputs
+        // layout: descriptors | block tables | inputs  (copied to the device
+        // arena) || status | outputs  (stored by the kernels into the staging)
         // (offsets first, checked against the slot, then the staging writes)
         size_t off = align256(sizeof(ReqDev) * n);
         for (Launch &L : launches) {
@@ -337,15 +356,21 @@ public:
         }
         const size_t off_in = off;
         for (int i = 0; i < n; ++i) off += take[i]->in_bytes;
+        const size_t h2d_end = align256(off);
+        // every kTimedEvery-th batch times its launches: per workgroup a
+        // {start, end} device-clock record, read back after the launches
+        b->timed = (batch_counter.fetch_add(1) % kTimedEvery) == 0;
+        const size_t off_clock = h2d_end;
+        int64_t nblk = 0;
+        for (const Launch &L : launches) nblk += L.count;
+        off = off_clock + (b->timed ? 16 * (size_t)nblk : 0);
         const size_t off_status = align256(off);
         off = align256(off_status + sizeof(int32_t) * n);
-        const size_t h2d_end = off;
         std::vector<size_t> out_off(n);
         for (int i = 0; i < n; ++i) {
             out_off[i] = off;
             off += take[i]->out_bytes;
         }
-        const size_t d2h_end = off;
         if (off > slot_bytes) {
             // admission keeps this from happening; fail the batch rather than overrun the slot
             b->t_launch = now_seconds();
@@ -366,18 +391,17 @@ public:
         size_t in = off_in;
         for (int i = 0; i < n; ++i) in += stage_request_inputs(*take[i], hb, db, in, hreq[i]);
         std::memset(hb + off_status, 0, sizeof(int32_t) * n);
-        char *ob = host_out ? h_stage_dev + (size_t)slot * slot_bytes : db;   // where results are stored
+        b->off_clock = off_clock;
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
-            finish_descriptor(r, ob, out_off[i], off_status + sizeof(int32_t) * i, hreq[i]);
+            finish_descriptor(r, hd, out_off[i], off_status + sizeof(int32_t) * i, hreq[i]);
             r.off_out = out_off[i];
             r.off_status = off_status + sizeof(int32_t) * i;
         }
         b->launches = std::move(launches);
 
-        // enqueue: inputs, launches (every kTimedEvery-th batch with a
-        // start/stop event pair bound to each launch; the batch event is
-        // always kept), statuses and outputs back
+        // enqueue: inputs, the launches (timed ones also with HIP events
+        // around each launch), the clock records back, the batch event
         b->t_launch = now_seconds();
         b->t_hip = b->t_launch;
         auto note = [&](hipError_t e) {
@@ -385,20 +409,23 @@ public:
         };
         note(hipMemcpyAsync(db, hb, h2d_end, hipMemcpyHostToDevice, stream));
         const ReqDev *dreq = reinterpret_cast<const ReqDev *>(db);
-        b->timed = (batch_counter.fetch_add(1) % kTimedEvery) == 0;
+        int64_t blk0 = 0;
         for (const Launch &L : b->launches) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
+            unsigned long long *ck = nullptr;
             if (b->timed) {
                 e0 = get_event();
                 e1 = get_event();
                 b->ev.push_back(e0);
                 b->ev.push_back(e1);
+                ck = reinterpret_cast<unsigned long long *>(db + off_clock) + 2 * blk0;
             }
-            note(launch_entries(L.v, dreq, reinterpret_cast<const EntryBlock *>(db + L.off_tab), L.count, stream, e0,
-                                e1));
+            note(launch_entries(L.v, dreq, reinterpret_cast<const EntryBlock *>(db + L.off_tab), L.count, stream, ck,
+                                e0, e1));
+            blk0 += L.count;
         }
-        if (!host_out)
-            note(hipMemcpyAsync(hb + off_status, db + off_status, d2h_end - off_status, hipMemcpyDeviceToHost, stream));
+        if (b->timed)
+            note(hipMemcpyAsync(hb + off_clock, db + off_clock, 16 * (size_t)blk0, hipMemcpyDeviceToHost, stream));
         b->ev_done = get_event();
         note(hipEventRecord(b->ev_done, stream));
         b->t_hip = now_seconds() - b->t_hip;
@@ -443,15 +470,27 @@ public:
             if (e == hipSuccess) e = b->enqueue_error;
             const double t_done = now_seconds();
             double ks = 0.0;
-            std::vector<double> dur(b->launches.size(), 0.0);
-            if (b->timed && e == hipSuccess)
+            std::vector<double> dur(b->launches.size(), 0.0), dev(b->launches.size(), 0.0);
+            if (b->timed && e == hipSuccess) {
+                const unsigned long long *ck =
+                    reinterpret_cast<const unsigned long long *>(h_stage + (size_t)b->slot * slot_bytes + b->off_clock);
                 for (size_t i = 0; i < b->launches.size(); ++i) {
                     float ms = 0.f;
-                    if (hipEventElapsedTime(&ms, b->ev[2 * i], b->ev[2 * i + 1]) == hipSuccess) {
-                        dur[i] = ms * 1e-3;
-                        ks += ms * 1e-3;
+                    if (hipEventElapsedTime(&ms, b->ev[2 * i], b->ev[2 * i + 1]) == hipSuccess) dur[i] = ms * 1e-3;
+                    // kernel execution: earliest workgroup start to latest workgroup end
+                    unsigned long long t0 = ~0ull, t1 = 0;
+                    for (int64_t w = 0; w < b->launches[i].count; ++w) {
+                        t0 = std::min(t0, ck[2 * w]);
+                        t1 = std::max(t1, ck[2 * w + 1]);
                     }
+                    ck += 2 * b->launches[i].count;
+                    if (t1 > t0) dev[i] = (double)(t1 - t0) / clock_hz;
+                    ks += dev[i];
+                    if (log_launches)
+                        fprintf(stderr, "[bem-launch] slot %d grid %lld events_us %.2f clock_us %.2f\n", b->slot,
+                                (long long)b->launches[i].count, 1e6 * dur[i], 1e6 * dev[i]);
                 }
+            }
             {
                 std::lock_guard<std::mutex> g(stat_mu);
                 n_batches += 1;
@@ -475,7 +514,8 @@ public:
                     k.entries += L.entries;
                     k.evals += L.evals;
                     k.loads += L.loads;
-                    k.seconds += dur[i];
+                    k.seconds += dev[i];
+                    k.seconds_events += dur[i];
                 }
             }
             char *hb = h_stage + (size_t)b->slot * slot_bytes;
@@ -537,6 +577,7 @@ public:
                 o.pair_evals = kv.second.evals;
                 o.triangle_loads = kv.second.loads;
                 o.seconds = kv.second.seconds;
+                o.seconds_events = kv.second.seconds_events;
             }
             ++i;
         }
