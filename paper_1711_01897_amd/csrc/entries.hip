@@ -14,9 +14,11 @@
 // kernel and launch; the side is a workgroup-uniform branch.
 //
 // FP32 path: positions are centroid-relative (bem_internal.hpp), 1/r is the
-// hardware reciprocal square root, the Helmholtz phase k r is formed and
-// reduced to a turn in [-1/2, 1/2] in FP64 and fed to the hardware sine and
-// cosine, which take their argument in turns.  The inner sum over one
+// hardware reciprocal square root; the Helmholtz phase k r is split into
+// k |D| (centroid distance, FP64 per triangle pair, reduced to a turn) and
+// k (r - |D|) from small quantities in FP32 (see Phase), and the turn in
+// [-1/2, 1/2] is fed to the hardware sine and cosine, which take their
+// argument in turns.  The inner sum over one
 // triangle's quadrature points is a plain FP32 sum; every coarser sum (over
 // the other triangle's points for P0, over triangle pairs for P1, and the
 // final per-entry reduction) is compensated with TwoSum (Knuth).
@@ -110,12 +112,43 @@ __device__ __forceinline__ void clock_end(unsigned long long *tc)
     }
 }
 
-// Green's function factors at one point pair, FP32.  d = x - y, r2 = |d|^2.
+// Helmholtz phase on the FP32 path.  With D the centroid difference of the
+// pair and d = o_p - o_q the offset difference of two quadrature points,
+// r = |D + d| and k r = k |D| + k (r - |D|).  The first term is formed once
+// per triangle pair in FP64 from the exact centroid parts and reduced to a
+// turn (t0); the second from N = r^2 - |D|^2 = 2 D.d + |d|^2, a sum of small
+// terms, as k (r - |D|) = k N / (r + |D|) in FP32.  The phase error is then
+// about k h 1e-7 (h the element size) instead of k r 1e-7.
+struct Phase {
+    float t0;     // frac(k |D| / 2 pi), in [-1/2, 1/2]
+    float dn;     // |D|
+    float dsq;    // |D_f|^2 of the FP32 centroid difference
+    float kkf;    // k / 2 pi
+};
+
+__device__ __forceinline__ Phase phase_base(const float *T, const float *S, double kk, float dcx, float dcy,
+                                            float dcz)
+{
+    const double dx = ((double)T[0] - (double)S[0]) + ((double)T[4] - (double)S[4]);
+    const double dy = ((double)T[1] - (double)S[1]) + ((double)T[5] - (double)S[5]);
+    const double dz = ((double)T[2] - (double)S[2]) + ((double)T[6] - (double)S[6]);
+    const double d = __builtin_sqrt(dx * dx + dy * dy + dz * dz);
+    const double t = kk * d;
+    Phase ph;
+    ph.t0 = (float)(t - __builtin_rint(t));
+    ph.dn = (float)d;
+    ph.dsq = fmaf(dcx, dcx, fmaf(dcy, dcy, dcz * dcz));
+    ph.kkf = (float)kk;
+    return ph;
+}
+
+// Green's function factors at one point pair, FP32.  r2 = |x - y|^2; for
+// Helmholtz also n = r^2 - |D|^2 (see Phase).
 // SLP: accumulates w/r;   DLP: w/r^3 (the (x-y).n_y factor is applied per
 // test point by the caller: the trial offsets lie in the trial plane, so
 // (x_p - y_q).n_y = (x_p - c_y).n_y for every q).
 template <int OP>
-__device__ __forceinline__ void kern_f32(float r2, float w, float kf, double kk, float &sr, float &si)
+__device__ __forceinline__ void kern_f32(float r2, float n, float w, float kf, const Phase &ph, float &sr, float &si)
 {
     const float ri = __builtin_amdgcn_rsqf(r2);
     if constexpr (OP == LSLP) {
@@ -124,9 +157,10 @@ __device__ __forceinline__ void kern_f32(float r2, float w, float kf, double kk,
         sr = fmaf(w, ri * ri * ri, sr);
     } else {
         const float r = r2 * ri;
-        const double t = (double)r * kk;               // phase in turns, FP64
-        const float f = (float)(t - __builtin_rint(t)); // reduced to [-1/2, 1/2]
-        const float sn = __builtin_amdgcn_sinf(f);      // sin(2 pi f)
+        const float delta = n * __builtin_amdgcn_rcpf(r + ph.dn);   // r - |D|
+        float f = fmaf(ph.kkf, delta, ph.t0);                         // phase in turns
+        f = f - __builtin_rintf(f);                                   // reduced to [-1/2, 1/2]
+        const float sn = __builtin_amdgcn_sinf(f);                    // sin(2 pi f)
         const float cs = __builtin_amdgcn_cosf(f);
         if constexpr (OP == HSLP) {
             const float g = w * ri;
@@ -180,20 +214,47 @@ __device__ __forceinline__ void pair_p0_f32(const float *T, const float *S, floa
     const float dcy = (T[1] - S[1]) + (T[5] - S[5]);
     const float dcz = (T[2] - S[2]) + (T[6] - S[6]);
     float hr = 0.f, lr = 0.f, hi = 0.f, li = 0.f;
+    if constexpr (is_cplx<OP>()) {
+        // n = r^2 - |D|^2 = (A'_p + B_q) + (-2 a_p).o_q with a_p = D + o_p,
+        // A'_p = 2 D.o_p + |o_p|^2, B_q = |o_q|^2; r^2 = n + |D|^2
+        const Phase ph = phase_base(T, S, kk, dcx, dcy, dcz);
+        float B[Q];
 #pragma unroll
-    for (int p = 0; p < Q; ++p) {
-        const float ax = dcx + T[12 + 3 * p], ay = dcy + T[13 + 3 * p], az = dcz + T[14 + 3 * p];
-        float sr = 0.f, si = 0.f;
+        for (int q = 0; q < Q; ++q)
+            B[q] = fmaf(S[12 + 3 * q], S[12 + 3 * q], fmaf(S[13 + 3 * q], S[13 + 3 * q], S[14 + 3 * q] * S[14 + 3 * q]));
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const float dx = ax - S[12 + 3 * q], dy = ay - S[13 + 3 * q], dz = az - S[14 + 3 * q];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-            kern_f32<OP>(r2, (float)rule::Rule<Q>::w[q], kf, kk, sr, si);
+        for (int p = 0; p < Q; ++p) {
+            const float ox = T[12 + 3 * p], oy = T[13 + 3 * p], oz = T[14 + 3 * p];
+            const float ax = dcx + ox, ay = dcy + oy, az = dcz + oz;
+            const float mx = -2.0f * ax, my = -2.0f * ay, mz = -2.0f * az;
+            const float Ap = fmaf(2.0f * dcx + ox, ox, fmaf(2.0f * dcy + oy, oy, (2.0f * dcz + oz) * oz));
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const float n = fmaf(mx, S[12 + 3 * q], fmaf(my, S[13 + 3 * q], fmaf(mz, S[14 + 3 * q], Ap + B[q])));
+                kern_f32<OP>(n + ph.dsq, n, (float)rule::Rule<Q>::w[q], kf, ph, sr, si);
+            }
+            float wp = (float)rule::Rule<Q>::w[p];
+            if constexpr (is_dlp<OP>()) wp *= fmaf(ax, S[8], fmaf(ay, S[9], az * S[10]));
+            two_sum_acc(hr, lr, wp * sr);
+            two_sum_acc(hi, li, wp * si);
         }
-        float wp = (float)rule::Rule<Q>::w[p];
-        if constexpr (is_dlp<OP>()) wp *= fmaf(ax, S[8], fmaf(ay, S[9], az * S[10]));
-        two_sum_acc(hr, lr, wp * sr);
-        if constexpr (is_cplx<OP>()) two_sum_acc(hi, li, wp * si);
+    } else {
+        const Phase ph{};
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const float ax = dcx + T[12 + 3 * p], ay = dcy + T[13 + 3 * p], az = dcz + T[14 + 3 * p];
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const float dx = ax - S[12 + 3 * q], dy = ay - S[13 + 3 * q], dz = az - S[14 + 3 * q];
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                kern_f32<OP>(r2, 0.f, (float)rule::Rule<Q>::w[q], kf, ph, sr, si);
+            }
+            float wp = (float)rule::Rule<Q>::w[p];
+            if constexpr (is_dlp<OP>()) wp *= fmaf(ax, S[8], fmaf(ay, S[9], az * S[10]));
+            two_sum_acc(hr, lr, wp * sr);
+        }
     }
     vr = hr + lr;
     vi = hi + li;
@@ -232,18 +293,25 @@ __device__ __forceinline__ void pair_p1_testfix_f32(const float *T, int a, const
 {
     // x_p - y_q = a_p - o_q with a_p the test point relative to the trial
     // centroid; r^2 = (|a_p|^2 + |o_q|^2) + (-2 a_p) . o_q costs one add and
-    // three fma per point pair.
+    // three fma per point pair.  Helmholtz: the same chain started from
+    // A'_p = |a_p|^2 - |D|^2 = 2 D.o_p + |o_p|^2 gives n = r^2 - |D|^2.
     const float dcx = (T[0] - S[0]) + (T[4] - S[4]);
     const float dcy = (T[1] - S[1]) + (T[5] - S[5]);
     const float dcz = (T[2] - S[2]) + (T[6] - S[6]);
+    Phase ph{};
+    if constexpr (is_cplx<OP>()) ph = phase_base(T, S, kk, dcx, dcy, dcz);
     float mx[Q], my[Q], mz[Q], A[Q], wa[Q];
 #pragma unroll
     for (int p = 0; p < Q; ++p) {
-        const float ax = dcx + T[12 + 3 * p], ay = dcy + T[13 + 3 * p], az = dcz + T[14 + 3 * p];
+        const float ox = T[12 + 3 * p], oy = T[13 + 3 * p], oz = T[14 + 3 * p];
+        const float ax = dcx + ox, ay = dcy + oy, az = dcz + oz;
         mx[p] = -2.0f * ax;
         my[p] = -2.0f * ay;
         mz[p] = -2.0f * az;
-        A[p] = fmaf(ax, ax, fmaf(ay, ay, az * az));
+        if constexpr (is_cplx<OP>())
+            A[p] = fmaf(2.0f * dcx + ox, ox, fmaf(2.0f * dcy + oy, oy, (2.0f * dcz + oz) * oz));
+        else
+            A[p] = fmaf(ax, ax, fmaf(ay, ay, az * az));
         const float l = (float)(a == 0 ? rule::Rule<Q>::l0[p] : (a == 1 ? rule::Rule<Q>::l1[p] : rule::Rule<Q>::l2[p]));
         wa[p] = (float)rule::Rule<Q>::w[p] * l;
         if constexpr (is_dlp<OP>()) wa[p] *= fmaf(ax, S[8], fmaf(ay, S[9], az * S[10]));
@@ -257,8 +325,11 @@ __device__ __forceinline__ void pair_p1_testfix_f32(const float *T, int a, const
         float tr = 0.f, ti = 0.f;
 #pragma unroll
         for (int p = 0; p < Q; ++p) {
-            const float r2 = fmaf(mx[p], ox, fmaf(my[p], oy, fmaf(mz[p], oz, A[p] + B)));
-            kern_f32<OP>(r2, wa[p], kf, kk, tr, ti);
+            const float v = fmaf(mx[p], ox, fmaf(my[p], oy, fmaf(mz[p], oz, A[p] + B)));
+            if constexpr (is_cplx<OP>())
+                kern_f32<OP>(v + ph.dsq, v, wa[p], kf, ph, tr, ti);
+            else
+                kern_f32<OP>(v, 0.f, wa[p], kf, ph, tr, ti);
         }
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
@@ -278,6 +349,8 @@ __device__ __forceinline__ void pair_p1_trialfix_f32(const float *T, const float
     const float dcx = (T[0] - S[0]) + (T[4] - S[4]);
     const float dcy = (T[1] - S[1]) + (T[5] - S[5]);
     const float dcz = (T[2] - S[2]) + (T[6] - S[6]);
+    Phase ph{};
+    if constexpr (is_cplx<OP>()) ph = phase_base(T, S, kk, dcx, dcy, dcz);
     float wb[Q], B[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -289,14 +362,22 @@ __device__ __forceinline__ void pair_p1_trialfix_f32(const float *T, const float
     for (int e = 0; e < 3; ++e) vr[e] = vi[e] = 0.f;
 #pragma unroll
     for (int p = 0; p < Q; ++p) {
-        const float ax = dcx + T[12 + 3 * p], ay = dcy + T[13 + 3 * p], az = dcz + T[14 + 3 * p];
+        const float ox = T[12 + 3 * p], oy = T[13 + 3 * p], oz = T[14 + 3 * p];
+        const float ax = dcx + ox, ay = dcy + oy, az = dcz + oz;
         const float mx = -2.0f * ax, my = -2.0f * ay, mz = -2.0f * az;
-        const float A = fmaf(ax, ax, fmaf(ay, ay, az * az));
+        float A;
+        if constexpr (is_cplx<OP>())
+            A = fmaf(2.0f * dcx + ox, ox, fmaf(2.0f * dcy + oy, oy, (2.0f * dcz + oz) * oz));
+        else
+            A = fmaf(ax, ax, fmaf(ay, ay, az * az));
         float tr = 0.f, ti = 0.f;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-            const float r2 = fmaf(mx, S[12 + 3 * q], fmaf(my, S[13 + 3 * q], fmaf(mz, S[14 + 3 * q], A + B[q])));
-            kern_f32<OP>(r2, wb[q], kf, kk, tr, ti);
+            const float v = fmaf(mx, S[12 + 3 * q], fmaf(my, S[13 + 3 * q], fmaf(mz, S[14 + 3 * q], A + B[q])));
+            if constexpr (is_cplx<OP>())
+                kern_f32<OP>(v + ph.dsq, v, wb[q], kf, ph, tr, ti);
+            else
+                kern_f32<OP>(v, 0.f, wb[q], kf, ph, tr, ti);
         }
         if constexpr (is_dlp<OP>()) {
             const float an = fmaf(ax, S[8], fmaf(ay, S[9], az * S[10]));

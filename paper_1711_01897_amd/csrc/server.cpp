@@ -483,12 +483,25 @@ public:
                         t0 = std::min(t0, ck[2 * w]);
                         t1 = std::max(t1, ck[2 * w + 1]);
                     }
-                    ck += 2 * b->launches[i].count;
                     if (t1 > t0) dev[i] = (double)(t1 - t0) / clock_hz;
                     ks += dev[i];
-                    if (log_launches)
-                        fprintf(stderr, "[bem-launch] slot %d grid %lld events_us %.2f clock_us %.2f\n", b->slot,
-                                (long long)b->launches[i].count, 1e6 * dur[i], 1e6 * dev[i]);
+                    if (log_launches) {
+                        // workgroup durations and start offsets (median, max), device clock
+                        const int64_t nw = b->launches[i].count;
+                        std::vector<double> wd(nw), ws(nw);
+                        for (int64_t w = 0; w < nw; ++w) {
+                            wd[w] = 1e6 * (double)(ck[2 * w + 1] - ck[2 * w]) / clock_hz;
+                            ws[w] = 1e6 * (double)(ck[2 * w] - t0) / clock_hz;
+                        }
+                        std::sort(wd.begin(), wd.end());
+                        std::sort(ws.begin(), ws.end());
+                        fprintf(stderr,
+                                "[bem-launch] slot %d grid %lld events_us %.2f clock_us %.2f wg_us med %.2f max %.2f "
+                                "start_us med %.2f max %.2f\n",
+                                b->slot, (long long)nw, 1e6 * dur[i], 1e6 * dev[i], wd[nw / 2], wd[nw - 1], ws[nw / 2],
+                                ws[nw - 1]);
+                    }
+                    ck += 2 * b->launches[i].count;
                 }
             }
             {
