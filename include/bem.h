@@ -149,10 +149,17 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
                            bem_prec prec, bem_near near, void *dev_out, void *stream);
 
 /* ---- request server ---------------------------------------------------- */
-/* Size the server before first use: arena_bytes of device memory (and the
- * same amount of pinned host staging) hold the batches in flight;
+/* Size the request server (Section 4's block threads are replaced by it):
+ * arena_bytes of device memory (and the same amount of pinned host staging),
+ * split into 8 batch slots, hold the batches in flight, so a batch admits
+ * requests while their inputs, outputs and tables fit one slot (admission by
+ * memory; a single request larger than a slot fails with BEM_E_OOM);
  * max_batch_requests bounds how many requests one fused launch takes.
- * BEM_E_BUSY once the server is running. */
+ * Defaults: 1 GiB, 16384.  arena_bytes >= 4 MiB, else BEM_E_ARG.  A running
+ * server is drained and restarted with the new sizes at the next submission;
+ * it must be idle (no request pending or in flight, no borrowed result
+ * outstanding), else BEM_E_BUSY and nothing changes.  A submission racing
+ * with the drain fails with BEM_E_BUSY. */
 int bem_server_config(size_t arena_bytes, int max_batch_requests);
 
 typedef struct {

@@ -269,7 +269,7 @@ def eval_entries_async(mesh: Mesh, op, space, k, rows, cols, out, prec=FP32, nea
     return out
 
 
-def server_config(arena_bytes: int, max_batch_requests: int = 8192):
+def server_config(arena_bytes: int, max_batch_requests: int = 16384):
     _check(lib().bem_server_config(int(arena_bytes), int(max_batch_requests)))
 
 

@@ -230,6 +230,7 @@ public:
     {
         {
             std::lock_guard<std::mutex> g(mu);
+            if (stop) return fail(BEM_E_BUSY, "server is being reconfigured");
             if (!started) {
                 int rc = start();
                 if (rc != BEM_OK) return rc;
@@ -572,6 +573,43 @@ public:
         }
     }
 
+    // New arena size and batch bound.  A running server is drained first: it
+    // must be idle (nothing pending or in flight, no result still lent); its
+    // threads, streams and arena are released and the next submission starts
+    // it again with the new sizes.
+    int reconfigure(size_t arena, int mb)
+    {
+        bool running;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            running = started;
+            if (running) {
+                bool busy = !pending.empty() || !inflight.empty();
+                for (int i = 0; i < nslots; ++i) busy = busy || slot_busy[i];
+                if (busy) return fail(BEM_E_BUSY, "server has requests in flight or results still lent");
+                stop = true;
+            }
+        }
+        if (running) {
+            cv.notify_all();
+            cvc.notify_all();
+            for (std::thread &t : threads) t.join();
+            threads.clear();
+            for (int i = 0; i < nstreams; ++i)
+                if (streams[i]) (void)hipStreamDestroy(streams[i]);
+            for (int i = 0; i < kMaxSlots; ++i) streams[i] = nullptr;
+            (void)hipFree(d_arena);
+            (void)hipHostFree(h_stage);
+            d_arena = h_stage = h_stage_dev = nullptr;
+        }
+        std::lock_guard<std::mutex> g(mu);
+        started = false;
+        stop = false;
+        arena_bytes = arena;
+        max_batch = mb;
+        return BEM_OK;
+    }
+
     void kernel_stats(bem_kernel_stats_t *out, int max, int *count, int reset)
     {
         std::lock_guard<std::mutex> g(stat_mu);
@@ -651,14 +689,9 @@ Server &server()
 
 int server_configure(size_t arena_bytes, int max_batch)
 {
-    Server &s = server();
-    std::lock_guard<std::mutex> g(s.mu);
-    if (s.started) return fail(BEM_E_BUSY, "server already running");
     if (arena_bytes < (size_t(4) << 20)) return fail(BEM_E_ARG, "arena must be at least 4 MiB");
     if (max_batch < 1) return fail(BEM_E_ARG, "max_batch_requests must be >= 1");
-    s.arena_bytes = arena_bytes;
-    s.max_batch = max_batch;
-    return BEM_OK;
+    return server().reconfigure(arena_bytes, max_batch);
 }
 
 int server_submit(Request *r) { return server().submit_many(&r, 1); }

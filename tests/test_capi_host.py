@@ -112,3 +112,13 @@ def test_device_rule_table_matches_oracle():
                    [(a1, a1, w1), (1 - 2 * a1, a1, w1), (a1, 1 - 2 * a1, w1),
                     (a2, a2, w2), (1 - 2 * a2, a2, w2), (a2, 1 - 2 * a2, w2)]])
     assert np.allclose(np.array(pts), np.array(mine), rtol=0, atol=2e-15)
+
+
+def test_server_config_rejects_small_arena():
+    """Argument checks run before the device is touched."""
+    with pytest.raises(bem.BemError) as ei:
+        bem.server_config(1 << 20)
+    assert ei.value.code == bem.E_ARG
+    with pytest.raises(bem.BemError) as ei:
+        bem.server_config(64 << 20, 0)
+    assert ei.value.code == bem.E_ARG
