@@ -27,14 +27,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic flops per kernel evaluation (one pair of quadrature points):
-# d = x - y (3), r^2 (1 mul + 2 fma = 5), 1/r (1), weighted accumulation
-# (fma = 2) -> 11; double layer + r^-3 (2 mul) -> 13; P1 adds the three
-# basis-weighted accumulations, 3 fma per point of the outer loop, i.e.
-# 1 flop per evaluation with 6 points -> 12 / 14.  Helmholtz adds r (1),
-# the FP64 phase (mul, round, subtract: 3), sin and cos (2) and the complex
-# accumulation (1 mul + 2 fma: 5) -> 21 / 27 (P0), +1 for P1.
-FLOPS_PER_EVAL = {(0, 0): 11, (1, 0): 13, (2, 0): 21, (3, 0): 27,
+# Algorithmic flops per kernel evaluation (one pair of quadrature points),
+# the per-unit figures of the hot-path measurement plan: FMA = 2, add/mul = 1,
+# rsq/sin/cos = 1 each.  Laplace single layer 11 (P0) / 15 (P1, three trial
+# accumulators), double layer 19 / 23 (the (x-y).n_y product per pair),
+# Helmholtz single layer 20 / 28, double layer 33 / 41.
+FLOPS_PER_EVAL = {(0, 0): 11, (1, 0): 19, (2, 0): 20, (3, 0): 33,
+                  (0, 1): 15, (1, 1): 23, (2, 1): 28, (3, 1): 41}
+# What the kernels execute per evaluation after hoisting the (x-y).n_y
+# product (constant over a trial triangle's points) and the basis weights
+# out of the inner loop: reported beside the algorithmic rate.
+FLOPS_EXECUTED = {(0, 0): 11, (1, 0): 13, (2, 0): 21, (3, 0): 27,
                   (0, 1): 12, (1, 1): 14, (2, 1): 22, (3, 1): 28}
 # Non-packed FP32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9
@@ -187,6 +190,9 @@ def roofline(kstats):
             "kernel": name, "launches": dom["launches"], "mean_launch_us": round(mean_s * 1e6, 2),
             "mean_launch_us_hip_events": round(mean_ev * 1e6, 2),
             "flops_per_launch": per_launch, "flops_per_eval": FLOPS_PER_EVAL[(dom["op"], dom["space"])],
+            "executed_flops_per_eval": FLOPS_EXECUTED[(dom["op"], dom["space"])],
+            "executed_tflops": round(dom["pair_evals"] * FLOPS_EXECUTED[(dom["op"], dom["space"])] /
+                                     dom["launches"] / mean_s / 1e12, 3),
             "frac_of_packed_fp32_peak": round(achieved * 1e12 / PEAK_FP32_PACKED, 4)}
     return roof, dom
 

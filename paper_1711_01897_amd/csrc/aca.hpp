@@ -78,8 +78,9 @@ struct AcaCore {
         phase = (m > 0 && n > 0 && limit > 0) ? NEED_ROW : DONE;
     }
 
-    // Raw block row i (length n).
-    void consume_row(const T *row)
+    // Raw block row i (length n), FP32 or FP64 entries (widened on the copy).
+    template <typename In>
+    void consume_row(const In *row)
     {
         v.assign(row, row + n);
         for (int l = 0; l < k; ++l) aca_axpy(v.data(), &V[(size_t)l * n], U[(size_t)l * m + i], n);
@@ -110,13 +111,14 @@ struct AcaCore {
             return;
         }
         j = jm;
-        const T piv = v[j];
-        for (int64_t c = 0; c < n; ++c) v[c] = v[c] / piv;
+        const T f = T(1.0) / v[j];
+        for (int64_t c = 0; c < n; ++c) v[c] = v[c] * f;
         phase = NEED_COL;
     }
 
-    // Raw block column j (length m).
-    void consume_col(const T *col)
+    // Raw block column j (length m), FP32 or FP64 entries.
+    template <typename In>
+    void consume_col(const In *col)
     {
         u.assign(col, col + m);
         for (int l = 0; l < k; ++l) aca_axpy(u.data(), &U[(size_t)l * m], V[(size_t)l * n + j], m);

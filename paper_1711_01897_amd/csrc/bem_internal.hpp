@@ -66,11 +66,11 @@ struct ReqDev {
     double kk;                 // k / (2 pi): phase in turns per unit length
 };
 
-struct EntryBlock {  // one workgroup of entry work
+struct EntryBlock {  // one workgroup of entry work (32 bytes, read with one scalar load)
     int32_t req;
     int32_t fixed;   // fixed position
-    int32_t chunk;   // lane-side chunk
-    int32_t pad;
+    int32_t s0, s1;  // P1: the fixed star, entries [s0, s1) of fstar; P0: s0 = the fixed triangle
+    int4 chunk;      // lane side: first lane, lanes, first dof, dofs
 };
 
 // Kernel variant: one compiled instantiation of the entry kernel (it serves
@@ -164,6 +164,7 @@ struct LaneSet {
 struct LaneRef {                      // device pointers of a resident LaneSet
     const int32_t *lane = nullptr, *seg_ptr = nullptr, *seg = nullptr;
     const int4 *chunk = nullptr;
+    const int32_t *chunk_host = nullptr;   // host copy of the chunk table (block records carry it)
     int64_t ndof = 0, nlane = 0, nseg = 0, nchunk = 0, ndistinct = 0;
 };
 
@@ -236,6 +237,7 @@ int server_submit(Request *r);
 int server_submit_many(Request *const *rs, size_t n);
 int server_wait(Request *r, double timeout_s);
 void server_release(Request *r);           // return a borrowed result
+void server_release_batch(void *batch, int n);   // return n borrowed results of one batch (Request::batch)
 int server_ensure_started();
 bool server_running();
 

@@ -443,20 +443,21 @@ __device__ __forceinline__ void pair_p1_f64(const double *T, const double *S, in
 // ---------------------------------------------------------------------------
 // Kernels.
 //
-// Workgroup B covers chunk B.chunk of the lane side against fixed position
-// B.fixed; thread t takes lane t of the chunk.  Threads past the end of the
+// Workgroup B covers the lane chunk B.chunk against fixed position B.fixed
+// (star entries [B.s0, B.s1), or triangle B.s0 for P0); thread t takes lane
+// t of the chunk.  Threads past the end of the
 // chunk repeat its first lane (valid loads) and store nothing; a wavefront
 // with no valid lane skips the arithmetic.
 
 template <int OP, int Q, bool ROWFIX>
 __device__ __forceinline__ void p0_body_f32(const ReqDev &R, const EntryBlock &B)
 {
-    const int4 ch = R.chunk[B.chunk];   // first lane, lanes, first dof, dofs
+    const int4 ch = B.chunk;   // first lane, lanes, first dof, dofs
     const int t = threadIdx.x;
     if ((t & ~63) >= ch.y) return;
     const bool act = t < ch.y;
     const int li = ch.x + (act ? t : 0);
-    const int tf = R.fix[B.fixed];
+    const int tf = B.s0;
     const int tn = R.lane[li];
     const int test = ROWFIX ? tf : tn, trial = ROWFIX ? tn : tf;
     const bool adj = share_vertex(R.vtx[test], R.vtx[trial]);
@@ -500,12 +501,12 @@ __global__ __launch_bounds__(kBlockLanes) void k_p0_f32(const ReqDev *__restrict
 template <int OP, int Q, bool ROWFIX>
 __device__ __forceinline__ void p0_body_f64(const ReqDev &R, const EntryBlock &B)
 {
-    const int4 ch = R.chunk[B.chunk];
+    const int4 ch = B.chunk;
     const int t = threadIdx.x;
     if ((t & ~63) >= ch.y) return;
     const bool act = t < ch.y;
     const int li = ch.x + (act ? t : 0);
-    const int tf = R.fix[B.fixed];
+    const int tf = B.s0;
     const int tn = R.lane[li];
     const int test = ROWFIX ? tf : tn, trial = ROWFIX ? tn : tf;
     const bool adj = share_vertex(R.vtx[test], R.vtx[trial]);
@@ -570,6 +571,23 @@ __device__ __forceinline__ int stage_star(const ReqDev &R, const R_T *__restrict
     return ns;
 }
 
+// The first kN segments of thread t's first entry (dof ch.z + t of the
+// chunk), loaded ahead of use.
+struct SegPrefetch {
+    static constexpr int kN = 8;
+    int g0 = 0, g1 = 0;
+    int seg[kN];
+    __device__ __forceinline__ void fetch(const ReqDev &R, const int4 &ch, int t)
+    {
+        if (t >= ch.w) return;
+        const int d = ch.z + t;
+        g0 = R.seg_ptr[d];
+        g1 = R.seg_ptr[d + 1];
+#pragma unroll
+        for (int i = 0; i < kN; ++i) seg[i] = g0 + i < g1 ? R.seg[g0 + i] : 0;
+    }
+};
+
 // P1, FP32.  Phase 1: lane triangle against the fixed vertex star; the three
 // compensated partial sums (one per local vertex of the lane triangle) go to
 // LDS.  Phase 2: thread j adds, for dof j of the chunk, the partials its
@@ -578,7 +596,7 @@ template <int OP, int Q, bool ROWFIX>
 __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B, float (*sG)[n32<Q>()], int4 *sV,
                                             int *sL, float4 (*sP)[3])
 {
-    const int4 ch = R.chunk[B.chunk];   // first lane, lanes, first dof, dofs
+    const int4 ch = B.chunk;   // first lane, lanes, first dof, dofs
     const int t = threadIdx.x;
     const bool wact = (t & ~63) < ch.y;   // wave-uniform
     const bool act = t < ch.y;
@@ -588,9 +606,14 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     float L[n32<Q>()];
     load32<Q>(R.g32, tn, L);
     float hr[3] = {0.f, 0.f, 0.f}, lr[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f}, lo[3] = {0.f, 0.f, 0.f};
-    const int s0 = R.fix[B.fixed], s1 = R.fix[B.fixed + 1];
+    const int s0 = B.s0, s1 = B.s1;
+    // phase 2 of this thread's first entry: its segment list, fetched while
+    // phase 1 computes (after the first stage, so the stage barrier does not
+    // wait for it)
+    SegPrefetch pf;
     for (int sb = s0; sb < s1; sb += kStage) {
         const int ns = stage_star<float, n32<Q>()>(R, R.g32, kGeo32Stride, sb, s1, sG, sV, sL);
+        if (sb == s0) pf.fetch(R, ch, t);
         if (!wact) continue;
         for (int s = 0; s < ns; ++s) {
             if (share_vertex(sV[s], vn)) {
@@ -618,13 +641,20 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
 #pragma unroll
         for (int e = 0; e < 3; ++e) sP[t][e] = make_float4(hr[e], lr[e], hi[e], lo[e]);
     }
+    if (s0 == s1) pf.fetch(R, ch, t);
     __syncthreads();
     for (int j = t; j < ch.w; j += kBlockLanes) {
         const int d = ch.z + j;
-        const int g0 = R.seg_ptr[d], g1 = R.seg_ptr[d + 1];
+        int g0, g1;
+        if (j == t) {
+            g0 = pf.g0;
+            g1 = pf.g1;
+        } else {
+            g0 = R.seg_ptr[d];
+            g1 = R.seg_ptr[d + 1];
+        }
         float ar = 0.f, br = 0.f, ai = 0.f, bi = 0.f;
-        for (int g = g0; g < g1; ++g) {
-            const int pk = R.seg[g];
+        auto add = [&](int pk) {
             const float4 v = sP[pk >> 2][pk & 3];
             two_sum_acc(ar, br, v.x);
             br += v.y;
@@ -632,7 +662,15 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
                 two_sum_acc(ai, bi, v.z);
                 bi += v.w;
             }
+        };
+        int g = g0;
+        if (j == t) {
+#pragma unroll
+            for (int i = 0; i < SegPrefetch::kN; ++i)
+                if (g0 + i < g1) add(pf.seg[i]);
+            g = g0 + SegPrefetch::kN;
         }
+        for (; g < g1; ++g) add(R.seg[g]);
         const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)d * R.sl;
         if constexpr (is_cplx<OP>())
             reinterpret_cast<float2 *>(R.out)[o] = make_float2(ar + br, ai + bi);
@@ -666,7 +704,7 @@ template <int OP, int Q, bool ROWFIX>
 __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B, double (*sG)[n64<Q>()], int4 *sV,
                                             int *sL, double2 (*sP)[3])
 {
-    const int4 ch = R.chunk[B.chunk];
+    const int4 ch = B.chunk;
     const int t = threadIdx.x;
     const bool wact = (t & ~63) < ch.y;
     const bool act = t < ch.y;
@@ -676,9 +714,11 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
     double L[n64<Q>()];
     load64<Q>(R.g64, tn, L);
     double ar[3] = {0.0, 0.0, 0.0}, ai[3] = {0.0, 0.0, 0.0};
-    const int s0 = R.fix[B.fixed], s1 = R.fix[B.fixed + 1];
+    const int s0 = B.s0, s1 = B.s1;
+    SegPrefetch pf;
     for (int sb = s0; sb < s1; sb += kStage) {
         const int ns = stage_star<double, n64<Q>()>(R, R.g64, kGeo64Stride, sb, s1, sG, sV, sL);
+        if (sb == s0) pf.fetch(R, ch, t);
         if (!wact) continue;
         for (int s = 0; s < ns; ++s) {
             if (share_vertex(sV[s], vn)) {
@@ -706,17 +746,32 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
 #pragma unroll
         for (int e = 0; e < 3; ++e) sP[t][e] = make_double2(ar[e], ai[e]);
     }
+    if (s0 == s1) pf.fetch(R, ch, t);
     __syncthreads();
     for (int j = t; j < ch.w; j += kBlockLanes) {
         const int d = ch.z + j;
-        const int g0 = R.seg_ptr[d], g1 = R.seg_ptr[d + 1];
+        int g0, g1;
+        if (j == t) {
+            g0 = pf.g0;
+            g1 = pf.g1;
+        } else {
+            g0 = R.seg_ptr[d];
+            g1 = R.seg_ptr[d + 1];
+        }
         double xr = 0.0, xi = 0.0;
-        for (int g = g0; g < g1; ++g) {
-            const int pk = R.seg[g];
+        auto add = [&](int pk) {
             const double2 v = sP[pk >> 2][pk & 3];
             xr += v.x;
             xi += v.y;
+        };
+        int g = g0;
+        if (j == t) {
+#pragma unroll
+            for (int i = 0; i < SegPrefetch::kN; ++i)
+                if (g0 + i < g1) add(pf.seg[i]);
+            g = g0 + SegPrefetch::kN;
         }
+        for (; g < g1; ++g) add(R.seg[g]);
         const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)d * R.sl;
         if constexpr (is_cplx<OP>())
             reinterpret_cast<double2 *>(R.out)[o] = make_double2(xr, xi);

@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <complex>
 #include <deque>
+#include <type_traits>
 #include <thread>
 
 #include "aca.hpp"
@@ -130,11 +131,37 @@ void store_cols<cd>(const std::vector<cd> &src, int k, int64_t len, int64_t cap,
     std::memcpy(dst, src.data(), sizeof(cd) * len * k);
 }
 
+// Feeds a device result (FP32 or FP64 entries, real or complex) to the ACA
+// state machine without an intermediate FP64 copy.
+template <typename T>
+void aca_consume(AcaCore<T> &core, const void *p, int prec)
+{
+    const bool row = core.phase == AcaCore<T>::NEED_ROW;
+    if constexpr (std::is_same<T, double>::value) {
+        if (prec == BEM_FP32) {
+            if (row) core.consume_row(static_cast<const float *>(p));
+            else core.consume_col(static_cast<const float *>(p));
+        } else {
+            if (row) core.consume_row(static_cast<const double *>(p));
+            else core.consume_col(static_cast<const double *>(p));
+        }
+    } else {
+        if (prec == BEM_FP32) {
+            if (row) core.consume_row(static_cast<const std::complex<float> *>(p));
+            else core.consume_col(static_cast<const std::complex<float> *>(p));
+        } else {
+            if (row) core.consume_row(static_cast<const cd *>(p));
+            else core.consume_col(static_cast<const cd *>(p));
+        }
+    }
+}
+
 // Lane sets of several dof lists, expanded on the host (in parallel) and
 // uploaded to the device in one buffer.
 struct ResidentLanes {
     int32_t *dev = nullptr;
     std::vector<LaneRef> refs;
+    std::vector<int32_t> chunk_host;   // chunk tables of all sets, host copies
     ResidentLanes() = default;
     ResidentLanes(const ResidentLanes &) = delete;
     ~ResidentLanes()
@@ -174,6 +201,14 @@ int make_resident(const bem_mesh &m, int space, const std::vector<std::pair<cons
         }
         pos = pad4(pos);
     }
+    std::vector<size_t> ch_at(n);
+    size_t nch = 0;
+    for (size_t i = 0; i < n; ++i) {
+        ch_at[i] = nch;
+        nch += sets[i].chunk.size();
+    }
+    out.chunk_host.resize(std::max<size_t>(nch, 1));
+    for (size_t i = 0; i < n; ++i) std::copy(sets[i].chunk.begin(), sets[i].chunk.end(), out.chunk_host.begin() + ch_at[i]);
     BEM_HIP_TRY(hipMalloc(&out.dev, sizeof(int32_t) * host.size()));
     BEM_HIP_TRY(hipMemcpy(out.dev, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice));
     for (size_t i = 0; i < n; ++i) {
@@ -186,6 +221,7 @@ int make_resident(const bem_mesh &m, int space, const std::vector<std::pair<cons
         r.nchunk = ls.nchunk();
         r.ndistinct = ls.ndistinct;
         r.chunk = ls.chunk.empty() ? nullptr : reinterpret_cast<const int4 *>(base);
+        r.chunk_host = out.chunk_host.data() + ch_at[i];
         base += ls.chunk.size();
         r.lane = ls.lane.empty() ? nullptr : base;
         base += ls.lane.size();
@@ -196,25 +232,43 @@ int make_resident(const bem_mesh &m, int space, const std::vector<std::pair<cons
     return BEM_OK;
 }
 
-// Completion queue of one worker.
+// Completion queue of one worker.  The worker spins briefly before it
+// sleeps, so a completion that arrives within the spin window costs the
+// completion thread no wake-up call.
 struct DoneQueue {
     std::mutex mu;
     std::condition_variable cv;
     std::vector<Request *> q;
+    std::atomic<int> ready{0};
+    bool sleeping = false;   // guarded by mu
+    double spin_s = 0.0;
     static void push(Request **rs, size_t n, void *ctx)
     {
         DoneQueue *d = (DoneQueue *)ctx;
+        bool wake;
         {
             std::lock_guard<std::mutex> g(d->mu);
             d->q.insert(d->q.end(), rs, rs + n);
+            d->ready.store(1, std::memory_order_release);
+            wake = d->sleeping;
         }
-        d->cv.notify_one();
+        if (wake) d->cv.notify_one();
     }
     // Up to `most` finished requests, oldest first.
     void pop_some(std::vector<Request *> &out, size_t most)
     {
+        if (spin_s > 0.0 && !ready.load(std::memory_order_acquire)) {
+            const double t0 = now_seconds();
+            int it = 0;
+            while (!ready.load(std::memory_order_acquire)) {
+                __builtin_ia32_pause();
+                if ((++it & 63) == 0 && now_seconds() - t0 > spin_s) break;
+            }
+        }
         std::unique_lock<std::mutex> lk(mu);
+        sleeping = true;
         cv.wait(lk, [&] { return !q.empty(); });
+        sleeping = false;
         if (q.size() <= most) {
             out.swap(q);
             q.clear();
@@ -222,6 +276,7 @@ struct DoneQueue {
             out.assign(q.begin(), q.begin() + most);
             q.erase(q.begin(), q.begin() + most);
         }
+        ready.store(q.empty() ? 0 : 1, std::memory_order_relaxed);
     }
 };
 
@@ -257,6 +312,7 @@ struct AssemblyCtx {
     double busy = 0.0;
     double qdelay = 0.0, proc = 0.0;   // completion -> pickup, pickup -> resubmit (summed over requests)
     int64_t nproc = 0;
+    double t_conv = 0.0, t_aca = 0.0, t_rel = 0.0, t_prep = 0.0, t_flush = 0.0;   // worker phases (summed)
 
     void set_error(int code, const std::string &msg)
     {
@@ -268,8 +324,24 @@ struct AssemblyCtx {
     }
 };
 
+// Spin window of an idle worker before it sleeps (BEM_WORKER_SPIN_US,
+// microseconds; default 0: sleep at once).
+double worker_spin_seconds()
+{
+    static const double v = [] {
+        const char *e = std::getenv("BEM_WORKER_SPIN_US");
+        return 1e-6 * (e ? std::max(0.0, std::atof(e)) : 0.0);
+    }();
+    return v;
+}
+
+// Per-worker tallies, added to the assembly's totals when the worker ends.
+struct WorkerTally {
+    int64_t aca_entries = 0, dense_entries = 0, requests = 0;
+};
+
 template <typename T>
-int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag)
+int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag, WorkerTally &w)
 {
     bem_hmat::Leaf &L = C.h->leaves[s.leaf];
     Request &r = s.req;
@@ -291,7 +363,7 @@ int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag)
         r.ncols = (int64_t)r.cols.size();
         const int rc = expand_request(r);
         if (rc != BEM_OK) return rc;
-        C.dense_entries.fetch_add(r.entries());
+        w.dense_entries += r.entries();
     } else {
         r.near = BEM_NEAR_ERROR;
         const Block &bk = C.h->part.blocks[s.leaf];
@@ -299,9 +371,9 @@ int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag)
             expand_single_fixed(r, L.rows[s.core.i], 1, &(*C.lanes)[bk.sigma]);
         else
             expand_single_fixed(r, L.cols[s.core.j], 0, &(*C.lanes)[bk.tau]);
-        C.aca_entries.fetch_add(r.entries());
+        w.aca_entries += r.entries();
     }
-    C.requests.fetch_add(1);
+    w.requests += 1;
     return BEM_OK;
 }
 
@@ -309,9 +381,19 @@ template <typename T>
 void worker(AssemblyCtx &C, int per_worker)
 {
     DoneQueue dq;
+    dq.spin_s = worker_spin_seconds();
+    WorkerTally tally;
     std::vector<Slot<T>> slots(per_worker);
     std::vector<Request *> submit, done;
     int active = 0;
+    // borrowed results go back once per run of requests from the same batch
+    void *rel_batch = nullptr;
+    int rel_n = 0;
+    auto release_run = [&]() {
+        server_release_batch(rel_batch, rel_n);
+        rel_batch = nullptr;
+        rel_n = 0;
+    };
     bool exhausted = false;
     auto start_job = [&](int64_t si) -> bool {
         Slot<T> &s = slots[si];
@@ -331,7 +413,7 @@ void worker(AssemblyCtx &C, int per_worker)
             s.core.init((int64_t)L.rows.size(), (int64_t)L.cols.size(), C.tol, C.max_rank,
                         default_zero_abs(*C.mesh, C.op, C.space, C.k, C.prec, support_distance(a, b)));
         }
-        const int rc = prepare_slot(C, s, dq, si);
+        const int rc = prepare_slot(C, s, dq, si, tally);
         if (rc != BEM_OK) {
             C.set_error(rc, std::string("request: ") + bem_last_error());
             return false;
@@ -355,6 +437,7 @@ void worker(AssemblyCtx &C, int per_worker)
         submit.clear();
     };
     double busy = 0.0, qd = 0.0, pr = 0.0;
+    double tc = 0.0, ta = 0.0, tr = 0.0, tp = 0.0, tf = 0.0;
     int64_t np = 0;
     double tb = now_seconds();
     for (int64_t si = 0; si < per_worker; ++si)
@@ -376,18 +459,18 @@ void worker(AssemblyCtx &C, int per_worker)
             } else {
                 bem_hmat::Leaf &L = C.h->leaves[s.leaf];
                 const int64_t cnt = r->entries();
-                s.buf.resize(cnt);
-                to_scalar<T>(r->result, C.prec, cnt, s.buf.data());
-                server_release(r);
                 if (!s.adm) {
+                    const double c0 = now_seconds();
+                    s.buf.resize(cnt);
+                    to_scalar<T>(r->result, C.prec, cnt, s.buf.data());
+                    tc += now_seconds() - c0;
                     L.D.resize((size_t)cnt * (sizeof(T) / sizeof(double)));
                     std::memcpy(L.D.data(), s.buf.data(), sizeof(T) * cnt);
                     finished = true;
                 } else {
-                    if (s.core.phase == AcaCore<T>::NEED_ROW)
-                        s.core.consume_row(s.buf.data());
-                    else
-                        s.core.consume_col(s.buf.data());
+                    const double a0 = now_seconds();
+                    aca_consume(s.core, r->result, C.prec);
+                    ta += now_seconds() - a0;
                     if (s.core.phase == AcaCore<T>::DONE) {
                         L.rank = s.core.k;
                         const size_t f = sizeof(T) / sizeof(double);
@@ -399,14 +482,26 @@ void worker(AssemblyCtx &C, int per_worker)
                     }
                 }
             }
-            if (r->batch) server_release(r);
+            if (r->batch) {
+                const double c1 = now_seconds();
+                if (r->batch != rel_batch) {
+                    release_run();
+                    rel_batch = r->batch;
+                }
+                ++rel_n;
+                r->batch = nullptr;
+                r->result = nullptr;
+                tr += now_seconds() - c1;
+            }
             if (finished || C.error.load()) {
                 s.busy = false;
                 --active;
                 if (!C.error.load()) start_job(r->tag);
                 continue;
             }
-            const int rc = prepare_slot(C, s, dq, r->tag);
+            const double p0 = now_seconds();
+            const int rc = prepare_slot(C, s, dq, r->tag, tally);
+            tp += now_seconds() - p0;
             if (rc != BEM_OK) {
                 C.set_error(rc, std::string("request: ") + bem_last_error());
                 s.busy = false;
@@ -415,17 +510,29 @@ void worker(AssemblyCtx &C, int per_worker)
             }
             submit.push_back(&s.req);
         }
+        release_run();
         const size_t nd = done.size();
         done.clear();
+        const double f0 = now_seconds();
         flush();
+        tf += now_seconds() - f0;
         pr += (now_seconds() - tb) * (double)nd;
     }
     busy += now_seconds() - tb;
+    release_run();
+    C.aca_entries.fetch_add(tally.aca_entries);
+    C.dense_entries.fetch_add(tally.dense_entries);
+    C.requests.fetch_add(tally.requests);
     std::lock_guard<std::mutex> g(C.busy_mu);
     C.busy += busy;
     C.qdelay += qd;
     C.proc += pr;
     C.nproc += np;
+    C.t_conv += tc;
+    C.t_aca += ta;
+    C.t_rel += tr;
+    C.t_prep += tp;
+    C.t_flush += tf;
 }
 
 template <typename T>
@@ -482,12 +589,7 @@ int aca_block_impl(bem_mesh *mesh, int op, int space, double k, const int32_t *r
         rc = server_wait(&r, -1.0);
         if (rc != BEM_OK) return rc == BEM_E_NEARFIELD ? fail(rc, "block contains a vertex-sharing pair") : rc;
         count += r.entries();
-        buf.resize(r.entries());
-        to_scalar<T>(out.data(), prec, r.entries(), buf.data());
-        if (core.phase == AcaCore<T>::NEED_ROW)
-            core.consume_row(buf.data());
-        else
-            core.consume_col(buf.data());
+        aca_consume(core, out.data(), prec);
     }
     store_cols<T>(core.U, core.k, m, p->max_rank, U);
     store_cols<T>(core.V, core.k, n, p->max_rank, V);
@@ -664,10 +766,15 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
     s.setup_seconds = t_setup - t_part;
     s.aca_seconds = t_aca - t_setup;
     s.worker_busy_seconds = C.busy;
-    if (std::getenv("BEM_DEBUG_TIMING"))
+    if (std::getenv("BEM_DEBUG_TIMING")) {
+        const double np = (double)std::max<int64_t>(1, C.nproc);
         fprintf(stderr, "[bem] assembly %.3fs: partition %.3f setup %.3f aca %.3f; %lld completions, mean pickup delay %.1f us, mean batch-processing span %.1f us\n",
                 s.seconds, s.partition_seconds, s.setup_seconds, s.aca_seconds, (long long)C.nproc,
-                1e6 * C.qdelay / std::max<int64_t>(1, C.nproc), 1e6 * C.proc / std::max<int64_t>(1, C.nproc));
+                1e6 * C.qdelay / np, 1e6 * C.proc / np);
+        fprintf(stderr, "[bem] worker us/request: busy %.3f convert %.3f aca %.3f release %.3f prepare %.3f submit %.3f\n",
+                1e6 * C.busy / np, 1e6 * C.t_conv / np, 1e6 * C.t_aca / np, 1e6 * C.t_rel / np, 1e6 * C.t_prep / np,
+                1e6 * C.t_flush / np);
+    }
     *out = h;
     return BEM_OK;
 }

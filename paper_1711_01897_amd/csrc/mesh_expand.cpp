@@ -227,7 +227,7 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
 size_t request_bytes(const Request &r)
 {
     // descriptor, inputs, status, outputs, block table, launch-timing records
-    return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * (sizeof(EntryBlock) + 16) + 64;
+    return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * (sizeof(EntryBlock) + 16) + 256;
 }
 
 size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d)
@@ -287,9 +287,26 @@ void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t 
 
 int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
 {
+    const int32_t *ch = r.ext ? r.ext->chunk_host : r.own.chunk.data();
     int64_t n = 0;
-    for (int32_t f = 0; f < (int32_t)r.nfix; ++f)
-        for (int32_t c = 0; c < (int32_t)r.nchunk; ++c) out[n++] = EntryBlock{ri, f, c, 0};
+    for (int32_t f = 0; f < (int32_t)r.nfix; ++f) {
+        int32_t s0, s1;
+        if (r.space == BEM_P0) {
+            s0 = r.fix[f];
+            s1 = s0 + 1;
+        } else {
+            s0 = r.fix[f];
+            s1 = r.fix[f + 1];
+        }
+        for (int32_t c = 0; c < (int32_t)r.nchunk; ++c) {
+            EntryBlock &b = out[n++];
+            b.req = ri;
+            b.fixed = f;
+            b.s0 = s0;
+            b.s1 = s1;
+            b.chunk = make_int4(ch[4 * c], ch[4 * c + 1], ch[4 * c + 2], ch[4 * c + 3]);
+        }
+    }
     return n;
 }
 

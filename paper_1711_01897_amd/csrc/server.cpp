@@ -209,17 +209,33 @@ public:
             r->t_done = t;
             r->status = st[i];
             r->done = true;
-            r->mesh->inflight.fetch_sub(1);
+            dec_inflight(r->mesh);
             const std::pair<void *, void *> key{(void *)r->on_done, r->cb_ctx};
             size_t g = 0;
             while (g < groups.size() && groups[g].first != key) ++g;
             if (g == groups.size()) groups.push_back({key, {}});
             groups[g].second.push_back(r);
         }
+        dec_inflight(nullptr);
         for (auto &g : groups) {
             auto cb = reinterpret_cast<void (*)(Request **, size_t, void *)>(g.first.first);
             cb(g.second.data(), g.second.size(), g.first.second);
         }
+    }
+
+    // Mesh in-flight counts drop once per run of requests on the same mesh
+    // (nullptr flushes the run); completion threads keep their own run.
+    void dec_inflight(bem_mesh *m)
+    {
+        thread_local bem_mesh *cur = nullptr;
+        thread_local int64_t cnt = 0;
+        if (m == cur) {
+            ++cnt;
+            return;
+        }
+        if (cur && cnt) cur->inflight.fetch_sub(cnt);
+        cur = m;
+        cnt = m ? 1 : 0;
     }
 
     // batch-level slack: alignment of sections and tables
@@ -238,15 +254,23 @@ public:
             for (size_t i = 0; i < n; ++i)
                 if (!fits(rs[i])) return fail(BEM_E_OOM, "request larger than a server batch slot; raise the arena size");
             const double t = now_seconds();
+            bem_mesh *cur = nullptr;
+            int64_t cnt = 0;
             for (size_t i = 0; i < n; ++i) {
                 Request *r = rs[i];
                 r->t_submit = t;
                 r->done = false;
                 r->result = nullptr;
                 r->batch = nullptr;
-                r->mesh->inflight.fetch_add(1);
+                if (r->mesh != cur) {
+                    if (cur) cur->inflight.fetch_add(cnt);
+                    cur = r->mesh;
+                    cnt = 0;
+                }
+                ++cnt;
                 pending.push_back(r);
             }
+            if (cur) cur->inflight.fetch_add(cnt);
         }
         cv.notify_one();
         return BEM_OK;
@@ -353,7 +377,7 @@ public:
         size_t off = align256(sizeof(ReqDev) * n);
         for (Launch &L : launches) {
             L.off_tab = off;
-            off = align256(off + 16 * (size_t)L.count);
+            off = align256(off + sizeof(EntryBlock) * (size_t)L.count);
         }
         const size_t off_in = off;
         for (int i = 0; i < n; ++i) off += take[i]->in_bytes;
@@ -382,7 +406,7 @@ public:
         }
 
         // staging writes
-        static_assert(sizeof(EntryBlock) == 16, "block records are 16 bytes");
+        static_assert(sizeof(EntryBlock) == 32, "block records are 32 bytes");
         for (const Launch &L : launches) {
             EntryBlock *p = reinterpret_cast<EntryBlock *>(hb + L.off_tab);
             int64_t k = 0;
@@ -433,9 +457,9 @@ public:
         return b;
     }
 
-    void release_batch(Batch *b)
+    void release_batch(Batch *b, int n = 1)
     {
-        if (b->refs.fetch_sub(1) != 1) return;
+        if (b->refs.fetch_sub(n) != n) return;
         {
             std::lock_guard<std::mutex> g(ev_mu);
             for (hipEvent_t ev : b->ev) event_pool.push_back(ev);
@@ -716,6 +740,11 @@ void server_release(Request *r)
     r->batch = nullptr;
     r->result = nullptr;
     server().release_batch(b);
+}
+
+void server_release_batch(void *batch, int n)
+{
+    if (batch && n > 0) server().release_batch(static_cast<Batch *>(batch), n);
 }
 
 int server_stats(bem_server_stats_t *s, int reset)
