@@ -48,8 +48,8 @@ struct ReqDev {
     const float *g32;
     const double *g64;
     const int4 *vtx;           // vertex ids per triangle (x, y, z; w unused)
-    const int32_t *fix;        // P0: triangle per fixed position; P1: star ranges (nfix + 1)
-    const int32_t *fstar;      // P1: packed (triangle << 2 | local vertex) of fixed stars
+    const int32_t *fstar;      // P1: the mesh star table (packed triangle << 2 | local vertex); block
+                               // records name the fixed dof's entries [s0, s1)
     const int32_t *lane;       // triangle per lane position
     const int4 *chunk;         // per chunk: first lane, lanes, first dof, dofs
     const int32_t *seg_ptr;    // P1: per lane-side dof, range into seg
@@ -66,11 +66,15 @@ struct ReqDev {
     double kk;                 // k / (2 pi): phase in turns per unit length
 };
 
-struct EntryBlock {  // one workgroup of entry work (32 bytes, read with one scalar load)
+struct EntryBlock {  // one workgroup of entry work (64 bytes, read with one scalar load)
     int32_t req;
-    int32_t fixed;   // fixed position
-    int32_t s0, s1;  // P1: the fixed star, entries [s0, s1) of fstar; P0: s0 = the fixed triangle
-    int4 chunk;      // lane side: first lane, lanes, first dof, dofs
+    int32_t fixed;         // fixed position
+    int32_t s0, s1;        // P1: the fixed dof's star, entries [s0, s1) of the mesh star table; P0: s0 = the fixed triangle
+    int4 chunk;            // lane side: first lane, lanes, first dof, dofs
+    const float *lgeo;     // lane records gathered per lane position (or null: gather through R.lane)
+    const int4 *lmeta;     // their vertex ids
+    const float *sgeo;     // P1: the mesh's star records (FP32), indexed by star entry
+    const int4 *smeta;     // their vertex ids, w = local vertex of the star's dof
 };
 
 // Kernel variant: one compiled instantiation of the entry kernel (it serves
@@ -97,6 +101,10 @@ hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock
                           unsigned long long *tclock = nullptr, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, int q, float *g32, double *g64,
                            int4 *vtx, int32_t *bad, hipStream_t s);
+// geo[i] = FP32 record of triangle index[i] >> shift, meta[i] = its vertex
+// ids (w = index[i] & 3 when shift == 2, else 0); i < n.
+hipError_t launch_gather(const float *g32, const int4 *vtx, const int32_t *index, int shift, int64_t n, float *geo,
+                         int4 *meta, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Errors
@@ -128,6 +136,9 @@ struct bem_mesh {
     float *d_g32 = nullptr;
     double *d_g64 = nullptr;
     int4 *d_vtx = nullptr;
+    int32_t *d_star = nullptr;   // star table on the device (packed triangle << 2 | local vertex)
+    float *d_sgeo = nullptr;     // FP32 record per star entry
+    int4 *d_smeta = nullptr;     // vertex ids per star entry, w = local vertex
     size_t dev_bytes = 0;
     std::atomic<int64_t> inflight{0};
 
@@ -165,6 +176,8 @@ struct LaneRef {                      // device pointers of a resident LaneSet
     const int32_t *lane = nullptr, *seg_ptr = nullptr, *seg = nullptr;
     const int4 *chunk = nullptr;
     const int32_t *chunk_host = nullptr;   // host copy of the chunk table (block records carry it)
+    const float *geo = nullptr;            // FP32 records gathered per lane position
+    const int4 *meta = nullptr;            // their vertex ids
     int64_t ndof = 0, nlane = 0, nseg = 0, nchunk = 0, ndistinct = 0;
 };
 
@@ -185,10 +198,11 @@ struct Request {
 
     // expansion
     int rowfix = 1;
-    std::vector<int32_t> fix, fstar;   // fixed side
+    std::vector<int32_t> fix;   // fixed side: P0 triangles; P1 star ranges [s0, s1) per fixed dof (2 each)
     LaneSet own;                       // lane side, when not external
     const LaneRef *ext = nullptr;      // device-resident lane side
     int64_t nfix = 0, nlane = 0, nchunk = 0, ndistinct = 0;
+    int64_t nstar = 0;          // P1: triangles over the fixed dofs' stars
     size_t elem_bytes = 0;
     size_t in_bytes = 0, out_bytes = 0;
     int64_t evals = 0;          // Q^2 x distinct (fixed, lane) triangle pairs, vertex-sharing pairs included

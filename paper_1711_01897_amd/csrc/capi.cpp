@@ -209,10 +209,10 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
                 for (int32_t b : r.cols)
                     if (mesh->adjacent(a, b)) return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
         } else {
-            for (size_t f = 0; f + 1 < r.fix.size(); ++f)
-                for (int32_t s = r.fix[f]; s < r.fix[f + 1]; ++s)
+            for (size_t f = 0; 2 * f + 1 < r.fix.size(); ++f)
+                for (int32_t s = r.fix[2 * f]; s < r.fix[2 * f + 1]; ++s)
                     for (int32_t t : r.own.lane)
-                        if (mesh->adjacent(r.fstar[s] >> 2, t))
+                        if (mesh->adjacent(mesh->star[s] >> 2, t))
                             return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
         }
     }

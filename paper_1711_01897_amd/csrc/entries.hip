@@ -588,6 +588,27 @@ struct SegPrefetch {
     }
 };
 
+// Stages up to kStage star entries [sb, ...) of the mesh star table into LDS
+// from the gathered star records of block B (FP32).
+template <int W>
+__device__ __forceinline__ int stage_star_tab(const EntryBlock &B, int sb, int s1, float (*sG)[W], int4 *sV, int *sL)
+{
+    const int t = threadIdx.x;
+    const int ns = min(kStage, s1 - sb);
+    __syncthreads();   // the previous stage has been read
+    if (t < ns * W) {
+        const int k = t / W, w = t - k * W;
+        sG[k][w] = B.sgeo[(size_t)(sb + k) * kGeo32Stride + w];
+    }
+    if (t < ns) {
+        const int4 m = B.smeta[sb + t];
+        sV[t] = m;
+        sL[t] = m.w;
+    }
+    __syncthreads();
+    return ns;
+}
+
 // P1, FP32.  Phase 1: lane triangle against the fixed vertex star; the three
 // compensated partial sums (one per local vertex of the lane triangle) go to
 // LDS.  Phase 2: thread j adds, for dof j of the chunk, the partials its
@@ -601,10 +622,17 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     const bool wact = (t & ~63) < ch.y;   // wave-uniform
     const bool act = t < ch.y;
     const int li = ch.x + (act ? t : 0);
-    const int tn = ch.y > 0 ? R.lane[li] : 0;   // a chunk of dofs without triangles has no lanes
-    const int4 vn = R.vtx[tn];
     float L[n32<Q>()];
-    load32<Q>(R.g32, tn, L);
+    int4 vn;
+    if (B.lgeo && ch.y > 0) {
+        // lane records gathered per lane position
+        vn = B.lmeta[li];
+        load32<Q>(B.lgeo, li, L);
+    } else {
+        const int tn = ch.y > 0 ? R.lane[li] : 0;   // a chunk of dofs without triangles has no lanes
+        vn = R.vtx[tn];
+        load32<Q>(R.g32, tn, L);
+    }
     float hr[3] = {0.f, 0.f, 0.f}, lr[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f}, lo[3] = {0.f, 0.f, 0.f};
     const int s0 = B.s0, s1 = B.s1;
     // phase 2 of this thread's first entry: its segment list, fetched while
@@ -612,7 +640,7 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     // wait for it)
     SegPrefetch pf;
     for (int sb = s0; sb < s1; sb += kStage) {
-        const int ns = stage_star<float, n32<Q>()>(R, R.g32, kGeo32Stride, sb, s1, sG, sV, sL);
+        const int ns = stage_star_tab<n32<Q>()>(B, sb, s1, sG, sV, sL);
         if (sb == s0) pf.fetch(R, ch, t);
         if (!wact) continue;
         for (int s = 0; s < ns; ++s) {

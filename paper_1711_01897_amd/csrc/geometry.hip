@@ -55,6 +55,39 @@ __global__ __launch_bounds__(256) void k_geometry(const double *__restrict__ xyz
     vtx[t] = make_int4(i0, i1, i2, 0);
 }
 
+// Gathered copies of triangle records: record i of the copy is the FP32
+// record (kGeo32Stride words) of triangle index[i] >> shift, and meta[i] its
+// vertex ids with w = index[i] & 3 when shift == 2 (the local vertex of a
+// packed star entry), else 0.  One thread per word.
+__global__ __launch_bounds__(256) void k_gather(const float *__restrict__ g32, const int4 *__restrict__ vtx,
+                                                const int32_t *__restrict__ index, int shift, int64_t n,
+                                                float *__restrict__ geo, int4 *__restrict__ meta)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n * kGeo32Stride) return;
+    const int64_t i = j / kGeo32Stride;
+    const int w = (int)(j - i * kGeo32Stride);
+    const int32_t pk = index[i];
+    const int32_t t = pk >> shift;
+    geo[j] = g32[(int64_t)t * kGeo32Stride + w];
+    if (w == 0) {
+        int4 v = vtx[t];
+        v.w = shift == 2 ? (pk & 3) : 0;
+        meta[i] = v;
+    }
+}
+
+hipError_t launch_gather(const float *g32, const int4 *vtx, const int32_t *index, int shift, int64_t n, float *geo,
+                         int4 *meta, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t words = n * kGeo32Stride;
+    const int64_t grid = (words + 255) / 256;
+    if (grid > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)grid), dim3(256), 0, s, g32, vtx, index, shift, n, geo, meta);
+    return hipGetLastError();
+}
+
 hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, int q, float *g32, double *g64,
                            int4 *vtx, int32_t *bad, hipStream_t s)
 {

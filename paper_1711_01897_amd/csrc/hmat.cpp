@@ -160,6 +160,8 @@ void aca_consume(AcaCore<T> &core, const void *p, int prec)
 // uploaded to the device in one buffer.
 struct ResidentLanes {
     int32_t *dev = nullptr;
+    float *geo = nullptr;              // FP32 records gathered per lane position, all sets
+    int4 *meta = nullptr;              // their vertex ids
     std::vector<LaneRef> refs;
     std::vector<int32_t> chunk_host;   // chunk tables of all sets, host copies
     ResidentLanes() = default;
@@ -167,6 +169,8 @@ struct ResidentLanes {
     ~ResidentLanes()
     {
         if (dev) (void)hipFree(dev);
+        if (geo) (void)hipFree(geo);
+        if (meta) (void)hipFree(meta);
     }
 };
 
@@ -211,6 +215,29 @@ int make_resident(const bem_mesh &m, int space, const std::vector<std::pair<cons
     for (size_t i = 0; i < n; ++i) std::copy(sets[i].chunk.begin(), sets[i].chunk.end(), out.chunk_host.begin() + ch_at[i]);
     BEM_HIP_TRY(hipMalloc(&out.dev, sizeof(int32_t) * host.size()));
     BEM_HIP_TRY(hipMemcpy(out.dev, host.data(), sizeof(int32_t) * host.size(), hipMemcpyHostToDevice));
+    // lane records gathered once, so the entry kernels read a lane's
+    // geometry without going through its triangle index
+    std::vector<size_t> lane_at(n);
+    size_t nl = 0;
+    for (size_t i = 0; i < n; ++i) {
+        lane_at[i] = nl;
+        nl += sets[i].lane.size();
+    }
+    if (nl > 0) {
+        std::vector<int32_t> idx(nl);
+        for (size_t i = 0; i < n; ++i) std::copy(sets[i].lane.begin(), sets[i].lane.end(), idx.begin() + lane_at[i]);
+        int32_t *d_idx = nullptr;
+        BEM_HIP_TRY(hipMalloc(&d_idx, sizeof(int32_t) * nl));
+        hipError_t e = hipMemcpy(d_idx, idx.data(), sizeof(int32_t) * nl, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&out.geo, sizeof(float) * kGeo32Stride * nl);
+        if (e == hipSuccess) e = hipMalloc(&out.meta, sizeof(int4) * nl);
+        if (e == hipSuccess) e = launch_gather(m.d_g32, m.d_vtx, d_idx, 0, (int64_t)nl, out.geo, out.meta, 0);
+        if (e == hipSuccess) e = hipStreamSynchronize(0);
+        (void)hipFree(d_idx);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? BEM_E_OOM : BEM_E_DEVICE,
+                        std::string("lane records: ") + hipGetErrorString(e));
+    }
     for (size_t i = 0; i < n; ++i) {
         const LaneSet &ls = sets[i];
         LaneRef &r = out.refs[i];
@@ -222,6 +249,9 @@ int make_resident(const bem_mesh &m, int space, const std::vector<std::pair<cons
         r.ndistinct = ls.ndistinct;
         r.chunk = ls.chunk.empty() ? nullptr : reinterpret_cast<const int4 *>(base);
         r.chunk_host = out.chunk_host.data() + ch_at[i];
+        const bool has = out.geo && !ls.lane.empty();
+        r.geo = has ? out.geo + kGeo32Stride * lane_at[i] : nullptr;
+        r.meta = has ? out.meta + lane_at[i] : nullptr;
         base += ls.chunk.size();
         r.lane = ls.lane.empty() ? nullptr : base;
         base += ls.lane.size();

@@ -81,16 +81,17 @@ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 void expand_fixed(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, Request &r)
 {
     r.fix.clear();
-    r.fstar.clear();
+    r.nstar = 0;
     if (space == BEM_P0) {
         r.fix.assign(dofs, dofs + n);
     } else {
-        r.fix.resize(n + 1);
-        r.fix[0] = 0;
+        // the fixed dofs' stars stay in the mesh's star table: ranges only
+        r.fix.resize(2 * n);
         for (int64_t f = 0; f < n; ++f) {
             const int32_t v = dofs[f];
-            for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) r.fstar.push_back(m.star[s]);
-            r.fix[f + 1] = (int32_t)r.fstar.size();
+            r.fix[2 * f] = (int32_t)m.star_ptr[v];
+            r.fix[2 * f + 1] = (int32_t)m.star_ptr[v + 1];
+            r.nstar += m.star_ptr[v + 1] - m.star_ptr[v];
         }
     }
     r.nfix = n;
@@ -101,11 +102,11 @@ void finalize_sizes(Request &r)
     const bem_mesh &m = *r.mesh;
     const int64_t q2 = (int64_t)m.q * m.q;
     r.elem_bytes = out_elem_bytes(r.op, r.prec);
-    const int64_t fixed_tris = r.space == BEM_P0 ? r.nfix : (int64_t)r.fstar.size();
+    const int64_t fixed_tris = r.space == BEM_P0 ? r.nfix : r.nstar;
     r.evals = fixed_tris * r.ndistinct * q2;
     r.nblocks = r.nfix * r.nchunk;
     const size_t own = r.ext ? 0 : r.own.ints();
-    r.in_bytes = align16(4 * (r.fix.size() + r.fstar.size() + own));
+    r.in_bytes = align16(4 * own);
     r.out_bytes = align16((size_t)r.entries() * r.elem_bytes);
     r.batch_bytes = request_bytes(r);
 }
@@ -258,8 +259,7 @@ size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t 
         d.seg_ptr = put(r.own.seg_ptr);
         d.seg = put(r.own.seg);
     }
-    d.fix = put(r.fix);
-    d.fstar = put(r.fstar);
+    d.fstar = m.d_star;
     if (r.rowfix) {
         d.sf = r.ncols;
         d.sl = 1;
@@ -287,7 +287,10 @@ void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t 
 
 int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
 {
+    const bem_mesh &m = *r.mesh;
     const int32_t *ch = r.ext ? r.ext->chunk_host : r.own.chunk.data();
+    const float *lgeo = r.ext ? r.ext->geo : nullptr;
+    const int4 *lmeta = r.ext ? r.ext->meta : nullptr;
     int64_t n = 0;
     for (int32_t f = 0; f < (int32_t)r.nfix; ++f) {
         int32_t s0, s1;
@@ -295,8 +298,8 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
             s0 = r.fix[f];
             s1 = s0 + 1;
         } else {
-            s0 = r.fix[f];
-            s1 = r.fix[f + 1];
+            s0 = r.fix[2 * f];
+            s1 = r.fix[2 * f + 1];
         }
         for (int32_t c = 0; c < (int32_t)r.nchunk; ++c) {
             EntryBlock &b = out[n++];
@@ -305,6 +308,10 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
             b.s0 = s0;
             b.s1 = s1;
             b.chunk = make_int4(ch[4 * c], ch[4 * c + 1], ch[4 * c + 2], ch[4 * c + 3]);
+            b.lgeo = lgeo;
+            b.lmeta = lmeta;
+            b.sgeo = r.space == BEM_P1 ? m.d_sgeo : nullptr;
+            b.smeta = r.space == BEM_P1 ? m.d_smeta : nullptr;
         }
     }
     return n;
@@ -387,6 +394,15 @@ int mesh_create_impl(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
     if (e == hipSuccess) e = hipMemcpy(d_bad, &bad, sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_geometry(d_xyz, d_tri, nt, q, m->d_g32, m->d_g64, m->d_vtx, d_bad, 0);
     if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost);
+    // star tables: the packed star entries and, per entry, its triangle's
+    // FP32 record and vertex ids with the local vertex in w
+    const int64_t ns = 3 * nt;
+    if (e == hipSuccess) e = hipMalloc(&m->d_star, sizeof(int32_t) * ns);
+    if (e == hipSuccess) e = hipMalloc(&m->d_sgeo, sizeof(float) * kGeo32Stride * ns);
+    if (e == hipSuccess) e = hipMalloc(&m->d_smeta, sizeof(int4) * ns);
+    if (e == hipSuccess) e = hipMemcpy(m->d_star, m->star.data(), sizeof(int32_t) * ns, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_gather(m->d_g32, m->d_vtx, m->d_star, 2, ns, m->d_sgeo, m->d_smeta, 0);
+    if (e == hipSuccess) e = hipStreamSynchronize(0);
     if (d_xyz) (void)hipFree(d_xyz);
     if (d_tri) (void)hipFree(d_tri);
     if (d_bad) (void)hipFree(d_bad);
@@ -395,13 +411,13 @@ int mesh_create_impl(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
     else if (bad)
         rc = fail(BEM_E_ARG, "degenerate triangle (zero area)");
     if (rc != BEM_OK) {
-        if (m->d_g32) (void)hipFree(m->d_g32);
-        if (m->d_g64) (void)hipFree(m->d_g64);
-        if (m->d_vtx) (void)hipFree(m->d_vtx);
+        for (void *p : {(void *)m->d_g32, (void *)m->d_g64, (void *)m->d_vtx, (void *)m->d_star, (void *)m->d_sgeo,
+                        (void *)m->d_smeta})
+            if (p) (void)hipFree(p);
         delete m;
         return rc;
     }
-    m->dev_bytes = b32 + b64 + bv;
+    m->dev_bytes = b32 + b64 + bv + 3 * (size_t)nt * (4 + 4 * kGeo32Stride + sizeof(int4));
     *out = m;
     return BEM_OK;
 }
@@ -410,9 +426,9 @@ int mesh_destroy_impl(bem_mesh *m)
 {
     if (!m) return fail(BEM_E_ARG, "null mesh");
     if (m->inflight.load() != 0) return fail(BEM_E_BUSY, "requests on this mesh are still in flight");
-    (void)hipFree(m->d_g32);
-    (void)hipFree(m->d_g64);
-    (void)hipFree(m->d_vtx);
+    for (void *p : {(void *)m->d_g32, (void *)m->d_g64, (void *)m->d_vtx, (void *)m->d_star, (void *)m->d_sgeo,
+                    (void *)m->d_smeta})
+        (void)hipFree(p);
     delete m;
     return BEM_OK;
 }

@@ -406,7 +406,7 @@ public:
         }
 
         // staging writes
-        static_assert(sizeof(EntryBlock) == 32, "block records are 32 bytes");
+        static_assert(sizeof(EntryBlock) == 64, "block records are 64 bytes");
         for (const Launch &L : launches) {
             EntryBlock *p = reinterpret_cast<EntryBlock *>(hb + L.off_tab);
             int64_t k = 0;
