@@ -16,6 +16,9 @@
 #include <deque>
 #include <type_traits>
 #include <thread>
+#include <mutex>
+#include <new>
+#include <sys/mman.h>
 
 #include "aca.hpp"
 #include <unordered_map>
@@ -24,6 +27,88 @@
 
 using cd = std::complex<double>;
 
+namespace bem {
+
+// Factor and dense-block values live in large blocks bump-allocated per
+// worker instead of three heap vectors per leaf: assembly makes no
+// allocator call per block, and destroying an H-matrix hands a few blocks
+// back to a process-wide pool (up to kPoolKeep of them are kept, so
+// repeated assemblies reuse memory that is already mapped).
+constexpr size_t kPoolDoubles = size_t(1) << 19;   // 4 MiB per block
+constexpr size_t kPoolKeep = 256;                  // at most 1 GiB retained
+
+struct ValueBlock {
+    double *p = nullptr;
+    size_t n = 0;   // doubles; kPoolDoubles for pooled blocks
+};
+
+class ValuePool {
+public:
+    ValueBlock take(size_t n)
+    {
+        if (n <= kPoolDoubles) {
+            {
+                std::lock_guard<std::mutex> g(mu_);
+                if (!free_.empty()) {
+                    double *p = free_.back();
+                    free_.pop_back();
+                    return {p, kPoolDoubles};
+                }
+            }
+            void *p = std::aligned_alloc(size_t(1) << 21, kPoolDoubles * sizeof(double));
+            if (!p) throw std::bad_alloc();
+            (void)madvise(p, kPoolDoubles * sizeof(double), MADV_HUGEPAGE);
+            return {static_cast<double *>(p), kPoolDoubles};
+        }
+        return {new double[n], n};
+    }
+    void give(std::vector<ValueBlock> &v)
+    {
+        std::lock_guard<std::mutex> g(mu_);
+        for (const ValueBlock &b : v) {
+            if (b.n == kPoolDoubles && free_.size() < kPoolKeep)
+                free_.push_back(b.p);
+            else if (b.n == kPoolDoubles)
+                std::free(b.p);
+            else
+                delete[] b.p;
+        }
+        v.clear();
+    }
+
+private:
+    std::mutex mu_;
+    std::vector<double *> free_;
+};
+
+ValuePool &value_pool()
+{
+    static ValuePool *pool = new ValuePool();   // never destroyed: outlives every H-matrix
+    return *pool;
+}
+
+// One worker's bump allocator over pool blocks.
+struct ValueArena {
+    std::vector<ValueBlock> blocks;
+    double *cur = nullptr;
+    size_t left = 0;
+    double *take(size_t n)
+    {
+        if (n > left || !cur) {   // a block always exists, so pointers are never null
+            const ValueBlock b = value_pool().take(n);
+            blocks.push_back(b);
+            cur = b.p;
+            left = b.n;
+        }
+        double *p = cur;
+        cur += n;
+        left -= n;
+        return p;
+    }
+};
+
+}  // namespace bem
+
 struct bem_hmat {
     int op = 0, space = 0;
     bool cplx = false;
@@ -31,12 +116,16 @@ struct bem_hmat {
     bem::Partition part;
     struct Leaf {
         int adm = 0;
-        std::vector<int32_t> rows, cols;
         int rank = 0;
-        std::vector<double> U, V, D;   // complex values interleaved
+        int64_t r0 = 0, m = 0, c0 = 0, n = 0;   // rows part.perm[r0, r0 + m), columns part.perm[c0, c0 + n)
+        const double *U = nullptr, *V = nullptr, *D = nullptr;   // complex values interleaved
     };
     std::vector<Leaf> leaves;
+    std::vector<bem::ValueBlock> store;   // owns the values the leaves point to
     bem_hmat_stats st{};
+    const int32_t *rows(const Leaf &L) const { return part.perm.data() + L.r0; }
+    const int32_t *cols(const Leaf &L) const { return part.perm.data() + L.c0; }
+    ~bem_hmat() { bem::value_pool().give(store); }
 };
 
 namespace bem {
@@ -387,8 +476,8 @@ int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag, WorkerT
     r.tag = tag;
     if (!s.adm) {
         r.near = BEM_NEAR_SKIP;
-        r.rows = L.rows;
-        r.cols = L.cols;
+        r.rows.assign(C.h->rows(L), C.h->rows(L) + L.m);
+        r.cols.assign(C.h->cols(L), C.h->cols(L) + L.n);
         r.nrows = (int64_t)r.rows.size();
         r.ncols = (int64_t)r.cols.size();
         const int rc = expand_request(r);
@@ -398,9 +487,9 @@ int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag, WorkerT
         r.near = BEM_NEAR_ERROR;
         const Block &bk = C.h->part.blocks[s.leaf];
         if (s.core.phase == AcaCore<T>::NEED_ROW)
-            expand_single_fixed(r, L.rows[s.core.i], 1, &(*C.lanes)[bk.sigma]);
+            expand_single_fixed(r, C.h->rows(L)[s.core.i], 1, &(*C.lanes)[bk.sigma]);
         else
-            expand_single_fixed(r, L.cols[s.core.j], 0, &(*C.lanes)[bk.tau]);
+            expand_single_fixed(r, C.h->cols(L)[s.core.j], 0, &(*C.lanes)[bk.tau]);
         w.aca_entries += r.entries();
     }
     w.requests += 1;
@@ -413,6 +502,7 @@ void worker(AssemblyCtx &C, int per_worker)
     DoneQueue dq;
     dq.spin_s = worker_spin_seconds();
     WorkerTally tally;
+    ValueArena arena;   // values of the blocks this worker finishes
     std::vector<Slot<T>> slots(per_worker);
     std::vector<Request *> submit, done;
     int active = 0;
@@ -440,7 +530,7 @@ void worker(AssemblyCtx &C, int per_worker)
             const Block &bk = C.h->part.blocks[s.leaf];
             const Cluster &a = C.h->part.nodes[bk.tau];
             const Cluster &b = C.h->part.nodes[bk.sigma];
-            s.core.init((int64_t)L.rows.size(), (int64_t)L.cols.size(), C.tol, C.max_rank,
+            s.core.init(L.m, L.n, C.tol, C.max_rank,
                         default_zero_abs(*C.mesh, C.op, C.space, C.k, C.prec, support_distance(a, b)));
         }
         const int rc = prepare_slot(C, s, dq, si, tally);
@@ -494,8 +584,9 @@ void worker(AssemblyCtx &C, int per_worker)
                     s.buf.resize(cnt);
                     to_scalar<T>(r->result, C.prec, cnt, s.buf.data());
                     tc += now_seconds() - c0;
-                    L.D.resize((size_t)cnt * (sizeof(T) / sizeof(double)));
-                    std::memcpy(L.D.data(), s.buf.data(), sizeof(T) * cnt);
+                    double *D = arena.take((size_t)cnt * (sizeof(T) / sizeof(double)));
+                    std::memcpy(D, s.buf.data(), sizeof(T) * cnt);
+                    L.D = D;
                     finished = true;
                 } else {
                     const double a0 = now_seconds();
@@ -504,10 +595,12 @@ void worker(AssemblyCtx &C, int per_worker)
                     if (s.core.phase == AcaCore<T>::DONE) {
                         L.rank = s.core.k;
                         const size_t f = sizeof(T) / sizeof(double);
-                        L.U.resize(s.core.U.size() * f);
-                        L.V.resize(s.core.V.size() * f);
-                        std::memcpy(L.U.data(), s.core.U.data(), sizeof(T) * s.core.U.size());
-                        std::memcpy(L.V.data(), s.core.V.data(), sizeof(T) * s.core.V.size());
+                        double *U = arena.take(s.core.U.size() * f);
+                        double *V = arena.take(s.core.V.size() * f);
+                        std::memcpy(U, s.core.U.data(), sizeof(T) * s.core.U.size());
+                        std::memcpy(V, s.core.V.data(), sizeof(T) * s.core.V.size());
+                        L.U = U;
+                        L.V = V;
                         finished = true;
                     }
                 }
@@ -554,6 +647,7 @@ void worker(AssemblyCtx &C, int per_worker)
     C.dense_entries.fetch_add(tally.dense_entries);
     C.requests.fetch_add(tally.requests);
     std::lock_guard<std::mutex> g(C.busy_mu);
+    C.h->store.insert(C.h->store.end(), arena.blocks.begin(), arena.blocks.end());
     C.busy += busy;
     C.qdelay += qd;
     C.proc += pr;
@@ -745,15 +839,17 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
         const Cluster &a = P.nodes[P.blocks[b].tau], &c = P.nodes[P.blocks[b].sigma];
         auto &L = h->leaves[b];
         L.adm = P.blocks[b].admissible;
-        L.rows.assign(P.perm.begin() + a.begin, P.perm.begin() + a.end);
-        L.cols.assign(P.perm.begin() + c.begin, P.perm.begin() + c.end);
+        L.r0 = a.begin;
+        L.m = a.end - a.begin;
+        L.c0 = c.begin;
+        L.n = c.end - c.begin;
         if (L.adm || p->dense_mode == 1) C.jobs.push_back(Job{(int64_t)b, L.adm});
     }
     // largest blocks first
     std::stable_sort(C.jobs.begin(), C.jobs.end(), [&](const Job &x, const Job &y) {
         const auto &a = h->leaves[x.leaf], &b = h->leaves[y.leaf];
-        const int64_t cx = x.adm ? (int64_t)(a.rows.size() + a.cols.size()) * 16 : (int64_t)(a.rows.size() * a.cols.size());
-        const int64_t cy = y.adm ? (int64_t)(b.rows.size() + b.cols.size()) * 16 : (int64_t)(b.rows.size() * b.cols.size());
+        const int64_t cx = x.adm ? (a.m + a.n) * 16 : a.m * a.n;
+        const int64_t cy = y.adm ? (b.m + b.n) * 16 : b.m * b.n;
         return cx > cy;
     });
     const double t_setup = now_seconds();
@@ -788,7 +884,11 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
         } else {
             s.dense_blocks++;
         }
-        bytes += sizeof(double) * (L.U.size() + L.V.size() + L.D.size());
+        const size_t f = h->cplx ? 2 : 1;
+        if (L.adm)
+            bytes += sizeof(double) * f * (size_t)L.rank * (size_t)(L.m + L.n);
+        else if (L.D)
+            bytes += sizeof(double) * f * (size_t)(L.m * L.n);
     }
     s.bytes = bytes;
     s.seconds = now_seconds() - t0;
@@ -822,38 +922,39 @@ int hmat_matvec(const bem_hmat *h, const void *xv, void *yv)
         std::vector<cd> tmp;
         for (size_t b = tid; b < h->leaves.size(); b += nth) {
             const auto &L = h->leaves[b];
-            const int64_t m = (int64_t)L.rows.size(), nc = (int64_t)L.cols.size();
+            const int64_t m = L.m, nc = L.n;
+            const int32_t *rows = h->rows(L), *cols = h->cols(L);
             if (h->cplx) {
                 const cd *X = reinterpret_cast<const cd *>(x);
                 cd *Y = reinterpret_cast<cd *>(y.data());
                 if (L.adm) {
-                    const cd *U = reinterpret_cast<const cd *>(L.U.data());
-                    const cd *V = reinterpret_cast<const cd *>(L.V.data());
+                    const cd *U = reinterpret_cast<const cd *>(L.U);
+                    const cd *V = reinterpret_cast<const cd *>(L.V);
                     tmp.assign(L.rank, cd(0));
                     for (int l = 0; l < L.rank; ++l)
-                        for (int64_t c = 0; c < nc; ++c) tmp[l] += V[(size_t)l * nc + c] * X[L.cols[c]];
+                        for (int64_t c = 0; c < nc; ++c) tmp[l] += V[(size_t)l * nc + c] * X[cols[c]];
                     for (int l = 0; l < L.rank; ++l)
-                        for (int64_t r = 0; r < m; ++r) Y[L.rows[r]] += U[(size_t)l * m + r] * tmp[l];
-                } else if (!L.D.empty()) {
-                    const cd *D = reinterpret_cast<const cd *>(L.D.data());
+                        for (int64_t r = 0; r < m; ++r) Y[rows[r]] += U[(size_t)l * m + r] * tmp[l];
+                } else if (L.D) {
+                    const cd *D = reinterpret_cast<const cd *>(L.D);
                     for (int64_t r = 0; r < m; ++r) {
                         cd s = 0;
-                        for (int64_t c = 0; c < nc; ++c) s += D[r * nc + c] * X[L.cols[c]];
-                        Y[L.rows[r]] += s;
+                        for (int64_t c = 0; c < nc; ++c) s += D[r * nc + c] * X[cols[c]];
+                        Y[rows[r]] += s;
                     }
                 }
             } else {
                 if (L.adm) {
                     std::vector<double> t(L.rank, 0.0);
                     for (int l = 0; l < L.rank; ++l)
-                        for (int64_t c = 0; c < nc; ++c) t[l] += L.V[(size_t)l * nc + c] * x[L.cols[c]];
+                        for (int64_t c = 0; c < nc; ++c) t[l] += L.V[(size_t)l * nc + c] * x[cols[c]];
                     for (int l = 0; l < L.rank; ++l)
-                        for (int64_t r = 0; r < m; ++r) y[L.rows[r]] += L.U[(size_t)l * m + r] * t[l];
-                } else if (!L.D.empty()) {
+                        for (int64_t r = 0; r < m; ++r) y[rows[r]] += L.U[(size_t)l * m + r] * t[l];
+                } else if (L.D) {
                     for (int64_t r = 0; r < m; ++r) {
                         double s = 0;
-                        for (int64_t c = 0; c < nc; ++c) s += L.D[r * nc + c] * x[L.cols[c]];
-                        y[L.rows[r]] += s;
+                        for (int64_t c = 0; c < nc; ++c) s += L.D[r * nc + c] * x[cols[c]];
+                        y[rows[r]] += s;
                     }
                 }
             }
@@ -877,11 +978,11 @@ int hmat_block_info(const bem_hmat *h, int64_t b, int32_t *adm, int64_t *m, int6
     if (!h || b < 0 || b >= (int64_t)h->leaves.size()) return fail(BEM_E_ARG, "block index out of range");
     const auto &L = h->leaves[b];
     if (adm) *adm = L.adm;
-    if (m) *m = (int64_t)L.rows.size();
-    if (n) *n = (int64_t)L.cols.size();
+    if (m) *m = L.m;
+    if (n) *n = L.n;
     if (rank) *rank = L.rank;
-    if (rows) *rows = L.rows.data();
-    if (cols) *cols = L.cols.data();
+    if (rows) *rows = h->rows(L);
+    if (cols) *cols = h->cols(L);
     return BEM_OK;
 }
 
@@ -889,20 +990,20 @@ int hmat_block_dense(const bem_hmat *h, int64_t b, void *outv)
 {
     if (!h || !outv || b < 0 || b >= (int64_t)h->leaves.size()) return fail(BEM_E_ARG, "bad block");
     const auto &L = h->leaves[b];
-    const int64_t m = (int64_t)L.rows.size(), n = (int64_t)L.cols.size();
+    const int64_t m = L.m, n = L.n;
     if (h->cplx) {
         cd *out = (cd *)outv;
         if (L.adm) {
-            const cd *U = reinterpret_cast<const cd *>(L.U.data());
-            const cd *V = reinterpret_cast<const cd *>(L.V.data());
+            const cd *U = reinterpret_cast<const cd *>(L.U);
+            const cd *V = reinterpret_cast<const cd *>(L.V);
             for (int64_t r = 0; r < m; ++r)
                 for (int64_t c = 0; c < n; ++c) {
                     cd s = 0;
                     for (int l = 0; l < L.rank; ++l) s += U[(size_t)l * m + r] * V[(size_t)l * n + c];
                     out[r * n + c] = s;
                 }
-        } else if (!L.D.empty()) {
-            std::memcpy(out, L.D.data(), sizeof(cd) * m * n);
+        } else if (L.D) {
+            std::memcpy(out, L.D, sizeof(cd) * m * n);
         } else {
             std::fill(out, out + m * n, cd(0));
         }
@@ -915,8 +1016,8 @@ int hmat_block_dense(const bem_hmat *h, int64_t b, void *outv)
                     for (int l = 0; l < L.rank; ++l) s += L.U[(size_t)l * m + r] * L.V[(size_t)l * n + c];
                     out[r * n + c] = s;
                 }
-        } else if (!L.D.empty()) {
-            std::memcpy(out, L.D.data(), sizeof(double) * m * n);
+        } else if (L.D) {
+            std::memcpy(out, L.D, sizeof(double) * m * n);
         } else {
             std::fill(out, out + m * n, 0.0);
         }
