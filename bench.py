@@ -56,8 +56,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workers", type=int, default=14)
-    ap.add_argument("--blocks-per-worker", type=int, default=128)
+    ap.add_argument("--workers", type=int, default=10)
+    ap.add_argument("--blocks-per-worker", type=int, default=180)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

@@ -105,6 +105,9 @@ hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, in
 // ids (w = index[i] & 3 when shift == 2, else 0); i < n.
 hipError_t launch_gather(const float *g32, const int4 *vtx, const int32_t *index, int shift, int64_t n, float *geo,
                          int4 *meta, hipStream_t s);
+// Copies bytes (a multiple of 16, both addresses 16-byte aligned) from src
+// (device-visible host staging) to dst (device) with a kernel on stream s.
+hipError_t launch_stage_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Errors

@@ -53,6 +53,10 @@ template <int Q>
 constexpr int n32() { return (12 + 3 * Q + 3) / 4 * 4; }
 template <int Q>
 constexpr int n64() { return (4 + 3 * Q + 1) / 2 * 2; }
+// A staged P1 star record on the trial side: the FP32 record with its
+// quadrature offsets scaled by -2, then |o_q|^2 per point (see pair_p1_*).
+template <int Q>
+constexpr int nstar32() { return (n32<Q>() + Q + 3) / 4 * 4; }
 
 template <int Q>
 __device__ __forceinline__ void load32(const float *__restrict__ g, int t, float *v)
@@ -287,12 +291,15 @@ __device__ __forceinline__ void pair_p0_f64(const double *T, const double *S, do
 // Test side fixed with local vertex a (basis lam_a at the test points), trial
 // side on the lane with all three local vertices e:
 //   v_e = sum_q w_q lam_e(q) [ sum_p w_p lam_a(p) K(x_p, y_q) ].
+//
+// The trial offsets arrive scaled by -2 (m_q = -2 o_q, exact) with
+// Bq[q] = |o_q|^2, both formed once per trial triangle.
 template <int OP, int Q>
-__device__ __forceinline__ void pair_p1_testfix_f32(const float *T, int a, const float *S, float kf, double kk,
-                                                    float *vr, float *vi)
+__device__ __forceinline__ void pair_p1_testfix_f32(const float *T, int a, const float *S, const float *Bq, float kf,
+                                                    double kk, float *vr, float *vi)
 {
     // x_p - y_q = a_p - o_q with a_p the test point relative to the trial
-    // centroid; r^2 = (|a_p|^2 + |o_q|^2) + (-2 a_p) . o_q costs one add and
+    // centroid; r^2 = (|a_p|^2 + |o_q|^2) + a_p . (-2 o_q) costs one add and
     // three fma per point pair.  Helmholtz: the same chain started from
     // A'_p = |a_p|^2 - |D|^2 = 2 D.o_p + |o_p|^2 gives n = r^2 - |D|^2.
     const float dcx = (T[0] - S[0]) + (T[4] - S[4]);
@@ -305,9 +312,9 @@ __device__ __forceinline__ void pair_p1_testfix_f32(const float *T, int a, const
     for (int p = 0; p < Q; ++p) {
         const float ox = T[12 + 3 * p], oy = T[13 + 3 * p], oz = T[14 + 3 * p];
         const float ax = dcx + ox, ay = dcy + oy, az = dcz + oz;
-        mx[p] = -2.0f * ax;
-        my[p] = -2.0f * ay;
-        mz[p] = -2.0f * az;
+        mx[p] = ax;
+        my[p] = ay;
+        mz[p] = az;
         if constexpr (is_cplx<OP>())
             A[p] = fmaf(2.0f * dcx + ox, ox, fmaf(2.0f * dcy + oy, oy, (2.0f * dcz + oz) * oz));
         else
@@ -321,7 +328,7 @@ __device__ __forceinline__ void pair_p1_testfix_f32(const float *T, int a, const
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const float ox = S[12 + 3 * q], oy = S[13 + 3 * q], oz = S[14 + 3 * q];
-        const float B = fmaf(ox, ox, fmaf(oy, oy, oz * oz));
+        const float B = Bq[q];
         float tr = 0.f, ti = 0.f;
 #pragma unroll
         for (int p = 0; p < Q; ++p) {
@@ -342,6 +349,8 @@ __device__ __forceinline__ void pair_p1_testfix_f32(const float *T, int a, const
 
 // Trial side fixed with local vertex b, test side on the lane with all three
 // local vertices d:  v_d = sum_p w_p lam_d(p) [ sum_q w_q lam_b(q) K(x_p, y_q) ].
+// S is a staged trial record (nstar32 layout: offsets scaled by -2, then
+// |o_q|^2).
 template <int OP, int Q>
 __device__ __forceinline__ void pair_p1_trialfix_f32(const float *T, const float *S, int b, float kf, double kk,
                                                      float *vr, float *vi)
@@ -356,7 +365,7 @@ __device__ __forceinline__ void pair_p1_trialfix_f32(const float *T, const float
     for (int q = 0; q < Q; ++q) {
         const float l = (float)(b == 0 ? rule::Rule<Q>::l0[q] : (b == 1 ? rule::Rule<Q>::l1[q] : rule::Rule<Q>::l2[q]));
         wb[q] = (float)rule::Rule<Q>::w[q] * l;
-        B[q] = fmaf(S[12 + 3 * q], S[12 + 3 * q], fmaf(S[13 + 3 * q], S[13 + 3 * q], S[14 + 3 * q] * S[14 + 3 * q]));
+        B[q] = S[n32<Q>() + q];
     }
 #pragma unroll
     for (int e = 0; e < 3; ++e) vr[e] = vi[e] = 0.f;
@@ -364,7 +373,7 @@ __device__ __forceinline__ void pair_p1_trialfix_f32(const float *T, const float
     for (int p = 0; p < Q; ++p) {
         const float ox = T[12 + 3 * p], oy = T[13 + 3 * p], oz = T[14 + 3 * p];
         const float ax = dcx + ox, ay = dcy + oy, az = dcz + oz;
-        const float mx = -2.0f * ax, my = -2.0f * ay, mz = -2.0f * az;
+        const float mx = ax, my = ay, mz = az;
         float A;
         if constexpr (is_cplx<OP>())
             A = fmaf(2.0f * dcx + ox, ox, fmaf(2.0f * dcy + oy, oy, (2.0f * dcz + oz) * oz));
@@ -589,16 +598,26 @@ struct SegPrefetch {
 };
 
 // Stages up to kStage star entries [sb, ...) of the mesh star table into LDS
-// from the gathered star records of block B (FP32).
-template <int W>
-__device__ __forceinline__ int stage_star_tab(const EntryBlock &B, int sb, int s1, float (*sG)[W], int4 *sV, int *sL)
+// from the gathered star records of block B (FP32).  A trial-side star
+// (TRIAL) is staged in the nstar32 layout: offsets scaled by -2 (exact) and
+// |o_q|^2 appended; a test-side star as the plain record.
+template <int Q, bool TRIAL>
+__device__ __forceinline__ int stage_star_tab(const EntryBlock &B, int sb, int s1, float (*sG)[nstar32<Q>()], int4 *sV,
+                                              int *sL)
 {
+    constexpr int W = n32<Q>();
     const int t = threadIdx.x;
     const int ns = min(kStage, s1 - sb);
     __syncthreads();   // the previous stage has been read
     if (t < ns * W) {
         const int k = t / W, w = t - k * W;
-        sG[k][w] = B.sgeo[(size_t)(sb + k) * kGeo32Stride + w];
+        const float x = B.sgeo[(size_t)(sb + k) * kGeo32Stride + w];
+        sG[k][w] = (TRIAL && w >= 12 && w < 12 + 3 * Q) ? -2.0f * x : x;
+    }
+    if (TRIAL && t < ns * Q) {
+        const int k = t / Q, q = t - k * Q;
+        const float *o = B.sgeo + (size_t)(sb + k) * kGeo32Stride + 12 + 3 * q;
+        sG[k][W + q] = fmaf(o[0], o[0], fmaf(o[1], o[1], o[2] * o[2]));
     }
     if (t < ns) {
         const int4 m = B.smeta[sb + t];
@@ -614,7 +633,7 @@ __device__ __forceinline__ int stage_star_tab(const EntryBlock &B, int sb, int s
 // LDS.  Phase 2: thread j adds, for dof j of the chunk, the partials its
 // segment list names, in order, compensated, and stores the entry.
 template <int OP, int Q, bool ROWFIX>
-__device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B, float (*sG)[n32<Q>()], int4 *sV,
+__device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B, float (*sG)[nstar32<Q>()], int4 *sV,
                                             int *sL, float4 (*sP)[3])
 {
     const int4 ch = B.chunk;   // first lane, lanes, first dof, dofs
@@ -633,6 +652,19 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
         vn = R.vtx[tn];
         load32<Q>(R.g32, tn, L);
     }
+    // row requests: the lane is the trial side; its offsets scaled by -2 and
+    // |o_q|^2 serve every star triangle
+    float Bq[ROWFIX ? Q : 1];
+    if constexpr (ROWFIX) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            float *o = L + 12 + 3 * q;
+            Bq[q] = fmaf(o[0], o[0], fmaf(o[1], o[1], o[2] * o[2]));
+            o[0] *= -2.0f;
+            o[1] *= -2.0f;
+            o[2] *= -2.0f;
+        }
+    }
     float hr[3] = {0.f, 0.f, 0.f}, lr[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f}, lo[3] = {0.f, 0.f, 0.f};
     const int s0 = B.s0, s1 = B.s1;
     // phase 2 of this thread's first entry: its segment list, fetched while
@@ -640,7 +672,7 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     // wait for it)
     SegPrefetch pf;
     for (int sb = s0; sb < s1; sb += kStage) {
-        const int ns = stage_star_tab<n32<Q>()>(B, sb, s1, sG, sV, sL);
+        const int ns = stage_star_tab<Q, !ROWFIX>(B, sb, s1, sG, sV, sL);
         if (sb == s0) pf.fetch(R, ch, t);
         if (!wact) continue;
         for (int s = 0; s < ns; ++s) {
@@ -648,13 +680,14 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
                 if (act && R.near_error) *R.status = 1;
                 continue;
             }
-            float F[n32<Q>()];
+            constexpr int FW = ROWFIX ? n32<Q>() : nstar32<Q>();
+            float F[FW];
 #pragma unroll
-            for (int i = 0; i < n32<Q>(); ++i) F[i] = sG[s][i];
+            for (int i = 0; i < FW; ++i) F[i] = sG[s][i];
             const int loc = sL[s];
             float vr[3], vi[3];
             if constexpr (ROWFIX)
-                pair_p1_testfix_f32<OP, Q>(F, loc, L, (float)R.k, R.kk, vr, vi);
+                pair_p1_testfix_f32<OP, Q>(F, loc, L, Bq, (float)R.k, R.kk, vr, vi);
             else
                 pair_p1_trialfix_f32<OP, Q>(L, F, loc, (float)R.k, R.kk, vr, vi);
             const float sc = F[3] * L[3] * kInv4PiF;
@@ -712,7 +745,7 @@ __global__ __launch_bounds__(kBlockLanes) void k_p1_f32(const ReqDev *__restrict
                                                         const EntryBlock *__restrict__ blocks, int64_t nblocks,
                                                         unsigned long long *tclock)
 {
-    __shared__ float sG[kStage][n32<Q>()];
+    __shared__ float sG[kStage][nstar32<Q>()];
     __shared__ int4 sV[kStage];
     __shared__ int sL[kStage];
     __shared__ float4 sP[kBlockLanes][3];

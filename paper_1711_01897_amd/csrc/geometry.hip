@@ -1,6 +1,9 @@
 // Per-triangle geometry, computed once on the device when a mesh is created
 // and kept resident (Section 3.2.1: normals, Jacobians and global quadrature
 // points are precomputed on the device and laid out for coalesced access).
+#include <algorithm>
+#include <cstdint>
+
 #include "bem_internal.hpp"
 #include "quad_rules.hpp"
 
@@ -85,6 +88,26 @@ hipError_t launch_gather(const float *g32, const int4 *vtx, const int32_t *index
     const int64_t grid = (words + 255) / 256;
     if (grid > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_gather, dim3((unsigned)grid), dim3(256), 0, s, g32, vtx, index, shift, n, geo, meta);
+    return hipGetLastError();
+}
+
+// Batch staging copy: n 16-byte words from host staging (its device
+// address) to the device arena, on the compute queue of the stream, so the
+// entry kernels that follow need no wait on a copy engine.
+__global__ __launch_bounds__(256) void k_stage_copy(const int4 *__restrict__ src, int4 *__restrict__ dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) dst[j] = src[j];
+}
+
+hipError_t launch_stage_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    if ((bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15)) return hipErrorInvalidValue;
+    const int64_t n = (int64_t)(bytes / 16);
+    const int64_t grid = std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_stage_copy, dim3((unsigned)grid), dim3(256), 0, s, static_cast<const int4 *>(src),
+                       static_cast<int4 *>(dst), n);
     return hipGetLastError();
 }
 

@@ -454,6 +454,17 @@ double worker_spin_seconds()
     return v;
 }
 
+// Finished requests a worker takes at once (BEM_WORKER_POP, default 64) and
+// the number of follow-up requests after which it submits them without
+// waiting for the rest of what it took (BEM_WORKER_FLUSH, default 64).
+// Smaller flushes shorten a block's wait between requests but hand the
+// dispatcher smaller batches; on the icosphere assemblies they were slower.
+int worker_env(const char *name, int def)
+{
+    const char *e = std::getenv(name);
+    return e ? std::max(1, std::atoi(e)) : def;
+}
+
 // Per-worker tallies, added to the assembly's totals when the worker ends.
 struct WorkerTally {
     int64_t aca_entries = 0, dense_entries = 0, requests = 0;
@@ -501,6 +512,8 @@ void worker(AssemblyCtx &C, int per_worker)
 {
     DoneQueue dq;
     dq.spin_s = worker_spin_seconds();
+    static const int pop_most = worker_env("BEM_WORKER_POP", 64);
+    static const int flush_every = worker_env("BEM_WORKER_FLUSH", 64);
     WorkerTally tally;
     ValueArena arena;   // values of the blocks this worker finishes
     std::vector<Slot<T>> slots(per_worker);
@@ -565,11 +578,16 @@ void worker(AssemblyCtx &C, int per_worker)
     flush();
     while (active > 0) {
         busy += now_seconds() - tb;
-        dq.pop_some(done, 64);
+        dq.pop_some(done, (size_t)pop_most);
         tb = now_seconds();
         for (Request *r : done) qd += tb - r->t_done;
         np += (int64_t)done.size();
         for (Request *r : done) {
+            if ((int)submit.size() >= flush_every) {
+                const double f0 = now_seconds();
+                flush();
+                tf += now_seconds() - f0;
+            }
             Slot<T> &s = slots[r->tag];
             bool finished = false;
             if (r->status != BEM_OK) {

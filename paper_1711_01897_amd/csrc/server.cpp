@@ -372,7 +372,8 @@ public:
         }
 
         // layout: descriptors | block tables | inputs  (copied to the device
-        // arena) || status | outputs  (stored by the kernels into the staging)
+        // arena by a kernel) || clock records | status | outputs  (stored by
+        // the kernels into the staging)
         // (offsets first, checked against the slot, then the staging writes)
         size_t off = align256(sizeof(ReqDev) * n);
         for (Launch &L : launches) {
@@ -425,14 +426,14 @@ public:
         }
         b->launches = std::move(launches);
 
-        // enqueue: inputs, the launches (timed ones also with HIP events
-        // around each launch), the clock records back, the batch event
+        // enqueue: the input copy, the launches (timed ones also with HIP
+        // events around each launch), the batch event
         b->t_launch = now_seconds();
         b->t_hip = b->t_launch;
         auto note = [&](hipError_t e) {
             if (e != hipSuccess && b->enqueue_error == hipSuccess) b->enqueue_error = e;
         };
-        note(hipMemcpyAsync(db, hb, h2d_end, hipMemcpyHostToDevice, stream));
+        note(launch_stage_copy(hd, db, h2d_end, stream));
         const ReqDev *dreq = reinterpret_cast<const ReqDev *>(db);
         int64_t blk0 = 0;
         for (const Launch &L : b->launches) {
@@ -443,14 +444,12 @@ public:
                 e1 = get_event();
                 b->ev.push_back(e0);
                 b->ev.push_back(e1);
-                ck = reinterpret_cast<unsigned long long *>(db + off_clock) + 2 * blk0;
+                ck = reinterpret_cast<unsigned long long *>(hd + off_clock) + 2 * blk0;
             }
             note(launch_entries(L.v, dreq, reinterpret_cast<const EntryBlock *>(db + L.off_tab), L.count, stream, ck,
                                 e0, e1));
             blk0 += L.count;
         }
-        if (b->timed)
-            note(hipMemcpyAsync(hb + off_clock, db + off_clock, 16 * (size_t)blk0, hipMemcpyDeviceToHost, stream));
         b->ev_done = get_event();
         note(hipEventRecord(b->ev_done, stream));
         b->t_hip = now_seconds() - b->t_hip;
