@@ -10,8 +10,11 @@ assembly with plain FP64 entries is timed beside it.  The request latencies
 (submit -> completion) of the timed steps give p50/p99.
 
 The roofline object is for the dominant kernel (largest summed duration):
-algorithmic flops per launch / mean launch duration, both from the server's
-HIP events around each launch on its stream.  `cpu_baseline` times the FP64
+algorithmic flops per launch / mean launch duration, the duration from the
+server's HIP events around each launch on its stream (what rocprofv3's
+kernel trace also reports); the workgroups' own device-clock span (first
+start to last end, without the dispatch and drain around it) is reported
+beside it.  `cpu_baseline` times the FP64
 oracle on a bounded sample of the same ACA row requests on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
@@ -174,9 +177,9 @@ def roofline(kstats):
     dom = max(main, key=lambda k: k["seconds"])
     flops = dom["pair_evals"] * FLOPS_PER_EVAL[(dom["op"], dom["space"])]
     per_launch = flops / dom["launches"]
-    mean_s = dom["seconds"] / dom["launches"]            # kernel execution, device clock
-    mean_ev = dom["seconds_events"] / dom["launches"]    # HIP events around the launch
-    achieved = per_launch / mean_s / 1e12
+    mean_ev = dom["seconds_events"] / dom["launches"]    # HIP events around the launch, on its stream
+    mean_dc = dom["seconds"] / dom["launches"]           # first workgroup start to last workgroup end
+    achieved = per_launch / mean_ev / 1e12
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -187,12 +190,13 @@ def roofline(kstats):
                                    dom["op"], dom["quad_points"])
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_VALU / 1e12, 1),
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_VALU, 4), "traffic": traffic,
-            "kernel": name, "launches": dom["launches"], "mean_launch_us": round(mean_s * 1e6, 2),
-            "mean_launch_us_hip_events": round(mean_ev * 1e6, 2),
+            "kernel": name, "launches": dom["launches"], "mean_launch_us": round(mean_ev * 1e6, 2),
+            "mean_launch_us_device_clock": round(mean_dc * 1e6, 2),
+            "frac_device_clock": round(per_launch / mean_dc / PEAK_FP32_VALU, 4),
             "flops_per_launch": per_launch, "flops_per_eval": FLOPS_PER_EVAL[(dom["op"], dom["space"])],
             "executed_flops_per_eval": FLOPS_EXECUTED[(dom["op"], dom["space"])],
             "executed_tflops": round(dom["pair_evals"] * FLOPS_EXECUTED[(dom["op"], dom["space"])] /
-                                     dom["launches"] / mean_s / 1e12, 3),
+                                     dom["launches"] / mean_ev / 1e12, 3),
             "frac_of_packed_fp32_peak": round(achieved * 1e12 / PEAK_FP32_PACKED, 4)}
     return roof, dom
 

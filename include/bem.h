@@ -151,7 +151,8 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
 /* ---- request server ---------------------------------------------------- */
 /* Size the request server (Section 4's block threads are replaced by it):
  * arena_bytes of device memory (and the same amount of pinned host staging),
- * split into 8 batch slots, hold the batches in flight, so a batch admits
+ * split into up to 16 batch slots (one per MiB of arena, at least 2), hold
+ * the batches in flight, so a batch admits
  * requests while their inputs, outputs and tables fit one slot (admission by
  * memory; a single request larger than a slot fails with BEM_E_OOM);
  * max_batch_requests bounds how many requests one fused launch takes.

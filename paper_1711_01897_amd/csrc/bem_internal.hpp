@@ -67,7 +67,8 @@ struct ReqDev {
 };
 
 struct EntryBlock {  // one workgroup of entry work (64 bytes, read with one scalar load)
-    int32_t req;
+    int32_t req;           // (request index << 1) | 1 if the test side is fixed (row request): the kernel
+                           // picks its code path before the request descriptor arrives
     int32_t fixed;         // fixed position
     int32_t s0, s1;        // P1: the fixed dof's star, entries [s0, s1) of the mesh star table; P0: s0 = the fixed triangle
     int4 chunk;            // lane side: first lane, lanes, first dof, dofs
@@ -252,6 +253,9 @@ void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t 
 // Server
 int server_submit(Request *r);
 int server_submit_many(Request *const *rs, size_t n);
+// With BEM_DEBUG_TIMING set: prints and resets per-phase host times of the
+// dispatch and completion threads (stderr).
+void server_print_phases();
 int server_wait(Request *r, double timeout_s);
 void server_release(Request *r);           // return a borrowed result
 void server_release_batch(void *batch, int n);   // return n borrowed results of one batch (Request::batch)

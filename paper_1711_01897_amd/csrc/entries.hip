@@ -499,8 +499,8 @@ __global__ __launch_bounds__(kBlockLanes) void k_p0_f32(const ReqDev *__restrict
     if ((int64_t)blockIdx.x >= nblocks) return;
     clock_start(tclock);
     const EntryBlock B = blocks[blockIdx.x];
-    const ReqDev &R = reqs[B.req];
-    if (R.rowfix)
+    const ReqDev &R = reqs[B.req >> 1];
+    if (B.req & 1)
         p0_body_f32<OP, Q, true>(R, B);
     else
         p0_body_f32<OP, Q, false>(R, B);
@@ -548,8 +548,8 @@ __global__ __launch_bounds__(kBlockLanes) void k_p0_f64(const ReqDev *__restrict
     if ((int64_t)blockIdx.x >= nblocks) return;
     clock_start(tclock);
     const EntryBlock B = blocks[blockIdx.x];
-    const ReqDev &R = reqs[B.req];
-    if (R.rowfix)
+    const ReqDev &R = reqs[B.req >> 1];
+    if (B.req & 1)
         p0_body_f64<OP, Q, true>(R, B);
     else
         p0_body_f64<OP, Q, false>(R, B);
@@ -752,8 +752,8 @@ __global__ __launch_bounds__(kBlockLanes) void k_p1_f32(const ReqDev *__restrict
     if ((int64_t)blockIdx.x >= nblocks) return;
     clock_start(tclock);
     const EntryBlock B = blocks[blockIdx.x];
-    const ReqDev &R = reqs[B.req];
-    if (R.rowfix)
+    const ReqDev &R = reqs[B.req >> 1];
+    if (B.req & 1)
         p1_body_f32<OP, Q, true>(R, B, sG, sV, sL, sP);
     else
         p1_body_f32<OP, Q, false>(R, B, sG, sV, sL, sP);
@@ -853,8 +853,8 @@ __global__ __launch_bounds__(kBlockLanes) void k_p1_f64(const ReqDev *__restrict
     if ((int64_t)blockIdx.x >= nblocks) return;
     clock_start(tclock);
     const EntryBlock B = blocks[blockIdx.x];
-    const ReqDev &R = reqs[B.req];
-    if (R.rowfix)
+    const ReqDev &R = reqs[B.req >> 1];
+    if (B.req & 1)
         p1_body_f64<OP, Q, true>(R, B, sG, sV, sL, sP);
     else
         p1_body_f64<OP, Q, false>(R, B, sG, sV, sL, sP);

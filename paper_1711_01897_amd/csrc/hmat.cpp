@@ -922,6 +922,7 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
         fprintf(stderr, "[bem] worker us/request: busy %.3f convert %.3f aca %.3f release %.3f prepare %.3f submit %.3f\n",
                 1e6 * C.busy / np, 1e6 * C.t_conv / np, 1e6 * C.t_aca / np, 1e6 * C.t_rel / np, 1e6 * C.t_prep / np,
                 1e6 * C.t_flush / np);
+        server_print_phases();
     }
     *out = h;
     return BEM_OK;

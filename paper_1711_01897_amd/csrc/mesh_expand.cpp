@@ -303,7 +303,7 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
         }
         for (int32_t c = 0; c < (int32_t)r.nchunk; ++c) {
             EntryBlock &b = out[n++];
-            b.req = ri;
+            b.req = (ri << 1) | (r.rowfix ? 1 : 0);
             b.fixed = f;
             b.s0 = s0;
             b.s1 = s1;

@@ -27,6 +27,7 @@
 // Each request's result is computed by the same workgroups with the same
 // summation order whichever batch it lands in.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -94,12 +95,22 @@ class Server {
 public:
     size_t arena_bytes = size_t(1) << 30;
     int max_batch = 16384;
-    int nslots = 8;     // BEM_SERVER_SLOTS
+    int nslots = 16;    // BEM_SERVER_SLOTS; by default one per MiB of arena, 2 to kMaxSlots
     int nstreams = 4;   // BEM_SERVER_STREAMS (slot s uses stream s % nstreams), default one per hardware queue
     int ndisp = 1;      // BEM_SERVER_DISPATCHERS
     int ncomp = 1;      // BEM_SERVER_COMPLETERS
     bool spin = false;       // BEM_SERVER_SPIN: completion threads poll batch events instead of blocking
+    // BEM_SERVER_MIN_BATCH / BEM_SERVER_MAX_WAIT_US: a batch is taken once
+    // this many requests are pending or the oldest has waited this long
+    // (defaults 1 and 0: take whatever is pending)
+    int min_batch = 1;
+    double max_wait_s = 0.0;
     bool log_launches = false;   // BEM_DEBUG_LAUNCHES: print each timed launch (grid, duration) to stderr
+    bool time_phases = false;    // BEM_DEBUG_TIMING: per-phase host seconds of dispatch and completion
+    // dispatch: group, layout, blocks, inputs+descriptors, enqueue; completion: wait, statistics, statuses,
+    // callbacks, release
+    double ph_disp[5] = {}, ph_comp[5] = {};
+    int64_t ph_nd = 0, ph_nc = 0;
 
     std::mutex mu;
     std::condition_variable cv;    // dispatchers: pending requests, free slots
@@ -131,7 +142,11 @@ public:
     int start()
     {
         if (started) return BEM_OK;
-        nslots = env_int("BEM_SERVER_SLOTS", nslots, 2, kMaxSlots);
+        // a slot stays busy until the workers hand back the results they
+        // borrowed from it, so more slots keep more batches moving; small
+        // arenas keep slots of at least 1 MiB
+        const int def_slots = (int)std::min<size_t>(kMaxSlots, std::max<size_t>(2, arena_bytes >> 20));
+        nslots = env_int("BEM_SERVER_SLOTS", def_slots, 2, kMaxSlots);
         // one stream per hardware queue: streams that share a queue run
         // their packets in one order, so more streams than queues only
         // serialise batches behind each other
@@ -140,7 +155,10 @@ public:
         ndisp = env_int("BEM_SERVER_DISPATCHERS", ndisp, 1, kMaxThreads);
         ncomp = env_int("BEM_SERVER_COMPLETERS", ncomp, 1, kMaxThreads);
         spin = env_int("BEM_SERVER_SPIN", spin ? 1 : 0, 0, 1) != 0;
+        min_batch = env_int("BEM_SERVER_MIN_BATCH", 1, 1, 1 << 20);
+        max_wait_s = 1e-6 * env_int("BEM_SERVER_MAX_WAIT_US", 0, 0, 1000000);
         log_launches = env_int("BEM_DEBUG_LAUNCHES", 0, 0, 1) != 0;
+        time_phases = std::getenv("BEM_DEBUG_TIMING") != nullptr;
         hipError_t e = hipGetDevice(&device);
         int khz = 0;
         if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
@@ -294,6 +312,13 @@ public:
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv.wait(lk, [&] { return stop || (!pending.empty() && free_slot() >= 0); });
+                while (!stop && min_batch > 1 && (int)pending.size() < min_batch) {
+                    const double waited = now_seconds() - pending.front()->t_submit;
+                    if (waited >= max_wait_s) break;
+                    cv.wait_for(lk, std::chrono::duration<double>(max_wait_s - waited));
+                    if (pending.empty() || free_slot() < 0)
+                        cv.wait(lk, [&] { return stop || (!pending.empty() && free_slot() >= 0); });
+                }
                 if (stop) {
                     std::vector<Request *> left(pending.begin(), pending.end());
                     pending.clear();
@@ -346,6 +371,8 @@ public:
         char *db = d_arena + (size_t)slot * slot_bytes;
         hipStream_t stream = streams[slot % nstreams];
         const int n = (int)take.size();
+        double tp[6] = {};
+        if (time_phases) tp[0] = now_seconds();
 
         // launch groups by (op, space, prec, rule)
         for (auto &g : sc.members) g.clear();
@@ -371,6 +398,7 @@ public:
             launches.push_back(L);
         }
 
+        if (time_phases) tp[1] = now_seconds();
         // layout: descriptors | block tables | inputs  (copied to the device
         // arena by a kernel) || clock records | status | outputs  (stored by
         // the kernels into the staging)
@@ -407,12 +435,14 @@ public:
         }
 
         // staging writes
+        if (time_phases) tp[2] = now_seconds();
         static_assert(sizeof(EntryBlock) == 64, "block records are 64 bytes");
         for (const Launch &L : launches) {
             EntryBlock *p = reinterpret_cast<EntryBlock *>(hb + L.off_tab);
             int64_t k = 0;
             for (int i : sc.members[L.key]) k += write_blocks(*take[i], i, p + k);
         }
+        if (time_phases) tp[3] = now_seconds();
         ReqDev *hreq = reinterpret_cast<ReqDev *>(hb);
         size_t in = off_in;
         for (int i = 0; i < n; ++i) in += stage_request_inputs(*take[i], hb, db, in, hreq[i]);
@@ -453,6 +483,13 @@ public:
         b->ev_done = get_event();
         note(hipEventRecord(b->ev_done, stream));
         b->t_hip = now_seconds() - b->t_hip;
+        if (time_phases) {
+            tp[4] = b->t_launch;
+            tp[5] = now_seconds();
+            std::lock_guard<std::mutex> g(stat_mu);
+            for (int i = 0; i < 5; ++i) ph_disp[i] += tp[i + 1] - tp[i];
+            ph_nd += 1;
+        }
         return b;
     }
 
@@ -493,6 +530,7 @@ public:
             }
             if (e == hipSuccess) e = b->enqueue_error;
             const double t_done = now_seconds();
+            double tc[6] = {tw0, t_done, 0, 0, 0, 0};
             double ks = 0.0;
             std::vector<double> dur(b->launches.size(), 0.0), dev(b->launches.size(), 0.0);
             if (b->timed && e == hipSuccess) {
@@ -555,6 +593,7 @@ public:
                     k.seconds_events += dur[i];
                 }
             }
+            if (time_phases) tc[2] = now_seconds();
             char *hb = h_stage + (size_t)b->slot * slot_bytes;
             std::vector<Request *> reqs;
             reqs.swap(b->reqs);
@@ -581,10 +620,18 @@ public:
             b->refs.fetch_add(lent);  // before any borrower can release
             const double nreq = (double)reqs.size();
             const double leg_q = b->q_sum, leg_s = nreq * (b->t_enq - b->t_take), leg_d = nreq * (t_done - b->t_enq);
+            if (time_phases) tc[3] = now_seconds();
             finish_all(reqs, sts);
+            if (time_phases) tc[4] = now_seconds();
             release_batch(b);   // b may be gone from here on
             {
                 const double t_fin = now_seconds();
+                if (time_phases) {
+                    tc[5] = t_fin;
+                    std::lock_guard<std::mutex> g(stat_mu);
+                    for (int i = 0; i < 5; ++i) ph_comp[i] += tc[i + 1] - tc[i];
+                    ph_nc += 1;
+                }
                 std::lock_guard<std::mutex> g(stat_mu);
                 wait_s += t_done - tw0;
                 complete_s += t_fin - t_done;
@@ -720,6 +767,22 @@ int server_configure(size_t arena_bytes, int max_batch)
 int server_submit(Request *r) { return server().submit_many(&r, 1); }
 
 int server_submit_many(Request *const *rs, size_t n) { return server().submit_many(rs, n); }
+
+void server_print_phases()
+{
+    Server &S = server();
+    std::lock_guard<std::mutex> g(S.stat_mu);
+    if (!S.time_phases || S.ph_nd == 0 || S.ph_nc == 0) return;
+    const double d = 1e6 / (double)S.ph_nd, c = 1e6 / (double)S.ph_nc;
+    fprintf(stderr, "[bem] dispatch us/batch: group %.2f layout %.2f blocks %.2f inputs %.2f enqueue %.2f (%lld batches)\n",
+            S.ph_disp[0] * d, S.ph_disp[1] * d, S.ph_disp[2] * d, S.ph_disp[3] * d, S.ph_disp[4] * d,
+            (long long)S.ph_nd);
+    fprintf(stderr, "[bem] completion us/batch: wait %.2f stats %.2f statuses %.2f callbacks %.2f release %.2f\n",
+            S.ph_comp[0] * c, S.ph_comp[1] * c, S.ph_comp[2] * c, S.ph_comp[3] * c, S.ph_comp[4] * c);
+    for (double &x : S.ph_disp) x = 0.0;
+    for (double &x : S.ph_comp) x = 0.0;
+    S.ph_nd = S.ph_nc = 0;
+}
 
 int server_wait(Request *r, double timeout_s)
 {
