@@ -191,6 +191,7 @@ def roofline(kstats):
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_VALU / 1e12, 1),
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_VALU, 4), "traffic": traffic,
             "kernel": name, "launches": dom["launches"], "mean_launch_us": round(mean_ev * 1e6, 2),
+            "workgroups_per_launch": round(dom["workgroups"] / dom["launches"], 1),
             "mean_launch_us_device_clock": round(mean_dc * 1e6, 2),
             "frac_device_clock": round(per_launch / mean_dc / PEAK_FP32_VALU, 4),
             "flops_per_launch": per_launch, "flops_per_eval": FLOPS_PER_EVAL[(dom["op"], dom["space"])],
