@@ -6,8 +6,9 @@ library ``paper_1711_01897_amd`` and imports nothing from it.
 
 Contents
   * ``OracleMesh`` (C, ``bem_oracle.c``): geometry, Gauss rules, kernels and
-    P0/P1 Galerkin entries of the Laplace/Helmholtz single and double layer
-    over regular triangle pairs (Section 2, Eqs. slp, dlp; Section 3.2).
+    P0/P1 Galerkin entries of the Laplace/Helmholtz single, double and
+    adjoint double layer over regular triangle pairs (Section 2, Eqs. slp,
+    dlp, adlp; Section 3.2).
   * near-field fixture (C, ``nearfield.c``): analytic inner integrals for the
     closed-form sphere checks only.
   * ``oracle.aca``: adaptive cross approximation, Algorithm "ACA" of
@@ -25,9 +26,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 LAPLACE_SLP, LAPLACE_DLP, HELMHOLTZ_SLP, HELMHOLTZ_DLP = 0, 1, 2, 3
+LAPLACE_ADLP, HELMHOLTZ_ADLP = 4, 5
 P0, P1 = 0, 1
 NEAR_ERROR, NEAR_SKIP = 0, 1
-OPS = {"laplace_slp": 0, "laplace_dlp": 1, "helmholtz_slp": 2, "helmholtz_dlp": 3}
+OPS = {"laplace_slp": 0, "laplace_dlp": 1, "helmholtz_slp": 2, "helmholtz_dlp": 3, "laplace_adlp": 4,
+       "helmholtz_adlp": 5}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -117,7 +120,7 @@ def tri_solid_angle(v0, v1, v2, x) -> float:
 
 
 def is_complex(op: int) -> bool:
-    return op in (HELMHOLTZ_SLP, HELMHOLTZ_DLP)
+    return op in (HELMHOLTZ_SLP, HELMHOLTZ_DLP, HELMHOLTZ_ADLP)
 
 
 class NearFieldError(RuntimeError):

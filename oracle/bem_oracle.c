@@ -11,6 +11,9 @@
  *   single layer (Eq. slp)  [S]_ij = int_Ti int_Tj psi_i(x) g(x,y) phi_j(y)
  *   double layer (Eq. dlp)  [K]_ij = same with dg/dn_y (normal of the trial
  *                                    triangle, which carries y)
+ *   adjoint double layer (Eq. adlp)
+ *                           [K']_ij = same with dg/dn_x (normal of the test
+ *                                    triangle, which carries x)
  *   Green's function (Section 2, after Eq. hypsHelmholtz)
  *                           g = exp(i k r) / (4 pi r),  r = |x - y|,
  *                           Laplace is k = 0.
@@ -85,9 +88,12 @@ int orc_rule(int npts, double *xi, double *eta, double *w)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Kernel g or dg/dn_y at one point pair; out = (re, im).                     */
-void orc_kernel(int op, double k, const double *x, const double *y, const double *ny, double *out)
+/* Kernel g, dg/dn_y or dg/dn_x at one point pair; out = (re, im).  `nrm` is
+ * n_y (trial normal) for the double layer and n_x (test normal) for the
+ * adjoint double layer.                                                      */
+void orc_kernel(int op, double k, const double *x, const double *y, const double *nrm, double *out)
 {
+    const double *ny = nrm, *nx = nrm;
     double d0 = x[0] - y[0], d1 = x[1] - y[1], d2 = x[2] - y[2];
     double r = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
     double g = 1.0 / (4.0 * ORC_PI * r);
@@ -113,6 +119,22 @@ void orc_kernel(int op, double k, const double *x, const double *y, const double
         double c = cos(k * r), s = sin(k * r);
         double f = g * dn / (r * r);
         /* (c + i s)(1 - i k r) = (c + s k r) + i (s - c k r) */
+        out[0] = f * (c + s * k * r);
+        out[1] = f * (s - c * k * r);
+        return;
+    }
+    case ORC_LAPLACE_ADLP: {
+        /* d/dn_x of 1/(4 pi |x-y|) = (y-x).n_x / (4 pi r^3) */
+        double dn = -(d0 * nx[0] + d1 * nx[1] + d2 * nx[2]);
+        out[0] = g * dn / (r * r);
+        out[1] = 0.0;
+        return;
+    }
+    case ORC_HELMHOLTZ_ADLP: {
+        /* d/dn_x exp(ikr)/(4 pi r) = exp(ikr) (1 - ikr) (y-x).n_x / (4 pi r^3) */
+        double dn = -(d0 * nx[0] + d1 * nx[1] + d2 * nx[2]);
+        double c = cos(k * r), s = sin(k * r);
+        double f = g * dn / (r * r);
         out[0] = f * (c + s * k * r);
         out[1] = f * (s - c * k * r);
         return;
@@ -212,6 +234,7 @@ void orc_pair(const orc_mesh *m, int op, double k, int64_t tm, int64_t tn,
               int a, int b, double *re, double *im)
 {
     const int q = m->q;
+    const int adj = op == ORC_LAPLACE_ADLP || op == ORC_HELMHOLTZ_ADLP;
     double sr = 0.0, si = 0.0;
     for (int p = 0; p < q; ++p) {
         const double *x = m->qp + (tm * q + p) * 3;
@@ -220,7 +243,7 @@ void orc_pair(const orc_mesh *m, int op, double k, int64_t tm, int64_t tn,
             const double *y = m->qp + (tn * q + qq) * 3;
             double wq = m->qw[qq] * (b < 0 ? 1.0 : orc_basis(m, b, qq));
             double kv[2];
-            orc_kernel(op, k, x, y, m->n + 3 * tn, kv);
+            orc_kernel(op, k, x, y, m->n + 3 * (adj ? tm : tn), kv);
             sr += wp * wq * kv[0];
             si += wp * wq * kv[1];
         }
@@ -272,7 +295,10 @@ static int orc_entry(const orc_mesh *m, int op, int space, double k, int64_t row
     return ORC_OK;
 }
 
-static int orc_is_complex(int op) { return op == ORC_HELMHOLTZ_SLP || op == ORC_HELMHOLTZ_DLP; }
+static int orc_is_complex(int op)
+{
+    return op == ORC_HELMHOLTZ_SLP || op == ORC_HELMHOLTZ_DLP || op == ORC_HELMHOLTZ_ADLP;
+}
 
 /* Sub-block A[rows, cols], row-major; complex operators write interleaved
  * (re, im).  nthreads <= 0 uses the OpenMP default.  Entries are independent;
@@ -281,7 +307,7 @@ int orc_entries(const orc_mesh *m, int op, int space, double k,
                 const int32_t *rows, int64_t nr, const int32_t *cols, int64_t nc,
                 int near, double *out, int nthreads)
 {
-    if (op < 0 || op > 3 || (space != ORC_P0 && space != ORC_P1)) return ORC_E_ARG;
+    if (op < 0 || op > 5 || (space != ORC_P0 && space != ORC_P1)) return ORC_E_ARG;
     int64_t ndof = space == ORC_P0 ? m->nt : m->nv;
     for (int64_t r = 0; r < nr; ++r)
         if (rows[r] < 0 || rows[r] >= ndof) return ORC_E_ARG;

@@ -10,7 +10,14 @@
 #define ORC_E_ARG (-1)
 #define ORC_E_NEARFIELD (-4)
 
-enum { ORC_LAPLACE_SLP = 0, ORC_LAPLACE_DLP = 1, ORC_HELMHOLTZ_SLP = 2, ORC_HELMHOLTZ_DLP = 3 };
+enum {
+    ORC_LAPLACE_SLP = 0,
+    ORC_LAPLACE_DLP = 1,
+    ORC_HELMHOLTZ_SLP = 2,
+    ORC_HELMHOLTZ_DLP = 3,
+    ORC_LAPLACE_ADLP = 4,
+    ORC_HELMHOLTZ_ADLP = 5
+};
 enum { ORC_P0 = 0, ORC_P1 = 1 };
 enum { ORC_NEAR_ERROR = 0, ORC_NEAR_SKIP = 1 };
 
@@ -30,7 +37,7 @@ typedef struct {
 } orc_mesh;
 
 int orc_rule(int npts, double *xi, double *eta, double *w);
-void orc_kernel(int op, double k, const double *x, const double *y, const double *ny, double *out);
+void orc_kernel(int op, double k, const double *x, const double *y, const double *nrm, double *out);
 int orc_adjacent(const orc_mesh *m, int64_t a, int64_t b);
 void orc_pair(const orc_mesh *m, int op, double k, int64_t tm, int64_t tn,
               int a, int b, double *re, double *im);

@@ -274,3 +274,26 @@ def test_icosphere_level3_regular_pair_count(ico):
             share |= tri[:, k][:, None] == tri[:, l][None, :]
     assert int(share.sum()) == 16580
     assert np.array_equal(share, A == 0)
+
+
+@pytest.mark.parametrize("space", [O.P0, O.P1])
+@pytest.mark.parametrize("pair,k", [((O.LAPLACE_ADLP, O.LAPLACE_DLP), 0.0), ((O.HELMHOLTZ_ADLP, O.HELMHOLTZ_DLP), 2.3)])
+def test_adjoint_double_layer_is_transposed_double_layer(space, pair, k, ico):
+    """Eqs. dlp and adlp with the same space and rule on both sides:
+    [K'_h]_ij = [K_h]_ji (the summation order differs, so not bitwise).  A
+    jittered mesh keeps K_h far from symmetric, so a double layer returned
+    for the adjoint, a dropped sign or the trial normal in place of the test
+    normal all fail."""
+    xyz, tri = ico(2)
+    rng = np.random.Generator(np.random.PCG64(3))
+    xyz = xyz * (1.0 + 0.08 * rng.uniform(-1, 1, size=(xyz.shape[0], 1)))
+    m = O.OracleMesh(xyz, tri, 6)
+    n = m.nt if space == O.P0 else m.nv
+    rows = rng.choice(n, 40, replace=False)
+    cols = rng.choice(n, 55, replace=False)
+    adj, dl = pair
+    A = m.entries(adj, space, k, rows, cols, near=O.NEAR_SKIP)
+    K = m.entries(dl, space, k, cols, rows, near=O.NEAR_SKIP)
+    scale = np.abs(K).max()
+    assert np.abs(A - K.T).max() <= 1e-13 * scale
+    assert np.abs(A - m.entries(dl, space, k, rows, cols, near=O.NEAR_SKIP)).max() > 1e-3 * scale

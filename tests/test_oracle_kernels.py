@@ -1,7 +1,8 @@
-"""Pins of the oracle's Green's function and its normal derivative.
+"""Pins of the oracle's Green's function and its normal derivatives.
 
 g(x,y) = exp(i k r)/(4 pi r) (Section 2, Green's function of the Helmholtz
-equation, Laplace at k = 0); the double layer uses dg/dn_y (Eq. dlp).
+equation, Laplace at k = 0); the double layer uses dg/dn_y (Eq. dlp), the
+adjoint double layer dg/dn_x (Eq. adlp).
 """
 import math
 
@@ -84,3 +85,26 @@ def test_helmholtz_phase_convention_outgoing():
             dphi = np.angle(g / prev[0])
             assert abs(dphi - k * (r - prev[1])) < 1e-12
         prev = (g, r)
+
+
+@pytest.mark.parametrize("op,k", [(O.LAPLACE_ADLP, 0.0), (O.HELMHOLTZ_ADLP, 2.7), (O.HELMHOLTZ_ADLP, 11.0)])
+def test_adjoint_double_layer_is_normal_derivative_in_x(op, k):
+    slp = O.LAPLACE_SLP if op == O.LAPLACE_ADLP else O.HELMHOLTZ_SLP
+    eps = 1e-5
+    for _ in range(10):
+        x, y, n = RNG.normal(size=3), RNG.normal(size=3), unit(RNG.normal(size=3))
+        fd = (O.kernel(slp, k, x + eps * n, y, n) - O.kernel(slp, k, x - eps * n, y, n)) / (2 * eps)
+        d = O.kernel(op, k, x, y, n)
+        assert abs(fd - d) <= 1e-7 * abs(d) + 1e-12
+
+
+@pytest.mark.parametrize("pair,k", [((O.LAPLACE_ADLP, O.LAPLACE_DLP), 0.0), ((O.HELMHOLTZ_ADLP, O.HELMHOLTZ_DLP), 4.2)])
+def test_adjoint_kernel_is_double_layer_with_points_exchanged(pair, k):
+    """g is symmetric in (x, y), so dg/dn_x at (x, y) is dg/dn_y at (y, x)
+    with the same normal."""
+    adj, dl = pair
+    for _ in range(10):
+        x, y, n = RNG.normal(size=3), RNG.normal(size=3), unit(RNG.normal(size=3))
+        a = O.kernel(adj, k, x, y, n)
+        d = O.kernel(dl, k, y, x, n)
+        assert abs(a - d) <= 1e-15 * abs(d)
