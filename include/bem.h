@@ -8,10 +8,15 @@
  *
  *   single layer, Eq. (slp):  A_ij = int_Gi int_Gj psi_i(x) g(x,y)     phi_j(y)
  *   double layer, Eq. (dlp):  A_ij = int_Gi int_Gj psi_i(x) dg/dn_y    phi_j(y)
+ *   adjoint double layer, Eq. (adlp):
+ *                             A_ij = int_Gi int_Gj psi_i(x) dg/dn_x    phi_j(y)
  *   g(x,y) = exp(i k |x-y|) / (4 pi |x-y|)   (Helmholtz; Laplace is k = 0)
  *
  * Row i is the test function psi_i (variable x), column j the trial function
- * phi_j (variable y); n_y is the unit normal of the trial triangle.  Basis
+ * phi_j (variable y); n_y is the unit normal of the trial triangle, n_x that
+ * of the test triangle.  With the same space and rule on both sides the
+ * adjoint double layer is the transposed double layer, A'_ij = K_ji, and is
+ * evaluated that way (the same kernels with test and trial exchanged).  Basis
  * functions: P0 (one dof per triangle, the indicator of the triangle) or P1
  * (one dof per vertex, the continuous piecewise-linear hat function).
  * Both integrals use the same symmetric Gauss rule per triangle (Section
@@ -63,7 +68,14 @@ extern "C" {
 #define BEM_E_TIMEOUT (-7)    /* wait timed out; the request is still pending */
 #define BEM_E_INTERNAL (-8)   /* internal inconsistency */
 
-typedef enum { BEM_LAPLACE_SLP = 0, BEM_LAPLACE_DLP = 1, BEM_HELMHOLTZ_SLP = 2, BEM_HELMHOLTZ_DLP = 3 } bem_op;
+typedef enum {
+    BEM_LAPLACE_SLP = 0,
+    BEM_LAPLACE_DLP = 1,
+    BEM_HELMHOLTZ_SLP = 2,
+    BEM_HELMHOLTZ_DLP = 3,
+    BEM_LAPLACE_ADLP = 4,
+    BEM_HELMHOLTZ_ADLP = 5
+} bem_op;
 typedef enum { BEM_P0 = 0, BEM_P1 = 1 } bem_space;
 /* BEM_FP64: plain FP64 quadrature.  BEM_FP32: FP32 quadrature with
  * compensated (TwoSum) accumulation, centroid-relative geometry and, for

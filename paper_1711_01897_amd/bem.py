@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbem.so")
 
 LAPLACE_SLP, LAPLACE_DLP, HELMHOLTZ_SLP, HELMHOLTZ_DLP = 0, 1, 2, 3
+LAPLACE_ADLP, HELMHOLTZ_ADLP = 4, 5
 P0, P1 = 0, 1
 FP64, FP32 = 0, 1
 NEAR_ERROR, NEAR_SKIP = 0, 1
@@ -162,7 +163,7 @@ def _idx(a):
 
 
 def is_complex(op):
-    return op in (HELMHOLTZ_SLP, HELMHOLTZ_DLP)
+    return op in (HELMHOLTZ_SLP, HELMHOLTZ_DLP, HELMHOLTZ_ADLP)
 
 
 def out_dtype(op, prec):

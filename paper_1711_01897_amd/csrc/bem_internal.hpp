@@ -201,7 +201,9 @@ struct Request {
     void *batch = nullptr;      // batch holding a borrowed result
 
     // expansion
-    int rowfix = 1;
+    int fixrows = 1;            // the fixed items are the request's rows (else its columns)
+    int rowfix = 1;             // kernel side: the fixed items are test functions (differs from fixrows
+                                // for the adjoint double layer, evaluated as the double layer transposed)
     std::vector<int32_t> fix;   // fixed side: P0 triangles; P1 star ranges [s0, s1) per fixed dof (2 each)
     LaneSet own;                       // lane side, when not external
     const LaneRef *ext = nullptr;      // device-resident lane side
@@ -233,6 +235,10 @@ struct Request {
 };
 
 bool is_complex_op(int op);
+bool is_adjoint_op(int op);
+// The operator the entry kernels evaluate: the adjoint double layer runs as
+// the double layer with test and trial exchanged.
+int kernel_op(int op);
 size_t out_elem_bytes(int op, int prec);
 
 // Validate and expand a request (host; runs on the submitting thread).

@@ -253,7 +253,7 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     pinned_release(host, e == hipSuccess ? ev : nullptr);
     if (e != hipSuccess) return fail(BEM_E_DEVICE, std::string("staging copy: ") + hipGetErrorString(e));
     const ReqDev *dreq = (const ReqDev *)(ws + off_req);
-    Variant v{r.op, r.space, r.prec, mesh->q};
+    Variant v{kernel_op(r.op), r.space, r.prec, mesh->q};
     BEM_HIP_TRY(launch_entries(v, dreq, (const EntryBlock *)(ws + off_b), r.nblocks, s));
     BEM_HIP_TRY(hipFreeAsync(ws, s));
     return BEM_OK;

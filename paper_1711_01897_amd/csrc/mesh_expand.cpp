@@ -42,7 +42,19 @@ double now_seconds()
     return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
 }
 
-bool is_complex_op(int op) { return op == BEM_HELMHOLTZ_SLP || op == BEM_HELMHOLTZ_DLP; }
+bool is_complex_op(int op)
+{
+    return op == BEM_HELMHOLTZ_SLP || op == BEM_HELMHOLTZ_DLP || op == BEM_HELMHOLTZ_ADLP;
+}
+
+bool is_adjoint_op(int op) { return op == BEM_LAPLACE_ADLP || op == BEM_HELMHOLTZ_ADLP; }
+
+int kernel_op(int op)
+{
+    if (op == BEM_LAPLACE_ADLP) return BEM_LAPLACE_DLP;
+    if (op == BEM_HELMHOLTZ_ADLP) return BEM_HELMHOLTZ_DLP;
+    return op;
+}
 
 size_t out_elem_bytes(int op, int prec)
 {
@@ -174,7 +186,7 @@ void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n
 int expand_request(Request &r)
 {
     const bem_mesh &m = *r.mesh;
-    if (r.op < 0 || r.op > 3) return fail(BEM_E_ARG, "unknown operator");
+    if (r.op < 0 || r.op > 5) return fail(BEM_E_ARG, "unknown operator");
     if (r.space != BEM_P0 && r.space != BEM_P1) return fail(BEM_E_ARG, "unknown space");
     if (r.prec != BEM_FP32 && r.prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
     if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP) return fail(BEM_E_ARG, "unknown near-field policy");
@@ -191,9 +203,13 @@ int expand_request(Request &r)
     if (r.nrows > INT32_MAX || r.ncols > INT32_MAX) return fail(BEM_E_ARG, "request dimension too large");
 
     r.ext = nullptr;
-    r.rowfix = r.ncols >= r.nrows ? 1 : 0;
-    const std::vector<int32_t> &fix_dofs = r.rowfix ? r.rows : r.cols;
-    const std::vector<int32_t> &lane_dofs = r.rowfix ? r.cols : r.rows;
+    // the smaller side is fixed; an adjoint double layer is evaluated as the
+    // double layer with test and trial exchanged (Eqs. dlp, adlp:
+    // [K'_h]_ij = [K_h]_ji for the same space on both sides)
+    r.fixrows = r.ncols >= r.nrows ? 1 : 0;
+    r.rowfix = is_adjoint_op(r.op) ? 1 - r.fixrows : r.fixrows;
+    const std::vector<int32_t> &fix_dofs = r.fixrows ? r.rows : r.cols;
+    const std::vector<int32_t> &lane_dofs = r.fixrows ? r.cols : r.rows;
     expand_fixed(m, r.space, fix_dofs.data(), (int64_t)fix_dofs.size(), r);
     build_lane_set(m, r.space, lane_dofs.data(), (int64_t)lane_dofs.size(), r.own);
     r.nlane = (int64_t)r.own.lane.size();
@@ -206,7 +222,8 @@ int expand_request(Request &r)
 void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext)
 {
     r.ext = ext;
-    r.rowfix = rowfix;
+    r.fixrows = rowfix;
+    r.rowfix = is_adjoint_op(r.op) ? 1 - rowfix : rowfix;
     r.own.lane.clear();
     r.own.chunk.clear();
     r.own.seg_ptr.clear();
@@ -215,7 +232,7 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
     r.nlane = ext->nlane;
     r.nchunk = ext->nchunk;
     r.ndistinct = ext->ndistinct;
-    if (rowfix) {
+    if (r.fixrows) {
         r.nrows = 1;
         r.ncols = ext->ndof;
     } else {
@@ -260,7 +277,7 @@ size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t 
         d.seg = put(r.own.seg);
     }
     d.fstar = m.d_star;
-    if (r.rowfix) {
+    if (r.fixrows) {   // output position of (fixed f, lane-side dof d): out[f * sf + d * sl]
         d.sf = r.ncols;
         d.sl = 1;
     } else {

@@ -55,7 +55,10 @@ int env_int(const char *name, int dflt, int lo, int hi)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int entry_key(const Request &r) { return ((r.op * 2 + r.space) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0); }
+int entry_key(const Request &r)
+{
+    return ((kernel_op(r.op) * 2 + r.space) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0);
+}
 
 struct Launch {
     Variant v{};

@@ -60,6 +60,8 @@ def test_aca_block_rejects_near_pairs(sphere4):
 
 @pytest.mark.parametrize("op,space,k,prec", [(bem.LAPLACE_SLP, bem.P1, 0.0, bem.FP32),
                                              (bem.LAPLACE_DLP, bem.P1, 0.0, bem.FP64),
+                                             (bem.LAPLACE_ADLP, bem.P1, 0.0, bem.FP32),
+                                             (bem.HELMHOLTZ_ADLP, bem.P0, 4.0, bem.FP64),
                                              (bem.HELMHOLTZ_SLP, bem.P0, 4.0, bem.FP32)])
 def test_hmat_matvec_against_dense(op, space, k, prec):
     xyz, tri = inputs.icosphere(3)

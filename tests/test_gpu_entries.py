@@ -16,14 +16,15 @@ from paper_1711_01897_amd import bem, inputs
 
 pytestmark = pytest.mark.gpu
 
-OPS = [bem.LAPLACE_SLP, bem.LAPLACE_DLP, bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP]
-K = {bem.LAPLACE_SLP: 0.0, bem.LAPLACE_DLP: 0.0, bem.HELMHOLTZ_SLP: 7.5, bem.HELMHOLTZ_DLP: 7.5}
+OPS = [bem.LAPLACE_SLP, bem.LAPLACE_DLP, bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP, bem.LAPLACE_ADLP, bem.HELMHOLTZ_ADLP]
+K = {bem.LAPLACE_SLP: 0.0, bem.LAPLACE_DLP: 0.0, bem.HELMHOLTZ_SLP: 7.5, bem.HELMHOLTZ_DLP: 7.5,
+     bem.LAPLACE_ADLP: 0.0, bem.HELMHOLTZ_ADLP: 7.5}
 
 
 def tol(op, prec):
     if prec == bem.FP64:
         return 1e-11
-    return 1e-5 if op in (bem.LAPLACE_SLP, bem.LAPLACE_DLP) else 1e-4
+    return 1e-5 if op in (bem.LAPLACE_SLP, bem.LAPLACE_DLP, bem.LAPLACE_ADLP) else 1e-4
 
 
 def normwise(a, b):
@@ -80,6 +81,26 @@ def test_requests_vs_oracle(sphere2, op, space, prec):
         assert e <= tol(op, prec), (nr, nc, e)
         if op == bem.LAPLACE_SLP:
             assert entrywise(got.astype(np.float64), ref) <= (1e-12 if prec == bem.FP64 else 1e-5)
+
+
+@pytest.mark.parametrize("pair", [(bem.LAPLACE_ADLP, bem.LAPLACE_DLP), (bem.HELMHOLTZ_ADLP, bem.HELMHOLTZ_DLP)])
+@pytest.mark.parametrize("space", [bem.P0, bem.P1])
+@pytest.mark.parametrize("prec", [bem.FP64, bem.FP32])
+def test_adjoint_double_layer_is_exact_transpose(sphere2, pair, space, prec):
+    """The adjoint double layer runs as the double layer with test and trial
+    exchanged: A'[rows, cols] equals K[cols, rows]^T bit for bit, for both
+    fixed sides (short and long row lists)."""
+    xyz, tri, mesh, om = sphere2
+    adj, dl = pair
+    n = tri.shape[0] if space == bem.P0 else xyz.shape[0]
+    rng = np.random.Generator(np.random.PCG64(4))
+    for nr, nc in [(1, 120), (120, 1), (33, 77), (77, 33)]:
+        rows = rng.choice(n, nr, replace=False).astype(np.int32)
+        cols = rng.choice(n, nc, replace=False).astype(np.int32)
+        a = bem.eval_entries(mesh, adj, space, K[adj], rows, cols, prec=prec)
+        d = bem.eval_entries(mesh, dl, space, K[dl], cols, rows, prec=prec)
+        assert a.shape == (nr, nc)
+        assert np.array_equal(a, d.T)
 
 
 @pytest.mark.parametrize("prec", [bem.FP64, bem.FP32])
