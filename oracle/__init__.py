@@ -7,8 +7,9 @@ library ``paper_1711_01897_amd`` and imports nothing from it.
 Contents
   * ``OracleMesh`` (C, ``bem_oracle.c``): geometry, Gauss rules, kernels and
     P0/P1 Galerkin entries of the Laplace/Helmholtz single, double and
-    adjoint double layer over regular triangle pairs (Section 2, Eqs. slp,
-    dlp, adlp; Section 3.2).
+    adjoint double layer, and P1 entries of the hypersingular operator, over
+    regular triangle pairs (Section 2, Eqs. slp, dlp, adlp, hypsHelmholtz;
+    Section 3.2).
   * near-field fixture (C, ``nearfield.c``): analytic inner integrals for the
     closed-form sphere checks only.
   * ``oracle.aca``: adaptive cross approximation, Algorithm "ACA" of
@@ -27,10 +28,11 @@ _LIB = None
 
 LAPLACE_SLP, LAPLACE_DLP, HELMHOLTZ_SLP, HELMHOLTZ_DLP = 0, 1, 2, 3
 LAPLACE_ADLP, HELMHOLTZ_ADLP = 4, 5
+LAPLACE_HYPS, HELMHOLTZ_HYPS = 6, 7
 P0, P1 = 0, 1
 NEAR_ERROR, NEAR_SKIP = 0, 1
 OPS = {"laplace_slp": 0, "laplace_dlp": 1, "helmholtz_slp": 2, "helmholtz_dlp": 3, "laplace_adlp": 4,
-       "helmholtz_adlp": 5}
+       "helmholtz_adlp": 5, "laplace_hyps": 6, "helmholtz_hyps": 7}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int32)
@@ -120,7 +122,7 @@ def tri_solid_angle(v0, v1, v2, x) -> float:
 
 
 def is_complex(op: int) -> bool:
-    return op in (HELMHOLTZ_SLP, HELMHOLTZ_DLP, HELMHOLTZ_ADLP)
+    return op in (HELMHOLTZ_SLP, HELMHOLTZ_DLP, HELMHOLTZ_ADLP, HELMHOLTZ_HYPS)
 
 
 class NearFieldError(RuntimeError):

@@ -14,6 +14,11 @@
  *   adjoint double layer (Eq. adlp)
  *                           [K']_ij = same with dg/dn_x (normal of the test
  *                                    triangle, which carries x)
+ *   hypersingular (Eq. hypsHelmholtz), P1 only
+ *                           [D]_ij = int int g [curl psi_i . curl phi_j
+ *                                    - k^2 psi_i phi_j n_x . n_y]
+ *                           with curl u = n x grad_Gamma u, constant on each
+ *                           triangle for the hat functions
  *   Green's function (Section 2, after Eq. hypsHelmholtz)
  *                           g = exp(i k r) / (4 pi r),  r = |x - y|,
  *                           Laplace is k = 0.
@@ -260,6 +265,64 @@ static int orc_local_index(const orc_mesh *m, int64_t t, int64_t v)
     return -1;
 }
 
+/* Surface curl of the hat function of local vertex `loc` on triangle t:
+ * curl u = n x grad_Gamma u.  The surface gradient is taken through the
+ * triangle's metric: with tangents t1 = v1 - v0, t2 = v2 - v0 and the
+ * reference derivatives (dl/dxi, dl/deta) = (-1,-1), (1,0), (0,1) for local
+ * vertices 0, 1, 2, grad_Gamma l = sum_ij Ginv_ij (dl/dxi_i) t_j with
+ * G_ij = t_i . t_j.                                                          */
+static void orc_curl(const orc_mesh *m, int64_t t, int loc, double *out)
+{
+    const double *v0 = m->xyz + 3 * m->tri[3 * t], *v1 = m->xyz + 3 * m->tri[3 * t + 1],
+                 *v2 = m->xyz + 3 * m->tri[3 * t + 2];
+    double t1[3], t2[3];
+    for (int d = 0; d < 3; ++d) {
+        t1[d] = v1[d] - v0[d];
+        t2[d] = v2[d] - v0[d];
+    }
+    double g11 = t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2];
+    double g12 = t1[0] * t2[0] + t1[1] * t2[1] + t1[2] * t2[2];
+    double g22 = t2[0] * t2[0] + t2[1] * t2[1] + t2[2] * t2[2];
+    double det = g11 * g22 - g12 * g12;
+    double d1 = loc == 0 ? -1.0 : (loc == 1 ? 1.0 : 0.0);
+    double d2 = loc == 0 ? -1.0 : (loc == 2 ? 1.0 : 0.0);
+    /* coefficients of t1, t2: Ginv (d1, d2) */
+    double c1 = (g22 * d1 - g12 * d2) / det;
+    double c2 = (-g12 * d1 + g11 * d2) / det;
+    double grad[3];
+    for (int d = 0; d < 3; ++d) grad[d] = c1 * t1[d] + c2 * t2[d];
+    const double *n = m->n + 3 * t;
+    out[0] = n[1] * grad[2] - n[2] * grad[1];
+    out[1] = n[2] * grad[0] - n[0] * grad[2];
+    out[2] = n[0] * grad[1] - n[1] * grad[0];
+}
+
+/* One regular pair's hypersingular contribution, test triangle tm with hat
+ * function of local vertex a, trial triangle tn with local vertex b:
+ *   (curl_a . curl_b) int int g  -  k^2 (n_m . n_n) int int g lam_a lam_b.    */
+static void orc_pair_hyps(const orc_mesh *m, double k, int64_t tm, int64_t tn, int a, int b, double *re,
+                          double *im)
+{
+    const int slp = k == 0.0 ? ORC_LAPLACE_SLP : ORC_HELMHOLTZ_SLP;
+    double s0r, s0i, s1r = 0.0, s1i = 0.0;
+    orc_pair(m, slp, k, tm, tn, -1, -1, &s0r, &s0i);
+    double ca[3], cb[3];
+    orc_curl(m, tm, a, ca);
+    orc_curl(m, tn, b, cb);
+    double cc = ca[0] * cb[0] + ca[1] * cb[1] + ca[2] * cb[2];
+    *re = cc * s0r;
+    *im = cc * s0i;
+    if (k != 0.0) {
+        orc_pair(m, slp, k, tm, tn, a, b, &s1r, &s1i);
+        const double *na = m->n + 3 * tm, *nb = m->n + 3 * tn;
+        double nn = na[0] * nb[0] + na[1] * nb[1] + na[2] * nb[2];
+        *re -= k * k * nn * s1r;
+        *im -= k * k * nn * s1i;
+    }
+}
+
+static int orc_is_hyps(int op) { return op == ORC_LAPLACE_HYPS || op == ORC_HELMHOLTZ_HYPS; }
+
 /* One entry A[row, col]; returns ORC_OK or ORC_E_NEARFIELD. */
 static int orc_entry(const orc_mesh *m, int op, int space, double k, int64_t row, int64_t col,
                      int near, double *re, double *im)
@@ -285,7 +348,10 @@ static int orc_entry(const orc_mesh *m, int op, int space, double k, int64_t row
             }
             int lb = orc_local_index(m, tn, col);
             double r, i;
-            orc_pair(m, op, k, tm, tn, la, lb, &r, &i);
+            if (orc_is_hyps(op))
+                orc_pair_hyps(m, k, tm, tn, la, lb, &r, &i);
+            else
+                orc_pair(m, op, k, tm, tn, la, lb, &r, &i);
             sr += r;
             si += i;
         }
@@ -297,7 +363,7 @@ static int orc_entry(const orc_mesh *m, int op, int space, double k, int64_t row
 
 static int orc_is_complex(int op)
 {
-    return op == ORC_HELMHOLTZ_SLP || op == ORC_HELMHOLTZ_DLP || op == ORC_HELMHOLTZ_ADLP;
+    return op == ORC_HELMHOLTZ_SLP || op == ORC_HELMHOLTZ_DLP || op == ORC_HELMHOLTZ_ADLP || op == ORC_HELMHOLTZ_HYPS;
 }
 
 /* Sub-block A[rows, cols], row-major; complex operators write interleaved
@@ -307,7 +373,8 @@ int orc_entries(const orc_mesh *m, int op, int space, double k,
                 const int32_t *rows, int64_t nr, const int32_t *cols, int64_t nc,
                 int near, double *out, int nthreads)
 {
-    if (op < 0 || op > 5 || (space != ORC_P0 && space != ORC_P1)) return ORC_E_ARG;
+    if (op < 0 || op > 7 || (space != ORC_P0 && space != ORC_P1)) return ORC_E_ARG;
+    if (orc_is_hyps(op) && space != ORC_P1) return ORC_E_ARG;   /* needs continuous trial/test functions */
     int64_t ndof = space == ORC_P0 ? m->nt : m->nv;
     for (int64_t r = 0; r < nr; ++r)
         if (rows[r] < 0 || rows[r] >= ndof) return ORC_E_ARG;

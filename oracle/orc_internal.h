@@ -16,7 +16,9 @@ enum {
     ORC_HELMHOLTZ_SLP = 2,
     ORC_HELMHOLTZ_DLP = 3,
     ORC_LAPLACE_ADLP = 4,
-    ORC_HELMHOLTZ_ADLP = 5
+    ORC_HELMHOLTZ_ADLP = 5,
+    ORC_LAPLACE_HYPS = 6,
+    ORC_HELMHOLTZ_HYPS = 7
 };
 enum { ORC_P0 = 0, ORC_P1 = 1 };
 enum { ORC_NEAR_ERROR = 0, ORC_NEAR_SKIP = 1 };

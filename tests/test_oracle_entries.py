@@ -297,3 +297,91 @@ def test_adjoint_double_layer_is_transposed_double_layer(space, pair, k, ico):
     scale = np.abs(K).max()
     assert np.abs(A - K.T).max() <= 1e-13 * scale
     assert np.abs(A - m.entries(dl, space, k, rows, cols, near=O.NEAR_SKIP)).max() > 1e-3 * scale
+
+
+# ---------------------------------------------------------------------------
+# Hypersingular operator, Eq. hypsHelmholtz (P1 only).
+
+
+def surface_curl(T, a):
+    """curl of the hat function of local vertex a on triangle T: n x grad,
+    the gradient from the linear system g.(v1-v0), g.(v2-v0) = hat
+    differences, g.n = 0."""
+    n = np.cross(T[1] - T[0], T[2] - T[0])
+    n /= np.linalg.norm(n)
+    hat = [1.0 if j == a else 0.0 for j in range(3)]
+    g = np.linalg.solve(np.array([T[1] - T[0], T[2] - T[0], n]), [hat[1] - hat[0], hat[2] - hat[0], 0.0])
+    return np.cross(n, g), n
+
+
+def hyps_brute(k, A, B, a_loc, b_loc):
+    ca, na = surface_curl(A, a_loc)
+    cb, nb = surface_curl(B, b_loc)
+    slp = O.LAPLACE_SLP if k == 0.0 else O.HELMHOLTZ_SLP
+    val = np.dot(ca, cb) * brute_pair(slp, k, A, B)
+    if k != 0.0:
+        val = val - k * k * np.dot(na, nb) * brute_pair(slp, k, A, B, a_loc, b_loc)
+    return val
+
+
+@pytest.mark.parametrize("k", [0.0, 1.1])
+@pytest.mark.parametrize("a_loc,b_loc", [(0, 1), (2, 0), (1, 2)])
+def test_hypersingular_pair_brute_force(k, a_loc, b_loc):
+    """One regular pair (two disjoint triangles, so the P1 entry is that
+    pair alone): the oracle matches the high-order integral of
+    curl.curl g - k^2 n.n lam lam g, with the curls from a linear solve."""
+    A, B = placed_pair(16.0)
+    m = O.OracleMesh(*two_triangle_mesh(A, B), 6)
+    op = O.LAPLACE_HYPS if k == 0.0 else O.HELMHOLTZ_HYPS
+    got = m.entries(op, O.P1, k, [a_loc], [3 + b_loc])[0, 0]
+    ref = hyps_brute(k, A, B, a_loc, b_loc)
+    # the 6-point rule's own error: ~1e-9 for Laplace at this distance, ~1e-6
+    # on exp(ikr) at k h ~ 1.1 (the Helmholtz single-layer pin allows 1e-4 at k = 2)
+    assert abs(got - ref) <= (1e-7 if k == 0.0 else 1e-5) * abs(ref)
+    if k != 0.0:
+        # the k^2 term with the opposite sign is far off
+        alt = ref + 2 * k * k * np.dot(surface_curl(A, 0)[1], surface_curl(B, 0)[1]) * \
+            brute_pair(O.HELMHOLTZ_SLP, k, A, B, a_loc, b_loc)
+        assert abs(got - alt) > 1e-2 * abs(ref)
+
+
+def jittered(ico, level=2, seed=3):
+    xyz, tri = ico(level)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return xyz * (1.0 + 0.08 * rng.uniform(-1, 1, size=(xyz.shape[0], 1))), tri
+
+
+def test_laplace_hypersingular_annihilates_constants(ico):
+    """curl of the constant function vanishes, triangle by triangle, so every
+    row of the Laplace hypersingular matrix sums to zero (regular pairs only
+    or not)."""
+    xyz, tri = jittered(ico)
+    m = O.OracleMesh(xyz, tri, 6)
+    rows = np.random.Generator(np.random.PCG64(5)).choice(m.nv, 15, replace=False)
+    D = m.entries(O.LAPLACE_HYPS, O.P1, 0.0, rows, np.arange(m.nv))
+    assert np.all(np.abs(D.sum(1)) <= 1e-13 * np.abs(D).sum(1))
+
+
+@pytest.mark.parametrize("op,k", [(O.LAPLACE_HYPS, 0.0), (O.HELMHOLTZ_HYPS, 2.1)])
+def test_hypersingular_symmetric(op, k, ico):
+    xyz, tri = jittered(ico)
+    m = O.OracleMesh(xyz, tri, 6)
+    idx = np.random.Generator(np.random.PCG64(6)).choice(m.nv, 40, replace=False)
+    D = m.entries(op, O.P1, k, idx, idx)
+    assert np.abs(D - D.T).max() <= 1e-13 * np.abs(D).max()
+
+
+def test_laplace_hypersingular_scales_linearly(ico):
+    """Under x -> s x: curls scale 1/s each, g 1/s, areas s^2 each: D -> s D."""
+    xyz, tri = jittered(ico)
+    idx = np.arange(0, 162, 7)
+    D1 = O.OracleMesh(xyz, tri, 6).entries(O.LAPLACE_HYPS, O.P1, 0.0, idx, idx)
+    D2 = O.OracleMesh(2.5 * xyz, tri, 6).entries(O.LAPLACE_HYPS, O.P1, 0.0, idx, idx)
+    assert np.abs(D2 - 2.5 * D1).max() <= 1e-13 * np.abs(D2).max()
+
+
+def test_hypersingular_needs_p1(ico):
+    xyz, tri = ico(1)
+    m = O.OracleMesh(xyz, tri, 6)
+    with pytest.raises(Exception):
+        m.entries(O.LAPLACE_HYPS, O.P0, 0.0, [0], [1])
