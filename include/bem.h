@@ -10,13 +10,20 @@
  *   double layer, Eq. (dlp):  A_ij = int_Gi int_Gj psi_i(x) dg/dn_y    phi_j(y)
  *   adjoint double layer, Eq. (adlp):
  *                             A_ij = int_Gi int_Gj psi_i(x) dg/dn_x    phi_j(y)
+ *   hypersingular, Eq. (hypsHelmholtz), P1 only:
+ *                             A_ij = int_Gi int_Gj g(x,y) [curl psi_i(x) . curl phi_j(y)
+ *                                                    - k^2 psi_i(x) phi_j(y) n_x . n_y]
  *   g(x,y) = exp(i k |x-y|) / (4 pi |x-y|)   (Helmholtz; Laplace is k = 0)
  *
  * Row i is the test function psi_i (variable x), column j the trial function
  * phi_j (variable y); n_y is the unit normal of the trial triangle, n_x that
  * of the test triangle.  With the same space and rule on both sides the
  * adjoint double layer is the transposed double layer, A'_ij = K_ji, and is
- * evaluated that way (the same kernels with test and trial exchanged).  Basis
+ * evaluated that way (the same kernels with test and trial exchanged).  For
+ * the hypersingular operator curl u = n x grad_Gamma u is constant on each
+ * triangle for the hat functions; P0 requests fail with BEM_E_ARG.  Its far
+ * entries cancel like (h/r)^2 (the curls of a triangle's three hat functions
+ * sum to zero), so FP32 loses about that factor in relative accuracy.  Basis
  * functions: P0 (one dof per triangle, the indicator of the triangle) or P1
  * (one dof per vertex, the continuous piecewise-linear hat function).
  * Both integrals use the same symmetric Gauss rule per triangle (Section
@@ -74,7 +81,9 @@ typedef enum {
     BEM_HELMHOLTZ_SLP = 2,
     BEM_HELMHOLTZ_DLP = 3,
     BEM_LAPLACE_ADLP = 4,
-    BEM_HELMHOLTZ_ADLP = 5
+    BEM_HELMHOLTZ_ADLP = 5,
+    BEM_LAPLACE_HYPS = 6,     /* P1 only */
+    BEM_HELMHOLTZ_HYPS = 7    /* P1 only */
 } bem_op;
 typedef enum { BEM_P0 = 0, BEM_P1 = 1 } bem_space;
 /* BEM_FP64: plain FP64 quadrature.  BEM_FP32: FP32 quadrature with

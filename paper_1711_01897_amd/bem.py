@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libbem.so")
 
 LAPLACE_SLP, LAPLACE_DLP, HELMHOLTZ_SLP, HELMHOLTZ_DLP = 0, 1, 2, 3
 LAPLACE_ADLP, HELMHOLTZ_ADLP = 4, 5
+LAPLACE_HYPS, HELMHOLTZ_HYPS = 6, 7
 P0, P1 = 0, 1
 FP64, FP32 = 0, 1
 NEAR_ERROR, NEAR_SKIP = 0, 1
@@ -163,7 +164,7 @@ def _idx(a):
 
 
 def is_complex(op):
-    return op in (HELMHOLTZ_SLP, HELMHOLTZ_DLP, HELMHOLTZ_ADLP)
+    return op in (HELMHOLTZ_SLP, HELMHOLTZ_DLP, HELMHOLTZ_ADLP, HELMHOLTZ_HYPS)
 
 
 def out_dtype(op, prec):

@@ -41,11 +41,14 @@ namespace bem {
 namespace {
 
 constexpr int LSLP = BEM_LAPLACE_SLP, LDLP = BEM_LAPLACE_DLP, HSLP = BEM_HELMHOLTZ_SLP, HDLP = BEM_HELMHOLTZ_DLP;
+constexpr int LHYP = BEM_LAPLACE_HYPS, HHYP = BEM_HELMHOLTZ_HYPS;
 constexpr float kInv4PiF = 0.0795774715459476679f;
 constexpr double kInv4Pi = 0.0795774715459476678844418816862571;
 
 template <int OP>
-constexpr bool is_cplx() { return OP == HSLP || OP == HDLP; }
+constexpr bool is_cplx() { return OP == HSLP || OP == HDLP || OP == HHYP; }
+template <int OP>
+constexpr bool is_hyp() { return OP == LHYP || OP == HHYP; }
 template <int OP>
 constexpr bool is_dlp() { return OP == LDLP || OP == HDLP; }
 
@@ -57,6 +60,16 @@ constexpr int n64() { return (4 + 3 * Q + 1) / 2 * 2; }
 // quadrature offsets scaled by -2, then |o_q|^2 per point (see pair_p1_*).
 template <int Q>
 constexpr int nstar32() { return (n32<Q>() + Q + 3) / 4 * 4; }
+
+// Edges from quadrature points.  The last orbit of each rule has barycentric
+// coordinates (1 - 2 alpha, alpha, alpha) rotated to each vertex: point
+// vpt(a) sits on the median through vertex a with x - c = (1 - 3 alpha)
+// (v_a - c), so the edge opposite a, v_{a+1} - v_{a+2}, is
+// (x_{vpt(a+1)} - x_{vpt(a+2)}) * vscale.
+template <int Q>
+constexpr int vpt(int a) { return Q - 3 + a; }
+template <int Q>
+constexpr double vscale() { return 1.0 / (1.0 - 3.0 * rule::Rule<Q>::l1[Q - 3]); }
 
 template <int Q>
 __device__ __forceinline__ void load32(const float *__restrict__ g, int t, float *v)
@@ -402,6 +415,231 @@ __device__ __forceinline__ void pair_p1_trialfix_f32(const float *T, const float
     }
 }
 
+// Hypersingular operator (Eq. hypsHelmholtz), P1, FP32.  On a flat triangle
+// the surface curl of the hat function of local vertex e is E_e / J with
+// E_e = v_{e+1} - v_{e+2} the edge opposite e, so one regular pair adds
+//   (E_a . E_b) / (J_x J_y) int int g  -  k^2 (n_x . n_y) int int g lam_a lam_b
+// to entry (a, b).  T is the test triangle, S the trial triangle (offsets
+// scaled by -2 with |o_q|^2 in Bq: the lane's for row requests, the staged
+// record's own for column requests).  TESTFIX: test vertex `fix` given, the
+// three trial vertices returned; else trial vertex `fix` given, the three
+// test vertices returned.  Returned values are divided by J_x J_y (the
+// caller multiplies by J_x J_y / 4 pi).
+template <int OP, int Q, bool TESTFIX>
+__device__ __forceinline__ void pair_p1_hyp_f32(const float *T, const float *S, int fix, const float *Bq, float kf,
+                                                double kk, float *vr, float *vi)
+{
+    const float dcx = (T[0] - S[0]) + (T[4] - S[4]);
+    const float dcy = (T[1] - S[1]) + (T[5] - S[5]);
+    const float dcz = (T[2] - S[2]) + (T[6] - S[6]);
+    Phase ph{};
+    if constexpr (is_cplx<OP>()) ph = phase_base(T, S, kk, dcx, dcy, dcz);
+    // g without 1/4pi at r^2 = v (+ |D|^2 for Helmholtz, see Phase)
+    auto green = [&](float v, float &gr, float &gi) {
+        if constexpr (is_cplx<OP>()) {
+            const float r2 = v + ph.dsq;
+            const float ri = __builtin_amdgcn_rsqf(r2);
+            const float r = r2 * ri;
+            const float delta = v * __builtin_amdgcn_rcpf(r + ph.dn);
+            float f = fmaf(ph.kkf, delta, ph.t0);
+            f = f - __builtin_rintf(f);
+            gr = ri * __builtin_amdgcn_cosf(f);
+            gi = ri * __builtin_amdgcn_sinf(f);
+        } else {
+            gr = __builtin_amdgcn_rsqf(v);
+            gi = 0.f;
+        }
+    };
+    float t0r = 0.f, t0i = 0.f;                              // sum w_p w_q g
+    float t1r[3] = {0.f, 0.f, 0.f}, t1i[3] = {0.f, 0.f, 0.f};   // Helmholtz: with both bases
+    if constexpr (TESTFIX) {
+        float ax[Q], ay[Q], az[Q], A[Q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const float ox = T[12 + 3 * p], oy = T[13 + 3 * p], oz = T[14 + 3 * p];
+            ax[p] = dcx + ox;
+            ay[p] = dcy + oy;
+            az[p] = dcz + oz;
+            if constexpr (is_cplx<OP>())
+                A[p] = fmaf(2.0f * dcx + ox, ox, fmaf(2.0f * dcy + oy, oy, (2.0f * dcz + oz) * oz));
+            else
+                A[p] = fmaf(ax[p], ax[p], fmaf(ay[p], ay[p], az[p] * az[p]));
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const float mx = S[12 + 3 * q], my = S[13 + 3 * q], mz = S[14 + 3 * q];
+            const float B = Bq[q];
+            float ur = 0.f, ui = 0.f, br = 0.f, bi = 0.f;
+#pragma unroll
+            for (int p = 0; p < Q; ++p) {
+                const float v = fmaf(ax[p], mx, fmaf(ay[p], my, fmaf(az[p], mz, A[p] + B)));
+                float gr, gi;
+                green(v, gr, gi);
+                const float w = (float)rule::Rule<Q>::w[p];
+                ur = fmaf(w, gr, ur);
+                if constexpr (is_cplx<OP>()) {
+                    ui = fmaf(w, gi, ui);
+                    const float l = (float)(fix == 0 ? rule::Rule<Q>::l0[p] : (fix == 1 ? rule::Rule<Q>::l1[p] : rule::Rule<Q>::l2[p]));
+                    br = fmaf(w * l, gr, br);
+                    bi = fmaf(w * l, gi, bi);
+                }
+            }
+            const float wq = (float)rule::Rule<Q>::w[q];
+            t0r = fmaf(wq, ur, t0r);
+            if constexpr (is_cplx<OP>()) {
+                t0i = fmaf(wq, ui, t0i);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const float wl = (float)(rule::Rule<Q>::w[q] * rule::lam<Q>(e, q));
+                    t1r[e] = fmaf(wl, br, t1r[e]);
+                    t1i[e] = fmaf(wl, bi, t1i[e]);
+                }
+            }
+        }
+    } else {
+        float B[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) B[q] = S[n32<Q>() + q];
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const float ox = T[12 + 3 * p], oy = T[13 + 3 * p], oz = T[14 + 3 * p];
+            const float ax = dcx + ox, ay = dcy + oy, az = dcz + oz;
+            float A;
+            if constexpr (is_cplx<OP>())
+                A = fmaf(2.0f * dcx + ox, ox, fmaf(2.0f * dcy + oy, oy, (2.0f * dcz + oz) * oz));
+            else
+                A = fmaf(ax, ax, fmaf(ay, ay, az * az));
+            float ur = 0.f, ui = 0.f, br = 0.f, bi = 0.f;
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                const float v = fmaf(ax, S[12 + 3 * q], fmaf(ay, S[13 + 3 * q], fmaf(az, S[14 + 3 * q], A + B[q])));
+                float gr, gi;
+                green(v, gr, gi);
+                const float w = (float)rule::Rule<Q>::w[q];
+                ur = fmaf(w, gr, ur);
+                if constexpr (is_cplx<OP>()) {
+                    ui = fmaf(w, gi, ui);
+                    const float l = (float)(fix == 0 ? rule::Rule<Q>::l0[q] : (fix == 1 ? rule::Rule<Q>::l1[q] : rule::Rule<Q>::l2[q]));
+                    br = fmaf(w * l, gr, br);
+                    bi = fmaf(w * l, gi, bi);
+                }
+            }
+            const float wp = (float)rule::Rule<Q>::w[p];
+            t0r = fmaf(wp, ur, t0r);
+            if constexpr (is_cplx<OP>()) {
+                t0i = fmaf(wp, ui, t0i);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const float wl = (float)(rule::Rule<Q>::w[p] * rule::lam<Q>(d, p));
+                    t1r[d] = fmaf(wl, br, t1r[d]);
+                    t1i[d] = fmaf(wl, bi, t1i[d]);
+                }
+            }
+        }
+    }
+    // curl products: test edges from unscaled offsets, trial edges from the
+    // -2-scaled ones
+    const float vs = (float)vscale<Q>();
+    float ET[3][3], ES[3][3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i1 = 12 + 3 * vpt<Q>((e + 1) % 3) + c, i2 = 12 + 3 * vpt<Q>((e + 2) % 3) + c;
+            ET[e][c] = (T[i1] - T[i2]) * vs;
+            ES[e][c] = (S[i1] - S[i2]) * (-0.5f * vs);
+        }
+    const float inv = 1.0f / (T[3] * S[3]);
+    float nn = 0.f;
+    if constexpr (is_cplx<OP>()) nn = fmaf(T[8], S[8], fmaf(T[9], S[9], T[10] * S[10])) * kf * kf;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const float *et = TESTFIX ? (fix == 0 ? ET[0] : (fix == 1 ? ET[1] : ET[2])) : ET[e];
+        const float *es = TESTFIX ? ES[e] : (fix == 0 ? ES[0] : (fix == 1 ? ES[1] : ES[2]));
+        const float cc = fmaf(et[0], es[0], fmaf(et[1], es[1], et[2] * es[2])) * inv;
+        vr[e] = cc * t0r;
+        vi[e] = cc * t0i;
+        if constexpr (is_cplx<OP>()) {
+            vr[e] = fmaf(-nn, t1r[e], vr[e]);
+            vi[e] = fmaf(-nn, t1i[e], vi[e]);
+        }
+    }
+}
+
+// Hypersingular operator, P1, FP64: the same terms from absolute points.
+template <int OP, int Q, bool TESTFIX>
+__device__ __forceinline__ void pair_p1_hyp_f64(const double *T, const double *S, int fix, double k, double *vr,
+                                                double *vi)
+{
+    constexpr int G = is_cplx<OP>() ? HSLP : LSLP;
+    double t0r = 0.0, t0i = 0.0, t1r[3] = {0.0, 0.0, 0.0}, t1i[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        double ur = 0.0, ui = 0.0, br[3] = {0.0, 0.0, 0.0}, bi[3] = {0.0, 0.0, 0.0};
+#pragma unroll f64_unroll<OP>()
+        for (int q = 0; q < Q; ++q) {
+            double gr = 0.0, gi = 0.0;
+            kern_f64<G>(T[4 + 3 * p] - S[4 + 3 * q], T[5 + 3 * p] - S[5 + 3 * q], T[6 + 3 * p] - S[6 + 3 * q], S, 1.0,
+                        k, gr, gi);
+            const double w = rule::Rule<Q>::w[q];
+            ur += w * gr;
+            ui += w * gi;
+            if constexpr (is_cplx<OP>()) {
+                if constexpr (TESTFIX) {
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        br[e] += w * rule::lam<Q>(e, q) * gr;
+                        bi[e] += w * rule::lam<Q>(e, q) * gi;
+                    }
+                } else {
+                    const double l = fix == 0 ? rule::Rule<Q>::l0[q] : (fix == 1 ? rule::Rule<Q>::l1[q] : rule::Rule<Q>::l2[q]);
+                    br[0] += w * l * gr;
+                    bi[0] += w * l * gi;
+                }
+            }
+        }
+        const double wp = rule::Rule<Q>::w[p];
+        t0r += wp * ur;
+        t0i += wp * ui;
+        if constexpr (is_cplx<OP>()) {
+            if constexpr (TESTFIX) {
+                const double l = fix == 0 ? rule::Rule<Q>::l0[p] : (fix == 1 ? rule::Rule<Q>::l1[p] : rule::Rule<Q>::l2[p]);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    t1r[e] += wp * l * br[e];
+                    t1i[e] += wp * l * bi[e];
+                }
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    t1r[d] += wp * rule::lam<Q>(d, p) * br[0];
+                    t1i[d] += wp * rule::lam<Q>(d, p) * bi[0];
+                }
+            }
+        }
+    }
+    const double vs = vscale<Q>();
+    double ET[3][3], ES[3][3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int i1 = 4 + 3 * vpt<Q>((e + 1) % 3) + c, i2 = 4 + 3 * vpt<Q>((e + 2) % 3) + c;
+            ET[e][c] = (T[i1] - T[i2]) * vs;
+            ES[e][c] = (S[i1] - S[i2]) * vs;
+        }
+    const double inv = 1.0 / (T[3] * S[3]);
+    const double nn = is_cplx<OP>() ? (T[0] * S[0] + T[1] * S[1] + T[2] * S[2]) * k * k : 0.0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const double *et = TESTFIX ? (fix == 0 ? ET[0] : (fix == 1 ? ET[1] : ET[2])) : ET[e];
+        const double *es = TESTFIX ? ES[e] : (fix == 0 ? ES[0] : (fix == 1 ? ES[1] : ES[2]));
+        const double cc = (et[0] * es[0] + et[1] * es[1] + et[2] * es[2]) * inv;
+        vr[e] = cc * t0r - nn * t1r[e];
+        vi[e] = cc * t0i - nn * t1i[e];
+    }
+}
+
 // FP64: general form with explicit test basis (a) and trial basis (b); the
 // free side (a or b == -1) is returned for all three local vertices.
 template <int OP, int Q, bool TESTFIX>
@@ -686,10 +924,16 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
             for (int i = 0; i < FW; ++i) F[i] = sG[s][i];
             const int loc = sL[s];
             float vr[3], vi[3];
-            if constexpr (ROWFIX)
+            if constexpr (is_hyp<OP>()) {
+                if constexpr (ROWFIX)
+                    pair_p1_hyp_f32<OP, Q, true>(F, L, loc, Bq, (float)R.k, R.kk, vr, vi);
+                else
+                    pair_p1_hyp_f32<OP, Q, false>(L, F, loc, nullptr, (float)R.k, R.kk, vr, vi);
+            } else if constexpr (ROWFIX) {
                 pair_p1_testfix_f32<OP, Q>(F, loc, L, Bq, (float)R.k, R.kk, vr, vi);
-            else
+            } else {
                 pair_p1_trialfix_f32<OP, Q>(L, F, loc, (float)R.k, R.kk, vr, vi);
+            }
             const float sc = F[3] * L[3] * kInv4PiF;
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
@@ -791,10 +1035,16 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
             for (int i = 0; i < n64<Q>(); ++i) F[i] = sG[s][i];
             const int loc = sL[s];
             double vr[3], vi[3];
-            if constexpr (ROWFIX)
+            if constexpr (is_hyp<OP>()) {
+                if constexpr (ROWFIX)
+                    pair_p1_hyp_f64<OP, Q, true>(F, L, loc, R.k, vr, vi);
+                else
+                    pair_p1_hyp_f64<OP, Q, false>(L, F, loc, R.k, vr, vi);
+            } else if constexpr (ROWFIX) {
                 pair_p1_f64<OP, Q, true>(F, L, loc, R.k, vr, vi);
-            else
+            } else {
                 pair_p1_f64<OP, Q, false>(L, F, loc, R.k, vr, vi);
+            }
             const double sc = F[3] * L[3] * kInv4Pi;
 #pragma unroll
             for (int e = 0; e < 3; ++e) {
@@ -868,7 +1118,11 @@ typedef void (*EntryKernel)(const ReqDev *, const EntryBlock *, int64_t, unsigne
 template <int OP, int Q>
 EntryKernel pick(int space, int prec)
 {
-    if (space == BEM_P0) return prec == BEM_FP32 ? k_p0_f32<OP, Q> : k_p0_f64<OP, Q>;
+    if constexpr (is_hyp<OP>()) {
+        if (space == BEM_P0) return nullptr;   // the hypersingular operator needs P1 (host-checked)
+    } else {
+        if (space == BEM_P0) return prec == BEM_FP32 ? k_p0_f32<OP, Q> : k_p0_f64<OP, Q>;
+    }
     return prec == BEM_FP32 ? k_p1_f32<OP, Q> : k_p1_f64<OP, Q>;
 }
 
@@ -884,7 +1138,10 @@ EntryKernel select_kernel(const Variant &v)
     case LSLP: return pick_q<LSLP>(v.space, v.prec, v.q);
     case LDLP: return pick_q<LDLP>(v.space, v.prec, v.q);
     case HSLP: return pick_q<HSLP>(v.space, v.prec, v.q);
-    default: return pick_q<HDLP>(v.space, v.prec, v.q);
+    case HDLP: return pick_q<HDLP>(v.space, v.prec, v.q);
+    case LHYP: return pick_q<LHYP>(v.space, v.prec, v.q);
+    case HHYP: return pick_q<HHYP>(v.space, v.prec, v.q);
+    default: return nullptr;
     }
 }
 
@@ -896,6 +1153,7 @@ hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > INT32_MAX) return hipErrorInvalidValue;
     const EntryKernel k = select_kernel(v);
+    if (!k) return hipErrorInvalidValue;
     if (start || stop)
         hipExtLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kBlockLanes), 0, s, start, stop, 0, reqs, blocks,
                               nblocks, tclock);

@@ -138,6 +138,8 @@ double vanish_scale(const bem_mesh &m, int op, int space, double k, double dist)
     const double J2 = m.mean_J * m.mean_J * (space == BEM_P0 ? 0.25 : 1.0);
     const double inv4pi = 0.0795774715459476678844418816862571;
     if (op == BEM_LAPLACE_SLP || op == BEM_HELMHOLTZ_SLP) return J2 * inv4pi / d;
+    if (op == BEM_LAPLACE_HYPS || op == BEM_HELMHOLTZ_HYPS)   // second derivatives of g, plus the k^2 term
+        return J2 * inv4pi * (1.0 / (d * d * d) + k * k / d);
     const bool helm_dl = op == BEM_HELMHOLTZ_DLP || op == BEM_HELMHOLTZ_ADLP;
     return J2 * inv4pi * (1.0 + (helm_dl ? k * d : 0.0)) / (d * d);
 }

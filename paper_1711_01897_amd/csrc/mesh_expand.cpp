@@ -44,7 +44,7 @@ double now_seconds()
 
 bool is_complex_op(int op)
 {
-    return op == BEM_HELMHOLTZ_SLP || op == BEM_HELMHOLTZ_DLP || op == BEM_HELMHOLTZ_ADLP;
+    return op == BEM_HELMHOLTZ_SLP || op == BEM_HELMHOLTZ_DLP || op == BEM_HELMHOLTZ_ADLP || op == BEM_HELMHOLTZ_HYPS;
 }
 
 bool is_adjoint_op(int op) { return op == BEM_LAPLACE_ADLP || op == BEM_HELMHOLTZ_ADLP; }
@@ -186,8 +186,10 @@ void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n
 int expand_request(Request &r)
 {
     const bem_mesh &m = *r.mesh;
-    if (r.op < 0 || r.op > 5) return fail(BEM_E_ARG, "unknown operator");
+    if (r.op < 0 || r.op > 7) return fail(BEM_E_ARG, "unknown operator");
     if (r.space != BEM_P0 && r.space != BEM_P1) return fail(BEM_E_ARG, "unknown space");
+    if ((r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS) && r.space != BEM_P1)
+        return fail(BEM_E_ARG, "the hypersingular operator needs continuous (P1) functions");
     if (r.prec != BEM_FP32 && r.prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
     if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP) return fail(BEM_E_ARG, "unknown near-field policy");
     if (is_complex_op(r.op)) {

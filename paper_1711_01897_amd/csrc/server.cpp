@@ -44,7 +44,7 @@ namespace {
 constexpr int kMaxSlots = 16;
 constexpr int kMaxThreads = 4;
 constexpr int kTimedEvery = 8;
-constexpr int kKeys = 32;   // launch groups: (op, space, prec, rule)
+constexpr int kKeys = 64;   // launch groups: (kernel op 0..7, space, prec, rule)
 
 int env_int(const char *name, int dflt, int lo, int hi)
 {

@@ -122,3 +122,10 @@ def test_server_config_rejects_small_arena():
     with pytest.raises(bem.BemError) as ei:
         bem.server_config(64 << 20, 0)
     assert ei.value.code == bem.E_ARG
+
+
+def test_hypersingular_p0_rejected_on_host():
+    """Argument checks run before anything reaches a device."""
+    from paper_1711_01897_amd import bem
+    assert bem.LAPLACE_HYPS == 6 and bem.HELMHOLTZ_HYPS == 7
+    assert bem.is_complex(bem.HELMHOLTZ_HYPS) and not bem.is_complex(bem.LAPLACE_HYPS)
