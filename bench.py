@@ -36,12 +36,17 @@ sys.path.insert(0, ROOT)
 # accumulators), double layer 19 / 23 (the (x-y).n_y product per pair),
 # Helmholtz single layer 20 / 28, double layer 33 / 41.
 FLOPS_PER_EVAL = {(0, 0): 11, (1, 0): 19, (2, 0): 20, (3, 0): 33,
-                  (0, 1): 15, (1, 1): 23, (2, 1): 28, (3, 1): 41}
+                  (0, 1): 15, (1, 1): 23, (2, 1): 28, (3, 1): 41,
+                  # hypersingular (P1), by the same rules: the plain pair sum of g
+                  # (Laplace 11, as the P0 single layer; Helmholtz 20) plus, for
+                  # Helmholtz, the basis-weighted complex sum (4)
+                  (6, 1): 11, (7, 1): 24}
 # What the kernels execute per evaluation after hoisting the (x-y).n_y
 # product (constant over a trial triangle's points) and the basis weights
 # out of the inner loop: reported beside the algorithmic rate.
 FLOPS_EXECUTED = {(0, 0): 11, (1, 0): 13, (2, 0): 21, (3, 0): 27,
-                  (0, 1): 12, (1, 1): 14, (2, 1): 22, (3, 1): 28}
+                  (0, 1): 12, (1, 1): 14, (2, 1): 22, (3, 1): 28,
+                  (6, 1): 10, (7, 1): 29}
 # Non-packed FP32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.
 PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9
 PEAK_FP32_PACKED = 2 * PEAK_FP32_VALU
@@ -64,6 +69,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--ops", default="laplace_slp,laplace_dlp",
+                    help="operators assembled per step (comma list of laplace_slp, laplace_dlp, laplace_adlp, "
+                         "laplace_hyps); the default is the stated workload")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -131,9 +139,25 @@ def traffic_from(args):
     print(json.dumps(rec))
 
 
+OP_NAMES = {"laplace_slp": 0, "laplace_dlp": 1, "laplace_adlp": 4, "laplace_hyps": 6}
+OP_LABEL = {0: "single", 1: "double", 4: "adjoint double", 6: "hypersingular"}
+
+
+def step_ops(args):
+    return [OP_NAMES[o] for o in args.ops.split(",")]
+
+
+def workload_name(args):
+    kinds = "single+double layer" if step_ops(args) == [0, 1] else \
+        " + ".join(OP_LABEL[o] for o in step_ops(args)) + " operator"
+    return (f"icosphere level 6 (81920 triangles, 40962 vertices), Laplace {kinds}, P1, 6-point rule, H-matrix leaf "
+            "100, eta 1.0, ACA tol 1e-5, every ACA row/column on the GPU through the request server, FP32 compensated "
+            "entries")
+
+
 def assemble_step(bem, mesh, prec, args):
     out = {"entries": 0, "requests": 0, "rank_sum": 0, "rank_max": 0, "blocks": 0, "phases": {}}
-    for op in (bem.LAPLACE_SLP, bem.LAPLACE_DLP):
+    for op in step_ops(args):
         H = bem.hmat_assemble(mesh, op, bem.P1, 0.0, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200,
                               n_workers=args.workers, blocks_per_worker=args.blocks_per_worker, prec=prec,
                               dense_mode=0)
@@ -202,10 +226,11 @@ def roofline(kstats):
     return roof, dom
 
 
-def cpu_baseline(bem, inputs, mesh, xyz, tri, seconds):
+def cpu_baseline(bem, inputs, mesh, xyz, tri, seconds, ops):
     """FP64 oracle on a seeded sample of the benchmark's ACA row/column
-    requests (single layer, P1), all host threads; stops after `seconds`.
-    Also returns the largest FP32-vs-oracle normwise error on that sample."""
+    requests (the step's operators in turn, P1), all host threads; stops
+    after `seconds`.  Also returns the largest FP32-vs-oracle normwise error
+    on that sample."""
     import numpy as np
     import oracle
 
@@ -221,7 +246,7 @@ def cpu_baseline(bem, inputs, mesh, xyz, tri, seconds):
         b = adm[int(rng.integers(adm.shape[0]))]
         rows = perm[ranges[b[0], 0]:ranges[b[0], 1]]
         cols = perm[ranges[b[1], 0]:ranges[b[1], 1]]
-        op = oracle.LAPLACE_SLP if nreq % 2 == 0 else oracle.LAPLACE_DLP
+        op = ops[nreq % len(ops)]   # the same ids in both modules
         if nreq % 4 < 2:
             r, c = rows[int(rng.integers(rows.size)):][:1], cols
         else:
@@ -234,7 +259,8 @@ def cpu_baseline(bem, inputs, mesh, xyz, tri, seconds):
         got = bem.eval_entries(mesh, op, bem.P1, 0.0, r, c, prec=bem.FP32, near=bem.NEAR_ERROR)
         worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
     return {"value": entries / spent, "unit": "entries/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"{nreq} ACA row/column requests (Laplace SLP and DLP, P1) of seeded admissible blocks of "
+            "sample": f"{nreq} ACA row/column requests ({'/'.join(sorted(set(OP_LABEL[o] for o in ops)))}, P1) of "
+                      f"seeded admissible blocks of "
                       f"the same partition, {entries} entries, {spent:.1f} s"}, worst
 
 
@@ -276,7 +302,7 @@ def main():
     cpu = None
     worst = None
     if not args.no_cpu_baseline:
-        cpu, worst = cpu_baseline(bem, inputs, mesh, xyz, tri, args.cpu_seconds)
+        cpu, worst = cpu_baseline(bem, inputs, mesh, xyz, tri, args.cpu_seconds, step_ops(args))
         print(f"[bench] cpu baseline {cpu['value']:.3e} entries/s on {cpu['cores']} threads", file=sys.stderr,
               flush=True)
 
@@ -295,9 +321,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "icosphere level 6 (81920 triangles, 40962 vertices), Laplace single+double layer, P1, "
-                        "6-point rule, H-matrix leaf 100, eta 1.0, ACA tol 1e-5, every ACA row/column on the GPU "
-                        "through the request server, FP32 compensated entries",
+            "workload": workload_name(args),
             "aca_entries_per_step": tot["entries"] // args.steps,
             "aca_requests_per_step": tot["requests"] // args.steps,
             "admissible_blocks_per_step": tot["blocks"] // args.steps,
