@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--dense", type=int, default=0, metavar="LEVEL",
+                    help="instead of the H-matrix workload: the dense P1 matrix of the --ops operators on the "
+                         "icosphere of this level, submitted to the request server in row chunks")
     ap.add_argument("--ops", default="laplace_slp,laplace_dlp",
                     help="operators assembled per step (comma list of laplace_slp, laplace_dlp, laplace_adlp, "
                          "laplace_hyps); the default is the stated workload")
@@ -264,6 +267,77 @@ def cpu_baseline(bem, inputs, mesh, xyz, tri, seconds, ops):
                       f"the same partition, {entries} entries, {spent:.1f} s"}, worst
 
 
+def dense_run(bem, mesh, idx, ops, prec, chunk):
+    n = idx.size
+    tickets = [bem.submit(mesh, op, bem.P1, 0.0, idx[i:i + chunk], idx, prec=prec)
+               for op in ops for i in range(0, n, chunk)]
+    for t in tickets:
+        t.wait()
+    return tickets
+
+
+def dense_main(args):
+    """Dense weak-form assembly (the paper's first benchmark): every entry of
+    the P1 matrix, all regular pairs, vertex-sharing pairs skipped."""
+    import numpy as np
+    import torch
+    # one server stream: dense launches are large and would otherwise overlap,
+    # stretching each launch's event bracket by the others
+    os.environ.setdefault("BEM_SERVER_STREAMS", "1")
+    from paper_1711_01897_amd import bem, inputs
+    xyz, tri = inputs.icosphere(args.dense)
+    n = xyz.shape[0]
+    mesh = bem.mesh_create(xyz, tri, 6)
+    ops = step_ops(args)
+    chunk = 512
+    # rows and columns in the cluster-tree order: a lane chunk then holds the
+    # stars of neighbouring vertices (the matrix is the same, permuted)
+    idx = bem.partition(xyz, tri, bem.P1, 100, 1.0)[0].astype(np.int32)
+    for _ in range(args.warmup):
+        dense_run(bem, mesh, idx, ops, bem.FP32, chunk)
+    bem.server_stats(reset=True)
+    bem.server_kernel_stats(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        last = dense_run(bem, mesh, idx, ops, bem.FP32, chunk)
+    dt = time.perf_counter() - t0
+    sst, kst = bem.server_stats(), bem.server_kernel_stats()
+    roof, _ = roofline(kst)
+    entries = len(ops) * n * n * args.steps
+    fp64 = None
+    if not args.no_fp64:
+        t1 = time.perf_counter()
+        dense_run(bem, mesh, idx, ops, bem.FP64, chunk)
+        dt64 = time.perf_counter() - t1
+        fp64 = {"value": len(ops) * n * n / dt64, "unit": "entries/s", "seconds_per_step": dt64}
+    worst = None
+    if not args.no_cpu_baseline:
+        import oracle
+        om = oracle.OracleMesh(xyz, tri, 6)
+        pos = np.arange(0, n, max(1, n // 4))[:4]   # row positions in idx
+        worst = 0.0
+        for k, op in enumerate(ops):
+            got = np.vstack([last[k * ((n + chunk - 1) // chunk) + r // chunk].out[r % chunk] for r in pos])
+            ref = om.entries(op, oracle.P1, 0.0, idx[pos], idx)
+            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    line = {
+        "metric": "dense weak-form entries/sec FP32 vs FP64",
+        "value": entries / dt, "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True, "scaling": "strong", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"dense P1 matrix of the Laplace {' + '.join(OP_LABEL[o] for o in ops)} operator(s), "
+                               f"icosphere level {args.dense} ({tri.shape[0]} triangles, {n} vertices), 6-point rule, "
+                               f"vertex-sharing pairs skipped, rows and columns in cluster-tree order, {chunk}-row requests through the "
+                               "request server, "
+                               "FP32 compensated entries, results copied to host memory"},
+        "fp64": fp64, "fp32_over_fp64": (entries / dt / fp64["value"]) if fp64 else None,
+        "max_rel_err_sampled": worst, "requests_per_batch": sst["requests"] / max(1, sst["batches"]),
+        "roofline": roof,
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -280,6 +354,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.dense:
+        dense_main(args)
         return
     from paper_1711_01897_amd import bem, inputs
 
