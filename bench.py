@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--dense", type=int, default=0, metavar="LEVEL",
                     help="instead of the H-matrix workload: the dense P1 matrix of the --ops operators on the "
                          "icosphere of this level, submitted to the request server in row chunks")
+    ap.add_argument("--concurrent", type=int, default=0,
+                    help="1: assemble the step's operators at the same time (one host thread each, the workers "
+                         "split between them), as concurrent clients of the request server")
     ap.add_argument("--ops", default="laplace_slp,laplace_dlp",
                     help="operators assembled per step (comma list of laplace_slp, laplace_dlp, laplace_adlp, "
                          "laplace_hyps); the default is the stated workload")
@@ -160,10 +163,27 @@ def workload_name(args):
 
 def assemble_step(bem, mesh, prec, args):
     out = {"entries": 0, "requests": 0, "rank_sum": 0, "rank_max": 0, "blocks": 0, "phases": {}}
-    for op in step_ops(args):
-        H = bem.hmat_assemble(mesh, op, bem.P1, 0.0, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200,
-                              n_workers=args.workers, blocks_per_worker=args.blocks_per_worker, prec=prec,
-                              dense_mode=0)
+    ops = step_ops(args)
+    if args.concurrent and len(ops) > 1:
+        import threading
+        workers = max(1, args.workers // len(ops))
+        done = {}
+
+        def one(op):
+            done[op] = bem.hmat_assemble(mesh, op, bem.P1, 0.0, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200,
+                                         n_workers=workers, blocks_per_worker=args.blocks_per_worker, prec=prec,
+                                         dense_mode=0)
+        th = [threading.Thread(target=one, args=(op,)) for op in ops]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        results = [done[op] for op in ops]
+    else:
+        results = (bem.hmat_assemble(mesh, op, bem.P1, 0.0, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200,
+                                     n_workers=args.workers, blocks_per_worker=args.blocks_per_worker, prec=prec,
+                                     dense_mode=0) for op in ops)
+    for H in results:
         st = H.stats()
         out["entries"] += st["aca_entries"]
         out["requests"] += st["aca_requests"]

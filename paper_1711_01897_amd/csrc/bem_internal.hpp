@@ -54,6 +54,7 @@ struct ReqDev {
     const int4 *chunk;         // per chunk: first lane, lanes, first dof, dofs
     const int32_t *seg_ptr;    // P1: per lane-side dof, range into seg
     const int32_t *seg;        // P1: packed (lane slot within the chunk << 2 | local vertex)
+    const int32_t *lpos;       // P1: output position of each lane-side dof (null: its own index)
     void *out;                 // final output, row-major nrows x ncols
     int32_t *status;           // set to 1: a vertex-sharing pair was met under BEM_NEAR_ERROR
     int64_t sf, sl;
@@ -172,8 +173,10 @@ struct LaneSet {
     std::vector<int32_t> chunk;       // 4 per chunk: first lane, lanes, first dof, dofs
     std::vector<int32_t> seg_ptr;     // P1: ndof + 1
     std::vector<int32_t> seg;         // P1: packed (slot within the chunk << 2 | local vertex)
+    std::vector<int32_t> pos;         // P1: output position of each lane-side dof when the set was
+                                      // reordered for locality (empty: identity)
     int64_t nchunk() const { return (int64_t)chunk.size() / 4; }
-    size_t ints() const { return chunk.size() + lane.size() + seg_ptr.size() + seg.size(); }
+    size_t ints() const { return chunk.size() + lane.size() + seg_ptr.size() + seg.size() + pos.size(); }
 };
 
 struct LaneRef {                      // device pointers of a resident LaneSet
@@ -185,7 +188,13 @@ struct LaneRef {                      // device pointers of a resident LaneSet
     int64_t ndof = 0, nlane = 0, nseg = 0, nchunk = 0, ndistinct = 0;
 };
 
-void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, LaneSet &ls);
+// Lane set of a dof list.  With reorder, a P1 list longer than one chunk is
+// first ordered along a Morton curve of the vertex positions (ls.pos keeps
+// each entry's position in the caller's list): chunks then hold the stars of
+// neighbouring vertices instead of whatever the caller's order groups, which
+// keeps the duplicated border lanes few.
+void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, LaneSet &ls,
+                    bool reorder = false);
 
 // ---------------------------------------------------------------------------
 // A request on its way through the server.

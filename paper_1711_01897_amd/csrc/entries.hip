@@ -976,7 +976,8 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
             g = g0 + SegPrefetch::kN;
         }
         for (; g < g1; ++g) add(R.seg[g]);
-        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)d * R.sl;
+        const int32_t dp = R.lpos ? R.lpos[d] : d;   // lane-side output position
+        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)dp * R.sl;
         if constexpr (is_cplx<OP>())
             reinterpret_cast<float2 *>(R.out)[o] = make_float2(ar + br, ai + bi);
         else
@@ -1083,7 +1084,8 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
             g = g0 + SegPrefetch::kN;
         }
         for (; g < g1; ++g) add(R.seg[g]);
-        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)d * R.sl;
+        const int32_t dp = R.lpos ? R.lpos[d] : d;   // lane-side output position
+        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)dp * R.sl;
         if constexpr (is_cplx<OP>())
             reinterpret_cast<double2 *>(R.out)[o] = make_double2(xr, xi);
         else

@@ -125,8 +125,55 @@ void finalize_sizes(Request &r)
 
 }  // namespace
 
-void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, LaneSet &ls)
+namespace {
+
+// 30-bit Morton code of a point in the mesh's bounding box (10 bits per axis).
+uint32_t morton3(double x, double y, double z, const double *lo, const double *inv)
 {
+    auto spread = [](uint32_t v) {
+        v &= 1023u;
+        v = (v | (v << 16)) & 0x030000FFu;
+        v = (v | (v << 8)) & 0x0300F00Fu;
+        v = (v | (v << 4)) & 0x030C30C3u;
+        v = (v | (v << 2)) & 0x09249249u;
+        return v;
+    };
+    auto q = [](double t) { return (uint32_t)std::min(1023.0, std::max(0.0, t * 1023.0)); };
+    return spread(q((x - lo[0]) * inv[0])) | (spread(q((y - lo[1]) * inv[1])) << 1) |
+           (spread(q((z - lo[2]) * inv[2])) << 2);
+}
+
+}  // namespace
+
+void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, LaneSet &ls, bool reorder)
+{
+    ls.pos.clear();
+    if (reorder && space == BEM_P1 && n > kBlockLanes) {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, inv[3];
+        for (int64_t v = 0; v < m.nv; ++v)
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = std::min(lo[d], m.xyz[3 * v + d]);
+                hi[d] = std::max(hi[d], m.xyz[3 * v + d]);
+            }
+        for (int d = 0; d < 3; ++d) inv[d] = hi[d] > lo[d] ? 1.0 / (hi[d] - lo[d]) : 0.0;
+        std::vector<std::pair<uint32_t, int32_t>> key((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            const double *x = &m.xyz[3 * (size_t)dofs[i]];
+            key[i] = {morton3(x[0], x[1], x[2], lo, inv), (int32_t)i};
+        }
+        std::sort(key.begin(), key.end());
+        std::vector<int32_t> sorted((size_t)n);
+        ls.pos.resize((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            sorted[i] = dofs[key[i].second];
+            ls.pos[i] = key[i].second;
+        }
+        std::vector<int32_t> keep;
+        keep.swap(ls.pos);
+        build_lane_set(m, space, sorted.data(), n, ls, false);
+        ls.pos.swap(keep);
+        return;
+    }
     ls.ndof = n;
     ls.lane.clear();
     ls.chunk.clear();
@@ -213,7 +260,7 @@ int expand_request(Request &r)
     const std::vector<int32_t> &fix_dofs = r.fixrows ? r.rows : r.cols;
     const std::vector<int32_t> &lane_dofs = r.fixrows ? r.cols : r.rows;
     expand_fixed(m, r.space, fix_dofs.data(), (int64_t)fix_dofs.size(), r);
-    build_lane_set(m, r.space, lane_dofs.data(), (int64_t)lane_dofs.size(), r.own);
+    build_lane_set(m, r.space, lane_dofs.data(), (int64_t)lane_dofs.size(), r.own, true);
     r.nlane = (int64_t)r.own.lane.size();
     r.nchunk = r.own.nchunk();
     r.ndistinct = r.own.ndistinct;
@@ -230,6 +277,7 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
     r.own.chunk.clear();
     r.own.seg_ptr.clear();
     r.own.seg.clear();
+    r.own.pos.clear();
     expand_fixed(*r.mesh, r.space, &dof, 1, r);
     r.nlane = ext->nlane;
     r.nchunk = ext->nchunk;
@@ -272,11 +320,13 @@ size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t 
         d.lane = r.ext->lane;
         d.seg_ptr = r.ext->seg_ptr;
         d.seg = r.ext->seg;
+        d.lpos = nullptr;
     } else {
         d.chunk = reinterpret_cast<const int4 *>(put(r.own.chunk));
         d.lane = put(r.own.lane);
         d.seg_ptr = put(r.own.seg_ptr);
         d.seg = put(r.own.seg);
+        d.lpos = put(r.own.pos);
     }
     d.fstar = m.d_star;
     if (r.fixrows) {   // output position of (fixed f, lane-side dof d): out[f * sf + d * sl]

@@ -103,6 +103,33 @@ def test_adjoint_double_layer_is_exact_transpose(sphere2, pair, space, prec):
         assert np.array_equal(a, d.T)
 
 
+@pytest.mark.parametrize("op", [bem.LAPLACE_SLP, bem.LAPLACE_DLP, bem.HELMHOLTZ_SLP, bem.LAPLACE_ADLP])
+@pytest.mark.parametrize("prec", [bem.FP64, bem.FP32])
+def test_p1_scrambled_long_lane_lists(op, prec):
+    """P1 lane lists longer than one chunk are reordered along a space-filling
+    curve inside the library; the entries still land at the caller's
+    positions, duplicates included, for both fixed sides."""
+    xyz, tri = inputs.icosphere(3)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    rng = np.random.Generator(np.random.PCG64(9))
+    nv = xyz.shape[0]
+    long_ = rng.permutation(nv)[:600].astype(np.int32)
+    long_ = np.concatenate([long_, long_[:37]])          # duplicated positions
+    short = rng.choice(nv, 5, replace=False).astype(np.int32)
+    for rows, cols in ((short, long_), (long_, short)):
+        got = bem.eval_entries(mesh, op, bem.P1, K[op], rows, cols, prec=prec)
+        ref = om.entries(op, O.P1, K[op], rows, cols)
+        e = normwise(got.astype(ref.dtype), ref)
+        assert e <= tol(op, prec), (rows.size, cols.size, e)
+        # duplicated indices give identical entries
+        if cols.size > rows.size:
+            assert np.array_equal(got[:, 600:], got[:, :37])
+        else:
+            assert np.array_equal(got[600:], got[:37])
+    mesh.destroy()
+
+
 @pytest.mark.parametrize("prec", [bem.FP64, bem.FP32])
 def test_four_point_rule_helmholtz_spheroid(prec):
     """4-point rule, elongated spheroid, Helmholtz single layer at 10
