@@ -224,6 +224,14 @@ struct Request {
     int64_t nblocks = 0;
     size_t batch_bytes = 0;     // request_bytes(), cached at expansion
 
+    // staging records built by the submitting thread (prebuild_staging); the
+    // server's dispatcher copies them into a batch and fills in what depends
+    // on the batch: the request index of each block, the staged inputs, the
+    // output and status addresses
+    int key = 0;                          // launch group (operator, space, precision, rule)
+    std::vector<EntryBlock> pre_blocks;   // `req` holds the fixed-side bit only
+    ReqDev pre_dev{};
+
     // completion
     std::mutex mu;
     std::condition_variable cv;
@@ -262,6 +270,14 @@ size_t request_bytes(const Request &r);
 // Writes the request's inputs at host_base + off (staging) and fills its
 // descriptor with device addresses at dev_base + off; returns the bytes used.
 size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d);
+// The descriptor fields that do not depend on where the request is staged.
+void describe_request(const Request &r, ReqDev &d);
+// Copies a request's own lane-side arrays into staging at `off` and points d
+// at their device copies (no-op for a device-resident lane side); returns
+// the bytes used (r.in_bytes).
+size_t stage_own_inputs(const Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d);
+// Fills r.key, r.pre_blocks and r.pre_dev (called by the submitting thread).
+void prebuild_staging(Request &r);
 // off_status addresses the request's int32 status word (zeroed by the caller).
 void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_status, ReqDev &d);
 

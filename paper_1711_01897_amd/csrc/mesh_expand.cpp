@@ -298,36 +298,22 @@ size_t request_bytes(const Request &r)
     return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * (sizeof(EntryBlock) + 16) + 256;
 }
 
-size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d)
+void describe_request(const Request &r, ReqDev &d)
 {
     const bem_mesh &m = *r.mesh;
-    char *h = host_base + off;
-    char *dv = dev_base + off;
-    auto put = [&](const std::vector<int32_t> &v) -> const int32_t * {
-        if (v.empty()) return nullptr;
-        std::memcpy(h, v.data(), 4 * v.size());
-        const int32_t *dp = reinterpret_cast<const int32_t *>(dv);
-        h += 4 * v.size();
-        dv += 4 * v.size();
-        return dp;
-    };
     d.g32 = m.d_g32;
     d.g64 = m.d_g64;
     d.vtx = m.d_vtx;
-    // the chunk table (int4 records) goes first: the section starts 16-byte aligned
     if (r.ext) {
         d.chunk = r.ext->chunk;
         d.lane = r.ext->lane;
         d.seg_ptr = r.ext->seg_ptr;
         d.seg = r.ext->seg;
-        d.lpos = nullptr;
     } else {
-        d.chunk = reinterpret_cast<const int4 *>(put(r.own.chunk));
-        d.lane = put(r.own.lane);
-        d.seg_ptr = put(r.own.seg_ptr);
-        d.seg = put(r.own.seg);
-        d.lpos = put(r.own.pos);
+        d.chunk = nullptr;
+        d.lane = d.seg_ptr = d.seg = nullptr;
     }
+    d.lpos = nullptr;
     d.fstar = m.d_star;
     if (r.fixrows) {   // output position of (fixed f, lane-side dof d): out[f * sf + d * sl]
         d.sf = r.ncols;
@@ -344,7 +330,36 @@ size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t 
     d.near_error = r.near == BEM_NEAR_ERROR ? 1 : 0;
     d.k = r.k;
     d.kk = r.k / (2.0 * 3.14159265358979323846);
+    d.out = nullptr;
+    d.status = nullptr;
+}
+
+size_t stage_own_inputs(const Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d)
+{
+    if (r.ext) return r.in_bytes;
+    char *h = host_base + off;
+    char *dv = dev_base + off;
+    auto put = [&](const std::vector<int32_t> &v) -> const int32_t * {
+        if (v.empty()) return nullptr;
+        std::memcpy(h, v.data(), 4 * v.size());
+        const int32_t *dp = reinterpret_cast<const int32_t *>(dv);
+        h += 4 * v.size();
+        dv += 4 * v.size();
+        return dp;
+    };
+    // the chunk table (int4 records) goes first: the section starts 16-byte aligned
+    d.chunk = reinterpret_cast<const int4 *>(put(r.own.chunk));
+    d.lane = put(r.own.lane);
+    d.seg_ptr = put(r.own.seg_ptr);
+    d.seg = put(r.own.seg);
+    d.lpos = put(r.own.pos);
     return r.in_bytes;
+}
+
+size_t stage_request_inputs(Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d)
+{
+    describe_request(r, d);
+    return stage_own_inputs(r, host_base, dev_base, off, d);
 }
 
 void finish_descriptor(const Request &r, char *dev_base, size_t off_out, size_t off_status, ReqDev &d)
@@ -384,6 +399,14 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
         }
     }
     return n;
+}
+
+void prebuild_staging(Request &r)
+{
+    r.key = ((kernel_op(r.op) * 2 + r.space) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0);
+    r.pre_blocks.resize((size_t)r.nblocks);
+    write_blocks(r, 0, r.pre_blocks.data());
+    describe_request(r, r.pre_dev);
 }
 
 }  // namespace bem

@@ -55,10 +55,6 @@ int env_int(const char *name, int dflt, int lo, int hi)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int entry_key(const Request &r)
-{
-    return ((kernel_op(r.op) * 2 + r.space) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0);
-}
 
 struct Launch {
     Variant v{};
@@ -265,6 +261,9 @@ public:
 
     int submit_many(Request *const *rs, size_t n)
     {
+        // block records and descriptors are built here, on the submitting
+        // thread, while its request data is in its own cache
+        for (size_t i = 0; i < n; ++i) prebuild_staging(*rs[i]);
         {
             std::lock_guard<std::mutex> g(mu);
             if (stop) return fail(BEM_E_BUSY, "server is being reconfigured");
@@ -381,7 +380,7 @@ public:
         for (auto &g : sc.members) g.clear();
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
-            if (r.nblocks > 0) sc.members[entry_key(r)].push_back(i);
+            if (r.nblocks > 0) sc.members[r.key].push_back(i);
             b->entries += r.entries();
             b->evals += r.evals;
         }
@@ -443,12 +442,21 @@ public:
         for (const Launch &L : launches) {
             EntryBlock *p = reinterpret_cast<EntryBlock *>(hb + L.off_tab);
             int64_t k = 0;
-            for (int i : sc.members[L.key]) k += write_blocks(*take[i], i, p + k);
+            for (int i : sc.members[L.key]) {
+                const Request &r = *take[i];
+                const int64_t nb = (int64_t)r.pre_blocks.size();
+                std::memcpy(p + k, r.pre_blocks.data(), sizeof(EntryBlock) * (size_t)nb);
+                for (int64_t j = 0; j < nb; ++j) p[k + j].req |= i << 1;
+                k += nb;
+            }
         }
         if (time_phases) tp[3] = now_seconds();
         ReqDev *hreq = reinterpret_cast<ReqDev *>(hb);
         size_t in = off_in;
-        for (int i = 0; i < n; ++i) in += stage_request_inputs(*take[i], hb, db, in, hreq[i]);
+        for (int i = 0; i < n; ++i) {
+            hreq[i] = take[i]->pre_dev;
+            in += stage_own_inputs(*take[i], hb, db, in, hreq[i]);
+        }
         std::memset(hb + off_status, 0, sizeof(int32_t) * n);
         b->off_clock = off_clock;
         for (int i = 0; i < n; ++i) {
