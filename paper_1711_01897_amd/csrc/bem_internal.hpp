@@ -136,6 +136,7 @@ struct bem_mesh {
     std::vector<int64_t> star_ptr;    // nv + 1
     std::vector<int32_t> star;        // packed (triangle << 2 | local vertex), ascending triangles
     double mean_J = 0.0, mean_edge = 0.0;
+    double box_lo[3] = {0.0, 0.0, 0.0}, box_inv[3] = {0.0, 0.0, 0.0};   // bounding box: low corner, 1/extent
     int max_star = 0;
     int device = 0;
     float *d_g32 = nullptr;

@@ -149,17 +149,10 @@ void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n
 {
     ls.pos.clear();
     if (reorder && space == BEM_P1 && n > kBlockLanes) {
-        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY}, inv[3];
-        for (int64_t v = 0; v < m.nv; ++v)
-            for (int d = 0; d < 3; ++d) {
-                lo[d] = std::min(lo[d], m.xyz[3 * v + d]);
-                hi[d] = std::max(hi[d], m.xyz[3 * v + d]);
-            }
-        for (int d = 0; d < 3; ++d) inv[d] = hi[d] > lo[d] ? 1.0 / (hi[d] - lo[d]) : 0.0;
         std::vector<std::pair<uint32_t, int32_t>> key((size_t)n);
         for (int64_t i = 0; i < n; ++i) {
             const double *x = &m.xyz[3 * (size_t)dofs[i]];
-            key[i] = {morton3(x[0], x[1], x[2], lo, inv), (int32_t)i};
+            key[i] = {morton3(x[0], x[1], x[2], m.box_lo, m.box_inv), (int32_t)i};
         }
         std::sort(key.begin(), key.end());
         std::vector<int32_t> sorted((size_t)n);
@@ -467,6 +460,15 @@ int mesh_create_impl(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
     }
     m->mean_J = sj / nt;
     m->mean_edge = se / (3.0 * nt);
+    for (int d = 0; d < 3; ++d) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t v = 0; v < nv; ++v) {
+            lo = std::min(lo, xyz[3 * v + d]);
+            hi = std::max(hi, xyz[3 * v + d]);
+        }
+        m->box_lo[d] = lo;
+        m->box_inv[d] = hi > lo ? 1.0 / (hi - lo) : 0.0;
+    }
 
     hipError_t e = hipGetDevice(&m->device);
     double *d_xyz = nullptr;
