@@ -90,7 +90,14 @@ typedef enum { BEM_P0 = 0, BEM_P1 = 1 } bem_space;
  * compensated (TwoSum) accumulation, centroid-relative geometry and, for
  * Helmholtz, the phase k r reduced to a turn in FP64. */
 typedef enum { BEM_FP64 = 0, BEM_FP32 = 1 } bem_prec;
-typedef enum { BEM_NEAR_ERROR = 0, BEM_NEAR_SKIP = 1 } bem_near;
+/* Vertex-sharing (identical, edge- or vertex-adjacent) triangle pairs:
+ * BEM_NEAR_ERROR fails the call, BEM_NEAR_SKIP lets them contribute zero,
+ * BEM_NEAR_SINGULAR integrates them on the device with a singular scheme
+ * (Section 3.2.3 leaves them to one; here: regularising transformations of
+ * the pair to the unit 4-cube, 8-point Gauss-Legendre per dimension, FP64,
+ * added to the regular part).  BEM_NEAR_SINGULAR is available for P0 and
+ * the Laplace single, double and adjoint double layer (BEM_E_ARG otherwise). */
+typedef enum { BEM_NEAR_ERROR = 0, BEM_NEAR_SKIP = 1, BEM_NEAR_SINGULAR = 2 } bem_near;
 
 typedef struct bem_mesh bem_mesh;
 typedef struct bem_ticket bem_ticket;

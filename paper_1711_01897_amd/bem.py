@@ -21,7 +21,7 @@ LAPLACE_ADLP, HELMHOLTZ_ADLP = 4, 5
 LAPLACE_HYPS, HELMHOLTZ_HYPS = 6, 7
 P0, P1 = 0, 1
 FP64, FP32 = 0, 1
-NEAR_ERROR, NEAR_SKIP = 0, 1
+NEAR_ERROR, NEAR_SKIP, NEAR_SINGULAR = 0, 1, 2
 
 OK, E_ARG, E_OOM, E_DEVICE, E_NEARFIELD, E_BUSY, E_CANCELLED, E_TIMEOUT, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6, -7, -8
 _NAMES = {E_ARG: "BEM_E_ARG", E_OOM: "BEM_E_OOM", E_DEVICE: "BEM_E_DEVICE", E_NEARFIELD: "BEM_E_NEARFIELD",

@@ -107,6 +107,32 @@ hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, in
 // ids (w = index[i] & 3 when shift == 2, else 0); i < n.
 hipError_t launch_gather(const float *g32, const int4 *vtx, const int32_t *index, int shift, int64_t n, float *geo,
                          int4 *meta, hipStream_t s);
+// One vertex-sharing (singular) P0 triangle pair of a BEM_NEAR_SINGULAR
+// request, integrated by near.hip.  Vertices in the layout of its kind:
+//   kind 0, identical:   v = V0, V1, V2 (the triangle in its own order)
+//   kind 1, common edge: v = P, Q, A, B (shared edge P-Q; A the test
+//                        triangle's third vertex, B the trial triangle's)
+//   kind 2, common vertex: v = P, A, B, C, D (shared P; A, B the test
+//                        triangle's others, C, D the trial triangle's)
+// ny: unit normal of the trial triangle; jt, js: |cross| of the test and
+// trial triangles (twice their areas).  out: the entry's address; the
+// kernel adds the pair's value to what the entry kernel stored there.
+struct NearItem {
+    double v[15];
+    double ny[3];
+    double jt, js;
+    void *out;
+    int32_t kind;
+    int32_t pad;
+};
+static_assert(sizeof(NearItem) == 176, "near items are 176 bytes");
+
+// Adds each item's singular pair integral (FP64, regularising 4D
+// transformations, Gauss-Legendre per dimension) to its entry: the Laplace
+// single (op 0) or double layer (op 1), into float (fp32 = true) or double
+// entries.  One workgroup per item.
+hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s);
+
 // Copies bytes (a multiple of 16, both addresses 16-byte aligned) from src
 // (device-visible host staging) to dst (device) with a kernel on stream s.
 hipError_t launch_stage_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
@@ -229,6 +255,8 @@ struct Request {
     // server's dispatcher copies them into a batch and fills in what depends
     // on the batch: the request index of each block, the staged inputs, the
     // output and status addresses
+    std::vector<NearItem> near_items;     // BEM_NEAR_SINGULAR: the request's vertex-sharing pairs
+    std::vector<int64_t> near_index;      // their entries' positions in the output
     int key = 0;                          // launch group (operator, space, precision, rule)
     std::vector<EntryBlock> pre_blocks;   // `req` holds the fixed-side bit only
     ReqDev pre_dev{};

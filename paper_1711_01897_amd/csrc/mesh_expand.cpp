@@ -223,6 +223,85 @@ void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n
     sc.next_gen();
 }
 
+namespace {
+
+// The vertex-sharing pairs of a P0 request in the layouts of NearItem.  The
+// kernels' test triangle is the row's (the column's for the adjoint double
+// layer, evaluated as the transposed double layer).
+void build_near_items(Request &r)
+{
+    const bem_mesh &m = *r.mesh;
+    const bool adj = is_adjoint_op(r.op);
+    std::vector<std::pair<int32_t, int64_t>> colpos((size_t)r.ncols);
+    for (int64_t c = 0; c < r.ncols; ++c) colpos[c] = {r.cols[c], c};
+    std::sort(colpos.begin(), colpos.end());
+    auto vtx = [&](int32_t t, int k) { return &m.xyz[3 * (size_t)m.tri[3 * (size_t)t + k]]; };
+    auto put3 = [](double *dst, const double *src) {
+        dst[0] = src[0];
+        dst[1] = src[1];
+        dst[2] = src[2];
+    };
+    auto cross_len = [&](int32_t t, double *n) {
+        const double *a = vtx(t, 0), *b = vtx(t, 1), *c = vtx(t, 2);
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double J = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        if (n)
+            for (int d = 0; d < 3; ++d) n[d] = N[d] / J;
+        return J;
+    };
+    std::vector<int32_t> nb;
+    for (int64_t ri = 0; ri < r.nrows; ++ri) {
+        const int32_t a = r.rows[ri];
+        nb.clear();
+        for (int k = 0; k < 3; ++k) {
+            const int32_t v = m.tri[3 * (size_t)a + k];
+            for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) nb.push_back(m.star[s] >> 2);
+        }
+        std::sort(nb.begin(), nb.end());
+        nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+        for (int32_t b : nb) {
+            auto it = std::lower_bound(colpos.begin(), colpos.end(), std::make_pair(b, (int64_t)-1));
+            for (; it != colpos.end() && it->first == b; ++it) {
+                const int32_t T = adj ? b : a, S = adj ? a : b;   // kernel test and trial triangles
+                NearItem q{};
+                const int32_t *tv = &m.tri[3 * (size_t)T], *sv = &m.tri[3 * (size_t)S];
+                int shared = 0, ts[3], ss[3];
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j)
+                        if (tv[i] == sv[j]) {
+                            ts[shared] = i;
+                            ss[shared] = j;
+                            ++shared;
+                        }
+                q.jt = cross_len(T, nullptr);
+                q.js = cross_len(S, q.ny);
+                if (shared == 3) {
+                    q.kind = 0;
+                    for (int k = 0; k < 3; ++k) put3(q.v + 3 * k, vtx(T, k));
+                } else if (shared == 2) {
+                    q.kind = 1;
+                    put3(q.v, vtx(T, ts[0]));
+                    put3(q.v + 3, vtx(T, ts[1]));
+                    put3(q.v + 6, vtx(T, 3 - ts[0] - ts[1]));
+                    put3(q.v + 9, vtx(S, 3 - ss[0] - ss[1]));
+                } else {
+                    q.kind = 2;
+                    put3(q.v, vtx(T, ts[0]));
+                    put3(q.v + 3, vtx(T, (ts[0] + 1) % 3));
+                    put3(q.v + 6, vtx(T, (ts[0] + 2) % 3));
+                    put3(q.v + 9, vtx(S, (ss[0] + 1) % 3));
+                    put3(q.v + 12, vtx(S, (ss[0] + 2) % 3));
+                }
+                r.near_items.push_back(q);
+                r.near_index.push_back(ri * r.ncols + it->second);
+            }
+        }
+    }
+}
+
+}  // namespace
+
 int expand_request(Request &r)
 {
     const bem_mesh &m = *r.mesh;
@@ -231,7 +310,12 @@ int expand_request(Request &r)
     if ((r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS) && r.space != BEM_P1)
         return fail(BEM_E_ARG, "the hypersingular operator needs continuous (P1) functions");
     if (r.prec != BEM_FP32 && r.prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
-    if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP) return fail(BEM_E_ARG, "unknown near-field policy");
+    if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP && r.near != BEM_NEAR_SINGULAR)
+        return fail(BEM_E_ARG, "unknown near-field policy");
+    if (r.near == BEM_NEAR_SINGULAR &&
+        (r.space != BEM_P0 || (r.op != BEM_LAPLACE_SLP && r.op != BEM_LAPLACE_DLP && r.op != BEM_LAPLACE_ADLP)))
+        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for P0 and the Laplace single, double and adjoint "
+                               "double layer");
     if (is_complex_op(r.op)) {
         if (!(std::isfinite(r.k) && r.k > 0.0)) return fail(BEM_E_ARG, "Helmholtz needs a finite wavenumber k > 0");
     } else if (r.k != 0.0) {
@@ -257,12 +341,17 @@ int expand_request(Request &r)
     r.nlane = (int64_t)r.own.lane.size();
     r.nchunk = r.own.nchunk();
     r.ndistinct = r.own.ndistinct;
+    r.near_items.clear();
+    r.near_index.clear();
+    if (r.near == BEM_NEAR_SINGULAR) build_near_items(r);
     finalize_sizes(r);
     return BEM_OK;
 }
 
 void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext)
 {
+    r.near_items.clear();
+    r.near_index.clear();
     r.ext = ext;
     r.fixrows = rowfix;
     r.rowfix = is_adjoint_op(r.op) ? 1 - rowfix : rowfix;
@@ -288,7 +377,8 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
 size_t request_bytes(const Request &r)
 {
     // descriptor, inputs, status, outputs, block table, launch-timing records
-    return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * (sizeof(EntryBlock) + 16) + 256;
+    return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * (sizeof(EntryBlock) + 16) +
+           r.near_items.size() * sizeof(NearItem) + 512;
 }
 
 void describe_request(const Request &r, ReqDev &d)

@@ -410,6 +410,13 @@ public:
             L.off_tab = off;
             off = align256(off + sizeof(EntryBlock) * (size_t)L.count);
         }
+        // singular pairs of BEM_NEAR_SINGULAR requests (few requests carry any)
+        std::vector<std::pair<int, size_t>> near_at;
+        for (int i = 0; i < n; ++i)
+            if (!take[i]->near_items.empty()) {
+                near_at.push_back({i, off});
+                off = align256(off + sizeof(NearItem) * take[i]->near_items.size());
+            }
         const size_t off_in = off;
         for (int i = 0; i < n; ++i) off += take[i]->in_bytes;
         const size_t h2d_end = align256(off);
@@ -458,6 +465,13 @@ public:
             in += stage_own_inputs(*take[i], hb, db, in, hreq[i]);
         }
         std::memset(hb + off_status, 0, sizeof(int32_t) * n);
+        for (const auto &na : near_at) {
+            const Request &r = *take[na.first];
+            NearItem *q = reinterpret_cast<NearItem *>(hb + na.second);
+            std::memcpy(q, r.near_items.data(), sizeof(NearItem) * r.near_items.size());
+            for (size_t j = 0; j < r.near_items.size(); ++j)
+                q[j].out = hd + out_off[na.first] + (size_t)r.near_index[j] * r.elem_bytes;
+        }
         b->off_clock = off_clock;
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
@@ -490,6 +504,12 @@ public:
             note(launch_entries(L.v, dreq, reinterpret_cast<const EntryBlock *>(db + L.off_tab), L.count, stream, ck,
                                 e0, e1));
             blk0 += L.count;
+        }
+        // singular pairs after the entry kernels, on the same stream
+        for (const auto &na : near_at) {
+            const Request &r = *take[na.first];
+            note(launch_near(kernel_op(r.op) == BEM_LAPLACE_DLP ? 1 : 0, r.prec == BEM_FP32,
+                             reinterpret_cast<const NearItem *>(db + na.second), (int64_t)r.near_items.size(), stream));
         }
         b->ev_done = get_event();
         note(hipEventRecord(b->ev_done, stream));
