@@ -297,12 +297,14 @@ typedef struct {
     int32_t n_workers;      /* host ACA worker threads */
     int32_t blocks_per_worker; /* ACA blocks each worker keeps in flight */
     bem_prec prec;          /* precision of the device entries */
-    int32_t dense_mode;     /* 0: dense leaves left empty; 1: their regular part (BEM_NEAR_SKIP) */
+    int32_t dense_mode;     /* 0: dense leaves left empty; 1: their regular part (BEM_NEAR_SKIP);
+                               2: complete, singular pairs included (BEM_NEAR_SINGULAR: P0 Laplace
+                               single, double and adjoint double layer only, else BEM_E_ARG) */
 } bem_hmat_params;
 
 /* Fill every admissible leaf of the block tree by ACA (all rows and columns
- * on the device) and, if dense_mode == 1, every dense leaf by its regular
- * part.  The caller gets an H-matrix handle. */
+ * on the device) and, if dense_mode is 1 or 2, every dense leaf (its regular
+ * part, or all of it).  The caller gets an H-matrix handle. */
 int bem_hmat_assemble(bem_mesh *mesh, bem_op op, bem_space space, double k,
                       const bem_hmat_params *params, bem_hmat **out);
 

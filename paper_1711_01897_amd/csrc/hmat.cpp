@@ -424,6 +424,7 @@ struct AssemblyCtx {
     int max_rank;
     bem_hmat *h;
     const std::vector<LaneRef> *lanes;  // per cluster id
+    int dense_near = BEM_NEAR_SKIP;      // near-field policy of the dense leaves
     std::vector<Job> jobs;
     std::atomic<int64_t> next{0};
     std::atomic<int> error{0};
@@ -489,7 +490,7 @@ int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag, WorkerT
     r.cb_ctx = &dq;
     r.tag = tag;
     if (!s.adm) {
-        r.near = BEM_NEAR_SKIP;
+        r.near = C.dense_near;
         r.rows.assign(C.h->rows(L), C.h->rows(L) + L.m);
         r.cols.assign(C.h->cols(L), C.h->cols(L) + L.n);
         r.nrows = (int64_t)r.rows.size();
@@ -805,7 +806,8 @@ int aca_callback(int64_t m, int64_t n, int is_complex, bem_row_fn get_row, bem_c
 int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_params *p, bem_hmat **out)
 {
     if (!mesh || !p || !out) return fail(BEM_E_ARG, "null argument");
-    if (p->leaf_size < 1 || !(p->eta > 0) || p->max_rank < 1 || !(p->aca_tol >= 0))
+    if (p->leaf_size < 1 || !(p->eta > 0) || p->max_rank < 1 || !(p->aca_tol >= 0) || p->dense_mode < 0 ||
+        p->dense_mode > 2)
         return fail(BEM_E_ARG, "bad H-matrix parameters");
     {
         // validate op/k/space/prec once with an empty request
@@ -815,7 +817,7 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
         probe.space = space;
         probe.prec = p->prec;
         probe.k = k;
-        probe.near = BEM_NEAR_SKIP;
+        probe.near = p->dense_mode == 2 ? BEM_NEAR_SINGULAR : BEM_NEAR_SKIP;
         const int rc = expand_request(probe);
         if (rc != BEM_OK) return rc;
     }
@@ -838,6 +840,7 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
     C.prec = p->prec;
     C.k = k;
     C.tol = p->aca_tol;
+    C.dense_near = p->dense_mode == 2 ? BEM_NEAR_SINGULAR : BEM_NEAR_SKIP;
     C.max_rank = p->max_rank;
     C.h = h;
     std::vector<std::pair<const int32_t *, int64_t>> lists(P.nodes.size(), {nullptr, 0});
@@ -864,7 +867,7 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
         L.m = a.end - a.begin;
         L.c0 = c.begin;
         L.n = c.end - c.begin;
-        if (L.adm || p->dense_mode == 1) C.jobs.push_back(Job{(int64_t)b, L.adm});
+        if (L.adm || p->dense_mode >= 1) C.jobs.push_back(Job{(int64_t)b, L.adm});
     }
     // largest blocks first
     std::stable_sort(C.jobs.begin(), C.jobs.end(), [&](const Job &x, const Job &y) {

@@ -85,3 +85,24 @@ def test_singular_policy_limits(ico2):
         bem.eval_entries(mesh, bem.LAPLACE_SLP, bem.P1, 0.0, idx, idx, near=bem.NEAR_SINGULAR)
     with pytest.raises(bem.BemError):
         bem.eval_entries(mesh, bem.HELMHOLTZ_SLP, bem.P0, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
+
+
+@pytest.mark.parametrize("op", [bem.LAPLACE_SLP, bem.LAPLACE_DLP])
+def test_complete_hmatrix_matvec(op):
+    """dense_mode 2: every leaf from the device, singular pairs included.
+    Reference: the oracle's full P0 matrix, vertex-sharing pairs from the
+    near-field fixture extrapolated over levels 4 and 5 (regular pairs are the
+    same in both levels, so the combination leaves them unchanged)."""
+    xyz, tri = inputs.icosphere(3)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    H = bem.hmat_assemble(mesh, op, bem.P0, 0.0, leaf_size=32, eta=1.0, aca_tol=1e-8, max_rank=100, n_workers=4,
+                          blocks_per_worker=8, prec=bem.FP64, dense_mode=2)
+    A = (4 * om.p0_matrix_with_nearfield(op, 0.0, 5) - om.p0_matrix_with_nearfield(op, 0.0, 4)) / 3
+    x = np.random.Generator(np.random.PCG64(3)).normal(size=tri.shape[0])
+    err = np.linalg.norm(H.matvec(x) - A @ x) / np.linalg.norm(A @ x)
+    st = H.stats()
+    print(st, err)
+    assert err <= 1e-6
+    H.destroy()
+    mesh.destroy()
