@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--dense", type=int, default=0, metavar="LEVEL",
                     help="instead of the H-matrix workload: the dense P1 matrix of the --ops operators on the "
                          "icosphere of this level, submitted to the request server in row chunks")
+    ap.add_argument("--complete", type=int, default=0, metavar="LEVEL",
+                    help="instead of the ACA workload: complete P0 Laplace single-layer H-matrices (dense leaves "
+                         "with their singular pairs) on the icosphere of this level, FP64")
     ap.add_argument("--concurrent", type=int, default=0,
                     help="1: assemble the step's operators at the same time (one host thread each, the workers "
                          "split between them), as concurrent clients of the request server")
@@ -358,6 +361,60 @@ def dense_main(args):
     print(json.dumps(line))
 
 
+def complete_main(args):
+    """Complete P0 Laplace single-layer H-matrix (leaf 100, eta 1, ACA tol
+    1e-8, FP64): admissible leaves by ACA, dense leaves with their
+    vertex-sharing pairs integrated on the device; timed against the same
+    assembly with the singular pairs skipped."""
+    import numpy as np
+    from paper_1711_01897_amd import bem, inputs
+    xyz, tri = inputs.icosphere(args.complete)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    nt = tri.shape[0]
+
+    def assemble(mode):
+        t0 = time.perf_counter()
+        H = bem.hmat_assemble(mesh, bem.LAPLACE_SLP, bem.P0, 0.0, leaf_size=100, eta=1.0, aca_tol=1e-8,
+                              max_rank=200, n_workers=args.workers, blocks_per_worker=args.blocks_per_worker,
+                              prec=bem.FP64, dense_mode=mode)
+        dt = time.perf_counter() - t0
+        st = H.stats()
+        H.destroy()
+        return dt, st
+
+    for _ in range(args.warmup):
+        assemble(2)
+    t2 = min(assemble(2)[0] for _ in range(args.steps))
+    t1, st = min((assemble(1) for _ in range(args.steps)), key=lambda r: r[0])
+    # vertex-sharing pairs by the number of shared vertices (3 identical, 2 common edge, 1 common vertex)
+    stars = [[] for _ in range(xyz.shape[0])]
+    for t, (a, b, c) in enumerate(tri.tolist()):
+        stars[a].append(t), stars[b].append(t), stars[c].append(t)
+    kinds = {1: 0, 2: 0, 3: 0}
+    for t, verts in enumerate(tri.tolist()):
+        vs = set(verts)
+        for s in set(stars[verts[0]] + stars[verts[1]] + stars[verts[2]]):
+            kinds[len(vs.intersection(tri[s].tolist()))] += 1
+    near_pairs = sum(kinds.values())
+    # algorithmic flops of the singular-pair kernel: 14 per kernel evaluation (difference vector 6, |c|^2 5,
+    # rsqrt 1, weighted sum 2); evaluations per pair 96 (identical), 1024 (common edge), 8192 (common vertex)
+    near_flops = 14 * (96 * kinds[3] + 1024 * kinds[2] + 8192 * kinds[1])
+    line = {
+        "metric": "complete H-matrix assembly seconds (P0 Laplace single layer, FP64)",
+        "value": t2, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"icosphere level {args.complete} ({nt} triangles), leaf 100, eta 1.0, ACA tol 1e-8, "
+                               "dense leaves complete (singular pairs on the device)",
+                   "admissible_blocks": st["admissible_blocks"], "dense_blocks": st["dense_blocks"],
+                   "dense_entries": st["dense_entries"], "aca_entries": st["aca_entries"]},
+        "seconds_without_singular_pairs": t1, "singular_pairs": near_pairs,
+        "singular_pairs_by_shared_vertices": {str(k): v for k, v in kinds.items()},
+        "singular_kernel_flops_per_assembly": near_flops,
+        "singular_pairs_per_second_marginal": near_pairs / max(t2 - t1, 1e-9),
+    }
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -377,6 +434,9 @@ def main():
         return
     if args.dense:
         dense_main(args)
+        return
+    if args.complete:
+        complete_main(args)
         return
     from paper_1711_01897_amd import bem, inputs
 

@@ -93,9 +93,10 @@ typedef enum { BEM_FP64 = 0, BEM_FP32 = 1 } bem_prec;
 /* Vertex-sharing (identical, edge- or vertex-adjacent) triangle pairs:
  * BEM_NEAR_ERROR fails the call, BEM_NEAR_SKIP lets them contribute zero,
  * BEM_NEAR_SINGULAR integrates them on the device with a singular scheme
- * (Section 3.2.3 leaves them to one; here: regularising transformations of
- * the pair to the unit 4-cube, 8-point Gauss-Legendre per dimension, FP64,
- * added to the regular part).  BEM_NEAR_SINGULAR is available for P0 and
+ * (Section 3.2.3 leaves them to one; here: coordinates around the pair's
+ * singular set with the radial integral in closed form and composite
+ * Gauss-Legendre rules for the rest, ~1e-12 relative, FP64, added to the
+ * regular part).  BEM_NEAR_SINGULAR is available for P0 and
  * the Laplace single, double and adjoint double layer (BEM_E_ARG otherwise). */
 typedef enum { BEM_NEAR_ERROR = 0, BEM_NEAR_SKIP = 1, BEM_NEAR_SINGULAR = 2 } bem_near;
 

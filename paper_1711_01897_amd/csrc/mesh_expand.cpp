@@ -277,6 +277,8 @@ void build_near_items(Request &r)
                 q.jt = cross_len(T, nullptr);
                 q.js = cross_len(S, q.ny);
                 if (shared == 3) {
+                    // the double layer of a flat triangle on itself vanishes ((x - y).n_y = 0)
+                    if (kernel_op(r.op) == BEM_LAPLACE_DLP) continue;
                     q.kind = 0;
                     for (int k = 0; k < 3; ++k) put3(q.v + 3 * k, vtx(T, k));
                 } else if (shared == 2) {

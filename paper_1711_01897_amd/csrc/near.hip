@@ -3,21 +3,34 @@
 //
 // The regular kernels integrate vertex-disjoint pairs only; Section 3.2.3
 // gives identical, edge-adjacent and vertex-adjacent pairs to a separate
-// singular scheme.  Here each such pair is mapped to the unit 4-cube by a
-// transformation whose Jacobian vanishes where x = y to the order of the
-// kernel's singularity, so the transformed integrand is smooth and a tensor
-// Gauss-Legendre rule (8 points per dimension) converges fast:
-//   identical:   the six-region decomposition of T x T over the reference
-//                triangle {0 <= x2 <= x1 <= 1}, Jacobian xi^3 eta1^2 eta2;
-//   common edge: Duffy coordinates from each triangle's third vertex
-//                (distance s1, s2 from the edge, position t, t' along it),
-//                then t - t' of either sign and the three pyramids of the
-//                (|t - t'|, s1, s2) cube, Jacobian rho^2 (1 - |t - t'|);
-//   common vertex: Duffy coordinates from the shared vertex, ordered by the
-//                larger radius, Jacobian s^3 z.
-// All three map polynomial integrands exactly (checked against product
-// rules on the two triangles) and meet the closed-form inner integrals of
-// the oracle's near-field fixture.
+// singular scheme.  Here each such pair is written in coordinates around its
+// singular set in which x - y is (radius) x (a vector of the remaining
+// coordinates).  Both kernels are homogeneous in x - y (degree -1 for 1/r,
+// -2 for (x-y).n_y / r^3, where only the test side's out-of-plane part
+// survives in the numerator), so the radial integral is a polynomial one and
+// is done in closed form; what remains is smooth and goes to a composite
+// Gauss-Legendre rule:
+//   identical:     the six-region decomposition of T x T over the reference
+//                  triangle {0 <= x2 <= x1 <= 1} (Jacobian xi^3 eta1^2 eta2);
+//                  x - y = xi eta1 eta2 c(eta3) with c one of three lines in
+//                  the plane of the edges, so the single layer is
+//                  (1/3) sum_c int_0^1 d(eta3) / |c(eta3)| and the double
+//                  layer vanishes (x - y lies in the plane);
+//   common edge:   affine coordinates x = P + u1 E + s1 a, y = P + u2 E + s2 b
+//                  (E the shared edge, a, b to the third vertices); the three
+//                  small coordinates (u1 - u2, s1, s2) in cone coordinates of
+//                  radius rho = max(s2, s1 + u1 - u2) (or its mirror), the
+//                  along-edge coordinate leaving a segment of length 1 - rho:
+//                  radial factor int rho (1 - rho) = 1/6 (single layer) or
+//                  int (1 - rho) = 1/2 (double layer), four faces of the
+//                  unit cone, each a square or a collapsed square;
+//   common vertex: Duffy coordinates from the shared vertex ordered by the
+//                  larger radius s (Jacobian s^3 z), x - y = s (a(u) - z b(v))
+//                  or s (z a(u) - b(v)): radial factor 1/3 or 1/2, a 3D
+//                  integral over (z, u, v).
+// Rules: 16 points per direction (two panels of the 8-point rule; 32 for the
+// identical case's 1D integrals): about 1e-12 relative on these pairs, where
+// the full 4D tensor rule with 8 points per direction left ~1e-8.
 #include <hip/hip_runtime.h>
 
 #include "bem_internal.hpp"
@@ -25,8 +38,14 @@
 namespace bem {
 namespace {
 
-constexpr int kGL = 8;   // Gauss-Legendre points per dimension (6 points leave ~2e-7 on these pairs)
+constexpr int kGL = 8;          // Gauss-Legendre points per panel
+constexpr int kPts = 2 * kGL;   // composite rule: two panels per direction
+constexpr int kIdPanels = 4;    // identical pairs: 1D integrals on four panels
+constexpr int kIdPts = kIdPanels * kGL;
 constexpr int kNearThreads = 256;
+static_assert(kPts * kPts == kNearThreads, "common-vertex pairs take one (u, v) node per thread");
+static_assert(4 * kPts * 4 == kNearThreads, "common-edge pairs take (face, p, q group) per thread");
+static_assert(3 * kIdPts <= kNearThreads, "identical pairs take one (line, node) per thread");
 
 // 8-point Gauss-Legendre rule on [0, 1] (nodes (1 + x)/2, weights w/2 of the
 // published rule on [-1, 1]).
@@ -47,87 +66,109 @@ __device__ __forceinline__ V3 ld(const double *p) { return {p[0], p[1], p[2]}; }
 __device__ __forceinline__ V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ __forceinline__ V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ V3 mul(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ V3 fma3(double s, V3 a, V3 b) { return {fma(s, a.x, b.x), fma(s, a.y, b.y), fma(s, a.z, b.z)}; }
+__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
-// Kernel without 1/4pi: single layer 1/r, double layer (x-y).n_y / r^3.
+// Kernel of the remaining integral at the scaled difference c: 1/|c| for
+// the single layer, num/|c|^3 for the double layer.
 template <int OP>
-__device__ __forceinline__ double green(V3 x, V3 y, V3 ny)
+__device__ __forceinline__ double kern(V3 c, double num)
 {
-    const V3 d = sub(x, y);
-    const double r2 = d.x * d.x + d.y * d.y + d.z * d.z;
-    const double ri = rsqrt(r2);
+    const double ri = rsqrt(dot(c, c));
     if constexpr (OP == 0) return ri;
-    return (d.x * ny.x + d.y * ny.y + d.z * ny.z) * ri * ri * ri;
+    return num * ri * ri * ri;
+}
+
+// This thread's share of the pair integral (without jt js / 4 pi and the
+// radial factor, which pair_scale gives); sx, sw hold the 16-point rule.
+template <int OP>
+__device__ double pair_part(const NearItem &it, const double *sx, const double *sw)
+{
+    const int t = threadIdx.x;
+    if (it.kind == 0) {
+        if constexpr (OP == 1) return 0.0;
+        if (t >= 3 * kIdPts) return 0.0;
+        const V3 V0 = ld(it.v), V1 = ld(it.v + 3), V2 = ld(it.v + 6);
+        const V3 E1 = sub(V1, V0), E2 = sub(V2, V1);
+        const int line = t / kIdPts, k = t - line * kIdPts;
+        const double e = (c_x[k % kGL] + (double)(k / kGL)) * (1.0 / kIdPanels);
+        const double w = c_w[k % kGL] * (1.0 / kIdPanels);
+        const V3 c = line == 0 ? fma3(e, E1, E2) : (line == 1 ? fma3(e, E2, E1) : fma3(-e, E1, mul(1.0 - e, E2)));
+        return w * kern<0>(c, 0.0);
+    }
+    if (it.kind == 1) {
+        const V3 P = ld(it.v), Q = ld(it.v + 3), A = ld(it.v + 6), B = ld(it.v + 9);
+        const V3 E = sub(Q, P), a = sub(A, P), b = sub(B, P);
+        const int face = t >> 6, ip = (t >> 2) & (kPts - 1), g = t & 3;
+        const double p = sx[ip], q1 = 1.0 - p;
+        // c = c0 + q c1 on the face; s1 = s1c + q s1q is the test side's
+        // distance from the edge (the double layer's numerator / (a.n_y))
+        V3 c0, c1;
+        double s1c, s1q, fw;
+        if (face == 0) {          // s2 = 1, s1 = (1 - d) q
+            c0 = sub(mul(p, E), b), c1 = mul(q1, a), s1c = 0.0, s1q = q1, fw = q1;
+        } else if (face == 1) {   // s1 + d = 1, s2 = q
+            c0 = fma3(p, E, mul(q1, a)), c1 = mul(-1.0, b), s1c = q1, s1q = 0.0, fw = 1.0;
+        } else if (face == 2) {   // s1 = 1, s2 = (1 - e) q, d = -e
+            c0 = fma3(-p, E, a), c1 = mul(-q1, b), s1c = 1.0, s1q = 0.0, fw = q1;
+        } else {                  // s2 + e = 1, s1 = q, d = -e
+            c0 = fma3(-p, E, mul(-q1, b)), c1 = a, s1c = 0.0, s1q = 1.0, fw = 1.0;
+        }
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kPts / 4; ++j) {
+            const double q = sx[g + 4 * j];
+            s += sw[g + 4 * j] * kern<OP>(fma3(q, c1, c0), fma(q, s1q, s1c));
+        }
+        return sw[ip] * fw * s;
+    }
+    const V3 P = ld(it.v), A = ld(it.v + 3), B = ld(it.v + 6), C = ld(it.v + 9), D = ld(it.v + 12);
+    const int iu = t / kPts, iv = t % kPts;
+    const V3 a = fma3(sx[iu], sub(B, A), sub(A, P));
+    const V3 b = fma3(sx[iv], sub(D, C), sub(C, P));
+    const double an = OP == 1 ? dot(a, ld(it.ny)) : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPts; ++k) {
+        const double z = sx[k], wz = sw[k] * z;
+        s += wz * (kern<OP>(fma3(-z, b, a), an) + (OP == 1 ? z : 1.0) * kern<OP>(fma3(z, a, mul(-1.0, b)), an));
+    }
+    return sw[iu] * sw[iv] * s;
+}
+
+// jt js / 4 pi times the closed-form radial integral of the pair's kind.
+template <int OP>
+__device__ double pair_scale(const NearItem &it)
+{
+    double radial;
+    if (it.kind == 0)
+        radial = OP == 0 ? 1.0 / 3.0 : 0.0;
+    else if (it.kind == 1)
+        radial = OP == 0 ? 1.0 / 6.0 : 0.5 * dot(sub(ld(it.v + 6), ld(it.v)), ld(it.ny));
+    else
+        radial = OP == 0 ? 1.0 / 3.0 : 0.5;
+    return radial * it.jt * it.js * kInv4PiD;
 }
 
 template <int OP>
 __device__ double pair_value(const NearItem &it)
 {
-    const int t = threadIdx.x;
-    const V3 ny = ld(it.ny);
-    double acc = 0.0;
-    constexpr int n4 = kGL * kGL * kGL * kGL;
-    if (it.kind == 0) {
-        const V3 V0 = ld(it.v), V1 = ld(it.v + 3), V2 = ld(it.v + 6);
-        const V3 E1 = sub(V1, V0), E2 = sub(V2, V1);
-        auto F = [&](double a, double b) { return add(V0, add(mul(a, E1), mul(b, E2))); };
-        for (int k = t; k < n4; k += kNearThreads) {
-            const int i0 = k % kGL, i1 = (k / kGL) % kGL, i2 = (k / (kGL * kGL)) % kGL, i3 = k / (kGL * kGL * kGL);
-            const double xi = c_x[i0], e1 = c_x[i1], e2 = c_x[i2], e3 = c_x[i3];
-            const double w = c_w[i0] * c_w[i1] * c_w[i2] * c_w[i3] * xi * xi * xi * e1 * e1 * e2;
-            double s = green<OP>(F(xi, xi * (1.0 - e1 + e1 * e2)), F(xi * (1.0 - e1 * e2 * e3), xi * (1.0 - e1)), ny);
-            s += green<OP>(F(xi * (1.0 - e1 * e2 * e3), xi * (1.0 - e1)), F(xi, xi * (1.0 - e1 + e1 * e2)), ny);
-            s += green<OP>(F(xi, xi * e1 * (1.0 - e2 + e2 * e3)), F(xi * (1.0 - e1 * e2), xi * e1 * (1.0 - e2)), ny);
-            s += green<OP>(F(xi * (1.0 - e1 * e2), xi * e1 * (1.0 - e2)), F(xi, xi * e1 * (1.0 - e2 + e2 * e3)), ny);
-            s += green<OP>(F(xi * (1.0 - e1 * e2 * e3), xi * e1 * (1.0 - e2 * e3)), F(xi, xi * e1 * (1.0 - e2)), ny);
-            s += green<OP>(F(xi, xi * e1 * (1.0 - e2)), F(xi * (1.0 - e1 * e2 * e3), xi * e1 * (1.0 - e2 * e3)), ny);
-            acc += w * s;
-        }
-    } else if (it.kind == 1) {
-        const V3 P = ld(it.v), Q = ld(it.v + 3), A = ld(it.v + 6), B = ld(it.v + 9);
-        const V3 E = sub(Q, P);
-        for (int k = t; k < 6 * n4; k += kNearThreads) {
-            const int reg = k / n4, kk = k - reg * n4;
-            const int i0 = kk % kGL, i1 = (kk / kGL) % kGL, i2 = (kk / (kGL * kGL)) % kGL, i3 = kk / (kGL * kGL * kGL);
-            const double rho = c_x[i0], w1 = c_x[i1], w2 = c_x[i2], tau = c_x[i3];
-            const int pyr = reg % 3;
-            const double d = pyr == 0 ? rho : rho * w1;
-            const double s1 = pyr == 1 ? rho : (pyr == 0 ? rho * w1 : rho * w2);
-            const double s2 = pyr == 2 ? rho : rho * w2;
-            double tx, ty;
-            if (reg < 3) {
-                ty = (1.0 - d) * tau;
-                tx = ty + d;
-            } else {
-                tx = (1.0 - d) * tau;
-                ty = tx + d;
-            }
-            const V3 ex = add(P, mul(tx, E)), ey = add(P, mul(ty, E));
-            const V3 x = sub(ex, mul(s1, sub(ex, A)));
-            const V3 y = sub(ey, mul(s2, sub(ey, B)));
-            const double w = c_w[i0] * c_w[i1] * c_w[i2] * c_w[i3] * rho * rho * (1.0 - d) * (1.0 - s1) * (1.0 - s2);
-            acc += w * green<OP>(x, y, ny);
-        }
-    } else {
-        const V3 P = ld(it.v), A = ld(it.v + 3), B = ld(it.v + 6), C = ld(it.v + 9), D = ld(it.v + 12);
-        for (int k = t; k < n4; k += kNearThreads) {
-            const int i0 = k % kGL, i1 = (k / kGL) % kGL, i2 = (k / (kGL * kGL)) % kGL, i3 = k / (kGL * kGL * kGL);
-            const double s = c_x[i0], z = c_x[i1], u = c_x[i2], v = c_x[i3];
-            const V3 a = add(mul(1.0 - u, sub(A, P)), mul(u, sub(B, P)));
-            const V3 b = add(mul(1.0 - v, sub(C, P)), mul(v, sub(D, P)));
-            const double w = c_w[i0] * c_w[i1] * c_w[i2] * c_w[i3] * s * s * s * z;
-            acc += w * (green<OP>(add(P, mul(s, a)), add(P, mul(s * z, b)), ny) +
-                        green<OP>(add(P, mul(s * z, a)), add(P, mul(s, b)), ny));
-        }
-    }
-    // fixed-order tree reduction over the workgroup
+    __shared__ double sx[kPts], sw[kPts];
     __shared__ double red[kNearThreads];
-    red[t] = acc;
+    const int t = threadIdx.x;
+    if (t < kPts) {
+        sx[t] = 0.5 * (c_x[t % kGL] + (double)(t / kGL));
+        sw[t] = 0.5 * c_w[t % kGL];
+    }
     __syncthreads();
+    red[t] = pair_part<OP>(it, sx, sw);
+    __syncthreads();
+    // fixed-order tree reduction over the workgroup
     for (int h = kNearThreads / 2; h > 0; h >>= 1) {
         if (t < h) red[t] += red[t + h];
         __syncthreads();
     }
-    return red[0] * it.jt * it.js * kInv4PiD;
+    return red[0] * pair_scale<OP>(it);
 }
 
 template <int OP, bool FP32>

@@ -410,12 +410,27 @@ public:
             L.off_tab = off;
             off = align256(off + sizeof(EntryBlock) * (size_t)L.count);
         }
-        // singular pairs of BEM_NEAR_SINGULAR requests (few requests carry any)
-        std::vector<std::pair<int, size_t>> near_at;
+        // singular pairs of BEM_NEAR_SINGULAR requests (few requests carry
+        // any), one contiguous run and one launch per (kernel, precision)
+        struct NearRun {
+            size_t off = 0;
+            int64_t count = 0;
+            std::vector<int> members;
+        };
+        NearRun near_runs[4];
+        auto near_group = [&](const Request &r) {
+            return (kernel_op(r.op) == BEM_LAPLACE_DLP ? 2 : 0) + (r.prec == BEM_FP32 ? 1 : 0);
+        };
         for (int i = 0; i < n; ++i)
             if (!take[i]->near_items.empty()) {
-                near_at.push_back({i, off});
-                off = align256(off + sizeof(NearItem) * take[i]->near_items.size());
+                NearRun &g = near_runs[near_group(*take[i])];
+                g.members.push_back(i);
+                g.count += (int64_t)take[i]->near_items.size();
+            }
+        for (NearRun &g : near_runs)
+            if (g.count) {
+                g.off = off;
+                off = align256(off + sizeof(NearItem) * (size_t)g.count);
             }
         const size_t off_in = off;
         for (int i = 0; i < n; ++i) off += take[i]->in_bytes;
@@ -465,12 +480,15 @@ public:
             in += stage_own_inputs(*take[i], hb, db, in, hreq[i]);
         }
         std::memset(hb + off_status, 0, sizeof(int32_t) * n);
-        for (const auto &na : near_at) {
-            const Request &r = *take[na.first];
-            NearItem *q = reinterpret_cast<NearItem *>(hb + na.second);
-            std::memcpy(q, r.near_items.data(), sizeof(NearItem) * r.near_items.size());
-            for (size_t j = 0; j < r.near_items.size(); ++j)
-                q[j].out = hd + out_off[na.first] + (size_t)r.near_index[j] * r.elem_bytes;
+        for (const NearRun &g : near_runs) {
+            NearItem *q = reinterpret_cast<NearItem *>(hb + g.off);
+            for (int i : g.members) {
+                const Request &r = *take[i];
+                std::memcpy(q, r.near_items.data(), sizeof(NearItem) * r.near_items.size());
+                for (size_t j = 0; j < r.near_items.size(); ++j)
+                    q[j].out = hd + out_off[i] + (size_t)r.near_index[j] * r.elem_bytes;
+                q += r.near_items.size();
+            }
         }
         b->off_clock = off_clock;
         for (int i = 0; i < n; ++i) {
@@ -506,11 +524,10 @@ public:
             blk0 += L.count;
         }
         // singular pairs after the entry kernels, on the same stream
-        for (const auto &na : near_at) {
-            const Request &r = *take[na.first];
-            note(launch_near(kernel_op(r.op) == BEM_LAPLACE_DLP ? 1 : 0, r.prec == BEM_FP32,
-                             reinterpret_cast<const NearItem *>(db + na.second), (int64_t)r.near_items.size(), stream));
-        }
+        for (int gi = 0; gi < 4; ++gi)
+            if (near_runs[gi].count)
+                note(launch_near(gi >> 1, gi & 1, reinterpret_cast<const NearItem *>(db + near_runs[gi].off),
+                                 near_runs[gi].count, stream));
         b->ev_done = get_event();
         note(hipEventRecord(b->ev_done, stream));
         b->t_hip = now_seconds() - b->t_hip;
