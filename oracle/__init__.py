@@ -72,6 +72,12 @@ def _lib():
     lib.orc_subdivided_rule.restype = ctypes.c_int
     lib.orc_nearfield_entry.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
     lib.orc_nearfield_entry.restype = ctypes.c_double
+    lib.orc_tri_moment_r.argtypes = [_dp, _dp, _dp, _dp]
+    lib.orc_tri_moment_r.restype = ctypes.c_double
+    lib.orc_nearfield_entries_c.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.c_int, ctypes.c_int, _dp]
+    lib.orc_nearfield_entries_c.restype = ctypes.c_int
     lib.orc_p0_matrix_with_nearfield.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
     lib.orc_p0_matrix_with_nearfield.restype = ctypes.c_int
     _LIB = lib
@@ -104,6 +110,11 @@ def subdivided_rule(level: int):
     xi, eta, w = np.zeros(n), np.zeros(n), np.zeros(n)
     _lib().orc_subdivided_rule(level, _d(xi), _d(eta), _d(w))
     return xi, eta, w
+
+
+def tri_moment_r(v0, v1, v2, x) -> float:
+    """int_T |x - y| dy over the flat triangle (v0, v1, v2), closed form."""
+    return _lib().orc_tri_moment_r(_d(_vec(v0)), _d(_vec(v1)), _d(_vec(v2)), _d(_vec(x)))
 
 
 def kernel(op: int, k: float, x, y, ny) -> complex:
@@ -180,6 +191,21 @@ class OracleMesh:
 
     def nearfield_entry(self, op: int, i: int, j: int, level: int = 3) -> float:
         return _lib().orc_nearfield_entry(self._h, op, i, j, level)
+
+    def nearfield_entries(self, op: int, k: float, rows, cols, level: int = 3, inner_level: int = 3) -> np.ndarray:
+        """Semi-analytic P0 entries (rows[t], cols[t]) of any of the four
+        operators, complex128 (imaginary part 0 for Laplace)."""
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        c = np.ascontiguousarray(np.asarray(cols, dtype=np.int64))
+        if r.shape != c.shape or r.ndim != 1:
+            raise ValueError("rows and cols: equal 1D sequences")
+        out = np.zeros(2 * r.size)
+        p64 = ctypes.POINTER(ctypes.c_int64)
+        st = _lib().orc_nearfield_entries_c(self._h, op, float(k), r.size, r.ctypes.data_as(p64),
+                                            c.ctypes.data_as(p64), level, inner_level, _d(out))
+        if st != 0:
+            raise ValueError("operator 0..3 and levels >= 0")
+        return out.view(np.complex128)
 
     def p0_matrix_with_nearfield(self, op: int, near_dist: float, level: int = 3) -> np.ndarray:
         out = np.zeros((self.nt, self.nt))

@@ -4,8 +4,9 @@
  * The weak-form path evaluates regular (vertex-disjoint) triangle pairs only;
  * the paper hands identical and adjacent pairs to a separate singular scheme
  * (Section 3.2.3).  The closed-form checks on the unit sphere (the sum of the
- * single-layer matrix, its spectrum, the double-layer identity) need every
- * pair, so this file supplies a semi-analytic P0 value for near pairs:
+ * single-layer matrix, its spectrum, the double-layer identity) and the
+ * parity of the device's singular pairs need every pair, so this file
+ * supplies a semi-analytic P0 value for near pairs:
  *
  *   inner integral over the flat trial triangle in closed form,
  *     single layer:  int_T 1/|x-y| dy          (potential of a uniform flat
@@ -15,8 +16,14 @@
  *   outer integral over the test triangle with the 6-point rule applied on
  *   4^L congruent sub-triangles.
  *
- * It is never compared against the product; it only serves the closed-form
- * pins of the oracle's regular entries.
+ * Helmholtz (Eq. slp/dlp with g = e^{ikr}/(4 pi r)): the kernel is expanded
+ * around r = 0 and the singular and non-smooth terms are integrated in closed
+ * form over the trial triangle,
+ *     e^{ikr}/r             = 1/r + ik - (k^2/2) r + T(r),
+ *     e^{ikr}(1 - ikr)/r^3  = 1/r^3 + (k^2/2)/r + i k^3/3 - (k^4/8) r + U(r)
+ * ((x-y).n_y is the height of x over the trial plane, constant in y), with
+ * int_T |x-y| dy in closed form as well; the remainders T = O(r^2) and
+ * U = O(r^2) go to the subdivided 6-point rule on the trial triangle.
  */
 #include <math.h>
 #include <stdint.h>
@@ -79,6 +86,88 @@ double orc_tri_potential(const double *v0, const double *v1, const double *v2, c
             sum -= ah * (atan(t0 * lp / (R0sq + ah * Rp)) - atan(t0 * lm / (R0sq + ah * Rm)));
     }
     return sum;
+}
+
+/* ln(R + l) for R = sqrt(R0sq + l^2), in the form without cancellation
+ * (R + l = R0sq / (R - l) for l < 0). */
+static double nf_log_rl(double l, double R, double R0sq)
+{
+    return l >= 0.0 ? log(R + l) : log(R0sq / (R - l));
+}
+
+/* int_T |x - y| dy for the flat triangle (v0, v1, v2).  With y' = y - rho
+ * (rho the projection of x on the plane, h the height of x over it) and
+ * R = |x - y|, the surface divergence div(y' R) = 3R - h^2/R, so
+ *   int_T R = (1/3) [ sum_e t_e int_e R dl + h^2 int_T 1/R ],
+ * t_e the distance of rho from edge e's line along the edge's outward
+ * in-plane normal, int_e R dl = (1/2) [l R + R0^2 ln(l + R)] between the
+ * edge's ends (l along the edge from the foot of the perpendicular,
+ * R0^2 = t_e^2 + h^2). */
+double orc_tri_moment_r(const double *v0, const double *v1, const double *v2, const double *x)
+{
+    const double *v[3] = {v0, v1, v2};
+    double e1[3], e2[3], N[3], n[3], xv0[3], rho[3];
+    sub3(v1, v0, e1);
+    sub3(v2, v0, e2);
+    cross3(e1, e2, N);
+    double nn = sqrt(dot3(N, N));
+    for (int d = 0; d < 3; ++d) n[d] = N[d] / nn;
+    sub3(x, v0, xv0);
+    double h = dot3(xv0, n);
+    for (int d = 0; d < 3; ++d) rho[d] = x[d] - h * n[d];
+    double sum = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double *pm = v[i], *pp = v[(i + 1) % 3];
+        double s[3], m[3], a[3], b[3];
+        sub3(pp, pm, s);
+        double L = sqrt(dot3(s, s));
+        for (int d = 0; d < 3; ++d) s[d] /= L;
+        cross3(s, n, m);
+        sub3(pp, rho, a);
+        sub3(pm, rho, b);
+        double lp = dot3(a, s), lm = dot3(b, s);
+        double t0 = dot3(b, m);
+        double R0sq = t0 * t0 + h * h;
+        double Rp = sqrt(R0sq + lp * lp), Rm = sqrt(R0sq + lm * lm);
+        double edge = 0.5 * (lp * Rp - lm * Rm);
+        if (R0sq > 0.0) edge += 0.5 * R0sq * (nf_log_rl(lp, Rp, R0sq) - nf_log_rl(lm, Rm, R0sq));
+        sum += t0 * edge;
+    }
+    return (sum + h * h * orc_tri_potential(v0, v1, v2, x)) / 3.0;
+}
+
+/* Remainders of the Helmholtz kernels after the terms integrated in closed
+ * form, at z = k r: T(r) r = sum_{n>=3} (iz)^n / n!, U(r) r^3 = sum_{n>=5}
+ * (1 - n) (iz)^n / n!.  Power series below z = 2, the closed expressions
+ * above (cos z - 1 + z^2/2 + i (sin z - z), and cos z + z sin z - 1 - z^2/2
+ * + z^4/8 + i (sin z - z cos z - z^3/3)). */
+static void nf_remainder(int dlp, double z, double *re, double *im)
+{
+    if (z < 2.0) {
+        double t = 1.0, sr = 0.0, si = 0.0;   /* t = z^n / n! */
+        for (int n = 1; n <= 40; ++n) {
+            t *= z / n;
+            if (n < (dlp ? 5 : 3)) continue;
+            double c = dlp ? (double)(1 - n) : 1.0;
+            switch (n & 3) {   /* i^n */
+            case 0: sr += c * t; break;
+            case 1: si += c * t; break;
+            case 2: sr -= c * t; break;
+            default: si -= c * t; break;
+            }
+        }
+        *re = sr;
+        *im = si;
+        return;
+    }
+    double c = cos(z), s = sin(z);
+    if (!dlp) {
+        *re = c - 1.0 + 0.5 * z * z;
+        *im = s - z;
+    } else {
+        *re = c + z * s - 1.0 - 0.5 * z * z + 0.125 * z * z * z * z;
+        *im = s - z * c - z * z * z / 3.0;
+    }
 }
 
 /* Signed solid angle of the triangle seen from x; positive when x lies on the
@@ -169,6 +258,92 @@ static double nf_entry(const orc_mesh *m, int op, int64_t i, int64_t j, int npts
         s += w[p] * inner;
     }
     return m->J[i] * s;
+}
+
+/* Semi-analytic P0 entry of the Helmholtz single (op 2) or double (op 3)
+ * layer for one pair: the outer rule (xi, eta, w) on the test triangle, the
+ * inner rule (ixi, ieta, iw) on the trial triangle for the smooth remainder. */
+static void nfc_entry(const orc_mesh *m, int op, double k, int64_t i, int64_t j, int npts, const double *xi,
+                      const double *eta, const double *w, int nin, const double *ixi, const double *ieta,
+                      const double *iw, double *re, double *im)
+{
+    const double *a = m->xyz + 3 * m->tri[3 * i], *b = m->xyz + 3 * m->tri[3 * i + 1],
+                 *c = m->xyz + 3 * m->tri[3 * i + 2];
+    const double *u0 = m->xyz + 3 * m->tri[3 * j], *u1 = m->xyz + 3 * m->tri[3 * j + 1],
+                 *u2 = m->xyz + 3 * m->tri[3 * j + 2];
+    const double area = 0.5 * m->J[j];
+    const int dlp = op == ORC_HELMHOLTZ_DLP;
+    double sr = 0.0, si = 0.0;
+    for (int p = 0; p < npts; ++p) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = a[d] + xi[p] * (b[d] - a[d]) + eta[p] * (c[d] - a[d]);
+        /* smooth remainder: T(r) (single layer) or U(r) (double layer, times
+         * the height below) over the trial triangle */
+        double rr = 0.0, ri = 0.0;
+        for (int q = 0; q < nin; ++q) {
+            double y[3], d3[3];
+            for (int d = 0; d < 3; ++d) y[d] = u0[d] + ixi[q] * (u1[d] - u0[d]) + ieta[q] * (u2[d] - u0[d]);
+            sub3(x, y, d3);
+            double r = sqrt(dot3(d3, d3));
+            if (r == 0.0) continue;   /* both remainders vanish as r -> 0 (T/r, U/r^3 = O(r)) */
+            double tr, ti;
+            nf_remainder(dlp, k * r, &tr, &ti);
+            double scale = dlp ? iw[q] / (r * r * r) : iw[q] / r;
+            rr += scale * tr;
+            ri += scale * ti;
+        }
+        rr *= m->J[j];
+        ri *= m->J[j];
+        double I0 = orc_tri_potential(u0, u1, u2, x), I1 = orc_tri_moment_r(u0, u1, u2, x);
+        double inr, ini;
+        if (!dlp) {
+            inr = I0 - 0.5 * k * k * I1 + rr;
+            ini = k * area + ri;
+        } else {
+            double xu[3];
+            sub3(x, u0, xu);
+            double hgt = dot3(xu, m->n + 3 * j);
+            if (fabs(hgt) <= 1e-12 * sqrt(m->J[j])) {
+                inr = ini = 0.0;   /* x in the trial plane: (x - y).n_y = 0 */
+            } else {
+                inr = -orc_tri_solid_angle(u0, u1, u2, x) + hgt * (0.5 * k * k * I0 - 0.125 * k * k * k * k * I1 + rr);
+                ini = hgt * (k * k * k * area / 3.0 + ri);
+            }
+        }
+        sr += w[p] * inr;
+        si += w[p] * ini;
+    }
+    *re = m->J[i] * sr / (4.0 * NF_PI);
+    *im = m->J[i] * si / (4.0 * NF_PI);
+}
+
+/* Near-field P0 entries of any of the four operators for n pairs (rows[t],
+ * cols[t]) (outer rule on 4^level sub-triangles; the Helmholtz remainder on
+ * 4^inner_level); out holds n complex values (imaginary parts 0 for Laplace). */
+int orc_nearfield_entries_c(const orc_mesh *m, int op, double k, int64_t n, const int64_t *rows,
+                            const int64_t *cols, int level, int inner_level, double *out)
+{
+    if (op < ORC_LAPLACE_SLP || op > ORC_HELMHOLTZ_DLP || level < 0 || inner_level < 0) return ORC_E_ARG;
+    int np = 6, ni = 6;
+    for (int l = 0; l < level; ++l) np *= 4;
+    for (int l = 0; l < inner_level; ++l) ni *= 4;
+    double *xi = (double *)malloc(sizeof(double) * 3 * (np + ni));
+    double *eta = xi + np, *w = xi + 2 * np, *ixi = xi + 3 * np, *ieta = ixi + ni, *iw = ixi + 2 * ni;
+    orc_subdivided_rule(level, xi, eta, w);
+    orc_subdivided_rule(inner_level, ixi, ieta, iw);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t t = 0; t < n; ++t) {
+        if (op <= ORC_LAPLACE_DLP) {
+            out[2 * t] = nf_entry(m, op, rows[t], cols[t], np, xi, eta, w);
+            out[2 * t + 1] = 0.0;
+        } else {
+            nfc_entry(m, op, k, rows[t], cols[t], np, xi, eta, w, ni, ixi, ieta, iw, out + 2 * t, out + 2 * t + 1);
+        }
+    }
+    free(xi);
+    return ORC_OK;
 }
 
 double orc_nearfield_entry(const orc_mesh *m, int op, int64_t i, int64_t j, int level)
