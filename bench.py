@@ -73,8 +73,11 @@ def parse():
                     help="instead of the H-matrix workload: the dense P1 matrix of the --ops operators on the "
                          "icosphere of this level, submitted to the request server in row chunks")
     ap.add_argument("--complete", type=int, default=0, metavar="LEVEL",
-                    help="instead of the ACA workload: complete P0 Laplace single-layer H-matrices (dense leaves "
-                         "with their singular pairs) on the icosphere of this level, FP64")
+                    help="instead of the ACA workload: complete P0 H-matrices (dense leaves with their singular "
+                         "pairs) on the icosphere of this level, FP64")
+    ap.add_argument("--complete-op", default="laplace_slp",
+                    choices=["laplace_slp", "laplace_dlp", "helmholtz_slp", "helmholtz_dlp"],
+                    help="operator of --complete (Helmholtz at 10 elements per wavelength)")
     ap.add_argument("--concurrent", type=int, default=0,
                     help="1: assemble the step's operators at the same time (one host thread each, the workers "
                          "split between them), as concurrent clients of the request server")
@@ -362,19 +365,22 @@ def dense_main(args):
 
 
 def complete_main(args):
-    """Complete P0 Laplace single-layer H-matrix (leaf 100, eta 1, ACA tol
-    1e-8, FP64): admissible leaves by ACA, dense leaves with their
-    vertex-sharing pairs integrated on the device; timed against the same
-    assembly with the singular pairs skipped."""
+    """Complete P0 H-matrix (leaf 100, eta 1, ACA tol 1e-8, FP64):
+    admissible leaves by ACA, dense leaves with their vertex-sharing pairs
+    integrated on the device; timed against the same assembly with the
+    singular pairs skipped."""
     import numpy as np
     from paper_1711_01897_amd import bem, inputs
     xyz, tri = inputs.icosphere(args.complete)
     mesh = bem.mesh_create(xyz, tri, 6)
     nt = tri.shape[0]
+    op = {"laplace_slp": bem.LAPLACE_SLP, "laplace_dlp": bem.LAPLACE_DLP, "helmholtz_slp": bem.HELMHOLTZ_SLP,
+          "helmholtz_dlp": bem.HELMHOLTZ_DLP}[args.complete_op]
+    k = inputs.wavenumber(xyz, tri, 10.0) if bem.is_complex(op) else 0.0
 
     def assemble(mode):
         t0 = time.perf_counter()
-        H = bem.hmat_assemble(mesh, bem.LAPLACE_SLP, bem.P0, 0.0, leaf_size=100, eta=1.0, aca_tol=1e-8,
+        H = bem.hmat_assemble(mesh, op, bem.P0, k, leaf_size=100, eta=1.0, aca_tol=1e-8,
                               max_rank=200, n_workers=args.workers, blocks_per_worker=args.blocks_per_worker,
                               prec=bem.FP64, dense_mode=mode)
         dt = time.perf_counter() - t0
@@ -395,22 +401,27 @@ def complete_main(args):
         vs = set(verts)
         for s in set(stars[verts[0]] + stars[verts[1]] + stars[verts[2]]):
             kinds[len(vs.intersection(tri[s].tolist()))] += 1
-    near_pairs = sum(kinds.values())
-    # algorithmic flops of the singular-pair kernel: 14 per kernel evaluation (difference vector 6, |c|^2 5,
-    # rsqrt 1, weighted sum 2); evaluations per pair 96 (identical), 1024 (common edge), 8192 (common vertex)
-    near_flops = 14 * (96 * kinds[3] + 1024 * kinds[2] + 8192 * kinds[1])
+    if op in (bem.LAPLACE_DLP, bem.HELMHOLTZ_DLP):
+        kinds[3] = 0   # the double layer of a flat triangle on itself vanishes: no items
+    # algorithmic flops of the Laplace single-layer singular-pair kernel: 14 per kernel evaluation (difference
+    # vector 6, |c|^2 5, rsqrt 1, weighted sum 2); evaluations per pair 96 (identical), 1024 (common edge),
+    # 8192 (common vertex)
+    near_flops = 14 * (96 * kinds[3] + 1024 * kinds[2] + 8192 * kinds[1]) if op == bem.LAPLACE_SLP else None
+    label = {bem.LAPLACE_SLP: "Laplace single layer", bem.LAPLACE_DLP: "Laplace double layer",
+             bem.HELMHOLTZ_SLP: "Helmholtz single layer", bem.HELMHOLTZ_DLP: "Helmholtz double layer"}[op]
     line = {
-        "metric": "complete H-matrix assembly seconds (P0 Laplace single layer, FP64)",
+        "metric": f"complete H-matrix assembly seconds (P0 {label}, FP64)",
         "value": t2, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"icosphere level {args.complete} ({nt} triangles), leaf 100, eta 1.0, ACA tol 1e-8, "
-                               "dense leaves complete (singular pairs on the device)",
+                               "dense leaves complete (singular pairs on the device)"
+                               + (f", k = {k:.4g} (10 elements per wavelength)" if k else ""),
                    "admissible_blocks": st["admissible_blocks"], "dense_blocks": st["dense_blocks"],
                    "dense_entries": st["dense_entries"], "aca_entries": st["aca_entries"]},
-        "seconds_without_singular_pairs": t1, "singular_pairs": near_pairs,
-        "singular_pairs_by_shared_vertices": {str(k): v for k, v in kinds.items()},
+        "seconds_without_singular_pairs": t1, "singular_pairs": sum(kinds.values()),
+        "singular_pairs_by_shared_vertices": {str(s): v for s, v in kinds.items()},
         "singular_kernel_flops_per_assembly": near_flops,
-        "singular_pairs_per_second_marginal": near_pairs / max(t2 - t1, 1e-9),
+        "singular_pairs_per_second_marginal": sum(kinds.values()) / max(t2 - t1, 1e-9),
     }
     print(json.dumps(line))
 
@@ -421,8 +432,8 @@ def main():
         traffic_from(args)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the workload has no multi-GPU path in this build "
-              "(blocks would be routed to independent per-GPU servers).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the request server drives one device (a multi-GPU run would route "
+              "blocks to independent per-GPU servers).", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

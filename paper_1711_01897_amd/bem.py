@@ -104,8 +104,8 @@ _LIB = None
 
 
 def lib():
-    """Load libbem.so once.  On a GPU machine torch is imported first so that the
-    library binds to the HIP runtime torch already loaded."""
+    """Load libbem.so once.  On a machine with a GPU torch is imported first
+    so that the library binds to the HIP runtime torch already loaded."""
     global _LIB
     if _LIB is not None:
         return _LIB

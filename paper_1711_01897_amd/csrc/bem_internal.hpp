@@ -121,15 +121,18 @@ struct NearItem {
     double v[15];
     double ny[3];
     double jt, js;
+    double k;   // wavenumber (Helmholtz)
     void *out;
     int32_t kind;
     int32_t pad;
 };
-static_assert(sizeof(NearItem) == 176, "near items are 176 bytes");
+static_assert(sizeof(NearItem) == 184, "near items are 184 bytes");
 
-// Adds each item's singular pair integral (FP64, regularising 4D
-// transformations, Gauss-Legendre per dimension) to its entry: the Laplace
-// single (op 0) or double layer (op 1), into float (fp32 = true) or double
+// Adds each item's singular pair integral (FP64; radial integral in closed
+// form for Laplace, by an 8-point rule for Helmholtz; composite
+// Gauss-Legendre for the rest) to its entry: the Laplace single (op 0) or
+// double layer (op 1), the Helmholtz single (op 2) or double layer (op 3),
+// into float / complex<float> (fp32 = true) or double / complex<double>
 // entries.  One workgroup per item.
 hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s);
 

@@ -262,7 +262,7 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     const ReqDev *dreq = (const ReqDev *)(ws + off_req);
     Variant v{kernel_op(r.op), r.space, r.prec, mesh->q};
     BEM_HIP_TRY(launch_entries(v, dreq, (const EntryBlock *)(ws + off_b), r.nblocks, s));
-    BEM_HIP_TRY(launch_near(kernel_op(r.op) == BEM_LAPLACE_DLP ? 1 : 0, r.prec == BEM_FP32,
+    BEM_HIP_TRY(launch_near(kernel_op(r.op), r.prec == BEM_FP32,
                             (const NearItem *)(ws + off_near), (int64_t)r.near_items.size(), s));
     BEM_HIP_TRY(hipFreeAsync(ws, s));
     return BEM_OK;

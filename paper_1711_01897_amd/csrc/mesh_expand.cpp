@@ -274,11 +274,12 @@ void build_near_items(Request &r)
                             ss[shared] = j;
                             ++shared;
                         }
+                q.k = is_complex_op(r.op) ? r.k : 0.0;
                 q.jt = cross_len(T, nullptr);
                 q.js = cross_len(S, q.ny);
                 if (shared == 3) {
                     // the double layer of a flat triangle on itself vanishes ((x - y).n_y = 0)
-                    if (kernel_op(r.op) == BEM_LAPLACE_DLP) continue;
+                    if (kernel_op(r.op) == BEM_LAPLACE_DLP || kernel_op(r.op) == BEM_HELMHOLTZ_DLP) continue;
                     q.kind = 0;
                     for (int k = 0; k < 3; ++k) put3(q.v + 3 * k, vtx(T, k));
                 } else if (shared == 2) {
@@ -315,9 +316,9 @@ int expand_request(Request &r)
     if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP && r.near != BEM_NEAR_SINGULAR)
         return fail(BEM_E_ARG, "unknown near-field policy");
     if (r.near == BEM_NEAR_SINGULAR &&
-        (r.space != BEM_P0 || (r.op != BEM_LAPLACE_SLP && r.op != BEM_LAPLACE_DLP && r.op != BEM_LAPLACE_ADLP)))
-        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for P0 and the Laplace single, double and adjoint "
-                               "double layer");
+        (r.space != BEM_P0 || r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS))
+        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for P0 and the single, double and adjoint double "
+                               "layer");
     if (is_complex_op(r.op)) {
         if (!(std::isfinite(r.k) && r.k > 0.0)) return fail(BEM_E_ARG, "Helmholtz needs a finite wavenumber k > 0");
     } else if (r.k != 0.0) {

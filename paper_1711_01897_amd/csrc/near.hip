@@ -31,6 +31,13 @@
 // Rules: 16 points per direction (two panels of the 8-point rule; 32 for the
 // identical case's 1D integrals): about 1e-12 relative on these pairs, where
 // the full 4D tensor rule with 8 points per direction left ~1e-8.
+// Helmholtz: g = e^{ikr}/(4 pi r) and its normal derivative
+// e^{ikr} (1 - ikr) (x-y).n_y / (4 pi r^3) are the Laplace kernels times a
+// factor smooth in the radius, so the same coordinates apply with the radial
+// integral int pi(rho) e^{i omega rho} (1 - i omega rho)^[double layer] d rho
+// (omega = k |c|, pi the Laplace case's radial polynomial, identical pairs
+// after folding xi eta1 eta2 into one radius with weight (1 - p)^2) taken
+// with the 8-point rule: exact for omega = 0, ~1e-10 at omega = 6.
 #include <hip/hip_runtime.h>
 
 #include "bem_internal.hpp"
@@ -68,6 +75,121 @@ __device__ __forceinline__ V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.
 __device__ __forceinline__ V3 mul(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
 __device__ __forceinline__ V3 fma3(double s, V3 a, V3 b) { return {fma(s, a.x, b.x), fma(s, a.y, b.y), fma(s, a.z, b.z)}; }
 __device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+struct Cx {
+    double re, im;
+};
+
+// Radial polynomials: identical (1 - p)^2, common edge rho (1 - rho) and
+// (1 - rho), common vertex s^2 and s (single / double layer).
+template <int POLY>
+__device__ __forceinline__ double radial_poly(double r)
+{
+    if constexpr (POLY == 0) return (1.0 - r) * (1.0 - r);
+    if constexpr (POLY == 1) return r * (1.0 - r);
+    if constexpr (POLY == 2) return 1.0 - r;
+    if constexpr (POLY == 3) return r * r;
+    return r;
+}
+
+// sum over the 8-point rule on [0, 1] of w pi(rho) e^{i om rho}, times
+// (1 - i om rho) for the double layer; the nodes come in pairs rho, 1 - rho,
+// whose phases are e^{i om rho} and e^{i om} conj(e^{i om rho}).
+template <int POLY, bool DL>
+__device__ Cx radial(double om)
+{
+    double s1, c1;
+    sincos(om, &s1, &c1);
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int m = 0; m < kGL / 2; ++m) {
+        const double r = c_x[m], w = c_w[m];
+        double s, c;
+        sincos(om * r, &s, &c);
+        const double er[2] = {c, c1 * c + s1 * s}, ei[2] = {s, s1 * c - c1 * s}, rr[2] = {r, 1.0 - r};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double p = w * radial_poly<POLY>(rr[h]);
+            double fr = p * er[h], fi = p * ei[h];
+            if constexpr (DL) {
+                const double t = om * rr[h];
+                const double gr = fr + t * fi, gi = fi - t * fr;
+                fr = gr, fi = gi;
+            }
+            ar += fr;
+            ai += fi;
+        }
+    }
+    return {ar, ai};
+}
+
+// Helmholtz share of this thread (op 2 single layer, op 3 double layer),
+// without jt js / 4 pi (and (a.n_y) for common-edge double layers).
+template <int OP>
+__device__ Cx pair_part_helmholtz(const NearItem &it, const double *sx, const double *sw)
+{
+    constexpr bool DL = OP == 3;
+    const int t = threadIdx.x;
+    const double k = it.k;
+    if (it.kind == 0) {
+        if (DL || t >= 3 * kIdPts) return {0.0, 0.0};
+        const V3 V0 = ld(it.v), V1 = ld(it.v + 3), V2 = ld(it.v + 6);
+        const V3 E1 = sub(V1, V0), E2 = sub(V2, V1);
+        const int line = t / kIdPts, kk = t - line * kIdPts;
+        const double e = (c_x[kk % kGL] + (double)(kk / kGL)) * (1.0 / kIdPanels);
+        const double w = c_w[kk % kGL] * (1.0 / kIdPanels);
+        const V3 c = line == 0 ? fma3(e, E1, E2) : (line == 1 ? fma3(e, E2, E1) : fma3(-e, E1, mul(1.0 - e, E2)));
+        const double ri = rsqrt(dot(c, c));
+        const Cx rad = radial<0, false>(k / ri);
+        return {w * ri * rad.re, w * ri * rad.im};
+    }
+    double ar = 0.0, ai = 0.0;
+    if (it.kind == 1) {
+        const V3 P = ld(it.v), Q = ld(it.v + 3), A = ld(it.v + 6), B = ld(it.v + 9);
+        const V3 E = sub(Q, P), a = sub(A, P), b = sub(B, P);
+        const int face = t >> 6, ip = (t >> 2) & (kPts - 1), g = t & 3;
+        const double p = sx[ip], q1 = 1.0 - p;
+        V3 c0, c1;
+        double s1c, s1q, fw;
+        if (face == 0) {
+            c0 = sub(mul(p, E), b), c1 = mul(q1, a), s1c = 0.0, s1q = q1, fw = q1;
+        } else if (face == 1) {
+            c0 = fma3(p, E, mul(q1, a)), c1 = mul(-1.0, b), s1c = q1, s1q = 0.0, fw = 1.0;
+        } else if (face == 2) {
+            c0 = fma3(-p, E, a), c1 = mul(-q1, b), s1c = 1.0, s1q = 0.0, fw = q1;
+        } else {
+            c0 = fma3(-p, E, mul(-q1, b)), c1 = a, s1c = 0.0, s1q = 1.0, fw = 1.0;
+        }
+        for (int j = 0; j < kPts / 4; ++j) {
+            const double q = sx[g + 4 * j];
+            const V3 c = fma3(q, c1, c0);
+            const double ri = rsqrt(dot(c, c));
+            const Cx rad = radial<DL ? 2 : 1, DL>(k / ri);
+            const double f = sw[g + 4 * j] * (DL ? fma(q, s1q, s1c) * ri * ri * ri : ri);
+            ar += f * rad.re;
+            ai += f * rad.im;
+        }
+        const double wf = sw[ip] * fw;
+        return {wf * ar, wf * ai};
+    }
+    const V3 P = ld(it.v), A = ld(it.v + 3), B = ld(it.v + 6), C = ld(it.v + 9), D = ld(it.v + 12);
+    const int iu = t / kPts, iv = t % kPts;
+    const V3 a = fma3(sx[iu], sub(B, A), sub(A, P));
+    const V3 b = fma3(sx[iv], sub(D, C), sub(C, P));
+    const double an = DL ? dot(a, ld(it.ny)) : 1.0;
+    for (int kz = 0; kz < kPts; ++kz) {
+        const double z = sx[kz], wz = sw[kz] * z;
+        const V3 d1 = fma3(-z, b, a), d2 = fma3(z, a, mul(-1.0, b));
+        const double r1 = rsqrt(dot(d1, d1)), r2 = rsqrt(dot(d2, d2));
+        const Cx g1 = radial<DL ? 4 : 3, DL>(k / r1), g2 = radial<DL ? 4 : 3, DL>(k / r2);
+        const double f1 = wz * an * (DL ? r1 * r1 * r1 : r1);
+        const double f2 = wz * an * (DL ? z * r2 * r2 * r2 : r2);
+        ar += f1 * g1.re + f2 * g2.re;
+        ai += f1 * g1.im + f2 * g2.im;
+    }
+    const double wuv = sw[iu] * sw[iv];
+    return {wuv * ar, wuv * ai};
+}
 
 // Kernel of the remaining integral at the scaled difference c: 1/|c| for
 // the single layer, num/|c|^3 for the double layer.
@@ -140,6 +262,10 @@ __device__ double pair_part(const NearItem &it, const double *sx, const double *
 template <int OP>
 __device__ double pair_scale(const NearItem &it)
 {
+    if constexpr (OP >= 2) {
+        const double an = (OP == 3 && it.kind == 1) ? dot(sub(ld(it.v + 6), ld(it.v)), ld(it.ny)) : 1.0;
+        return an * it.jt * it.js * kInv4PiD;
+    }
     double radial;
     if (it.kind == 0)
         radial = OP == 0 ? 1.0 / 3.0 : 0.0;
@@ -151,24 +277,35 @@ __device__ double pair_scale(const NearItem &it)
 }
 
 template <int OP>
-__device__ double pair_value(const NearItem &it)
+__device__ Cx pair_value(const NearItem &it)
 {
     __shared__ double sx[kPts], sw[kPts];
-    __shared__ double red[kNearThreads];
+    __shared__ double red[2][kNearThreads];
     const int t = threadIdx.x;
     if (t < kPts) {
         sx[t] = 0.5 * (c_x[t % kGL] + (double)(t / kGL));
         sw[t] = 0.5 * c_w[t % kGL];
     }
     __syncthreads();
-    red[t] = pair_part<OP>(it, sx, sw);
+    if constexpr (OP >= 2) {
+        const Cx v = pair_part_helmholtz<OP>(it, sx, sw);
+        red[0][t] = v.re;
+        red[1][t] = v.im;
+    } else {
+        red[0][t] = pair_part<OP>(it, sx, sw);
+        red[1][t] = 0.0;
+    }
     __syncthreads();
     // fixed-order tree reduction over the workgroup
     for (int h = kNearThreads / 2; h > 0; h >>= 1) {
-        if (t < h) red[t] += red[t + h];
+        if (t < h) {
+            red[0][t] += red[0][t + h];
+            red[1][t] += red[1][t + h];
+        }
         __syncthreads();
     }
-    return red[0] * pair_scale<OP>(it);
+    const double sc = pair_scale<OP>(it);
+    return {red[0][0] * sc, red[1][0] * sc};
 }
 
 template <int OP, bool FP32>
@@ -176,14 +313,17 @@ __global__ __launch_bounds__(kNearThreads) void k_near_p0(const NearItem *__rest
 {
     if ((int64_t)blockIdx.x >= n) return;
     const NearItem &it = items[blockIdx.x];
-    const double v = pair_value<OP>(it);
+    const Cx v = pair_value<OP>(it);
     if (threadIdx.x == 0) {
+        constexpr int kParts = OP >= 2 ? 2 : 1;   // complex entries: (re, im)
         if constexpr (FP32) {
             float *o = static_cast<float *>(it.out);
-            *o = (float)((double)*o + v);
+            o[0] = (float)((double)o[0] + v.re);
+            if constexpr (kParts == 2) o[1] = (float)((double)o[1] + v.im);
         } else {
             double *o = static_cast<double *>(it.out);
-            *o = *o + v;
+            o[0] = o[0] + v.re;
+            if constexpr (kParts == 2) o[1] = o[1] + v.im;
         }
     }
 }
@@ -193,19 +333,22 @@ __global__ __launch_bounds__(kNearThreads) void k_near_p0(const NearItem *__rest
 hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (n > INT32_MAX || (op != 0 && op != 1)) return hipErrorInvalidValue;
+    if (n > INT32_MAX || op < 0 || op > 3) return hipErrorInvalidValue;
     const dim3 grid((unsigned)n), block(kNearThreads);
-    if (op == 0) {
-        if (fp32)
-            hipLaunchKernelGGL((k_near_p0<0, true>), grid, block, 0, s, items, n);
-        else
-            hipLaunchKernelGGL((k_near_p0<0, false>), grid, block, 0, s, items, n);
-    } else {
-        if (fp32)
-            hipLaunchKernelGGL((k_near_p0<1, true>), grid, block, 0, s, items, n);
-        else
-            hipLaunchKernelGGL((k_near_p0<1, false>), grid, block, 0, s, items, n);
+#define BEM_NEAR_LAUNCH(O)                                                              \
+    do {                                                                                \
+        if (fp32)                                                                       \
+            hipLaunchKernelGGL((k_near_p0<O, true>), grid, block, 0, s, items, n);      \
+        else                                                                            \
+            hipLaunchKernelGGL((k_near_p0<O, false>), grid, block, 0, s, items, n);     \
+    } while (0)
+    switch (op) {
+    case 0: BEM_NEAR_LAUNCH(0); break;
+    case 1: BEM_NEAR_LAUNCH(1); break;
+    case 2: BEM_NEAR_LAUNCH(2); break;
+    default: BEM_NEAR_LAUNCH(3); break;
     }
+#undef BEM_NEAR_LAUNCH
     return hipGetLastError();
 }
 

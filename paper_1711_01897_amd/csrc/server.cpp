@@ -417,10 +417,8 @@ public:
             int64_t count = 0;
             std::vector<int> members;
         };
-        NearRun near_runs[4];
-        auto near_group = [&](const Request &r) {
-            return (kernel_op(r.op) == BEM_LAPLACE_DLP ? 2 : 0) + (r.prec == BEM_FP32 ? 1 : 0);
-        };
+        NearRun near_runs[8];
+        auto near_group = [&](const Request &r) { return 2 * kernel_op(r.op) + (r.prec == BEM_FP32 ? 1 : 0); };
         for (int i = 0; i < n; ++i)
             if (!take[i]->near_items.empty()) {
                 NearRun &g = near_runs[near_group(*take[i])];
@@ -524,7 +522,7 @@ public:
             blk0 += L.count;
         }
         // singular pairs after the entry kernels, on the same stream
-        for (int gi = 0; gi < 4; ++gi)
+        for (int gi = 0; gi < 8; ++gi)
             if (near_runs[gi].count)
                 note(launch_near(gi >> 1, gi & 1, reinterpret_cast<const NearItem *>(db + near_runs[gi].off),
                                  near_runs[gi].count, stream));

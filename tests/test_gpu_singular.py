@@ -89,7 +89,45 @@ def test_singular_policy_limits(ico2):
     with pytest.raises(bem.BemError):
         bem.eval_entries(mesh, bem.LAPLACE_SLP, bem.P1, 0.0, idx, idx, near=bem.NEAR_SINGULAR)
     with pytest.raises(bem.BemError):
-        bem.eval_entries(mesh, bem.HELMHOLTZ_SLP, bem.P0, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
+        bem.eval_entries(mesh, bem.HELMHOLTZ_SLP, bem.P1, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
+    with pytest.raises(bem.BemError):
+        bem.eval_entries(mesh, bem.LAPLACE_HYPS, bem.P1, 0.0, idx, idx, near=bem.NEAR_SINGULAR)
+
+
+@pytest.mark.parametrize("op", [bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP])
+@pytest.mark.parametrize("kh", [0.6, 3.0])
+@pytest.mark.parametrize("prec", [bem.FP64, bem.FP32])
+def test_singular_helmholtz_vs_oracle_nearfield(ico2, op, kh, prec):
+    """Helmholtz singular pairs at about 10 and 2 elements per wavelength
+    against the oracle's Helmholtz near-field (levels 4 and 5 extrapolated,
+    remainder on 4^3 sub-triangles): that fixture is accurate to ~1e-8 (single
+    layer) and ~1e-7 (double layer at kh = 3)."""
+    xyz, tri, mesh, om = ico2
+    k = kh / inputs.mean_edge_length(xyz, tri)
+    nt = tri.shape[0]
+    rows = np.random.Generator(np.random.PCG64(11)).choice(nt, 6, replace=False).astype(np.int32)
+    cols = np.arange(nt, dtype=np.int32)
+    got = bem.eval_entries(mesh, op, bem.P0, k, rows, cols, prec=prec, near=bem.NEAR_SINGULAR)
+    skip = bem.eval_entries(mesh, op, bem.P0, k, rows, cols, prec=prec, near=bem.NEAR_SKIP)
+    near = np.array([[adjacent(tri, a, b) for b in cols] for a in rows])
+    assert np.array_equal(got[~near], skip[~near])
+    ri, ci = np.nonzero(near)
+    ref = (4 * om.nearfield_entries(op, k, rows[ri], cols[ci], 5, 3) -
+           om.nearfield_entries(op, k, rows[ri], cols[ci], 4, 3)) / 3
+    err = np.abs(got[near].astype(np.complex128) - ref).max() / np.abs(ref).max()
+    bound = 1e-6 if prec == bem.FP32 else (1e-7 if op == bem.HELMHOLTZ_SLP else 3e-7)
+    print(f"op {op} kh {kh} prec {prec}: {near.sum()} singular entries, max rel err {err:.2e}")
+    assert err <= bound
+
+
+def test_singular_helmholtz_adjoint_is_transposed_double_layer(ico2):
+    xyz, tri, mesh, om = ico2
+    rng = np.random.Generator(np.random.PCG64(12))
+    rows = rng.choice(tri.shape[0], 12, replace=False).astype(np.int32)
+    cols = np.arange(tri.shape[0], dtype=np.int32)
+    a = bem.eval_entries(mesh, bem.HELMHOLTZ_ADLP, bem.P0, 3.0, rows, cols, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    d = bem.eval_entries(mesh, bem.HELMHOLTZ_DLP, bem.P0, 3.0, cols, rows, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    assert np.array_equal(a, d.T)
 
 
 @pytest.mark.parametrize("op", [bem.LAPLACE_SLP, bem.LAPLACE_DLP])
@@ -108,6 +146,32 @@ def test_complete_hmatrix_matvec(op):
     err = np.linalg.norm(H.matvec(x) - A @ x) / np.linalg.norm(A @ x)
     st = H.stats()
     print(st, err)
+    assert err <= 1e-6
+    H.destroy()
+    mesh.destroy()
+
+
+@pytest.mark.parametrize("op", [bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP])
+def test_complete_helmholtz_hmatrix_matvec(op):
+    """dense_mode 2 for the Helmholtz single and double layer (level-2
+    icosphere, kh = 1): reference matrix from the oracle's regular entries and
+    its near-field for the vertex-sharing pairs (levels 3 and 4 extrapolated,
+    remainder on 4^2 sub-triangles; ~1e-7)."""
+    xyz, tri = inputs.icosphere(2)
+    nt = tri.shape[0]
+    k = 1.0 / inputs.mean_edge_length(xyz, tri)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    H = bem.hmat_assemble(mesh, op, bem.P0, k, leaf_size=16, eta=1.0, aca_tol=1e-8, max_rank=100, n_workers=4,
+                          blocks_per_worker=8, prec=bem.FP64, dense_mode=2)
+    idx = np.arange(nt, dtype=np.int32)
+    A = om.entries(op, O.P0, k, idx, idx, near=O.NEAR_SKIP)
+    ri, ci = np.nonzero(np.array([[adjacent(tri, a, b) for b in range(nt)] for a in range(nt)]))
+    A[ri, ci] = (4 * om.nearfield_entries(op, k, ri, ci, 4, 2) - om.nearfield_entries(op, k, ri, ci, 3, 2)) / 3
+    rng = np.random.Generator(np.random.PCG64(4))
+    x = rng.normal(size=nt) + 1j * rng.normal(size=nt)
+    err = np.linalg.norm(H.matvec(x) - A @ x) / np.linalg.norm(A @ x)
+    print(H.stats(), err)
     assert err <= 1e-6
     H.destroy()
     mesh.destroy()
