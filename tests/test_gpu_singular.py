@@ -175,3 +175,42 @@ def test_complete_helmholtz_hmatrix_matvec(op):
     assert err <= 1e-6
     H.destroy()
     mesh.destroy()
+
+
+def test_served_singular_pairs_of_mixed_operators_and_precisions(ico2):
+    """BEM_NEAR_SINGULAR requests of all six operators in both precisions,
+    submitted together so that batches mix them (one singular launch per
+    kernel and precision per batch): each result equals the same request
+    evaluated alone, bitwise, and through the asynchronous device path."""
+    xyz, tri, mesh, om = ico2
+    rng = np.random.Generator(np.random.PCG64(13))
+    nt = tri.shape[0]
+    ops = [bem.LAPLACE_SLP, bem.LAPLACE_DLP, bem.LAPLACE_ADLP, bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP,
+           bem.HELMHOLTZ_ADLP]
+    reqs = []
+    for rep in range(3):
+        for op in ops:
+            for prec in (bem.FP32, bem.FP64):
+                rows = np.sort(rng.choice(nt, 24, replace=False)).astype(np.int32)
+                cols = np.arange(nt, dtype=np.int32) if rep != 1 else rows.copy()
+                reqs.append((op, prec, rows, cols, 0.0 if op in ops[:3] else 2.0 + rep))
+    order = rng.permutation(len(reqs))
+    reqs = [reqs[i] for i in order]
+    alone = [bem.eval_entries(mesh, op, bem.P0, k, r, c, prec=p, near=bem.NEAR_SINGULAR) for op, p, r, c, k in reqs]
+    bem.server_stats(reset=True)
+    tickets = [bem.submit(mesh, op, bem.P0, k, r, c, prec=p, near=bem.NEAR_SINGULAR) for op, p, r, c, k in reqs]
+    mixed = [t.wait() for t in tickets]
+    st = bem.server_stats()
+    del tickets
+    assert st["requests"] >= len(reqs)
+    for (op, p, r, c, k), a, b in zip(reqs, alone, mixed):
+        assert np.array_equal(a, b), (op, p)
+    import torch
+    dts = {np.float32: torch.float32, np.float64: torch.float64, np.complex64: torch.complex64,
+           np.complex128: torch.complex128}
+    for (op, p, r, c, k), a in list(zip(reqs, alone))[:12]:
+        out = torch.empty(a.shape, dtype=dts[a.dtype.type], device="cuda")
+        bem.eval_entries_async(mesh, op, bem.P0, k, r, c, out, prec=p, near=bem.NEAR_SINGULAR)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), a), (op, p)
+    print(f"{len(reqs)} requests in {st['batches']} batches")
