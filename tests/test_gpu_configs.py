@@ -90,3 +90,33 @@ def test_cylinder_1m_laplace_p1_leaf16():
     w = check_blocks(mesh, om, bem.LAPLACE_SLP, bem.P1, 0.0, blocks, bem.FP32, 1e-5)
     print(f"FP32 {w:.2e}")
     mesh.destroy()
+
+
+def test_spheroid_262k_helmholtz_singular_pairs_sampled():
+    """The singular scheme at the full spheroid size (262,186 triangles,
+    10 elements per wavelength): requests of seeded triangles against their
+    neighbourhoods with BEM_NEAR_SINGULAR; regular entries bitwise those of
+    BEM_NEAR_SKIP, vertex-sharing entries against the oracle's Helmholtz
+    near-field (levels 3 and 4 extrapolated, ~1e-7 here) within 1e-6 of the
+    largest (FP64) and 2e-6 (complex64)."""
+    xyz, tri = inputs.spheroid(10.0, 1.0, 262144)
+    k = inputs.wavenumber(xyz, tri, 10.0)
+    mesh = bem.mesh_create(xyz, tri, 4)
+    om = O.OracleMesh(xyz, tri, 4)
+    rng = np.random.Generator(np.random.PCG64(5))
+    rows = np.sort(rng.choice(tri.shape[0], 4, replace=False)).astype(np.int32)
+    # columns: every triangle around the rows' vertices plus a few distant ones
+    near_cols = np.flatnonzero(np.isin(tri, tri[rows].ravel()).any(1))
+    cols = np.unique(np.concatenate([near_cols, rng.choice(tri.shape[0], 16, replace=False)])).astype(np.int32)
+    near = np.array([[len(set(tri[a]) & set(tri[b])) > 0 for b in cols] for a in rows])
+    ri, ci = np.nonzero(near)
+    ref = (4 * om.nearfield_entries(bem.HELMHOLTZ_SLP, k, rows[ri], cols[ci], 4, 2) -
+           om.nearfield_entries(bem.HELMHOLTZ_SLP, k, rows[ri], cols[ci], 3, 2)) / 3
+    for prec, bound in ((bem.FP64, 1e-6), (bem.FP32, 2e-6)):
+        got = bem.eval_entries(mesh, bem.HELMHOLTZ_SLP, bem.P0, k, rows, cols, prec=prec, near=bem.NEAR_SINGULAR)
+        skip = bem.eval_entries(mesh, bem.HELMHOLTZ_SLP, bem.P0, k, rows, cols, prec=prec, near=bem.NEAR_SKIP)
+        assert np.array_equal(got[~near], skip[~near])
+        err = np.abs(got[near].astype(np.complex128) - ref).max() / np.abs(ref).max()
+        print(f"prec {prec}: {near.sum()} singular entries, k={k:.2f}, max rel err {err:.2e}")
+        assert err <= bound
+    mesh.destroy()
