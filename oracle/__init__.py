@@ -10,8 +10,12 @@ Contents
     adjoint double layer, and P1 entries of the hypersingular operator, over
     regular triangle pairs (Section 2, Eqs. slp, dlp, adlp, hypsHelmholtz;
     Section 3.2).
-  * near-field fixture (C, ``nearfield.c``): analytic inner integrals for the
-    closed-form sphere checks only.
+  * near-field fixtures (C, ``nearfield.c``) for vertex-sharing pairs, the
+    reference of the device's singular scheme and of the closed-form sphere
+    checks: P0 Laplace (closed-form inner potential and solid angle), P0
+    Helmholtz (the kernel expanded around r = 0, singular terms in closed
+    form, the remainder on a subdivided rule), P1 Laplace local matrices
+    (closed-form potentials of a linear density).
   * ``oracle.aca``: adaptive cross approximation, Algorithm "ACA" of
     Section 2.1 with the row pivot of Bebendorf's partial pivoting.
   * ``oracle.tree``: geometric cluster tree and block tree (Section 2.1).
@@ -78,6 +82,12 @@ def _lib():
                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                             ctypes.c_int, ctypes.c_int, _dp]
     lib.orc_nearfield_entries_c.restype = ctypes.c_int
+    lib.orc_tri_vector_moments.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
+    lib.orc_tri_vector_moments.restype = None
+    lib.orc_nearfield_p1_local.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64,
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.c_int, _dp]
+    lib.orc_nearfield_p1_local.restype = ctypes.c_int
     lib.orc_p0_matrix_with_nearfield.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
     lib.orc_p0_matrix_with_nearfield.restype = ctypes.c_int
     _LIB = lib
@@ -115,6 +125,14 @@ def subdivided_rule(level: int):
 def tri_moment_r(v0, v1, v2, x) -> float:
     """int_T |x - y| dy over the flat triangle (v0, v1, v2), closed form."""
     return _lib().orc_tri_moment_r(_d(_vec(v0)), _d(_vec(v1)), _d(_vec(v2)), _d(_vec(x)))
+
+
+def tri_vector_moments(v0, v1, v2, x):
+    """(int_T (y - rho)/R dy, int_T (y - rho)/R^3 dy), rho the projection of x
+    on the triangle's plane, closed form."""
+    V1, V3 = np.zeros(3), np.zeros(3)
+    _lib().orc_tri_vector_moments(_d(_vec(v0)), _d(_vec(v1)), _d(_vec(v2)), _d(_vec(x)), _d(V1), _d(V3))
+    return V1, V3
 
 
 def kernel(op: int, k: float, x, y, ny) -> complex:
@@ -206,6 +224,22 @@ class OracleMesh:
         if st != 0:
             raise ValueError("operator 0..3 and levels >= 0")
         return out.view(np.complex128)
+
+    def nearfield_p1_local(self, op: int, rows, cols, level: int = 3) -> np.ndarray:
+        """3 x 3 local P1 matrices (test vertex order x trial vertex order of
+        the mesh's triangles) of the pairs (rows[t], cols[t]), Laplace single
+        or double layer, semi-analytic; shape (n, 3, 3)."""
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        c = np.ascontiguousarray(np.asarray(cols, dtype=np.int64))
+        if r.shape != c.shape or r.ndim != 1:
+            raise ValueError("rows and cols: equal 1D sequences")
+        out = np.zeros(9 * r.size)
+        p64 = ctypes.POINTER(ctypes.c_int64)
+        st = _lib().orc_nearfield_p1_local(self._h, op, r.size, r.ctypes.data_as(p64), c.ctypes.data_as(p64),
+                                           level, _d(out))
+        if st != 0:
+            raise ValueError("Laplace single or double layer and level >= 0")
+        return out.reshape(r.size, 3, 3)
 
     def p0_matrix_with_nearfield(self, op: int, near_dist: float, level: int = 3) -> np.ndarray:
         out = np.zeros((self.nt, self.nt))

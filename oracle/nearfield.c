@@ -37,6 +37,9 @@
 
 static const double NF_PI = 3.14159265358979323846264338327950288;
 
+double orc_tri_solid_angle(const double *v0, const double *v1, const double *v2, const double *x);
+int orc_subdivided_rule(int level, double *xi, double *eta, double *w);
+
 static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 static void cross3(const double *a, const double *b, double *o)
@@ -134,6 +137,122 @@ double orc_tri_moment_r(const double *v0, const double *v1, const double *v2, co
         sum += t0 * edge;
     }
     return (sum + h * h * orc_tri_potential(v0, v1, v2, x)) / 3.0;
+}
+
+/* Vector moments of the flat triangle (v0, v1, v2) seen from x, with rho the
+ * projection of x on its plane: V1 = int_T (y - rho)/|x - y| dy and
+ * V3 = int_T (y - rho)/|x - y|^3 dy.  The in-plane gradient of R = |x - y|
+ * is (y - rho)/R and that of 1/R is -(y - rho)/R^3, so by the gradient
+ * theorem V1 = sum_e m_e int_e R dl and V3 = -sum_e m_e int_e dl/R, m_e the
+ * edge's outward in-plane normal; int_e dl/R = ln(l + R) between the ends.
+ * V3 needs x off the edges' lines (R0 > 0); it returns zeros where R0 = 0. */
+void orc_tri_vector_moments(const double *v0, const double *v1, const double *v2, const double *x, double *V1,
+                            double *V3)
+{
+    const double *v[3] = {v0, v1, v2};
+    double e1[3], e2[3], N[3], n[3], xv0[3], rho[3];
+    sub3(v1, v0, e1);
+    sub3(v2, v0, e2);
+    cross3(e1, e2, N);
+    double nn = sqrt(dot3(N, N));
+    for (int d = 0; d < 3; ++d) n[d] = N[d] / nn;
+    sub3(x, v0, xv0);
+    double h = dot3(xv0, n);
+    for (int d = 0; d < 3; ++d) rho[d] = x[d] - h * n[d];
+    for (int d = 0; d < 3; ++d) V1[d] = V3[d] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double *pm = v[i], *pp = v[(i + 1) % 3];
+        double s[3], m[3], a[3], b[3];
+        sub3(pp, pm, s);
+        double L = sqrt(dot3(s, s));
+        for (int d = 0; d < 3; ++d) s[d] /= L;
+        cross3(s, n, m);
+        sub3(pp, rho, a);
+        sub3(pm, rho, b);
+        double lp = dot3(a, s), lm = dot3(b, s);
+        double t0 = dot3(b, m);
+        double R0sq = t0 * t0 + h * h;
+        double Rp = sqrt(R0sq + lp * lp), Rm = sqrt(R0sq + lm * lm);
+        double lg = R0sq > 0.0 ? nf_log_rl(lp, Rp, R0sq) - nf_log_rl(lm, Rm, R0sq) : 0.0;
+        double edge_r = 0.5 * (lp * Rp - lm * Rm + R0sq * lg);
+        for (int d = 0; d < 3; ++d) {
+            V1[d] += m[d] * edge_r;
+            V3[d] -= m[d] * lg;
+        }
+    }
+}
+
+/* 3 x 3 local matrix of a triangle pair for the P1 hat functions restricted
+ * to the pair, Laplace single (op 0) or double (op 1) layer:
+ * M[a][b] = int_{T_i} phi_a(x) int_{T_j} psi_b(y) K(x, y) dy dx, a and b in
+ * the mesh's vertex order of each triangle.  psi_b is affine, so with rho
+ * the projection of x on the trial plane, psi_b(y) = psi_b(rho) +
+ * grad psi_b . (y - rho) and the inner integrals are
+ *   single layer: psi_b(rho) int 1/R + grad psi_b . V1,
+ *   double layer: -psi_b(rho) Omega + h grad psi_b . V3  (h the height of x);
+ * the outer integral takes the rule (xi, eta, w) on the test triangle. */
+static void nf_p1_local(const orc_mesh *m, int op, int64_t i, int64_t j, int npts, const double *xi,
+                        const double *eta, const double *w, double *M)
+{
+    const double *a = m->xyz + 3 * m->tri[3 * i], *b = m->xyz + 3 * m->tri[3 * i + 1],
+                 *c = m->xyz + 3 * m->tri[3 * i + 2];
+    const double *u[3] = {m->xyz + 3 * m->tri[3 * j], m->xyz + 3 * m->tri[3 * j + 1], m->xyz + 3 * m->tri[3 * j + 2]};
+    const double *nj = m->n + 3 * j;
+    const double Jj = m->J[j];
+    double grad[3][3];   /* in-plane gradients of the trial barycentrics */
+    for (int q = 0; q < 3; ++q) {
+        double ed[3];
+        sub3(u[(q + 2) % 3], u[(q + 1) % 3], ed);
+        cross3(nj, ed, grad[q]);
+        for (int d = 0; d < 3; ++d) grad[q][d] /= Jj;
+    }
+    for (int k = 0; k < 9; ++k) M[k] = 0.0;
+    for (int p = 0; p < npts; ++p) {
+        double x[3], xu[3], rho[3], V1[3], V3[3];
+        for (int d = 0; d < 3; ++d) x[d] = a[d] + xi[p] * (b[d] - a[d]) + eta[p] * (c[d] - a[d]);
+        const double phi[3] = {1.0 - xi[p] - eta[p], xi[p], eta[p]};
+        sub3(x, u[0], xu);
+        const double hgt = dot3(xu, nj);
+        for (int d = 0; d < 3; ++d) rho[d] = x[d] - hgt * nj[d];
+        double base;
+        if (op == ORC_LAPLACE_SLP) {
+            base = orc_tri_potential(u[0], u[1], u[2], x);
+        } else {
+            if (fabs(hgt) <= 1e-12 * sqrt(Jj)) continue;   /* (x - y).n_y = 0 */
+            base = -orc_tri_solid_angle(u[0], u[1], u[2], x);
+        }
+        orc_tri_vector_moments(u[0], u[1], u[2], x, V1, V3);
+        for (int q = 0; q < 3; ++q) {
+            double r1[3], r2[3], cr[3];
+            sub3(u[(q + 1) % 3], rho, r1);
+            sub3(u[(q + 2) % 3], rho, r2);
+            cross3(r1, r2, cr);
+            const double lam = dot3(cr, nj) / Jj;   /* psi_q(rho) */
+            const double inner = op == ORC_LAPLACE_SLP ? lam * base + dot3(grad[q], V1)
+                                                       : lam * base + hgt * dot3(grad[q], V3);
+            for (int t = 0; t < 3; ++t) M[3 * t + q] += w[p] * phi[t] * inner;
+        }
+    }
+    for (int k = 0; k < 9; ++k) M[k] *= m->J[i] / (4.0 * NF_PI);
+}
+
+/* P1 local matrices of n pairs (rows[t], cols[t]), Laplace single or double
+ * layer, outer rule on 4^level sub-triangles; out holds n row-major 3 x 3. */
+int orc_nearfield_p1_local(const orc_mesh *m, int op, int64_t n, const int64_t *rows, const int64_t *cols,
+                           int level, double *out)
+{
+    if ((op != ORC_LAPLACE_SLP && op != ORC_LAPLACE_DLP) || level < 0) return ORC_E_ARG;
+    int np = 6;
+    for (int l = 0; l < level; ++l) np *= 4;
+    double *xi = (double *)malloc(sizeof(double) * 3 * np);
+    double *eta = xi + np, *w = xi + 2 * np;
+    orc_subdivided_rule(level, xi, eta, w);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t t = 0; t < n; ++t) nf_p1_local(m, op, rows[t], cols[t], np, xi, eta, w, out + 9 * t);
+    free(xi);
+    return ORC_OK;
 }
 
 /* Remainders of the Helmholtz kernels after the terms integrated in closed
