@@ -97,8 +97,9 @@ typedef enum { BEM_FP64 = 0, BEM_FP32 = 1 } bem_prec;
  * singular set with the radial integral in closed form and composite
  * Gauss-Legendre rules for the rest, ~1e-12 relative, FP64, added to the
  * regular part; Helmholtz: the radial integral of e^{ikr} by an 8-point
- * rule).  BEM_NEAR_SINGULAR is available for P0 and the Laplace and
- * Helmholtz single, double and adjoint double layer (BEM_E_ARG otherwise). */
+ * rule; P1: each pair's 3 x 3 local matrix, then a fixed-order sum per
+ * entry).  BEM_NEAR_SINGULAR is available for the single, double and adjoint
+ * double layer: P0 Laplace and Helmholtz, P1 Laplace (BEM_E_ARG otherwise). */
 typedef enum { BEM_NEAR_ERROR = 0, BEM_NEAR_SKIP = 1, BEM_NEAR_SINGULAR = 2 } bem_near;
 
 typedef struct bem_mesh bem_mesh;
@@ -300,8 +301,9 @@ typedef struct {
     int32_t blocks_per_worker; /* ACA blocks each worker keeps in flight */
     bem_prec prec;          /* precision of the device entries */
     int32_t dense_mode;     /* 0: dense leaves left empty; 1: their regular part (BEM_NEAR_SKIP);
-                               2: complete, singular pairs included (BEM_NEAR_SINGULAR: P0 single,
-                               double and adjoint double layer only, else BEM_E_ARG) */
+                               2: complete, singular pairs included (BEM_NEAR_SINGULAR: single,
+                               double and adjoint double layer, P0 Laplace and Helmholtz, P1
+                               Laplace; else BEM_E_ARG) */
 } bem_hmat_params;
 
 /* Fill every admissible leaf of the block tree by ACA (all rows and columns

@@ -134,7 +134,36 @@ static_assert(sizeof(NearItem) == 184, "near items are 184 bytes");
 // double layer (op 1), the Helmholtz single (op 2) or double layer (op 3),
 // into float / complex<float> (fp32 = true) or double / complex<double>
 // entries.  One workgroup per item.
+// P1 singular region of a request: items | gather records | sources | local
+// matrices (offsets from the region's start, each 256-byte aligned).
+struct NearP1Layout {
+    size_t items, recs, src, local, bytes;
+};
+NearP1Layout near_p1_layout(const Request &r);
+// Writes the region's host image at host; dev is the region's device
+// address, out_dev the request's output on the device.
+void stage_near_p1(const Request &r, char *host, char *dev, char *out_dev);
+// Enqueues the P1 singular pairs of a staged region (local matrices, then the
+// gather into the entries).
+hipError_t launch_near_p1_region(const Request &r, char *dev, hipStream_t s);
+
 hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s);
+
+// P1: one entry's singular contributions, src[first .. first + count) into
+// the pairs' local matrices (9 doubles per pair, row-major test x trial).
+struct NearGather {
+    void *out;
+    int32_t first, count;
+};
+static_assert(sizeof(NearGather) == 16, "gather records are 16 bytes");
+
+// P1 Laplace single (op 0) or double layer (op 1): each item's 3 x 3 local
+// matrix (FP64) into the 9 doubles at item.out.  One workgroup per item.
+hipError_t launch_near_p1(int op, const NearItem *items, int64_t n, hipStream_t s);
+// Adds each record's fixed-order sum of local-matrix values to its float
+// (fp32) or double entry.  One thread per record.
+hipError_t launch_near_gather(bool fp32, const NearGather *recs, int64_t n, const int32_t *src, const double *local,
+                              hipStream_t s);
 
 // Copies bytes (a multiple of 16, both addresses 16-byte aligned) from src
 // (device-visible host staging) to dst (device) with a kernel on stream s.
@@ -259,7 +288,13 @@ struct Request {
     // on the batch: the request index of each block, the staged inputs, the
     // output and status addresses
     std::vector<NearItem> near_items;     // BEM_NEAR_SINGULAR: the request's vertex-sharing pairs
-    std::vector<int64_t> near_index;      // their entries' positions in the output
+    std::vector<int64_t> near_index;      // P0: their entries' positions in the output
+    struct NearRec {
+        int64_t entry;                    // position in the output
+        int32_t first, count;             // into near_src
+    };
+    std::vector<NearRec> near_recs;       // P1: entries with singular contributions, ascending
+    std::vector<int32_t> near_src;        // P1: pair * 9 + 3 a + b of each contribution, per entry ascending
     int key = 0;                          // launch group (operator, space, precision, rule)
     std::vector<EntryBlock> pre_blocks;   // `req` holds the fixed-side bit only
     ReqDev pre_dev{};

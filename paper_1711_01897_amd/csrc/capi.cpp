@@ -224,7 +224,8 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     const size_t off_b = off;
     off = al(off + sizeof(EntryBlock) * (size_t)r.nblocks);
     const size_t off_near = off;
-    off = al(off + sizeof(NearItem) * r.near_items.size());
+    const bool p1_near = r.space == BEM_P1 && !r.near_items.empty();
+    off = al(off + (p1_near ? near_p1_layout(r).bytes : sizeof(NearItem) * r.near_items.size()));
     const size_t off_in = off;
     off = al(off + r.in_bytes);
     const size_t off_status = off;
@@ -248,10 +249,14 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     d.out = dev_out;
     std::memcpy(host + off_req, &d, sizeof(ReqDev));
     write_blocks(r, 0, reinterpret_cast<EntryBlock *>(host + off_b));
-    NearItem *q = reinterpret_cast<NearItem *>(host + off_near);
-    for (size_t j = 0; j < r.near_items.size(); ++j) {
-        q[j] = r.near_items[j];
-        q[j].out = static_cast<char *>(dev_out) + (size_t)r.near_index[j] * r.elem_bytes;
+    if (p1_near) {
+        stage_near_p1(r, host + off_near, ws + off_near, static_cast<char *>(dev_out));
+    } else {
+        NearItem *q = reinterpret_cast<NearItem *>(host + off_near);
+        for (size_t j = 0; j < r.near_items.size(); ++j) {
+            q[j] = r.near_items[j];
+            q[j].out = static_cast<char *>(dev_out) + (size_t)r.near_index[j] * r.elem_bytes;
+        }
     }
     e = hipMemcpyAsync(ws, host, in_total, hipMemcpyHostToDevice, s);
     hipEvent_t ev = nullptr;
@@ -262,8 +267,11 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     const ReqDev *dreq = (const ReqDev *)(ws + off_req);
     Variant v{kernel_op(r.op), r.space, r.prec, mesh->q};
     BEM_HIP_TRY(launch_entries(v, dreq, (const EntryBlock *)(ws + off_b), r.nblocks, s));
-    BEM_HIP_TRY(launch_near(kernel_op(r.op), r.prec == BEM_FP32,
-                            (const NearItem *)(ws + off_near), (int64_t)r.near_items.size(), s));
+    if (p1_near)
+        BEM_HIP_TRY(launch_near_p1_region(r, ws + off_near, s));
+    else
+        BEM_HIP_TRY(launch_near(kernel_op(r.op), r.prec == BEM_FP32, (const NearItem *)(ws + off_near),
+                                (int64_t)r.near_items.size(), s));
     BEM_HIP_TRY(hipFreeAsync(ws, s));
     return BEM_OK;
 }

@@ -303,7 +303,169 @@ void build_near_items(Request &r)
     }
 }
 
+// The vertex-sharing pairs of a P1 request and, per output entry, the local
+// matrix values that sum into it.  A pair (a on the row side, b adjacent to
+// it) counts if a lies in the star of a requested row vertex and b touches a
+// requested column vertex; its local matrix M[i][j] (kernel test vertex i,
+// trial vertex j) goes to the entries of the row and column positions of
+// those vertices (exchanged for the adjoint double layer).
+void build_near_items_p1(Request &r)
+{
+    const bem_mesh &m = *r.mesh;
+    const bool adj = is_adjoint_op(r.op);
+    const bool dlp = kernel_op(r.op) == BEM_LAPLACE_DLP;
+    std::vector<std::pair<int32_t, int64_t>> rowpos((size_t)r.nrows), colpos((size_t)r.ncols);
+    for (int64_t i = 0; i < r.nrows; ++i) rowpos[i] = {r.rows[i], i};
+    for (int64_t i = 0; i < r.ncols; ++i) colpos[i] = {r.cols[i], i};
+    std::sort(rowpos.begin(), rowpos.end());
+    std::sort(colpos.begin(), colpos.end());
+    auto first_of = [](const std::vector<std::pair<int32_t, int64_t>> &v, int32_t x) {
+        return std::lower_bound(v.begin(), v.end(), std::make_pair(x, (int64_t)-1));
+    };
+    auto vtx = [&](int32_t t, int k) { return &m.xyz[3 * (size_t)m.tri[3 * (size_t)t + k]]; };
+    auto put3 = [](double *dst, const double *src) {
+        dst[0] = src[0];
+        dst[1] = src[1];
+        dst[2] = src[2];
+    };
+    auto cross_len = [&](int32_t t, double *n) {
+        const double *a = vtx(t, 0), *b = vtx(t, 1), *c = vtx(t, 2);
+        const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]}, e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double J = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        if (n)
+            for (int d = 0; d < 3; ++d) n[d] = N[d] / J;
+        return J;
+    };
+    auto star_of = [&](const int32_t *verts, int nv, std::vector<int32_t> &out) {
+        out.clear();
+        for (int k = 0; k < nv; ++k)
+            for (int64_t s = m.star_ptr[verts[k]]; s < m.star_ptr[verts[k] + 1]; ++s) out.push_back(m.star[s] >> 2);
+        std::sort(out.begin(), out.end());
+        out.erase(std::unique(out.begin(), out.end()), out.end());
+    };
+    std::vector<int32_t> rt, nb;
+    {
+        std::vector<int32_t> rv(r.rows.begin(), r.rows.end());
+        std::sort(rv.begin(), rv.end());
+        rv.erase(std::unique(rv.begin(), rv.end()), rv.end());
+        rt.clear();
+        for (int32_t v : rv)
+            for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) rt.push_back(m.star[s] >> 2);
+        std::sort(rt.begin(), rt.end());
+        rt.erase(std::unique(rt.begin(), rt.end()), rt.end());
+    }
+    std::vector<std::pair<int64_t, int32_t>> contrib;
+    for (int32_t a : rt) {
+        star_of(&m.tri[3 * (size_t)a], 3, nb);
+        for (int32_t b : nb) {
+            bool touches = false;
+            for (int k = 0; k < 3 && !touches; ++k) {
+                const int32_t v = m.tri[3 * (size_t)b + k];
+                auto it = first_of(colpos, v);
+                touches = it != colpos.end() && it->first == v;
+            }
+            if (!touches) continue;
+            const int32_t T = adj ? b : a, S = adj ? a : b;   // kernel test and trial triangles
+            const int32_t *tv = &m.tri[3 * (size_t)T], *sv = &m.tri[3 * (size_t)S];
+            int shared = 0, ts[3], ss[3];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j)
+                    if (tv[i] == sv[j]) {
+                        ts[shared] = i;
+                        ss[shared] = j;
+                        ++shared;
+                    }
+            if (shared == 3 && dlp) continue;   // (x - y).n_y = 0 on a flat triangle
+            NearItem q{};
+            int32_t tl[3], sl[3];   // global vertices in the kernel's local orders
+            q.jt = cross_len(T, nullptr);
+            q.js = cross_len(S, q.ny);
+            if (shared == 3) {
+                q.kind = 0;
+                for (int k = 0; k < 3; ++k) {
+                    put3(q.v + 3 * k, vtx(T, k));
+                    tl[k] = sl[k] = tv[k];
+                }
+            } else if (shared == 2) {
+                q.kind = 1;
+                const int t3 = 3 - ts[0] - ts[1], s3 = 3 - ss[0] - ss[1];
+                put3(q.v, vtx(T, ts[0]));
+                put3(q.v + 3, vtx(T, ts[1]));
+                put3(q.v + 6, vtx(T, t3));
+                put3(q.v + 9, vtx(S, s3));
+                tl[0] = tv[ts[0]], tl[1] = tv[ts[1]], tl[2] = tv[t3];
+                sl[0] = sv[ss[0]], sl[1] = sv[ss[1]], sl[2] = sv[s3];
+            } else {
+                q.kind = 2;
+                for (int k = 0; k < 3; ++k) {
+                    put3(q.v + 3 * k, vtx(T, (ts[0] + k) % 3));
+                    tl[k] = tv[(ts[0] + k) % 3];
+                }
+                put3(q.v + 9, vtx(S, (ss[0] + 1) % 3));
+                put3(q.v + 12, vtx(S, (ss[0] + 2) % 3));
+                for (int k = 0; k < 3; ++k) sl[k] = sv[(ss[0] + k) % 3];
+            }
+            const int32_t pi = (int32_t)r.near_items.size();
+            r.near_items.push_back(q);
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    const int32_t rv = adj ? sl[j] : tl[i], cv = adj ? tl[i] : sl[j];
+                    for (auto ri = first_of(rowpos, rv); ri != rowpos.end() && ri->first == rv; ++ri)
+                        for (auto ci = first_of(colpos, cv); ci != colpos.end() && ci->first == cv; ++ci)
+                            contrib.push_back({ri->second * r.ncols + ci->second, pi * 9 + 3 * i + j});
+                }
+        }
+    }
+    std::sort(contrib.begin(), contrib.end());
+    r.near_src.resize(contrib.size());
+    for (size_t k = 0; k < contrib.size(); ++k) {
+        r.near_src[k] = contrib[k].second;
+        if (k == 0 || contrib[k].first != contrib[k - 1].first)
+            r.near_recs.push_back({contrib[k].first, (int32_t)k, 0});
+        ++r.near_recs.back().count;
+    }
+}
+
 }  // namespace
+
+static size_t align256_sz(size_t x) { return (x + 255) & ~(size_t)255; }
+
+NearP1Layout near_p1_layout(const Request &r)
+{
+    NearP1Layout L;
+    L.items = 0;
+    L.recs = align256_sz(sizeof(NearItem) * r.near_items.size());
+    L.src = L.recs + align256_sz(sizeof(NearGather) * r.near_recs.size());
+    L.local = L.src + align256_sz(sizeof(int32_t) * r.near_src.size());
+    L.bytes = L.local + align256_sz(9 * sizeof(double) * r.near_items.size());
+    return L;
+}
+
+void stage_near_p1(const Request &r, char *host, char *dev, char *out_dev)
+{
+    const NearP1Layout L = near_p1_layout(r);
+    NearItem *q = reinterpret_cast<NearItem *>(host + L.items);
+    for (size_t j = 0; j < r.near_items.size(); ++j) {
+        q[j] = r.near_items[j];
+        q[j].out = dev + L.local + 9 * sizeof(double) * j;
+    }
+    NearGather *g = reinterpret_cast<NearGather *>(host + L.recs);
+    for (size_t j = 0; j < r.near_recs.size(); ++j)
+        g[j] = {out_dev + (size_t)r.near_recs[j].entry * r.elem_bytes, r.near_recs[j].first, r.near_recs[j].count};
+    if (!r.near_src.empty()) std::memcpy(host + L.src, r.near_src.data(), sizeof(int32_t) * r.near_src.size());
+}
+
+hipError_t launch_near_p1_region(const Request &r, char *dev, hipStream_t s)
+{
+    const NearP1Layout L = near_p1_layout(r);
+    hipError_t e = launch_near_p1(kernel_op(r.op), reinterpret_cast<const NearItem *>(dev + L.items),
+                                  (int64_t)r.near_items.size(), s);
+    if (e != hipSuccess) return e;
+    return launch_near_gather(r.prec == BEM_FP32, reinterpret_cast<const NearGather *>(dev + L.recs),
+                              (int64_t)r.near_recs.size(), reinterpret_cast<const int32_t *>(dev + L.src),
+                              reinterpret_cast<const double *>(dev + L.local), s);
+}
 
 int expand_request(Request &r)
 {
@@ -316,9 +478,9 @@ int expand_request(Request &r)
     if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP && r.near != BEM_NEAR_SINGULAR)
         return fail(BEM_E_ARG, "unknown near-field policy");
     if (r.near == BEM_NEAR_SINGULAR &&
-        (r.space != BEM_P0 || r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS))
-        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for P0 and the single, double and adjoint double "
-                               "layer");
+        (r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS || (r.space == BEM_P1 && is_complex_op(r.op))))
+        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for the single, double and adjoint double layer: "
+                               "P0 Laplace and Helmholtz, P1 Laplace");
     if (is_complex_op(r.op)) {
         if (!(std::isfinite(r.k) && r.k > 0.0)) return fail(BEM_E_ARG, "Helmholtz needs a finite wavenumber k > 0");
     } else if (r.k != 0.0) {
@@ -346,7 +508,14 @@ int expand_request(Request &r)
     r.ndistinct = r.own.ndistinct;
     r.near_items.clear();
     r.near_index.clear();
-    if (r.near == BEM_NEAR_SINGULAR) build_near_items(r);
+    r.near_recs.clear();
+    r.near_src.clear();
+    if (r.near == BEM_NEAR_SINGULAR) {
+        if (r.space == BEM_P0)
+            build_near_items(r);
+        else
+            build_near_items_p1(r);
+    }
     finalize_sizes(r);
     return BEM_OK;
 }
@@ -355,6 +524,8 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
 {
     r.near_items.clear();
     r.near_index.clear();
+    r.near_recs.clear();
+    r.near_src.clear();
     r.ext = ext;
     r.fixrows = rowfix;
     r.rowfix = is_adjoint_op(r.op) ? 1 - rowfix : rowfix;
@@ -381,7 +552,7 @@ size_t request_bytes(const Request &r)
 {
     // descriptor, inputs, status, outputs, block table, launch-timing records
     return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * (sizeof(EntryBlock) + 16) +
-           r.near_items.size() * sizeof(NearItem) + 512;
+           (r.space == BEM_P1 ? near_p1_layout(r).bytes : r.near_items.size() * sizeof(NearItem)) + 512;
 }
 
 void describe_request(const Request &r, ReqDev &d)

@@ -331,7 +331,215 @@ __global__ __launch_bounds__(kNearThreads) void k_near_p0(const NearItem *__rest
     }
 }
 
+// ---------------------------------------------------------------------------
+// P1 pairs: the 3 x 3 local matrix M[a][b] = int_T lambda_a int_S mu_b K of
+// the pair's barycentrics in the item's vertex order (test (V0, V1, V2),
+// (P, Q, A), (P, A, B); trial (V0, V1, V2), (P, Q, B), (P, C, D) for the
+// identical, common-edge and common-vertex kinds).  Same coordinates and face
+// rules as P0; the barycentrics are affine in the radius (bilinear in radius
+// and along-edge coordinate; for identical pairs polynomial in xi, eta1,
+// eta2), so those directions take Gauss rules exact for the degrees that
+// occur: 3 points for the radius (degree 4), 2 for the rest (degree <= 3).
+
+// 2- and 3-point Gauss-Legendre rules on [0, 1].
+constexpr double kG2x[2] = {0.5 - 0.28867513459481288225, 0.5 + 0.28867513459481288225};
+constexpr double kG3x[3] = {0.5 - 0.38729833462074168852, 0.5, 0.5 + 0.38729833462074168852};
+constexpr double kG3w[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+struct L3 {
+    double v[3];
+};
+
+// acc[3a + b] += w * l[a] * m[b]
+__device__ __forceinline__ void outer_acc(double *acc, double w, const L3 &l, const L3 &m)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double wa = w * l.v[a];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[3 * a + b] = fma(wa, m.v[b], acc[3 * a + b]);
+    }
+}
+
+// This thread's share of the 9 local integrals (without jt js / 4 pi and,
+// for the common-edge double layer, without (a.n_y)).
+template <int OP>
+__device__ void pair_part_p1(const NearItem &it, const double *sx, const double *sw, double *acc)
+{
+    const int t = threadIdx.x;
+    if (it.kind == 0) {
+        if (OP == 1 || t >= 3 * kIdPts) return;
+        const V3 V0 = ld(it.v), V1 = ld(it.v + 3), V2 = ld(it.v + 6);
+        const V3 E1 = sub(V1, V0), E2 = sub(V2, V1);
+        const int line = t / kIdPts, kk = t - line * kIdPts;
+        const double e3 = (c_x[kk % kGL] + (double)(kk / kGL)) * (1.0 / kIdPanels);
+        const double w3 = c_w[kk % kGL] * (1.0 / kIdPanels);
+        const V3 c = line == 0 ? fma3(e3, E1, E2) : (line == 1 ? fma3(e3, E2, E1) : fma3(-e3, E1, mul(1.0 - e3, E2)));
+        const double ic = rsqrt(dot(c, c));
+        // barycentrics of V0 + a E1 + b E2: (1 - a, a - b, b)
+        auto lam = [](double a, double b) { return L3{{1.0 - a, a - b, b}}; };
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    const double xi = kG3x[i], e1 = kG2x[j], e2 = kG2x[l];
+                    double xa, xb, ya, yb;
+                    if (line == 0) {
+                        xa = xi, xb = xi * (1.0 - e1 + e1 * e2), ya = xi * (1.0 - e1 * e2 * e3), yb = xi * (1.0 - e1);
+                    } else if (line == 1) {
+                        xa = xi, xb = xi * e1 * (1.0 - e2 + e2 * e3), ya = xi * (1.0 - e1 * e2), yb = xi * e1 * (1.0 - e2);
+                    } else {
+                        xa = xi * (1.0 - e1 * e2 * e3), xb = xi * e1 * (1.0 - e2 * e3), ya = xi, yb = xi * e1 * (1.0 - e2);
+                    }
+                    const L3 lx = lam(xa, xb), ly = lam(ya, yb);
+                    const double w = w3 * kG3w[i] * 0.25 * xi * xi * e1 * ic;
+                    // the region and its mirror (x and y exchanged)
+                    outer_acc(acc, w, lx, ly);
+                    outer_acc(acc, w, ly, lx);
+                }
+        return;
+    }
+    if (it.kind == 1) {
+        const V3 P = ld(it.v), Q = ld(it.v + 3), A = ld(it.v + 6), B = ld(it.v + 9);
+        const V3 E = sub(Q, P), a = sub(A, P), b = sub(B, P);
+        const int face = t >> 6, ip = (t >> 2) & (kPts - 1), g = t & 3;
+        const double p = sx[ip], q1 = 1.0 - p;
+        for (int j = 0; j < kPts / 4; ++j) {
+            const double q = sx[g + 4 * j];
+            double dh, s1h, s2h, fw;
+            if (face == 0)
+                dh = p, s1h = q1 * q, s2h = 1.0, fw = q1;
+            else if (face == 1)
+                dh = p, s1h = q1, s2h = q, fw = 1.0;
+            else if (face == 2)
+                dh = -p, s1h = 1.0, s2h = q1 * q, fw = q1;
+            else
+                dh = -p, s1h = q, s2h = q1, fw = 1.0;
+            const V3 c = fma3(dh, E, fma3(s1h, a, mul(-s2h, b)));
+            const double ic = rsqrt(dot(c, c));
+            const double K = sw[ip] * sw[g + 4 * j] * fw * (OP == 0 ? ic : s1h * ic * ic * ic);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    const double rho = kG3x[i], tau = kG2x[l];
+                    double u1, u2;
+                    if (face < 2) {
+                        u2 = (1.0 - rho) * tau;
+                        u1 = u2 + rho * dh;
+                    } else {
+                        u1 = (1.0 - rho) * tau;
+                        u2 = u1 - rho * dh;
+                    }
+                    const double s1 = rho * s1h, s2 = rho * s2h;
+                    const double rad = OP == 0 ? rho * (1.0 - rho) : 1.0 - rho;
+                    outer_acc(acc, K * kG3w[i] * 0.5 * rad, L3{{1.0 - u1 - s1, u1, s1}}, L3{{1.0 - u2 - s2, u2, s2}});
+                }
+        }
+        return;
+    }
+    const V3 P = ld(it.v), A = ld(it.v + 3), B = ld(it.v + 6), C = ld(it.v + 9), D = ld(it.v + 12);
+    const int iu = t / kPts, iv = t % kPts;
+    const double u = sx[iu], v = sx[iv];
+    const V3 av = fma3(u, sub(B, A), sub(A, P));
+    const V3 bv = fma3(v, sub(D, C), sub(C, P));
+    const double an = OP == 1 ? dot(av, ld(it.ny)) : 1.0;
+    const double wuv = sw[iu] * sw[iv];
+    for (int kz = 0; kz < kPts; ++kz) {
+        const double z = sx[kz];
+        const V3 c1 = fma3(-z, bv, av), c2 = fma3(z, av, mul(-1.0, bv));
+        const double i1 = rsqrt(dot(c1, c1)), i2 = rsqrt(dot(c2, c2));
+        const double f = wuv * sw[kz] * z * an;
+        const double k1 = f * (OP == 0 ? i1 : i1 * i1 * i1), k2 = f * (OP == 0 ? i2 : z * i2 * i2 * i2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double s = kG3x[i], sz = s * z;
+            const double rad = kG3w[i] * (OP == 0 ? s * s : s);
+            outer_acc(acc, rad * k1, L3{{1.0 - s, s * (1.0 - u), s * u}}, L3{{1.0 - sz, sz * (1.0 - v), sz * v}});
+            outer_acc(acc, rad * k2, L3{{1.0 - sz, sz * (1.0 - u), sz * u}}, L3{{1.0 - s, s * (1.0 - v), s * v}});
+        }
+    }
+}
+
+template <int OP>
+__global__ __launch_bounds__(kNearThreads) void k_near_p1(const NearItem *__restrict__ items, int64_t n)
+{
+    if ((int64_t)blockIdx.x >= n) return;
+    const NearItem &it = items[blockIdx.x];
+    __shared__ double sx[kPts], sw[kPts];
+    __shared__ double red[9][kNearThreads];
+    const int t = threadIdx.x;
+    if (t < kPts) {
+        sx[t] = 0.5 * (c_x[t % kGL] + (double)(t / kGL));
+        sw[t] = 0.5 * c_w[t % kGL];
+    }
+    __syncthreads();
+    double acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+    pair_part_p1<OP>(it, sx, sw, acc);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) red[k][t] = acc[k];
+    __syncthreads();
+    for (int h = kNearThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) red[k][t] += red[k][t + h];
+        __syncthreads();
+    }
+    if (t < 9) {
+        const double an = (OP == 1 && it.kind == 1) ? dot(sub(ld(it.v + 6), ld(it.v)), ld(it.ny)) : 1.0;
+        static_cast<double *>(it.out)[t] = red[t][0] * an * it.jt * it.js * kInv4PiD;
+    }
+}
+
+// Each record sums its sources (indices into the local matrices) in order
+// and adds the sum to its entry.
+template <bool FP32>
+__global__ void k_near_gather(const NearGather *__restrict__ recs, int64_t n, const int32_t *__restrict__ src,
+                              const double *__restrict__ local)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const NearGather g = recs[i];
+    double s = 0.0;
+    for (int32_t k = 0; k < g.count; ++k) s += local[src[g.first + k]];
+    if constexpr (FP32) {
+        float *o = static_cast<float *>(g.out);
+        *o = (float)((double)*o + s);
+    } else {
+        double *o = static_cast<double *>(g.out);
+        *o = *o + s;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_near_p1(int op, const NearItem *items, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (n > INT32_MAX || (op != 0 && op != 1)) return hipErrorInvalidValue;
+    if (op == 0)
+        hipLaunchKernelGGL((k_near_p1<0>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
+    else
+        hipLaunchKernelGGL((k_near_p1<1>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_near_gather(bool fp32, const NearGather *recs, int64_t n, const int32_t *src, const double *local,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    if (fp32)
+        hipLaunchKernelGGL((k_near_gather<true>), dim3((unsigned)blocks), dim3(256), 0, s, recs, n, src, local);
+    else
+        hipLaunchKernelGGL((k_near_gather<false>), dim3((unsigned)blocks), dim3(256), 0, s, recs, n, src, local);
+    return hipGetLastError();
+}
 
 hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s)
 {

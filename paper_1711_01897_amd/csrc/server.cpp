@@ -419,8 +419,12 @@ public:
         };
         NearRun near_runs[8];
         auto near_group = [&](const Request &r) { return 2 * kernel_op(r.op) + (r.prec == BEM_FP32 ? 1 : 0); };
+        std::vector<std::pair<int, size_t>> p1_at;   // P1 singular regions, one per request
         for (int i = 0; i < n; ++i)
-            if (!take[i]->near_items.empty()) {
+            if (!take[i]->near_items.empty() && take[i]->space == BEM_P1) {
+                p1_at.push_back({i, off});
+                off = align256(off + near_p1_layout(*take[i]).bytes);
+            } else if (!take[i]->near_items.empty()) {
                 NearRun &g = near_runs[near_group(*take[i])];
                 g.members.push_back(i);
                 g.count += (int64_t)take[i]->near_items.size();
@@ -488,6 +492,8 @@ public:
                 q += r.near_items.size();
             }
         }
+        for (const auto &pa : p1_at)
+            stage_near_p1(*take[pa.first], hb + pa.second, db + pa.second, hd + out_off[pa.first]);
         b->off_clock = off_clock;
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
@@ -526,6 +532,7 @@ public:
             if (near_runs[gi].count)
                 note(launch_near(gi >> 1, gi & 1, reinterpret_cast<const NearItem *>(db + near_runs[gi].off),
                                  near_runs[gi].count, stream));
+        for (const auto &pa : p1_at) note(launch_near_p1_region(*take[pa.first], db + pa.second, stream));
         b->ev_done = get_event();
         note(hipEventRecord(b->ev_done, stream));
         b->t_hip = now_seconds() - b->t_hip;

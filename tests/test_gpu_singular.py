@@ -87,8 +87,6 @@ def test_singular_policy_limits(ico2):
     xyz, tri, mesh, om = ico2
     idx = np.arange(5, dtype=np.int32)
     with pytest.raises(bem.BemError):
-        bem.eval_entries(mesh, bem.LAPLACE_SLP, bem.P1, 0.0, idx, idx, near=bem.NEAR_SINGULAR)
-    with pytest.raises(bem.BemError):
         bem.eval_entries(mesh, bem.HELMHOLTZ_SLP, bem.P1, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
     with pytest.raises(bem.BemError):
         bem.eval_entries(mesh, bem.LAPLACE_HYPS, bem.P1, 0.0, idx, idx, near=bem.NEAR_SINGULAR)
@@ -214,3 +212,99 @@ def test_served_singular_pairs_of_mixed_operators_and_precisions(ico2):
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), a), (op, p)
     print(f"{len(reqs)} requests in {st['batches']} batches")
+
+
+def p1_singular_reference(xyz, tri, om, op, rows, cols, level_hi=5):
+    """Singular part of P1 entries (rows x cols, vertex ids) from the oracle's
+    P1 local matrices of every vertex-sharing triangle pair (levels
+    level_hi - 1 and level_hi extrapolated)."""
+    rows, cols = np.asarray(rows), np.asarray(cols)
+    nt = tri.shape[0]
+    rset, cset = set(rows.tolist()), set(cols.tolist())
+    pairs = [(a, b) for a in range(nt) if rset & set(tri[a].tolist())
+             for b in range(nt) if cset & set(tri[b].tolist()) and set(tri[a].tolist()) & set(tri[b].tolist())]
+    pa, pb = np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs])
+    M = (4 * om.nearfield_p1_local(op, pa, pb, level_hi) - om.nearfield_p1_local(op, pa, pb, level_hi - 1)) / 3
+    rpos = {v: i for i, v in enumerate(rows.tolist())}
+    cpos = {v: i for i, v in enumerate(cols.tolist())}
+    S = np.zeros((rows.size, cols.size))
+    for t, (a, b) in enumerate(pairs):
+        for i in range(3):
+            for j in range(3):
+                I, J = int(tri[a][i]), int(tri[b][j])
+                if I in rpos and J in cpos:
+                    S[rpos[I], cpos[J]] += M[t, i, j]
+    return S
+
+
+@pytest.mark.parametrize("op", [bem.LAPLACE_SLP, bem.LAPLACE_DLP])
+@pytest.mark.parametrize("prec,bound", [(bem.FP64, 1e-6), (bem.FP32, 2e-6)])
+def test_p1_singular_pairs_vs_oracle(ico2, op, prec, bound):
+    """P1: the singular part (BEM_NEAR_SINGULAR minus BEM_NEAR_SKIP) against
+    the oracle's P1 local matrices (levels 4 and 5 extrapolated, ~2e-7);
+    entries without vertex-sharing pairs are bitwise those of
+    BEM_NEAR_SKIP."""
+    xyz, tri, mesh, om = ico2
+    nv = xyz.shape[0]
+    rows = np.random.Generator(np.random.PCG64(21)).choice(nv, 8, replace=False).astype(np.int32)
+    cols = np.arange(nv, dtype=np.int32)
+    got = bem.eval_entries(mesh, op, bem.P1, 0.0, rows, cols, prec=prec, near=bem.NEAR_SINGULAR)
+    skip = bem.eval_entries(mesh, op, bem.P1, 0.0, rows, cols, prec=prec, near=bem.NEAR_SKIP)
+    ref = p1_singular_reference(xyz, tri, om, op, rows, cols)
+    near = ref != 0.0
+    assert np.array_equal(got[~near], skip[~near])
+    err = np.abs((got.astype(np.float64) - skip) - ref)[near].max() / np.abs(ref).max()
+    print(f"P1 op {op} prec {prec}: {near.sum()} entries with singular pairs, max rel err {err:.2e}")
+    assert err <= bound
+
+
+def test_p1_singular_adjoint_is_transposed_double_layer(ico2):
+    xyz, tri, mesh, om = ico2
+    nv = xyz.shape[0]
+    rows = np.random.Generator(np.random.PCG64(22)).choice(nv, 10, replace=False).astype(np.int32)
+    cols = np.arange(nv, dtype=np.int32)
+    a = bem.eval_entries(mesh, bem.LAPLACE_ADLP, bem.P1, 0.0, rows, cols, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    d = bem.eval_entries(mesh, bem.LAPLACE_DLP, bem.P1, 0.0, cols, rows, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    assert np.abs(a - d.T).max() <= 1e-14 * np.abs(d).max()
+
+
+def test_p1_double_layer_row_sums_on_closed_surface():
+    """P1 double layer of the constant on the closed level-3 icosphere: row I
+    sums to -1/2 of the hat function's integral once the singular pairs are
+    in (the regular pairs' 6-point error aside)."""
+    xyz, tri = inputs.icosphere(3)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    nv = xyz.shape[0]
+    rows = np.arange(0, nv, 23, dtype=np.int32)
+    cols = np.arange(nv, dtype=np.int32)
+    area = 0.5 * np.linalg.norm(np.cross(xyz[tri[:, 1]] - xyz[tri[:, 0]], xyz[tri[:, 2]] - xyz[tri[:, 0]]), axis=1)
+    hat = np.bincount(tri.ravel(), np.repeat(area / 3.0, 3), minlength=nv)
+    K = bem.eval_entries(mesh, bem.LAPLACE_DLP, bem.P1, 0.0, rows, cols, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    Ks = bem.eval_entries(mesh, bem.LAPLACE_DLP, bem.P1, 0.0, rows, cols, prec=bem.FP64, near=bem.NEAR_SKIP)
+    rel = np.abs(K.sum(1) + 0.5 * hat[rows]) / (0.5 * hat[rows])
+    rel_skip = np.abs(Ks.sum(1) + 0.5 * hat[rows]) / (0.5 * hat[rows])
+    print(f"P1 row-sum error with singular pairs {rel.max():.2e}, without {rel_skip.min():.2e}")
+    assert rel.max() <= 1e-4
+    assert rel_skip.min() > 1e-2
+    mesh.destroy()
+
+
+@pytest.mark.parametrize("op", [bem.LAPLACE_SLP, bem.LAPLACE_DLP])
+def test_complete_p1_hmatrix_matvec(op):
+    """dense_mode 2 for P1 (level-2 icosphere, leaf 16): reference matrix
+    from the oracle's regular P1 entries plus its P1 local matrices of every
+    vertex-sharing pair (levels 3 and 4 extrapolated)."""
+    xyz, tri = inputs.icosphere(2)
+    nv = xyz.shape[0]
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    H = bem.hmat_assemble(mesh, op, bem.P1, 0.0, leaf_size=16, eta=1.0, aca_tol=1e-8, max_rank=100, n_workers=4,
+                          blocks_per_worker=8, prec=bem.FP64, dense_mode=2)
+    idx = np.arange(nv, dtype=np.int32)
+    A = om.entries(op, O.P1, 0.0, idx, idx, near=O.NEAR_SKIP) + p1_singular_reference(xyz, tri, om, op, idx, idx, 4)
+    x = np.random.Generator(np.random.PCG64(5)).normal(size=nv)
+    err = np.linalg.norm(H.matvec(x) - A @ x) / np.linalg.norm(A @ x)
+    print(H.stats(), err)
+    assert err <= 1e-6
+    H.destroy()
+    mesh.destroy()
