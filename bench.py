@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--complete-op", default="laplace_slp",
                     choices=["laplace_slp", "laplace_dlp", "helmholtz_slp", "helmholtz_dlp"],
                     help="operator of --complete (Helmholtz at 10 elements per wavelength)")
+    ap.add_argument("--complete-space", default="p0", choices=["p0", "p1"],
+                    help="space of --complete (P1: Laplace operators)")
     ap.add_argument("--concurrent", type=int, default=0,
                     help="1: assemble the step's operators at the same time (one host thread each, the workers "
                          "split between them), as concurrent clients of the request server")
@@ -377,10 +379,11 @@ def complete_main(args):
     op = {"laplace_slp": bem.LAPLACE_SLP, "laplace_dlp": bem.LAPLACE_DLP, "helmholtz_slp": bem.HELMHOLTZ_SLP,
           "helmholtz_dlp": bem.HELMHOLTZ_DLP}[args.complete_op]
     k = inputs.wavenumber(xyz, tri, 10.0) if bem.is_complex(op) else 0.0
+    space = bem.P1 if args.complete_space == "p1" else bem.P0
 
     def assemble(mode):
         t0 = time.perf_counter()
-        H = bem.hmat_assemble(mesh, op, bem.P0, k, leaf_size=100, eta=1.0, aca_tol=1e-8,
+        H = bem.hmat_assemble(mesh, op, space, k, leaf_size=100, eta=1.0, aca_tol=1e-8,
                               max_rank=200, n_workers=args.workers, blocks_per_worker=args.blocks_per_worker,
                               prec=bem.FP64, dense_mode=mode)
         dt = time.perf_counter() - t0
@@ -406,11 +409,12 @@ def complete_main(args):
     # algorithmic flops of the Laplace single-layer singular-pair kernel: 14 per kernel evaluation (difference
     # vector 6, |c|^2 5, rsqrt 1, weighted sum 2); evaluations per pair 96 (identical), 1024 (common edge),
     # 8192 (common vertex)
-    near_flops = 14 * (96 * kinds[3] + 1024 * kinds[2] + 8192 * kinds[1]) if op == bem.LAPLACE_SLP else None
+    near_flops = 14 * (96 * kinds[3] + 1024 * kinds[2] + 8192 * kinds[1]) \
+        if (op == bem.LAPLACE_SLP and space == bem.P0) else None
     label = {bem.LAPLACE_SLP: "Laplace single layer", bem.LAPLACE_DLP: "Laplace double layer",
              bem.HELMHOLTZ_SLP: "Helmholtz single layer", bem.HELMHOLTZ_DLP: "Helmholtz double layer"}[op]
     line = {
-        "metric": f"complete H-matrix assembly seconds (P0 {label}, FP64)",
+        "metric": f"complete H-matrix assembly seconds ({args.complete_space.upper()} {label}, FP64)",
         "value": t2, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"icosphere level {args.complete} ({nt} triangles), leaf 100, eta 1.0, ACA tol 1e-8, "

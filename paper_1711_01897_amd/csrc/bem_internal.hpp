@@ -139,13 +139,18 @@ static_assert(sizeof(NearItem) == 184, "near items are 184 bytes");
 struct NearP1Layout {
     size_t items, recs, src, local, bytes;
 };
+NearP1Layout near_p1_layout(int64_t items, int64_t recs, int64_t src);
 NearP1Layout near_p1_layout(const Request &r);
-// Writes the region's host image at host; dev is the region's device
-// address, out_dev the request's output on the device.
-void stage_near_p1(const Request &r, char *host, char *dev, char *out_dev);
+// Writes request r's part of a region's host image at host (dev: the region's
+// device address, out_dev: r's output on the device), its pairs, records and
+// sources after the first pb, rb and sb of the region (requests of one
+// kernel and precision share a region).
+void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *dev, char *out_dev, int64_t pb,
+                   int64_t rb, int64_t sb);
 // Enqueues the P1 singular pairs of a staged region (local matrices, then the
 // gather into the entries).
-hipError_t launch_near_p1_region(const Request &r, char *dev, hipStream_t s);
+hipError_t launch_near_p1_region(int op, bool fp32, const NearP1Layout &L, char *dev, int64_t items, int64_t recs,
+                                 hipStream_t s);
 
 hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s);
 

@@ -250,7 +250,7 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     std::memcpy(host + off_req, &d, sizeof(ReqDev));
     write_blocks(r, 0, reinterpret_cast<EntryBlock *>(host + off_b));
     if (p1_near) {
-        stage_near_p1(r, host + off_near, ws + off_near, static_cast<char *>(dev_out));
+        stage_near_p1(r, near_p1_layout(r), host + off_near, ws + off_near, static_cast<char *>(dev_out), 0, 0, 0);
     } else {
         NearItem *q = reinterpret_cast<NearItem *>(host + off_near);
         for (size_t j = 0; j < r.near_items.size(); ++j) {
@@ -268,7 +268,8 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     Variant v{kernel_op(r.op), r.space, r.prec, mesh->q};
     BEM_HIP_TRY(launch_entries(v, dreq, (const EntryBlock *)(ws + off_b), r.nblocks, s));
     if (p1_near)
-        BEM_HIP_TRY(launch_near_p1_region(r, ws + off_near, s));
+        BEM_HIP_TRY(launch_near_p1_region(kernel_op(r.op), r.prec == BEM_FP32, near_p1_layout(r), ws + off_near,
+                                          (int64_t)r.near_items.size(), (int64_t)r.near_recs.size(), s));
     else
         BEM_HIP_TRY(launch_near(kernel_op(r.op), r.prec == BEM_FP32, (const NearItem *)(ws + off_near),
                                 (int64_t)r.near_items.size(), s));

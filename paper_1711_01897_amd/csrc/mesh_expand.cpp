@@ -431,39 +431,45 @@ void build_near_items_p1(Request &r)
 
 static size_t align256_sz(size_t x) { return (x + 255) & ~(size_t)255; }
 
-NearP1Layout near_p1_layout(const Request &r)
+NearP1Layout near_p1_layout(int64_t items, int64_t recs, int64_t src)
 {
     NearP1Layout L;
     L.items = 0;
-    L.recs = align256_sz(sizeof(NearItem) * r.near_items.size());
-    L.src = L.recs + align256_sz(sizeof(NearGather) * r.near_recs.size());
-    L.local = L.src + align256_sz(sizeof(int32_t) * r.near_src.size());
-    L.bytes = L.local + align256_sz(9 * sizeof(double) * r.near_items.size());
+    L.recs = align256_sz(sizeof(NearItem) * (size_t)items);
+    L.src = L.recs + align256_sz(sizeof(NearGather) * (size_t)recs);
+    L.local = L.src + align256_sz(sizeof(int32_t) * (size_t)src);
+    L.bytes = L.local + align256_sz(9 * sizeof(double) * (size_t)items);
     return L;
 }
 
-void stage_near_p1(const Request &r, char *host, char *dev, char *out_dev)
+NearP1Layout near_p1_layout(const Request &r)
 {
-    const NearP1Layout L = near_p1_layout(r);
-    NearItem *q = reinterpret_cast<NearItem *>(host + L.items);
-    for (size_t j = 0; j < r.near_items.size(); ++j) {
-        q[j] = r.near_items[j];
-        q[j].out = dev + L.local + 9 * sizeof(double) * j;
-    }
-    NearGather *g = reinterpret_cast<NearGather *>(host + L.recs);
-    for (size_t j = 0; j < r.near_recs.size(); ++j)
-        g[j] = {out_dev + (size_t)r.near_recs[j].entry * r.elem_bytes, r.near_recs[j].first, r.near_recs[j].count};
-    if (!r.near_src.empty()) std::memcpy(host + L.src, r.near_src.data(), sizeof(int32_t) * r.near_src.size());
+    return near_p1_layout((int64_t)r.near_items.size(), (int64_t)r.near_recs.size(), (int64_t)r.near_src.size());
 }
 
-hipError_t launch_near_p1_region(const Request &r, char *dev, hipStream_t s)
+void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *dev, char *out_dev, int64_t pb,
+                   int64_t rb, int64_t sb)
 {
-    const NearP1Layout L = near_p1_layout(r);
-    hipError_t e = launch_near_p1(kernel_op(r.op), reinterpret_cast<const NearItem *>(dev + L.items),
-                                  (int64_t)r.near_items.size(), s);
+    NearItem *q = reinterpret_cast<NearItem *>(host + L.items) + pb;
+    for (size_t j = 0; j < r.near_items.size(); ++j) {
+        q[j] = r.near_items[j];
+        q[j].out = dev + L.local + 9 * sizeof(double) * ((size_t)pb + j);
+    }
+    NearGather *g = reinterpret_cast<NearGather *>(host + L.recs) + rb;
+    for (size_t j = 0; j < r.near_recs.size(); ++j)
+        g[j] = {out_dev + (size_t)r.near_recs[j].entry * r.elem_bytes, (int32_t)(sb + r.near_recs[j].first),
+                r.near_recs[j].count};
+    int32_t *src = reinterpret_cast<int32_t *>(host + L.src) + sb;
+    for (size_t j = 0; j < r.near_src.size(); ++j) src[j] = (int32_t)(9 * pb) + r.near_src[j];
+}
+
+hipError_t launch_near_p1_region(int op, bool fp32, const NearP1Layout &L, char *dev, int64_t items, int64_t recs,
+                                 hipStream_t s)
+{
+    hipError_t e = launch_near_p1(op, reinterpret_cast<const NearItem *>(dev + L.items), items, s);
     if (e != hipSuccess) return e;
-    return launch_near_gather(r.prec == BEM_FP32, reinterpret_cast<const NearGather *>(dev + L.recs),
-                              (int64_t)r.near_recs.size(), reinterpret_cast<const int32_t *>(dev + L.src),
+    return launch_near_gather(fp32, reinterpret_cast<const NearGather *>(dev + L.recs), recs,
+                              reinterpret_cast<const int32_t *>(dev + L.src),
                               reinterpret_cast<const double *>(dev + L.local), s);
 }
 

@@ -419,11 +419,22 @@ public:
         };
         NearRun near_runs[8];
         auto near_group = [&](const Request &r) { return 2 * kernel_op(r.op) + (r.prec == BEM_FP32 ? 1 : 0); };
-        std::vector<std::pair<int, size_t>> p1_at;   // P1 singular regions, one per request
+        // P1 singular pairs: one region (pairs | gather records | sources |
+        // local matrices) and one pair launch + one gather per (kernel, precision)
+        struct P1Run {
+            std::vector<int> members;
+            int64_t items = 0, recs = 0, src = 0;
+            size_t off = 0;
+            NearP1Layout L{};
+        };
+        P1Run p1_runs[4];
         for (int i = 0; i < n; ++i)
             if (!take[i]->near_items.empty() && take[i]->space == BEM_P1) {
-                p1_at.push_back({i, off});
-                off = align256(off + near_p1_layout(*take[i]).bytes);
+                P1Run &g = p1_runs[near_group(*take[i])];
+                g.members.push_back(i);
+                g.items += (int64_t)take[i]->near_items.size();
+                g.recs += (int64_t)take[i]->near_recs.size();
+                g.src += (int64_t)take[i]->near_src.size();
             } else if (!take[i]->near_items.empty()) {
                 NearRun &g = near_runs[near_group(*take[i])];
                 g.members.push_back(i);
@@ -433,6 +444,12 @@ public:
             if (g.count) {
                 g.off = off;
                 off = align256(off + sizeof(NearItem) * (size_t)g.count);
+            }
+        for (P1Run &g : p1_runs)
+            if (g.items) {
+                g.off = off;
+                g.L = near_p1_layout(g.items, g.recs, g.src);
+                off = align256(off + g.L.bytes);
             }
         const size_t off_in = off;
         for (int i = 0; i < n; ++i) off += take[i]->in_bytes;
@@ -492,8 +509,16 @@ public:
                 q += r.near_items.size();
             }
         }
-        for (const auto &pa : p1_at)
-            stage_near_p1(*take[pa.first], hb + pa.second, db + pa.second, hd + out_off[pa.first]);
+        for (const P1Run &g : p1_runs) {
+            int64_t pb = 0, rb = 0, sb = 0;
+            for (int i : g.members) {
+                const Request &r = *take[i];
+                stage_near_p1(r, g.L, hb + g.off, db + g.off, hd + out_off[i], pb, rb, sb);
+                pb += (int64_t)r.near_items.size();
+                rb += (int64_t)r.near_recs.size();
+                sb += (int64_t)r.near_src.size();
+            }
+        }
         b->off_clock = off_clock;
         for (int i = 0; i < n; ++i) {
             Request &r = *take[i];
@@ -532,7 +557,10 @@ public:
             if (near_runs[gi].count)
                 note(launch_near(gi >> 1, gi & 1, reinterpret_cast<const NearItem *>(db + near_runs[gi].off),
                                  near_runs[gi].count, stream));
-        for (const auto &pa : p1_at) note(launch_near_p1_region(*take[pa.first], db + pa.second, stream));
+        for (int gi = 0; gi < 4; ++gi)
+            if (p1_runs[gi].items)
+                note(launch_near_p1_region(gi >> 1, gi & 1, p1_runs[gi].L, db + p1_runs[gi].off, p1_runs[gi].items,
+                                           p1_runs[gi].recs, stream));
         b->ev_done = get_event();
         note(hipEventRecord(b->ev_done, stream));
         b->t_hip = now_seconds() - b->t_hip;
