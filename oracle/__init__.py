@@ -228,7 +228,8 @@ class OracleMesh:
     def nearfield_p1_local(self, op: int, rows, cols, level: int = 3) -> np.ndarray:
         """3 x 3 local P1 matrices (test vertex order x trial vertex order of
         the mesh's triangles) of the pairs (rows[t], cols[t]), Laplace single
-        or double layer, semi-analytic; shape (n, 3, 3)."""
+        or double layer or hypersingular operator, semi-analytic; shape
+        (n, 3, 3)."""
         r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
         c = np.ascontiguousarray(np.asarray(cols, dtype=np.int64))
         if r.shape != c.shape or r.ndim != 1:
@@ -238,7 +239,7 @@ class OracleMesh:
         st = _lib().orc_nearfield_p1_local(self._h, op, r.size, r.ctypes.data_as(p64), c.ctypes.data_as(p64),
                                            level, _d(out))
         if st != 0:
-            raise ValueError("Laplace single or double layer and level >= 0")
+            raise ValueError("Laplace single, double layer or hypersingular operator and level >= 0")
         return out.reshape(r.size, 3, 3)
 
     def p0_matrix_with_nearfield(self, op: int, near_dist: float, level: int = 3) -> np.ndarray:

@@ -271,7 +271,7 @@ static int orc_local_index(const orc_mesh *m, int64_t t, int64_t v)
  * reference derivatives (dl/dxi, dl/deta) = (-1,-1), (1,0), (0,1) for local
  * vertices 0, 1, 2, grad_Gamma l = sum_ij Ginv_ij (dl/dxi_i) t_j with
  * G_ij = t_i . t_j.                                                          */
-static void orc_curl(const orc_mesh *m, int64_t t, int loc, double *out)
+void orc_curl(const orc_mesh *m, int64_t t, int loc, double *out)
 {
     const double *v0 = m->xyz + 3 * m->tri[3 * t], *v1 = m->xyz + 3 * m->tri[3 * t + 1],
                  *v2 = m->xyz + 3 * m->tri[3 * t + 2];

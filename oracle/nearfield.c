@@ -39,6 +39,8 @@ static const double NF_PI = 3.14159265358979323846264338327950288;
 
 double orc_tri_solid_angle(const double *v0, const double *v1, const double *v2, const double *x);
 int orc_subdivided_rule(int level, double *xi, double *eta, double *w);
+static double nf_entry(const orc_mesh *m, int op, int64_t i, int64_t j, int npts, const double *xi,
+                       const double *eta, const double *w);
 
 static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -237,11 +239,14 @@ static void nf_p1_local(const orc_mesh *m, int op, int64_t i, int64_t j, int npt
 }
 
 /* P1 local matrices of n pairs (rows[t], cols[t]), Laplace single or double
- * layer, outer rule on 4^level sub-triangles; out holds n row-major 3 x 3. */
+ * layer, or the Laplace hypersingular operator (Eq. hypsHelmholtz at k = 0:
+ * curl_a . curl_b times the pair's P0 single-layer integral, the hat
+ * functions' surface curls being constant per triangle), outer rule on
+ * 4^level sub-triangles; out holds n row-major 3 x 3. */
 int orc_nearfield_p1_local(const orc_mesh *m, int op, int64_t n, const int64_t *rows, const int64_t *cols,
                            int level, double *out)
 {
-    if ((op != ORC_LAPLACE_SLP && op != ORC_LAPLACE_DLP) || level < 0) return ORC_E_ARG;
+    if ((op != ORC_LAPLACE_SLP && op != ORC_LAPLACE_DLP && op != ORC_LAPLACE_HYPS) || level < 0) return ORC_E_ARG;
     int np = 6;
     for (int l = 0; l < level; ++l) np *= 4;
     double *xi = (double *)malloc(sizeof(double) * 3 * np);
@@ -250,7 +255,20 @@ int orc_nearfield_p1_local(const orc_mesh *m, int op, int64_t n, const int64_t *
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
-    for (int64_t t = 0; t < n; ++t) nf_p1_local(m, op, rows[t], cols[t], np, xi, eta, w, out + 9 * t);
+    for (int64_t t = 0; t < n; ++t) {
+        if (op != ORC_LAPLACE_HYPS) {
+            nf_p1_local(m, op, rows[t], cols[t], np, xi, eta, w, out + 9 * t);
+            continue;
+        }
+        const double v = nf_entry(m, ORC_LAPLACE_SLP, rows[t], cols[t], np, xi, eta, w);
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double ca[3], cb[3];
+                orc_curl(m, rows[t], a, ca);
+                orc_curl(m, cols[t], b, cb);
+                out[9 * t + 3 * a + b] = (ca[0] * cb[0] + ca[1] * cb[1] + ca[2] * cb[2]) * v;
+            }
+    }
     free(xi);
     return ORC_OK;
 }

@@ -41,6 +41,8 @@ typedef struct {
 int orc_rule(int npts, double *xi, double *eta, double *w);
 void orc_kernel(int op, double k, const double *x, const double *y, const double *nrm, double *out);
 int orc_adjacent(const orc_mesh *m, int64_t a, int64_t b);
+/* surface curl n x grad of the hat function of local vertex loc on triangle t */
+void orc_curl(const orc_mesh *m, int64_t t, int loc, double *out);
 void orc_pair(const orc_mesh *m, int op, double k, int64_t tm, int64_t tn,
               int a, int b, double *re, double *im);
 

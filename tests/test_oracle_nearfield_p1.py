@@ -135,3 +135,40 @@ def test_single_layer_sphere_constant_density_p1():
         errs.append(np.abs(A.sum(1) - hat).max() / hat.max())
     assert errs[-1] < 2e-2
     assert 3.0 < errs[0] / errs[1] < 5.0   # O(h^2): the polyhedron against the sphere
+
+
+def full_hyps_matrix(level, with_singular=True):
+    xyz, tri = inputs.icosphere(level)
+    om = O.OracleMesh(xyz, tri, 6)
+    nv, nt = xyz.shape[0], tri.shape[0]
+    idx = np.arange(nv, dtype=np.int32)
+    A = om.entries(O.LAPLACE_HYPS, O.P1, 0.0, idx, idx, near=O.NEAR_SKIP)
+    if with_singular:
+        rows, cols = np.nonzero(np.array([[bool(set(tri[a]) & set(tri[b])) for b in range(nt)] for a in range(nt)]))
+        M = (4 * om.nearfield_p1_local(O.LAPLACE_HYPS, rows, cols, 3) -
+             om.nearfield_p1_local(O.LAPLACE_HYPS, rows, cols, 2)) / 3
+        for t, (i, j) in enumerate(zip(rows, cols)):
+            A[np.ix_(tri[i], tri[j])] += M[t]
+    area = 0.5 * np.linalg.norm(np.cross(xyz[tri[:, 1]] - xyz[tri[:, 0]], xyz[tri[:, 2]] - xyz[tri[:, 0]]), axis=1)
+    mass = np.zeros((nv, nv))
+    for t in range(nt):
+        mass[np.ix_(tri[t], tri[t])] += area[t] / 12.0 * (np.ones((3, 3)) + np.eye(3))
+    return xyz, A, mass
+
+
+def test_hypersingular_sphere_linear_functions():
+    """Laplace hypersingular operator on the unit sphere: the degree-1
+    spherical harmonics (the coordinates) are eigenfunctions with eigenvalue
+    n(n+1)/(2n+1) = 2/3, so the complete P1 Galerkin matrix D satisfies
+    D x ~ (2/3) M x (M the mass matrix) with an O(h^2) error from the
+    polyhedral surface; without the singular pairs it fails outright."""
+    errs = []
+    for level in (2, 3):
+        xyz, D, mass = full_hyps_matrix(level)
+        u = xyz[:, 0]
+        errs.append(np.linalg.norm(D @ u - (2.0 / 3.0) * mass @ u) / np.linalg.norm((2.0 / 3.0) * mass @ u))
+    assert errs[-1] < 5e-3
+    assert 3.0 < errs[0] / errs[1] < 5.0
+    xyz, Ds, mass = full_hyps_matrix(2, with_singular=False)
+    u = xyz[:, 0]
+    assert np.linalg.norm(Ds @ u - (2.0 / 3.0) * mass @ u) / np.linalg.norm((2.0 / 3.0) * mass @ u) > 0.1
