@@ -98,8 +98,11 @@ typedef enum { BEM_FP64 = 0, BEM_FP32 = 1 } bem_prec;
  * Gauss-Legendre rules for the rest, ~1e-12 relative, FP64, added to the
  * regular part; Helmholtz: the radial integral of e^{ikr} by an 8-point
  * rule; P1: each pair's 3 x 3 local matrix, then a fixed-order sum per
- * entry).  BEM_NEAR_SINGULAR is available for the single, double and adjoint
- * double layer: P0 Laplace and Helmholtz, P1 Laplace (BEM_E_ARG otherwise). */
+ * entry; the Laplace hypersingular operator: the hat functions' constant
+ * curls times each pair's P0 single-layer integral).  BEM_NEAR_SINGULAR is
+ * available for the single, double and adjoint double layer (P0 Laplace and
+ * Helmholtz, P1 Laplace) and the Laplace hypersingular operator (BEM_E_ARG
+ * otherwise). */
 typedef enum { BEM_NEAR_ERROR = 0, BEM_NEAR_SKIP = 1, BEM_NEAR_SINGULAR = 2 } bem_near;
 
 typedef struct bem_mesh bem_mesh;
@@ -303,7 +306,7 @@ typedef struct {
     int32_t dense_mode;     /* 0: dense leaves left empty; 1: their regular part (BEM_NEAR_SKIP);
                                2: complete, singular pairs included (BEM_NEAR_SINGULAR: single,
                                double and adjoint double layer, P0 Laplace and Helmholtz, P1
-                               Laplace; else BEM_E_ARG) */
+                               Laplace; Laplace hypersingular; else BEM_E_ARG) */
 } bem_hmat_params;
 
 /* Fill every admissible leaf of the block tree by ACA (all rows and columns

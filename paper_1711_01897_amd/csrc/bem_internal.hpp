@@ -134,12 +134,16 @@ static_assert(sizeof(NearItem) == 184, "near items are 184 bytes");
 // double layer (op 1), the Helmholtz single (op 2) or double layer (op 3),
 // into float / complex<float> (fp32 = true) or double / complex<double>
 // entries.  One workgroup per item.
-// P1 singular region of a request: items | gather records | sources | local
-// matrices (offsets from the region's start, each 256-byte aligned).
+// P1 singular region of a request: items | gather records | sources |
+// source weights (hypersingular operator) | local values (9 per pair, 1 for
+// the hypersingular operator); offsets from the region's start, each
+// 256-byte aligned.
 struct NearP1Layout {
-    size_t items, recs, src, local, bytes;
+    size_t items, recs, src, wt, local, bytes;
+    int per;   // local values per pair
+    bool weighted;
 };
-NearP1Layout near_p1_layout(int64_t items, int64_t recs, int64_t src);
+NearP1Layout near_p1_layout(bool hyps, int64_t items, int64_t recs, int64_t src);
 NearP1Layout near_p1_layout(const Request &r);
 // Writes request r's part of a region's host image at host (dev: the region's
 // device address, out_dev: r's output on the device), its pairs, records and
@@ -151,6 +155,8 @@ void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *de
 // gather into the entries).
 hipError_t launch_near_p1_region(int op, bool fp32, const NearP1Layout &L, char *dev, int64_t items, int64_t recs,
                                  hipStream_t s);
+// Index of the P1 singular run of a request (kernel and precision), 0..5.
+int near_p1_group(const Request &r);
 
 hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s);
 
@@ -163,12 +169,15 @@ struct NearGather {
 static_assert(sizeof(NearGather) == 16, "gather records are 16 bytes");
 
 // P1 Laplace single (op 0) or double layer (op 1): each item's 3 x 3 local
-// matrix (FP64) into the 9 doubles at item.out.  One workgroup per item.
+// matrix (FP64) into the 9 doubles at item.out; Laplace hypersingular
+// operator (op 6): the pair's P0 single-layer integral into the double at
+// item.out.  One workgroup per item.
 hipError_t launch_near_p1(int op, const NearItem *items, int64_t n, hipStream_t s);
-// Adds each record's fixed-order sum of local-matrix values to its float
-// (fp32) or double entry.  One thread per record.
-hipError_t launch_near_gather(bool fp32, const NearGather *recs, int64_t n, const int32_t *src, const double *local,
-                              hipStream_t s);
+// Adds each record's fixed-order sum of local values (times the source
+// weights when wt is not null) to its float (fp32) or double entry.  One
+// thread per record.
+hipError_t launch_near_gather(bool fp32, const NearGather *recs, int64_t n, const int32_t *src, const double *wt,
+                              const double *local, hipStream_t s);
 
 // Copies bytes (a multiple of 16, both addresses 16-byte aligned) from src
 // (device-visible host staging) to dst (device) with a kernel on stream s.
@@ -300,6 +309,8 @@ struct Request {
     };
     std::vector<NearRec> near_recs;       // P1: entries with singular contributions, ascending
     std::vector<int32_t> near_src;        // P1: pair * 9 + 3 a + b of each contribution, per entry ascending
+                                          // (hypersingular operator: the pair)
+    std::vector<double> near_wt;          // P1 hypersingular operator: curl_a . curl_b of each contribution
     int key = 0;                          // launch group (operator, space, precision, rule)
     std::vector<EntryBlock> pre_blocks;   // `req` holds the fixed-side bit only
     ReqDev pre_dev{};

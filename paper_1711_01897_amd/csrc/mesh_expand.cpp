@@ -314,6 +314,7 @@ void build_near_items_p1(Request &r)
     const bem_mesh &m = *r.mesh;
     const bool adj = is_adjoint_op(r.op);
     const bool dlp = kernel_op(r.op) == BEM_LAPLACE_DLP;
+    const bool hyps = r.op == BEM_LAPLACE_HYPS;
     std::vector<std::pair<int32_t, int64_t>> rowpos((size_t)r.nrows), colpos((size_t)r.ncols);
     for (int64_t i = 0; i < r.nrows; ++i) rowpos[i] = {r.rows[i], i};
     for (int64_t i = 0; i < r.ncols; ++i) colpos[i] = {r.cols[i], i};
@@ -355,7 +356,23 @@ void build_near_items_p1(Request &r)
         std::sort(rt.begin(), rt.end());
         rt.erase(std::unique(rt.begin(), rt.end()), rt.end());
     }
-    std::vector<std::pair<int64_t, int32_t>> contrib;
+    // surface curl of the hat function of global vertex v on triangle t: with
+    // the mesh's vertex order (v0, v1, v2) and J = |(v1 - v0) x (v2 - v0)|,
+    // curl lambda_i = (v_{i+1} - v_{i+2}) / J
+    auto curl = [&](int32_t t, int32_t v, double *c) {
+        int i = 0;
+        while (m.tri[3 * (size_t)t + i] != v) ++i;
+        const double *p1 = vtx(t, (i + 1) % 3), *p2 = vtx(t, (i + 2) % 3);
+        const double J = cross_len(t, nullptr);
+        for (int d = 0; d < 3; ++d) c[d] = (p1[d] - p2[d]) / J;
+    };
+    struct Contrib {
+        int64_t entry;
+        int32_t src;
+        double wt;
+        bool operator<(const Contrib &o) const { return entry != o.entry ? entry < o.entry : src < o.src; }
+    };
+    std::vector<Contrib> contrib;
     for (int32_t a : rt) {
         star_of(&m.tri[3 * (size_t)a], 3, nb);
         for (int32_t b : nb) {
@@ -411,18 +428,27 @@ void build_near_items_p1(Request &r)
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) {
                     const int32_t rv = adj ? sl[j] : tl[i], cv = adj ? tl[i] : sl[j];
+                    double w = 1.0;
+                    if (hyps) {
+                        double ct[3], cs[3];
+                        curl(T, tl[i], ct);
+                        curl(S, sl[j], cs);
+                        w = ct[0] * cs[0] + ct[1] * cs[1] + ct[2] * cs[2];
+                    }
                     for (auto ri = first_of(rowpos, rv); ri != rowpos.end() && ri->first == rv; ++ri)
                         for (auto ci = first_of(colpos, cv); ci != colpos.end() && ci->first == cv; ++ci)
-                            contrib.push_back({ri->second * r.ncols + ci->second, pi * 9 + 3 * i + j});
+                            contrib.push_back({ri->second * r.ncols + ci->second, hyps ? pi : pi * 9 + 3 * i + j, w});
                 }
         }
     }
     std::sort(contrib.begin(), contrib.end());
     r.near_src.resize(contrib.size());
+    if (hyps) r.near_wt.resize(contrib.size());
     for (size_t k = 0; k < contrib.size(); ++k) {
-        r.near_src[k] = contrib[k].second;
-        if (k == 0 || contrib[k].first != contrib[k - 1].first)
-            r.near_recs.push_back({contrib[k].first, (int32_t)k, 0});
+        r.near_src[k] = contrib[k].src;
+        if (hyps) r.near_wt[k] = contrib[k].wt;
+        if (k == 0 || contrib[k].entry != contrib[k - 1].entry)
+            r.near_recs.push_back({contrib[k].entry, (int32_t)k, 0});
         ++r.near_recs.back().count;
     }
 }
@@ -431,20 +457,29 @@ void build_near_items_p1(Request &r)
 
 static size_t align256_sz(size_t x) { return (x + 255) & ~(size_t)255; }
 
-NearP1Layout near_p1_layout(int64_t items, int64_t recs, int64_t src)
+NearP1Layout near_p1_layout(bool hyps, int64_t items, int64_t recs, int64_t src)
 {
     NearP1Layout L;
+    L.per = hyps ? 1 : 9;
+    L.weighted = hyps;
     L.items = 0;
     L.recs = align256_sz(sizeof(NearItem) * (size_t)items);
     L.src = L.recs + align256_sz(sizeof(NearGather) * (size_t)recs);
-    L.local = L.src + align256_sz(sizeof(int32_t) * (size_t)src);
-    L.bytes = L.local + align256_sz(9 * sizeof(double) * (size_t)items);
+    L.wt = L.src + align256_sz(sizeof(int32_t) * (size_t)src);
+    L.local = L.wt + (hyps ? align256_sz(sizeof(double) * (size_t)src) : 0);
+    L.bytes = L.local + align256_sz(L.per * sizeof(double) * (size_t)items);
     return L;
 }
 
 NearP1Layout near_p1_layout(const Request &r)
 {
-    return near_p1_layout((int64_t)r.near_items.size(), (int64_t)r.near_recs.size(), (int64_t)r.near_src.size());
+    return near_p1_layout(r.op == BEM_LAPLACE_HYPS, (int64_t)r.near_items.size(), (int64_t)r.near_recs.size(),
+                          (int64_t)r.near_src.size());
+}
+
+int near_p1_group(const Request &r)
+{
+    return 2 * (r.op == BEM_LAPLACE_HYPS ? 2 : kernel_op(r.op)) + (r.prec == BEM_FP32 ? 1 : 0);
 }
 
 void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *dev, char *out_dev, int64_t pb,
@@ -453,14 +488,16 @@ void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *de
     NearItem *q = reinterpret_cast<NearItem *>(host + L.items) + pb;
     for (size_t j = 0; j < r.near_items.size(); ++j) {
         q[j] = r.near_items[j];
-        q[j].out = dev + L.local + 9 * sizeof(double) * ((size_t)pb + j);
+        q[j].out = dev + L.local + L.per * sizeof(double) * ((size_t)pb + j);
     }
     NearGather *g = reinterpret_cast<NearGather *>(host + L.recs) + rb;
     for (size_t j = 0; j < r.near_recs.size(); ++j)
         g[j] = {out_dev + (size_t)r.near_recs[j].entry * r.elem_bytes, (int32_t)(sb + r.near_recs[j].first),
                 r.near_recs[j].count};
     int32_t *src = reinterpret_cast<int32_t *>(host + L.src) + sb;
-    for (size_t j = 0; j < r.near_src.size(); ++j) src[j] = (int32_t)(9 * pb) + r.near_src[j];
+    for (size_t j = 0; j < r.near_src.size(); ++j) src[j] = (int32_t)(L.per * pb) + r.near_src[j];
+    if (L.weighted && !r.near_wt.empty())
+        std::memcpy(reinterpret_cast<double *>(host + L.wt) + sb, r.near_wt.data(), sizeof(double) * r.near_wt.size());
 }
 
 hipError_t launch_near_p1_region(int op, bool fp32, const NearP1Layout &L, char *dev, int64_t items, int64_t recs,
@@ -470,6 +507,7 @@ hipError_t launch_near_p1_region(int op, bool fp32, const NearP1Layout &L, char 
     if (e != hipSuccess) return e;
     return launch_near_gather(fp32, reinterpret_cast<const NearGather *>(dev + L.recs), recs,
                               reinterpret_cast<const int32_t *>(dev + L.src),
+                              L.weighted ? reinterpret_cast<const double *>(dev + L.wt) : nullptr,
                               reinterpret_cast<const double *>(dev + L.local), s);
 }
 
@@ -483,10 +521,9 @@ int expand_request(Request &r)
     if (r.prec != BEM_FP32 && r.prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
     if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP && r.near != BEM_NEAR_SINGULAR)
         return fail(BEM_E_ARG, "unknown near-field policy");
-    if (r.near == BEM_NEAR_SINGULAR &&
-        (r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS || (r.space == BEM_P1 && is_complex_op(r.op))))
-        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for the single, double and adjoint double layer: "
-                               "P0 Laplace and Helmholtz, P1 Laplace");
+    if (r.near == BEM_NEAR_SINGULAR && r.space == BEM_P1 && is_complex_op(r.op))
+        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for the single, double and adjoint double layer "
+                               "(P0 Laplace and Helmholtz, P1 Laplace) and the Laplace hypersingular operator");
     if (is_complex_op(r.op)) {
         if (!(std::isfinite(r.k) && r.k > 0.0)) return fail(BEM_E_ARG, "Helmholtz needs a finite wavenumber k > 0");
     } else if (r.k != 0.0) {
@@ -516,6 +553,7 @@ int expand_request(Request &r)
     r.near_index.clear();
     r.near_recs.clear();
     r.near_src.clear();
+    r.near_wt.clear();
     if (r.near == BEM_NEAR_SINGULAR) {
         if (r.space == BEM_P0)
             build_near_items(r);
@@ -532,6 +570,7 @@ void expand_single_fixed(Request &r, int32_t dof, int rowfix, const LaneRef *ext
     r.near_index.clear();
     r.near_recs.clear();
     r.near_src.clear();
+    r.near_wt.clear();
     r.ext = ext;
     r.fixrows = rowfix;
     r.rowfix = is_adjoint_op(r.op) ? 1 - rowfix : rowfix;

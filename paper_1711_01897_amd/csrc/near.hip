@@ -495,17 +495,32 @@ __global__ __launch_bounds__(kNearThreads) void k_near_p1(const NearItem *__rest
     }
 }
 
-// Each record sums its sources (indices into the local matrices) in order
-// and adds the sum to its entry.
+// Laplace hypersingular operator (Eq. hypsHelmholtz at k = 0): the hat
+// functions' surface curls are constant per triangle, so a pair's local
+// matrix is curl_a . curl_b times its P0 single-layer integral; the pair
+// kernel stores that integral, the gather applies the curl products.
+__global__ __launch_bounds__(kNearThreads) void k_near_slp_value(const NearItem *__restrict__ items, int64_t n)
+{
+    if ((int64_t)blockIdx.x >= n) return;
+    const NearItem &it = items[blockIdx.x];
+    const Cx v = pair_value<0>(it);
+    if (threadIdx.x == 0) *static_cast<double *>(it.out) = v.re;
+}
+
+// Each record sums its sources (indices into the local values, times the
+// source's weight when wt is given) in order and adds the sum to its entry.
 template <bool FP32>
 __global__ void k_near_gather(const NearGather *__restrict__ recs, int64_t n, const int32_t *__restrict__ src,
-                              const double *__restrict__ local)
+                              const double *__restrict__ wt, const double *__restrict__ local)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const NearGather g = recs[i];
     double s = 0.0;
-    for (int32_t k = 0; k < g.count; ++k) s += local[src[g.first + k]];
+    if (wt)
+        for (int32_t k = 0; k < g.count; ++k) s += wt[g.first + k] * local[src[g.first + k]];
+    else
+        for (int32_t k = 0; k < g.count; ++k) s += local[src[g.first + k]];
     if constexpr (FP32) {
         float *o = static_cast<float *>(g.out);
         *o = (float)((double)*o + s);
@@ -520,24 +535,26 @@ __global__ void k_near_gather(const NearGather *__restrict__ recs, int64_t n, co
 hipError_t launch_near_p1(int op, const NearItem *items, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (n > INT32_MAX || (op != 0 && op != 1)) return hipErrorInvalidValue;
-    if (op == 0)
+    if (n > INT32_MAX || (op != 0 && op != 1 && op != BEM_LAPLACE_HYPS)) return hipErrorInvalidValue;
+    if (op == BEM_LAPLACE_HYPS)
+        hipLaunchKernelGGL(k_near_slp_value, dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
+    else if (op == 0)
         hipLaunchKernelGGL((k_near_p1<0>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
     else
         hipLaunchKernelGGL((k_near_p1<1>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
     return hipGetLastError();
 }
 
-hipError_t launch_near_gather(bool fp32, const NearGather *recs, int64_t n, const int32_t *src, const double *local,
-                              hipStream_t s)
+hipError_t launch_near_gather(bool fp32, const NearGather *recs, int64_t n, const int32_t *src, const double *wt,
+                              const double *local, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     if (fp32)
-        hipLaunchKernelGGL((k_near_gather<true>), dim3((unsigned)blocks), dim3(256), 0, s, recs, n, src, local);
+        hipLaunchKernelGGL((k_near_gather<true>), dim3((unsigned)blocks), dim3(256), 0, s, recs, n, src, wt, local);
     else
-        hipLaunchKernelGGL((k_near_gather<false>), dim3((unsigned)blocks), dim3(256), 0, s, recs, n, src, local);
+        hipLaunchKernelGGL((k_near_gather<false>), dim3((unsigned)blocks), dim3(256), 0, s, recs, n, src, wt, local);
     return hipGetLastError();
 }
 

@@ -89,7 +89,7 @@ def test_singular_policy_limits(ico2):
     with pytest.raises(bem.BemError):
         bem.eval_entries(mesh, bem.HELMHOLTZ_SLP, bem.P1, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
     with pytest.raises(bem.BemError):
-        bem.eval_entries(mesh, bem.LAPLACE_HYPS, bem.P1, 0.0, idx, idx, near=bem.NEAR_SINGULAR)
+        bem.eval_entries(mesh, bem.HELMHOLTZ_HYPS, bem.P1, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
 
 
 @pytest.mark.parametrize("op", [bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP])
@@ -306,5 +306,52 @@ def test_complete_p1_hmatrix_matvec(op):
     err = np.linalg.norm(H.matvec(x) - A @ x) / np.linalg.norm(A @ x)
     print(H.stats(), err)
     assert err <= 1e-6
+    H.destroy()
+    mesh.destroy()
+
+
+@pytest.mark.parametrize("prec,bound", [(bem.FP64, 1e-6), (bem.FP32, 1e-5)])
+def test_p1_hypersingular_singular_pairs_vs_oracle(ico2, prec, bound):
+    """Laplace hypersingular operator, P1: the singular part (curl products
+    times each pair's P0 single-layer integral) against the oracle's local
+    matrices built the same way from its near-field fixture."""
+    xyz, tri, mesh, om = ico2
+    nv = xyz.shape[0]
+    rows = np.random.Generator(np.random.PCG64(23)).choice(nv, 8, replace=False).astype(np.int32)
+    cols = np.arange(nv, dtype=np.int32)
+    got = bem.eval_entries(mesh, bem.LAPLACE_HYPS, bem.P1, 0.0, rows, cols, prec=prec, near=bem.NEAR_SINGULAR)
+    skip = bem.eval_entries(mesh, bem.LAPLACE_HYPS, bem.P1, 0.0, rows, cols, prec=prec, near=bem.NEAR_SKIP)
+    ref = p1_singular_reference(xyz, tri, om, bem.LAPLACE_HYPS, rows, cols)
+    near = ref != 0.0
+    assert np.array_equal(got[~near], skip[~near])
+    err = np.abs((got.astype(np.float64) - skip) - ref)[near].max() / np.abs(ref).max()
+    print(f"P1 hypersingular prec {prec}: {near.sum()} entries with singular pairs, max rel err {err:.2e}")
+    assert err <= bound
+
+
+def test_complete_hypersingular_hmatrix_on_the_sphere():
+    """dense_mode 2 for the Laplace hypersingular operator (level-3
+    icosphere, P1, FP64): matvec against the oracle's complete matrix, and the
+    unit sphere's degree-1 eigenvalue: D x ~ (2/3) M x (O(h^2), 2.1e-3 here)."""
+    xyz, tri = inputs.icosphere(3)
+    nv, nt = xyz.shape[0], tri.shape[0]
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    H = bem.hmat_assemble(mesh, bem.LAPLACE_HYPS, bem.P1, 0.0, leaf_size=32, eta=1.0, aca_tol=1e-8, max_rank=100,
+                          n_workers=4, blocks_per_worker=8, prec=bem.FP64, dense_mode=2)
+    idx = np.arange(nv, dtype=np.int32)
+    A = om.entries(O.LAPLACE_HYPS, O.P1, 0.0, idx, idx, near=O.NEAR_SKIP) + \
+        p1_singular_reference(xyz, tri, om, bem.LAPLACE_HYPS, idx, idx, 3)
+    u = xyz[:, 0].copy()
+    Du = H.matvec(u)
+    err = np.linalg.norm(Du - A @ u) / np.linalg.norm(A @ u)
+    area = 0.5 * np.linalg.norm(np.cross(xyz[tri[:, 1]] - xyz[tri[:, 0]], xyz[tri[:, 2]] - xyz[tri[:, 0]]), axis=1)
+    Mu = np.zeros(nv)
+    for t in range(nt):
+        Mu[tri[t]] += area[t] / 12.0 * (np.ones((3, 3)) + np.eye(3)) @ u[tri[t]]
+    eig = np.linalg.norm(Du - (2.0 / 3.0) * Mu) / np.linalg.norm((2.0 / 3.0) * Mu)
+    print(H.stats(), f"matvec {err:.2e}, sphere eigenvalue residual {eig:.2e}")
+    assert err <= 1e-6
+    assert eig <= 5e-3
     H.destroy()
     mesh.destroy()
