@@ -355,3 +355,36 @@ def test_complete_hypersingular_hmatrix_on_the_sphere():
     assert eig <= 5e-3
     H.destroy()
     mesh.destroy()
+
+
+@pytest.mark.parametrize("space,op", [(bem.P0, bem.LAPLACE_SLP), (bem.P0, bem.HELMHOLTZ_DLP),
+                                      (bem.P1, bem.LAPLACE_SLP), (bem.P1, bem.LAPLACE_ADLP),
+                                      (bem.P1, bem.LAPLACE_HYPS)])
+def test_singular_edge_cases(ico2, space, op):
+    """Duplicated and unsorted indices give the rows and columns of the plain
+    request; rows with no vertex-sharing column are bitwise the skip policy's;
+    a single entry (the diagonal) works; the asynchronous path agrees."""
+    xyz, tri, mesh, om = ico2
+    n = tri.shape[0] if space == bem.P0 else xyz.shape[0]
+    k = 3.0 if bem.is_complex(op) else 0.0
+    rng = np.random.Generator(np.random.PCG64(31))
+    base_r = np.sort(rng.choice(n, 6, replace=False)).astype(np.int32)
+    base_c = np.arange(n, dtype=np.int32)
+    ref = bem.eval_entries(mesh, op, space, k, base_r, base_c, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    pr = np.concatenate([base_r[::-1], base_r[:2]])
+    pc = rng.permutation(np.concatenate([base_c, base_c[:5]])).astype(np.int32)
+    got = bem.eval_entries(mesh, op, space, k, pr, pc, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    ri = {v: i for i, v in enumerate(base_r.tolist())}
+    expect = ref[[ri[v] for v in pr.tolist()]][:, pc]
+    assert np.abs(got - expect).max() <= 1e-14 * np.abs(ref).max()
+    # far columns only: nothing singular
+    if space == bem.P0:
+        cen = xyz[tri].mean(1)
+        far = np.flatnonzero(np.linalg.norm(cen - cen[base_r[0]], axis=1) > 1.0).astype(np.int32)
+    else:
+        far = np.flatnonzero(np.linalg.norm(xyz - xyz[base_r[0]], axis=1) > 1.0).astype(np.int32)
+    a = bem.eval_entries(mesh, op, space, k, base_r[:1], far, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    b = bem.eval_entries(mesh, op, space, k, base_r[:1], far, prec=bem.FP64, near=bem.NEAR_SKIP)
+    assert np.array_equal(a, b)
+    d = bem.eval_entries(mesh, op, space, k, base_r[:1], base_r[:1], prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    assert abs(d[0, 0] - ref[0, base_r[0]]) <= 1e-14 * np.abs(ref).max()
