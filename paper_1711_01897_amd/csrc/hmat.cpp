@@ -495,6 +495,14 @@ int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag, WorkerT
         r.cols.assign(C.h->cols(L), C.h->cols(L) + L.n);
         r.nrows = (int64_t)r.rows.size();
         r.ncols = (int64_t)r.cols.size();
+        if (r.near == BEM_NEAR_SINGULAR) {
+            // triangles sharing a vertex both contain it, so leaves whose support
+            // boxes are apart have no singular pairs: skip the search for them
+            double alo[3], ahi[3], blo[3], bhi[3];
+            support_box(*C.mesh, C.space, r.rows.data(), r.nrows, alo, ahi);
+            support_box(*C.mesh, C.space, r.cols.data(), r.ncols, blo, bhi);
+            if (box_distance(alo, ahi, blo, bhi) > 0.0) r.near = BEM_NEAR_SKIP;
+        }
         const int rc = expand_request(r);
         if (rc != BEM_OK) return rc;
         w.dense_entries += r.entries();
