@@ -1,5 +1,7 @@
-// Singular (vertex-sharing) P0 triangle pairs of the Laplace single and
-// double layer on the device.
+// Singular (vertex-sharing) triangle pairs on the device: P0 Laplace and
+// Helmholtz single and double layer, P1 Laplace single and double layer
+// (3 x 3 local matrices, summed into the entries by a fixed-order gather) and
+// the P1 Laplace hypersingular operator.
 //
 // The regular kernels integrate vertex-disjoint pairs only; Section 3.2.3
 // gives identical, edge-adjacent and vertex-adjacent pairs to a separate
@@ -41,6 +43,8 @@
 // pi, c_n = 1, or 1 - n with the double layer's factor), 48 terms in Horner
 // form: ~1e-14 relative at omega = 6 (two elements per wavelength reach
 // omega ~ 2 pi), 5e-10 at omega = 12 where the alternating terms cancel.
+// The adjoint double layer is the double layer with test and trial exchanged
+// (the host builds its items that way).
 #include <hip/hip_runtime.h>
 
 #include "bem_internal.hpp"
