@@ -14,8 +14,9 @@ Contents
     reference of the device's singular scheme and of the closed-form sphere
     checks: P0 Laplace (closed-form inner potential and solid angle), P0
     Helmholtz (the kernel expanded around r = 0, singular terms in closed
-    form, the remainder on a subdivided rule), P1 Laplace local matrices
-    (closed-form potentials of a linear density).
+    form, the remainder on a subdivided rule), P1 Laplace and Helmholtz local
+    matrices (closed-form potentials of a linear density, the Helmholtz
+    remainder on a subdivided rule) and the Laplace hypersingular operator's.
   * ``oracle.aca``: adaptive cross approximation, Algorithm "ACA" of
     Section 2.1 with the row pivot of Bebendorf's partial pivoting.
   * ``oracle.tree``: geometric cluster tree and block tree (Section 2.1).
@@ -88,6 +89,12 @@ def _lib():
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                            ctypes.c_int, _dp]
     lib.orc_nearfield_p1_local.restype = ctypes.c_int
+    lib.orc_tri_vector_moment_r.argtypes = [_dp, _dp, _dp, _dp, _dp]
+    lib.orc_tri_vector_moment_r.restype = None
+    lib.orc_nearfield_p1_local_c.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.c_int, ctypes.c_int, _dp]
+    lib.orc_nearfield_p1_local_c.restype = ctypes.c_int
     lib.orc_p0_matrix_with_nearfield.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp]
     lib.orc_p0_matrix_with_nearfield.restype = ctypes.c_int
     _LIB = lib
@@ -133,6 +140,14 @@ def tri_vector_moments(v0, v1, v2, x):
     V1, V3 = np.zeros(3), np.zeros(3)
     _lib().orc_tri_vector_moments(_d(_vec(v0)), _d(_vec(v1)), _d(_vec(v2)), _d(_vec(x)), _d(V1), _d(V3))
     return V1, V3
+
+
+def tri_vector_moment_r(v0, v1, v2, x):
+    """int_T (y - rho) |x - y| dy, rho the projection of x on the triangle's
+    plane, closed form."""
+    W1 = np.zeros(3)
+    _lib().orc_tri_vector_moment_r(_d(_vec(v0)), _d(_vec(v1)), _d(_vec(v2)), _d(_vec(x)), _d(W1))
+    return W1
 
 
 def kernel(op: int, k: float, x, y, ny) -> complex:
@@ -241,6 +256,21 @@ class OracleMesh:
         if st != 0:
             raise ValueError("Laplace single, double layer or hypersingular operator and level >= 0")
         return out.reshape(r.size, 3, 3)
+
+    def nearfield_p1_local_c(self, op: int, k: float, rows, cols, level: int = 3, inner_level: int = 3) -> np.ndarray:
+        """Complex 3 x 3 local P1 matrices of the Helmholtz single or double
+        layer for the pairs (rows[t], cols[t]); shape (n, 3, 3)."""
+        r = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        c = np.ascontiguousarray(np.asarray(cols, dtype=np.int64))
+        if r.shape != c.shape or r.ndim != 1:
+            raise ValueError("rows and cols: equal 1D sequences")
+        out = np.zeros(18 * r.size)
+        p64 = ctypes.POINTER(ctypes.c_int64)
+        st = _lib().orc_nearfield_p1_local_c(self._h, op, float(k), r.size, r.ctypes.data_as(p64),
+                                             c.ctypes.data_as(p64), level, inner_level, _d(out))
+        if st != 0:
+            raise ValueError("Helmholtz single or double layer and levels >= 0")
+        return out.view(np.complex128).reshape(r.size, 3, 3)
 
     def p0_matrix_with_nearfield(self, op: int, near_dist: float, level: int = 3) -> np.ndarray:
         out = np.zeros((self.nt, self.nt))

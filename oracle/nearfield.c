@@ -41,6 +41,7 @@ double orc_tri_solid_angle(const double *v0, const double *v1, const double *v2,
 int orc_subdivided_rule(int level, double *xi, double *eta, double *w);
 static double nf_entry(const orc_mesh *m, int op, int64_t i, int64_t j, int npts, const double *xi,
                        const double *eta, const double *w);
+static void nf_remainder(int dlp, double z, double *re, double *im);
 
 static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -184,6 +185,43 @@ void orc_tri_vector_moments(const double *v0, const double *v1, const double *v2
     }
 }
 
+/* W1 = int_T (y - rho) |x - y| dy: the in-plane gradient of R^3/3 is
+ * R (y - rho), so W1 = sum_e m_e int_e R^3/3 dl with
+ * int_e R^3 dl = [l R^3/4 + 3 R0^2 l R/8 + 3 R0^4 ln(l + R)/8] between the
+ * edge's ends. */
+void orc_tri_vector_moment_r(const double *v0, const double *v1, const double *v2, const double *x, double *W1)
+{
+    const double *v[3] = {v0, v1, v2};
+    double e1[3], e2[3], N[3], n[3], xv0[3], rho[3];
+    sub3(v1, v0, e1);
+    sub3(v2, v0, e2);
+    cross3(e1, e2, N);
+    double nn = sqrt(dot3(N, N));
+    for (int d = 0; d < 3; ++d) n[d] = N[d] / nn;
+    sub3(x, v0, xv0);
+    double h = dot3(xv0, n);
+    for (int d = 0; d < 3; ++d) rho[d] = x[d] - h * n[d];
+    for (int d = 0; d < 3; ++d) W1[d] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        const double *pm = v[i], *pp = v[(i + 1) % 3];
+        double s[3], m[3], a[3], b[3];
+        sub3(pp, pm, s);
+        double L = sqrt(dot3(s, s));
+        for (int d = 0; d < 3; ++d) s[d] /= L;
+        cross3(s, n, m);
+        sub3(pp, rho, a);
+        sub3(pm, rho, b);
+        double lp = dot3(a, s), lm = dot3(b, s);
+        double t0 = dot3(b, m);
+        double R0sq = t0 * t0 + h * h;
+        double Rp = sqrt(R0sq + lp * lp), Rm = sqrt(R0sq + lm * lm);
+        double lg = R0sq > 0.0 ? nf_log_rl(lp, Rp, R0sq) - nf_log_rl(lm, Rm, R0sq) : 0.0;
+        double edge = (lp * Rp * Rp * Rp - lm * Rm * Rm * Rm) / 4.0 + 3.0 * R0sq * (lp * Rp - lm * Rm) / 8.0 +
+                      3.0 * R0sq * R0sq * lg / 8.0;
+        for (int d = 0; d < 3; ++d) W1[d] += m[d] * edge / 3.0;
+    }
+}
+
 /* 3 x 3 local matrix of a triangle pair for the P1 hat functions restricted
  * to the pair, Laplace single (op 0) or double (op 1) layer:
  * M[a][b] = int_{T_i} phi_a(x) int_{T_j} psi_b(y) K(x, y) dy dx, a and b in
@@ -236,6 +274,109 @@ static void nf_p1_local(const orc_mesh *m, int op, int64_t i, int64_t j, int npt
         }
     }
     for (int k = 0; k < 9; ++k) M[k] *= m->J[i] / (4.0 * NF_PI);
+}
+
+/* Complex 3 x 3 local matrix of the P1 hat functions for the Helmholtz single
+ * (op 2) or double layer (op 3): the kernel expanded as for P0,
+ *   single layer: psi_b . (1/R + ik - (k^2/2) R + T(R)),
+ *   double layer: psi_b . h (1/R^3 + (k^2/2)/R + i k^3/3 - (k^4/8) R + U(R)),
+ * each singular term over the trial triangle in closed form for the affine
+ * psi_b = psi_b(rho) + grad psi_b . (y - rho) (potentials I0, I1 = int R,
+ * solid angle, vector moments V1, V3, W1; int psi_b = |T|/3), the
+ * remainder on the inner rule (ixi, ieta, iw); M is 9 complex values. */
+static void nf_p1_local_c(const orc_mesh *m, int op, double k, int64_t i, int64_t j, int npts, const double *xi,
+                          const double *eta, const double *w, int nin, const double *ixi, const double *ieta,
+                          const double *iw, double *M)
+{
+    const double *a = m->xyz + 3 * m->tri[3 * i], *b = m->xyz + 3 * m->tri[3 * i + 1],
+                 *c = m->xyz + 3 * m->tri[3 * i + 2];
+    const double *u[3] = {m->xyz + 3 * m->tri[3 * j], m->xyz + 3 * m->tri[3 * j + 1], m->xyz + 3 * m->tri[3 * j + 2]};
+    const double *nj = m->n + 3 * j;
+    const double Jj = m->J[j], area3 = Jj / 6.0;
+    const int dlp = op == ORC_HELMHOLTZ_DLP;
+    double grad[3][3];
+    for (int q = 0; q < 3; ++q) {
+        double ed[3];
+        sub3(u[(q + 2) % 3], u[(q + 1) % 3], ed);
+        cross3(nj, ed, grad[q]);
+        for (int d = 0; d < 3; ++d) grad[q][d] /= Jj;
+    }
+    for (int kk = 0; kk < 18; ++kk) M[kk] = 0.0;
+    for (int p = 0; p < npts; ++p) {
+        double x[3], xu[3], rho[3], V1[3], V3[3], W1[3];
+        for (int d = 0; d < 3; ++d) x[d] = a[d] + xi[p] * (b[d] - a[d]) + eta[p] * (c[d] - a[d]);
+        const double phi[3] = {1.0 - xi[p] - eta[p], xi[p], eta[p]};
+        sub3(x, u[0], xu);
+        const double hgt = dot3(xu, nj);
+        if (dlp && fabs(hgt) <= 1e-12 * sqrt(Jj)) continue;   /* (x - y).n_y = 0 */
+        for (int d = 0; d < 3; ++d) rho[d] = x[d] - hgt * nj[d];
+        const double I0 = orc_tri_potential(u[0], u[1], u[2], x), I1 = orc_tri_moment_r(u[0], u[1], u[2], x);
+        orc_tri_vector_moments(u[0], u[1], u[2], x, V1, V3);
+        orc_tri_vector_moment_r(u[0], u[1], u[2], x, W1);
+        const double Om = dlp ? orc_tri_solid_angle(u[0], u[1], u[2], x) : 0.0;
+        /* remainder with the trial hat functions at the inner points */
+        double rr[3] = {0, 0, 0}, ri[3] = {0, 0, 0};
+        for (int q = 0; q < nin; ++q) {
+            double y[3], d3[3];
+            for (int d = 0; d < 3; ++d) y[d] = u[0][d] + ixi[q] * (u[1][d] - u[0][d]) + ieta[q] * (u[2][d] - u[0][d]);
+            sub3(x, y, d3);
+            double r = sqrt(dot3(d3, d3));
+            if (r == 0.0) continue;
+            double tr, ti;
+            nf_remainder(dlp, k * r, &tr, &ti);
+            const double sc = dlp ? iw[q] / (r * r * r) : iw[q] / r;
+            const double psi[3] = {1.0 - ixi[q] - ieta[q], ixi[q], ieta[q]};
+            for (int bb = 0; bb < 3; ++bb) {
+                rr[bb] += sc * tr * psi[bb];
+                ri[bb] += sc * ti * psi[bb];
+            }
+        }
+        for (int q = 0; q < 3; ++q) {
+            double r1[3], r2[3], cr[3];
+            sub3(u[(q + 1) % 3], rho, r1);
+            sub3(u[(q + 2) % 3], rho, r2);
+            cross3(r1, r2, cr);
+            const double lam = dot3(cr, nj) / Jj;
+            double inr, ini;
+            if (!dlp) {
+                inr = lam * (I0 - 0.5 * k * k * I1) + dot3(grad[q], V1) - 0.5 * k * k * dot3(grad[q], W1) + Jj * rr[q];
+                ini = k * area3 + Jj * ri[q];
+            } else {
+                inr = -lam * Om + hgt * dot3(grad[q], V3) +
+                      hgt * (0.5 * k * k * (lam * I0 + dot3(grad[q], V1)) -
+                             0.125 * k * k * k * k * (lam * I1 + dot3(grad[q], W1)) + Jj * rr[q]);
+                ini = hgt * (k * k * k * area3 / 3.0 + Jj * ri[q]);
+            }
+            for (int t = 0; t < 3; ++t) {
+                M[2 * (3 * t + q)] += w[p] * phi[t] * inr;
+                M[2 * (3 * t + q) + 1] += w[p] * phi[t] * ini;
+            }
+        }
+    }
+    for (int kk = 0; kk < 18; ++kk) M[kk] *= m->J[i] / (4.0 * NF_PI);
+}
+
+/* Complex P1 local matrices of n pairs, Helmholtz single (op 2) or double
+ * (op 3) layer: outer rule on 4^level, remainder on 4^inner_level
+ * sub-triangles; out holds n row-major 3 x 3 complex (18 doubles). */
+int orc_nearfield_p1_local_c(const orc_mesh *m, int op, double k, int64_t n, const int64_t *rows,
+                             const int64_t *cols, int level, int inner_level, double *out)
+{
+    if ((op != ORC_HELMHOLTZ_SLP && op != ORC_HELMHOLTZ_DLP) || level < 0 || inner_level < 0) return ORC_E_ARG;
+    int np = 6, ni = 6;
+    for (int l = 0; l < level; ++l) np *= 4;
+    for (int l = 0; l < inner_level; ++l) ni *= 4;
+    double *xi = (double *)malloc(sizeof(double) * 3 * (np + ni));
+    double *eta = xi + np, *w = xi + 2 * np, *ixi = xi + 3 * np, *ieta = ixi + ni, *iw = ixi + 2 * ni;
+    orc_subdivided_rule(level, xi, eta, w);
+    orc_subdivided_rule(inner_level, ixi, ieta, iw);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t t = 0; t < n; ++t)
+        nf_p1_local_c(m, op, k, rows[t], cols[t], np, xi, eta, w, ni, ixi, ieta, iw, out + 18 * t);
+    free(xi);
+    return ORC_OK;
 }
 
 /* P1 local matrices of n pairs (rows[t], cols[t]), Laplace single or double

@@ -1,5 +1,7 @@
-"""Pins of the oracle's P1 near-field fixture: 3 x 3 local matrices of the
-Laplace single and double layer for a triangle pair,
+"""Pins of the oracle's P1 near-field fixtures: 3 x 3 local matrices of the
+Laplace single and double layer (and, at the end, of the Helmholtz single
+and double layer, whose expansion adds int (y - rho) R; pinned the same way
+plus the smooth imaginary part and k -> 0) for a triangle pair,
 M[a][b] = int_T phi_a int_S psi_b K, from the closed-form potentials of a
 linear density (the constant part's potential or solid angle, plus the
 in-plane vector moments int (y - rho)/R and int (y - rho)/R^3 from edge
@@ -172,3 +174,80 @@ def test_hypersingular_sphere_linear_functions():
     xyz, Ds, mass = full_hyps_matrix(2, with_singular=False)
     u = xyz[:, 0]
     assert np.linalg.norm(Ds @ u - (2.0 / 3.0) * mass @ u) / np.linalg.norm((2.0 / 3.0) * mass @ u) > 0.1
+
+
+@pytest.mark.parametrize("x", [[0.4, 0.3, 0.5], [2.0, 1.0, 0.0], [-0.3, -0.2, 0.31], [5.0, 5.0, 5.0]])
+def test_vector_moment_r_vs_brute_force(x):
+    v0, v1, v2 = np.array([0.0, 0.0, 0.0]), np.array([1.0, 0.1, 0.0]), np.array([0.3, 0.8, 0.05])
+    xi, eta, w = O.subdivided_rule(6)
+    Y = v0 + xi[:, None] * (v1 - v0) + eta[:, None] * (v2 - v0)
+    N = np.cross(v1 - v0, v2 - v0)
+    J = np.linalg.norm(N)
+    x = np.asarray(x)
+    rho = x - ((x - v0) @ (N / J)) * (N / J)
+    bf = J * np.sum(w[:, None] * (Y - rho) * np.linalg.norm(Y - x, axis=1)[:, None], axis=0)
+    W1 = O.tri_vector_moment_r(v0, v1, v2, x)
+    assert np.abs(W1 - bf).max() <= 1e-12 * np.abs(bf).max()
+
+
+def product_rule_local_c(xyz, tri, op, k, i, j, level=3):
+    """Helmholtz P1 local matrix by the subdivided rule on both triangles:
+    the real part of the k-dependent correction and the imaginary part."""
+    xi, eta, w = O.subdivided_rule(level)
+    a, b, c = xyz[tri[i]]
+    u0, u1, u2 = xyz[tri[j]]
+    X = a + xi[:, None] * (b - a) + eta[:, None] * (c - a)
+    Y = u0 + xi[:, None] * (u1 - u0) + eta[:, None] * (u2 - u0)
+    Nj = np.cross(u1 - u0, u2 - u0)
+    Jj = np.linalg.norm(Nj)
+    Ji = np.linalg.norm(np.cross(b - a, c - a))
+    D = X[:, None, :] - Y[None, :, :]
+    r = np.linalg.norm(D, axis=2)
+    r0 = r == 0.0
+    r = np.where(r0, 1.0, r)
+    z = k * r
+    if op == O.HELMHOLTZ_SLP:
+        re, im = (np.cos(z) - 1.0) / r, np.where(r0, k, np.sin(z) / r)
+    else:
+        hgt = D @ (Nj / Jj)
+        re = (np.cos(z) + z * np.sin(z) - 1.0) * hgt / r ** 3
+        im = np.where(r0, 0.0, (np.sin(z) - z * np.cos(z)) * hgt / r ** 3)
+    re = np.where(r0, 0.0, re)
+    phi = np.stack([1 - xi - eta, xi, eta])
+    f = Ji * Jj / (4 * np.pi)
+    return (f * np.einsum("ap,bq,p,q,pq->ab", phi, phi, w, w, re),
+            f * np.einsum("ap,bq,p,q,pq->ab", phi, phi, w, w, im))
+
+
+@pytest.mark.parametrize("op", [O.HELMHOLTZ_SLP, O.HELMHOLTZ_DLP])
+def test_helmholtz_p1_separated_pairs_vs_product_rule(ico2, op):
+    xyz, tri, om = ico2
+    cen = xyz[tri].mean(1)
+    h = inputs.mean_edge_length(xyz, tri)
+    d = np.linalg.norm(cen[0] - cen, axis=1)
+    cols = [int(np.argmin(abs(d - f * h))) for f in (2.5, 6.0)]
+    k = 6.0
+    M = om.nearfield_p1_local_c(op, k, [0] * len(cols), cols, 3, 3)
+    L = om.nearfield_p1_local(op - 2, [0] * len(cols), cols, 3)
+    for q, j in enumerate(cols):
+        re, im = product_rule_local_c(xyz, tri, op, k, 0, j)
+        ref = L[q] + re + 1j * im
+        assert np.abs(M[q] - ref).max() <= 1e-8 * np.abs(ref).max(), j
+
+
+@pytest.mark.parametrize("op", [O.HELMHOLTZ_SLP, O.HELMHOLTZ_DLP])
+def test_helmholtz_p1_adjacent_pairs(ico2, op):
+    """Vertex-sharing pairs: the imaginary part (smooth kernel) against the
+    product rule; the local matrices sum to the P0 value; k -> 0 gives the
+    Laplace fixture."""
+    xyz, tri, om = ico2
+    adj = [j for j in range(tri.shape[0]) if set(tri[0]) & set(tri[j])]
+    k = 4.0
+    M = om.nearfield_p1_local_c(op, k, [0] * len(adj), adj, 3, 3)
+    im = np.array([product_rule_local_c(xyz, tri, op, k, 0, j)[1] for j in adj])
+    assert np.abs(M.imag - im).max() <= 1e-12 * np.abs(M.imag).max()
+    p0 = om.nearfield_entries(op, k, [0] * len(adj), adj, 3, 3)
+    assert np.abs(M.sum((1, 2)) - p0).max() <= 1e-14 * np.abs(p0).max()
+    M0 = om.nearfield_p1_local_c(op, 1e-7, [0] * len(adj), adj, 2, 2)
+    L = om.nearfield_p1_local(op - 2, [0] * len(adj), adj, 2)
+    assert np.abs(M0.real - L).max() <= 1e-12 * np.abs(L).max()
