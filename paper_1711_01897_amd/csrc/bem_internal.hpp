@@ -140,10 +140,14 @@ static_assert(sizeof(NearItem) == 184, "near items are 184 bytes");
 // 256-byte aligned.
 struct NearP1Layout {
     size_t items, recs, src, wt, local, bytes;
-    int per;   // local values per pair
-    bool weighted;
+    int per;       // doubles per pair in the local values
+    int src_per;   // gather source units per pair (9 values, 9 complex values, or 1)
+    bool weighted, cplx;
 };
-NearP1Layout near_p1_layout(bool hyps, int64_t items, int64_t recs, int64_t src);
+// mode: 0 real 3 x 3 local matrices, 1 hypersingular (one value per pair,
+// weighted sources), 2 complex 3 x 3 local matrices
+NearP1Layout near_p1_layout(int mode, int64_t items, int64_t recs, int64_t src);
+int near_p1_mode(const Request &r);
 NearP1Layout near_p1_layout(const Request &r);
 // Writes request r's part of a region's host image at host (dev: the region's
 // device address, out_dev: r's output on the device), its pairs, records and
@@ -155,7 +159,9 @@ void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *de
 // gather into the entries).
 hipError_t launch_near_p1_region(int op, bool fp32, const NearP1Layout &L, char *dev, int64_t items, int64_t recs,
                                  hipStream_t s);
-// Index of the P1 singular run of a request (kernel and precision), 0..5.
+// Index of the P1 singular run of a request (kernel and precision), 0..9:
+// 2 g + fp32 with g = 0 single, 1 double layer, 2 hypersingular (Laplace),
+// 3 single, 4 double layer (Helmholtz).
 int near_p1_group(const Request &r);
 
 hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s);
@@ -169,15 +175,16 @@ struct NearGather {
 static_assert(sizeof(NearGather) == 16, "gather records are 16 bytes");
 
 // P1 Laplace single (op 0) or double layer (op 1): each item's 3 x 3 local
-// matrix (FP64) into the 9 doubles at item.out; Laplace hypersingular
+// matrix (FP64) into the 9 doubles at item.out; Helmholtz single (op 2) or
+// double layer (op 3): 9 complex values (18 doubles); Laplace hypersingular
 // operator (op 6): the pair's P0 single-layer integral into the double at
 // item.out.  One workgroup per item.
 hipError_t launch_near_p1(int op, const NearItem *items, int64_t n, hipStream_t s);
 // Adds each record's fixed-order sum of local values (times the source
 // weights when wt is not null) to its float (fp32) or double entry.  One
 // thread per record.
-hipError_t launch_near_gather(bool fp32, const NearGather *recs, int64_t n, const int32_t *src, const double *wt,
-                              const double *local, hipStream_t s);
+hipError_t launch_near_gather(bool fp32, bool cplx, const NearGather *recs, int64_t n, const int32_t *src,
+                              const double *wt, const double *local, hipStream_t s);
 
 // Copies bytes (a multiple of 16, both addresses 16-byte aligned) from src
 // (device-visible host staging) to dst (device) with a kernel on stream s.

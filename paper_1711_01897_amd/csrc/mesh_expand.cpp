@@ -313,7 +313,7 @@ void build_near_items_p1(Request &r)
 {
     const bem_mesh &m = *r.mesh;
     const bool adj = is_adjoint_op(r.op);
-    const bool dlp = kernel_op(r.op) == BEM_LAPLACE_DLP;
+    const bool dlp = kernel_op(r.op) == BEM_LAPLACE_DLP || kernel_op(r.op) == BEM_HELMHOLTZ_DLP;
     const bool hyps = r.op == BEM_LAPLACE_HYPS;
     std::vector<std::pair<int32_t, int64_t>> rowpos((size_t)r.nrows), colpos((size_t)r.ncols);
     for (int64_t i = 0; i < r.nrows; ++i) rowpos[i] = {r.rows[i], i};
@@ -395,6 +395,7 @@ void build_near_items_p1(Request &r)
                     }
             if (shared == 3 && dlp) continue;   // (x - y).n_y = 0 on a flat triangle
             NearItem q{};
+            q.k = is_complex_op(r.op) ? r.k : 0.0;
             int32_t tl[3], sl[3];   // global vertices in the kernel's local orders
             q.jt = cross_len(T, nullptr);
             q.js = cross_len(S, q.ny);
@@ -457,11 +458,14 @@ void build_near_items_p1(Request &r)
 
 static size_t align256_sz(size_t x) { return (x + 255) & ~(size_t)255; }
 
-NearP1Layout near_p1_layout(bool hyps, int64_t items, int64_t recs, int64_t src)
+NearP1Layout near_p1_layout(int mode, int64_t items, int64_t recs, int64_t src)
 {
+    const bool hyps = mode == 1;
     NearP1Layout L;
-    L.per = hyps ? 1 : 9;
+    L.per = hyps ? 1 : (mode == 2 ? 18 : 9);
+    L.src_per = hyps ? 1 : 9;
     L.weighted = hyps;
+    L.cplx = mode == 2;
     L.items = 0;
     L.recs = align256_sz(sizeof(NearItem) * (size_t)items);
     L.src = L.recs + align256_sz(sizeof(NearGather) * (size_t)recs);
@@ -471,15 +475,19 @@ NearP1Layout near_p1_layout(bool hyps, int64_t items, int64_t recs, int64_t src)
     return L;
 }
 
+int near_p1_mode(const Request &r) { return r.op == BEM_LAPLACE_HYPS ? 1 : (is_complex_op(r.op) ? 2 : 0); }
+
 NearP1Layout near_p1_layout(const Request &r)
 {
-    return near_p1_layout(r.op == BEM_LAPLACE_HYPS, (int64_t)r.near_items.size(), (int64_t)r.near_recs.size(),
+    return near_p1_layout(near_p1_mode(r), (int64_t)r.near_items.size(), (int64_t)r.near_recs.size(),
                           (int64_t)r.near_src.size());
 }
 
 int near_p1_group(const Request &r)
 {
-    return 2 * (r.op == BEM_LAPLACE_HYPS ? 2 : kernel_op(r.op)) + (r.prec == BEM_FP32 ? 1 : 0);
+    const int kop = kernel_op(r.op);
+    const int g = r.op == BEM_LAPLACE_HYPS ? 2 : (kop == BEM_HELMHOLTZ_SLP ? 3 : (kop == BEM_HELMHOLTZ_DLP ? 4 : kop));
+    return 2 * g + (r.prec == BEM_FP32 ? 1 : 0);
 }
 
 void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *dev, char *out_dev, int64_t pb,
@@ -495,7 +503,7 @@ void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *de
         g[j] = {out_dev + (size_t)r.near_recs[j].entry * r.elem_bytes, (int32_t)(sb + r.near_recs[j].first),
                 r.near_recs[j].count};
     int32_t *src = reinterpret_cast<int32_t *>(host + L.src) + sb;
-    for (size_t j = 0; j < r.near_src.size(); ++j) src[j] = (int32_t)(L.per * pb) + r.near_src[j];
+    for (size_t j = 0; j < r.near_src.size(); ++j) src[j] = (int32_t)(L.src_per * pb) + r.near_src[j];
     if (L.weighted && !r.near_wt.empty())
         std::memcpy(reinterpret_cast<double *>(host + L.wt) + sb, r.near_wt.data(), sizeof(double) * r.near_wt.size());
 }
@@ -505,7 +513,7 @@ hipError_t launch_near_p1_region(int op, bool fp32, const NearP1Layout &L, char 
 {
     hipError_t e = launch_near_p1(op, reinterpret_cast<const NearItem *>(dev + L.items), items, s);
     if (e != hipSuccess) return e;
-    return launch_near_gather(fp32, reinterpret_cast<const NearGather *>(dev + L.recs), recs,
+    return launch_near_gather(fp32, L.cplx, reinterpret_cast<const NearGather *>(dev + L.recs), recs,
                               reinterpret_cast<const int32_t *>(dev + L.src),
                               L.weighted ? reinterpret_cast<const double *>(dev + L.wt) : nullptr,
                               reinterpret_cast<const double *>(dev + L.local), s);
@@ -521,9 +529,9 @@ int expand_request(Request &r)
     if (r.prec != BEM_FP32 && r.prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
     if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP && r.near != BEM_NEAR_SINGULAR)
         return fail(BEM_E_ARG, "unknown near-field policy");
-    if (r.near == BEM_NEAR_SINGULAR && r.space == BEM_P1 && is_complex_op(r.op))
+    if (r.near == BEM_NEAR_SINGULAR && r.op == BEM_HELMHOLTZ_HYPS)
         return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for the single, double and adjoint double layer "
-                               "(P0 Laplace and Helmholtz, P1 Laplace) and the Laplace hypersingular operator");
+                               "and the Laplace hypersingular operator");
     if (is_complex_op(r.op)) {
         if (!(std::isfinite(r.k) && r.k > 0.0)) return fail(BEM_E_ARG, "Helmholtz needs a finite wavenumber k > 0");
     } else if (r.k != 0.0) {

@@ -1,7 +1,7 @@
-// Singular (vertex-sharing) triangle pairs on the device: P0 Laplace and
-// Helmholtz single and double layer, P1 Laplace single and double layer
-// (3 x 3 local matrices, summed into the entries by a fixed-order gather) and
-// the P1 Laplace hypersingular operator.
+// Singular (vertex-sharing) triangle pairs on the device: the Laplace and
+// Helmholtz single and double layer, P0 and P1 (P1: 3 x 3 local matrices,
+// summed into the entries by a fixed-order gather), and the P1 Laplace
+// hypersingular operator.
 //
 // The regular kernels integrate vertex-disjoint pairs only; Section 3.2.3
 // gives identical, edge-adjacent and vertex-adjacent pairs to a separate
@@ -120,6 +120,43 @@ template <int POLY, bool DL>
 __device__ __forceinline__ Cx radial(double om)
 {
     constexpr RadialSeries<POLY, DL> c{};
+    const double w2 = om * om;
+    double r = c.re[kSeries / 2 - 1], i = c.im[kSeries / 2 - 1];
+#pragma unroll
+    for (int m = kSeries / 2 - 2; m >= 0; --m) {
+        r = fma(r, w2, c.re[m]);
+        i = fma(i, w2, c.im[m]);
+    }
+    return {r, om * i};
+}
+
+// int_0^1 rho^A (1 - rho)^B e^{i om rho} (1 - i om rho)^[DL] d rho (B <= 2)
+// by the same 48-term series (moments of rho^A (1 - rho)^B).
+template <int A, int B, bool DL>
+struct MomentSeries {
+    double re[kSeries / 2], im[kSeries / 2];
+    constexpr MomentSeries() : re(), im()
+    {
+        double fact = 1.0;
+        for (int n = 0; n < kSeries; ++n) {
+            if (n > 0) fact *= n;
+            const double e = n + A;
+            const double mu = B == 0 ? 1.0 / (e + 1) : B == 1 ? 1.0 / ((e + 1) * (e + 2)) : 2.0 / ((e + 1) * (e + 2) * (e + 3));
+            const double a = mu * (DL ? 1.0 - n : 1.0) / fact;
+            const int m = n / 2;
+            const double sgn = (m % 2) ? -1.0 : 1.0;
+            if (n % 2 == 0)
+                re[m] = sgn * a;
+            else
+                im[m] = sgn * a;
+        }
+    }
+};
+
+template <int A, int B, bool DL>
+__device__ __forceinline__ Cx moment(double om)
+{
+    constexpr MomentSeries<A, B, DL> c{};
     const double w2 = om * om;
     double r = c.re[kSeries / 2 - 1], i = c.im[kSeries / 2 - 1];
 #pragma unroll
@@ -467,6 +504,173 @@ __device__ void pair_part_p1(const NearItem &it, const double *sx, const double 
     }
 }
 
+// acc[3a + b] += K (alpha_a gamma_b J0 + (alpha_a delta_b + beta_a gamma_b) J1
+// + beta_a delta_b J2): the radial integral of (alpha + beta rho)(gamma +
+// delta rho) against the moments J_m (complex), times K.
+__device__ __forceinline__ void moment_acc(double *ar, double *ai, double K, const L3 &al, const L3 &be, const L3 &ga,
+                                           const L3 &de, const Cx &J0, const Cx &J1, const Cx &J2)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double c0 = K * al.v[a] * ga.v[b], c1 = K * (al.v[a] * de.v[b] + be.v[a] * ga.v[b]),
+                         c2 = K * be.v[a] * de.v[b];
+            ar[3 * a + b] += c0 * J0.re + c1 * J1.re + c2 * J2.re;
+            ai[3 * a + b] += c0 * J0.im + c1 * J1.im + c2 * J2.im;
+        }
+}
+
+// P1 Helmholtz (op 2 single, op 3 double layer): the Laplace P1 scheme with
+// the radial factor e^{ikr}: at each face point the barycentrics are
+// alpha + beta rho (test) and gamma + delta rho (trial), and the radial
+// integrals are three moment series (identical pairs: the radius xi, the
+// moments at omega eta1 eta2, eta1 and eta2 on the 8-point rule).
+template <int OP>
+__device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, const double *sw, double *ar,
+                                       double *ai)
+{
+    constexpr bool DL = OP == 3;
+    const int t = threadIdx.x;
+    const double k = it.k;
+    if (it.kind == 0) {
+        if (DL || t >= 3 * kIdPts) return;
+        const V3 V0 = ld(it.v), V1 = ld(it.v + 3), V2 = ld(it.v + 6);
+        const V3 E1 = sub(V1, V0), E2 = sub(V2, V1);
+        const int line = t / kIdPts, kk = t - line * kIdPts;
+        const double e3 = (c_x[kk % kGL] + (double)(kk / kGL)) * (1.0 / kIdPanels);
+        const double w3 = c_w[kk % kGL] * (1.0 / kIdPanels);
+        const V3 c = line == 0 ? fma3(e3, E1, E2) : (line == 1 ? fma3(e3, E2, E1) : fma3(-e3, E1, mul(1.0 - e3, E2)));
+        const double ic = rsqrt(dot(c, c));
+        const double om = k / ic;
+        for (int j = 0; j < kGL; ++j)
+            for (int l = 0; l < kGL; ++l) {
+                const double e1 = c_x[j], e2 = c_x[l];
+                // x = xi (A1, B1), y = xi (A2, B2) in the (a, b) coordinates
+                double A1, B1, A2, B2;
+                if (line == 0) {
+                    A1 = 1.0, B1 = 1.0 - e1 + e1 * e2, A2 = 1.0 - e1 * e2 * e3, B2 = 1.0 - e1;
+                } else if (line == 1) {
+                    A1 = 1.0, B1 = e1 * (1.0 - e2 + e2 * e3), A2 = 1.0 - e1 * e2, B2 = e1 * (1.0 - e2);
+                } else {
+                    A1 = 1.0 - e1 * e2 * e3, B1 = e1 * (1.0 - e2 * e3), A2 = 1.0, B2 = e1 * (1.0 - e2);
+                }
+                const double w = w3 * c_w[j] * c_w[l] * e1 * ic;
+                const double oe = om * e1 * e2;
+                const Cx J0 = moment<2, 0, false>(oe), J1 = moment<3, 0, false>(oe), J2 = moment<4, 0, false>(oe);
+                const L3 al{{1.0, 0.0, 0.0}}, bx{{-A1, A1 - B1, B1}}, by{{-A2, A2 - B2, B2}};
+                moment_acc(ar, ai, w, al, bx, al, by, J0, J1, J2);   // the region
+                moment_acc(ar, ai, w, al, by, al, bx, J0, J1, J2);   // and its mirror
+            }
+        return;
+    }
+    if (it.kind == 1) {
+        const V3 P = ld(it.v), Q = ld(it.v + 3), A = ld(it.v + 6), B = ld(it.v + 9);
+        const V3 E = sub(Q, P), a = sub(A, P), b = sub(B, P);
+        const int face = t >> 6, ip = (t >> 2) & (kPts - 1), g = t & 3;
+        const double p = sx[ip], q1 = 1.0 - p;
+        for (int j = 0; j < kPts / 4; ++j) {
+            const double q = sx[g + 4 * j];
+            double dh, s1h, s2h, fw;
+            if (face == 0)
+                dh = p, s1h = q1 * q, s2h = 1.0, fw = q1;
+            else if (face == 1)
+                dh = p, s1h = q1, s2h = q, fw = 1.0;
+            else if (face == 2)
+                dh = -p, s1h = 1.0, s2h = q1 * q, fw = q1;
+            else
+                dh = -p, s1h = q, s2h = q1, fw = 1.0;
+            const V3 c = fma3(dh, E, fma3(s1h, a, mul(-s2h, b)));
+            const double ic = rsqrt(dot(c, c));
+            const double om = k / ic;
+            const double K = sw[ip] * sw[g + 4 * j] * fw * (DL ? s1h * ic * ic * ic : ic);
+            Cx J0, J1, J2;
+            if constexpr (DL) {
+                J0 = moment<0, 1, true>(om), J1 = moment<1, 1, true>(om), J2 = moment<2, 1, true>(om);
+            } else {
+                J0 = moment<1, 1, false>(om), J1 = moment<2, 1, false>(om), J2 = moment<3, 1, false>(om);
+            }
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                const double tau = kG2x[l];
+                L3 al, be, ga, de;
+                al = L3{{1.0 - tau, tau, 0.0}};
+                ga = L3{{1.0 - tau, tau, 0.0}};
+                if (face < 2) {   // u2 = (1 - rho) tau, u1 = u2 + rho dh
+                    be = L3{{tau - dh - s1h, dh - tau, s1h}};
+                    de = L3{{tau - s2h, -tau, s2h}};
+                } else {          // u1 = (1 - rho) tau, u2 = u1 - rho dh
+                    be = L3{{tau - s1h, -tau, s1h}};
+                    de = L3{{tau + dh - s2h, -dh - tau, s2h}};
+                }
+                moment_acc(ar, ai, 0.5 * K, al, be, ga, de, J0, J1, J2);
+            }
+        }
+        return;
+    }
+    const V3 P = ld(it.v), A = ld(it.v + 3), B = ld(it.v + 6), C = ld(it.v + 9), D = ld(it.v + 12);
+    const int iu = t / kPts, iv = t % kPts;
+    const double u = sx[iu], v = sx[iv];
+    const V3 av = fma3(u, sub(B, A), sub(A, P));
+    const V3 bv = fma3(v, sub(D, C), sub(C, P));
+    const double an = DL ? dot(av, ld(it.ny)) : 1.0;
+    const double wuv = sw[iu] * sw[iv];
+    const L3 al{{1.0, 0.0, 0.0}}, bu{{-1.0, 1.0 - u, u}}, bvv{{-1.0, 1.0 - v, v}};
+    for (int kz = 0; kz < kPts; ++kz) {
+        const double z = sx[kz];
+        const V3 c1 = fma3(-z, bv, av), c2 = fma3(z, av, mul(-1.0, bv));
+        const double i1 = rsqrt(dot(c1, c1)), i2 = rsqrt(dot(c2, c2));
+        const double f = wuv * sw[kz] * z * an;
+        const double k1 = f * (DL ? i1 * i1 * i1 : i1), k2 = f * (DL ? z * i2 * i2 * i2 : i2);
+        Cx J0, J1, J2, H0, H1, H2;
+        if constexpr (DL) {
+            J0 = moment<1, 0, true>(k / i1), J1 = moment<2, 0, true>(k / i1), J2 = moment<3, 0, true>(k / i1);
+            H0 = moment<1, 0, true>(k / i2), H1 = moment<2, 0, true>(k / i2), H2 = moment<3, 0, true>(k / i2);
+        } else {
+            J0 = moment<2, 0, false>(k / i1), J1 = moment<3, 0, false>(k / i1), J2 = moment<4, 0, false>(k / i1);
+            H0 = moment<2, 0, false>(k / i2), H1 = moment<3, 0, false>(k / i2), H2 = moment<4, 0, false>(k / i2);
+        }
+        const L3 zbv{{-z, z * (1.0 - v), z * v}}, zbu{{-z, z * (1.0 - u), z * u}};
+        moment_acc(ar, ai, k1, al, bu, al, zbv, J0, J1, J2);    // x = P + s a(u), y = P + s z b(v)
+        moment_acc(ar, ai, k2, al, zbu, al, bvv, H0, H1, H2);   // x = P + s z a(u), y = P + s b(v)
+    }
+}
+
+template <int OP>
+__global__ __launch_bounds__(kNearThreads) void k_near_p1_helmholtz(const NearItem *__restrict__ items, int64_t n)
+{
+    if ((int64_t)blockIdx.x >= n) return;
+    const NearItem &it = items[blockIdx.x];
+    __shared__ double sx[kPts], sw[kPts];
+    __shared__ double red[18][kNearThreads];
+    const int t = threadIdx.x;
+    if (t < kPts) {
+        sx[t] = 0.5 * (c_x[t % kGL] + (double)(t / kGL));
+        sw[t] = 0.5 * c_w[t % kGL];
+    }
+    __syncthreads();
+    double ar[9], ai[9];
+#pragma unroll
+    for (int kk = 0; kk < 9; ++kk) ar[kk] = ai[kk] = 0.0;
+    pair_part_p1_helmholtz<OP>(it, sx, sw, ar, ai);
+#pragma unroll
+    for (int kk = 0; kk < 9; ++kk) {
+        red[2 * kk][t] = ar[kk];
+        red[2 * kk + 1][t] = ai[kk];
+    }
+    __syncthreads();
+    for (int h = kNearThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+#pragma unroll
+            for (int kk = 0; kk < 18; ++kk) red[kk][t] += red[kk][t + h];
+        __syncthreads();
+    }
+    if (t < 18) {
+        const double an = (OP == 3 && it.kind == 1) ? dot(sub(ld(it.v + 6), ld(it.v)), ld(it.ny)) : 1.0;
+        static_cast<double *>(it.out)[t] = red[t][0] * an * it.jt * it.js * kInv4PiD;
+    }
+}
+
 template <int OP>
 __global__ __launch_bounds__(kNearThreads) void k_near_p1(const NearItem *__restrict__ items, int64_t n)
 {
@@ -513,13 +717,31 @@ __global__ __launch_bounds__(kNearThreads) void k_near_slp_value(const NearItem 
 
 // Each record sums its sources (indices into the local values, times the
 // source's weight when wt is given) in order and adds the sum to its entry.
-template <bool FP32>
+template <bool FP32, bool CPLX>
 __global__ void k_near_gather(const NearGather *__restrict__ recs, int64_t n, const int32_t *__restrict__ src,
                               const double *__restrict__ wt, const double *__restrict__ local)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const NearGather g = recs[i];
+    if constexpr (CPLX) {   // complex local values (re, im) and entries
+        double sr = 0.0, si = 0.0;
+        for (int32_t k = 0; k < g.count; ++k) {
+            const int64_t q = 2 * (int64_t)src[g.first + k];
+            sr += local[q];
+            si += local[q + 1];
+        }
+        if constexpr (FP32) {
+            float *o = static_cast<float *>(g.out);
+            o[0] = (float)((double)o[0] + sr);
+            o[1] = (float)((double)o[1] + si);
+        } else {
+            double *o = static_cast<double *>(g.out);
+            o[0] = o[0] + sr;
+            o[1] = o[1] + si;
+        }
+        return;
+    }
     double s = 0.0;
     if (wt)
         for (int32_t k = 0; k < g.count; ++k) s += wt[g.first + k] * local[src[g.first + k]];
@@ -539,8 +761,12 @@ __global__ void k_near_gather(const NearGather *__restrict__ recs, int64_t n, co
 hipError_t launch_near_p1(int op, const NearItem *items, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (n > INT32_MAX || (op != 0 && op != 1 && op != BEM_LAPLACE_HYPS)) return hipErrorInvalidValue;
-    if (op == BEM_LAPLACE_HYPS)
+    if (n > INT32_MAX || op < 0 || (op > 3 && op != BEM_LAPLACE_HYPS)) return hipErrorInvalidValue;
+    if (op == 2)
+        hipLaunchKernelGGL((k_near_p1_helmholtz<2>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
+    else if (op == 3)
+        hipLaunchKernelGGL((k_near_p1_helmholtz<3>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
+    else if (op == BEM_LAPLACE_HYPS)
         hipLaunchKernelGGL(k_near_slp_value, dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
     else if (op == 0)
         hipLaunchKernelGGL((k_near_p1<0>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
@@ -549,16 +775,23 @@ hipError_t launch_near_p1(int op, const NearItem *items, int64_t n, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_near_gather(bool fp32, const NearGather *recs, int64_t n, const int32_t *src, const double *wt,
-                              const double *local, hipStream_t s)
+hipError_t launch_near_gather(bool fp32, bool cplx, const NearGather *recs, int64_t n, const int32_t *src,
+                              const double *wt, const double *local, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    if (fp32)
-        hipLaunchKernelGGL((k_near_gather<true>), dim3((unsigned)blocks), dim3(256), 0, s, recs, n, src, wt, local);
-    else
-        hipLaunchKernelGGL((k_near_gather<false>), dim3((unsigned)blocks), dim3(256), 0, s, recs, n, src, wt, local);
+    const dim3 grid((unsigned)blocks), block(256);
+    if (cplx) {
+        if (fp32)
+            hipLaunchKernelGGL((k_near_gather<true, true>), grid, block, 0, s, recs, n, src, wt, local);
+        else
+            hipLaunchKernelGGL((k_near_gather<false, true>), grid, block, 0, s, recs, n, src, wt, local);
+    } else if (fp32) {
+        hipLaunchKernelGGL((k_near_gather<true, false>), grid, block, 0, s, recs, n, src, wt, local);
+    } else {
+        hipLaunchKernelGGL((k_near_gather<false, false>), grid, block, 0, s, recs, n, src, wt, local);
+    }
     return hipGetLastError();
 }
 

@@ -427,7 +427,7 @@ public:
             size_t off = 0;
             NearP1Layout L{};
         };
-        P1Run p1_runs[6];
+        P1Run p1_runs[10];
         for (int i = 0; i < n; ++i)
             if (!take[i]->near_items.empty() && take[i]->space == BEM_P1) {
                 P1Run &g = p1_runs[near_p1_group(*take[i])];
@@ -445,10 +445,16 @@ public:
                 g.off = off;
                 off = align256(off + sizeof(NearItem) * (size_t)g.count);
             }
-        for (int gi = 0; gi < 6; ++gi)
+        // group 2 g + fp32 -> layout mode and kernel operator
+        auto p1_mode = [](int gi) { return (gi >> 1) == 2 ? 1 : ((gi >> 1) >= 3 ? 2 : 0); };
+        auto p1_op = [](int gi) {
+            const int g = gi >> 1;
+            return g == 2 ? (int)BEM_LAPLACE_HYPS : (g >= 3 ? g - 1 : g);
+        };
+        for (int gi = 0; gi < 10; ++gi)
             if (P1Run &g = p1_runs[gi]; g.items) {
                 g.off = off;
-                g.L = near_p1_layout(gi >= 4, g.items, g.recs, g.src);
+                g.L = near_p1_layout(p1_mode(gi), g.items, g.recs, g.src);
                 off = align256(off + g.L.bytes);
             }
         const size_t off_in = off;
@@ -557,10 +563,10 @@ public:
             if (near_runs[gi].count)
                 note(launch_near(gi >> 1, gi & 1, reinterpret_cast<const NearItem *>(db + near_runs[gi].off),
                                  near_runs[gi].count, stream));
-        for (int gi = 0; gi < 6; ++gi)
+        for (int gi = 0; gi < 10; ++gi)
             if (p1_runs[gi].items)
-                note(launch_near_p1_region(gi >= 4 ? BEM_LAPLACE_HYPS : gi >> 1, gi & 1, p1_runs[gi].L,
-                                           db + p1_runs[gi].off, p1_runs[gi].items, p1_runs[gi].recs, stream));
+                note(launch_near_p1_region(p1_op(gi), gi & 1, p1_runs[gi].L, db + p1_runs[gi].off, p1_runs[gi].items,
+                                           p1_runs[gi].recs, stream));
         b->ev_done = get_event();
         note(hipEventRecord(b->ev_done, stream));
         b->t_hip = now_seconds() - b->t_hip;

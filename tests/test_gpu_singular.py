@@ -87,8 +87,6 @@ def test_singular_policy_limits(ico2):
     xyz, tri, mesh, om = ico2
     idx = np.arange(5, dtype=np.int32)
     with pytest.raises(bem.BemError):
-        bem.eval_entries(mesh, bem.HELMHOLTZ_SLP, bem.P1, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
-    with pytest.raises(bem.BemError):
         bem.eval_entries(mesh, bem.HELMHOLTZ_HYPS, bem.P1, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
 
 
@@ -214,20 +212,26 @@ def test_served_singular_pairs_of_mixed_operators_and_precisions(ico2):
     print(f"{len(reqs)} requests in {st['batches']} batches")
 
 
-def p1_singular_reference(xyz, tri, om, op, rows, cols, level_hi=5):
+def p1_singular_reference(xyz, tri, om, op, rows, cols, level_hi=5, k=0.0, inner=2):
     """Singular part of P1 entries (rows x cols, vertex ids) from the oracle's
     P1 local matrices of every vertex-sharing triangle pair (levels
-    level_hi - 1 and level_hi extrapolated)."""
+    level_hi - 1 and level_hi extrapolated; Helmholtz remainder on 4^inner
+    sub-triangles, ~4e-8 at inner = 2)."""
     rows, cols = np.asarray(rows), np.asarray(cols)
     nt = tri.shape[0]
     rset, cset = set(rows.tolist()), set(cols.tolist())
     pairs = [(a, b) for a in range(nt) if rset & set(tri[a].tolist())
              for b in range(nt) if cset & set(tri[b].tolist()) and set(tri[a].tolist()) & set(tri[b].tolist())]
     pa, pb = np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs])
-    M = (4 * om.nearfield_p1_local(op, pa, pb, level_hi) - om.nearfield_p1_local(op, pa, pb, level_hi - 1)) / 3
+    if bem.is_complex(op):
+        kop = bem.HELMHOLTZ_DLP if op == bem.HELMHOLTZ_ADLP else op
+        M = (4 * om.nearfield_p1_local_c(kop, k, pa, pb, level_hi, inner) -
+             om.nearfield_p1_local_c(kop, k, pa, pb, level_hi - 1, inner)) / 3
+    else:
+        M = (4 * om.nearfield_p1_local(op, pa, pb, level_hi) - om.nearfield_p1_local(op, pa, pb, level_hi - 1)) / 3
     rpos = {v: i for i, v in enumerate(rows.tolist())}
     cpos = {v: i for i, v in enumerate(cols.tolist())}
-    S = np.zeros((rows.size, cols.size))
+    S = np.zeros((rows.size, cols.size), dtype=M.dtype)
     for t, (a, b) in enumerate(pairs):
         for i in range(3):
             for j in range(3):
@@ -388,3 +392,59 @@ def test_singular_edge_cases(ico2, space, op):
     assert np.array_equal(a, b)
     d = bem.eval_entries(mesh, op, space, k, base_r[:1], base_r[:1], prec=bem.FP64, near=bem.NEAR_SINGULAR)
     assert abs(d[0, 0] - ref[0, base_r[0]]) <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("op", [bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP])
+@pytest.mark.parametrize("kh", [0.6, 3.0])
+@pytest.mark.parametrize("prec,bound", [(bem.FP64, 1e-6), (bem.FP32, 2e-6)])
+def test_p1_helmholtz_singular_pairs_vs_oracle(ico2, op, kh, prec, bound):
+    """P1 Helmholtz at about 10 and 2 elements per wavelength: the singular
+    part against the oracle's complex P1 local matrices (levels 4 and 5
+    extrapolated); entries without vertex-sharing pairs bitwise those of
+    BEM_NEAR_SKIP."""
+    xyz, tri, mesh, om = ico2
+    nv = xyz.shape[0]
+    k = kh / inputs.mean_edge_length(xyz, tri)
+    rows = np.random.Generator(np.random.PCG64(24)).choice(nv, 3, replace=False).astype(np.int32)
+    cols = np.arange(nv, dtype=np.int32)
+    got = bem.eval_entries(mesh, op, bem.P1, k, rows, cols, prec=prec, near=bem.NEAR_SINGULAR)
+    skip = bem.eval_entries(mesh, op, bem.P1, k, rows, cols, prec=prec, near=bem.NEAR_SKIP)
+    ref = p1_singular_reference(xyz, tri, om, op, rows, cols, k=k)
+    near = ref != 0.0
+    assert np.array_equal(got[~near], skip[~near])
+    err = np.abs((got.astype(np.complex128) - skip) - ref)[near].max() / np.abs(ref).max()
+    print(f"P1 Helmholtz op {op} kh {kh} prec {prec}: {near.sum()} entries, max rel err {err:.2e}")
+    assert err <= bound
+
+
+def test_p1_helmholtz_singular_adjoint_is_transposed_double_layer(ico2):
+    xyz, tri, mesh, om = ico2
+    nv = xyz.shape[0]
+    rows = np.random.Generator(np.random.PCG64(25)).choice(nv, 10, replace=False).astype(np.int32)
+    cols = np.arange(nv, dtype=np.int32)
+    a = bem.eval_entries(mesh, bem.HELMHOLTZ_ADLP, bem.P1, 3.0, rows, cols, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    d = bem.eval_entries(mesh, bem.HELMHOLTZ_DLP, bem.P1, 3.0, cols, rows, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+    assert np.abs(a - d.T).max() <= 1e-14 * np.abs(d).max()
+
+
+@pytest.mark.parametrize("op", [bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP])
+def test_complete_p1_helmholtz_hmatrix_matvec(op):
+    """dense_mode 2, P1 Helmholtz (level-2 icosphere, kh = 1): against the
+    oracle's regular entries plus its complex P1 local matrices (levels 3 and
+    4 extrapolated: ~5e-7 single, ~2e-6 double layer)."""
+    xyz, tri = inputs.icosphere(2)
+    nv = xyz.shape[0]
+    k = 1.0 / inputs.mean_edge_length(xyz, tri)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    H = bem.hmat_assemble(mesh, op, bem.P1, k, leaf_size=16, eta=1.0, aca_tol=1e-8, max_rank=100, n_workers=4,
+                          blocks_per_worker=8, prec=bem.FP64, dense_mode=2)
+    idx = np.arange(nv, dtype=np.int32)
+    A = om.entries(op, O.P1, k, idx, idx, near=O.NEAR_SKIP) + p1_singular_reference(xyz, tri, om, op, idx, idx, 4, k)
+    rng = np.random.Generator(np.random.PCG64(6))
+    x = rng.normal(size=nv) + 1j * rng.normal(size=nv)
+    err = np.linalg.norm(H.matvec(x) - A @ x) / np.linalg.norm(A @ x)
+    print(H.stats(), err)
+    assert err <= 1e-5
+    H.destroy()
+    mesh.destroy()
