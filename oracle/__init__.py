@@ -269,7 +269,7 @@ class OracleMesh:
         st = _lib().orc_nearfield_p1_local_c(self._h, op, float(k), r.size, r.ctypes.data_as(p64),
                                              c.ctypes.data_as(p64), level, inner_level, _d(out))
         if st != 0:
-            raise ValueError("Helmholtz single or double layer and levels >= 0")
+            raise ValueError("Helmholtz single, double layer or hypersingular operator and levels >= 0")
         return out.view(np.complex128).reshape(r.size, 3, 3)
 
     def p0_matrix_with_nearfield(self, op: int, near_dist: float, level: int = 3) -> np.ndarray:

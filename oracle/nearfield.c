@@ -42,6 +42,9 @@ int orc_subdivided_rule(int level, double *xi, double *eta, double *w);
 static double nf_entry(const orc_mesh *m, int op, int64_t i, int64_t j, int npts, const double *xi,
                        const double *eta, const double *w);
 static void nf_remainder(int dlp, double z, double *re, double *im);
+static void nfc_entry(const orc_mesh *m, int op, double k, int64_t i, int64_t j, int npts, const double *xi,
+                      const double *eta, const double *w, int nin, const double *ixi, const double *ieta,
+                      const double *iw, double *re, double *im);
 
 static void sub3(const double *a, const double *b, double *o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -357,12 +360,17 @@ static void nf_p1_local_c(const orc_mesh *m, int op, double k, int64_t i, int64_
 }
 
 /* Complex P1 local matrices of n pairs, Helmholtz single (op 2) or double
- * (op 3) layer: outer rule on 4^level, remainder on 4^inner_level
- * sub-triangles; out holds n row-major 3 x 3 complex (18 doubles). */
+ * (op 3) layer, or the Helmholtz hypersingular operator (op 7, Eq.
+ * hypsHelmholtz: curl_a . curl_b times the pair's P0 single-layer value minus
+ * k^2 (n_x . n_y) times its P1 single-layer local matrix): outer rule on
+ * 4^level, remainder on 4^inner_level sub-triangles; out holds n row-major
+ * 3 x 3 complex (18 doubles). */
 int orc_nearfield_p1_local_c(const orc_mesh *m, int op, double k, int64_t n, const int64_t *rows,
                              const int64_t *cols, int level, int inner_level, double *out)
 {
-    if ((op != ORC_HELMHOLTZ_SLP && op != ORC_HELMHOLTZ_DLP) || level < 0 || inner_level < 0) return ORC_E_ARG;
+    if ((op != ORC_HELMHOLTZ_SLP && op != ORC_HELMHOLTZ_DLP && op != ORC_HELMHOLTZ_HYPS) || level < 0 ||
+        inner_level < 0)
+        return ORC_E_ARG;
     int np = 6, ni = 6;
     for (int l = 0; l < level; ++l) np *= 4;
     for (int l = 0; l < inner_level; ++l) ni *= 4;
@@ -373,8 +381,27 @@ int orc_nearfield_p1_local_c(const orc_mesh *m, int op, double k, int64_t n, con
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1)
 #endif
-    for (int64_t t = 0; t < n; ++t)
-        nf_p1_local_c(m, op, k, rows[t], cols[t], np, xi, eta, w, ni, ixi, ieta, iw, out + 18 * t);
+    for (int64_t t = 0; t < n; ++t) {
+        if (op != ORC_HELMHOLTZ_HYPS) {
+            nf_p1_local_c(m, op, k, rows[t], cols[t], np, xi, eta, w, ni, ixi, ieta, iw, out + 18 * t);
+            continue;
+        }
+        double *M = out + 18 * t, v[2];
+        nf_p1_local_c(m, ORC_HELMHOLTZ_SLP, k, rows[t], cols[t], np, xi, eta, w, ni, ixi, ieta, iw, M);
+        nfc_entry(m, ORC_HELMHOLTZ_SLP, k, rows[t], cols[t], np, xi, eta, w, ni, ixi, ieta, iw, v, v + 1);
+        const double *na = m->n + 3 * rows[t], *nb = m->n + 3 * cols[t];
+        const double nn = na[0] * nb[0] + na[1] * nb[1] + na[2] * nb[2];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double ca[3], cb[3];
+                orc_curl(m, rows[t], a, ca);
+                orc_curl(m, cols[t], b, cb);
+                const double cc = ca[0] * cb[0] + ca[1] * cb[1] + ca[2] * cb[2];
+                double *e = M + 2 * (3 * a + b);
+                e[0] = cc * v[0] - k * k * nn * e[0];
+                e[1] = cc * v[1] - k * k * nn * e[1];
+            }
+    }
     free(xi);
     return ORC_OK;
 }

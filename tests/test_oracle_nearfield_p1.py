@@ -251,3 +251,35 @@ def test_helmholtz_p1_adjacent_pairs(ico2, op):
     M0 = om.nearfield_p1_local_c(op, 1e-7, [0] * len(adj), adj, 2, 2)
     L = om.nearfield_p1_local(op - 2, [0] * len(adj), adj, 2)
     assert np.abs(M0.real - L).max() <= 1e-12 * np.abs(L).max()
+
+
+def test_helmholtz_hypersingular_sphere_linear_functions():
+    """Helmholtz hypersingular operator (Eq. hypsHelmholtz) on the unit
+    sphere: the degree-1 spherical harmonics are eigenfunctions with
+    eigenvalue -i k^3 j_1'(k) h_1'(k) (spherical Bessel and Hankel functions;
+    2/3 as k -> 0), so the complete P1 matrix D satisfies D x ~ mu M x with an
+    O(h^2) error."""
+    from scipy.special import spherical_jn, spherical_yn
+    k = 1.5
+    jp = spherical_jn(1, k, derivative=True)
+    mu = -1j * k ** 3 * jp * (jp + 1j * spherical_yn(1, k, derivative=True))
+    errs = []
+    for level in (2, 3):
+        xyz, tri = inputs.icosphere(level)
+        om = O.OracleMesh(xyz, tri, 6)
+        nv, nt = xyz.shape[0], tri.shape[0]
+        idx = np.arange(nv, dtype=np.int32)
+        D = om.entries(O.HELMHOLTZ_HYPS, O.P1, k, idx, idx, near=O.NEAR_SKIP)
+        rows, cols = np.nonzero(np.array([[bool(set(tri[a]) & set(tri[b])) for b in range(nt)] for a in range(nt)]))
+        M = (4 * om.nearfield_p1_local_c(O.HELMHOLTZ_HYPS, k, rows, cols, 3, 2) -
+             om.nearfield_p1_local_c(O.HELMHOLTZ_HYPS, k, rows, cols, 2, 2)) / 3
+        for t, (i, j) in enumerate(zip(rows, cols)):
+            D[np.ix_(tri[i], tri[j])] += M[t]
+        area = 0.5 * np.linalg.norm(np.cross(xyz[tri[:, 1]] - xyz[tri[:, 0]], xyz[tri[:, 2]] - xyz[tri[:, 0]]), axis=1)
+        mass = np.zeros((nv, nv))
+        for t in range(nt):
+            mass[np.ix_(tri[t], tri[t])] += area[t] / 12.0 * (np.ones((3, 3)) + np.eye(3))
+        u = xyz[:, 0]
+        errs.append(np.linalg.norm(D @ u - mu * (mass @ u)) / np.linalg.norm(mu * (mass @ u)))
+    assert errs[-1] < 1e-2
+    assert 3.0 < errs[0] / errs[1] < 5.0
