@@ -100,9 +100,8 @@ typedef enum { BEM_FP64 = 0, BEM_FP32 = 1 } bem_prec;
  * rule; P1: each pair's 3 x 3 local matrix, then a fixed-order sum per
  * entry; the Laplace hypersingular operator: the hat functions' constant
  * curls times each pair's P0 single-layer integral).  BEM_NEAR_SINGULAR is
- * available for the single, double and adjoint double layer (Laplace and
- * Helmholtz, P0 and P1) and the Laplace hypersingular operator (BEM_E_ARG for
- * the Helmholtz hypersingular operator). */
+ * available for every operator and space (the hypersingular operator: P1
+ * only, as everywhere). */
 typedef enum { BEM_NEAR_ERROR = 0, BEM_NEAR_SKIP = 1, BEM_NEAR_SINGULAR = 2 } bem_near;
 
 typedef struct bem_mesh bem_mesh;
@@ -304,9 +303,7 @@ typedef struct {
     int32_t blocks_per_worker; /* ACA blocks each worker keeps in flight */
     bem_prec prec;          /* precision of the device entries */
     int32_t dense_mode;     /* 0: dense leaves left empty; 1: their regular part (BEM_NEAR_SKIP);
-                               2: complete, singular pairs included (BEM_NEAR_SINGULAR: single,
-                               double and adjoint double layer, Laplace and Helmholtz, P0 and
-                               P1; Laplace hypersingular; else BEM_E_ARG) */
+                               2: complete, singular pairs included (BEM_NEAR_SINGULAR) */
 } bem_hmat_params;
 
 /* Fill every admissible leaf of the block tree by ACA (all rows and columns

@@ -144,8 +144,10 @@ struct NearP1Layout {
     int src_per;   // gather source units per pair (9 values, 9 complex values, or 1)
     bool weighted, cplx;
 };
-// mode: 0 real 3 x 3 local matrices, 1 hypersingular (one value per pair,
-// weighted sources), 2 complex 3 x 3 local matrices
+// mode: 0 real 3 x 3 local matrices, 1 Laplace hypersingular (one value per
+// pair, weighted sources), 2 complex 3 x 3 local matrices, 3 Helmholtz
+// hypersingular (complex 3 x 3 single-layer local matrix and P0 value,
+// weighted sources)
 NearP1Layout near_p1_layout(int mode, int64_t items, int64_t recs, int64_t src);
 int near_p1_mode(const Request &r);
 NearP1Layout near_p1_layout(const Request &r);
@@ -159,9 +161,9 @@ void stage_near_p1(const Request &r, const NearP1Layout &L, char *host, char *de
 // gather into the entries).
 hipError_t launch_near_p1_region(int op, bool fp32, const NearP1Layout &L, char *dev, int64_t items, int64_t recs,
                                  hipStream_t s);
-// Index of the P1 singular run of a request (kernel and precision), 0..9:
+// Index of the P1 singular run of a request (kernel and precision), 0..11:
 // 2 g + fp32 with g = 0 single, 1 double layer, 2 hypersingular (Laplace),
-// 3 single, 4 double layer (Helmholtz).
+// 3 single, 4 double layer, 5 hypersingular (Helmholtz).
 int near_p1_group(const Request &r);
 
 hipError_t launch_near(int op, bool fp32, const NearItem *items, int64_t n, hipStream_t s);

@@ -268,7 +268,8 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     Variant v{kernel_op(r.op), r.space, r.prec, mesh->q};
     BEM_HIP_TRY(launch_entries(v, dreq, (const EntryBlock *)(ws + off_b), r.nblocks, s));
     if (p1_near)
-        BEM_HIP_TRY(launch_near_p1_region(r.op == BEM_LAPLACE_HYPS ? (int)BEM_LAPLACE_HYPS : kernel_op(r.op),
+        BEM_HIP_TRY(launch_near_p1_region(r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS ? (int)r.op
+                                                                                                : kernel_op(r.op),
                                           r.prec == BEM_FP32, near_p1_layout(r), ws + off_near,
                                           (int64_t)r.near_items.size(), (int64_t)r.near_recs.size(), s));
     else

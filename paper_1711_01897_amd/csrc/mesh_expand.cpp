@@ -314,7 +314,7 @@ void build_near_items_p1(Request &r)
     const bem_mesh &m = *r.mesh;
     const bool adj = is_adjoint_op(r.op);
     const bool dlp = kernel_op(r.op) == BEM_LAPLACE_DLP || kernel_op(r.op) == BEM_HELMHOLTZ_DLP;
-    const bool hyps = r.op == BEM_LAPLACE_HYPS;
+    const bool hyps = r.op == BEM_LAPLACE_HYPS, hhyps = r.op == BEM_HELMHOLTZ_HYPS;
     std::vector<std::pair<int32_t, int64_t>> rowpos((size_t)r.nrows), colpos((size_t)r.ncols);
     for (int64_t i = 0; i < r.nrows; ++i) rowpos[i] = {r.rows[i], i};
     for (int64_t i = 0; i < r.ncols; ++i) colpos[i] = {r.cols[i], i};
@@ -397,7 +397,8 @@ void build_near_items_p1(Request &r)
             NearItem q{};
             q.k = is_complex_op(r.op) ? r.k : 0.0;
             int32_t tl[3], sl[3];   // global vertices in the kernel's local orders
-            q.jt = cross_len(T, nullptr);
+            double nt[3];
+            q.jt = cross_len(T, nt);
             q.js = cross_len(S, q.ny);
             if (shared == 3) {
                 q.kind = 0;
@@ -430,24 +431,34 @@ void build_near_items_p1(Request &r)
                 for (int j = 0; j < 3; ++j) {
                     const int32_t rv = adj ? sl[j] : tl[i], cv = adj ? tl[i] : sl[j];
                     double w = 1.0;
-                    if (hyps) {
+                    if (hyps || hhyps) {
                         double ct[3], cs[3];
                         curl(T, tl[i], ct);
                         curl(S, sl[j], cs);
                         w = ct[0] * cs[0] + ct[1] * cs[1] + ct[2] * cs[2];
                     }
+                    // Helmholtz hypersingular: curl products times the P0 value (source 9 of the pair)
+                    // minus k^2 n_x . n_y times the single layer's local matrix
+                    const double wn = -r.k * r.k * (nt[0] * q.ny[0] + nt[1] * q.ny[1] + nt[2] * q.ny[2]);
                     for (auto ri = first_of(rowpos, rv); ri != rowpos.end() && ri->first == rv; ++ri)
-                        for (auto ci = first_of(colpos, cv); ci != colpos.end() && ci->first == cv; ++ci)
-                            contrib.push_back({ri->second * r.ncols + ci->second, hyps ? pi : pi * 9 + 3 * i + j, w});
+                        for (auto ci = first_of(colpos, cv); ci != colpos.end() && ci->first == cv; ++ci) {
+                            const int64_t e = ri->second * r.ncols + ci->second;
+                            if (hhyps) {
+                                contrib.push_back({e, pi * 10 + 9, w});
+                                contrib.push_back({e, pi * 10 + 3 * i + j, wn});
+                            } else {
+                                contrib.push_back({e, hyps ? pi : pi * 9 + 3 * i + j, w});
+                            }
+                        }
                 }
         }
     }
     std::sort(contrib.begin(), contrib.end());
     r.near_src.resize(contrib.size());
-    if (hyps) r.near_wt.resize(contrib.size());
+    if (hyps || hhyps) r.near_wt.resize(contrib.size());
     for (size_t k = 0; k < contrib.size(); ++k) {
         r.near_src[k] = contrib[k].src;
-        if (hyps) r.near_wt[k] = contrib[k].wt;
+        if (hyps || hhyps) r.near_wt[k] = contrib[k].wt;
         if (k == 0 || contrib[k].entry != contrib[k - 1].entry)
             r.near_recs.push_back({contrib[k].entry, (int32_t)k, 0});
         ++r.near_recs.back().count;
@@ -460,22 +471,24 @@ static size_t align256_sz(size_t x) { return (x + 255) & ~(size_t)255; }
 
 NearP1Layout near_p1_layout(int mode, int64_t items, int64_t recs, int64_t src)
 {
-    const bool hyps = mode == 1;
     NearP1Layout L;
-    L.per = hyps ? 1 : (mode == 2 ? 18 : 9);
-    L.src_per = hyps ? 1 : 9;
-    L.weighted = hyps;
-    L.cplx = mode == 2;
+    L.per = mode == 1 ? 1 : (mode == 2 ? 18 : (mode == 3 ? 20 : 9));
+    L.src_per = mode == 1 ? 1 : (mode == 3 ? 10 : 9);
+    L.weighted = mode == 1 || mode == 3;
+    L.cplx = mode >= 2;
     L.items = 0;
     L.recs = align256_sz(sizeof(NearItem) * (size_t)items);
     L.src = L.recs + align256_sz(sizeof(NearGather) * (size_t)recs);
     L.wt = L.src + align256_sz(sizeof(int32_t) * (size_t)src);
-    L.local = L.wt + (hyps ? align256_sz(sizeof(double) * (size_t)src) : 0);
+    L.local = L.wt + (L.weighted ? align256_sz(sizeof(double) * (size_t)src) : 0);
     L.bytes = L.local + align256_sz(L.per * sizeof(double) * (size_t)items);
     return L;
 }
 
-int near_p1_mode(const Request &r) { return r.op == BEM_LAPLACE_HYPS ? 1 : (is_complex_op(r.op) ? 2 : 0); }
+int near_p1_mode(const Request &r)
+{
+    return r.op == BEM_LAPLACE_HYPS ? 1 : (r.op == BEM_HELMHOLTZ_HYPS ? 3 : (is_complex_op(r.op) ? 2 : 0));
+}
 
 NearP1Layout near_p1_layout(const Request &r)
 {
@@ -486,7 +499,11 @@ NearP1Layout near_p1_layout(const Request &r)
 int near_p1_group(const Request &r)
 {
     const int kop = kernel_op(r.op);
-    const int g = r.op == BEM_LAPLACE_HYPS ? 2 : (kop == BEM_HELMHOLTZ_SLP ? 3 : (kop == BEM_HELMHOLTZ_DLP ? 4 : kop));
+    const int g = r.op == BEM_LAPLACE_HYPS   ? 2
+                : r.op == BEM_HELMHOLTZ_HYPS ? 5
+                : kop == BEM_HELMHOLTZ_SLP   ? 3
+                : kop == BEM_HELMHOLTZ_DLP   ? 4
+                                             : kop;
     return 2 * g + (r.prec == BEM_FP32 ? 1 : 0);
 }
 
@@ -529,9 +546,6 @@ int expand_request(Request &r)
     if (r.prec != BEM_FP32 && r.prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
     if (r.near != BEM_NEAR_ERROR && r.near != BEM_NEAR_SKIP && r.near != BEM_NEAR_SINGULAR)
         return fail(BEM_E_ARG, "unknown near-field policy");
-    if (r.near == BEM_NEAR_SINGULAR && r.op == BEM_HELMHOLTZ_HYPS)
-        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR is available for the single, double and adjoint double layer "
-                               "and the Laplace hypersingular operator");
     if (is_complex_op(r.op)) {
         if (!(std::isfinite(r.k) && r.k > 0.0)) return fail(BEM_E_ARG, "Helmholtz needs a finite wavenumber k > 0");
     } else if (r.k != 0.0) {

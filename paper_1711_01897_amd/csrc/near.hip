@@ -1,7 +1,7 @@
 // Singular (vertex-sharing) triangle pairs on the device: the Laplace and
 // Helmholtz single and double layer, P0 and P1 (P1: 3 x 3 local matrices,
-// summed into the entries by a fixed-order gather), and the P1 Laplace
-// hypersingular operator.
+// summed into the entries by a fixed-order gather), and the P1 Laplace and
+// Helmholtz hypersingular operator.
 //
 // The regular kernels integrate vertex-disjoint pairs only; Section 3.2.3
 // gives identical, edge-adjacent and vertex-adjacent pairs to a separate
@@ -636,7 +636,9 @@ __device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, con
     }
 }
 
-template <int OP>
+// WITH_P0 (the Helmholtz hypersingular operator): the pair's P0 single-layer
+// value follows the 9 complex local-matrix values (20 doubles per pair).
+template <int OP, bool WITH_P0>
 __global__ __launch_bounds__(kNearThreads) void k_near_p1_helmholtz(const NearItem *__restrict__ items, int64_t n)
 {
     if ((int64_t)blockIdx.x >= n) return;
@@ -668,6 +670,13 @@ __global__ __launch_bounds__(kNearThreads) void k_near_p1_helmholtz(const NearIt
     if (t < 18) {
         const double an = (OP == 3 && it.kind == 1) ? dot(sub(ld(it.v + 6), ld(it.v)), ld(it.ny)) : 1.0;
         static_cast<double *>(it.out)[t] = red[t][0] * an * it.jt * it.js * kInv4PiD;
+    }
+    if constexpr (WITH_P0) {
+        const Cx v = pair_value<2>(it);
+        if (t == 0) {
+            static_cast<double *>(it.out)[18] = v.re;
+            static_cast<double *>(it.out)[19] = v.im;
+        }
     }
 }
 
@@ -728,8 +737,9 @@ __global__ void k_near_gather(const NearGather *__restrict__ recs, int64_t n, co
         double sr = 0.0, si = 0.0;
         for (int32_t k = 0; k < g.count; ++k) {
             const int64_t q = 2 * (int64_t)src[g.first + k];
-            sr += local[q];
-            si += local[q + 1];
+            const double w = wt ? wt[g.first + k] : 1.0;
+            sr += w * local[q];
+            si += w * local[q + 1];
         }
         if constexpr (FP32) {
             float *o = static_cast<float *>(g.out);
@@ -761,11 +771,14 @@ __global__ void k_near_gather(const NearGather *__restrict__ recs, int64_t n, co
 hipError_t launch_near_p1(int op, const NearItem *items, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    if (n > INT32_MAX || op < 0 || (op > 3 && op != BEM_LAPLACE_HYPS)) return hipErrorInvalidValue;
+    if (n > INT32_MAX || op < 0 || (op > 3 && op != BEM_LAPLACE_HYPS && op != BEM_HELMHOLTZ_HYPS))
+        return hipErrorInvalidValue;
     if (op == 2)
-        hipLaunchKernelGGL((k_near_p1_helmholtz<2>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
+        hipLaunchKernelGGL((k_near_p1_helmholtz<2, false>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
     else if (op == 3)
-        hipLaunchKernelGGL((k_near_p1_helmholtz<3>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
+        hipLaunchKernelGGL((k_near_p1_helmholtz<3, false>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
+    else if (op == BEM_HELMHOLTZ_HYPS)
+        hipLaunchKernelGGL((k_near_p1_helmholtz<2, true>), dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
     else if (op == BEM_LAPLACE_HYPS)
         hipLaunchKernelGGL(k_near_slp_value, dim3((unsigned)n), dim3(kNearThreads), 0, s, items, n);
     else if (op == 0)

@@ -427,7 +427,7 @@ public:
             size_t off = 0;
             NearP1Layout L{};
         };
-        P1Run p1_runs[10];
+        P1Run p1_runs[12];
         for (int i = 0; i < n; ++i)
             if (!take[i]->near_items.empty() && take[i]->space == BEM_P1) {
                 P1Run &g = p1_runs[near_p1_group(*take[i])];
@@ -446,12 +446,15 @@ public:
                 off = align256(off + sizeof(NearItem) * (size_t)g.count);
             }
         // group 2 g + fp32 -> layout mode and kernel operator
-        auto p1_mode = [](int gi) { return (gi >> 1) == 2 ? 1 : ((gi >> 1) >= 3 ? 2 : 0); };
+        auto p1_mode = [](int gi) {
+            const int g = gi >> 1;
+            return g == 2 ? 1 : (g == 5 ? 3 : (g >= 3 ? 2 : 0));
+        };
         auto p1_op = [](int gi) {
             const int g = gi >> 1;
-            return g == 2 ? (int)BEM_LAPLACE_HYPS : (g >= 3 ? g - 1 : g);
+            return g == 2 ? (int)BEM_LAPLACE_HYPS : (g == 5 ? (int)BEM_HELMHOLTZ_HYPS : (g >= 3 ? g - 1 : g));
         };
-        for (int gi = 0; gi < 10; ++gi)
+        for (int gi = 0; gi < 12; ++gi)
             if (P1Run &g = p1_runs[gi]; g.items) {
                 g.off = off;
                 g.L = near_p1_layout(p1_mode(gi), g.items, g.recs, g.src);
@@ -563,7 +566,7 @@ public:
             if (near_runs[gi].count)
                 note(launch_near(gi >> 1, gi & 1, reinterpret_cast<const NearItem *>(db + near_runs[gi].off),
                                  near_runs[gi].count, stream));
-        for (int gi = 0; gi < 10; ++gi)
+        for (int gi = 0; gi < 12; ++gi)
             if (p1_runs[gi].items)
                 note(launch_near_p1_region(p1_op(gi), gi & 1, p1_runs[gi].L, db + p1_runs[gi].off, p1_runs[gi].items,
                                            p1_runs[gi].recs, stream));

@@ -87,7 +87,7 @@ def test_singular_policy_limits(ico2):
     xyz, tri, mesh, om = ico2
     idx = np.arange(5, dtype=np.int32)
     with pytest.raises(bem.BemError):
-        bem.eval_entries(mesh, bem.HELMHOLTZ_HYPS, bem.P1, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
+        bem.eval_entries(mesh, bem.HELMHOLTZ_HYPS, bem.P0, 2.0, idx, idx, near=bem.NEAR_SINGULAR)
 
 
 @pytest.mark.parametrize("op", [bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP])
@@ -224,7 +224,7 @@ def p1_singular_reference(xyz, tri, om, op, rows, cols, level_hi=5, k=0.0, inner
              for b in range(nt) if cset & set(tri[b].tolist()) and set(tri[a].tolist()) & set(tri[b].tolist())]
     pa, pb = np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs])
     if bem.is_complex(op):
-        kop = bem.HELMHOLTZ_DLP if op == bem.HELMHOLTZ_ADLP else op
+        kop = bem.HELMHOLTZ_DLP if op == bem.HELMHOLTZ_ADLP else op   # (the oracle's op 7 is the hypersingular)
         M = (4 * om.nearfield_p1_local_c(kop, k, pa, pb, level_hi, inner) -
              om.nearfield_p1_local_c(kop, k, pa, pb, level_hi - 1, inner)) / 3
     else:
@@ -446,5 +446,51 @@ def test_complete_p1_helmholtz_hmatrix_matvec(op):
     err = np.linalg.norm(H.matvec(x) - A @ x) / np.linalg.norm(A @ x)
     print(H.stats(), err)
     assert err <= 1e-5
+    H.destroy()
+    mesh.destroy()
+
+
+@pytest.mark.parametrize("prec,bound", [(bem.FP64, 1e-6), (bem.FP32, 1e-5)])
+def test_p1_helmholtz_hypersingular_singular_pairs_vs_oracle(ico2, prec, bound):
+    """Helmholtz hypersingular operator, P1 (kh = 1): the singular part
+    (curl products times the P0 single-layer value minus k^2 n_x . n_y times
+    the P1 single-layer local matrix) against the oracle's local matrices."""
+    xyz, tri, mesh, om = ico2
+    nv = xyz.shape[0]
+    k = 1.0 / inputs.mean_edge_length(xyz, tri)
+    rows = np.random.Generator(np.random.PCG64(26)).choice(nv, 3, replace=False).astype(np.int32)
+    cols = np.arange(nv, dtype=np.int32)
+    got = bem.eval_entries(mesh, bem.HELMHOLTZ_HYPS, bem.P1, k, rows, cols, prec=prec, near=bem.NEAR_SINGULAR)
+    skip = bem.eval_entries(mesh, bem.HELMHOLTZ_HYPS, bem.P1, k, rows, cols, prec=prec, near=bem.NEAR_SKIP)
+    ref = p1_singular_reference(xyz, tri, om, bem.HELMHOLTZ_HYPS, rows, cols, k=k)
+    near = ref != 0.0
+    assert np.array_equal(got[~near], skip[~near])
+    err = np.abs((got.astype(np.complex128) - skip) - ref)[near].max() / np.abs(ref).max()
+    print(f"P1 Helmholtz hypersingular prec {prec}: {near.sum()} entries, max rel err {err:.2e}")
+    assert err <= bound
+
+
+def test_complete_helmholtz_hypersingular_hmatrix_on_the_sphere():
+    """dense_mode 2, Helmholtz hypersingular operator (level-3 icosphere,
+    k = 1.5, FP64): the unit sphere's degree-1 eigenvalue
+    -i k^3 j_1'(k) h_1'(k): D x ~ mu M x (O(h^2), 6.2e-3 here)."""
+    from scipy.special import spherical_jn, spherical_yn
+    k = 1.5
+    jp = spherical_jn(1, k, derivative=True)
+    mu = -1j * k ** 3 * jp * (jp + 1j * spherical_yn(1, k, derivative=True))
+    xyz, tri = inputs.icosphere(3)
+    nv, nt = xyz.shape[0], tri.shape[0]
+    mesh = bem.mesh_create(xyz, tri, 6)
+    H = bem.hmat_assemble(mesh, bem.HELMHOLTZ_HYPS, bem.P1, k, leaf_size=32, eta=1.0, aca_tol=1e-8, max_rank=100,
+                          n_workers=4, blocks_per_worker=8, prec=bem.FP64, dense_mode=2)
+    u = xyz[:, 0].astype(np.complex128)
+    Du = H.matvec(u)
+    area = 0.5 * np.linalg.norm(np.cross(xyz[tri[:, 1]] - xyz[tri[:, 0]], xyz[tri[:, 2]] - xyz[tri[:, 0]]), axis=1)
+    Mu = np.zeros(nv, dtype=np.complex128)
+    for t in range(nt):
+        Mu[tri[t]] += area[t] / 12.0 * (np.ones((3, 3)) + np.eye(3)) @ u[tri[t]]
+    eig = np.linalg.norm(Du - mu * Mu) / np.linalg.norm(mu * Mu)
+    print(H.stats(), f"sphere eigenvalue residual {eig:.2e}")
+    assert eig <= 1e-2
     H.destroy()
     mesh.destroy()
