@@ -76,9 +76,10 @@ def parse():
                     help="instead of the ACA workload: complete P0 H-matrices (dense leaves with their singular "
                          "pairs) on the icosphere of this level, FP64")
     ap.add_argument("--complete-op", default="laplace_slp",
-                    choices=["laplace_slp", "laplace_dlp", "helmholtz_slp", "helmholtz_dlp", "laplace_hyps"],
+                    choices=["laplace_slp", "laplace_dlp", "helmholtz_slp", "helmholtz_dlp", "laplace_hyps",
+                             "helmholtz_hyps"],
                     help="operator of --complete (Helmholtz at 10 elements per wavelength; the hypersingular "
-                         "operator with --complete-space p1)")
+                         "operators with --complete-space p1)")
     ap.add_argument("--complete-space", default="p0", choices=["p0", "p1"],
                     help="space of --complete (P1: Laplace operators)")
     ap.add_argument("--concurrent", type=int, default=0,
@@ -378,7 +379,8 @@ def complete_main(args):
     mesh = bem.mesh_create(xyz, tri, 6)
     nt = tri.shape[0]
     op = {"laplace_slp": bem.LAPLACE_SLP, "laplace_dlp": bem.LAPLACE_DLP, "helmholtz_slp": bem.HELMHOLTZ_SLP,
-          "helmholtz_dlp": bem.HELMHOLTZ_DLP, "laplace_hyps": bem.LAPLACE_HYPS}[args.complete_op]
+          "helmholtz_dlp": bem.HELMHOLTZ_DLP, "laplace_hyps": bem.LAPLACE_HYPS,
+          "helmholtz_hyps": bem.HELMHOLTZ_HYPS}[args.complete_op]
     k = inputs.wavenumber(xyz, tri, 10.0) if bem.is_complex(op) else 0.0
     space = bem.P1 if args.complete_space == "p1" else bem.P0
 
@@ -414,7 +416,8 @@ def complete_main(args):
         if (op == bem.LAPLACE_SLP and space == bem.P0) else None
     label = {bem.LAPLACE_SLP: "Laplace single layer", bem.LAPLACE_DLP: "Laplace double layer",
              bem.HELMHOLTZ_SLP: "Helmholtz single layer", bem.HELMHOLTZ_DLP: "Helmholtz double layer",
-             bem.LAPLACE_HYPS: "Laplace hypersingular operator"}[op]
+             bem.LAPLACE_HYPS: "Laplace hypersingular operator",
+             bem.HELMHOLTZ_HYPS: "Helmholtz hypersingular operator"}[op]
     line = {
         "metric": f"complete H-matrix assembly seconds ({args.complete_space.upper()} {label}, FP64)",
         "value": t2, "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
