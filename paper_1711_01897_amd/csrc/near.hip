@@ -504,6 +504,51 @@ __device__ void pair_part_p1(const NearItem &it, const double *sx, const double 
     }
 }
 
+// The three series J_m = int rho^(A0 + m) (1 - rho)^B e^{i om rho} (...)
+// (m = 0, 1, 2) evaluated together from a coefficient table staged in LDS
+// (interleaved re/im of the three per power of om^2): literal FP64
+// coefficients would otherwise be held in registers across the face loops.
+template <int A0, int B, bool DL>
+struct MomentTable3 {
+    double v[6 * (kSeries / 2)];
+    constexpr MomentTable3() : v()
+    {
+        const MomentSeries<A0, B, DL> s0{};
+        const MomentSeries<A0 + 1, B, DL> s1{};
+        const MomentSeries<A0 + 2, B, DL> s2{};
+        for (int m = 0; m < kSeries / 2; ++m) {
+            v[6 * m] = s0.re[m], v[6 * m + 1] = s0.im[m];
+            v[6 * m + 2] = s1.re[m], v[6 * m + 3] = s1.im[m];
+            v[6 * m + 4] = s2.re[m], v[6 * m + 5] = s2.im[m];
+        }
+    }
+};
+constexpr int kTab3 = 6 * (kSeries / 2);
+__constant__ MomentTable3<2, 0, false> c_tab_s20{};   // identical and common-vertex single layer
+__constant__ MomentTable3<1, 1, false> c_tab_s11{};   // common-edge single layer
+__constant__ MomentTable3<1, 0, true> c_tab_d10{};    // common-vertex double layer
+__constant__ MomentTable3<0, 1, true> c_tab_d01{};    // common-edge double layer
+
+__device__ __forceinline__ void moment3(double om, const double *tab, Cx &J0, Cx &J1, Cx &J2)
+{
+    const double w2 = om * om;
+    const double *t = tab + 6 * (kSeries / 2 - 1);
+    double r0 = t[0], i0 = t[1], r1 = t[2], i1 = t[3], r2 = t[4], i2 = t[5];
+#pragma unroll 4
+    for (int m = kSeries / 2 - 2; m >= 0; --m) {
+        t = tab + 6 * m;
+        r0 = fma(r0, w2, t[0]);
+        i0 = fma(i0, w2, t[1]);
+        r1 = fma(r1, w2, t[2]);
+        i1 = fma(i1, w2, t[3]);
+        r2 = fma(r2, w2, t[4]);
+        i2 = fma(i2, w2, t[5]);
+    }
+    J0 = {r0, om * i0};
+    J1 = {r1, om * i1};
+    J2 = {r2, om * i2};
+}
+
 // acc[3a + b] += K (alpha_a gamma_b J0 + (alpha_a delta_b + beta_a gamma_b) J1
 // + beta_a delta_b J2): the radial integral of (alpha + beta rho)(gamma +
 // delta rho) against the moments J_m (complex), times K.
@@ -526,9 +571,11 @@ __device__ __forceinline__ void moment_acc(double *ar, double *ai, double K, con
 // alpha + beta rho (test) and gamma + delta rho (trial), and the radial
 // integrals are three moment series (identical pairs: the radius xi, the
 // moments at omega eta1 eta2, eta1 and eta2 on the 8-point rule).
+// tr: the radial table of identical and common-vertex pairs, te: of
+// common-edge pairs (both in LDS).
 template <int OP>
-__device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, const double *sw, double *ar,
-                                       double *ai)
+__device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, const double *sw, const double *tr,
+                                       const double *te, double *ar, double *ai)
 {
     constexpr bool DL = OP == 3;
     const int t = threadIdx.x;
@@ -543,7 +590,11 @@ __device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, con
         const V3 c = line == 0 ? fma3(e3, E1, E2) : (line == 1 ? fma3(e3, E2, E1) : fma3(-e3, E1, mul(1.0 - e3, E2)));
         const double ic = rsqrt(dot(c, c));
         const double om = k / ic;
+        // loops kept rolled: the unrolled series would hold every node's
+        // coefficients in registers
+#pragma unroll 1
         for (int j = 0; j < kGL; ++j)
+#pragma unroll 1
             for (int l = 0; l < kGL; ++l) {
                 const double e1 = c_x[j], e2 = c_x[l];
                 // x = xi (A1, B1), y = xi (A2, B2) in the (a, b) coordinates
@@ -557,7 +608,8 @@ __device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, con
                 }
                 const double w = w3 * c_w[j] * c_w[l] * e1 * ic;
                 const double oe = om * e1 * e2;
-                const Cx J0 = moment<2, 0, false>(oe), J1 = moment<3, 0, false>(oe), J2 = moment<4, 0, false>(oe);
+                Cx J0, J1, J2;
+                moment3(oe, tr, J0, J1, J2);
                 const L3 al{{1.0, 0.0, 0.0}}, bx{{-A1, A1 - B1, B1}}, by{{-A2, A2 - B2, B2}};
                 moment_acc(ar, ai, w, al, bx, al, by, J0, J1, J2);   // the region
                 moment_acc(ar, ai, w, al, by, al, bx, J0, J1, J2);   // and its mirror
@@ -569,6 +621,7 @@ __device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, con
         const V3 E = sub(Q, P), a = sub(A, P), b = sub(B, P);
         const int face = t >> 6, ip = (t >> 2) & (kPts - 1), g = t & 3;
         const double p = sx[ip], q1 = 1.0 - p;
+#pragma unroll 1
         for (int j = 0; j < kPts / 4; ++j) {
             const double q = sx[g + 4 * j];
             double dh, s1h, s2h, fw;
@@ -585,11 +638,7 @@ __device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, con
             const double om = k / ic;
             const double K = sw[ip] * sw[g + 4 * j] * fw * (DL ? s1h * ic * ic * ic : ic);
             Cx J0, J1, J2;
-            if constexpr (DL) {
-                J0 = moment<0, 1, true>(om), J1 = moment<1, 1, true>(om), J2 = moment<2, 1, true>(om);
-            } else {
-                J0 = moment<1, 1, false>(om), J1 = moment<2, 1, false>(om), J2 = moment<3, 1, false>(om);
-            }
+            moment3(om, te, J0, J1, J2);
 #pragma unroll
             for (int l = 0; l < 2; ++l) {
                 const double tau = kG2x[l];
@@ -616,6 +665,7 @@ __device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, con
     const double an = DL ? dot(av, ld(it.ny)) : 1.0;
     const double wuv = sw[iu] * sw[iv];
     const L3 al{{1.0, 0.0, 0.0}}, bu{{-1.0, 1.0 - u, u}}, bvv{{-1.0, 1.0 - v, v}};
+#pragma unroll 1
     for (int kz = 0; kz < kPts; ++kz) {
         const double z = sx[kz];
         const V3 c1 = fma3(-z, bv, av), c2 = fma3(z, av, mul(-1.0, bv));
@@ -623,13 +673,8 @@ __device__ void pair_part_p1_helmholtz(const NearItem &it, const double *sx, con
         const double f = wuv * sw[kz] * z * an;
         const double k1 = f * (DL ? i1 * i1 * i1 : i1), k2 = f * (DL ? z * i2 * i2 * i2 : i2);
         Cx J0, J1, J2, H0, H1, H2;
-        if constexpr (DL) {
-            J0 = moment<1, 0, true>(k / i1), J1 = moment<2, 0, true>(k / i1), J2 = moment<3, 0, true>(k / i1);
-            H0 = moment<1, 0, true>(k / i2), H1 = moment<2, 0, true>(k / i2), H2 = moment<3, 0, true>(k / i2);
-        } else {
-            J0 = moment<2, 0, false>(k / i1), J1 = moment<3, 0, false>(k / i1), J2 = moment<4, 0, false>(k / i1);
-            H0 = moment<2, 0, false>(k / i2), H1 = moment<3, 0, false>(k / i2), H2 = moment<4, 0, false>(k / i2);
-        }
+        moment3(k / i1, tr, J0, J1, J2);
+        moment3(k / i2, tr, H0, H1, H2);
         const L3 zbv{{-z, z * (1.0 - v), z * v}}, zbu{{-z, z * (1.0 - u), z * u}};
         moment_acc(ar, ai, k1, al, bu, al, zbv, J0, J1, J2);    // x = P + s a(u), y = P + s z b(v)
         moment_acc(ar, ai, k2, al, zbu, al, bvv, H0, H1, H2);   // x = P + s z a(u), y = P + s b(v)
@@ -644,17 +689,22 @@ __global__ __launch_bounds__(kNearThreads) void k_near_p1_helmholtz(const NearIt
     if ((int64_t)blockIdx.x >= n) return;
     const NearItem &it = items[blockIdx.x];
     __shared__ double sx[kPts], sw[kPts];
+    __shared__ double tr[kTab3], te[kTab3];
     __shared__ double red[18][kNearThreads];
     const int t = threadIdx.x;
     if (t < kPts) {
         sx[t] = 0.5 * (c_x[t % kGL] + (double)(t / kGL));
         sw[t] = 0.5 * c_w[t % kGL];
     }
+    for (int i = t; i < kTab3; i += kNearThreads) {
+        tr[i] = OP == 3 ? c_tab_d10.v[i] : c_tab_s20.v[i];
+        te[i] = OP == 3 ? c_tab_d01.v[i] : c_tab_s11.v[i];
+    }
     __syncthreads();
     double ar[9], ai[9];
 #pragma unroll
     for (int kk = 0; kk < 9; ++kk) ar[kk] = ai[kk] = 0.0;
-    pair_part_p1_helmholtz<OP>(it, sx, sw, ar, ai);
+    pair_part_p1_helmholtz<OP>(it, sx, sw, tr, te, ar, ai);
 #pragma unroll
     for (int kk = 0; kk < 9; ++kk) {
         red[2 * kk][t] = ar[kk];
