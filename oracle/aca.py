@@ -9,8 +9,11 @@ row), with the choices the paper leaves to the literature:
     u_k has its largest modulus (partial pivoting); ties go to the lowest
     index;
   * "does not vanish": the residual row vanishes when max|v~| <= zero_abs,
-    an absolute threshold supplied by the caller; a vanishing row is marked
-    used and the next unused row (lowest index) is tried;
+    an absolute threshold supplied by the caller.  Before the first pivot a
+    vanishing row is marked used and the next unused row (lowest index) is
+    tried (a block may start with zero rows); after it, the row was chosen
+    where the newest column is largest, so a vanishing residual there ends
+    the approximation;
   * stopping criterion: ||u_k|| ||v_k|| <= tol ||S_k||_F, or every row used,
     or k = min(m, n), or k = max_rank; ||S_k||_F is updated from
     ||S_k||^2 = ||S_{k-1}||^2 + 2 Re sum_{l<k} (u_l^H u_k)(v_l^H v_k)
@@ -46,7 +49,7 @@ def aca(get_row, get_col, m: int, n: int, tol: float, max_rank: int, zero_abs: f
             v = v - U[l][i] * V[l]
         used[i] = True
         if np.max(np.abs(v)) <= zero_abs:
-            if used.all():
+            if used.all() or k > 0:
                 break
             i = int(np.flatnonzero(~used)[0])
             continue

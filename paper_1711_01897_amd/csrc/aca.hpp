@@ -7,8 +7,13 @@
 // Choices the paper leaves open:
 //   * row pivots: first local row, then the unused row where |u_k| is
 //     largest (ties: lowest index);
-//   * a residual row with max |v~| <= zero_abs vanishes: it is marked used
-//     and the lowest unused row is tried next;
+//   * a residual row with max |v~| <= zero_abs vanishes: before the first
+//     pivot (k = 0) it is marked used and the lowest unused row is tried
+//     next (blocks whose leading rows are zero); once k >= 1 the row was
+//     chosen where the newest column u_k is largest, so a vanishing residual
+//     there means the remaining rows are resolved to the entries' own noise
+//     level and the approximation stops (walking the rows one request at a
+//     time would spend a request per row on FP32 rounding noise);
 //   * stop when ||u_k|| ||v_k|| <= tol ||S_k||_F, with ||S_k||_F updated by
 //     ||S_k||^2 = ||S_{k-1}||^2 + 2 Re sum_{l<k} (u_l^H u_k)(v_l^H v_k)
 //                + ||u_k||^2 ||v_k||^2,
@@ -98,7 +103,7 @@ struct AcaCore {
             }
         }
         if (!(std::sqrt(amax2) > zero_abs)) {
-            if (nused == m) {
+            if (nused == m || k > 0) {
                 phase = DONE;
                 return;
             }

@@ -84,6 +84,32 @@ def test_aca_callback_exact_rank(cplx):
     assert np.abs(V - Vo).max() <= 1e-12 * np.abs(Vo).max()
 
 
+def test_aca_callback_stops_at_a_vanishing_row_like_the_oracle():
+    # after the first pivot a vanishing residual row ends the approximation in
+    # both state machines: same rank, same number of row and column requests
+    rng = np.random.Generator(np.random.PCG64(3))
+    m, n = 40, 30
+    M = rng.normal(size=(m, 2)) @ rng.normal(size=(2, n)) + 1e-10 * rng.normal(size=(m, n))
+    counts = []
+    for run in ("lib", "oracle"):
+        c = {"row": 0, "col": 0}
+
+        def row(i, c=c):
+            c["row"] += 1
+            return M[i]
+
+        def col(j, c=c):
+            c["col"] += 1
+            return M[:, j]
+
+        if run == "lib":
+            U, V = bem.aca_callback(row, col, m, n, 1e-14, 20, 1e-7, False)
+        else:
+            U, V, _, _ = OA.aca(row, col, m, n, 1e-14, 20, 1e-7)
+        counts.append((U.shape[1], c["row"], c["col"]))
+    assert counts[0] == counts[1] == (2, 3, 2)
+
+
 @pytest.mark.parametrize("op,space,k", [(O.LAPLACE_SLP, O.P1, 0.0), (O.LAPLACE_DLP, O.P1, 0.0),
                                         (O.HELMHOLTZ_SLP, O.P0, 5.0), (O.HELMHOLTZ_DLP, O.P0, 5.0)])
 def test_aca_callback_matches_oracle_on_admissible_blocks(op, space, k):

@@ -4,7 +4,9 @@
   * the running Frobenius norm of S_k equals ||U V^T||_F;
   * on admissible blocks of a real mesh the approximation error against the
     dense oracle block is bounded by a small multiple of the tolerance;
-  * a vanishing residual row is skipped, not used as a pivot row.
+  * a vanishing residual row is skipped, not used as a pivot row, before
+    the first pivot; after it, a vanishing residual at the pivot-row
+    candidate ends the approximation instead of walking the other rows.
 """
 import numpy as np
 import pytest
@@ -47,6 +49,33 @@ def test_vanishing_rows_are_skipped():
     assert piv[0][0] == 3
     assert U.shape[1] == 1
     assert np.linalg.norm(M - U @ V.T) <= 1e-14 * np.linalg.norm(M)
+
+
+def test_vanishing_row_after_a_pivot_stops():
+    # rank 2 plus noise far below the vanishing threshold: after two pivots the
+    # next candidate row's residual is noise, so ACA stops with one extra row
+    # request instead of requesting every remaining row
+    m, n = 40, 30
+    M = RNG.normal(size=(m, 2)) @ RNG.normal(size=(2, n)) + 1e-10 * RNG.normal(size=(m, n))
+    calls = {"row": 0, "col": 0}
+
+    def row(i):
+        calls["row"] += 1
+        return M[i]
+
+    def col(j):
+        calls["col"] += 1
+        return M[:, j]
+
+    U, V, piv, _ = A.aca(row, col, m, n, tol=1e-14, max_rank=20, zero_abs=1e-7)
+    assert U.shape[1] == 2
+    assert calls == {"row": 3, "col": 2}
+    assert np.linalg.norm(M - U @ V.T) <= 1e-8 * np.linalg.norm(M)
+    # before the first pivot a vanishing row is skipped: zero leading rows are walked
+    Z = M.copy()
+    Z[:5] = 0.0
+    U, V, piv, _ = A.aca_dense(Z, tol=1e-14, max_rank=20, zero_abs=1e-7)
+    assert piv[0][0] == 5 and U.shape[1] == 2
 
 
 def admissible_blocks(space, leaf=40, count=6):
