@@ -1,21 +1,31 @@
-"""Benchmark: H-matrix (ACA) assembly of the Laplace single- and double-layer
-operators, P1, on the level-6 icosphere (81,920 triangles, 40,962 vertices),
-leaf size 100, eta = 1, ACA tolerance 1e-5, every ACA row and column
-evaluated on the GPU through the request server.
+"""Benchmark of the served ACA weak-form entry path.
 
-One step = both assemblies with FP32 (compensated) entries.  The timed steps
-give `value` = ACA entries evaluated per second of wall time (whole job:
-tree, host ACA in FP64, batching, device kernels, copies).  The same
-assembly with plain FP64 entries is timed beside it.  The request latencies
-(submit -> completion) of the timed steps give p50/p99.
+Default workload (the largest single-GPU configuration): the served Laplace
+single layer, P1, on the 1,049,540-triangle capped cylinder (R = 1, L = 16,
+vertices jittered by +-1% of the edge, seed 0), 6-point rule, H-matrix leaf
+16, eta = 1, largest admissible block 4,096, ACA tolerance 1e-5, 32 host ACA
+workers.  The admissible blocks are drawn in a seeded order (seed 2) and cut
+into warmup + steps segments that together cover the whole matrix once; one
+step = one segment served as a stream whose blocks arrive as a Poisson
+process (seed 1) at an offered load above the capacity measured on the
+warm-up segments, so the timed steps measure what the device path sustains
+while requests arrive continuously.  `value` = ACA entries evaluated per
+second of wall time over the timed steps (host ACA in FP64, batching,
+device kernels, transfers); p50/p99 = submit -> completion latency of the
+ACA row/column requests of the timed steps.  The same segments with plain
+FP64 entries form the FP64 leg; extra segments at 50/80/95% of capacity give
+latency against load.
 
 The roofline object is for the dominant kernel (largest summed duration):
 algorithmic flops per launch / mean launch duration, the duration from the
 server's HIP events around each launch on its stream (what rocprofv3's
-kernel trace also reports); the workgroups' own device-clock span (first
-start to last end, without the dispatch and drain around it) is reported
-beside it.  `cpu_baseline` times the FP64
-oracle on a bounded sample of the same ACA row requests on the host cores.
+kernel trace also reports).  `cpu_baseline` times the FP64 oracle on a
+bounded seeded sample of the same ACA row/column requests, on all host
+threads and on one.
+
+Other workloads: --workload icosphere6 (Laplace single + double layer, P1,
+81,920-triangle icosphere, leaf 100, H-matrix assembly per step), --dense,
+--complete.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 """
@@ -51,7 +61,9 @@ FLOPS_EXECUTED = {(0, 0): 11, (1, 0): 13, (2, 0): 21, (3, 0): 27,
 PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9
 PEAK_FP32_PACKED = 2 * PEAK_FP32_VALU
 KERNEL_NAMES = {0: "k_p0", 1: "k_p1"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_icosphere6_p1.json")
+def traffic_file(workload):
+    """Calibrated HBM traffic record of the dominant kernel of a workload."""
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}_p1.json")
 
 
 def kernel_source_hash():
@@ -64,8 +76,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workers", type=int, default=10)
-    ap.add_argument("--blocks-per-worker", type=int, default=180)
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "icosphere6"],
+                    help="cylinder: the served 1,049,540-triangle capped cylinder (default); icosphere6: H-matrix "
+                         "assembly of the Laplace single and double layer on the level-6 icosphere per step")
+    ap.add_argument("--workers", type=int, default=None, help="host ACA workers (cylinder 32, icosphere6 10)")
+    ap.add_argument("--blocks-per-worker", type=int, default=None,
+                    help="ACA blocks each worker keeps in flight (cylinder 128, icosphere6 180)")
+    ap.add_argument("--load", type=float, default=1.25,
+                    help="cylinder: offered block arrival rate of the timed steps as a multiple of the capacity "
+                         "measured on the warm-up segments")
+    ap.add_argument("--sweep", default="0.5,0.8,0.95",
+                    help="cylinder: offered loads of the extra latency-against-load segments ('' for none)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -96,7 +117,12 @@ def parse():
     ap.add_argument("--traffic-kernel", default="k_p1_f32<1, 6>",
                     help="kernel name fragment of the dominant kernel for --traffic-from")
     ap.add_argument("--traffic-copy-bytes", type=int, default=256 << 20)
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.workers is None:
+        a.workers = 32 if a.workload == "cylinder" else 10
+    if a.blocks_per_worker is None:
+        a.blocks_per_worker = 128 if a.workload == "cylinder" else 180
+    return a
 
 
 def copy_calibration(nbytes):
@@ -150,7 +176,7 @@ def traffic_from(args):
            "copy_bytes": args.traffic_copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_factor": f_fetch, "write_factor": f_write,
            "bytes_per_launch": (fetch * f_fetch + write * f_write) * 1024.0}
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(traffic_file(args.workload), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 
@@ -227,7 +253,7 @@ def timed(bem, mesh, prec, steps, warmup, args):
     return dt, tot, bem.server_stats(), bem.server_kernel_stats()
 
 
-def roofline(kstats):
+def roofline(kstats, workload="icosphere6"):
     main = list(kstats)
     if not main:
         return None, None
@@ -238,8 +264,8 @@ def roofline(kstats):
     mean_dc = dom["seconds"] / dom["launches"]           # first workgroup start to last workgroup end
     achieved = per_launch / mean_ev / 1e12
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
+    if os.path.exists(traffic_file(workload)):
+        with open(traffic_file(workload)) as f:
             t = json.load(f)
         if t.get("kernel_source_hash") == kernel_source_hash():
             traffic = t.get("bytes_per_launch")
@@ -435,6 +461,273 @@ def complete_main(args):
     print(json.dumps(line))
 
 
+def gpu_telemetry():
+    """GPU temperature and clocks (the paper saw thermal down-clocking in its
+    runs, Section 5), or None where the management library is unavailable."""
+    try:
+        import amdsmi
+        amdsmi.amdsmi_init()
+        try:
+            handles = amdsmi.amdsmi_get_processor_handles()
+            if not handles:
+                return None
+            h = handles[0]
+            out = {}
+            try:
+                out["edge_temp_c"] = amdsmi.amdsmi_get_temp_metric(h, amdsmi.AmdSmiTemperatureType.EDGE,
+                                                                   amdsmi.AmdSmiTemperatureMetric.CURRENT)
+            except Exception:
+                pass
+            try:
+                out["hotspot_temp_c"] = amdsmi.amdsmi_get_temp_metric(h, amdsmi.AmdSmiTemperatureType.HOTSPOT,
+                                                                      amdsmi.AmdSmiTemperatureMetric.CURRENT)
+            except Exception:
+                pass
+            try:
+                c = amdsmi.amdsmi_get_clock_info(h, amdsmi.AmdSmiClkType.GFX)
+                out["gfx_clock_mhz"] = c.get("clk")
+                out["gfx_clock_max_mhz"] = c.get("max_clk")
+            except Exception:
+                pass
+            try:
+                act = amdsmi.amdsmi_get_gpu_activity(h)
+                out["gfx_activity_pct"] = act.get("gfx_activity")
+            except Exception:
+                pass
+            return out or None
+        finally:
+            amdsmi.amdsmi_shut_down()
+    except Exception:
+        return None
+
+
+def host_cores():
+    """Cores this process may use (affinity), the machine's logical CPUs and
+    the CPU model (from /proc/cpuinfo, as lscpu reports it)."""
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"usable": usable, "logical": os.cpu_count(), "model": model}
+
+
+CYL = {"leaf": 16, "eta": 1.0, "tol": 1e-5, "max_block": 4096, "max_rank": 200}
+
+
+def cylinder_workload_name(nt, nv, args):
+    return (f"served Laplace single layer, P1, capped cylinder R=1 L=16 ({nt} triangles, {nv} vertices, +-1% "
+            f"jitter seed 0), 6-point rule, H-matrix leaf {CYL['leaf']}, eta {CYL['eta']}, largest block "
+            f"{CYL['max_block']}, ACA tol {CYL['tol']}, {args.workers} host ACA workers x {args.blocks_per_worker} "
+            "blocks, Poisson block arrivals (seed 1), every ACA row/column on the GPU through the request server, "
+            "FP32 compensated entries")
+
+
+def poisson_arrivals(rng, n, rate):
+    """n arrival times (s) of a Poisson process of the given rate, first at t=0."""
+    import numpy as np
+    gaps = rng.exponential(1.0 / rate, size=n)
+    gaps[0] = 0.0
+    return np.cumsum(gaps)
+
+
+def serve_leg(bem, inputs, plan, segs, prec, args, label):
+    """Warm-up segments closed-loop (capacity), then the timed segments as
+    Poisson streams at args.load x capacity, then the load sweep."""
+    import numpy as np
+    import torch
+    nw = args.warmup
+    warm = []
+    for i in range(nw):
+        t0 = time.perf_counter()
+        st = plan.run(segs[i], None, prec)
+        warm.append((st, time.perf_counter() - t0))
+    use = warm[1:] if len(warm) > 1 else warm
+    if use:
+        cap_blocks = sum(w[0]["blocks"] for w in use) / sum(w[1] for w in use)
+        cap_entries = sum(w[0]["entries"] for w in use) / sum(w[1] for w in use)
+    else:
+        t0 = time.perf_counter()
+        st = plan.run(segs[0][: max(1, len(segs[0]) // 4)], None, prec)
+        dt = time.perf_counter() - t0
+        cap_blocks, cap_entries = st["blocks"] / dt, st["entries"] / dt
+    rate = args.load * cap_blocks
+    rng = inputs.rng(inputs.SEED_ARRIVALS)
+    bem.server_stats(reset=True)
+    bem.server_kernel_stats(reset=True)
+    tel0 = gpu_telemetry()
+    torch.cuda.synchronize()
+    steps = []
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        seg = segs[nw + i]
+        arr = poisson_arrivals(rng, len(seg), rate)
+        t0 = time.perf_counter()
+        st = plan.run(seg, arr, prec)
+        dt = time.perf_counter() - t0
+        steps.append((st, dt))
+        print(f"[bench] {label} step {i}: {st['blocks']} blocks {st['entries']} entries {dt:.3f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_all
+    tel1 = gpu_telemetry()
+    sst = bem.server_stats()
+    kst = bem.server_kernel_stats()
+    ent = sum(x[0]["entries"] for x in steps)
+    secs = sum(x[1] for x in steps)
+    per = sorted(x[0]["entries"] / x[1] for x in steps)
+    out = {
+        "value": ent / wall, "entries_per_step": ent // max(1, len(steps)),
+        "requests_per_step": sum(x[0]["requests"] for x in steps) // max(1, len(steps)),
+        "blocks_per_step": sum(x[0]["blocks"] for x in steps) // max(1, len(steps)),
+        "seconds_per_step": secs / max(1, len(steps)), "wall": wall,
+        "step_entries_per_s_median": per[len(per) // 2] if per else None,
+        "step_entries_per_s_min": per[0] if per else None,
+        "rank_sum": sum(x[0]["rank_sum"] for x in steps), "rank_max": max((x[0]["rank_max"] for x in steps),
+                                                                           default=0),
+        "mean_rank": sum(x[0]["rank_sum"] for x in steps) / max(1, sum(x[0]["blocks"] for x in steps)),
+        "capacity_blocks_per_s": cap_blocks, "capacity_entries_per_s": cap_entries, "arrival_rate_blocks_per_s": rate,
+        "mean_block_start_delay_ms": 1e3 * sum(x[0]["mean_start_delay"] * x[0]["blocks"] for x in steps) /
+        max(1, sum(x[0]["blocks"] for x in steps)),
+        "mean_block_ms": 1e3 * sum(x[0]["mean_block_seconds"] * x[0]["blocks"] for x in steps) /
+        max(1, sum(x[0]["blocks"] for x in steps)),
+        "latency_p50_ms": sst["latency_p50"] * 1e3, "latency_p99_ms": sst["latency_p99"] * 1e3,
+        "sst": sst, "kst": kst, "telemetry": {"before": tel0, "after": tel1},
+    }
+    sweep = []
+    loads = [float(x) for x in args.sweep.split(",") if x.strip()] if args.sweep else []
+    for j, ld in enumerate(loads):
+        seg = segs[(nw + args.steps + j) % len(segs)]
+        arr = poisson_arrivals(rng, len(seg), ld * cap_blocks)
+        bem.server_stats(reset=True)
+        t0 = time.perf_counter()
+        st = plan.run(seg, arr, prec)
+        dt = time.perf_counter() - t0
+        ss = bem.server_stats()
+        sweep.append({"load": ld, "entries_per_s": st["entries"] / dt, "latency_p50_ms": ss["latency_p50"] * 1e3,
+                      "latency_p99_ms": ss["latency_p99"] * 1e3,
+                      "mean_block_start_delay_ms": st["mean_start_delay"] * 1e3})
+    out["latency_vs_load"] = sweep
+    return out
+
+
+def cylinder_cpu_baseline(bem, inputs, plan, mesh, xyz, tri, seconds):
+    """FP64 oracle on a seeded sample of ACA row/column requests of the
+    plan's admissible blocks (seed 3): all usable host threads for most of
+    the budget, one thread for the rest.  Also returns the largest FP32
+    normwise error of the device on the same requests."""
+    import numpy as np
+    import oracle
+
+    om = oracle.OracleMesh(xyz, tri, 6)
+    nb = plan.info()["blocks"]
+    rng = inputs.rng(inputs.SEED_SAMPLING)
+    worst = 0.0
+
+    def sample(budget, nthreads):
+        nonlocal worst
+        spent, entries, nreq = 0.0, 0, 0
+        while spent < budget:
+            rows, cols = plan.block(int(rng.integers(nb)))
+            if nreq % 2 == 0:
+                r, c = rows[int(rng.integers(rows.size)):][:1], cols
+            else:
+                r, c = rows, cols[int(rng.integers(cols.size)):][:1]
+            t0 = time.perf_counter()
+            ref = om.entries(oracle.LAPLACE_SLP, oracle.P1, 0.0, r, c, nthreads=nthreads)
+            spent += time.perf_counter() - t0
+            entries += ref.size
+            nreq += 1
+            got = bem.eval_entries(mesh, bem.LAPLACE_SLP, bem.P1, 0.0, r, c, prec=bem.FP32, near=bem.NEAR_ERROR)
+            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+        return entries / spent, nreq, entries, spent
+
+    cores = host_cores()
+    all_rate, n_all, e_all, s_all = sample(0.75 * seconds, 0)
+    one_rate, n_one, e_one, s_one = sample(0.25 * seconds, 1)
+    return {"value": all_rate, "unit": "entries/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"{n_all} ACA row/column requests of seeded admissible blocks of the served cylinder "
+                      f"partition (Laplace single layer, P1), {e_all} entries, {s_all:.1f} s on "
+                      f"{oracle.max_threads()} threads; {n_one} requests, {e_one} entries, {s_one:.1f} s on 1",
+            "one_core_value": one_rate, "host": cores}, worst
+
+
+def cylinder_main(args):
+    import numpy as np
+    from paper_1711_01897_amd import bem, inputs
+
+    t0 = time.perf_counter()
+    xyz, tri = inputs.capped_cylinder()
+    mesh = bem.mesh_create(xyz, tri, 6)
+    print(f"[bench] mesh {tri.shape[0]} triangles / {xyz.shape[0]} vertices resident "
+          f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    plan = bem.aca_plan_create(mesh, bem.LAPLACE_SLP, bem.P1, 0.0, leaf_size=CYL["leaf"], eta=CYL["eta"],
+                               aca_tol=CYL["tol"], max_rank=CYL["max_rank"], n_workers=args.workers,
+                               blocks_per_worker=args.blocks_per_worker, prec=bem.FP32, max_block=CYL["max_block"])
+    info = plan.info()
+    print(f"[bench] plan: {info['blocks']} admissible blocks, set-up {info['setup_seconds']:.1f} s", file=sys.stderr,
+          flush=True)
+    order = inputs.rng(inputs.SEED_REQUESTS).permutation(info["blocks"]).astype(np.int64)
+    segs = np.array_split(order, args.warmup + args.steps)
+    f32 = serve_leg(bem, inputs, plan, segs, bem.FP32, args, "fp32")
+    roof, dom = roofline(f32["kst"], "cylinder")
+    fp64 = None
+    if not args.no_fp64:
+        f64 = serve_leg(bem, inputs, plan, segs, bem.FP64, args, "fp64")
+        fp64 = {k: f64[k] for k in ("value", "entries_per_step", "requests_per_step", "seconds_per_step",
+                                    "step_entries_per_s_median", "step_entries_per_s_min", "mean_rank", "rank_max",
+                                    "latency_p50_ms", "latency_p99_ms", "capacity_entries_per_s",
+                                    "arrival_rate_blocks_per_s", "latency_vs_load")}
+        fp64["unit"] = "entries/s"
+    cpu, worst = (None, None)
+    if not args.no_cpu_baseline:
+        cpu, worst = cylinder_cpu_baseline(bem, inputs, plan, mesh, xyz, tri, args.cpu_seconds)
+        cpu["speedup_S"] = f32["value"] / cpu["value"]
+        cpu["speedup_S_one_core"] = f32["value"] / cpu["one_core_value"]
+        print(f"[bench] cpu baseline {cpu['value']:.3e} entries/s on {cpu['cores']} threads", file=sys.stderr,
+              flush=True)
+    sst = f32["sst"]
+    line = {
+        "metric": "weak-form entries/sec FP32 vs FP64 at stated rel err; p50/p99 ACA request latency",
+        "value": f32["value"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": f32["wall"] / max(1, args.steps) * 1e3, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cylinder_workload_name(tri.shape[0], xyz.shape[0], args),
+                   "admissible_blocks": info["blocks"], "blocks_per_step": f32["blocks_per_step"],
+                   "aca_entries_per_step": f32["entries_per_step"], "aca_requests_per_step": f32["requests_per_step"],
+                   "mean_rank": f32["mean_rank"], "max_rank": f32["rank_max"], "workers": args.workers,
+                   "blocks_per_worker": args.blocks_per_worker, "offered_load": args.load,
+                   "arrival_rate_blocks_per_s": f32["arrival_rate_blocks_per_s"],
+                   "plan_setup_seconds": info["setup_seconds"]},
+        "latency_p50_ms": f32["latency_p50_ms"], "latency_p99_ms": f32["latency_p99_ms"],
+        "step_entries_per_s_median": f32["step_entries_per_s_median"],
+        "step_entries_per_s_min": f32["step_entries_per_s_min"],
+        "capacity_entries_per_s": f32["capacity_entries_per_s"],
+        "mean_block_start_delay_ms": f32["mean_block_start_delay_ms"], "mean_block_ms": f32["mean_block_ms"],
+        "latency_vs_load": f32["latency_vs_load"],
+        "fused_launch_batches": sst["batches"], "requests_per_batch": sst["requests"] / max(1, sst["batches"]),
+        "server_seconds_per_step": {"dispatch": sst["dispatch_seconds"] / args.steps,
+                                    "dispatch_hip_calls": sst["dispatch_hip_seconds"] / args.steps,
+                                    "complete": sst["complete_seconds"] / args.steps,
+                                    "event_wait": sst["wait_seconds"] / args.steps,
+                                    "entry_kernels": sst["kernel_seconds"] / args.steps},
+        "request_latency_legs_us": {k: round(sst["mean_%s_seconds" % k] * 1e6, 1)
+                                    for k in ("queue", "stage", "device", "complete")},
+        "kernel_busy_fraction": sst["kernel_seconds"] / f32["wall"] if f32["wall"] > 0 else None,
+        "fp64": fp64, "fp32_over_fp64": (f32["value"] / fp64["value"]) if fp64 else None,
+        "max_rel_err_sampled": worst, "gpu_telemetry": f32["telemetry"],
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    plan.destroy()
+    mesh.destroy()
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -457,6 +750,9 @@ def main():
         return
     if args.complete:
         complete_main(args)
+        return
+    if args.workload == "cylinder":
+        cylinder_main(args)
         return
     from paper_1711_01897_amd import bem, inputs
 

@@ -36,7 +36,7 @@
  *
  * Conventions for every call
  *   - Indices are 0-based int32 dof ids: triangle ids for P0, vertex ids for
- *     P1.  Duplicated indices are allowed.
+ *     P1, 3 t + a for DP1.  Duplicated indices are allowed.
  *   - Outputs are row-major nrows x ncols.  Element type by (operator,
  *     precision): Laplace FP64 -> double, Laplace FP32 -> float, Helmholtz
  *     FP64 -> complex double, Helmholtz FP32 -> complex float; complex values
@@ -85,7 +85,13 @@ typedef enum {
     BEM_LAPLACE_HYPS = 6,     /* P1 only */
     BEM_HELMHOLTZ_HYPS = 7    /* P1 only */
 } bem_op;
-typedef enum { BEM_P0 = 0, BEM_P1 = 1 } bem_space;
+/* Trial and test spaces (the same on both sides): BEM_P0, one dof per
+ * triangle (its indicator); BEM_P1, one dof per vertex (the continuous hat
+ * function); BEM_DP1, three dofs per triangle, dof 3 t + a the barycentric
+ * function of local vertex a on triangle t alone (discontinuous piecewise
+ * linear: the space whose single layer gives the hypersingular operator by
+ * sparse transformations, Eq. hyp_via_slp). */
+typedef enum { BEM_P0 = 0, BEM_P1 = 1, BEM_DP1 = 2 } bem_space;
 /* BEM_FP64: plain FP64 quadrature.  BEM_FP32: FP32 quadrature with
  * compensated (TwoSum) accumulation, centroid-relative geometry and, for
  * Helmholtz, the phase k r reduced to a turn in FP64. */
@@ -96,12 +102,15 @@ typedef enum { BEM_FP64 = 0, BEM_FP32 = 1 } bem_prec;
  * (Section 3.2.3 leaves them to one; here: coordinates around the pair's
  * singular set with the radial integral in closed form and composite
  * Gauss-Legendre rules for the rest, ~1e-12 relative, FP64, added to the
- * regular part; Helmholtz: the radial integral of e^{ikr} by an 8-point
- * rule; P1: each pair's 3 x 3 local matrix, then a fixed-order sum per
- * entry; the Laplace hypersingular operator: the hat functions' constant
- * curls times each pair's P0 single-layer integral).  BEM_NEAR_SINGULAR is
- * available for every operator and space (the hypersingular operator: P1
- * only, as everywhere). */
+ * regular part; Helmholtz: the radial integral of e^{ikr} as a 48-term
+ * power series in omega = k |c| (x - y = rho c), accurate to ~5e-10 up to
+ * omega = 12: a Helmholtz request whose vertex-sharing pairs reach beyond
+ * that (about one element per wavelength or coarser) fails with BEM_E_ARG;
+ * P1: each pair's 3 x 3 local matrix, then a fixed-order sum per entry; the
+ * hypersingular operators: the hat functions' constant curls times each
+ * pair's P0 single-layer integral, minus k^2 n_x . n_y times its P1
+ * single-layer local matrix).  BEM_NEAR_SINGULAR is available for every
+ * operator and space (the hypersingular operator: P1 only, as everywhere). */
 typedef enum { BEM_NEAR_ERROR = 0, BEM_NEAR_SKIP = 1, BEM_NEAR_SINGULAR = 2 } bem_near;
 
 typedef struct bem_mesh bem_mesh;
@@ -282,14 +291,16 @@ int bem_aca_callback(int64_t m, int64_t n, int is_complex, bem_row_fn get_row, b
  * split at the midpoint of the longest bounding-box side (median split when
  * one side would be empty), and the block tree from (root, root) whose
  * leaves are admissible when dist > 0 and min(diam) <= eta dist on the
- * clusters' support boxes, dense when either cluster is a leaf.
+ * clusters' support boxes and, with max_block > 0, neither cluster holds
+ * more than max_block dofs (0: no bound); dense when either cluster is a
+ * leaf.
  * Host-only.  Writes up to max_blocks leaves as (row cluster, col cluster,
  * admissible) triples and the dof ranges of every cluster: cluster c holds
  * dofs perm[cl_begin[c] .. cl_end[c]).  Sizes are returned in *nblocks and
  * *nclusters; when a capacity is too small nothing else is written and
  * BEM_E_ARG is returned with the needed sizes. */
 int bem_partition(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, bem_space space,
-                  int32_t leaf_size, double eta,
+                  int32_t leaf_size, double eta, int32_t max_block,
                   int32_t *perm, int32_t *cl_begin, int32_t *cl_end, int64_t max_clusters,
                   int32_t *blocks /* 3 x max_blocks */, int64_t max_blocks,
                   int64_t *nclusters, int64_t *nblocks);
@@ -304,6 +315,8 @@ typedef struct {
     bem_prec prec;          /* precision of the device entries */
     int32_t dense_mode;     /* 0: dense leaves left empty; 1: their regular part (BEM_NEAR_SKIP);
                                2: complete, singular pairs included (BEM_NEAR_SINGULAR) */
+    int32_t max_block;      /* largest dimension of an admissible block (0: no bound); larger
+                               cluster pairs are split further */
 } bem_hmat_params;
 
 /* Fill every admissible leaf of the block tree by ACA (all rows and columns
@@ -339,6 +352,53 @@ int bem_hmat_block_info(const bem_hmat *h, int64_t b, int32_t *admissible, int64
                         int32_t *rank, const int32_t **rows, const int32_t **cols);
 int bem_hmat_block_dense(const bem_hmat *h, int64_t b, void *out);
 int bem_hmat_destroy(bem_hmat *h);
+
+/* ---- served ACA block streams ------------------------------------------- */
+/* An ACA plan is the set-up of bem_hmat_assemble kept for repeated use: the
+ * partition (leaf_size, eta, max_block of params) and, on the device, the
+ * lane sets of every cluster of an admissible block.  bem_aca_plan_run then
+ * approximates any list of the plan's admissible blocks by ACA (Algorithm
+ * "ACA", Section 2.1), every block row and column evaluated on the device
+ * through the request server, as a served stream: block i starts no earlier
+ * than arrival[i] seconds after the call, params->n_workers host threads
+ * keep up to params->blocks_per_worker blocks each in flight (Section 4
+ * gives every block its own CPU thread; here each thread holds many blocks
+ * as resumable state machines).  Plan block ids run 0 .. n_blocks-1 over
+ * the admissible leaves in block-tree order.  aca_tol, max_rank come from
+ * params; the precision is chosen per run.  Errors: BEM_E_ARG (bad
+ * arguments, a block id out of range, arrival times not finite or
+ * decreasing), BEM_E_OOM, BEM_E_DEVICE. */
+typedef struct bem_aca_plan bem_aca_plan;
+int bem_aca_plan_create(bem_mesh *mesh, bem_op op, bem_space space, double k, const bem_hmat_params *params,
+                        bem_aca_plan **out);
+/* n_blocks: admissible blocks; ndof: dofs of the space; setup_seconds:
+ * partition and lane sets. */
+int bem_aca_plan_info(const bem_aca_plan *plan, int64_t *n_blocks, int64_t *ndof, double *setup_seconds);
+/* Dimensions and dof lists of plan block b (pointers owned by the plan). */
+int bem_aca_plan_block(const bem_aca_plan *plan, int64_t b, int64_t *m, int64_t *n, const int32_t **rows,
+                       const int32_t **cols);
+
+typedef struct {
+    int64_t blocks;             /* blocks approximated */
+    int64_t entries;            /* entries requested from the device */
+    int64_t requests;           /* row and column requests */
+    int64_t rank_sum;
+    int32_t rank_max;
+    double seconds;             /* call -> last block finished */
+    double mean_start_delay;    /* arrival -> first request of a block, mean over blocks */
+    double mean_block_seconds;  /* first request -> factors stored, mean over blocks */
+} bem_aca_run_stats;
+
+/* Approximates plan blocks blocks[0 .. n) with entries of precision prec;
+ * arrival (seconds after the call, non-decreasing) may be NULL: every block
+ * is available at once.  The factors replace those of the previous run. */
+int bem_aca_plan_run(bem_aca_plan *plan, const int64_t *blocks, const double *arrival, int64_t n, bem_prec prec,
+                     bem_aca_run_stats *stats);
+/* Factors of plan block b from the last run: *rank, and when U, V are not
+ * NULL, U column-major m x rank and V column-major n x rank (double or
+ * complex double), block ~= U V^T.  BEM_E_ARG if b was not in the last run. */
+int bem_aca_plan_factors(const bem_aca_plan *plan, int64_t b, int32_t *rank, void *U, void *V);
+int bem_aca_plan_destroy(bem_aca_plan *plan);
 
 #ifdef __cplusplus
 }

@@ -9,7 +9,11 @@ Contents
     P0/P1 Galerkin entries of the Laplace/Helmholtz single, double and
     adjoint double layer, and P1 entries of the hypersingular operator, over
     regular triangle pairs (Section 2, Eqs. slp, dlp, adlp, hypsHelmholtz;
-    Section 3.2).
+    Section 3.2); also entries on the discontinuous P1 space (DP1, dof
+    3 t + a: the barycentric function of local vertex a on triangle t), the
+    space whose single layer gives the hypersingular operator by sparse
+    transformations (Eq. hyp_via_slp), and those transformations
+    (``hyp_via_slp_factors``).
   * near-field fixtures (C, ``nearfield.c``) for vertex-sharing pairs, the
     reference of the device's singular scheme and of the closed-form sphere
     checks: P0 Laplace (closed-form inner potential and solid angle), P0
@@ -34,7 +38,7 @@ _LIB = None
 LAPLACE_SLP, LAPLACE_DLP, HELMHOLTZ_SLP, HELMHOLTZ_DLP = 0, 1, 2, 3
 LAPLACE_ADLP, HELMHOLTZ_ADLP = 4, 5
 LAPLACE_HYPS, HELMHOLTZ_HYPS = 6, 7
-P0, P1 = 0, 1
+P0, P1, DP1 = 0, 1, 2
 NEAR_ERROR, NEAR_SKIP = 0, 1
 OPS = {"laplace_slp": 0, "laplace_dlp": 1, "helmholtz_slp": 2, "helmholtz_dlp": 3, "laplace_adlp": 4,
        "helmholtz_adlp": 5, "laplace_hyps": 6, "helmholtz_hyps": 7}
@@ -278,6 +282,36 @@ class OracleMesh:
         if st != 0:
             raise ValueError("only Laplace single/double layer")
         return out
+
+
+def hyp_via_slp_factors(xyz, tri):
+    """The sparse matrices of Eq. hyp_via_slp as dense numpy arrays (small
+    meshes only): Q[j] (3 nt x nv), the j-th component of the surface curl
+    of each continuous hat function, constant on a triangle and written on
+    the discontinuous P1 space as that constant on all three local
+    functions; P[j] (3 nt x nv), the hat function of a vertex on each of its
+    triangles times the j-th component of the triangle's unit normal.  Then
+    D = sum_j Q_j^T S Q_j - k^2 sum_j P_j^T S P_j with S the single layer on
+    the discontinuous space.  The curl of the hat function of local vertex a
+    is n x grad lambda_a with grad lambda_a = n x E_a / J, E_a = v_{a+2} -
+    v_{a+1} the edge opposite a and J = |(v1 - v0) x (v2 - v0)|."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    tri = np.asarray(tri, dtype=np.int64)
+    nt, nv = tri.shape[0], xyz.shape[0]
+    Q = np.zeros((3, 3 * nt, nv))
+    P = np.zeros((3, 3 * nt, nv))
+    for t in range(nt):
+        v = xyz[tri[t]]
+        N = np.cross(v[1] - v[0], v[2] - v[0])
+        J = np.linalg.norm(N)
+        n = N / J
+        for a in range(3):
+            E = v[(a + 2) % 3] - v[(a + 1) % 3]
+            curl = np.cross(n, np.cross(n, E)) / J
+            for j in range(3):
+                Q[j, 3 * t:3 * t + 3, tri[t, a]] += curl[j]
+                P[j, 3 * t + a, tri[t, a]] = n[j]
+    return Q, P
 
 
 def max_threads() -> int:

@@ -334,6 +334,14 @@ static int orc_entry(const orc_mesh *m, int op, int space, double k, int64_t row
         orc_pair(m, op, k, row, col, -1, -1, re, im);
         return ORC_OK;
     }
+    if (space == ORC_DP1) {
+        /* discontinuous P1: dof 3 t + a is the barycentric function of local
+         * vertex a on triangle t alone, so an entry is one triangle pair with
+         * one basis function on each side */
+        if (orc_adjacent(m, row / 3, col / 3)) return near == ORC_NEAR_SKIP ? ORC_OK : ORC_E_NEARFIELD;
+        orc_pair(m, op, k, row / 3, col / 3, (int)(row % 3), (int)(col % 3), re, im);
+        return ORC_OK;
+    }
     /* P1: sum over test triangles m around vertex `row`, trial triangles n
      * around vertex `col`, both ascending. */
     double sr = 0.0, si = 0.0;
@@ -373,9 +381,9 @@ int orc_entries(const orc_mesh *m, int op, int space, double k,
                 const int32_t *rows, int64_t nr, const int32_t *cols, int64_t nc,
                 int near, double *out, int nthreads)
 {
-    if (op < 0 || op > 7 || (space != ORC_P0 && space != ORC_P1)) return ORC_E_ARG;
+    if (op < 0 || op > 7 || (space != ORC_P0 && space != ORC_P1 && space != ORC_DP1)) return ORC_E_ARG;
     if (orc_is_hyps(op) && space != ORC_P1) return ORC_E_ARG;   /* needs continuous trial/test functions */
-    int64_t ndof = space == ORC_P0 ? m->nt : m->nv;
+    int64_t ndof = space == ORC_P0 ? m->nt : (space == ORC_P1 ? m->nv : 3 * m->nt);
     for (int64_t r = 0; r < nr; ++r)
         if (rows[r] < 0 || rows[r] >= ndof) return ORC_E_ARG;
     for (int64_t c = 0; c < nc; ++c)

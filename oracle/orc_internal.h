@@ -20,7 +20,7 @@ enum {
     ORC_LAPLACE_HYPS = 6,
     ORC_HELMHOLTZ_HYPS = 7
 };
-enum { ORC_P0 = 0, ORC_P1 = 1 };
+enum { ORC_P0 = 0, ORC_P1 = 1, ORC_DP1 = 2 };
 enum { ORC_NEAR_ERROR = 0, ORC_NEAR_SKIP = 1 };
 
 /* ------------------------------------------------------------------------ */

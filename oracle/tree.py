@@ -15,7 +15,10 @@ this oracle takes them as follows, step by step:
       by coordinate, then dof index; the first floor(n/2) go left);
   block tree, from (root, root)
     * admissible iff dist > 0 and min(diam(tau), diam(sigma)) <= eta dist,
-      diameters and distance taken on the clusters' support boxes;
+      diameters and distance taken on the clusters' support boxes, and, when
+      a largest block dimension max_block > 0 is given, both clusters hold at
+      most max_block dofs (larger pairs split further, so no ACA row or
+      column is longer than max_block);
     * otherwise a dense leaf if either cluster is a leaf, else the four child
       pairs (t1,s1), (t1,s2), (t2,s1), (t2,s2) in that order.
 Support boxes make every admissible block free of vertex-sharing pairs.
@@ -102,20 +105,22 @@ def box_dist(lo1, hi1, lo2, hi2) -> float:
     return math.sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2])
 
 
-def admissible(t: Cluster, s: Cluster, eta: float) -> bool:
+def admissible(t: Cluster, s: Cluster, eta: float, max_block: int = 0) -> bool:
+    if max_block > 0 and max(t.idx.size, s.idx.size) > max_block:
+        return False
     d = box_dist(t.slo, t.shi, s.slo, s.shi)
     if not d > 0.0:
         return False
     return min(box_diam(t.slo, t.shi), box_diam(s.slo, s.shi)) <= eta * d
 
 
-def build_block_tree(nodes, eta: float):
+def build_block_tree(nodes, eta: float, max_block: int = 0):
     """Leaves as (tau_id, sigma_id, is_admissible) in depth-first order."""
     leaves = []
     stack = [(nodes[0], nodes[0])]
     while stack:
         t, s = stack.pop()
-        if admissible(t, s, eta):
+        if admissible(t, s, eta, max_block):
             leaves.append((t.id, s.id, True))
         elif not t.children or not s.children:
             leaves.append((t.id, s.id, False))
@@ -127,7 +132,7 @@ def build_block_tree(nodes, eta: float):
     return leaves
 
 
-def partition(xyz, tri, space: int, leaf_size: int = 100, eta: float = 1.0):
+def partition(xyz, tri, space: int, leaf_size: int = 100, eta: float = 1.0, max_block: int = 0):
     pts, slo, shi = dof_geometry(xyz, tri, space)
     nodes = build_cluster_tree(pts, slo, shi, leaf_size)
-    return nodes, build_block_tree(nodes, eta)
+    return nodes, build_block_tree(nodes, eta, max_block)

@@ -33,6 +33,8 @@ EXPORTS = [
     "bem_ticket_wait", "bem_ticket_times", "bem_ticket_free", "bem_eval_entries_async", "bem_server_config",
     "bem_server_stats", "bem_server_kernel_stats", "bem_aca_block", "bem_aca_callback", "bem_partition", "bem_hmat_assemble",
     "bem_hmat_matvec", "bem_hmat_stats_get", "bem_hmat_block_info", "bem_hmat_block_dense", "bem_hmat_destroy",
+    "bem_aca_plan_create", "bem_aca_plan_info", "bem_aca_plan_block", "bem_aca_plan_run", "bem_aca_plan_factors",
+    "bem_aca_plan_destroy",
 ]
 
 
@@ -85,7 +87,13 @@ class AcaParams(ctypes.Structure):
 class HmatParams(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
                 ("max_rank", ctypes.c_int32), ("n_workers", ctypes.c_int32), ("blocks_per_worker", ctypes.c_int32),
-                ("prec", ctypes.c_int), ("dense_mode", ctypes.c_int32)]
+                ("prec", ctypes.c_int), ("dense_mode", ctypes.c_int32), ("max_block", ctypes.c_int32)]
+
+
+class AcaRunStats(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_int64), ("entries", ctypes.c_int64), ("requests", ctypes.c_int64),
+                ("rank_sum", ctypes.c_int64), ("rank_max", ctypes.c_int32), ("seconds", ctypes.c_double),
+                ("mean_start_delay", ctypes.c_double), ("mean_block_seconds", ctypes.c_double)]
 
 
 class HmatStats(ctypes.Structure):
@@ -137,7 +145,7 @@ def lib():
     L.bem_aca_callback.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ROW_FN, COL_FN, _p,
                                    ctypes.POINTER(AcaParams), _p, _p, _i32p]
     L.bem_partition.argtypes = [_dp, ctypes.c_int64, _i32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int32,
-                                ctypes.c_double, _i32p, _i32p, _i32p, ctypes.c_int64, _i32p, ctypes.c_int64, _i64p,
+                                ctypes.c_double, ctypes.c_int32, _i32p, _i32p, _i32p, ctypes.c_int64, _i32p, ctypes.c_int64, _i64p,
                                 _i64p]
     L.bem_hmat_assemble.argtypes = [_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(HmatParams),
                                     ctypes.POINTER(_p)]
@@ -147,6 +155,13 @@ def lib():
                                       ctypes.POINTER(_i32p)]
     L.bem_hmat_block_dense.argtypes = [_p, ctypes.c_int64, _p]
     L.bem_hmat_destroy.argtypes = [_p]
+    L.bem_aca_plan_create.argtypes = [_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(HmatParams),
+                                      ctypes.POINTER(_p)]
+    L.bem_aca_plan_info.argtypes = [_p, _i64p, _i64p, _dp]
+    L.bem_aca_plan_block.argtypes = [_p, ctypes.c_int64, _i64p, _i64p, ctypes.POINTER(_i32p), ctypes.POINTER(_i32p)]
+    L.bem_aca_plan_run.argtypes = [_p, _i64p, _dp, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(AcaRunStats)]
+    L.bem_aca_plan_factors.argtypes = [_p, ctypes.c_int64, _i32p, _p, _p]
+    L.bem_aca_plan_destroy.argtypes = [_p]
     _LIB = L
     return L
 
@@ -338,14 +353,14 @@ def aca_callback(get_row, get_col, m, n, tol=1e-5, max_rank=200, zero_abs=0.0, i
     return U[:r].T.copy(), V[:r].T.copy()
 
 
-def partition(xyz, tri, space, leaf_size=100, eta=1.0):
+def partition(xyz, tri, space, leaf_size=100, eta=1.0, max_block=0):
     """(perm, cluster ranges [(begin, end)], blocks [(tau, sigma, admissible)])."""
     xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64))
     tri = np.ascontiguousarray(np.asarray(tri, dtype=np.int32))
     nd = xyz.shape[0] if space == P1 else tri.shape[0]
     nc, nb = ctypes.c_int64(), ctypes.c_int64()
     rc = lib().bem_partition(xyz.ctypes.data_as(_dp), xyz.shape[0], _ip(tri), tri.shape[0], space, leaf_size,
-                             float(eta), None, None, None, 0, None, 0, ctypes.byref(nc), ctypes.byref(nb))
+                             float(eta), int(max_block), None, None, None, 0, None, 0, ctypes.byref(nc), ctypes.byref(nb))
     if rc not in (OK, E_ARG) or nc.value <= 0:
         _check(rc)
     perm = np.zeros(nd, dtype=np.int32)
@@ -353,7 +368,7 @@ def partition(xyz, tri, space, leaf_size=100, eta=1.0):
     ce = np.zeros(nc.value, dtype=np.int32)
     blocks = np.zeros((nb.value, 3), dtype=np.int32)
     _check(lib().bem_partition(xyz.ctypes.data_as(_dp), xyz.shape[0], _ip(tri), tri.shape[0], space, leaf_size,
-                               float(eta), _ip(perm), _ip(cb), _ip(ce), nc.value, _ip(blocks), nb.value,
+                               float(eta), int(max_block), _ip(perm), _ip(cb), _ip(ce), nc.value, _ip(blocks), nb.value,
                                ctypes.byref(nc), ctypes.byref(nb)))
     return perm, np.stack([cb, ce], axis=1), blocks
 
@@ -400,8 +415,73 @@ class HMatrix:
 
 
 def hmat_assemble(mesh: Mesh, op, space, k, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200, n_workers=8,
-                  blocks_per_worker=32, prec=FP32, dense_mode=0) -> HMatrix:
-    prm = HmatParams(leaf_size, eta, aca_tol, max_rank, n_workers, blocks_per_worker, prec, dense_mode)
+                  blocks_per_worker=32, prec=FP32, dense_mode=0, max_block=0) -> HMatrix:
+    prm = HmatParams(leaf_size, eta, aca_tol, max_rank, n_workers, blocks_per_worker, prec, dense_mode, max_block)
     h = _p()
     _check(lib().bem_hmat_assemble(mesh.handle, op, space, float(k), ctypes.byref(prm), ctypes.byref(h)))
     return HMatrix(h, mesh.nt if space == P0 else mesh.nv, is_complex(op))
+
+
+class AcaPlan:
+    """Handle of an ACA plan (bem_aca_plan_create): partition and resident
+    lane sets of one operator, serving runs over its admissible blocks."""
+
+    def __init__(self, handle, cplx):
+        self.handle = handle
+        self.cplx = cplx
+
+    def info(self):
+        nb, nd, st = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().bem_aca_plan_info(self.handle, ctypes.byref(nb), ctypes.byref(nd), ctypes.byref(st)))
+        return {"blocks": nb.value, "ndof": nd.value, "setup_seconds": st.value}
+
+    def block(self, b):
+        m, n = ctypes.c_int64(), ctypes.c_int64()
+        rp, cp = _i32p(), _i32p()
+        _check(lib().bem_aca_plan_block(self.handle, int(b), ctypes.byref(m), ctypes.byref(n), ctypes.byref(rp),
+                                        ctypes.byref(cp)))
+        return (np.ctypeslib.as_array(rp, shape=(m.value,)).copy(),
+                np.ctypeslib.as_array(cp, shape=(n.value,)).copy())
+
+    def run(self, blocks, arrival=None, prec=FP32) -> dict:
+        blocks = np.ascontiguousarray(np.asarray(blocks, dtype=np.int64).ravel())
+        arr = None
+        if arrival is not None:
+            arr = np.ascontiguousarray(np.asarray(arrival, dtype=np.float64).ravel())
+            if arr.size != blocks.size:
+                raise ValueError("one arrival time per block")
+        st = AcaRunStats()
+        _check(lib().bem_aca_plan_run(self.handle, blocks.ctypes.data_as(_i64p),
+                                      arr.ctypes.data_as(_dp) if arr is not None else None, blocks.size, prec,
+                                      ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in AcaRunStats._fields_}
+
+    def factors(self, b):
+        rows, cols = self.block(b)
+        r = ctypes.c_int32()
+        _check(lib().bem_aca_plan_factors(self.handle, int(b), ctypes.byref(r), None, None))
+        dt = np.complex128 if self.cplx else np.float64
+        U = np.zeros((r.value, rows.size), dtype=dt)
+        V = np.zeros((r.value, cols.size), dtype=dt)
+        _check(lib().bem_aca_plan_factors(self.handle, int(b), ctypes.byref(r), U.ctypes.data_as(_p),
+                                          V.ctypes.data_as(_p)))
+        return U.T.copy(), V.T.copy()
+
+    def destroy(self):
+        if self.handle:
+            lib().bem_aca_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def aca_plan_create(mesh: Mesh, op, space, k, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200, n_workers=8,
+                    blocks_per_worker=32, prec=FP32, max_block=0) -> AcaPlan:
+    prm = HmatParams(leaf_size, eta, aca_tol, max_rank, n_workers, blocks_per_worker, prec, 0, max_block)
+    h = _p()
+    _check(lib().bem_aca_plan_create(mesh.handle, op, space, float(k), ctypes.byref(prm), ctypes.byref(h)))
+    return AcaPlan(h, is_complex(op))

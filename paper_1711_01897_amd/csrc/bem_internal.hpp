@@ -216,6 +216,7 @@ struct bem_mesh {
     std::vector<int32_t> tri;         // nt x 3
     std::vector<int64_t> star_ptr;    // nv + 1
     std::vector<int32_t> star;        // packed (triangle << 2 | local vertex), ascending triangles
+    std::vector<int32_t> dp1_star;    // 3 nt: star-table position of (triangle t, local vertex a) at 3 t + a
     double mean_J = 0.0, mean_edge = 0.0;
     double box_lo[3] = {0.0, 0.0, 0.0}, box_inv[3] = {0.0, 0.0, 0.0};   // bounding box: low corner, 1/extent
     int max_star = 0;
@@ -344,6 +345,12 @@ struct Request {
 };
 
 bool is_complex_op(int op);
+// Dofs of a space on a mesh: triangles (P0), vertices (P1), 3 x triangles (DP1).
+int64_t space_ndof(const bem_mesh &m, int space);
+// The entry kernels' space: P0 kernels for P0, the P1 kernels (fixed star
+// against lane triangles, per-dof reduction) for P1 and DP1 (a DP1 dof is a
+// one-triangle star).
+inline int kernel_space(int space) { return space == BEM_P0 ? BEM_P0 : BEM_P1; }
 bool is_adjoint_op(int op);
 // The operator the entry kernels evaluate: the adjoint double layer runs as
 // the double layer with test and trial exchanged.

@@ -24,6 +24,12 @@ int hmat_block_info(const bem_hmat *, int64_t, int32_t *, int64_t *, int64_t *, 
 int hmat_block_dense(const bem_hmat *, int64_t, void *);
 int hmat_stats(const bem_hmat *, bem_hmat_stats *);
 int hmat_destroy(bem_hmat *);
+int plan_create(bem_mesh *, int, int, double, const bem_hmat_params *, bem_aca_plan **);
+int plan_info(const bem_aca_plan *, int64_t *, int64_t *, double *);
+int plan_block(const bem_aca_plan *, int64_t, int64_t *, int64_t *, const int32_t **, const int32_t **);
+int plan_run(bem_aca_plan *, const int64_t *, const double *, int64_t, int, bem_aca_run_stats *);
+int plan_factors(const bem_aca_plan *, int64_t, int32_t *, void *, void *);
+int plan_destroy(bem_aca_plan *);
 }  // namespace bem
 
 using namespace bem;
@@ -224,7 +230,7 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     const size_t off_b = off;
     off = al(off + sizeof(EntryBlock) * (size_t)r.nblocks);
     const size_t off_near = off;
-    const bool p1_near = r.space == BEM_P1 && !r.near_items.empty();
+    const bool p1_near = r.space != BEM_P0 && !r.near_items.empty();
     off = al(off + (p1_near ? near_p1_layout(r).bytes : sizeof(NearItem) * r.near_items.size()));
     const size_t off_in = off;
     off = al(off + r.in_bytes);
@@ -310,12 +316,12 @@ int bem_aca_callback(int64_t m, int64_t n, int is_complex, bem_row_fn get_row, b
 }
 
 int bem_partition(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, bem_space space, int32_t leaf_size,
-                  double eta, int32_t *perm, int32_t *cl_begin, int32_t *cl_end, int64_t max_clusters, int32_t *blocks,
+                  double eta, int32_t max_block, int32_t *perm, int32_t *cl_begin, int32_t *cl_end, int64_t max_clusters, int32_t *blocks,
                   int64_t max_blocks, int64_t *nclusters, int64_t *nblocks)
 {
-    if (!xyz || !tri || nv < 1 || nt < 1 || leaf_size < 1 || !(eta > 0) || !nclusters || !nblocks)
+    if (!xyz || !tri || nv < 1 || nt < 1 || leaf_size < 1 || !(eta > 0) || max_block < 0 || !nclusters || !nblocks)
         return fail(BEM_E_ARG, "bad partition arguments");
-    if (space != BEM_P0 && space != BEM_P1) return fail(BEM_E_ARG, "unknown space");
+    if (space != BEM_P0 && space != BEM_P1 && space != BEM_DP1) return fail(BEM_E_ARG, "unknown space");
     for (int64_t i = 0; i < 3 * nt; ++i)
         if (tri[i] < 0 || tri[i] >= nv) return fail(BEM_E_ARG, "triangle vertex index out of range");
     bem_mesh m;
@@ -326,7 +332,7 @@ int bem_partition(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
     std::vector<double> pts, slo, shi;
     dof_geometry(m, space, pts, slo, shi);
     Partition P;
-    build_partition(pts, slo, shi, leaf_size, eta, P);
+    build_partition(pts, slo, shi, leaf_size, eta, max_block, P);
     *nclusters = (int64_t)P.nodes.size();
     *nblocks = (int64_t)P.blocks.size();
     if ((int64_t)P.nodes.size() > max_clusters || (int64_t)P.blocks.size() > max_blocks)
@@ -364,5 +370,35 @@ int bem_hmat_block_info(const bem_hmat *h, int64_t b, int32_t *admissible, int64
 int bem_hmat_block_dense(const bem_hmat *h, int64_t b, void *out) { return hmat_block_dense(h, b, out); }
 
 int bem_hmat_destroy(bem_hmat *h) { return hmat_destroy(h); }
+
+int bem_aca_plan_create(bem_mesh *mesh, bem_op op, bem_space space, double k, const bem_hmat_params *params,
+                        bem_aca_plan **out)
+{
+    return plan_create(mesh, op, space, k, params, out);
+}
+
+int bem_aca_plan_info(const bem_aca_plan *plan, int64_t *n_blocks, int64_t *ndof, double *setup_seconds)
+{
+    return plan_info(plan, n_blocks, ndof, setup_seconds);
+}
+
+int bem_aca_plan_block(const bem_aca_plan *plan, int64_t b, int64_t *m, int64_t *n, const int32_t **rows,
+                       const int32_t **cols)
+{
+    return plan_block(plan, b, m, n, rows, cols);
+}
+
+int bem_aca_plan_run(bem_aca_plan *plan, const int64_t *blocks, const double *arrival, int64_t n, bem_prec prec,
+                     bem_aca_run_stats *stats)
+{
+    return plan_run(plan, blocks, arrival, n, prec, stats);
+}
+
+int bem_aca_plan_factors(const bem_aca_plan *plan, int64_t b, int32_t *rank, void *U, void *V)
+{
+    return plan_factors(plan, b, rank, U, V);
+}
+
+int bem_aca_plan_destroy(bem_aca_plan *plan) { return plan_destroy(plan); }
 
 }  // extern "C"

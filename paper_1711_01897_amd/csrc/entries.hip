@@ -870,15 +870,67 @@ __device__ __forceinline__ int stage_star_tab(const EntryBlock &B, int sb, int s
 // compensated partial sums (one per local vertex of the lane triangle) go to
 // LDS.  Phase 2: thread j adds, for dof j of the chunk, the partials its
 // segment list names, in order, compensated, and stores the entry.
+// Lane groups of a P1 chunk.  A chunk of at most 64 (128) lane triangles
+// runs on all four wavefronts: the workgroup is cut into 4 (2) groups of one
+// (two) wavefronts, every group holds all lanes and takes every 4th (2nd)
+// triangle of the fixed star, and the groups' partial sums are combined in
+// group order before the per-entry reduction.  Small requests (the rows and
+// columns of small admissible blocks) then keep every wavefront busy
+// instead of leaving three of four idle.  Workgroup-uniform.
+struct LaneGroups {
+    int size;    // threads (lanes) per group
+    int count;   // groups: 4, 2 or 1
+    __device__ __forceinline__ explicit LaneGroups(int lanes)
+    {
+        size = lanes <= 64 ? 64 : (lanes <= 128 ? 128 : kBlockLanes);
+        count = kBlockLanes / size;
+    }
+};
+
+// Combines the groups' compensated partials of lane t < G.size into sP[t]
+// (group order).  Every thread of the workgroup calls it (it synchronises).
+template <bool CPLX>
+__device__ __forceinline__ void combine_groups_f32(const LaneGroups &G, int lanes, float4 (*sP)[3])
+{
+    if (G.count == 1) return;
+    const int t = threadIdx.x;
+    float4 c[3];
+    const bool mine = t < G.size && t < lanes;
+    if (mine) {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            c[e] = sP[t][e];
+            for (int g = 1; g < G.count; ++g) {
+                const float4 v = sP[t + g * G.size][e];
+                two_sum_acc(c[e].x, c[e].y, v.x);
+                c[e].y += v.y;
+                if constexpr (CPLX) {
+                    two_sum_acc(c[e].z, c[e].w, v.z);
+                    c[e].w += v.w;
+                }
+            }
+        }
+    }
+    __syncthreads();   // every group's partials have been read
+    if (mine) {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) sP[t][e] = c[e];
+    }
+    __syncthreads();
+}
+
 template <int OP, int Q, bool ROWFIX>
 __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B, float (*sG)[nstar32<Q>()], int4 *sV,
                                             int *sL, float4 (*sP)[3])
 {
     const int4 ch = B.chunk;   // first lane, lanes, first dof, dofs
     const int t = threadIdx.x;
-    const bool wact = (t & ~63) < ch.y;   // wave-uniform
-    const bool act = t < ch.y;
-    const int li = ch.x + (act ? t : 0);
+    const LaneGroups G(ch.y);
+    const int lt = t % G.size;             // lane of this thread
+    const int grp = t / G.size;            // its group: star entries s0 + grp, s0 + grp + G.count, ...
+    const bool wact = (lt & ~63) < ch.y;   // wave-uniform
+    const bool act = lt < ch.y;
+    const int li = ch.x + (act ? lt : 0);
     float L[n32<Q>()];
     int4 vn;
     if (B.lgeo && ch.y > 0) {
@@ -909,11 +961,12 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     // phase 1 computes (after the first stage, so the stage barrier does not
     // wait for it)
     SegPrefetch pf;
+    static_assert(kStage % 4 == 0, "every stage starts a new round of the lane groups");
     for (int sb = s0; sb < s1; sb += kStage) {
         const int ns = stage_star_tab<Q, !ROWFIX>(B, sb, s1, sG, sV, sL);
         if (sb == s0) pf.fetch(R, ch, t);
         if (!wact) continue;
-        for (int s = 0; s < ns; ++s) {
+        for (int s = grp; s < ns; s += G.count) {
             if (share_vertex(sV[s], vn)) {
                 if (act && R.near_error) *R.status = 1;
                 continue;
@@ -948,6 +1001,7 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     }
     if (s0 == s1) pf.fetch(R, ch, t);
     __syncthreads();
+    combine_groups_f32<is_cplx<OP>()>(G, ch.y, sP);
     for (int j = t; j < ch.w; j += kBlockLanes) {
         const int d = ch.z + j;
         int g0, g1;
@@ -1012,9 +1066,12 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
 {
     const int4 ch = B.chunk;
     const int t = threadIdx.x;
-    const bool wact = (t & ~63) < ch.y;
-    const bool act = t < ch.y;
-    const int li = ch.x + (act ? t : 0);
+    const LaneGroups G(ch.y);
+    const int lt = t % G.size;
+    const int grp = t / G.size;
+    const bool wact = (lt & ~63) < ch.y;
+    const bool act = lt < ch.y;
+    const int li = ch.x + (act ? lt : 0);
     const int tn = ch.y > 0 ? R.lane[li] : 0;
     const int4 vn = R.vtx[tn];
     double L[n64<Q>()];
@@ -1026,7 +1083,7 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
         const int ns = stage_star<double, n64<Q>()>(R, R.g64, kGeo64Stride, sb, s1, sG, sV, sL);
         if (sb == s0) pf.fetch(R, ch, t);
         if (!wact) continue;
-        for (int s = 0; s < ns; ++s) {
+        for (int s = grp; s < ns; s += G.count) {
             if (share_vertex(sV[s], vn)) {
                 if (act && R.near_error) *R.status = 1;
                 continue;
@@ -1060,6 +1117,27 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
     }
     if (s0 == s1) pf.fetch(R, ch, t);
     __syncthreads();
+    if (G.count > 1) {
+        // the groups' partials of lane t, added in group order
+        double2 c[3];
+        const bool mine = t < G.size && t < ch.y;
+        if (mine) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                c[e] = sP[t][e];
+                for (int g = 1; g < G.count; ++g) {
+                    c[e].x += sP[t + g * G.size][e].x;
+                    c[e].y += sP[t + g * G.size][e].y;
+                }
+            }
+        }
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) sP[t][e] = c[e];
+        }
+        __syncthreads();
+    }
     for (int j = t; j < ch.w; j += kBlockLanes) {
         const int d = ch.z + j;
         int g0, g1;

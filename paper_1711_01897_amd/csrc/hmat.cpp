@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <complex>
+#include <chrono>
 #include <deque>
 #include <type_traits>
 #include <thread>
@@ -135,7 +136,9 @@ namespace {
 double vanish_scale(const bem_mesh &m, int op, int space, double k, double dist)
 {
     const double d = dist > 0.0 ? dist : m.mean_edge;
-    const double J2 = m.mean_J * m.mean_J * (space == BEM_P0 ? 0.25 : 1.0);
+    // (integral of a basis function)^2 ~ J^2 times (1/2)^2 for P0 (a triangle),
+    // 1 for P1 (a star of ~6 triangles, 1/3 each), (1/6)^2 for DP1
+    const double J2 = m.mean_J * m.mean_J * (space == BEM_P0 ? 0.25 : (space == BEM_P1 ? 1.0 : 1.0 / 36.0));
     const double inv4pi = 0.0795774715459476678844418816862571;
     if (op == BEM_LAPLACE_SLP || op == BEM_HELMHOLTZ_SLP) return J2 * inv4pi / d;
     if (op == BEM_LAPLACE_HYPS || op == BEM_HELMHOLTZ_HYPS)   // second derivatives of g, plus the k^2 term
@@ -167,6 +170,8 @@ void support_box(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, d
     for (int64_t i = 0; i < n; ++i) {
         if (space == BEM_P0) {
             add_tri(dofs[i]);
+        } else if (space == BEM_DP1) {
+            add_tri(dofs[i] / 3);
         } else {
             for (int64_t s = m.star_ptr[dofs[i]]; s < m.star_ptr[dofs[i] + 1]; ++s) add_tri(m.star[s] >> 2);
         }
@@ -411,6 +416,7 @@ template <typename T>
 struct Slot {
     int64_t leaf = -1;
     bool adm = false;
+    double t_start = 0.0;
     AcaCore<T> core;
     Request req;
     std::vector<T> buf;
@@ -426,6 +432,8 @@ struct AssemblyCtx {
     const std::vector<LaneRef> *lanes;  // per cluster id
     int dense_near = BEM_NEAR_SKIP;      // near-field policy of the dense leaves
     std::vector<Job> jobs;
+    const double *arrival = nullptr;     // per job: earliest start, seconds after t0 (null: all at t0)
+    double t0 = 0.0;
     std::atomic<int64_t> next{0};
     std::atomic<int> error{0};
     std::mutex err_mu;
@@ -436,6 +444,8 @@ struct AssemblyCtx {
     double qdelay = 0.0, proc = 0.0;   // completion -> pickup, pickup -> resubmit (summed over requests)
     int64_t nproc = 0;
     double t_conv = 0.0, t_aca = 0.0, t_rel = 0.0, t_prep = 0.0, t_flush = 0.0;   // worker phases (summed)
+    double start_delay = 0.0, block_time = 0.0;   // arrival -> start, start -> done (summed over blocks)
+    int64_t blocks_done = 0;
 
     void set_error(int code, const std::string &msg)
     {
@@ -540,16 +550,31 @@ void worker(AssemblyCtx &C, int per_worker)
         rel_n = 0;
     };
     bool exhausted = false;
-    auto start_job = [&](int64_t si) -> bool {
+    double start_delay = 0.0, block_time = 0.0;
+    int64_t blocks_done = 0;
+    const int64_t njobs = (int64_t)C.jobs.size();
+    // Takes the next job into slot si if it has arrived: 1 started, 0 the next
+    // job has not arrived yet, -1 none left (or an error).
+    auto start_job = [&](int64_t si) -> int {
         Slot<T> &s = slots[si];
-        if (exhausted || C.error.load()) return false;
-        const int64_t j = C.next.fetch_add(1);
-        if (j >= (int64_t)C.jobs.size()) {
-            exhausted = true;
-            return false;
+        if (exhausted || C.error.load()) return -1;
+        int64_t j = C.next.load(std::memory_order_relaxed);
+        double t = 0.0;
+        for (;;) {
+            if (j >= njobs) {
+                exhausted = true;
+                return -1;
+            }
+            if (C.arrival) {
+                t = now_seconds();
+                if (C.t0 + C.arrival[j] > t) return 0;
+            }
+            if (C.next.compare_exchange_weak(j, j + 1)) break;
         }
+        if (C.arrival) start_delay += t - (C.t0 + C.arrival[j]);
         s.leaf = C.jobs[j].leaf;
         s.adm = C.jobs[j].adm != 0;
+        s.t_start = now_seconds();
         if (s.adm) {
             const bem_hmat::Leaf &L = C.h->leaves[s.leaf];
             const Block &bk = C.h->part.blocks[s.leaf];
@@ -561,12 +586,21 @@ void worker(AssemblyCtx &C, int per_worker)
         const int rc = prepare_slot(C, s, dq, si, tally);
         if (rc != BEM_OK) {
             C.set_error(rc, std::string("request: ") + bem_last_error());
-            return false;
+            return -1;
         }
         s.busy = true;
         ++active;
         submit.push_back(&s.req);
-        return true;
+        return 1;
+    };
+    // free slots, lowest index on top
+    std::vector<int64_t> free_slots;
+    for (int64_t si = per_worker - 1; si >= 0; --si) free_slots.push_back(si);
+    auto fill = [&]() {
+        while (!free_slots.empty()) {
+            if (start_job(free_slots.back()) <= 0) break;
+            free_slots.pop_back();
+        }
     };
     auto flush = [&]() {
         if (submit.empty()) return;
@@ -577,6 +611,7 @@ void worker(AssemblyCtx &C, int per_worker)
             for (Request *r : submit) {
                 slots[r->tag].busy = false;
                 --active;
+                free_slots.push_back(r->tag);
             }
         }
         submit.clear();
@@ -585,10 +620,26 @@ void worker(AssemblyCtx &C, int per_worker)
     double tc = 0.0, ta = 0.0, tr = 0.0, tp = 0.0, tf = 0.0;
     int64_t np = 0;
     double tb = now_seconds();
-    for (int64_t si = 0; si < per_worker; ++si)
-        if (!start_job(si)) break;
+    fill();
     flush();
-    while (active > 0) {
+    for (;;) {
+        if (active == 0) {
+            if (exhausted || C.error.load()) break;
+            // nothing in flight and the next block has not arrived: sleep until
+            // it does (in short steps, so an error elsewhere is seen soon)
+            const int64_t j = C.next.load();
+            if (j < njobs && C.arrival) {
+                const double wait = C.t0 + C.arrival[j] - now_seconds();
+                if (wait > 0.0) {
+                    busy += now_seconds() - tb;
+                    std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 2e-4)));
+                    tb = now_seconds();
+                }
+            }
+            fill();
+            flush();
+            continue;
+        }
         busy += now_seconds() - tb;
         dq.pop_some(done, (size_t)pop_most);
         tb = now_seconds();
@@ -649,7 +700,10 @@ void worker(AssemblyCtx &C, int per_worker)
             if (finished || C.error.load()) {
                 s.busy = false;
                 --active;
-                if (!C.error.load()) start_job(r->tag);
+                block_time += now_seconds() - s.t_start;
+                ++blocks_done;
+                free_slots.push_back(r->tag);
+                if (!C.error.load()) fill();
                 continue;
             }
             const double p0 = now_seconds();
@@ -659,6 +713,7 @@ void worker(AssemblyCtx &C, int per_worker)
                 C.set_error(rc, std::string("request: ") + bem_last_error());
                 s.busy = false;
                 --active;
+                free_slots.push_back(r->tag);
                 continue;
             }
             submit.push_back(&s.req);
@@ -666,6 +721,7 @@ void worker(AssemblyCtx &C, int per_worker)
         release_run();
         const size_t nd = done.size();
         done.clear();
+        fill();   // blocks that arrived meanwhile
         const double f0 = now_seconds();
         flush();
         tf += now_seconds() - f0;
@@ -687,6 +743,9 @@ void worker(AssemblyCtx &C, int per_worker)
     C.t_rel += tr;
     C.t_prep += tp;
     C.t_flush += tf;
+    C.start_delay += start_delay;
+    C.block_time += block_time;
+    C.blocks_done += blocks_done;
 }
 
 template <typename T>
@@ -815,7 +874,7 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
 {
     if (!mesh || !p || !out) return fail(BEM_E_ARG, "null argument");
     if (p->leaf_size < 1 || !(p->eta > 0) || p->max_rank < 1 || !(p->aca_tol >= 0) || p->dense_mode < 0 ||
-        p->dense_mode > 2)
+        p->dense_mode > 2 || p->max_block < 0)
         return fail(BEM_E_ARG, "bad H-matrix parameters");
     {
         // validate op/k/space/prec once with an empty request
@@ -834,10 +893,10 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
     h->op = op;
     h->space = space;
     h->cplx = is_complex_op(op);
-    h->ndof = space == BEM_P0 ? mesh->nt : mesh->nv;
+    h->ndof = space_ndof(*mesh, space);
     std::vector<double> pts, slo, shi;
     dof_geometry(*mesh, space, pts, slo, shi);
-    build_partition(pts, slo, shi, p->leaf_size, p->eta, h->part);
+    build_partition(pts, slo, shi, p->leaf_size, p->eta, p->max_block, h->part);
     const double t_part = now_seconds();
     const auto &P = h->part;
     h->leaves.resize(P.blocks.size());
@@ -939,6 +998,200 @@ int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_pa
         server_print_phases();
     }
     *out = h;
+    return BEM_OK;
+}
+
+}  // namespace bem
+
+// An ACA plan: the partition and resident lane sets of one operator on one
+// mesh, kept between runs; the H-matrix object holds the leaves, whose
+// factors are those of the last run.
+struct bem_aca_plan {
+    bem_mesh *mesh = nullptr;
+    int op = 0, space = 0;
+    double k = 0.0;
+    bem_hmat_params p{};
+    bem_hmat *h = nullptr;
+    bem::ResidentLanes lanes;
+    std::vector<int64_t> adm;       // leaf index of each plan block
+    std::vector<int64_t> last;      // leaves of the last run
+    double setup_seconds = 0.0;
+    std::mutex run_mu;              // one run at a time
+    ~bem_aca_plan() { delete h; }
+};
+
+namespace bem {
+
+int plan_create(bem_mesh *mesh, int op, int space, double k, const bem_hmat_params *p, bem_aca_plan **out)
+{
+    if (!mesh || !p || !out) return fail(BEM_E_ARG, "null argument");
+    if (p->leaf_size < 1 || !(p->eta > 0) || p->max_rank < 1 || !(p->aca_tol >= 0) || p->max_block < 0 ||
+        p->n_workers < 1 || p->blocks_per_worker < 1)
+        return fail(BEM_E_ARG, "bad plan parameters");
+    {
+        Request probe;
+        probe.mesh = mesh;
+        probe.op = op;
+        probe.space = space;
+        probe.prec = p->prec;
+        probe.k = k;
+        probe.near = BEM_NEAR_ERROR;
+        const int rc = expand_request(probe);
+        if (rc != BEM_OK) return rc;
+    }
+    const double t0 = now_seconds();
+    bem_aca_plan *pl = new bem_aca_plan();
+    pl->mesh = mesh;
+    pl->op = op;
+    pl->space = space;
+    pl->k = k;
+    pl->p = *p;
+    pl->h = new bem_hmat();
+    bem_hmat *h = pl->h;
+    h->op = op;
+    h->space = space;
+    h->cplx = is_complex_op(op);
+    h->ndof = space_ndof(*mesh, space);
+    std::vector<double> pts, slo, shi;
+    dof_geometry(*mesh, space, pts, slo, shi);
+    build_partition(pts, slo, shi, p->leaf_size, p->eta, p->max_block, h->part);
+    const auto &P = h->part;
+    h->leaves.resize(P.blocks.size());
+    std::vector<std::pair<const int32_t *, int64_t>> lists(P.nodes.size(), {nullptr, 0});
+    for (size_t b = 0; b < P.blocks.size(); ++b) {
+        const Block &bk = P.blocks[b];
+        const Cluster &a = P.nodes[bk.tau], &c = P.nodes[bk.sigma];
+        auto &L = h->leaves[b];
+        L.adm = bk.admissible;
+        L.r0 = a.begin;
+        L.m = a.end - a.begin;
+        L.c0 = c.begin;
+        L.n = c.end - c.begin;
+        if (!bk.admissible) continue;
+        pl->adm.push_back((int64_t)b);
+        for (int cid : {bk.tau, bk.sigma}) {
+            const Cluster &cl = P.nodes[cid];
+            lists[cid] = {P.perm.data() + cl.begin, cl.end - cl.begin};
+        }
+    }
+    const int rc = make_resident(*mesh, space, lists, pl->lanes);
+    if (rc != BEM_OK) {
+        delete pl;
+        return rc;
+    }
+    pl->setup_seconds = now_seconds() - t0;
+    *out = pl;
+    return BEM_OK;
+}
+
+int plan_info(const bem_aca_plan *pl, int64_t *nb, int64_t *ndof, double *setup)
+{
+    if (!pl) return fail(BEM_E_ARG, "null plan");
+    if (nb) *nb = (int64_t)pl->adm.size();
+    if (ndof) *ndof = pl->h->ndof;
+    if (setup) *setup = pl->setup_seconds;
+    return BEM_OK;
+}
+
+int plan_block(const bem_aca_plan *pl, int64_t b, int64_t *m, int64_t *n, const int32_t **rows, const int32_t **cols)
+{
+    if (!pl || b < 0 || b >= (int64_t)pl->adm.size()) return fail(BEM_E_ARG, "plan block out of range");
+    const auto &L = pl->h->leaves[pl->adm[b]];
+    if (m) *m = L.m;
+    if (n) *n = L.n;
+    if (rows) *rows = pl->h->rows(L);
+    if (cols) *cols = pl->h->cols(L);
+    return BEM_OK;
+}
+
+int plan_run(bem_aca_plan *pl, const int64_t *blocks, const double *arrival, int64_t n, int prec,
+             bem_aca_run_stats *st)
+{
+    if (!pl || (n > 0 && !blocks) || n < 0) return fail(BEM_E_ARG, "bad run arguments");
+    if (prec != BEM_FP32 && prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
+    const int64_t nb = (int64_t)pl->adm.size();
+    for (int64_t i = 0; i < n; ++i) {
+        if (blocks[i] < 0 || blocks[i] >= nb) return fail(BEM_E_ARG, "plan block out of range");
+        if (arrival && (!std::isfinite(arrival[i]) || arrival[i] < 0.0 || (i > 0 && arrival[i] < arrival[i - 1])))
+            return fail(BEM_E_ARG, "arrival times must be finite, >= 0 and non-decreasing");
+    }
+    std::lock_guard<std::mutex> run_guard(pl->run_mu);
+    bem_hmat *h = pl->h;
+    // the previous run's factors go back to the pool
+    for (int64_t leaf : pl->last) {
+        auto &L = h->leaves[leaf];
+        L.rank = 0;
+        L.U = L.V = nullptr;
+    }
+    pl->last.clear();
+    value_pool().give(h->store);
+    AssemblyCtx C;
+    C.mesh = pl->mesh;
+    C.op = pl->op;
+    C.space = pl->space;
+    C.prec = prec;
+    C.k = pl->k;
+    C.tol = pl->p.aca_tol;
+    C.max_rank = pl->p.max_rank;
+    C.h = h;
+    C.lanes = &pl->lanes.refs;
+    C.jobs.reserve((size_t)n);
+    for (int64_t i = 0; i < n; ++i) C.jobs.push_back(Job{pl->adm[blocks[i]], 1});
+    C.arrival = arrival;
+    const int nw = std::max(1, pl->p.n_workers);
+    const int per = std::max(1, pl->p.blocks_per_worker);
+    C.t0 = now_seconds();
+    std::vector<std::thread> th;
+    for (int w = 0; w < nw; ++w) {
+        if (h->cplx)
+            th.emplace_back([&] { worker<cd>(C, per); });
+        else
+            th.emplace_back([&] { worker<double>(C, per); });
+    }
+    for (auto &t : th) t.join();
+    const double t1 = now_seconds();
+    for (const Job &j : C.jobs) pl->last.push_back(j.leaf);
+    if (C.error.load() != 0) return fail(C.error.load(), "ACA run: " + C.err_msg);
+    if (st) {
+        *st = bem_aca_run_stats{};
+        st->blocks = n;
+        st->entries = C.aca_entries.load();
+        st->requests = C.requests.load();
+        for (const Job &j : C.jobs) {
+            const auto &L = h->leaves[j.leaf];
+            st->rank_sum += L.rank;
+            st->rank_max = std::max(st->rank_max, (int32_t)L.rank);
+        }
+        st->seconds = t1 - C.t0;
+        const double nd = (double)std::max<int64_t>(1, C.blocks_done);
+        st->mean_start_delay = C.start_delay / nd;
+        st->mean_block_seconds = C.block_time / nd;
+    }
+    if (std::getenv("BEM_DEBUG_TIMING")) server_print_phases();
+    return BEM_OK;
+}
+
+int plan_factors(const bem_aca_plan *pl, int64_t b, int32_t *rank, void *U, void *V)
+{
+    if (!pl || !rank || b < 0 || b >= (int64_t)pl->adm.size()) return fail(BEM_E_ARG, "plan block out of range");
+    const int64_t leaf = pl->adm[b];
+    if (std::find(pl->last.begin(), pl->last.end(), leaf) == pl->last.end())
+        return fail(BEM_E_ARG, "block was not approximated by the last run");
+    const auto &L = pl->h->leaves[leaf];
+    *rank = L.rank;
+    const size_t f = pl->h->cplx ? 2 : 1;
+    if (U && L.U) std::memcpy(U, L.U, sizeof(double) * f * (size_t)L.m * (size_t)L.rank);
+    if (V && L.V) std::memcpy(V, L.V, sizeof(double) * f * (size_t)L.n * (size_t)L.rank);
+    return BEM_OK;
+}
+
+int plan_destroy(bem_aca_plan *pl)
+{
+    if (!pl) return fail(BEM_E_ARG, "null plan");
+    {
+        std::lock_guard<std::mutex> g(pl->run_mu);
+    }
+    delete pl;
     return BEM_OK;
 }
 

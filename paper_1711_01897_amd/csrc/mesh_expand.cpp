@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <string>
 
 #include "bem_internal.hpp"
 
@@ -48,6 +49,11 @@ bool is_complex_op(int op)
 }
 
 bool is_adjoint_op(int op) { return op == BEM_LAPLACE_ADLP || op == BEM_HELMHOLTZ_ADLP; }
+
+int64_t space_ndof(const bem_mesh &m, int space)
+{
+    return space == BEM_P0 ? m.nt : (space == BEM_P1 ? m.nv : 3 * m.nt);
+}
 
 int kernel_op(int op)
 {
@@ -96,7 +102,7 @@ void expand_fixed(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, 
     r.nstar = 0;
     if (space == BEM_P0) {
         r.fix.assign(dofs, dofs + n);
-    } else {
+    } else if (space == BEM_P1) {
         // the fixed dofs' stars stay in the mesh's star table: ranges only
         r.fix.resize(2 * n);
         for (int64_t f = 0; f < n; ++f) {
@@ -105,6 +111,14 @@ void expand_fixed(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, 
             r.fix[2 * f + 1] = (int32_t)m.star_ptr[v + 1];
             r.nstar += m.star_ptr[v + 1] - m.star_ptr[v];
         }
+    } else {
+        // DP1: a dof is the one-triangle star (t, a), one entry of the star table
+        r.fix.resize(2 * n);
+        for (int64_t f = 0; f < n; ++f) {
+            r.fix[2 * f] = m.dp1_star[dofs[f]];
+            r.fix[2 * f + 1] = r.fix[2 * f] + 1;
+        }
+        r.nstar = n;
     }
     r.nfix = n;
 }
@@ -148,10 +162,12 @@ uint32_t morton3(double x, double y, double z, const double *lo, const double *i
 void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n, LaneSet &ls, bool reorder)
 {
     ls.pos.clear();
-    if (reorder && space == BEM_P1 && n > kBlockLanes) {
+    if (reorder && space != BEM_P0 && n > kBlockLanes) {
         std::vector<std::pair<uint32_t, int32_t>> key((size_t)n);
         for (int64_t i = 0; i < n; ++i) {
-            const double *x = &m.xyz[3 * (size_t)dofs[i]];
+            // P1: the vertex; DP1: the first vertex of the dof's triangle
+            const int32_t v = space == BEM_P1 ? dofs[i] : m.tri[3 * (size_t)(dofs[i] / 3)];
+            const double *x = &m.xyz[3 * (size_t)v];
             key[i] = {morton3(x[0], x[1], x[2], m.box_lo, m.box_inv), (int32_t)i};
         }
         std::sort(key.begin(), key.end());
@@ -196,12 +212,24 @@ void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n
         dof0 = end;
         sc.next_gen();
     };
+    // the star-table range of a dof: its vertex's star (P1) or the one entry
+    // of its triangle and local vertex (DP1)
+    auto range = [&](int32_t d, int64_t &b, int64_t &e) {
+        if (space == BEM_P1) {
+            b = m.star_ptr[d];
+            e = m.star_ptr[d + 1];
+        } else {
+            b = m.dp1_star[d];
+            e = b + 1;
+        }
+    };
     for (int64_t c = 0; c < n; ++c) {
-        const int32_t v = dofs[c];
+        int64_t sb, se;
+        range(dofs[c], sb, se);
         int32_t fresh = 0;
-        for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) fresh += sc.stamp[m.star[s] >> 2] != sc.gen;
+        for (int64_t s = sb; s < se; ++s) fresh += sc.stamp[m.star[s] >> 2] != sc.gen;
         if (count + fresh > kBlockLanes && c > dof0) close(c);
-        for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) {
+        for (int64_t s = sb; s < se; ++s) {
             const int32_t t = m.star[s] >> 2;
             if (sc.stamp[t] != sc.gen) {
                 sc.stamp[t] = sc.gen;
@@ -224,6 +252,75 @@ void build_lane_set(const bem_mesh &m, int space, const int32_t *dofs, int64_t n
 }
 
 namespace {
+
+// Largest |c| over a singular item's integration domain, where the device
+// writes x - y = rho c with the radius rho in [0, 1] and the Helmholtz
+// radial integrals take omega = k |c| (near.hip).  |c| is convex in each
+// coordinate of the (bi)linear parameterisations, so its maximum sits at the
+// corners of the parameter domain:
+//   identical:     c runs along the three edge vectors, the longest edge;
+//   common edge:   c = dh E + s1 a - s2 b on four faces, dh in {0, +-1},
+//                  s1, s2 in {0, 1} at the corners;
+//   common vertex: c = a(u) - z b(v) or z a(u) - b(v), u, v, z in {0, 1}.
+double near_span(const NearItem &q)
+{
+    auto dist = [](const double *a, const double *b) {
+        const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+        return std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    };
+    const double *v = q.v;
+    if (q.kind == 0) return std::max(std::max(dist(v + 3, v), dist(v + 6, v + 3)), dist(v + 6, v));
+    if (q.kind == 1) {
+        double E[3], a[3], b[3];
+        for (int d = 0; d < 3; ++d) {
+            E[d] = v[3 + d] - v[d];
+            a[d] = v[6 + d] - v[d];
+            b[d] = v[9 + d] - v[d];
+        }
+        double best = 0.0;
+        for (int face = 0; face < 4; ++face)
+            for (int p = 0; p <= 1; ++p)
+                for (int qq = 0; qq <= 1; ++qq) {
+                    double dh, s1, s2;
+                    if (face == 0) dh = p, s1 = (1 - p) * qq, s2 = 1;
+                    else if (face == 1) dh = p, s1 = 1 - p, s2 = qq;
+                    else if (face == 2) dh = -p, s1 = 1, s2 = (1 - p) * qq;
+                    else dh = -p, s1 = qq, s2 = 1 - p;
+                    double c2 = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double c = dh * E[d] + s1 * a[d] - s2 * b[d];
+                        c2 += c * c;
+                    }
+                    best = std::max(best, std::sqrt(c2));
+                }
+        return best;
+    }
+    const double *P = v, *T[2] = {v + 3, v + 6}, *S[2] = {v + 9, v + 12};
+    double best = 0.0;
+    for (int i = 0; i < 2; ++i) {
+        best = std::max(best, std::max(dist(T[i], P), dist(S[i], P)));
+        for (int j = 0; j < 2; ++j) best = std::max(best, dist(T[i], S[j]));
+    }
+    return best;
+}
+
+// The 48-term radial series of the Helmholtz singular pairs holds ~1e-14
+// relative accuracy at omega = 6 and ~5e-10 at 12, then fails quickly (its
+// largest terms grow like omega^n / n!): requests whose items reach beyond
+// kOmegaMax are refused.
+constexpr double kOmegaMax = 12.0;
+
+int check_near_omega(const Request &r)
+{
+    if (!is_complex_op(r.op)) return BEM_OK;
+    double span = 0.0;
+    for (const NearItem &q : r.near_items) span = std::max(span, near_span(q));
+    if (r.k * span > kOmegaMax)
+        return fail(BEM_E_ARG, "BEM_NEAR_SINGULAR Helmholtz pair with k |x - y| up to " + std::to_string(r.k * span) +
+                                   " > 12: the singular scheme's radial series is accurate only below that (the mesh "
+                                   "needs more than about one element per wavelength)");
+    return BEM_OK;
+}
 
 // The vertex-sharing pairs of a P0 request in the layouts of NearItem.  The
 // kernels' test triangle is the row's (the column's for the adjoint double
@@ -303,12 +400,14 @@ void build_near_items(Request &r)
     }
 }
 
-// The vertex-sharing pairs of a P1 request and, per output entry, the local
-// matrix values that sum into it.  A pair (a on the row side, b adjacent to
-// it) counts if a lies in the star of a requested row vertex and b touches a
-// requested column vertex; its local matrix M[i][j] (kernel test vertex i,
-// trial vertex j) goes to the entries of the row and column positions of
-// those vertices (exchanged for the adjoint double layer).
+// The vertex-sharing pairs of a P1 (or DP1) request and, per output entry,
+// the local matrix values that sum into it.  A pair (a on the row side, b
+// adjacent to it) counts if a lies in the star of a requested row vertex
+// (DP1: is the triangle of a requested row dof) and b touches a requested
+// column vertex (DP1: is the triangle of a requested column dof); its local
+// matrix M[i][j] (kernel test vertex i, trial vertex j) goes to the entries
+// of the row and column positions of those vertices (DP1: of the dofs (a, i)
+// and (b, j), one entry each), exchanged for the adjoint double layer.
 void build_near_items_p1(Request &r)
 {
     const bem_mesh &m = *r.mesh;
@@ -345,14 +444,27 @@ void build_near_items_p1(Request &r)
         std::sort(out.begin(), out.end());
         out.erase(std::unique(out.begin(), out.end()), out.end());
     };
+    // P1 dofs are vertices; a DP1 dof is (triangle t, local vertex) = 3 t + local
+    const bool dp1 = r.space == BEM_DP1;
+    auto dof_of = [&](int32_t t, int32_t v) -> int32_t {
+        if (!dp1) return v;
+        int i = 0;
+        while (m.tri[3 * (size_t)t + i] != v) ++i;
+        return 3 * t + i;
+    };
     std::vector<int32_t> rt, nb;
     {
         std::vector<int32_t> rv(r.rows.begin(), r.rows.end());
         std::sort(rv.begin(), rv.end());
         rv.erase(std::unique(rv.begin(), rv.end()), rv.end());
         rt.clear();
-        for (int32_t v : rv)
+        for (int32_t v : rv) {
+            if (dp1) {
+                rt.push_back(v / 3);
+                continue;
+            }
             for (int64_t s = m.star_ptr[v]; s < m.star_ptr[v + 1]; ++s) rt.push_back(m.star[s] >> 2);
+        }
         std::sort(rt.begin(), rt.end());
         rt.erase(std::unique(rt.begin(), rt.end()), rt.end());
     }
@@ -378,7 +490,7 @@ void build_near_items_p1(Request &r)
         for (int32_t b : nb) {
             bool touches = false;
             for (int k = 0; k < 3 && !touches; ++k) {
-                const int32_t v = m.tri[3 * (size_t)b + k];
+                const int32_t v = dp1 ? 3 * b + k : m.tri[3 * (size_t)b + k];
                 auto it = first_of(colpos, v);
                 touches = it != colpos.end() && it->first == v;
             }
@@ -429,7 +541,8 @@ void build_near_items_p1(Request &r)
             r.near_items.push_back(q);
             for (int i = 0; i < 3; ++i)
                 for (int j = 0; j < 3; ++j) {
-                    const int32_t rv = adj ? sl[j] : tl[i], cv = adj ? tl[i] : sl[j];
+                    const int32_t rv = adj ? dof_of(S, sl[j]) : dof_of(T, tl[i]);
+                    const int32_t cv = adj ? dof_of(T, tl[i]) : dof_of(S, sl[j]);
                     double w = 1.0;
                     if (hyps || hhyps) {
                         double ct[3], cs[3];
@@ -540,7 +653,7 @@ int expand_request(Request &r)
 {
     const bem_mesh &m = *r.mesh;
     if (r.op < 0 || r.op > 7) return fail(BEM_E_ARG, "unknown operator");
-    if (r.space != BEM_P0 && r.space != BEM_P1) return fail(BEM_E_ARG, "unknown space");
+    if (r.space != BEM_P0 && r.space != BEM_P1 && r.space != BEM_DP1) return fail(BEM_E_ARG, "unknown space");
     if ((r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS) && r.space != BEM_P1)
         return fail(BEM_E_ARG, "the hypersingular operator needs continuous (P1) functions");
     if (r.prec != BEM_FP32 && r.prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
@@ -551,7 +664,7 @@ int expand_request(Request &r)
     } else if (r.k != 0.0) {
         return fail(BEM_E_ARG, "Laplace needs k = 0");
     }
-    const int64_t ndof = r.space == BEM_P0 ? m.nt : m.nv;
+    const int64_t ndof = space_ndof(m, r.space);
     for (int32_t v : r.rows)
         if (v < 0 || v >= ndof) return fail(BEM_E_ARG, "row index out of range");
     for (int32_t v : r.cols)
@@ -581,6 +694,8 @@ int expand_request(Request &r)
             build_near_items(r);
         else
             build_near_items_p1(r);
+        const int rc = check_near_omega(r);
+        if (rc != BEM_OK) return rc;
     }
     finalize_sizes(r);
     return BEM_OK;
@@ -619,7 +734,7 @@ size_t request_bytes(const Request &r)
 {
     // descriptor, inputs, status, outputs, block table, launch-timing records
     return sizeof(ReqDev) + r.in_bytes + 8 + r.out_bytes + (size_t)r.nblocks * (sizeof(EntryBlock) + 16) +
-           (r.space == BEM_P1 ? near_p1_layout(r).bytes : r.near_items.size() * sizeof(NearItem)) + 512;
+           (r.space != BEM_P0 ? near_p1_layout(r).bytes : r.near_items.size() * sizeof(NearItem)) + 512;
 }
 
 void describe_request(const Request &r, ReqDev &d)
@@ -718,8 +833,8 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
             b.chunk = make_int4(ch[4 * c], ch[4 * c + 1], ch[4 * c + 2], ch[4 * c + 3]);
             b.lgeo = lgeo;
             b.lmeta = lmeta;
-            b.sgeo = r.space == BEM_P1 ? m.d_sgeo : nullptr;
-            b.smeta = r.space == BEM_P1 ? m.d_smeta : nullptr;
+            b.sgeo = r.space != BEM_P0 ? m.d_sgeo : nullptr;
+            b.smeta = r.space != BEM_P0 ? m.d_smeta : nullptr;
         }
     }
     return n;
@@ -727,7 +842,7 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
 
 void prebuild_staging(Request &r)
 {
-    r.key = ((kernel_op(r.op) * 2 + r.space) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0);
+    r.key = ((kernel_op(r.op) * 2 + kernel_space(r.space)) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0);
     r.pre_blocks.resize((size_t)r.nblocks);
     write_blocks(r, 0, r.pre_blocks.data());
     describe_request(r, r.pre_dev);
@@ -770,6 +885,8 @@ int mesh_create_impl(const double *xyz, int64_t nv, const int32_t *tri, int64_t 
         for (int64_t t = 0; t < nt; ++t)
             for (int k = 0; k < 3; ++k) m->star[fill[tri[3 * t + k]]++] = (int32_t)((t << 2) | k);
     }
+    m->dp1_star.resize(3 * nt);
+    for (int64_t s = 0; s < 3 * nt; ++s) m->dp1_star[3 * (size_t)(m->star[s] >> 2) + (m->star[s] & 3)] = (int32_t)s;
     for (int64_t v = 0; v < nv; ++v) m->max_star = std::max<int>(m->max_star, (int)(m->star_ptr[v + 1] - m->star_ptr[v]));
     if (m->max_star > kBlockLanes) {
         delete m;

@@ -429,7 +429,7 @@ public:
         };
         P1Run p1_runs[12];
         for (int i = 0; i < n; ++i)
-            if (!take[i]->near_items.empty() && take[i]->space == BEM_P1) {
+            if (!take[i]->near_items.empty() && take[i]->space != BEM_P0) {
                 P1Run &g = p1_runs[near_p1_group(*take[i])];
                 g.members.push_back(i);
                 g.items += (int64_t)take[i]->near_items.size();

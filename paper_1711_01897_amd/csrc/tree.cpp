@@ -1,7 +1,8 @@
 // Cluster tree and block tree (host, FP64), Section 2.1's geometric
 // partition of the matrix into admissible (low-rank) and dense leaves.
 //
-//  * dof points: triangle centroids (P0) or vertices (P1); every dof carries
+//  * dof points: triangle centroids (P0, and the three dofs of a triangle
+//    for DP1) or vertices (P1); every dof carries
 //    a support box, the bounding box of the vertices of the triangles its
 //    basis function lives on;
 //  * a cluster with more than leaf_size dofs is split at the midpoint of the
@@ -10,9 +11,10 @@
 //    side would be empty, the dofs are sorted by (coordinate, index) and the
 //    first half goes to the first child;
 //  * blocks start at (root, root); a block is admissible when the distance
-//    of the two support boxes is positive and the smaller support-box
-//    diameter is at most eta times that distance; otherwise it is dense if
-//    either cluster is a leaf, else it splits into its four child pairs.
+//    of the two support boxes is positive, the smaller support-box
+//    diameter is at most eta times that distance and (with max_block > 0)
+//    neither cluster holds more than max_block dofs; otherwise it is dense
+//    if either cluster is a leaf, else it splits into its four child pairs.
 // Support boxes keep every vertex-sharing triangle pair out of admissible
 // blocks, so ACA only ever requests regular entries.
 #include "tree.hpp"
@@ -34,14 +36,23 @@ void dof_geometry(const bem_mesh &m, int space, std::vector<double> &pts, std::v
             tlo[3 * t + d] = std::min(std::min(a, b), c);
             thi[3 * t + d] = std::max(std::max(a, b), c);
         }
-    if (space == BEM_P0) {
-        pts.resize(3 * nt);
+    if (space == BEM_P0 || space == BEM_DP1) {
+        // a triangle's dofs (one for P0, three for DP1) sit at its centroid
+        // and are supported on it
+        const int per = space == BEM_P0 ? 1 : 3;
+        pts.resize(3 * per * nt);
+        slo.resize(3 * per * nt);
+        shi.resize(3 * per * nt);
         for (int64_t t = 0; t < nt; ++t)
-            for (int d = 0; d < 3; ++d)
-                pts[3 * t + d] = ((m.xyz[3 * m.tri[3 * t] + d] + m.xyz[3 * m.tri[3 * t + 1] + d]) +
+            for (int d = 0; d < 3; ++d) {
+                const double c = ((m.xyz[3 * m.tri[3 * t] + d] + m.xyz[3 * m.tri[3 * t + 1] + d]) +
                                   m.xyz[3 * m.tri[3 * t + 2] + d]) / 3.0;
-        slo = tlo;
-        shi = thi;
+                for (int a = 0; a < per; ++a) {
+                    pts[3 * (per * t + a) + d] = c;
+                    slo[3 * (per * t + a) + d] = tlo[3 * t + d];
+                    shi[3 * (per * t + a) + d] = thi[3 * t + d];
+                }
+            }
         return;
     }
     pts.assign(m.xyz.begin(), m.xyz.end());
@@ -130,8 +141,9 @@ double box_dist(const Cluster &a, const Cluster &b)
 
 }  // namespace
 
-bool admissible(const Cluster &a, const Cluster &b, double eta)
+bool admissible(const Cluster &a, const Cluster &b, double eta, int max_block)
 {
+    if (max_block > 0 && std::max(a.end - a.begin, b.end - b.begin) > max_block) return false;
     const double d = box_dist(a, b);
     if (!(d > 0.0)) return false;
     return std::min(box_diam(a.slo, a.shi), box_diam(b.slo, b.shi)) <= eta * d;
@@ -140,7 +152,7 @@ bool admissible(const Cluster &a, const Cluster &b, double eta)
 double support_distance(const Cluster &a, const Cluster &b) { return box_dist(a, b); }
 
 void build_partition(const std::vector<double> &pts, const std::vector<double> &slo, const std::vector<double> &shi,
-                     int leaf_size, double eta, Partition &P)
+                     int leaf_size, double eta, int max_block, Partition &P)
 {
     const int64_t n = (int64_t)pts.size() / 3;
     P.perm.resize(n);
@@ -155,7 +167,7 @@ void build_partition(const std::vector<double> &pts, const std::vector<double> &
         const auto ts = stack.back();
         stack.pop_back();
         const Cluster &t = P.nodes[ts.first], &s = P.nodes[ts.second];
-        if (admissible(t, s, eta)) {
+        if (admissible(t, s, eta, max_block)) {
             P.blocks.push_back({ts.first, ts.second, 1});
         } else if (t.child[0] < 0 || s.child[0] < 0) {
             P.blocks.push_back({ts.first, ts.second, 0});

@@ -28,8 +28,8 @@ struct Partition {
 void dof_geometry(const bem_mesh &m, int space, std::vector<double> &pts, std::vector<double> &slo,
                   std::vector<double> &shi);
 void build_partition(const std::vector<double> &pts, const std::vector<double> &slo, const std::vector<double> &shi,
-                     int leaf_size, double eta, Partition &P);
-bool admissible(const Cluster &a, const Cluster &b, double eta);
+                     int leaf_size, double eta, int max_block, Partition &P);
+bool admissible(const Cluster &a, const Cluster &b, double eta, int max_block);
 double support_distance(const Cluster &a, const Cluster &b);
 
 }  // namespace bem

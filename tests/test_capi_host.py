@@ -41,11 +41,12 @@ def test_library_error_path_without_device():
         bem.mesh_create(np.zeros((3, 3)), np.array([[0, 1, 5]], dtype=np.int32))
 
 
-@pytest.mark.parametrize("space,level,leaf", [(0, 3, 32), (1, 3, 32), (1, 6, 100), (0, 5, 100)])
-def test_partition_matches_oracle(space, level, leaf):
+@pytest.mark.parametrize("space,level,leaf,max_block", [(0, 3, 32, 0), (1, 3, 32, 0), (1, 6, 100, 0), (0, 5, 100, 0),
+                                                        (1, 5, 16, 256), (0, 4, 16, 64)])
+def test_partition_matches_oracle(space, level, leaf, max_block):
     xyz, tri = inputs.icosphere(level)
-    perm, ranges, blocks = bem.partition(xyz, tri, space, leaf, 1.0)
-    nodes, leaves = OT.partition(xyz, tri, space, leaf, 1.0)
+    perm, ranges, blocks = bem.partition(xyz, tri, space, leaf, 1.0, max_block)
+    nodes, leaves = OT.partition(xyz, tri, space, leaf, 1.0, max_block)
     assert len(nodes) == ranges.shape[0]
     for c, node in enumerate(nodes):
         b, e = ranges[c]

@@ -494,3 +494,68 @@ def test_complete_helmholtz_hypersingular_hmatrix_on_the_sphere():
     assert eig <= 1e-2
     H.destroy()
     mesh.destroy()
+
+
+def _near_span(xyz, tri, a, b):
+    """Largest |c| (x - y = rho c, rho in [0, 1]) over the singular
+    coordinates of the vertex-sharing pair (test a, trial b): the longest
+    edge for identical pairs, otherwise the largest distance between the
+    corners of the parameterisation, which for these pairs is bounded by the
+    distances of their vertices and the cone faces' corners."""
+    ta, tb = list(tri[a]), list(tri[b])
+    shared = [v for v in ta if v in tb]
+    P = lambda v: xyz[v]
+    if len(shared) == 3:
+        return max(np.linalg.norm(P(ta[i]) - P(ta[(i + 1) % 3])) for i in range(3))
+    if len(shared) == 2:
+        p, q = shared
+        A = [v for v in ta if v not in shared][0]
+        B = [v for v in tb if v not in shared][0]
+        E, av, bv = P(q) - P(p), P(A) - P(p), P(B) - P(p)
+        best = 0.0
+        for face in range(4):
+            for pp in (0, 1):
+                for qq in (0, 1):
+                    dh, s1, s2 = [(pp, (1 - pp) * qq, 1), (pp, 1 - pp, qq), (-pp, 1, (1 - pp) * qq),
+                                  (-pp, qq, 1 - pp)][face]
+                    best = max(best, np.linalg.norm(dh * E + s1 * av - s2 * bv))
+        return best
+    p = shared[0]
+    T = [v for v in ta if v != p]
+    S = [v for v in tb if v != p]
+    cand = [np.linalg.norm(P(v) - P(p)) for v in T + S]
+    cand += [np.linalg.norm(P(u) - P(v)) for u in T for v in S]
+    return max(cand)
+
+
+def test_singular_helmholtz_range_guard(ico2):
+    """BEM_NEAR_SINGULAR Helmholtz requests are refused when a pair's radial
+    argument k |c| passes 12 (where the radial series stops holding its
+    accuracy); just inside, the entries still match the oracle's fixture."""
+    xyz, tri, mesh, om = ico2
+    nt = tri.shape[0]
+    span = 0.0
+    for a in range(nt):
+        for b in range(nt):
+            if adjacent(tri, a, b):
+                span = max(span, _near_span(xyz, tri, a, b))
+    rows = np.arange(nt, dtype=np.int32)
+    for op in (bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP):
+        with pytest.raises(bem.BemError) as e:
+            bem.eval_entries(mesh, op, bem.P0, 12.3 / span, rows, rows, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+        assert e.value.code == bem.E_ARG
+        with pytest.raises(bem.BemError):
+            bem.eval_entries(mesh, op, bem.P1, 12.3 / span, np.arange(xyz.shape[0]), np.arange(xyz.shape[0]), prec=bem.FP64,
+                             near=bem.NEAR_SINGULAR)
+    # just inside the range: parity against the oracle's Helmholtz near field
+    k = 11.5 / span
+    sel = np.random.Generator(np.random.PCG64(12)).choice(nt, 4, replace=False).astype(np.int32)
+    for op in (bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP):
+        got = bem.eval_entries(mesh, op, bem.P0, k, sel, rows, prec=bem.FP64, near=bem.NEAR_SINGULAR)
+        near = np.array([[adjacent(tri, a, b) for b in rows] for a in sel])
+        ri, ci = np.nonzero(near)
+        ref = (4 * om.nearfield_entries(op, k, sel[ri], rows[ci], 5, 3) -
+               om.nearfield_entries(op, k, sel[ri], rows[ci], 4, 3)) / 3
+        err = np.abs(got[near] - ref).max() / np.abs(ref).max()
+        print(f"op {op} k {k:.3f} (k span 11.5): max rel err {err:.2e}")
+        assert err <= 1e-6

@@ -30,10 +30,10 @@ def test_cluster_tree_partitions_dofs(space):
         assert np.all(pts[c.idx] >= c.lo) and np.all(pts[c.idx] <= c.hi)
 
 
-@pytest.mark.parametrize("space", [0, 1])
-def test_block_tree_tiles_square_and_admissible_blocks_are_regular(space):
+@pytest.mark.parametrize("space,leaf,max_block", [(0, 32, 0), (1, 32, 0), (1, 8, 48), (0, 8, 40)])
+def test_block_tree_tiles_square_and_admissible_blocks_are_regular(space, leaf, max_block):
     xyz, tri = inputs.icosphere(3)
-    nodes, leaves = T.partition(xyz, tri, space, 32, 1.0)
+    nodes, leaves = T.partition(xyz, tri, space, leaf, 1.0, max_block)
     n = xyz.shape[0] if space == 1 else tri.shape[0]
     cover = np.zeros((n, n), dtype=np.int32)
     # triangles supporting each dof
@@ -51,6 +51,8 @@ def test_block_tree_tiles_square_and_admissible_blocks_are_regular(space):
             va = np.unique(tri[np.concatenate([support[i] for i in ra])])
             vb = np.unique(tri[np.concatenate([support[j] for j in cb])])
             assert np.intersect1d(va, vb).size == 0
+            if max_block:
+                assert max(ra.size, cb.size) <= max_block
         else:
             assert not nodes[a].children or not nodes[b].children
     assert (cover == 1).all()
@@ -66,3 +68,26 @@ def test_icosphere_level6_p1_partition_counts():
     assert len(adm) == 24256 and len(den) == 17178
     assert sum(nodes[a].idx.size + nodes[b].idx.size for a, b in adm) == 8839546
     assert sum(nodes[a].idx.size * nodes[b].idx.size for a, b in den) == 112017666
+
+
+def test_max_block_only_splits_oversized_admissible_blocks():
+    """With a largest block dimension, every admissible block of the
+    unbounded partition that fits is kept, every one that does not is
+    replaced by blocks tiling the same index rectangle."""
+    xyz, tri = inputs.icosphere(4)
+    nodes, free = T.partition(xyz, tri, 1, 16, 1.0)
+    _, capped = T.partition(xyz, tri, 1, 16, 1.0, 96)
+    big = [(a, b) for a, b, ok in free if ok and max(nodes[a].idx.size, nodes[b].idx.size) > 96]
+    assert big, "the level-4 icosphere has admissible blocks above 96 dofs"
+    small = {(a, b) for a, b, ok in free if ok and (a, b) not in set(big)}
+    kept = {(a, b) for a, b, ok in capped if ok}
+    assert small <= kept
+    n = xyz.shape[0]
+    for a, b in big:
+        cover = np.zeros((n, n), dtype=np.int32)
+        cover[np.ix_(nodes[a].idx, nodes[b].idx)] = -1
+        for c, d, ok in capped:
+            sub = np.ix_(nodes[c].idx, nodes[d].idx)
+            if (cover[sub] != 0).any():
+                cover[sub] += 1
+        assert (cover[np.ix_(nodes[a].idx, nodes[b].idx)] == 0).all()
