@@ -76,9 +76,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "icosphere6"],
+    ap.add_argument("--workload", default="cylinder", choices=["cylinder", "icosphere6", "spheroid", "mix", "sphere3"],
                     help="cylinder: the served 1,049,540-triangle capped cylinder (default); icosphere6: H-matrix "
-                         "assembly of the Laplace single and double layer on the level-6 icosphere per step")
+                         "assembly of the Laplace single and double layer on the level-6 icosphere per step; spheroid: "
+                         "H-matrix of the Helmholtz single layer, P0, on the 262,186-triangle 10:1:1 spheroid, "
+                         "complex64 vs complex128; mix: served Helmholtz single layer on 8 meshes x 4 wavenumbers; "
+                         "sphere3: the dense P0 Laplace single layer of the level-3 icosphere, FP64")
     ap.add_argument("--workers", type=int, default=None, help="host ACA workers (cylinder 32, icosphere6 10)")
     ap.add_argument("--blocks-per-worker", type=int, default=None,
                     help="ACA blocks each worker keeps in flight (cylinder 128, icosphere6 180)")
@@ -89,6 +92,7 @@ def parse():
                     help="cylinder: offered loads of the extra latency-against-load segments ('' for none)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-star", action="store_true", help="--dense: skip the star-kernel comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--dense", type=int, default=0, metavar="LEVEL",
                     help="instead of the H-matrix workload: the dense P1 matrix of the --ops operators on the "
@@ -332,41 +336,78 @@ def dense_run(bem, mesh, idx, ops, prec, chunk):
     return tickets
 
 
+# Algorithmic flops per kernel evaluation of a pair's 3 x 3 local matrix:
+# the kernel core of the measurement plan's P0 count (without its weighted
+# accumulation), three test-basis accumulations per point pair, and the nine
+# trial-basis products per trial point spread over its Q test points
+# (Q = 6: 18 / Q = 3 flops, complex twice that).
+FLOPS_PER_EVAL_DENSE = {0: 9 + 6 + 3, 1: 17 + 6 + 3, 2: 16 + 12 + 6, 3: 29 + 12 + 6}
+
+
 def dense_main(args):
     """Dense weak-form assembly (the paper's first benchmark): every entry of
-    the P1 matrix, all regular pairs, vertex-sharing pairs skipped."""
+    the P1 matrix, all regular pairs (vertex-sharing pairs skipped), by
+    triangle pairs (bem_eval_dense: each pair's local matrix once, 144 kernel
+    evaluations per entry), beside the same matrix through the request server's
+    star kernels (each pair once per test vertex, 432 per entry)."""
     import numpy as np
     import torch
-    # one server stream: dense launches are large and would otherwise overlap,
-    # stretching each launch's event bracket by the others
     os.environ.setdefault("BEM_SERVER_STREAMS", "1")
     from paper_1711_01897_amd import bem, inputs
     xyz, tri = inputs.icosphere(args.dense)
     n = xyz.shape[0]
     mesh = bem.mesh_create(xyz, tri, 6)
     ops = step_ops(args)
-    chunk = 512
-    # rows and columns in the cluster-tree order: a lane chunk then holds the
-    # stars of neighbouring vertices (the matrix is the same, permuted)
+    # rows and columns in the cluster-tree order (the matrix is the same,
+    # permuted): a panel's row stars then share their triangles
     idx = bem.partition(xyz, tri, bem.P1, 100, 1.0)[0].astype(np.int32)
+
+    def run(prec):
+        stats = []
+        outs = []
+        for op in ops:
+            out, st = bem.eval_dense(mesh, op, bem.P1, 0.0, idx, idx, prec=prec, near=bem.NEAR_SKIP, stats=True)
+            stats.append(st)
+            outs.append(out)
+        return outs, stats
+
     for _ in range(args.warmup):
-        dense_run(bem, mesh, idx, ops, bem.FP32, chunk)
-    bem.server_stats(reset=True)
-    bem.server_kernel_stats(reset=True)
+        run(bem.FP32)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    times = []
     for _ in range(args.steps):
-        last = dense_run(bem, mesh, idx, ops, bem.FP32, chunk)
-    dt = time.perf_counter() - t0
-    sst, kst = bem.server_stats(), bem.server_kernel_stats()
-    roof, _ = roofline(kst)
+        t0 = time.perf_counter()
+        last, stats = run(bem.FP32)
+        times.append(time.perf_counter() - t0)
+    dt = sum(times)
     entries = len(ops) * n * n * args.steps
+    # roofline of the local-matrix kernel: its first panel, HIP events
+    st0, op0 = stats[0], ops[0]
+    flops = st0["first_pairs"] * 36 * FLOPS_PER_EVAL_DENSE[op0 if op0 < 4 else 1]
+    achieved = flops / st0["first_local_seconds"] if st0["first_local_seconds"] > 0 else 0.0
+    roof = {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_FP32_VALU / 1e12, 1),
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 4), "traffic": None,
+            "kernel": f"k_local_f32<op={op0},Q=6>", "pairs_per_launch": st0["first_pairs"],
+            "launch_us": round(st0["first_local_seconds"] * 1e6, 1),
+            "gather_us": round(st0["first_gather_seconds"] * 1e6, 1),
+            "flops_per_eval": FLOPS_PER_EVAL_DENSE[op0 if op0 < 4 else 1],
+            "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED, 4)}
+    evals_per_entry = sum(st["pairs"] for st in stats) * 36 / (len(ops) * n * n)
     fp64 = None
     if not args.no_fp64:
         t1 = time.perf_counter()
-        dense_run(bem, mesh, idx, ops, bem.FP64, chunk)
+        run(bem.FP64)
         dt64 = time.perf_counter() - t1
         fp64 = {"value": len(ops) * n * n / dt64, "unit": "entries/s", "seconds_per_step": dt64}
+    # the same matrix through the request server's star kernels, one step
+    star = None
+    if not args.no_star:
+        chunk = 512
+        t2 = time.perf_counter()
+        dense_run(bem, mesh, idx, ops, bem.FP32, chunk)
+        dts = time.perf_counter() - t2
+        star = {"value": len(ops) * n * n / dts, "unit": "entries/s", "evals_per_entry": 432,
+                "requests": f"{chunk}-row requests through the request server"}
     worst = None
     if not args.no_cpu_baseline:
         import oracle
@@ -374,9 +415,8 @@ def dense_main(args):
         pos = np.arange(0, n, max(1, n // 4))[:4]   # row positions in idx
         worst = 0.0
         for k, op in enumerate(ops):
-            got = np.vstack([last[k * ((n + chunk - 1) // chunk) + r // chunk].out[r % chunk] for r in pos])
             ref = om.entries(op, oracle.P1, 0.0, idx[pos], idx)
-            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+            worst = max(worst, float(np.max(np.abs(last[k][pos] - ref)) / np.max(np.abs(ref))))
     line = {
         "metric": "dense weak-form entries/sec FP32 vs FP64",
         "value": entries / dt, "unit": "entries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -384,12 +424,14 @@ def dense_main(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"dense P1 matrix of the Laplace {' + '.join(OP_LABEL[o] for o in ops)} operator(s), "
                                f"icosphere level {args.dense} ({tri.shape[0]} triangles, {n} vertices), 6-point rule, "
-                               f"vertex-sharing pairs skipped, rows and columns in cluster-tree order, {chunk}-row requests through the "
-                               "request server, "
-                               "FP32 compensated entries, results copied to host memory"},
+                               "vertex-sharing pairs skipped, rows and columns in cluster-tree order, each triangle "
+                               "pair's local matrix once (bem_eval_dense), FP32 compensated entries, results in host "
+                               "memory", "panels": stats[0]["panels"],
+                   "kernel_evals_per_entry": round(evals_per_entry, 1)},
+        "step_seconds_median": sorted(times)[len(times) // 2], "step_seconds_min": min(times),
         "fp64": fp64, "fp32_over_fp64": (entries / dt / fp64["value"]) if fp64 else None,
-        "max_rel_err_sampled": worst, "requests_per_batch": sst["requests"] / max(1, sst["batches"]),
-        "roofline": roof,
+        "star_kernel_path": star, "pair_over_star": (entries / dt / star["value"]) if star else None,
+        "max_rel_err_sampled": worst, "roofline": roof,
     }
     print(json.dumps(line))
 
@@ -728,6 +770,191 @@ def cylinder_main(args):
     mesh.destroy()
 
 
+def timed_runs(fn, warmup, steps):
+    """warmup untimed calls, then `steps` timed ones: (times, last result)."""
+    for _ in range(warmup):
+        fn()
+    times, res = [], None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        res = fn()
+        times.append(time.perf_counter() - t0)
+    return times, res
+
+
+def spheroid_main(args):
+    """H-matrix of the Helmholtz single layer, P0, 4-point rule, on the
+    262,186-triangle 10:1:1 prolate spheroid at 10 elements per wavelength
+    (leaf 100, eta 1, ACA tol 1e-4), one assembly per step: complex64
+    entries against complex128 entries, both by the measurement protocol
+    (warm-ups, then timed runs; median and min)."""
+    import numpy as np
+    from paper_1711_01897_amd import bem, inputs
+    xyz, tri = inputs.spheroid(10.0, 1.0, 262144)
+    mesh = bem.mesh_create(xyz, tri, 4)
+    k = inputs.wavenumber(xyz, tri, 10.0)
+    res = {}
+    for prec in (bem.FP32, bem.FP64):
+        def one():
+            H = bem.hmat_assemble(mesh, bem.HELMHOLTZ_SLP, bem.P0, k, leaf_size=100, eta=1.0, aca_tol=1e-4,
+                                  max_rank=300, n_workers=args.workers, blocks_per_worker=args.blocks_per_worker,
+                                  prec=prec, dense_mode=0)
+            st = H.stats()
+            H.destroy()
+            return st
+        bem.server_stats(reset=True)
+        bem.server_kernel_stats(reset=True)
+        times, st = timed_runs(one, args.warmup, args.steps)
+        sst = bem.server_stats()
+        res[prec] = {"entries_per_s": st["aca_entries"] / float(np.median(times)),
+                     "seconds_median": float(np.median(times)), "seconds_min": min(times),
+                     "aca_entries": st["aca_entries"], "aca_requests": st["aca_requests"],
+                     "mean_rank": st["rank_sum"] / max(1, st["admissible_blocks"]), "rank_max": st["rank_max"],
+                     "latency_p50_ms": sst["latency_p50"] * 1e3, "latency_p99_ms": sst["latency_p99"] * 1e3,
+                     "kst": bem.server_kernel_stats()}
+        print(f"[bench] spheroid prec {prec}: median {res[prec]['seconds_median']:.3f} s", file=sys.stderr, flush=True)
+    roof, _ = roofline(res[bem.FP32].pop("kst"), "spheroid")
+    res[bem.FP64].pop("kst")
+    f32, f64 = res[bem.FP32], res[bem.FP64]
+    line = {"metric": "weak-form entries/sec complex64 vs complex128 (H-matrix ACA assembly)",
+            "value": f32["entries_per_s"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": f32["seconds_median"] * 1e3, "higher_is_better": True,
+            "scaling": "strong", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+            "config": {"workload": f"Helmholtz single layer, P0, 4-point rule, 10:1:1 spheroid ({tri.shape[0]} "
+                                   f"triangles), k = {k:.4g} (10 elements per wavelength), H-matrix leaf 100, eta 1, "
+                                   f"ACA tol 1e-4, {args.workers} workers"},
+            "fp32": f32, "fp64": f64, "fp32_over_fp64": f32["entries_per_s"] / f64["entries_per_s"],
+            "seconds_fp32_over_fp64": f32["seconds_median"] / f64["seconds_median"], "roofline": roof,
+            "gpu_telemetry": gpu_telemetry()}
+    print(json.dumps(line))
+
+
+def mix_main(args):
+    """Served mixed Helmholtz workload: 8 meshes (icospheres with 5,120 to
+    327,680 triangles, 10:1:1 spheroids with ~10k to ~400k) x 4 wavenumbers
+    (2, 5, 10, 20 elements per wavelength), Helmholtz single layer, P0,
+    4-point rule, complex64, ACA plans with leaf 16, eta 1, tol 1e-4; one step
+    = every (mesh, k) instance serving a seeded segment of its admissible
+    blocks at the same time (one host thread each, one worker per instance:
+    32 workers sharing one device queue)."""
+    import threading
+    import numpy as np
+    from paper_1711_01897_amd import bem, inputs
+    meshes = [("icosphere", 4), ("icosphere", 5), ("icosphere", 6), ("icosphere", 7),
+              ("spheroid", 10000), ("spheroid", 40000), ("spheroid", 160000), ("spheroid", 400000)]
+    inst = []
+    for kind, size in meshes:
+        xyz, tri = inputs.icosphere(size) if kind == "icosphere" else inputs.spheroid(10.0, 1.0, size)
+        mesh = bem.mesh_create(xyz, tri, 4)
+        for epw in (2.0, 5.0, 10.0, 20.0):
+            k = inputs.wavenumber(xyz, tri, epw)
+            plan = bem.aca_plan_create(mesh, bem.HELMHOLTZ_SLP, bem.P0, k, leaf_size=16, eta=1.0, aca_tol=1e-4,
+                                       max_rank=200, n_workers=1, blocks_per_worker=64, prec=bem.FP32)
+            nb = plan.info()["blocks"]
+            order = inputs.rng(inputs.SEED_REQUESTS).permutation(nb)
+            inst.append({"mesh": mesh, "plan": plan, "k": k, "name": f"{kind}{size}@{epw:g}",
+                         "segs": np.array_split(order, max(1, (args.warmup + args.steps) * 8))})
+    print(f"[bench] mix: {len(inst)} instances", file=sys.stderr, flush=True)
+
+    def step(i, prec):
+        out = [None] * len(inst)
+
+        def one(j):
+            out[j] = inst[j]["plan"].run(inst[j]["segs"][i % len(inst[j]["segs"])], None, prec)
+        th = [threading.Thread(target=one, args=(j,)) for j in range(len(inst))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        return sum(o["entries"] for o in out)
+
+    res = {}
+    for prec in (bem.FP32, bem.FP64):
+        for i in range(args.warmup):
+            step(i, prec)
+        bem.server_stats(reset=True)
+        times, ents = [], 0
+        for i in range(args.steps):
+            t0 = time.perf_counter()
+            ents += step(args.warmup + i, prec)
+            times.append(time.perf_counter() - t0)
+        sst = bem.server_stats()
+        res[prec] = {"entries_per_s": ents / sum(times), "latency_p50_ms": sst["latency_p50"] * 1e3,
+                     "latency_p99_ms": sst["latency_p99"] * 1e3, "requests_per_batch":
+                     sst["requests"] / max(1, sst["batches"]), "step_seconds_median": float(np.median(times))}
+    # error per (mesh, k) instance against the oracle on seeded ACA rows
+    worst = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = inputs.rng(inputs.SEED_SAMPLING)
+        cache = {}
+        for it in inst:
+            key = id(it["mesh"])
+            if key not in cache:
+                m = it["mesh"]
+                # the oracle needs the geometry: rebuild it from the generator
+                kind, size = meshes[len(cache)]
+                xyz, tri = inputs.icosphere(size) if kind == "icosphere" else inputs.spheroid(10.0, 1.0, size)
+                cache[key] = oracle.OracleMesh(xyz, tri, 4)
+            om = cache[key]
+            e = 0.0
+            for _ in range(2):
+                rows, cols = it["plan"].block(int(rng.integers(it["plan"].info()["blocks"])))
+                r = rows[:1]
+                got = bem.eval_entries(it["mesh"], bem.HELMHOLTZ_SLP, bem.P0, it["k"], r, cols, prec=bem.FP32,
+                                       near=bem.NEAR_ERROR)
+                ref = om.entries(oracle.HELMHOLTZ_SLP, oracle.P0, it["k"], r, cols)
+                e = max(e, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+            worst[it["name"]] = e
+    f32, f64 = res[bem.FP32], res[bem.FP64]
+    line = {"metric": "weak-form entries/sec FP32 vs FP64 at stated rel err; p50/p99 ACA request latency",
+            "value": f32["entries_per_s"], "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": f32["step_seconds_median"] * 1e3, "higher_is_better": True,
+            "scaling": "strong", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+            "config": {"workload": "served Helmholtz single layer, P0, 4-point rule, 8 meshes (icospheres 5,120-"
+                                   "327,680 triangles, 10:1:1 spheroids ~10k-400k) x 4 wavenumbers (2, 5, 10, 20 "
+                                   "elements per wavelength), ACA plans leaf 16, eta 1, tol 1e-4, one device queue"},
+            "latency_p50_ms": f32["latency_p50_ms"], "latency_p99_ms": f32["latency_p99_ms"],
+            "fp64": f64, "fp32_over_fp64": f32["entries_per_s"] / f64["entries_per_s"],
+            "max_rel_err_sampled_per_instance": worst}
+    print(json.dumps(line))
+    for it in inst:
+        it["plan"].destroy()
+
+
+def sphere3_main(args):
+    """The dense P0 Laplace single layer of the level-3 icosphere (1,280
+    triangles), FP64 plain path: 1,638,400 entries of which 1,621,820 regular
+    (vertex-sharing pairs skipped), one request per step; checked entry by
+    entry against the oracle."""
+    import numpy as np
+    from paper_1711_01897_amd import bem, inputs
+    xyz, tri = inputs.icosphere(3)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    idx = np.arange(tri.shape[0], dtype=np.int32)
+    res = {}
+    for prec in (bem.FP64, bem.FP32):
+        times, A = timed_runs(lambda: bem.eval_entries(mesh, bem.LAPLACE_SLP, bem.P0, 0.0, idx, idx, prec=prec,
+                                                       near=bem.NEAR_SKIP), args.warmup, args.steps)
+        res[prec] = (times, A)
+    import oracle
+    om = oracle.OracleMesh(xyz, tri, 6)
+    ref = om.entries(oracle.LAPLACE_SLP, oracle.P0, 0.0, idx, idx)
+    nz = ref != 0
+    err = {p: float(np.max(np.abs(res[p][1][nz] - ref[nz]) / np.abs(ref[nz]))) for p in res}
+    n = idx.size * idx.size
+    t64 = res[bem.FP64][0]
+    line = {"metric": "weak-form entries/sec FP64 (dense P0 parity configuration)",
+            "value": n / float(np.median(t64)), "unit": "entries/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": float(np.median(t64)) * 1e3, "higher_is_better": True,
+            "scaling": "strong", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "Laplace single layer, P0, 6-point rule, icosphere level 3 (1280 triangles), all "
+                                   "1,638,400 entries in one request (1,621,820 regular, vertex-sharing pairs 0)"},
+            "seconds_min": min(t64), "fp32_entries_per_s": n / float(np.median(res[bem.FP32][0])),
+            "max_rel_err_fp64": err[bem.FP64], "max_rel_err_fp32": err[bem.FP32], "regular_entries": int(nz.sum())}
+    print(json.dumps(line))
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -753,6 +980,15 @@ def main():
         return
     if args.workload == "cylinder":
         cylinder_main(args)
+        return
+    if args.workload == "spheroid":
+        spheroid_main(args)
+        return
+    if args.workload == "mix":
+        mix_main(args)
+        return
+    if args.workload == "sphere3":
+        sphere3_main(args)
         return
     from paper_1711_01897_amd import bem, inputs
 

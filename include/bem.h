@@ -190,6 +190,35 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
                            const int32_t *rows, int64_t nrows, const int32_t *cols, int64_t ncols,
                            bem_prec prec, bem_near near, void *dev_out, void *stream);
 
+/* ---- pair-based dense blocks ------------------------------------------- */
+typedef struct {
+    int64_t pairs;               /* triangle pairs integrated (row-star x column-star triangles, all panels) */
+    int64_t panels;              /* row panels */
+    double seconds;              /* wall time of the call */
+    int64_t first_pairs;         /* pairs of the first panel */
+    double first_local_seconds;  /* its local-matrix kernel, HIP events on the compute stream */
+    double first_gather_seconds; /* its gather kernel */
+} bem_dense_stats;
+
+/* A[rows, cols] of a P1 block by triangle pairs (Section 3's dense
+ * assembly: kernel values at all pairs of Gauss points of a triangle pair,
+ * weighted with the basis functions of every local dof pair): each regular
+ * pair of star(rows) x star(cols) is integrated once into its 3 x 3 local
+ * matrix on the device (144 kernel evaluations per entry of a full matrix,
+ * where row requests integrate a pair once per test vertex), then every
+ * entry adds its pairs' values in a fixed order (row star outer, column star
+ * inner; compensated in FP32).  Rows go in panels whose local matrices fit
+ * BEM_DENSE_BUDGET_MB (environment, default 1024) MiB of device memory; a
+ * panel's assembly overlaps the transfer of the previous panel's entries.
+ * out: host, nrows x ncols row-major (types as bem_eval_entries).  Single
+ * and double layer (Laplace, Helmholtz), P1, BEM_NEAR_ERROR (checked on the
+ * host before anything runs) or BEM_NEAR_SKIP; stats may be NULL.  The
+ * call allocates its device workspace and pinned staging and frees them
+ * before it returns.  Errors as bem_eval_entries. */
+int bem_eval_dense(bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows, int64_t nrows,
+                   const int32_t *cols, int64_t ncols, bem_prec prec, bem_near near, void *out,
+                   bem_dense_stats *stats);
+
 /* ---- request server ---------------------------------------------------- */
 /* Size the request server (Section 4's block threads are replaced by it):
  * arena_bytes of device memory (and the same amount of pinned host staging),
@@ -296,7 +325,8 @@ int bem_aca_callback(int64_t m, int64_t n, int is_complex, bem_row_fn get_row, b
  * leaf.
  * Host-only.  Writes up to max_blocks leaves as (row cluster, col cluster,
  * admissible) triples and the dof ranges of every cluster: cluster c holds
- * dofs perm[cl_begin[c] .. cl_end[c]).  Sizes are returned in *nblocks and
+ * dofs perm[cl_begin[c] .. cl_end[c]); perm holds one entry per dof of the
+ * space (nt, nv or 3 nt).  Sizes are returned in *nblocks and
  * *nclusters; when a capacity is too small nothing else is written and
  * BEM_E_ARG is returned with the needed sizes. */
 int bem_partition(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt, bem_space space,
@@ -317,11 +347,19 @@ typedef struct {
                                2: complete, singular pairs included (BEM_NEAR_SINGULAR) */
     int32_t max_block;      /* largest dimension of an admissible block (0: no bound); larger
                                cluster pairs are split further */
+    int32_t hyps_via_slp;   /* hypersingular operators: 1 = assemble the single layer on DP1 (same
+                               parameters) and apply D = sum_j Q_j^T S Q_j - k^2 sum_j P_j^T S P_j
+                               with the sparse curl (Q_j) and normal (P_j) factors, Eq. hyp_via_slp
+                               (its entries are sums of positive-kernel integrals, so FP32 ACA keeps
+                               its accuracy); 0 = assemble D's entries directly */
 } bem_hmat_params;
 
 /* Fill every admissible leaf of the block tree by ACA (all rows and columns
  * on the device) and, if dense_mode is 1 or 2, every dense leaf (its regular
- * part, or all of it).  The caller gets an H-matrix handle. */
+ * part, or all of it).  The caller gets an H-matrix handle.  With
+ * hyps_via_slp the handle applies D through the DP1 single layer: its
+ * matvec takes P1 vectors, its statistics, block info and dense blocks are
+ * those of the DP1 single layer. */
 int bem_hmat_assemble(bem_mesh *mesh, bem_op op, bem_space space, double k,
                       const bem_hmat_params *params, bem_hmat **out);
 

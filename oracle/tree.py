@@ -5,7 +5,8 @@ admissible (compressed by ACA) or dense.  The paper does not fix the rules;
 this oracle takes them as follows, step by step:
 
   cluster tree
-    * dof points: triangle centroids (P0) or vertices (P1);
+    * dof points: triangle centroids (P0, and all three dofs of a triangle
+      for the discontinuous P1 space, dof 3 t + a) or vertices (P1);
     * each dof carries a support box: the bounding box of the vertices of the
       triangles on which its basis function lives;
     * a cluster with more than leaf_size dofs is split at the midpoint of the
@@ -44,7 +45,8 @@ class Cluster:
 
 
 def dof_geometry(xyz, tri, space: int):
-    """(points, support_lo, support_hi) per dof; space 0 = P0, 1 = P1."""
+    """(points, support_lo, support_hi) per dof; space 0 = P0, 1 = P1,
+    2 = discontinuous P1."""
     xyz = np.asarray(xyz, dtype=np.float64)
     tri = np.asarray(tri, dtype=np.int64)
     a, b, c = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
@@ -53,6 +55,9 @@ def dof_geometry(xyz, tri, space: int):
     if space == 0:
         pts = (a + b + c) / 3.0
         return pts, tlo, thi
+    if space == 2:
+        pts = (a + b + c) / 3.0
+        return np.repeat(pts, 3, axis=0), np.repeat(tlo, 3, axis=0), np.repeat(thi, 3, axis=0)
     nv = xyz.shape[0]
     slo = np.full((nv, 3), np.inf)
     shi = np.full((nv, 3), -np.inf)

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbem.so")
 LAPLACE_SLP, LAPLACE_DLP, HELMHOLTZ_SLP, HELMHOLTZ_DLP = 0, 1, 2, 3
 LAPLACE_ADLP, HELMHOLTZ_ADLP = 4, 5
 LAPLACE_HYPS, HELMHOLTZ_HYPS = 6, 7
-P0, P1 = 0, 1
+P0, P1, DP1 = 0, 1, 2
 FP64, FP32 = 0, 1
 NEAR_ERROR, NEAR_SKIP, NEAR_SINGULAR = 0, 1, 2
 
@@ -34,7 +34,7 @@ EXPORTS = [
     "bem_server_stats", "bem_server_kernel_stats", "bem_aca_block", "bem_aca_callback", "bem_partition", "bem_hmat_assemble",
     "bem_hmat_matvec", "bem_hmat_stats_get", "bem_hmat_block_info", "bem_hmat_block_dense", "bem_hmat_destroy",
     "bem_aca_plan_create", "bem_aca_plan_info", "bem_aca_plan_block", "bem_aca_plan_run", "bem_aca_plan_factors",
-    "bem_aca_plan_destroy",
+    "bem_aca_plan_destroy", "bem_eval_dense",
 ]
 
 
@@ -87,7 +87,14 @@ class AcaParams(ctypes.Structure):
 class HmatParams(ctypes.Structure):
     _fields_ = [("leaf_size", ctypes.c_int32), ("eta", ctypes.c_double), ("aca_tol", ctypes.c_double),
                 ("max_rank", ctypes.c_int32), ("n_workers", ctypes.c_int32), ("blocks_per_worker", ctypes.c_int32),
-                ("prec", ctypes.c_int), ("dense_mode", ctypes.c_int32), ("max_block", ctypes.c_int32)]
+                ("prec", ctypes.c_int), ("dense_mode", ctypes.c_int32), ("max_block", ctypes.c_int32),
+                ("hyps_via_slp", ctypes.c_int32)]
+
+
+class DenseStats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("panels", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("first_pairs", ctypes.c_int64), ("first_local_seconds", ctypes.c_double),
+                ("first_gather_seconds", ctypes.c_double)]
 
 
 class AcaRunStats(ctypes.Structure):
@@ -162,6 +169,7 @@ def lib():
     L.bem_aca_plan_run.argtypes = [_p, _i64p, _dp, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(AcaRunStats)]
     L.bem_aca_plan_factors.argtypes = [_p, ctypes.c_int64, _i32p, _p, _p]
     L.bem_aca_plan_destroy.argtypes = [_p]
+    L.bem_eval_dense.argtypes = entry_args + [_p, ctypes.POINTER(DenseStats)]
     _LIB = L
     return L
 
@@ -230,6 +238,19 @@ def eval_entries(mesh: Mesh, op, space, k, rows, cols, prec=FP32, near=NEAR_SKIP
     out = np.empty((rows.size, cols.size), dtype=out_dtype(op, prec))
     _check(lib().bem_eval_entries(mesh.handle, op, space, float(k), _ip(rows), rows.size, _ip(cols), cols.size,
                                   prec, near, out.ctypes.data_as(_p)))
+    return out
+
+
+def eval_dense(mesh: Mesh, op, space, k, rows, cols, prec=FP32, near=NEAR_SKIP, stats=False):
+    """A[rows, cols] of a P1 block by triangle pairs (bem_eval_dense); with
+    stats=True also returns the call's bem_dense_stats as a dict."""
+    rows, cols = _idx(rows), _idx(cols)
+    out = np.empty((rows.size, cols.size), dtype=out_dtype(op, prec))
+    st = DenseStats()
+    _check(lib().bem_eval_dense(mesh.handle, op, space, float(k), _ip(rows), rows.size, _ip(cols), cols.size, prec,
+                                near, out.ctypes.data_as(_p), ctypes.byref(st)))
+    if stats:
+        return out, {f: getattr(st, f) for f, _ in DenseStats._fields_}
     return out
 
 
@@ -357,7 +378,7 @@ def partition(xyz, tri, space, leaf_size=100, eta=1.0, max_block=0):
     """(perm, cluster ranges [(begin, end)], blocks [(tau, sigma, admissible)])."""
     xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64))
     tri = np.ascontiguousarray(np.asarray(tri, dtype=np.int32))
-    nd = xyz.shape[0] if space == P1 else tri.shape[0]
+    nd = {P0: tri.shape[0], P1: xyz.shape[0], DP1: 3 * tri.shape[0]}[space]
     nc, nb = ctypes.c_int64(), ctypes.c_int64()
     rc = lib().bem_partition(xyz.ctypes.data_as(_dp), xyz.shape[0], _ip(tri), tri.shape[0], space, leaf_size,
                              float(eta), int(max_block), None, None, None, 0, None, 0, ctypes.byref(nc), ctypes.byref(nb))
@@ -415,11 +436,12 @@ class HMatrix:
 
 
 def hmat_assemble(mesh: Mesh, op, space, k, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200, n_workers=8,
-                  blocks_per_worker=32, prec=FP32, dense_mode=0, max_block=0) -> HMatrix:
-    prm = HmatParams(leaf_size, eta, aca_tol, max_rank, n_workers, blocks_per_worker, prec, dense_mode, max_block)
+                  blocks_per_worker=32, prec=FP32, dense_mode=0, max_block=0, hyps_via_slp=0) -> HMatrix:
+    prm = HmatParams(leaf_size, eta, aca_tol, max_rank, n_workers, blocks_per_worker, prec, dense_mode, max_block,
+                     hyps_via_slp)
     h = _p()
     _check(lib().bem_hmat_assemble(mesh.handle, op, space, float(k), ctypes.byref(prm), ctypes.byref(h)))
-    return HMatrix(h, mesh.nt if space == P0 else mesh.nv, is_complex(op))
+    return HMatrix(h, {P0: mesh.nt, P1: mesh.nv, DP1: 3 * mesh.nt}[space], is_complex(op))
 
 
 class AcaPlan:
@@ -481,7 +503,7 @@ class AcaPlan:
 
 def aca_plan_create(mesh: Mesh, op, space, k, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200, n_workers=8,
                     blocks_per_worker=32, prec=FP32, max_block=0) -> AcaPlan:
-    prm = HmatParams(leaf_size, eta, aca_tol, max_rank, n_workers, blocks_per_worker, prec, 0, max_block)
+    prm = HmatParams(leaf_size, eta, aca_tol, max_rank, n_workers, blocks_per_worker, prec, 0, max_block, 0)
     h = _p()
     _check(lib().bem_aca_plan_create(mesh.handle, op, space, float(k), ctypes.byref(prm), ctypes.byref(h)))
     return AcaPlan(h, is_complex(op))

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libbem.so")
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
 DEVICE_SOURCES = ["entries.hip", "geometry.hip", "near.hip"]
-HOST_SOURCES = ["mesh_expand.cpp", "server.cpp", "hmat.cpp", "tree.cpp", "capi.cpp", "aca_kernels.cpp"]
+HOST_SOURCES = ["mesh_expand.cpp", "server.cpp", "hmat.cpp", "tree.cpp", "capi.cpp", "aca_kernels.cpp", "dense.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-Wall",
           "-Wno-unused-result"]

@@ -30,6 +30,8 @@ int plan_block(const bem_aca_plan *, int64_t, int64_t *, int64_t *, const int32_
 int plan_run(bem_aca_plan *, const int64_t *, const double *, int64_t, int, bem_aca_run_stats *);
 int plan_factors(const bem_aca_plan *, int64_t, int32_t *, void *, void *);
 int plan_destroy(bem_aca_plan *);
+int eval_dense(bem_mesh *, int, int, double, const int32_t *, int64_t, const int32_t *, int64_t, int, int, void *,
+               bem_dense_stats *);
 }  // namespace bem
 
 using namespace bem;
@@ -400,5 +402,12 @@ int bem_aca_plan_factors(const bem_aca_plan *plan, int64_t b, int32_t *rank, voi
 }
 
 int bem_aca_plan_destroy(bem_aca_plan *plan) { return plan_destroy(plan); }
+
+int bem_eval_dense(bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows, int64_t nrows,
+                   const int32_t *cols, int64_t ncols, bem_prec prec, bem_near near, void *out, bem_dense_stats *stats)
+{
+    if (nrows > 0 && ncols > 0 && !out) return fail(BEM_E_ARG, "null output");
+    return eval_dense(mesh, op, space, k, rows, nrows, cols, ncols, prec, near, out, stats);
+}
 
 }  // extern "C"

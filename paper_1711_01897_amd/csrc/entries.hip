@@ -1225,6 +1225,333 @@ EntryKernel select_kernel(const Variant &v)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Pair-based P1 blocks (dense assembly).
+//
+// Section 3's dense assembly evaluates the kernel at all pairs of Gauss
+// points of a triangle pair once, weights the values with the basis
+// functions of every pair of local dofs and adds the results to the global
+// entries.  The star kernels above integrate a pair once per test vertex
+// (three times for a full block); here a block's pairs are integrated once
+// into their 3 x 3 local matrices (k_local_*, one lane per trial triangle
+// against a tile of test triangles staged in LDS), stored plane by plane
+// (L[(m 9 + 3 a + b) ntrial + n] for test triangle m, trial triangle n), and
+// every entry then adds its pairs' local values in a fixed order, test
+// triangles of its row's star outer, trial triangles of its column's star
+// inner (k_gather_dense_*; compensated in FP32).  Vertex-sharing pairs
+// contribute zero (regular part).
+constexpr int kLocalTile = 8;   // test triangles staged per workgroup
+
+// 3 x 3 local matrix of a regular pair, FP32, without J_x J_y / 4 pi:
+// M[a][b] = sum_q w_q lam_b(q) sum_p w_p lam_a(p) K(x_p, y_q).  T is the test
+// record, S the trial record with its offsets scaled by -2 and Bq[q] =
+// |o_q|^2 (see pair_p1_testfix_f32).
+template <int OP, int Q>
+__device__ __forceinline__ void pair_local_f32(const float *T, const float *S, const float *Bq, float kf, double kk,
+                                               float (*Mr)[3], float (*Mi)[3])
+{
+    const float dcx = (T[0] - S[0]) + (T[4] - S[4]);
+    const float dcy = (T[1] - S[1]) + (T[5] - S[5]);
+    const float dcz = (T[2] - S[2]) + (T[6] - S[6]);
+    Phase ph{};
+    if constexpr (is_cplx<OP>()) ph = phase_base(T, S, kk, dcx, dcy, dcz);
+    float mx[Q], my[Q], mz[Q], A[Q], wa[3][Q];
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const float ox = T[12 + 3 * p], oy = T[13 + 3 * p], oz = T[14 + 3 * p];
+        const float ax = dcx + ox, ay = dcy + oy, az = dcz + oz;
+        mx[p] = ax;
+        my[p] = ay;
+        mz[p] = az;
+        if constexpr (is_cplx<OP>())
+            A[p] = fmaf(2.0f * dcx + ox, ox, fmaf(2.0f * dcy + oy, oy, (2.0f * dcz + oz) * oz));
+        else
+            A[p] = fmaf(ax, ax, fmaf(ay, ay, az * az));
+        float wn = (float)rule::Rule<Q>::w[p];
+        if constexpr (is_dlp<OP>()) wn *= fmaf(ax, S[8], fmaf(ay, S[9], az * S[10]));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) wa[a][p] = wn * (float)rule::lam<Q>(a, p);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Mr[a][b] = Mi[a][b] = 0.f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const float ox = S[12 + 3 * q], oy = S[13 + 3 * q], oz = S[14 + 3 * q];
+        const float B = Bq[q];
+        float ur[3] = {0.f, 0.f, 0.f}, ui[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int p = 0; p < Q; ++p) {
+            const float v = fmaf(mx[p], ox, fmaf(my[p], oy, fmaf(mz[p], oz, A[p] + B)));
+            float kr = 0.f, ki = 0.f;
+            if constexpr (is_cplx<OP>())
+                kern_f32<OP>(v + ph.dsq, v, 1.0f, kf, ph, kr, ki);
+            else
+                kern_f32<OP>(v, 0.f, 1.0f, kf, ph, kr, ki);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ur[a] = fmaf(wa[a][p], kr, ur[a]);
+                if constexpr (is_cplx<OP>()) ui[a] = fmaf(wa[a][p], ki, ui[a]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const float wl = (float)(rule::Rule<Q>::w[q] * rule::lam<Q>(b, q));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Mr[a][b] = fmaf(wl, ur[a], Mr[a][b]);
+                if constexpr (is_cplx<OP>()) Mi[a][b] = fmaf(wl, ui[a], Mi[a][b]);
+            }
+        }
+    }
+}
+
+// The same in FP64 from absolute points.
+template <int OP, int Q>
+__device__ __forceinline__ void pair_local_f64(const double *T, const double *S, double k, double (*Mr)[3],
+                                               double (*Mi)[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Mr[a][b] = Mi[a][b] = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        double ur[3] = {0.0, 0.0, 0.0}, ui[3] = {0.0, 0.0, 0.0};
+#pragma unroll f64_unroll<OP>()
+        for (int p = 0; p < Q; ++p) {
+            double kr = 0.0, ki = 0.0;
+            kern_f64<OP>(T[4 + 3 * p] - S[4 + 3 * q], T[5 + 3 * p] - S[5 + 3 * q], T[6 + 3 * p] - S[6 + 3 * q], S,
+                         rule::Rule<Q>::w[p], k, kr, ki);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ur[a] += rule::lam<Q>(a, p) * kr;
+                ui[a] += rule::lam<Q>(a, p) * ki;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double wl = rule::Rule<Q>::w[q] * rule::lam<Q>(b, q);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Mr[a][b] += wl * ur[a];
+                Mi[a][b] += wl * ui[a];
+            }
+        }
+    }
+}
+
+// Local matrices of the pairs (test[m], trial[n]) for m in this workgroup's
+// tile of kLocalTile test triangles, n = one lane per trial triangle.
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void k_local_f32(const float *__restrict__ g32, const int4 *__restrict__ vtx,
+                                                           const int32_t *__restrict__ test, int ntest,
+                                                           const int32_t *__restrict__ trial, int ntrial,
+                                                           float *__restrict__ Lr, float *__restrict__ Li, float kf,
+                                                           double kk)
+{
+    constexpr int W = n32<Q>();
+    __shared__ float sT[kLocalTile][W];
+    __shared__ int4 sV[kLocalTile];
+    const int t = threadIdx.x;
+    const int m0 = blockIdx.y * kLocalTile;
+    const int nm = min(kLocalTile, ntest - m0);
+    for (int i = t; i < nm * W; i += kBlockLanes) {
+        const int k = i / W, w = i - k * W;
+        sT[k][w] = g32[(size_t)test[m0 + k] * kGeo32Stride + w];
+    }
+    if (t < nm) sV[t] = vtx[test[m0 + t]];
+    __syncthreads();
+    const int n = blockIdx.x * kBlockLanes + t;
+    if (n >= ntrial) return;   // no barrier below
+    float S[W], Bq[Q];
+    load32<Q>(g32, trial[n], S);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        float *o = S + 12 + 3 * q;
+        Bq[q] = fmaf(o[0], o[0], fmaf(o[1], o[1], o[2] * o[2]));
+        o[0] *= -2.0f;
+        o[1] *= -2.0f;
+        o[2] *= -2.0f;
+    }
+    const int4 vs = vtx[trial[n]];
+    for (int i = 0; i < nm; ++i) {
+        float Mr[3][3], Mi[3][3];
+        if (share_vertex(sV[i], vs)) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Mr[a][b] = Mi[a][b] = 0.f;
+        } else {
+            float T[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) T[w] = sT[i][w];
+            pair_local_f32<OP, Q>(T, S, Bq, kf, kk, Mr, Mi);
+            const float sc = T[3] * S[3] * kInv4PiF;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    Mr[a][b] *= sc;
+                    Mi[a][b] *= sc;
+                }
+        }
+        float *lr = Lr + (size_t)(m0 + i) * 9 * ntrial + n;
+        float *li = is_cplx<OP>() ? Li + (size_t)(m0 + i) * 9 * ntrial + n : nullptr;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            lr[(size_t)k * ntrial] = Mr[k / 3][k % 3];
+            if constexpr (is_cplx<OP>()) li[(size_t)k * ntrial] = Mi[k / 3][k % 3];
+        }
+    }
+}
+
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void k_local_f64(const double *__restrict__ g64, const int4 *__restrict__ vtx,
+                                                           const int32_t *__restrict__ test, int ntest,
+                                                           const int32_t *__restrict__ trial, int ntrial,
+                                                           double *__restrict__ Lr, double *__restrict__ Li, double k)
+{
+    constexpr int W = n64<Q>();
+    __shared__ double sT[kLocalTile][W];
+    __shared__ int4 sV[kLocalTile];
+    const int t = threadIdx.x;
+    const int m0 = blockIdx.y * kLocalTile;
+    const int nm = min(kLocalTile, ntest - m0);
+    for (int i = t; i < nm * W; i += kBlockLanes) {
+        const int kk = i / W, w = i - kk * W;
+        sT[kk][w] = g64[(size_t)test[m0 + kk] * kGeo64Stride + w];
+    }
+    if (t < nm) sV[t] = vtx[test[m0 + t]];
+    __syncthreads();
+    const int n = blockIdx.x * kBlockLanes + t;
+    if (n >= ntrial) return;
+    double S[W];
+    load64<Q>(g64, trial[n], S);
+    const int4 vs = vtx[trial[n]];
+    for (int i = 0; i < nm; ++i) {
+        double Mr[3][3], Mi[3][3];
+        if (share_vertex(sV[i], vs)) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Mr[a][b] = Mi[a][b] = 0.0;
+        } else {
+            double T[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) T[w] = sT[i][w];
+            pair_local_f64<OP, Q>(T, S, k, Mr, Mi);
+            const double sc = T[3] * S[3] * kInv4Pi;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    Mr[a][b] *= sc;
+                    Mi[a][b] *= sc;
+                }
+        }
+        double *lr = Lr + (size_t)(m0 + i) * 9 * ntrial + n;
+        double *li = is_cplx<OP>() ? Li + (size_t)(m0 + i) * 9 * ntrial + n : nullptr;
+#pragma unroll
+        for (int kk = 0; kk < 9; ++kk) {
+            lr[(size_t)kk * ntrial] = Mr[kk / 3][kk % 3];
+            if constexpr (is_cplx<OP>()) li[(size_t)kk * ntrial] = Mi[kk / 3][kk % 3];
+        }
+    }
+}
+
+// Entry (r, c) of a panel: sum over the row's star (rsrc[rptr[r] ..], packed
+// test index << 2 | local vertex) and the column's star (csrc[cptr[c] ..],
+// trial index << 2 | local vertex) of the local values, in that order.
+template <bool CPLX>
+__global__ __launch_bounds__(kBlockLanes) void k_gather_dense_f32(const float *__restrict__ Lr,
+                                                                  const float *__restrict__ Li, int ntrial,
+                                                                  const int32_t *__restrict__ rptr,
+                                                                  const int32_t *__restrict__ rsrc,
+                                                                  const int32_t *__restrict__ cptr,
+                                                                  const int32_t *__restrict__ csrc, int ncols,
+                                                                  void *__restrict__ out)
+{
+    const int c = blockIdx.x * kBlockLanes + threadIdx.x;
+    const int r = blockIdx.y;
+    if (c >= ncols) return;
+    float hr = 0.f, lr = 0.f, hi = 0.f, li = 0.f;
+    const int c0 = cptr[c], c1 = cptr[c + 1];
+    for (int i = rptr[r]; i < rptr[r + 1]; ++i) {
+        const int ms = rsrc[i];
+        const size_t base = ((size_t)(ms >> 2) * 9 + 3 * (ms & 3)) * ntrial;
+        for (int j = c0; j < c1; ++j) {
+            const int ns = csrc[j];
+            const size_t o = base + (size_t)(ns & 3) * ntrial + (ns >> 2);
+            two_sum_acc(hr, lr, Lr[o]);
+            if constexpr (CPLX) two_sum_acc(hi, li, Li[o]);
+        }
+    }
+    const size_t e = (size_t)r * ncols + c;
+    if constexpr (CPLX)
+        reinterpret_cast<float2 *>(out)[e] = make_float2(hr + lr, hi + li);
+    else
+        reinterpret_cast<float *>(out)[e] = hr + lr;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(kBlockLanes) void k_gather_dense_f64(const double *__restrict__ Lr,
+                                                                  const double *__restrict__ Li, int ntrial,
+                                                                  const int32_t *__restrict__ rptr,
+                                                                  const int32_t *__restrict__ rsrc,
+                                                                  const int32_t *__restrict__ cptr,
+                                                                  const int32_t *__restrict__ csrc, int ncols,
+                                                                  void *__restrict__ out)
+{
+    const int c = blockIdx.x * kBlockLanes + threadIdx.x;
+    const int r = blockIdx.y;
+    if (c >= ncols) return;
+    double sr = 0.0, si = 0.0;
+    const int c0 = cptr[c], c1 = cptr[c + 1];
+    for (int i = rptr[r]; i < rptr[r + 1]; ++i) {
+        const int ms = rsrc[i];
+        const size_t base = ((size_t)(ms >> 2) * 9 + 3 * (ms & 3)) * ntrial;
+        for (int j = c0; j < c1; ++j) {
+            const int ns = csrc[j];
+            const size_t o = base + (size_t)(ns & 3) * ntrial + (ns >> 2);
+            sr += Lr[o];
+            if constexpr (CPLX) si += Li[o];
+        }
+    }
+    const size_t e = (size_t)r * ncols + c;
+    if constexpr (CPLX)
+        reinterpret_cast<double2 *>(out)[e] = make_double2(sr, si);
+    else
+        reinterpret_cast<double *>(out)[e] = sr;
+}
+
+template <int OP>
+hipError_t local_launch(bool fp32, int q, const bem_mesh &m, const int32_t *test, int ntest, const int32_t *trial,
+                        int ntrial, void *Lr, void *Li, double k, hipStream_t s)
+{
+    const dim3 grid((unsigned)((ntrial + kBlockLanes - 1) / kBlockLanes),
+                    (unsigned)((ntest + kLocalTile - 1) / kLocalTile));
+    const float kf = (float)k;
+    const double kk = k / (2.0 * 3.14159265358979323846);
+    if (fp32) {
+        if (q == 6)
+            hipLaunchKernelGGL((k_local_f32<OP, 6>), grid, dim3(kBlockLanes), 0, s, m.d_g32, m.d_vtx, test, ntest,
+                               trial, ntrial, (float *)Lr, (float *)Li, kf, kk);
+        else
+            hipLaunchKernelGGL((k_local_f32<OP, 4>), grid, dim3(kBlockLanes), 0, s, m.d_g32, m.d_vtx, test, ntest,
+                               trial, ntrial, (float *)Lr, (float *)Li, kf, kk);
+    } else {
+        if (q == 6)
+            hipLaunchKernelGGL((k_local_f64<OP, 6>), grid, dim3(kBlockLanes), 0, s, m.d_g64, m.d_vtx, test, ntest,
+                               trial, ntrial, (double *)Lr, (double *)Li, k);
+        else
+            hipLaunchKernelGGL((k_local_f64<OP, 4>), grid, dim3(kBlockLanes), 0, s, m.d_g64, m.d_vtx, test, ntest,
+                               trial, ntrial, (double *)Lr, (double *)Li, k);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock *blocks, int64_t nblocks, hipStream_t s,
@@ -1239,6 +1566,49 @@ hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock
                               nblocks, tclock);
     else
         hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kBlockLanes), 0, s, reqs, blocks, nblocks, tclock);
+    return hipGetLastError();
+}
+
+}  // namespace bem
+
+namespace bem {
+
+hipError_t launch_dense_local(int op, bool fp32, const bem_mesh &m, const int32_t *test, int ntest,
+                              const int32_t *trial, int ntrial, void *Lr, void *Li, double k, hipStream_t s)
+{
+    if (ntest <= 0 || ntrial <= 0) return hipSuccess;
+    if ((ntest + kLocalTile - 1) / kLocalTile > 65535) return hipErrorInvalidValue;
+    switch (op) {
+    case LSLP: return local_launch<LSLP>(fp32, m.q, m, test, ntest, trial, ntrial, Lr, Li, k, s);
+    case LDLP: return local_launch<LDLP>(fp32, m.q, m, test, ntest, trial, ntrial, Lr, Li, k, s);
+    case HSLP: return local_launch<HSLP>(fp32, m.q, m, test, ntest, trial, ntrial, Lr, Li, k, s);
+    case HDLP: return local_launch<HDLP>(fp32, m.q, m, test, ntest, trial, ntrial, Lr, Li, k, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_dense_gather(bool fp32, bool cplx, const void *Lr, const void *Li, int ntrial, const int32_t *rptr,
+                               const int32_t *rsrc, int nrows, const int32_t *cptr, const int32_t *csrc, int ncols,
+                               void *out, hipStream_t s)
+{
+    if (nrows <= 0 || ncols <= 0) return hipSuccess;
+    if (nrows > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((ncols + kBlockLanes - 1) / kBlockLanes), (unsigned)nrows);
+    if (fp32) {
+        if (cplx)
+            hipLaunchKernelGGL(k_gather_dense_f32<true>, grid, dim3(kBlockLanes), 0, s, (const float *)Lr,
+                               (const float *)Li, ntrial, rptr, rsrc, cptr, csrc, ncols, out);
+        else
+            hipLaunchKernelGGL(k_gather_dense_f32<false>, grid, dim3(kBlockLanes), 0, s, (const float *)Lr,
+                               (const float *)Li, ntrial, rptr, rsrc, cptr, csrc, ncols, out);
+    } else {
+        if (cplx)
+            hipLaunchKernelGGL(k_gather_dense_f64<true>, grid, dim3(kBlockLanes), 0, s, (const double *)Lr,
+                               (const double *)Li, ntrial, rptr, rsrc, cptr, csrc, ncols, out);
+        else
+            hipLaunchKernelGGL(k_gather_dense_f64<false>, grid, dim3(kBlockLanes), 0, s, (const double *)Lr,
+                               (const double *)Li, ntrial, rptr, rsrc, cptr, csrc, ncols, out);
+    }
     return hipGetLastError();
 }
 

@@ -124,9 +124,21 @@ struct bem_hmat {
     std::vector<Leaf> leaves;
     std::vector<bem::ValueBlock> store;   // owns the values the leaves point to
     bem_hmat_stats st{};
+    // Hypersingular operator through the single layer on DP1 (Eq.
+    // hyp_via_slp): `inner` is that single layer's H-matrix; per triangle t
+    // the curls of its three hat functions (curl[9 t + 3 a + j]) and its unit
+    // normal (normal[3 t + j]) give the sparse factors Q_j and P_j.
+    bem_hmat *inner = nullptr;
+    std::vector<int32_t> tri;
+    std::vector<double> curl, normal;
+    double k = 0.0;
     const int32_t *rows(const Leaf &L) const { return part.perm.data() + L.r0; }
     const int32_t *cols(const Leaf &L) const { return part.perm.data() + L.c0; }
-    ~bem_hmat() { bem::value_pool().give(store); }
+    ~bem_hmat()
+    {
+        bem::value_pool().give(store);
+        delete inner;
+    }
 };
 
 namespace bem {
@@ -870,12 +882,63 @@ int aca_callback(int64_t m, int64_t n, int is_complex, bem_row_fn get_row, bem_c
     return BEM_OK;
 }
 
+int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_params *p, bem_hmat **out);
+
+// Eq. hyp_via_slp: D = sum_j Q_j^T S Q_j - k^2 sum_j P_j^T S P_j, S the
+// single layer (Laplace or Helmholtz) on DP1 assembled as an H-matrix with
+// the same parameters, Q_j the j-th curl component of the hat functions
+// (constant on a triangle, the same value on its three DP1 functions), P_j
+// the hat functions times the j-th normal component.  On a flat triangle
+// curl lambda_a = n x grad lambda_a = (v_{a+1} - v_{a+2}) / J.
+int hmat_assemble_hyps_via_slp(bem_mesh *mesh, int op, double k, const bem_hmat_params *p, bem_hmat **out)
+{
+    bem_hmat_params q = *p;
+    q.hyps_via_slp = 0;
+    bem_hmat *S = nullptr;
+    const int slp = op == BEM_LAPLACE_HYPS ? BEM_LAPLACE_SLP : BEM_HELMHOLTZ_SLP;
+    const int rc = hmat_assemble(mesh, slp, BEM_DP1, k, &q, &S);
+    if (rc != BEM_OK) return rc;
+    bem_hmat *h = new bem_hmat();
+    h->op = op;
+    h->space = BEM_P1;
+    h->cplx = is_complex_op(op);
+    h->ndof = mesh->nv;
+    h->inner = S;
+    h->k = op == BEM_LAPLACE_HYPS ? 0.0 : k;
+    h->tri = mesh->tri;
+    const int64_t nt = mesh->nt;
+    h->curl.resize(9 * (size_t)nt);
+    h->normal.resize(3 * (size_t)nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        const double *v[3];
+        for (int a = 0; a < 3; ++a) v[a] = &mesh->xyz[3 * (size_t)mesh->tri[3 * t + a]];
+        double e1[3], e2[3];
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = v[1][d] - v[0][d];
+            e2[d] = v[2][d] - v[0][d];
+        }
+        const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        const double J = std::sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+        for (int d = 0; d < 3; ++d) h->normal[3 * t + d] = N[d] / J;
+        for (int a = 0; a < 3; ++a)
+            for (int d = 0; d < 3; ++d) h->curl[9 * t + 3 * a + d] = (v[(a + 1) % 3][d] - v[(a + 2) % 3][d]) / J;
+    }
+    h->st = S->st;
+    h->st.ndof = mesh->nv;
+    *out = h;
+    return BEM_OK;
+}
+
 int hmat_assemble(bem_mesh *mesh, int op, int space, double k, const bem_hmat_params *p, bem_hmat **out)
 {
     if (!mesh || !p || !out) return fail(BEM_E_ARG, "null argument");
     if (p->leaf_size < 1 || !(p->eta > 0) || p->max_rank < 1 || !(p->aca_tol >= 0) || p->dense_mode < 0 ||
-        p->dense_mode > 2 || p->max_block < 0)
+        p->dense_mode > 2 || p->max_block < 0 || p->hyps_via_slp < 0 || p->hyps_via_slp > 1)
         return fail(BEM_E_ARG, "bad H-matrix parameters");
+    if (p->hyps_via_slp && (op == BEM_LAPLACE_HYPS || op == BEM_HELMHOLTZ_HYPS)) {
+        if (space != BEM_P1) return fail(BEM_E_ARG, "the hypersingular operator needs continuous (P1) functions");
+        return hmat_assemble_hyps_via_slp(mesh, op, k, p, out);
+    }
     {
         // validate op/k/space/prec once with an empty request
         Request probe;
@@ -1195,9 +1258,51 @@ int plan_destroy(bem_aca_plan *pl)
     return BEM_OK;
 }
 
+int hmat_matvec(const bem_hmat *h, const void *xv, void *yv);
+
+// D x by Eq. hyp_via_slp: per component j, z = Q_j x on DP1, w = S z, y +=
+// Q_j^T w; for Helmholtz also y -= k^2 P_j^T S P_j x.
+int hyps_via_slp_matvec(const bem_hmat *h, const void *xv, void *yv)
+{
+    const int64_t nv = h->ndof, nt = (int64_t)h->tri.size() / 3;
+    const int f = h->cplx ? 2 : 1;
+    const double *x = (const double *)xv;
+    std::vector<double> y((size_t)nv * f, 0.0), z((size_t)3 * nt * f), w((size_t)3 * nt * f);
+    for (int pass = 0; pass < (h->k != 0.0 ? 2 : 1); ++pass)
+        for (int j = 0; j < 3; ++j) {
+            for (int64_t t = 0; t < nt; ++t)
+                for (int c = 0; c < f; ++c) {
+                    if (pass == 0) {
+                        double v = 0.0;
+                        for (int a = 0; a < 3; ++a) v += h->curl[9 * t + 3 * a + j] * x[f * h->tri[3 * t + a] + c];
+                        for (int a = 0; a < 3; ++a) z[f * (3 * t + a) + c] = v;
+                    } else {
+                        for (int a = 0; a < 3; ++a)
+                            z[f * (3 * t + a) + c] = h->normal[3 * t + j] * x[f * h->tri[3 * t + a] + c];
+                    }
+                }
+            const int rc = hmat_matvec(h->inner, z.data(), w.data());
+            if (rc != BEM_OK) return rc;
+            const double s = pass == 0 ? 1.0 : -h->k * h->k;
+            for (int64_t t = 0; t < nt; ++t)
+                for (int c = 0; c < f; ++c) {
+                    if (pass == 0) {
+                        const double sum = (w[f * (3 * t) + c] + w[f * (3 * t + 1) + c]) + w[f * (3 * t + 2) + c];
+                        for (int a = 0; a < 3; ++a) y[f * h->tri[3 * t + a] + c] += h->curl[9 * t + 3 * a + j] * sum;
+                    } else {
+                        for (int a = 0; a < 3; ++a)
+                            y[f * h->tri[3 * t + a] + c] += s * h->normal[3 * t + j] * w[f * (3 * t + a) + c];
+                    }
+                }
+        }
+    std::memcpy(yv, y.data(), sizeof(double) * y.size());
+    return BEM_OK;
+}
+
 int hmat_matvec(const bem_hmat *h, const void *xv, void *yv)
 {
     if (!h || !xv || !yv) return fail(BEM_E_ARG, "null argument");
+    if (h->inner) return hyps_via_slp_matvec(h, xv, yv);
     const int64_t n = h->ndof;
     const int f = h->cplx ? 2 : 1;
     const double *x = (const double *)xv;
@@ -1261,6 +1366,7 @@ int hmat_matvec(const bem_hmat *h, const void *xv, void *yv)
 int hmat_block_info(const bem_hmat *h, int64_t b, int32_t *adm, int64_t *m, int64_t *n, int32_t *rank,
                     const int32_t **rows, const int32_t **cols)
 {
+    if (h && h->inner) h = h->inner;   // the blocks of the single layer on DP1
     if (!h || b < 0 || b >= (int64_t)h->leaves.size()) return fail(BEM_E_ARG, "block index out of range");
     const auto &L = h->leaves[b];
     if (adm) *adm = L.adm;
@@ -1274,6 +1380,7 @@ int hmat_block_info(const bem_hmat *h, int64_t b, int32_t *adm, int64_t *m, int6
 
 int hmat_block_dense(const bem_hmat *h, int64_t b, void *outv)
 {
+    if (h && h->inner) h = h->inner;
     if (!h || !outv || b < 0 || b >= (int64_t)h->leaves.size()) return fail(BEM_E_ARG, "bad block");
     const auto &L = h->leaves[b];
     const int64_t m = L.m, n = L.n;

@@ -42,7 +42,8 @@ def test_library_error_path_without_device():
 
 
 @pytest.mark.parametrize("space,level,leaf,max_block", [(0, 3, 32, 0), (1, 3, 32, 0), (1, 6, 100, 0), (0, 5, 100, 0),
-                                                        (1, 5, 16, 256), (0, 4, 16, 64)])
+                                                        (1, 5, 16, 256), (0, 4, 16, 64), (2, 3, 48, 0),
+                                                        (2, 4, 100, 512)])
 def test_partition_matches_oracle(space, level, leaf, max_block):
     xyz, tri = inputs.icosphere(level)
     perm, ranges, blocks = bem.partition(xyz, tri, space, leaf, 1.0, max_block)

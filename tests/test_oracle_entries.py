@@ -385,3 +385,83 @@ def test_hypersingular_needs_p1(ico):
     m = O.OracleMesh(xyz, tri, 6)
     with pytest.raises(Exception):
         m.entries(O.LAPLACE_HYPS, O.P0, 0.0, [0], [1])
+
+
+# ---------------------------------------------------------------------------
+# Discontinuous P1 (dof 3 t + a) and the hypersingular operator through the
+# single layer on it (Eq. hyp_via_slp).
+
+
+@pytest.mark.parametrize("op,k", [(O.LAPLACE_SLP, 0.0), (O.LAPLACE_DLP, 0.0), (O.HELMHOLTZ_SLP, 1.7),
+                                  (O.HELMHOLTZ_DLP, 1.7)])
+def test_dp1_entry_brute_force(op, k):
+    """A DP1 entry of two disjoint triangles is the basis-weighted pair
+    integral: against the Duffy/Gauss-Legendre product rule, within the
+    6-point rule's error, which falls as the pair moves apart; the entry
+    with the basis functions' corners exchanged is far off."""
+    # Helmholtz at k = 1.7 keeps the phase error of the rule across a
+    # triangle (k h ~ 1.7) at any distance; Laplace's falls like (h/d)^5
+    far = 3e-6 if k == 0.0 else 5e-4
+    for d, bound in ((2.5, 5e-4), (8.0, far)):
+        A, B = placed_pair(d)
+        xyz, tri = two_triangle_mesh(A, B)
+        m = O.OracleMesh(xyz, tri, 6)
+        for a in range(3):
+            for b in range(3):
+                got = m.entries(op, O.DP1, k, [a], [3 + b], near=O.NEAR_ERROR)[0, 0]
+                ref = brute_pair(op, k, A, B, a, b, n=24)
+                assert abs(got - ref) <= bound * abs(ref), (d, a, b, got, ref)
+                if d < 3:
+                    wrong = brute_pair(op, k, A, B, (a + 1) % 3, b, n=24)
+                    assert abs(wrong - ref) > 1e-2 * abs(ref)
+
+
+@pytest.mark.parametrize("op,k", [(O.LAPLACE_SLP, 0.0), (O.LAPLACE_DLP, 0.0), (O.HELMHOLTZ_SLP, 2.1)])
+def test_dp1_sums_to_p0_and_assembles_p1(op, k, ico):
+    """Partition of unity: the three local functions of a triangle sum to
+    its indicator, so DP1 blocks summed over local indices give the P0
+    entries; gathering DP1 entries over the stars of two vertices (the
+    continuity map, an incidence matrix) gives the P1 entries."""
+    xyz, tri = ico(2)
+    m = O.OracleMesh(xyz, tri, 6)
+    nt, nv = tri.shape[0], xyz.shape[0]
+    rt = np.arange(0, nt, 7)
+    ct = np.arange(3, nt, 5)
+    dr = (3 * rt[:, None] + np.arange(3)).ravel()
+    dc = (3 * ct[:, None] + np.arange(3)).ravel()
+    D = m.entries(op, O.DP1, k, dr, dc)
+    P0 = m.entries(op, O.P0, k, rt, ct)
+    S = D.reshape(rt.size, 3, ct.size, 3).sum(axis=(1, 3))
+    assert np.abs(S - P0).max() <= 1e-13 * np.abs(P0).max()
+    C = np.zeros((nv, 3 * nt))
+    for t in range(nt):
+        for a in range(3):
+            C[tri[t, a], 3 * t + a] = 1.0
+    Dfull = m.entries(op, O.DP1, k, np.arange(3 * nt), np.arange(3 * nt))
+    rows, cols = np.arange(0, nv, 9), np.arange(2, nv, 4)
+    P1 = m.entries(op, O.P1, k, rows, cols)
+    G = C[rows] @ Dfull @ C[cols].T
+    assert np.abs(G - P1).max() <= 1e-12 * np.abs(P1).max()
+
+
+@pytest.mark.parametrize("op,k", [(O.LAPLACE_HYPS, 0.0), (O.HELMHOLTZ_HYPS, 2.3)])
+def test_hypersingular_via_single_layer_on_dp1(op, k, ico):
+    """Eq. hyp_via_slp: D = sum_j Q_j^T S Q_j - k^2 sum_j P_j^T S P_j with S
+    the single layer on DP1, Q_j the curl components and P_j the normal
+    components (oracle.hyp_via_slp_factors), equals the direct P1
+    hypersingular entries on the same regular pairs; a transposed or
+    sign-flipped factor, or a missing k^2 term, fails."""
+    xyz, tri = jittered(ico, level=1)
+    m = O.OracleMesh(xyz, tri, 6)
+    nt, nv = tri.shape[0], xyz.shape[0]
+    slp = O.LAPLACE_SLP if k == 0.0 else O.HELMHOLTZ_SLP
+    S = m.entries(slp, O.DP1, k, np.arange(3 * nt), np.arange(3 * nt))
+    Q, P = O.hyp_via_slp_factors(xyz, tri)
+    D = sum(Q[j].T @ S @ Q[j] for j in range(3)) - k * k * sum(P[j].T @ S @ P[j] for j in range(3))
+    ref = m.entries(op, O.P1, k, np.arange(nv), np.arange(nv))
+    assert np.abs(D - ref).max() <= 1e-11 * np.abs(ref).max()
+    if k != 0.0:
+        D0 = sum(Q[j].T @ S @ Q[j] for j in range(3))
+        assert np.abs(D0 - ref).max() > 1e-3 * np.abs(ref).max()
+    Dbad = sum(Q[j].T @ S @ Q[(j + 1) % 3] for j in range(3))
+    assert np.abs(Dbad - ref).max() > 1e-3 * np.abs(ref).max()

@@ -30,15 +30,17 @@ def test_cluster_tree_partitions_dofs(space):
         assert np.all(pts[c.idx] >= c.lo) and np.all(pts[c.idx] <= c.hi)
 
 
-@pytest.mark.parametrize("space,leaf,max_block", [(0, 32, 0), (1, 32, 0), (1, 8, 48), (0, 8, 40)])
+@pytest.mark.parametrize("space,leaf,max_block", [(0, 32, 0), (1, 32, 0), (1, 8, 48), (0, 8, 40), (2, 24, 0)])
 def test_block_tree_tiles_square_and_admissible_blocks_are_regular(space, leaf, max_block):
-    xyz, tri = inputs.icosphere(3)
+    xyz, tri = inputs.icosphere(3 if space != 2 else 2)
     nodes, leaves = T.partition(xyz, tri, space, leaf, 1.0, max_block)
-    n = xyz.shape[0] if space == 1 else tri.shape[0]
+    n = {0: tri.shape[0], 1: xyz.shape[0], 2: 3 * tri.shape[0]}[space]
     cover = np.zeros((n, n), dtype=np.int32)
     # triangles supporting each dof
     if space == 0:
         support = [np.array([t]) for t in range(n)]
+    elif space == 2:
+        support = [np.array([d // 3]) for d in range(n)]
     else:
         support = [np.flatnonzero((tri == v).any(1)) for v in range(n)]
     for a, b, ok in leaves:
