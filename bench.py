@@ -34,6 +34,7 @@ import hashlib
 import json
 import math
 import os
+import resource
 import sys
 import time
 
@@ -605,6 +606,7 @@ def serve_leg(bem, inputs, plan, segs, prec, args, label):
     tel0 = gpu_telemetry()
     torch.cuda.synchronize()
     steps = []
+    ru0 = resource.getrusage(resource.RUSAGE_SELF)
     t_all = time.perf_counter()
     for i in range(args.steps):
         seg = segs[nw + i]
@@ -617,6 +619,7 @@ def serve_leg(bem, inputs, plan, segs, prec, args, label):
               flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_all
+    ru1 = resource.getrusage(resource.RUSAGE_SELF)
     tel1 = gpu_telemetry()
     sst = bem.server_stats()
     kst = bem.server_kernel_stats()
@@ -640,6 +643,11 @@ def serve_leg(bem, inputs, plan, segs, prec, args, label):
         max(1, sum(x[0]["blocks"] for x in steps)),
         "latency_p50_ms": sst["latency_p50"] * 1e3, "latency_p99_ms": sst["latency_p99"] * 1e3,
         "sst": sst, "kst": kst, "telemetry": {"before": tel0, "after": tel1},
+        # host CPU time of the whole process over the timed steps (all threads)
+        "host_cpu": {"user_seconds": ru1.ru_utime - ru0.ru_utime, "system_seconds": ru1.ru_stime - ru0.ru_stime,
+                     "cores_busy": (ru1.ru_utime - ru0.ru_utime + ru1.ru_stime - ru0.ru_stime) / wall,
+                     "voluntary_switches": ru1.ru_nvcsw - ru0.ru_nvcsw,
+                     "involuntary_switches": ru1.ru_nivcsw - ru0.ru_nivcsw},
     }
     sweep = []
     loads = [float(x) for x in args.sweep.split(",") if x.strip()] if args.sweep else []
@@ -762,7 +770,7 @@ def cylinder_main(args):
                                     for k in ("queue", "stage", "device", "complete")},
         "kernel_busy_fraction": sst["kernel_seconds"] / f32["wall"] if f32["wall"] > 0 else None,
         "fp64": fp64, "fp32_over_fp64": (f32["value"] / fp64["value"]) if fp64 else None,
-        "max_rel_err_sampled": worst, "gpu_telemetry": f32["telemetry"],
+        "max_rel_err_sampled": worst, "gpu_telemetry": f32["telemetry"], "host_cpu": f32["host_cpu"],
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -1230,7 +1230,15 @@ int plan_run(bem_aca_plan *pl, const int64_t *blocks, const double *arrival, int
         st->mean_start_delay = C.start_delay / nd;
         st->mean_block_seconds = C.block_time / nd;
     }
-    if (std::getenv("BEM_DEBUG_TIMING")) server_print_phases();
+    if (std::getenv("BEM_DEBUG_TIMING")) {
+        const double np = (double)std::max<int64_t>(1, C.nproc);
+        fprintf(stderr, "[bem] run %.3fs: %lld completions, mean pickup delay %.1f us, mean batch-processing span %.1f us\n",
+                t1 - C.t0, (long long)C.nproc, 1e6 * C.qdelay / np, 1e6 * C.proc / np);
+        fprintf(stderr, "[bem] worker us/request: busy %.3f convert %.3f aca %.3f release %.3f prepare %.3f submit %.3f\n",
+                1e6 * C.busy / np, 1e6 * C.t_conv / np, 1e6 * C.t_aca / np, 1e6 * C.t_rel / np, 1e6 * C.t_prep / np,
+                1e6 * C.t_flush / np);
+        server_print_phases();
+    }
     return BEM_OK;
 }
 
