@@ -190,6 +190,31 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
                            const int32_t *rows, int64_t nrows, const int32_t *cols, int64_t ncols,
                            bem_prec prec, bem_near near, void *dev_out, void *stream);
 
+/* For callers that cannot allocate device memory (code that runs under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same request as bem_eval_entries_async, computed by the same kernels, with
+ * its workspace (descriptor, block table, singular-pair records, staged
+ * inputs, status word) in a fixed 32 MiB static device array instead of the
+ * stream-ordered allocator, and its host image in a per-thread pageable
+ * buffer instead of pinned staging.  The call makes no device or pinned
+ * allocation.  Differences from bem_eval_entries_async:
+ *   - a request whose workspace exceeds 32 MiB fails with BEM_E_OOM
+ *     (nothing enqueued); a P1 row or column of 4,096 entries needs well
+ *     under 1 MiB;
+ *   - the copy of the workspace from pageable host memory is synchronous
+ *     with the host, so the call returns once the stream has reached it;
+ *   - every call on one device uses the same workspace: calls that overlap on
+ *     a device race (two streams, or two host threads) and must be ordered
+ *     by the caller, for instance by issuing them on one stream from one
+ *     thread.  The workspace keeps the last call's contents; everything a
+ *     call reads is rewritten by that call.
+ * dev_out (device, nrows x ncols, types as bem_eval_entries) is complete
+ * when `stream` reaches the end of the work this call enqueued.  Arguments
+ * and errors otherwise as bem_eval_entries_async. */
+int bem_eval_entries_async_noalloc(bem_mesh *mesh, bem_op op, bem_space space, double k,
+                                   const int32_t *rows, int64_t nrows, const int32_t *cols, int64_t ncols,
+                                   bem_prec prec, bem_near near, void *dev_out, void *stream);
+
 /* ---- pair-based dense blocks ------------------------------------------- */
 typedef struct {
     int64_t pairs;               /* triangle pairs integrated (row-star x column-star triangles, all panels) */

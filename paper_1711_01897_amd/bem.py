@@ -34,7 +34,7 @@ EXPORTS = [
     "bem_server_stats", "bem_server_kernel_stats", "bem_aca_block", "bem_aca_callback", "bem_partition", "bem_hmat_assemble",
     "bem_hmat_matvec", "bem_hmat_stats_get", "bem_hmat_block_info", "bem_hmat_block_dense", "bem_hmat_destroy",
     "bem_aca_plan_create", "bem_aca_plan_info", "bem_aca_plan_block", "bem_aca_plan_run", "bem_aca_plan_factors",
-    "bem_aca_plan_destroy", "bem_eval_dense",
+    "bem_aca_plan_destroy", "bem_eval_dense", "bem_eval_entries_async_noalloc",
 ]
 
 
@@ -143,6 +143,7 @@ def lib():
     L.bem_ticket_times.argtypes = [_p, _dp, _dp]
     L.bem_ticket_free.argtypes = [_p]
     L.bem_eval_entries_async.argtypes = entry_args + [_p, _p]
+    L.bem_eval_entries_async_noalloc.argtypes = entry_args + [_p, _p]
     L.bem_server_config.argtypes = [ctypes.c_size_t, ctypes.c_int]
     L.bem_server_stats.argtypes = [ctypes.POINTER(ServerStats), ctypes.c_int]
     L.bem_server_kernel_stats.argtypes = [ctypes.POINTER(KernelStats), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -290,10 +291,7 @@ def submit(mesh: Mesh, op, space, k, rows, cols, prec=FP32, near=NEAR_SKIP) -> T
     return Ticket(t, out, (rows, cols))
 
 
-def eval_entries_async(mesh: Mesh, op, space, k, rows, cols, out, prec=FP32, near=NEAR_SKIP, stream=None):
-    """Write A[rows, cols] into the device tensor `out` (torch, row-major,
-    dtype matching op/prec) on `stream` (torch.cuda.Stream; default: the
-    current stream)."""
+def _device_request(fn, mesh: Mesh, op, space, k, rows, cols, out, prec, near, stream):
     import torch
     rows, cols = _idx(rows), _idx(cols)
     want = {np.float32: torch.float32, np.float64: torch.float64, np.complex64: torch.complex64,
@@ -301,10 +299,23 @@ def eval_entries_async(mesh: Mesh, op, space, k, rows, cols, out, prec=FP32, nea
     if out.dtype != want or not out.is_cuda or not out.is_contiguous() or out.numel() != rows.size * cols.size:
         raise ValueError("out must be a contiguous device tensor of the right dtype and size")
     s = stream if stream is not None else torch.cuda.current_stream(out.device)
-    _check(lib().bem_eval_entries_async(mesh.handle, op, space, float(k), _ip(rows), rows.size, _ip(cols),
-                                        cols.size, prec, near, ctypes.c_void_p(out.data_ptr()),
-                                        ctypes.c_void_p(s.cuda_stream)))
+    _check(fn(mesh.handle, op, space, float(k), _ip(rows), rows.size, _ip(cols), cols.size, prec, near,
+              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s.cuda_stream)))
     return out
+
+
+def eval_entries_async(mesh: Mesh, op, space, k, rows, cols, out, prec=FP32, near=NEAR_SKIP, stream=None):
+    """Write A[rows, cols] into the device tensor `out` (torch, row-major,
+    dtype matching op/prec) on `stream` (torch.cuda.Stream; default: the
+    current stream)."""
+    return _device_request(lib().bem_eval_entries_async, mesh, op, space, k, rows, cols, out, prec, near, stream)
+
+
+def eval_entries_async_noalloc(mesh: Mesh, op, space, k, rows, cols, out, prec=FP32, near=NEAR_SKIP, stream=None):
+    """bem_eval_entries_async_noalloc: as eval_entries_async, with the
+    library's fixed per-device workspace instead of any allocation."""
+    return _device_request(lib().bem_eval_entries_async_noalloc, mesh, op, space, k, rows, cols, out, prec, near,
+                           stream)
 
 
 def server_config(arena_bytes: int, max_batch_requests: int = 16384):

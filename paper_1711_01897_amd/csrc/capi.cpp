@@ -101,6 +101,140 @@ void pinned_release(char *p, hipEvent_t after)
     g_stage_pending.push_back({after, p});
 }
 
+// Enqueues an expanded request on `s` with its result in device memory
+// dev_out.  Workspace layout: descriptor | block table | singular pairs |
+// inputs | status word, copied to the device in one piece before the
+// launches.  With fixed == nullptr the workspace comes from the
+// stream-ordered allocator and the host image from pinned staging released
+// once its copy has completed; otherwise both live in fixed memory: the
+// workspace is `fixed` (fixed_bytes long; larger requests fail), the host
+// image a per-thread pageable buffer whose copy completes before the call
+// returns (a pageable host-to-device copy is synchronous with the host).
+int enqueue_device_request(Request &r, void *dev_out, hipStream_t s, char *fixed, size_t fixed_bytes)
+{
+    bem_mesh *mesh = r.mesh;
+    if (r.near == BEM_NEAR_ERROR) {
+        // host-side check: nothing may be enqueued for a failing request
+        if (r.space == BEM_P0) {
+            for (int32_t a : r.rows)
+                for (int32_t b : r.cols)
+                    if (mesh->adjacent(a, b)) return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
+        } else {
+            for (size_t f = 0; 2 * f + 1 < r.fix.size(); ++f)
+                for (int32_t st = r.fix[2 * f]; st < r.fix[2 * f + 1]; ++st)
+                    for (int32_t t : r.own.lane)
+                        if (mesh->adjacent(mesh->star[st] >> 2, t))
+                            return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
+        }
+    }
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t off_req = off;
+    off = al(off + sizeof(ReqDev));
+    const size_t off_b = off;
+    off = al(off + sizeof(EntryBlock) * (size_t)r.nblocks);
+    const size_t off_near = off;
+    const bool p1_near = r.space != BEM_P0 && !r.near_items.empty();
+    off = al(off + (p1_near ? near_p1_layout(r).bytes : sizeof(NearItem) * r.near_items.size()));
+    const size_t off_in = off;
+    off = al(off + r.in_bytes);
+    const size_t off_status = off;
+    off = al(off + 8);
+    const size_t in_total = off;
+    if (fixed && in_total > fixed_bytes)
+        return fail(BEM_E_OOM, "request needs " + std::to_string(in_total) + " bytes of workspace, more than the " +
+                                   std::to_string(fixed_bytes) + "-byte static workspace of the no-allocation entry point");
+    char *host = nullptr;
+    thread_local std::vector<char> pageable;
+    if (fixed) {
+        pageable.assign(in_total, 0);
+        host = pageable.data();
+    } else {
+        // descriptors go through pinned staging that is released once the
+        // copy has completed (checked on later calls), so nothing here waits
+        host = pinned_stage(in_total);
+        if (!host) return fail(BEM_E_OOM, "pinned staging allocation failed");
+        std::memset(host, 0, in_total);
+    }
+    char *ws = fixed;
+    if (!fixed) {
+        hipError_t e = hipMallocAsync((void **)&ws, in_total, s);
+        if (e != hipSuccess) {
+            pinned_release(host, nullptr);
+            return fail(BEM_E_DEVICE, std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        }
+    }
+    ReqDev d;
+    stage_request_inputs(r, host, ws, off_in, d);
+    finish_descriptor(r, ws, 0, off_status, d);
+    d.out = dev_out;
+    std::memcpy(host + off_req, &d, sizeof(ReqDev));
+    write_blocks(r, 0, reinterpret_cast<EntryBlock *>(host + off_b));
+    if (p1_near) {
+        stage_near_p1(r, near_p1_layout(r), host + off_near, ws + off_near, static_cast<char *>(dev_out), 0, 0, 0);
+    } else {
+        NearItem *q = reinterpret_cast<NearItem *>(host + off_near);
+        for (size_t j = 0; j < r.near_items.size(); ++j) {
+            q[j] = r.near_items[j];
+            q[j].out = static_cast<char *>(dev_out) + (size_t)r.near_index[j] * r.elem_bytes;
+        }
+    }
+    hipError_t e = hipMemcpyAsync(ws, host, in_total, hipMemcpyHostToDevice, s);
+    if (!fixed) {
+        hipEvent_t ev = nullptr;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(ev, s);
+        pinned_release(host, e == hipSuccess ? ev : nullptr);
+    }
+    if (e != hipSuccess) return fail(BEM_E_DEVICE, std::string("staging copy: ") + hipGetErrorString(e));
+    const ReqDev *dreq = (const ReqDev *)(ws + off_req);
+    Variant v{kernel_op(r.op), r.space, r.prec, mesh->q};
+    BEM_HIP_TRY(launch_entries(v, dreq, (const EntryBlock *)(ws + off_b), r.nblocks, s));
+    if (p1_near)
+        BEM_HIP_TRY(launch_near_p1_region(r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS ? (int)r.op
+                                                                                                : kernel_op(r.op),
+                                          r.prec == BEM_FP32, near_p1_layout(r), ws + off_near,
+                                          (int64_t)r.near_items.size(), (int64_t)r.near_recs.size(), s));
+    else
+        BEM_HIP_TRY(launch_near(kernel_op(r.op), r.prec == BEM_FP32, (const NearItem *)(ws + off_near),
+                                (int64_t)r.near_items.size(), s));
+    if (!fixed) BEM_HIP_TRY(hipFreeAsync(ws, s));
+    return BEM_OK;
+}
+
+// Workspace of bem_eval_entries_async_noalloc: one request's descriptor,
+// block table, singular-pair records, inputs and status word.  Each device
+// the library runs on holds its own copy for the life of the process; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// that device.
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device
+// with that device current (the previous current device is restored).
+int noalloc_workspace(int device, char **out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(BEM_E_ARG, "device ordinal out of range");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        BEM_HIP_TRY(hipGetDevice(&cur));
+        if (cur != device) BEM_HIP_TRY(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(BEM_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return BEM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -210,81 +344,22 @@ int bem_eval_entries_async(bem_mesh *mesh, bem_op op, bem_space space, double k,
     if (rc != BEM_OK) return rc;
     if (r.entries() == 0) return BEM_OK;
     if (!dev_out) return fail(BEM_E_ARG, "null output");
-    if (near == BEM_NEAR_ERROR) {
-        // host-side check: nothing may be enqueued for a failing request
-        if (space == BEM_P0) {
-            for (int32_t a : r.rows)
-                for (int32_t b : r.cols)
-                    if (mesh->adjacent(a, b)) return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
-        } else {
-            for (size_t f = 0; 2 * f + 1 < r.fix.size(); ++f)
-                for (int32_t s = r.fix[2 * f]; s < r.fix[2 * f + 1]; ++s)
-                    for (int32_t t : r.own.lane)
-                        if (mesh->adjacent(mesh->star[s] >> 2, t))
-                            return fail(BEM_E_NEARFIELD, "a contributing triangle pair shares a vertex");
-        }
-    }
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    // layout: descriptor | block table | singular pairs | inputs | status
-    size_t off = 0;
-    const size_t off_req = off;
-    off = al(off + sizeof(ReqDev));
-    const size_t off_b = off;
-    off = al(off + sizeof(EntryBlock) * (size_t)r.nblocks);
-    const size_t off_near = off;
-    const bool p1_near = r.space != BEM_P0 && !r.near_items.empty();
-    off = al(off + (p1_near ? near_p1_layout(r).bytes : sizeof(NearItem) * r.near_items.size()));
-    const size_t off_in = off;
-    off = al(off + r.in_bytes);
-    const size_t off_status = off;
-    off = al(off + 8);
-    const size_t in_total = off;
-    // descriptors go through pinned staging that is released once the copy
-    // has completed (checked on later calls), so nothing here waits
-    char *host = pinned_stage(in_total);
-    if (!host) return fail(BEM_E_OOM, "pinned staging allocation failed");
-    std::memset(host, 0, in_total);
-    hipStream_t s = (hipStream_t)stream;
+    return enqueue_device_request(r, dev_out, (hipStream_t)stream, nullptr, 0);
+}
+
+int bem_eval_entries_async_noalloc(bem_mesh *mesh, bem_op op, bem_space space, double k, const int32_t *rows,
+                                   int64_t nrows, const int32_t *cols, int64_t ncols, bem_prec prec, bem_near near,
+                                   void *dev_out, void *stream)
+{
+    Request r;
+    int rc = fill_request(r, mesh, op, space, k, rows, nrows, cols, ncols, prec, near);
+    if (rc != BEM_OK) return rc;
+    if (r.entries() == 0) return BEM_OK;
+    if (!dev_out) return fail(BEM_E_ARG, "null output");
     char *ws = nullptr;
-    hipError_t e = hipMallocAsync((void **)&ws, off, s);
-    if (e != hipSuccess) {
-        pinned_release(host, nullptr);
-        return fail(BEM_E_DEVICE, std::string("hipMallocAsync: ") + hipGetErrorString(e));
-    }
-    ReqDev d;
-    stage_request_inputs(r, host, ws, off_in, d);
-    finish_descriptor(r, ws, 0, off_status, d);
-    d.out = dev_out;
-    std::memcpy(host + off_req, &d, sizeof(ReqDev));
-    write_blocks(r, 0, reinterpret_cast<EntryBlock *>(host + off_b));
-    if (p1_near) {
-        stage_near_p1(r, near_p1_layout(r), host + off_near, ws + off_near, static_cast<char *>(dev_out), 0, 0, 0);
-    } else {
-        NearItem *q = reinterpret_cast<NearItem *>(host + off_near);
-        for (size_t j = 0; j < r.near_items.size(); ++j) {
-            q[j] = r.near_items[j];
-            q[j].out = static_cast<char *>(dev_out) + (size_t)r.near_index[j] * r.elem_bytes;
-        }
-    }
-    e = hipMemcpyAsync(ws, host, in_total, hipMemcpyHostToDevice, s);
-    hipEvent_t ev = nullptr;
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(ev, s);
-    pinned_release(host, e == hipSuccess ? ev : nullptr);
-    if (e != hipSuccess) return fail(BEM_E_DEVICE, std::string("staging copy: ") + hipGetErrorString(e));
-    const ReqDev *dreq = (const ReqDev *)(ws + off_req);
-    Variant v{kernel_op(r.op), r.space, r.prec, mesh->q};
-    BEM_HIP_TRY(launch_entries(v, dreq, (const EntryBlock *)(ws + off_b), r.nblocks, s));
-    if (p1_near)
-        BEM_HIP_TRY(launch_near_p1_region(r.op == BEM_LAPLACE_HYPS || r.op == BEM_HELMHOLTZ_HYPS ? (int)r.op
-                                                                                                : kernel_op(r.op),
-                                          r.prec == BEM_FP32, near_p1_layout(r), ws + off_near,
-                                          (int64_t)r.near_items.size(), (int64_t)r.near_recs.size(), s));
-    else
-        BEM_HIP_TRY(launch_near(kernel_op(r.op), r.prec == BEM_FP32, (const NearItem *)(ws + off_near),
-                                (int64_t)r.near_items.size(), s));
-    BEM_HIP_TRY(hipFreeAsync(ws, s));
-    return BEM_OK;
+    rc = noalloc_workspace(mesh->device, &ws);
+    if (rc != BEM_OK) return rc;
+    return enqueue_device_request(r, dev_out, (hipStream_t)stream, ws, kNoAllocBytes);
 }
 
 int bem_server_config(size_t arena_bytes, int max_batch_requests)
