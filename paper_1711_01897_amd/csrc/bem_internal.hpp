@@ -20,11 +20,16 @@ struct Request;
 // ---------------------------------------------------------------------------
 // Device layout of one triangle.
 //
-// FP32 record, 32 floats (128 B), for the compensated FP32 path:
-//   [0..2]  centroid, high part (float of the FP64 centroid)   [3]  J = |(b-a)x(c-a)|
-//   [4..6]  centroid, low part  (float of the FP64 remainder)  [7]  0
-//   [8..10] unit normal                                        [11] 0
-//   [12..]  quadrature points relative to the centroid, point-major (x,y,z)
+// FP32 record, 16 floats (64 B, one load of four float4), for the
+// compensated FP32 path:
+//   [0..2]   centroid, high part (float of the FP64 centroid)   [3]  J = |(b-a)x(c-a)|
+//   [4..6]   centroid, low part  (float of the FP64 remainder)  [7]  n_x
+//   [8..10]  e1 = b - a                                         [11] n_y
+//   [12..14] e2 = c - a                                         [15] n_z
+// (n the unit normal).  Kernels expand it in registers to the working
+// layout of n32<Q>() words: [0..2] centroid high, [3] J, [4..6] centroid
+// low, [8..10] n, and from [12] the quadrature points relative to the
+// centroid, x_p - c = (xi_p - 1/3) e1 + (eta_p - 1/3) e2, point-major.
 // Differences of two triangles' positions are formed as (hi_a - hi_b) +
 // (lo_a - lo_b) + (offset_p - offset_q): the large centroid parts cancel
 // first, so the result keeps FP32 relative accuracy in |x - y| wherever the
@@ -32,7 +37,7 @@ struct Request;
 //
 // FP64 record, 24 doubles (192 B), for the plain FP64 path:
 //   [0..2] unit normal  [3] J  [4..] absolute quadrature points, point-major.
-constexpr int kGeo32Stride = 32;
+constexpr int kGeo32Stride = 16;
 constexpr int kGeo64Stride = 24;
 constexpr int kBlockLanes = 256;    // lane-side items per workgroup (4 wavefronts)
 constexpr int kStage = 8;           // fixed-side triangles staged in LDS at a time

@@ -71,18 +71,44 @@ constexpr int vpt(int a) { return Q - 3 + a; }
 template <int Q>
 constexpr double vscale() { return 1.0 / (1.0 - 3.0 * rule::Rule<Q>::l1[Q - 3]); }
 
+// Working layout (n32<Q>() words) of a packed FP32 triangle record (see
+// bem_internal.hpp): centroid parts, J and normal copied, the quadrature
+// points relative to the centroid formed from the two edges as
+// x_p - c = (xi_p - 1/3) e1 + (eta_p - 1/3) e2.  Every kernel expands a
+// record with this one function, so a triangle's points are the same bits
+// wherever it is used.
+template <int Q>
+__device__ __forceinline__ void expand32(const float4 &r0, const float4 &r1, const float4 &r2, const float4 &r3,
+                                         float *v)
+{
+    v[0] = r0.x;
+    v[1] = r0.y;
+    v[2] = r0.z;
+    v[3] = r0.w;
+    v[4] = r1.x;
+    v[5] = r1.y;
+    v[6] = r1.z;
+    v[7] = 0.0f;
+    v[8] = r1.w;
+    v[9] = r2.w;
+    v[10] = r3.w;
+    v[11] = 0.0f;
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const float a = (float)(rule::Rule<Q>::l1[p] - 1.0 / 3.0), b = (float)(rule::Rule<Q>::l2[p] - 1.0 / 3.0);
+        v[12 + 3 * p] = fmaf(b, r3.x, a * r2.x);
+        v[13 + 3 * p] = fmaf(b, r3.y, a * r2.y);
+        v[14 + 3 * p] = fmaf(b, r3.z, a * r2.z);
+    }
+#pragma unroll
+    for (int i = 12 + 3 * Q; i < n32<Q>(); ++i) v[i] = 0.0f;
+}
+
 template <int Q>
 __device__ __forceinline__ void load32(const float *__restrict__ g, int t, float *v)
 {
     const float4 *p = reinterpret_cast<const float4 *>(g + (size_t)t * kGeo32Stride);
-#pragma unroll
-    for (int i = 0; i < n32<Q>() / 4; ++i) {
-        const float4 x = p[i];
-        v[4 * i] = x.x;
-        v[4 * i + 1] = x.y;
-        v[4 * i + 2] = x.z;
-        v[4 * i + 3] = x.w;
-    }
+    expand32<Q>(p[0], p[1], p[2], p[3], v);
 }
 
 template <int Q>
@@ -847,17 +873,22 @@ __device__ __forceinline__ int stage_star_tab(const EntryBlock &B, int sb, int s
     const int t = threadIdx.x;
     const int ns = min(kStage, s1 - sb);
     __syncthreads();   // the previous stage has been read
-    if (t < ns * W) {
-        const int k = t / W, w = t - k * W;
-        const float x = B.sgeo[(size_t)(sb + k) * kGeo32Stride + w];
-        sG[k][w] = (TRIAL && w >= 12 && w < 12 + 3 * Q) ? -2.0f * x : x;
-    }
-    if (TRIAL && t < ns * Q) {
-        const int k = t / Q, q = t - k * Q;
-        const float *o = B.sgeo + (size_t)(sb + k) * kGeo32Stride + 12 + 3 * q;
-        sG[k][W + q] = fmaf(o[0], o[0], fmaf(o[1], o[1], o[2] * o[2]));
-    }
     if (t < ns) {
+        // one thread per staged triangle expands its record
+        float v[W];
+        load32<Q>(B.sgeo, sb + t, v);
+        if constexpr (TRIAL) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                float *o = v + 12 + 3 * q;
+                sG[t][W + q] = fmaf(o[0], o[0], fmaf(o[1], o[1], o[2] * o[2]));
+                o[0] *= -2.0f;
+                o[1] *= -2.0f;
+                o[2] *= -2.0f;
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) sG[t][w] = v[w];
         const int4 m = B.smeta[sb + t];
         sV[t] = m;
         sL[t] = m.w;
@@ -1357,11 +1388,13 @@ __global__ __launch_bounds__(kBlockLanes) void k_local_f32(const float *__restri
     const int t = threadIdx.x;
     const int m0 = blockIdx.y * kLocalTile;
     const int nm = min(kLocalTile, ntest - m0);
-    for (int i = t; i < nm * W; i += kBlockLanes) {
-        const int k = i / W, w = i - k * W;
-        sT[k][w] = g32[(size_t)test[m0 + k] * kGeo32Stride + w];
+    if (t < nm) {
+        float v[W];
+        load32<Q>(g32, test[m0 + t], v);
+#pragma unroll
+        for (int w = 0; w < W; ++w) sT[t][w] = v[w];
+        sV[t] = vtx[test[m0 + t]];
     }
-    if (t < nm) sV[t] = vtx[test[m0 + t]];
     __syncthreads();
     const int n = blockIdx.x * kBlockLanes + t;
     if (n >= ntrial) return;   // no barrier below

@@ -1,6 +1,8 @@
 // Per-triangle geometry, computed once on the device when a mesh is created
 // and kept resident (Section 3.2.1: normals, Jacobians and global quadrature
 // points are precomputed on the device and laid out for coalesced access).
+// The FP32 record keeps the two edge vectors instead of the quadrature
+// points (64 bytes instead of 128); the kernels form the points from them.
 #include <algorithm>
 #include <cstdint>
 
@@ -33,28 +35,27 @@ __global__ __launch_bounds__(256) void k_geometry(const double *__restrict__ xyz
     for (int d = 0; d < 3; ++d) cen[d] = ((a[d] + b[d]) + c[d]) / 3.0;
 
     double *r64 = g64 + t * kGeo64Stride;
-    float *r32 = g32 + t * kGeo32Stride;
+    float r32[kGeo32Stride];
     for (int d = 0; d < 3; ++d) {
         r64[d] = N[d] * inv;
         const float hi = (float)cen[d];
         r32[d] = hi;
         r32[4 + d] = (float)(cen[d] - (double)hi);
-        r32[8 + d] = (float)(N[d] * inv);
+        r32[8 + d] = (float)e1[d];
+        r32[12 + d] = (float)e2[d];
     }
     r64[3] = J;
     r32[3] = (float)J;
-    r32[7] = 0.0f;
-    r32[11] = 0.0f;
+    r32[7] = (float)(N[0] * inv);
+    r32[11] = (float)(N[1] * inv);
+    r32[15] = (float)(N[2] * inv);
+    float4 *o32 = reinterpret_cast<float4 *>(g32 + t * kGeo32Stride);
+    for (int i = 0; i < kGeo32Stride / 4; ++i) o32[i] = make_float4(r32[4 * i], r32[4 * i + 1], r32[4 * i + 2], r32[4 * i + 3]);
 #pragma unroll
     for (int p = 0; p < Q; ++p) {
-        for (int d = 0; d < 3; ++d) {
-            const double x = a[d] + rule::Rule<Q>::l1[p] * e1[d] + rule::Rule<Q>::l2[p] * e2[d];
-            r64[4 + 3 * p + d] = x;
-            r32[12 + 3 * p + d] = (float)(x - cen[d]);
-        }
+        for (int d = 0; d < 3; ++d) r64[4 + 3 * p + d] = a[d] + rule::Rule<Q>::l1[p] * e1[d] + rule::Rule<Q>::l2[p] * e2[d];
     }
     for (int i = 4 + 3 * Q; i < kGeo64Stride; ++i) r64[i] = 0.0;
-    for (int i = 12 + 3 * Q; i < kGeo32Stride; ++i) r32[i] = 0.0f;
     vtx[t] = make_int4(i0, i1, i2, 0);
 }
 

@@ -548,6 +548,9 @@ void worker(AssemblyCtx &C, int per_worker)
     dq.spin_s = worker_spin_seconds();
     static const int pop_most = worker_env("BEM_WORKER_POP", 64);
     static const int flush_every = worker_env("BEM_WORKER_FLUSH", 64);
+    // per-request phase timers (a clock read costs tens of nanoseconds, a
+    // noticeable share of a request's host work): only with BEM_DEBUG_TIMING
+    static const bool fine = std::getenv("BEM_DEBUG_TIMING") != nullptr;
     WorkerTally tally;
     ValueArena arena;   // values of the blocks this worker finishes
     std::vector<Slot<T>> slots(per_worker);
@@ -659,9 +662,9 @@ void worker(AssemblyCtx &C, int per_worker)
         np += (int64_t)done.size();
         for (Request *r : done) {
             if ((int)submit.size() >= flush_every) {
-                const double f0 = now_seconds();
+                const double f0 = fine ? now_seconds() : 0.0;
                 flush();
-                tf += now_seconds() - f0;
+                if (fine) tf += now_seconds() - f0;
             }
             Slot<T> &s = slots[r->tag];
             bool finished = false;
@@ -673,18 +676,18 @@ void worker(AssemblyCtx &C, int per_worker)
                 bem_hmat::Leaf &L = C.h->leaves[s.leaf];
                 const int64_t cnt = r->entries();
                 if (!s.adm) {
-                    const double c0 = now_seconds();
+                    const double c0 = fine ? now_seconds() : 0.0;
                     s.buf.resize(cnt);
                     to_scalar<T>(r->result, C.prec, cnt, s.buf.data());
-                    tc += now_seconds() - c0;
+                    if (fine) tc += now_seconds() - c0;
                     double *D = arena.take((size_t)cnt * (sizeof(T) / sizeof(double)));
                     std::memcpy(D, s.buf.data(), sizeof(T) * cnt);
                     L.D = D;
                     finished = true;
                 } else {
-                    const double a0 = now_seconds();
+                    const double a0 = fine ? now_seconds() : 0.0;
                     aca_consume(s.core, r->result, C.prec);
-                    ta += now_seconds() - a0;
+                    if (fine) ta += now_seconds() - a0;
                     if (s.core.phase == AcaCore<T>::DONE) {
                         L.rank = s.core.k;
                         const size_t f = sizeof(T) / sizeof(double);
@@ -699,7 +702,7 @@ void worker(AssemblyCtx &C, int per_worker)
                 }
             }
             if (r->batch) {
-                const double c1 = now_seconds();
+                const double c1 = fine ? now_seconds() : 0.0;
                 if (r->batch != rel_batch) {
                     release_run();
                     rel_batch = r->batch;
@@ -707,7 +710,7 @@ void worker(AssemblyCtx &C, int per_worker)
                 ++rel_n;
                 r->batch = nullptr;
                 r->result = nullptr;
-                tr += now_seconds() - c1;
+                if (fine) tr += now_seconds() - c1;
             }
             if (finished || C.error.load()) {
                 s.busy = false;
@@ -718,9 +721,9 @@ void worker(AssemblyCtx &C, int per_worker)
                 if (!C.error.load()) fill();
                 continue;
             }
-            const double p0 = now_seconds();
+            const double p0 = fine ? now_seconds() : 0.0;
             const int rc = prepare_slot(C, s, dq, r->tag, tally);
-            tp += now_seconds() - p0;
+            if (fine) tp += now_seconds() - p0;
             if (rc != BEM_OK) {
                 C.set_error(rc, std::string("request: ") + bem_last_error());
                 s.busy = false;
@@ -734,10 +737,13 @@ void worker(AssemblyCtx &C, int per_worker)
         const size_t nd = done.size();
         done.clear();
         fill();   // blocks that arrived meanwhile
-        const double f0 = now_seconds();
+        const double f0 = fine ? now_seconds() : 0.0;
         flush();
-        tf += now_seconds() - f0;
-        pr += (now_seconds() - tb) * (double)nd;
+        if (fine) {
+            const double f1 = now_seconds();
+            tf += f1 - f0;
+            pr += (f1 - tb) * (double)nd;
+        }
     }
     busy += now_seconds() - tb;
     release_run();
