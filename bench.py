@@ -248,9 +248,11 @@ def timed(bem, mesh, prec, steps, warmup, args):
     bem.server_kernel_stats(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    tot = {"entries": 0, "requests": 0, "rank_sum": 0, "rank_max": 0, "blocks": 0, "phases": {}}
+    tot = {"entries": 0, "requests": 0, "rank_sum": 0, "rank_max": 0, "blocks": 0, "phases": {}, "step_seconds": []}
     for _ in range(steps):
+        ts = time.perf_counter()
         s = assemble_step(bem, mesh, prec, args)
+        tot["step_seconds"].append(time.perf_counter() - ts)
         for k in ("entries", "requests", "rank_sum", "blocks"):
             tot[k] += s[k]
         for k, v in s["phases"].items():
@@ -1013,11 +1015,16 @@ def main():
 
     fp64 = None
     if not args.no_fp64:
-        dt64, tot64, sst64, kst64 = timed(bem, mesh, bem.FP64, 1, 0, args)
-        fp64 = {"value": tot64["entries"] / dt64, "unit": "entries/s", "seconds_per_step": dt64,
+        # the same protocol as the FP32 leg: warm-ups, then the timed steps
+        dt64, tot64, sst64, kst64 = timed(bem, mesh, bem.FP64, args.steps, args.warmup, args)
+        t64 = sorted(tot64["step_seconds"])
+        fp64 = {"value": tot64["entries"] / dt64, "unit": "entries/s", "seconds_per_step": dt64 / args.steps,
+                "step_seconds_median": t64[len(t64) // 2], "step_seconds_min": t64[0],
+                "aca_entries_per_step": tot64["entries"] // args.steps,
+                "aca_requests_per_step": tot64["requests"] // args.steps,
                 "latency_p50_ms": sst64["latency_p50"] * 1e3, "latency_p99_ms": sst64["latency_p99"] * 1e3,
-                "rank_sum": tot64["rank_sum"]}
-        print(f"[bench] fp64: 1 step in {dt64:.3f} s", file=sys.stderr, flush=True)
+                "rank_sum": tot64["rank_sum"] // args.steps}
+        print(f"[bench] fp64: {args.steps} steps in {dt64:.3f} s", file=sys.stderr, flush=True)
 
     cpu = None
     worst = None
@@ -1047,6 +1054,7 @@ def main():
             "admissible_blocks_per_step": tot["blocks"] // args.steps,
             "mean_rank": tot["rank_sum"] / max(1, tot["blocks"]),
             "max_rank": tot["rank_max"],
+            "rank_sum_per_step": tot["rank_sum"] // args.steps,
             "workers": args.workers,
             "blocks_per_worker": args.blocks_per_worker,
         },
@@ -1055,6 +1063,8 @@ def main():
         "fused_launch_batches": sst["batches"],
         "requests_per_batch": sst["requests"] / max(1, sst["batches"]),
         "assembly_seconds_per_step": tot["phases"],
+        "step_seconds_median": sorted(tot["step_seconds"])[len(tot["step_seconds"]) // 2],
+        "step_seconds_min": min(tot["step_seconds"]),
         "server_seconds_per_step": {"dispatch": sst["dispatch_seconds"] / args.steps,
                                     "dispatch_hip_calls": sst["dispatch_hip_seconds"] / args.steps,
                                     "complete": sst["complete_seconds"] / args.steps,

@@ -114,7 +114,14 @@ public:
     std::mutex mu;
     std::condition_variable cv;    // dispatchers: pending requests, free slots
     std::condition_variable cvc;   // completers: batches in flight
-    std::deque<Request *> pending;
+    // pending requests with their slot bytes, so taking a batch reads no
+    // request memory while the lock is held
+    struct Pending {
+        Request *r;
+        size_t bytes;
+    };
+    std::deque<Pending> pending;
+    uint64_t generation = 0;   // bumped by reconfigure (guarded by mu)
     std::deque<Batch *> inflight;
     bool slot_busy[kMaxSlots] = {};
     bool started = false, stop = false;
@@ -217,6 +224,7 @@ public:
     {
         const double t = now_seconds();
         std::vector<std::pair<std::pair<void *, void *>, std::vector<Request *>>> groups;
+        size_t last = 0;
         for (size_t i = 0; i < rs.size(); ++i) {
             Request *r = rs[i];
             if (!r->on_done) {
@@ -228,9 +236,14 @@ public:
             r->done = true;
             dec_inflight(r->mesh);
             const std::pair<void *, void *> key{(void *)r->on_done, r->cb_ctx};
-            size_t g = 0;
-            while (g < groups.size() && groups[g].first != key) ++g;
-            if (g == groups.size()) groups.push_back({key, {}});
+            // a submitter's requests sit together in the batch: try the last group first
+            size_t g = last;
+            if (g >= groups.size() || groups[g].first != key) {
+                g = 0;
+                while (g < groups.size() && groups[g].first != key) ++g;
+                if (g == groups.size()) groups.push_back({key, {}});
+                last = g;
+            }
             groups[g].second.push_back(r);
         }
         dec_inflight(nullptr);
@@ -264,6 +277,7 @@ public:
         // block records and descriptors are built here, on the submitting
         // thread, while its request data is in its own cache
         for (size_t i = 0; i < n; ++i) prebuild_staging(*rs[i]);
+        uint64_t gen = 0;
         {
             std::lock_guard<std::mutex> g(mu);
             if (stop) return fail(BEM_E_BUSY, "server is being reconfigured");
@@ -271,26 +285,46 @@ public:
                 int rc = start();
                 if (rc != BEM_OK) return rc;
             }
-            for (size_t i = 0; i < n; ++i)
-                if (!fits(rs[i])) return fail(BEM_E_OOM, "request larger than a server batch slot; raise the arena size");
-            const double t = now_seconds();
+            gen = generation;
+        }
+        // slot_bytes is fixed while the server runs (reconfiguration needs an
+        // idle server and bumps the generation, checked below)
+        for (size_t i = 0; i < n; ++i)
+            if (!fits(rs[i])) return fail(BEM_E_OOM, "request larger than a server batch slot; raise the arena size");
+        thread_local std::vector<Pending> items;
+        items.resize(n);
+        const double t = now_seconds();
+        for (size_t i = 0; i < n; ++i) {
+            Request *r = rs[i];
+            r->t_submit = t;
+            r->done = false;
+            r->result = nullptr;
+            r->batch = nullptr;
+            items[i] = Pending{r, r->batch_bytes};
+        }
+        // in-flight counts per run of requests on one mesh, before the
+        // requests become visible to the dispatcher
+        auto count = [&](int sign) {
             bem_mesh *cur = nullptr;
             int64_t cnt = 0;
             for (size_t i = 0; i < n; ++i) {
-                Request *r = rs[i];
-                r->t_submit = t;
-                r->done = false;
-                r->result = nullptr;
-                r->batch = nullptr;
-                if (r->mesh != cur) {
-                    if (cur) cur->inflight.fetch_add(cnt);
-                    cur = r->mesh;
+                if (rs[i]->mesh != cur) {
+                    if (cur) cur->inflight.fetch_add(sign * cnt);
+                    cur = rs[i]->mesh;
                     cnt = 0;
                 }
                 ++cnt;
-                pending.push_back(r);
             }
-            if (cur) cur->inflight.fetch_add(cnt);
+            if (cur) cur->inflight.fetch_add(sign * cnt);
+        };
+        count(1);
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (stop || generation != gen || !started) {
+                count(-1);
+                return fail(BEM_E_BUSY, "server is being reconfigured");
+            }
+            pending.insert(pending.end(), items.begin(), items.end());
         }
         cv.notify_one();
         return BEM_OK;
@@ -315,14 +349,15 @@ public:
                 std::unique_lock<std::mutex> lk(mu);
                 cv.wait(lk, [&] { return stop || (!pending.empty() && free_slot() >= 0); });
                 while (!stop && min_batch > 1 && (int)pending.size() < min_batch) {
-                    const double waited = now_seconds() - pending.front()->t_submit;
+                    const double waited = now_seconds() - pending.front().r->t_submit;
                     if (waited >= max_wait_s) break;
                     cv.wait_for(lk, std::chrono::duration<double>(max_wait_s - waited));
                     if (pending.empty() || free_slot() < 0)
                         cv.wait(lk, [&] { return stop || (!pending.empty() && free_slot() >= 0); });
                 }
                 if (stop) {
-                    std::vector<Request *> left(pending.begin(), pending.end());
+                    std::vector<Request *> left;
+                    for (const Pending &p : pending) left.push_back(p.r);
                     pending.clear();
                     lk.unlock();
                     finish_all(left, std::vector<int>(left.size(), BEM_E_CANCELLED));
@@ -331,11 +366,10 @@ public:
                 slot = free_slot();
                 size_t bytes = kSlack;
                 while (!pending.empty() && (int)take.size() < max_batch) {
-                    Request *r = pending.front();
-                    const size_t rb = r->batch_bytes;
-                    if (!take.empty() && bytes + rb > slot_bytes) break;
-                    take.push_back(r);
-                    bytes += rb;
+                    const Pending &p = pending.front();
+                    if (!take.empty() && bytes + p.bytes > slot_bytes) break;
+                    take.push_back(p.r);
+                    bytes += p.bytes;
                     pending.pop_front();
                 }
                 slot_busy[slot] = true;
@@ -765,6 +799,7 @@ public:
         std::lock_guard<std::mutex> g(mu);
         started = false;
         stop = false;
+        ++generation;
         arena_bytes = arena;
         max_batch = mb;
         return BEM_OK;
