@@ -127,9 +127,9 @@ def parse():
     ap.add_argument("--traffic-copy-bytes", type=int, default=256 << 20)
     a = ap.parse_args()
     if a.workers is None:
-        a.workers = 32 if a.workload == "cylinder" else 10
+        a.workers = 32 if a.workload in ("cylinder", "mix") else 10
     if a.blocks_per_worker is None:
-        a.blocks_per_worker = 128 if a.workload == "cylinder" else 180
+        a.blocks_per_worker = 128 if a.workload in ("cylinder", "mix") else 180
     return a
 
 
@@ -848,26 +848,43 @@ def mix_main(args):
     (2, 5, 10, 20 elements per wavelength), Helmholtz single layer, P0,
     4-point rule, complex64, ACA plans with leaf 16, eta 1, tol 1e-4; one step
     = every (mesh, k) instance serving a seeded segment of its admissible
-    blocks at the same time (one host thread each, one worker per instance:
-    32 workers sharing one device queue)."""
+    blocks at the same time, all into one device queue.  The 32 host ACA
+    workers are spread over the instances in proportion to their admissible
+    blocks (at least one each), so the large meshes are not served by a
+    single thread."""
     import threading
     import numpy as np
     from paper_1711_01897_amd import bem, inputs
     meshes = [("icosphere", 4), ("icosphere", 5), ("icosphere", 6), ("icosphere", 7),
               ("spheroid", 10000), ("spheroid", 40000), ("spheroid", 160000), ("spheroid", 400000)]
     inst = []
-    for kind, size in meshes:
-        xyz, tri = inputs.icosphere(size) if kind == "icosphere" else inputs.spheroid(10.0, 1.0, size)
+    geo = [inputs.icosphere(size) if kind == "icosphere" else inputs.spheroid(10.0, 1.0, size)
+           for kind, size in meshes]
+    # admissible blocks per mesh (the same partition for every wavenumber)
+    nadm = []
+    for xyz, tri in geo:
+        blocks = bem.partition(xyz, tri, bem.P0, 16, 1.0)[2]
+        nadm.append(int((blocks[:, 2] == 1).sum()))
+    total_workers = args.workers
+    share = [4 * n for n in nadm]   # four instances per mesh
+    workers = [max(1, int(total_workers * n / (4.0 * sum(share)))) for n in nadm]
+    while 4 * sum(workers) > total_workers and max(workers) > 1:
+        workers[workers.index(max(workers))] -= 1
+    while 4 * sum(workers) + 4 <= total_workers:
+        workers[max(range(len(workers)), key=lambda i: nadm[i] / workers[i])] += 1
+    for (kind, size), (xyz, tri), nw in zip(meshes, geo, workers):
         mesh = bem.mesh_create(xyz, tri, 4)
         for epw in (2.0, 5.0, 10.0, 20.0):
             k = inputs.wavenumber(xyz, tri, epw)
             plan = bem.aca_plan_create(mesh, bem.HELMHOLTZ_SLP, bem.P0, k, leaf_size=16, eta=1.0, aca_tol=1e-4,
-                                       max_rank=200, n_workers=1, blocks_per_worker=64, prec=bem.FP32)
+                                       max_rank=200, n_workers=nw, blocks_per_worker=args.blocks_per_worker,
+                                       prec=bem.FP32)
             nb = plan.info()["blocks"]
             order = inputs.rng(inputs.SEED_REQUESTS).permutation(nb)
             inst.append({"mesh": mesh, "plan": plan, "k": k, "name": f"{kind}{size}@{epw:g}",
                          "segs": np.array_split(order, max(1, (args.warmup + args.steps) * 8))})
-    print(f"[bench] mix: {len(inst)} instances", file=sys.stderr, flush=True)
+    print(f"[bench] mix: {len(inst)} instances, workers per instance of each mesh {workers}", file=sys.stderr,
+          flush=True)
 
     def step(i, prec):
         out = [None] * len(inst)
@@ -904,10 +921,7 @@ def mix_main(args):
         for it in inst:
             key = id(it["mesh"])
             if key not in cache:
-                m = it["mesh"]
-                # the oracle needs the geometry: rebuild it from the generator
-                kind, size = meshes[len(cache)]
-                xyz, tri = inputs.icosphere(size) if kind == "icosphere" else inputs.spheroid(10.0, 1.0, size)
+                xyz, tri = geo[len(cache)]
                 cache[key] = oracle.OracleMesh(xyz, tri, 4)
             om = cache[key]
             e = 0.0
@@ -926,7 +940,9 @@ def mix_main(args):
             "scaling": "strong", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
             "config": {"workload": "served Helmholtz single layer, P0, 4-point rule, 8 meshes (icospheres 5,120-"
                                    "327,680 triangles, 10:1:1 spheroids ~10k-400k) x 4 wavenumbers (2, 5, 10, 20 "
-                                   "elements per wavelength), ACA plans leaf 16, eta 1, tol 1e-4, one device queue"},
+                                   "elements per wavelength), ACA plans leaf 16, eta 1, tol 1e-4, one device queue, "
+                                   f"{args.workers} host ACA workers spread over the instances by their blocks "
+                                   f"({workers} per instance of each mesh) x {args.blocks_per_worker} blocks"},
             "latency_p50_ms": f32["latency_p50_ms"], "latency_p99_ms": f32["latency_p99_ms"],
             "fp64": f64, "fp32_over_fp64": f32["entries_per_s"] / f64["entries_per_s"],
             "max_rel_err_sampled_per_instance": worst}

@@ -105,6 +105,13 @@ public:
     int min_batch = 1;
     double max_wait_s = 0.0;
     bool log_launches = false;   // BEM_DEBUG_LAUNCHES: print each timed launch (grid, duration) to stderr
+    // BEM_SERVER_DIRECT (default 1): batches with no inputs of their own and
+    // no singular pairs (the rows and columns of resident lane sets) skip the
+    // staging copy; the entry kernels read descriptors and block records
+    // from the host-coherent staging itself (a few host-link reads per
+    // workgroup instead of a copy kernel and its launch gap per batch:
+    // about 4% more throughput on the 1M-triangle cylinder)
+    bool direct = true;
     bool time_phases = false;    // BEM_DEBUG_TIMING: per-phase host seconds of dispatch and completion
     // dispatch: group, layout, blocks, inputs+descriptors, enqueue; completion: wait, statistics, statuses,
     // callbacks, release
@@ -164,6 +171,7 @@ public:
         min_batch = env_int("BEM_SERVER_MIN_BATCH", 1, 1, 1 << 20);
         max_wait_s = 1e-6 * env_int("BEM_SERVER_MAX_WAIT_US", 0, 0, 1000000);
         log_launches = env_int("BEM_DEBUG_LAUNCHES", 0, 0, 1) != 0;
+        direct = env_int("BEM_SERVER_DIRECT", 1, 0, 1) != 0;
         time_phases = std::getenv("BEM_DEBUG_TIMING") != nullptr;
         hipError_t e = hipGetDevice(&device);
         int khz = 0;
@@ -496,6 +504,13 @@ public:
             }
         const size_t off_in = off;
         for (int i = 0; i < n; ++i) off += take[i]->in_bytes;
+        bool has_near = false;
+        for (const NearRun &g : near_runs) has_near = has_near || g.count > 0;
+        for (const P1Run &g : p1_runs) has_near = has_near || g.items > 0;
+        const bool direct_batch = direct && off == off_in && !has_near;
+        // descriptors and block tables: the device arena (after the staging
+        // copy) or, for a direct batch, the staging itself
+        char *src = direct_batch ? hd : db;
         const size_t h2d_end = align256(off);
         // every kTimedEvery-th batch times its launches: per workgroup a
         // {start, end} device-clock record, read back after the launches
@@ -578,8 +593,8 @@ public:
         auto note = [&](hipError_t e) {
             if (e != hipSuccess && b->enqueue_error == hipSuccess) b->enqueue_error = e;
         };
-        note(launch_stage_copy(hd, db, h2d_end, stream));
-        const ReqDev *dreq = reinterpret_cast<const ReqDev *>(db);
+        if (!direct_batch) note(launch_stage_copy(hd, db, h2d_end, stream));
+        const ReqDev *dreq = reinterpret_cast<const ReqDev *>(src);
         int64_t blk0 = 0;
         for (const Launch &L : b->launches) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -591,7 +606,7 @@ public:
                 b->ev.push_back(e1);
                 ck = reinterpret_cast<unsigned long long *>(hd + off_clock) + 2 * blk0;
             }
-            note(launch_entries(L.v, dreq, reinterpret_cast<const EntryBlock *>(db + L.off_tab), L.count, stream, ck,
+            note(launch_entries(L.v, dreq, reinterpret_cast<const EntryBlock *>(src + L.off_tab), L.count, stream, ck,
                                 e0, e1));
             blk0 += L.count;
         }
