@@ -156,10 +156,15 @@ def _counter_rows(d):
 
 
 def _mean_kib(rows, counter, pick):
-    vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == counter and pick(r["Kernel_Name"])]
-    if not vals:
+    """Mean counter value per dispatch of the picked kernel, the dispatch
+    count and the counter's sum over all workgroups of those dispatches
+    divided by their workgroups (per-workgroup mean)."""
+    sel = [r for r in rows if r["Counter_Name"] == counter and pick(r["Kernel_Name"])]
+    if not sel:
         raise SystemExit(f"no {counter} rows for the requested kernel")
-    return sum(vals) / len(vals), len(vals)
+    vals = [float(r["Counter_Value"]) for r in sel]
+    wgs = [max(1, int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"]))) for r in sel]
+    return sum(vals) / len(vals), len(vals), sum(vals) / sum(wgs)
 
 
 def traffic_from(args):
@@ -170,8 +175,8 @@ def traffic_from(args):
     frag = args.traffic_kernel
     is_dom = lambda name: frag in name
     is_copy = lambda name: "copyBuffer" in name
-    fetch, nf = _mean_kib(_counter_rows(fdir), "FETCH_SIZE", is_dom)
-    write, nw = _mean_kib(_counter_rows(wdir), "WRITE_SIZE", is_dom)
+    fetch, nf, fetch_wg = _mean_kib(_counter_rows(fdir), "FETCH_SIZE", is_dom)
+    write, nw, write_wg = _mean_kib(_counter_rows(wdir), "WRITE_SIZE", is_dom)
     # the copy reads and writes args.traffic_copy_bytes; take its largest dispatch
     cf = max(float(r["Counter_Value"]) for r in _counter_rows(cfdir)
              if r["Counter_Name"] == "FETCH_SIZE" and is_copy(r["Kernel_Name"]))
@@ -183,7 +188,10 @@ def traffic_from(args):
            "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
            "copy_bytes": args.traffic_copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
            "fetch_factor": f_fetch, "write_factor": f_write,
-           "bytes_per_launch": (fetch * f_fetch + write * f_write) * 1024.0}
+           "bytes_per_launch": (fetch * f_fetch + write * f_write) * 1024.0,
+           # per workgroup: launch sizes differ between the counter runs and
+           # the timed run, so the roofline scales this by its own launches
+           "bytes_per_workgroup": (fetch_wg * f_fetch + write_wg * f_write) * 1024.0}
     with open(traffic_file(args.workload), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
@@ -274,11 +282,16 @@ def roofline(kstats, workload="icosphere6"):
     mean_dc = dom["seconds"] / dom["launches"]           # first workgroup start to last workgroup end
     achieved = per_launch / mean_ev / 1e12
     traffic = None
+    wg_per_launch = dom["workgroups"] / dom["launches"]
     if os.path.exists(traffic_file(workload)):
         with open(traffic_file(workload)) as f:
             t = json.load(f)
-        if t.get("kernel_source_hash") == kernel_source_hash():
-            traffic = t.get("bytes_per_launch")
+        if t.get("kernel_source_hash") == kernel_source_hash() and "bytes_per_workgroup" in t:
+            traffic = t["bytes_per_workgroup"] * wg_per_launch
+    # algorithmic bytes per entry of the measurement plan (P1, 6-point rule):
+    # two trial triangles of 36 B of vertex coordinates, a 4-byte index and a
+    # 4-byte FP32 output
+    alg_bytes = 80.0 * dom["entries"] / dom["launches"]
     name = "%s_f%s<op=%d,Q=%d>" % (KERNEL_NAMES[dom["space"]], "32" if dom["prec"] == 1 else "64",
                                    dom["op"], dom["quad_points"])
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_PACKED / 1e12, 1),
@@ -291,7 +304,9 @@ def roofline(kstats, workload="icosphere6"):
             "executed_flops_per_eval": FLOPS_EXECUTED[(dom["op"], dom["space"])],
             "executed_tflops": round(dom["pair_evals"] * FLOPS_EXECUTED[(dom["op"], dom["space"])] /
                                      dom["launches"] / mean_ev / 1e12, 3),
-            "frac_of_unpacked_fp32_peak": round(achieved * 1e12 / PEAK_FP32_VALU, 4)}
+            "frac_of_unpacked_fp32_peak": round(achieved * 1e12 / PEAK_FP32_VALU, 4),
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "traffic_over_algorithmic": round(traffic / alg_bytes, 3) if traffic else None}
     return roof, dom
 
 

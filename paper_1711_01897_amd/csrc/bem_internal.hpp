@@ -345,6 +345,7 @@ struct Request {
 
     // placement inside a batch
     size_t off_out = 0, off_status = 0;
+    bool fast = false;          // written into its batch by the submitter (server fast path)
 
     int64_t entries() const { return nrows * ncols; }
 };
@@ -380,6 +381,8 @@ void describe_request(const Request &r, ReqDev &d);
 // at their device copies (no-op for a device-resident lane side); returns
 // the bytes used (r.in_bytes).
 size_t stage_own_inputs(const Request &r, char *host_base, char *dev_base, size_t off, ReqDev &d);
+// Launch group of a request: (kernel operator, kernel space, precision, rule).
+int request_key(const Request &r);
 // Fills r.key, r.pre_blocks and r.pre_dev (called by the submitting thread).
 void prebuild_staging(Request &r);
 // off_status addresses the request's int32 status word (zeroed by the caller).
@@ -392,6 +395,11 @@ int server_submit_many(Request *const *rs, size_t n);
 // dispatch and completion threads (stderr).
 void server_print_phases();
 int server_wait(Request *r, double timeout_s);
+// Status of a finished request handed to a completion callback (requests
+// submitted through the server's fast path carry it in the batch).
+int server_request_status(const Request *r);
+// Completion time of such a request (library clock).
+double server_request_done_time(const Request *r);
 void server_release(Request *r);           // return a borrowed result
 void server_release_batch(void *batch, int n);   // return n borrowed results of one batch (Request::batch)
 int server_ensure_started();

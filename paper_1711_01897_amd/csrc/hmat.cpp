@@ -658,9 +658,23 @@ void worker(AssemblyCtx &C, int per_worker)
         busy += now_seconds() - tb;
         dq.pop_some(done, (size_t)pop_most);
         tb = now_seconds();
-        for (Request *r : done) qd += tb - r->t_done;
+        if (fine)
+            for (Request *r : done) qd += tb - server_request_done_time(r);
         np += (int64_t)done.size();
-        for (Request *r : done) {
+        for (size_t di = 0; di < done.size(); ++di) {
+            Request *r = done[di];
+            if (di + 2 < done.size()) {
+                // the entries of a request two ahead were written by the device
+                // and are not in this core's cache: start their loads now
+                const Request *nx = done[di + 2];
+                if (const char *res = static_cast<const char *>(nx->result)) {
+                    __builtin_prefetch(res);
+                    __builtin_prefetch(res + 64);
+                    __builtin_prefetch(res + 128);
+                    __builtin_prefetch(res + 192);
+                }
+                __builtin_prefetch(&slots[nx->tag]);
+            }
             if ((int)submit.size() >= flush_every) {
                 const double f0 = fine ? now_seconds() : 0.0;
                 flush();
@@ -668,9 +682,10 @@ void worker(AssemblyCtx &C, int per_worker)
             }
             Slot<T> &s = slots[r->tag];
             bool finished = false;
-            if (r->status != BEM_OK) {
-                C.set_error(r->status, r->status == BEM_E_NEARFIELD ? "admissible block met a vertex-sharing pair"
-                                                                    : "device request failed");
+            const int rst = server_request_status(r);
+            if (rst != BEM_OK) {
+                C.set_error(rst, rst == BEM_E_NEARFIELD ? "admissible block met a vertex-sharing pair"
+                                                        : "device request failed");
                 finished = true;
             } else {
                 bem_hmat::Leaf &L = C.h->leaves[s.leaf];

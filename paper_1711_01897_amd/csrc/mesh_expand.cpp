@@ -840,9 +840,14 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
     return n;
 }
 
+int request_key(const Request &r)
+{
+    return ((kernel_op(r.op) * 2 + kernel_space(r.space)) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0);
+}
+
 void prebuild_staging(Request &r)
 {
-    r.key = ((kernel_op(r.op) * 2 + kernel_space(r.space)) * 2 + r.prec) * 2 + (r.mesh->q == 6 ? 1 : 0);
+    r.key = request_key(r);
     r.pre_blocks.resize((size_t)r.nblocks);
     write_blocks(r, 0, r.pre_blocks.data());
     describe_request(r, r.pre_dev);

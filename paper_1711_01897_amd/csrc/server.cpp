@@ -69,9 +69,25 @@ struct KStat {
     double seconds = 0.0, seconds_events = 0.0;
 };
 
+// A submitter's requests inside a batch filled through the fast path: they
+// complete with one callback.
+struct FastGroup {
+    int first = 0, n = 0;              // positions in Batch::reqs
+    void (*cb)(Request **, size_t, void *) = nullptr;
+    void *ctx = nullptr;
+    bem_mesh *mesh = nullptr;
+    double t_submit = 0.0;
+};
+
 struct Batch {
     int slot = 0;
     std::vector<Request *> reqs;
+    // fast path (submitters write their records into the slot themselves)
+    bool fast = false;
+    std::vector<FastGroup> groups;
+    char *hb = nullptr;                // the slot's host staging
+    hipError_t error = hipSuccess;     // set before the callbacks run
+    double t_done = 0.0;
     std::vector<Launch> launches;
     std::vector<hipEvent_t> ev;   // start/stop per launch (timed batches)
     hipEvent_t ev_done = nullptr;
@@ -129,6 +145,35 @@ public:
     };
     std::deque<Pending> pending;
     uint64_t generation = 0;   // bumped by reconfigure (guarded by mu)
+
+    // Fast path.  Requests whose lane side is resident on the device, with a
+    // completion callback, borrowed results and no singular pairs (the rows
+    // and columns ACA workers ask for) skip the pending queue: a submitting
+    // thread reserves room in the open batch (request positions, block
+    // records, output bytes; under mu, O(1) per request), then writes its
+    // descriptors, block records and status words straight into the slot's
+    // host-coherent staging without the lock.  The dispatcher closes the
+    // open batch, waits until every reservation is written and launches it;
+    // the kernels read the records from the staging.  No other thread
+    // touches these requests until their submitter's callback.
+    struct Open {
+        Batch *b = nullptr;
+        int key = -1;
+        int nreq = 0, writers = 0;
+        int64_t nblk = 0;
+        size_t out = 0;                 // output bytes reserved (from off_out0)
+        int64_t entries = 0, evals = 0, loads = 0;
+        double t_first = 0.0;
+    };
+    Open *open = nullptr;              // guarded by mu
+    std::condition_variable wcv;       // dispatcher: reservations of a closed batch written
+    bool fast_enabled = true;          // BEM_SERVER_FAST (default 1)
+    int fast_min = 256;                // BEM_SERVER_FAST_MIN: close at this many requests ...
+    double fast_wait_s = 30e-6;        // BEM_SERVER_FAST_WAIT_US: ... or when the first has waited this long
+    // slot layout of a fast batch: descriptors | status words | block records | clock records | outputs
+    int fmaxreq = 0;
+    int64_t fmaxblk = 0;
+    size_t f_status = 0, f_blk = 0, f_clock = 0, f_out0 = 0;
     std::deque<Batch *> inflight;
     bool slot_busy[kMaxSlots] = {};
     bool started = false, stop = false;
@@ -191,6 +236,16 @@ public:
                         std::string("server start: ") + hipGetErrorString(e));
         }
         slot_bytes = (arena_bytes / nslots) & ~(size_t)255;
+        fast_enabled = env_int("BEM_SERVER_FAST", 1, 0, 1) != 0;
+        fast_min = env_int("BEM_SERVER_FAST_MIN", 256, 1, 1 << 20);
+        fast_wait_s = 1e-6 * env_int("BEM_SERVER_FAST_WAIT_US", 30, 0, 1000000);
+        fmaxreq = (int)std::min<size_t>({(size_t)8192, (size_t)max_batch, std::max<size_t>(16, slot_bytes / 4096)});
+        fmaxblk = 4 * (int64_t)fmaxreq;
+        f_status = align256(sizeof(ReqDev) * (size_t)fmaxreq);
+        f_blk = align256(f_status + sizeof(int32_t) * (size_t)fmaxreq);
+        f_clock = align256(f_blk + sizeof(EntryBlock) * (size_t)fmaxblk);
+        f_out0 = align256(f_clock + 16 * (size_t)fmaxblk);
+        if (f_out0 + (size_t(1) << 16) > slot_bytes) fast_enabled = false;
         started = true;
         for (int i = 0; i < ndisp; ++i) threads.emplace_back([this] { dispatch_loop(); });
         for (int i = 0; i < ncomp; ++i) threads.emplace_back([this] { complete_loop(); });
@@ -284,7 +339,6 @@ public:
     {
         // block records and descriptors are built here, on the submitting
         // thread, while its request data is in its own cache
-        for (size_t i = 0; i < n; ++i) prebuild_staging(*rs[i]);
         uint64_t gen = 0;
         {
             std::lock_guard<std::mutex> g(mu);
@@ -297,6 +351,11 @@ public:
         }
         // slot_bytes is fixed while the server runs (reconfiguration needs an
         // idle server and bumps the generation, checked below)
+        if (fast_enabled && n > 0 && fast_eligible(rs, n) && submit_fast(rs, n, gen)) return BEM_OK;
+        for (size_t i = 0; i < n; ++i) {
+            rs[i]->fast = false;
+            prebuild_staging(*rs[i]);
+        }
         for (size_t i = 0; i < n; ++i)
             if (!fits(rs[i])) return fail(BEM_E_OOM, "request larger than a server batch slot; raise the arena size");
         thread_local std::vector<Pending> items;
@@ -338,6 +397,164 @@ public:
         return BEM_OK;
     }
 
+    // Requests that can go through the fast path together: one submitter
+    // (callback, context), one mesh and one launch group, borrowed results,
+    // a device-resident lane side, no singular pairs, no inputs to stage.
+    bool fast_eligible(Request *const *rs, size_t n) const
+    {
+        const Request &a = *rs[0];
+        if (!a.on_done || !a.mesh) return false;
+        const int key = request_key(a);
+        for (size_t i = 0; i < n; ++i) {
+            const Request &r = *rs[i];
+            if (r.on_done != a.on_done || r.cb_ctx != a.cb_ctx || r.mesh != a.mesh || !r.borrow || !r.ext ||
+                !r.near_items.empty() || r.in_bytes != 0 || r.nblocks <= 0 || r.nblocks > fmaxblk ||
+                request_key(r) != key)
+                return false;
+        }
+        return true;
+    }
+
+    // Reserves room for rs[0..n) in the open batch and writes their records
+    // into its staging; false when there is no open batch, it holds another
+    // launch group, or it has no room (the caller queues them instead).
+    bool submit_fast(Request *const *rs, size_t n, uint64_t gen)
+    {
+        const int key = request_key(*rs[0]);
+        int64_t blk = 0, ent = 0, ev = 0, ld = 0;
+        size_t outb = 0;
+        for (size_t i = 0; i < n; ++i) {
+            const Request &r = *rs[i];
+            blk += r.nblocks;
+            outb += r.out_bytes;
+            ent += r.entries();
+            ev += r.evals;
+            ld += r.nfix * r.nlane;
+        }
+        Open *o = nullptr;
+        Batch *b = nullptr;
+        int i0 = 0;
+        int64_t b0 = 0;
+        size_t o0 = 0;
+        const double t = now_seconds();
+        bool wake = false;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (stop || generation != gen || !started || !open) return false;
+            o = open;
+            if (o->nreq > 0 && o->key != key) return false;
+            if (o->nreq + (int64_t)n > fmaxreq || o->nblk + blk > fmaxblk || f_out0 + o->out + outb > slot_bytes)
+                return false;
+            if (o->nreq == 0) {
+                o->key = key;
+                o->t_first = t;
+            }
+            i0 = o->nreq;
+            b0 = o->nblk;
+            o0 = o->out;
+            o->nreq += (int)n;
+            o->nblk += blk;
+            o->out += outb;
+            o->entries += ent;
+            o->evals += ev;
+            o->loads += ld;
+            o->writers += 1;
+            b = o->b;
+            FastGroup fg;
+            fg.first = i0;
+            fg.n = (int)n;
+            fg.cb = rs[0]->on_done;
+            fg.ctx = rs[0]->cb_ctx;
+            fg.mesh = rs[0]->mesh;
+            fg.t_submit = t;
+            b->groups.push_back(fg);
+            b->reqs.insert(b->reqs.end(), rs, rs + n);
+            wake = i0 == 0 || o->nreq >= fast_min;
+        }
+        // the records, without the lock (the dispatcher launches the batch
+        // only after every reservation is written)
+        char *hd = h_stage_dev + (size_t)b->slot * slot_bytes;
+        ReqDev *desc = reinterpret_cast<ReqDev *>(b->hb);
+        int32_t *stw = reinterpret_cast<int32_t *>(b->hb + f_status);
+        EntryBlock *blocks = reinterpret_cast<EntryBlock *>(b->hb + f_blk);
+        size_t oo = f_out0 + o0;
+        int64_t bb = b0;
+        for (size_t k = 0; k < n; ++k) {
+            Request *r = rs[k];
+            const int i = i0 + (int)k;
+            ReqDev d;
+            describe_request(*r, d);
+            finish_descriptor(*r, hd, oo, f_status + sizeof(int32_t) * (size_t)i, d);
+            desc[i] = d;
+            stw[i] = 0;
+            bb += write_blocks(*r, i, blocks + bb);
+            r->t_submit = t;
+            r->done = false;
+            r->fast = true;
+            r->batch = b;
+            r->result = b->hb + oo;
+            r->off_out = oo;
+            r->off_status = f_status + sizeof(int32_t) * (size_t)i;
+            oo += r->out_bytes;
+        }
+        rs[0]->mesh->inflight.fetch_add((int64_t)n);
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (--o->writers == 0) wcv.notify_all();
+        }
+        if (wake) cv.notify_one();
+        return true;
+    }
+
+    Batch *new_fast_batch(int slot)
+    {
+        Batch *b = new Batch();
+        b->slot = slot;
+        b->fast = true;
+        b->hb = h_stage + (size_t)slot * slot_bytes;
+        b->reqs.reserve((size_t)fmaxreq);
+        return b;
+    }
+
+    // Launches a closed open batch (every reservation written).
+    void launch_fast(Open *o)
+    {
+        Batch *b = o->b;
+        hipStream_t stream = streams[b->slot % nstreams];
+        char *hd = h_stage_dev + (size_t)b->slot * slot_bytes;
+        Launch L;
+        L.key = o->key;
+        L.v = Variant{o->key >> 3, (o->key >> 2) & 1, (o->key >> 1) & 1, (o->key & 1) ? 6 : 4};
+        L.off_tab = f_blk;
+        L.count = o->nblk;
+        L.entries = o->entries;
+        L.evals = o->evals;
+        L.loads = o->loads;
+        b->entries = o->entries;
+        b->evals = o->evals;
+        b->timed = (batch_counter.fetch_add(1) % kTimedEvery) == 0;
+        b->off_clock = f_clock;
+        b->launches.push_back(L);
+        b->t_launch = now_seconds();
+        b->t_hip = b->t_launch;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        unsigned long long *ck = nullptr;
+        if (b->timed) {
+            e0 = get_event();
+            e1 = get_event();
+            b->ev.push_back(e0);
+            b->ev.push_back(e1);
+            ck = reinterpret_cast<unsigned long long *>(hd + f_clock);
+        }
+        hipError_t e = launch_entries(L.v, reinterpret_cast<const ReqDev *>(hd),
+                                      reinterpret_cast<const EntryBlock *>(hd + f_blk), L.count, stream, ck, e0, e1);
+        if (e != hipSuccess) b->enqueue_error = e;
+        b->ev_done = get_event();
+        e = hipEventRecord(b->ev_done, stream);
+        if (e != hipSuccess && b->enqueue_error == hipSuccess) b->enqueue_error = e;
+        b->t_hip = now_seconds() - b->t_hip;
+    }
+
     int free_slot() const
     {
         for (int s = 0; s < nslots; ++s)
@@ -353,9 +570,68 @@ public:
             std::vector<Request *> take;
             int slot = -1;
             bool more = false;
+            Open *fo = nullptr;   // a fast batch to close and launch
             {
                 std::unique_lock<std::mutex> lk(mu);
-                cv.wait(lk, [&] { return stop || (!pending.empty() && free_slot() >= 0); });
+                for (;;) {
+                    if (stop) break;
+                    if (open && open->nreq > 0) {
+                        const double waited = now_seconds() - open->t_first;
+                        if (open->nreq >= fast_min || waited >= fast_wait_s) {
+                            fo = open;
+                            open = nullptr;
+                            break;
+                        }
+                        if (!pending.empty() && free_slot() >= 0) break;
+                        cv.wait_for(lk, std::chrono::duration<double>(fast_wait_s - waited));
+                        continue;
+                    }
+                    // queued requests take a free slot before a new open batch does
+                    if (!pending.empty() && free_slot() >= 0) break;
+                    if (fast_enabled && !open) {
+                        // keep one batch open for fast submissions
+                        const int fs = free_slot();
+                        if (fs >= 0) {
+                            open = new Open();
+                            open->b = new_fast_batch(fs);
+                            slot_busy[fs] = true;
+                            continue;
+                        }
+                    }
+                    cv.wait(lk);
+                }
+                if (fo && !stop) {
+                    // the next open batch, if a slot is free and nothing is queued
+                    const int fs = free_slot();
+                    if (fs >= 0 && pending.empty()) {
+                        open = new Open();
+                        open->b = new_fast_batch(fs);
+                        slot_busy[fs] = true;
+                    }
+                    const double t0 = now_seconds();
+                    wcv.wait(lk, [&] { return fo->writers == 0; });
+                    lk.unlock();
+                    launch_fast(fo);
+                    Batch *b = fo->b;
+                    const double t1 = now_seconds();
+                    double qs = 0.0;
+                    for (const FastGroup &g : b->groups) qs += g.n * (t0 - g.t_submit);
+                    b->t_take = t0;
+                    b->t_enq = t1;
+                    b->q_sum = qs;
+                    delete fo;
+                    {
+                        std::lock_guard<std::mutex> g(stat_mu);
+                        dispatch_s += t1 - t0;
+                        dispatch_hip_s += b->t_hip;
+                    }
+                    {
+                        std::lock_guard<std::mutex> g(mu);
+                        inflight.push_back(b);
+                    }
+                    cvc.notify_one();
+                    continue;
+                }
                 while (!stop && min_batch > 1 && (int)pending.size() < min_batch) {
                     const double waited = now_seconds() - pending.front().r->t_submit;
                     if (waited >= max_wait_s) break;
@@ -718,8 +994,14 @@ public:
                 }
                 busy += std::max(0.0, t_done - std::max(b->t_launch, last_done));
                 last_done = std::max(last_done, t_done);
-                for (Request *r : b->reqs)
-                    if (latencies.size() < (size_t(1) << 24)) latencies.push_back((float)(t_done - r->t_submit));
+                if (b->fast) {
+                    for (const FastGroup &g : b->groups)
+                        for (int i = 0; i < g.n && latencies.size() < (size_t(1) << 24); ++i)
+                            latencies.push_back((float)(t_done - g.t_submit));
+                } else {
+                    for (Request *r : b->reqs)
+                        if (latencies.size() < (size_t(1) << 24)) latencies.push_back((float)(t_done - r->t_submit));
+                }
                 for (size_t i = 0; b->timed && i < b->launches.size(); ++i) {
                     const Launch &L = b->launches[i];
                     KStat &k = kstats[L.v];
@@ -733,6 +1015,36 @@ public:
                 }
             }
             if (time_phases) tc[2] = now_seconds();
+            if (b->fast) {
+                // statuses stay in the staging (server_request_status); one
+                // callback per submitter group, no request is touched here
+                b->error = e;
+                b->t_done = t_done;
+                const double nreq = (double)b->reqs.size();
+                b->refs.fetch_add((int)b->reqs.size());   // each request holds its result until released
+                if (time_phases) tc[3] = now_seconds();
+                for (const FastGroup &g : b->groups) {
+                    g.mesh->inflight.fetch_sub(g.n);
+                    g.cb(b->reqs.data() + g.first, (size_t)g.n, g.ctx);
+                }
+                if (time_phases) tc[4] = now_seconds();
+                const double leg_q = b->q_sum, leg_s = nreq * (b->t_enq - b->t_take), leg_d = nreq * (t_done - b->t_enq);
+                release_batch(b);   // b may be gone from here on
+                const double t_fin = now_seconds();
+                std::lock_guard<std::mutex> g(stat_mu);
+                if (time_phases) {
+                    tc[5] = t_fin;
+                    for (int i = 0; i < 5; ++i) ph_comp[i] += tc[i + 1] - tc[i];
+                    ph_nc += 1;
+                }
+                wait_s += t_done - tw0;
+                complete_s += t_fin - t_done;
+                leg_queue += leg_q;
+                leg_stage += leg_s;
+                leg_device += leg_d;
+                leg_complete += nreq * (t_fin - t_done);
+                continue;
+            }
             char *hb = h_stage + (size_t)b->slot * slot_bytes;
             std::vector<Request *> reqs;
             reqs.swap(b->reqs);
@@ -793,8 +1105,8 @@ public:
             std::lock_guard<std::mutex> g(mu);
             running = started;
             if (running) {
-                bool busy = !pending.empty() || !inflight.empty();
-                for (int i = 0; i < nslots; ++i) busy = busy || slot_busy[i];
+                bool busy = !pending.empty() || !inflight.empty() || (open && (open->nreq > 0 || open->writers > 0));
+                for (int i = 0; i < nslots; ++i) busy = busy || (slot_busy[i] && !(open && open->b->slot == i));
                 if (busy) return fail(BEM_E_BUSY, "server has requests in flight or results still lent");
                 stop = true;
             }
@@ -807,6 +1119,12 @@ public:
             for (int i = 0; i < nstreams; ++i)
                 if (streams[i]) (void)hipStreamDestroy(streams[i]);
             for (int i = 0; i < kMaxSlots; ++i) streams[i] = nullptr;
+            if (open) {   // empty (checked above)
+                delete open->b;
+                delete open;
+                open = nullptr;
+            }
+            for (int i = 0; i < kMaxSlots; ++i) slot_busy[i] = false;
             (void)hipFree(d_arena);
             (void)hipHostFree(h_stage);
             d_arena = h_stage = h_stage_dev = nullptr;
@@ -933,6 +1251,19 @@ int server_wait(Request *r, double timeout_s)
         return BEM_E_TIMEOUT;
     }
     return r->status;
+}
+
+int server_request_status(const Request *r)
+{
+    if (!r->fast) return r->status;
+    const Batch *b = static_cast<const Batch *>(r->batch);
+    if (b->error != hipSuccess) return BEM_E_DEVICE;
+    return *reinterpret_cast<const volatile int32_t *>(b->hb + r->off_status) != 0 ? BEM_E_NEARFIELD : BEM_OK;
+}
+
+double server_request_done_time(const Request *r)
+{
+    return r->fast ? static_cast<const Batch *>(r->batch)->t_done : r->t_done;
 }
 
 void server_release(Request *r)
