@@ -568,16 +568,22 @@ def host_cores():
     """Cores this process may use (affinity), the machine's logical CPUs and
     the CPU model (from /proc/cpuinfo, as lscpu reports it)."""
     usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    model = None
+    model = cores_per_socket = siblings = None
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
+                key = line.split(":", 1)[0].strip()
+                val = line.split(":", 1)[1].strip() if ":" in line else ""
+                if key == "model name" and model is None:
+                    model = val
+                elif key == "cpu cores" and cores_per_socket is None:
+                    cores_per_socket = int(val)
+                elif key == "siblings" and siblings is None:
+                    siblings = int(val)
+    except (OSError, ValueError):
         pass
-    return {"usable": usable, "logical": os.cpu_count(), "model": model}
+    smt = (siblings // cores_per_socket) if (siblings and cores_per_socket) else None
+    return {"usable": usable, "logical": os.cpu_count(), "model": model, "threads_per_core": smt}
 
 
 CYL = {"leaf": 16, "eta": 1.0, "tol": 1e-5, "max_block": 4096, "max_rank": 200}
@@ -790,7 +796,8 @@ def cylinder_main(args):
                                     for k in ("queue", "stage", "device", "complete")},
         "kernel_busy_fraction": sst["kernel_seconds"] / f32["wall"] if f32["wall"] > 0 else None,
         "fp64": fp64, "fp32_over_fp64": (f32["value"] / fp64["value"]) if fp64 else None,
-        "max_rel_err_sampled": worst, "gpu_telemetry": f32["telemetry"], "host_cpu": f32["host_cpu"],
+        "max_rel_err_sampled": worst, "gpu_telemetry": f32["telemetry"],
+        "host_cpu": dict(f32["host_cpu"], **host_cores()),
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -35,6 +35,8 @@
 #include <map>
 #include <thread>
 
+#include <immintrin.h>
+
 #include "bem_internal.hpp"
 
 namespace bem {
@@ -54,6 +56,17 @@ int env_int(const char *name, int dflt, int lo, int hi)
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Streaming (non-temporal) copy of `bytes` (a multiple of 16) to 16-byte
+// aligned staging: the records go to memory without first reading their
+// cache lines into this core's cache.  Ordered before later stores by an
+// sfence (issued once per submission group).
+void stream_copy(void *dst, const void *src, size_t bytes)
+{
+    __m128i *d = static_cast<__m128i *>(dst);
+    const __m128i *p = static_cast<const __m128i *>(src);
+    for (size_t i = 0; i < bytes / 16; ++i) _mm_stream_si128(d + i, _mm_loadu_si128(p + i));
+}
 
 
 struct Launch {
@@ -479,15 +492,20 @@ public:
         EntryBlock *blocks = reinterpret_cast<EntryBlock *>(b->hb + f_blk);
         size_t oo = f_out0 + o0;
         int64_t bb = b0;
+        static_assert(sizeof(ReqDev) % 16 == 0 && sizeof(EntryBlock) % 16 == 0, "records are 16-byte multiples");
+        thread_local std::vector<EntryBlock> tb;
         for (size_t k = 0; k < n; ++k) {
             Request *r = rs[k];
             const int i = i0 + (int)k;
             ReqDev d;
             describe_request(*r, d);
             finish_descriptor(*r, hd, oo, f_status + sizeof(int32_t) * (size_t)i, d);
-            desc[i] = d;
-            stw[i] = 0;
-            bb += write_blocks(*r, i, blocks + bb);
+            stream_copy(desc + i, &d, sizeof(ReqDev));
+            _mm_stream_si32(reinterpret_cast<int *>(stw + i), 0);
+            tb.resize((size_t)r->nblocks);
+            const int64_t nb = write_blocks(*r, i, tb.data());
+            stream_copy(blocks + bb, tb.data(), sizeof(EntryBlock) * (size_t)nb);
+            bb += nb;
             r->t_submit = t;
             r->done = false;
             r->fast = true;
@@ -498,6 +516,7 @@ public:
             oo += r->out_bytes;
         }
         rs[0]->mesh->inflight.fetch_add((int64_t)n);
+        _mm_sfence();   // the streamed records are in memory before the batch can be launched
         {
             std::lock_guard<std::mutex> g(mu);
             if (--o->writers == 0) wcv.notify_all();
