@@ -94,6 +94,8 @@ def parse():
                          "measured on the warm-up segments")
     ap.add_argument("--sweep", default="0.5,0.8,0.95",
                     help="cylinder: offered loads of the extra latency-against-load segments ('' for none)")
+    ap.add_argument("--mix-fraction", type=float, default=0.125,
+                    help="mix: the seeded share of every instance's admissible blocks served (1.0: all 16.8M)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-star", action="store_true", help="--dense: skip the star-kernel comparison")
@@ -110,7 +112,7 @@ def parse():
                     help="operator of --complete (Helmholtz at 10 elements per wavelength; the hypersingular "
                          "operators with --complete-space p1)")
     ap.add_argument("--complete-space", default="p0", choices=["p0", "p1"],
-                    help="space of --complete (P1: Laplace operators)")
+                    help="space of --complete (P0 or P1; the hypersingular operators need P1)")
     ap.add_argument("--concurrent", type=int, default=0,
                     help="1: assemble the step's operators at the same time (one host thread each, the workers "
                          "split between them), as concurrent clients of the request server")
@@ -868,72 +870,70 @@ def mix_main(args):
     """Served mixed Helmholtz workload: 8 meshes (icospheres with 5,120 to
     327,680 triangles, 10:1:1 spheroids with ~10k to ~400k) x 4 wavenumbers
     (2, 5, 10, 20 elements per wavelength), Helmholtz single layer, P0,
-    4-point rule, complex64, ACA plans with leaf 16, eta 1, tol 1e-4; one step
-    = every (mesh, k) instance serving a seeded segment of its admissible
-    blocks at the same time, all into one device queue.  The 32 host ACA
-    workers are spread over the instances in proportion to their admissible
-    blocks (at least one each), so the large meshes are not served by a
-    single thread."""
-    import threading
+    4-point rule, complex64, ACA plans with leaf 16, eta 1, tol 1e-4.  All 32
+    (mesh, k) instances are served together (bem_aca_plans_run): one pool of
+    32 host ACA workers takes blocks from every instance through the one
+    device queue.  A seeded share (--mix-fraction, seed 2) of the admissible
+    blocks of all instances, in that seeded order, is cut into warm-up +
+    timed segments; the warm-up segments run closed-loop and give the capacity, each
+    timed segment is a Poisson stream of block arrivals (seed 1) at
+    args.load x capacity.  The same with complex128 entries is the FP64 leg."""
     import numpy as np
     from paper_1711_01897_amd import bem, inputs
     meshes = [("icosphere", 4), ("icosphere", 5), ("icosphere", 6), ("icosphere", 7),
               ("spheroid", 10000), ("spheroid", 40000), ("spheroid", 160000), ("spheroid", 400000)]
-    inst = []
     geo = [inputs.icosphere(size) if kind == "icosphere" else inputs.spheroid(10.0, 1.0, size)
            for kind, size in meshes]
-    # admissible blocks per mesh (the same partition for every wavenumber)
-    nadm = []
-    for xyz, tri in geo:
-        blocks = bem.partition(xyz, tri, bem.P0, 16, 1.0)[2]
-        nadm.append(int((blocks[:, 2] == 1).sum()))
-    total_workers = args.workers
-    share = [4 * n for n in nadm]   # four instances per mesh
-    workers = [max(1, int(total_workers * n / (4.0 * sum(share)))) for n in nadm]
-    while 4 * sum(workers) > total_workers and max(workers) > 1:
-        workers[workers.index(max(workers))] -= 1
-    while 4 * sum(workers) + 4 <= total_workers:
-        workers[max(range(len(workers)), key=lambda i: nadm[i] / workers[i])] += 1
-    for (kind, size), (xyz, tri), nw in zip(meshes, geo, workers):
+    inst = []
+    for (kind, size), (xyz, tri) in zip(meshes, geo):
         mesh = bem.mesh_create(xyz, tri, 4)
         for epw in (2.0, 5.0, 10.0, 20.0):
             k = inputs.wavenumber(xyz, tri, epw)
             plan = bem.aca_plan_create(mesh, bem.HELMHOLTZ_SLP, bem.P0, k, leaf_size=16, eta=1.0, aca_tol=1e-4,
-                                       max_rank=200, n_workers=nw, blocks_per_worker=args.blocks_per_worker,
-                                       prec=bem.FP32)
-            nb = plan.info()["blocks"]
-            order = inputs.rng(inputs.SEED_REQUESTS).permutation(nb)
+                                       max_rank=200, n_workers=1, blocks_per_worker=1, prec=bem.FP32)
             inst.append({"mesh": mesh, "plan": plan, "k": k, "name": f"{kind}{size}@{epw:g}",
-                         "segs": np.array_split(order, max(1, (args.warmup + args.steps) * 8))})
-    print(f"[bench] mix: {len(inst)} instances, workers per instance of each mesh {workers}", file=sys.stderr,
+                         "blocks": plan.info()["blocks"]})
+    plans = [it["plan"] for it in inst]
+    pidx = np.concatenate([np.full(it["blocks"], p, dtype=np.int64) for p, it in enumerate(inst)])
+    bidx = np.concatenate([np.arange(it["blocks"], dtype=np.int64) for it in inst])
+    order = inputs.rng(inputs.SEED_REQUESTS).permutation(pidx.size)
+    order = order[:max(1, int(round(args.mix_fraction * order.size)))]
+    segs = np.array_split(order, args.warmup + args.steps)
+    print(f"[bench] mix: {len(inst)} instances, {pidx.size} admissible blocks, serving {order.size}", file=sys.stderr,
           flush=True)
 
-    def step(i, prec):
-        out = [None] * len(inst)
-
-        def one(j):
-            out[j] = inst[j]["plan"].run(inst[j]["segs"][i % len(inst[j]["segs"])], None, prec)
-        th = [threading.Thread(target=one, args=(j,)) for j in range(len(inst))]
-        for t in th:
-            t.start()
-        for t in th:
-            t.join()
-        return sum(o["entries"] for o in out)
+    def run(seg, arr, prec):
+        return bem.aca_plans_run(plans, pidx[seg], bidx[seg], arr, prec, n_workers=args.workers,
+                                 blocks_per_worker=args.blocks_per_worker)
 
     res = {}
     for prec in (bem.FP32, bem.FP64):
+        warm = []
         for i in range(args.warmup):
-            step(i, prec)
-        bem.server_stats(reset=True)
-        times, ents = [], 0
-        for i in range(args.steps):
             t0 = time.perf_counter()
-            ents += step(args.warmup + i, prec)
+            st = run(segs[i], None, prec)
+            warm.append((st["blocks"], time.perf_counter() - t0))
+        use = warm[1:] if len(warm) > 1 else warm
+        cap = sum(w[0] for w in use) / sum(w[1] for w in use) if use else None
+        rng = inputs.rng(inputs.SEED_ARRIVALS)
+        bem.server_stats(reset=True)
+        times, ents, reqs = [], 0, 0
+        for i in range(args.steps):
+            seg = segs[args.warmup + i]
+            arr = poisson_arrivals(rng, seg.size, args.load * cap) if cap else None
+            t0 = time.perf_counter()
+            st = run(seg, arr, prec)
             times.append(time.perf_counter() - t0)
+            ents += st["entries"]
+            reqs += st["requests"]
+            print(f"[bench] mix prec {prec} step {i}: {st['blocks']} blocks {st['entries']} entries "
+                  f"{times[-1]:.3f} s", file=sys.stderr, flush=True)
         sst = bem.server_stats()
         res[prec] = {"entries_per_s": ents / sum(times), "latency_p50_ms": sst["latency_p50"] * 1e3,
-                     "latency_p99_ms": sst["latency_p99"] * 1e3, "requests_per_batch":
-                     sst["requests"] / max(1, sst["batches"]), "step_seconds_median": float(np.median(times))}
+                     "latency_p99_ms": sst["latency_p99"] * 1e3,
+                     "requests_per_batch": sst["requests"] / max(1, sst["batches"]),
+                     "step_seconds_median": float(np.median(times)), "requests_per_step": reqs // args.steps,
+                     "entries_per_step": ents // args.steps, "capacity_blocks_per_s": cap}
     # error per (mesh, k) instance against the oracle on seeded ACA rows
     worst = {}
     if not args.no_cpu_baseline:
@@ -948,7 +948,7 @@ def mix_main(args):
             om = cache[key]
             e = 0.0
             for _ in range(2):
-                rows, cols = it["plan"].block(int(rng.integers(it["plan"].info()["blocks"])))
+                rows, cols = it["plan"].block(int(rng.integers(it["blocks"])))
                 r = rows[:1]
                 got = bem.eval_entries(it["mesh"], bem.HELMHOLTZ_SLP, bem.P0, it["k"], r, cols, prec=bem.FP32,
                                        near=bem.NEAR_ERROR)
@@ -963,9 +963,14 @@ def mix_main(args):
             "config": {"workload": "served Helmholtz single layer, P0, 4-point rule, 8 meshes (icospheres 5,120-"
                                    "327,680 triangles, 10:1:1 spheroids ~10k-400k) x 4 wavenumbers (2, 5, 10, 20 "
                                    "elements per wavelength), ACA plans leaf 16, eta 1, tol 1e-4, one device queue, "
-                                   f"{args.workers} host ACA workers spread over the instances by their blocks "
-                                   f"({workers} per instance of each mesh) x {args.blocks_per_worker} blocks"},
+                                   f"one pool of {args.workers} host ACA workers x {args.blocks_per_worker} blocks "
+                                   "over all 32 instances, Poisson block arrivals (seed 1) at "
+                                   f"{args.load} x the warm-up capacity",
+                       "admissible_blocks": int(pidx.size), "blocks_served": int(order.size),
+                       "requests_per_step": f32["requests_per_step"],
+                       "entries_per_step": f32["entries_per_step"]},
             "latency_p50_ms": f32["latency_p50_ms"], "latency_p99_ms": f32["latency_p99_ms"],
+            "requests_per_batch": f32["requests_per_batch"],
             "fp64": f64, "fp32_over_fp64": f32["entries_per_s"] / f64["entries_per_s"],
             "max_rel_err_sampled_per_instance": worst}
     print(json.dumps(line))

@@ -457,6 +457,23 @@ typedef struct {
  * is available at once.  The factors replace those of the previous run. */
 int bem_aca_plan_run(bem_aca_plan *plan, const int64_t *blocks, const double *arrival, int64_t n, bem_prec prec,
                      bem_aca_run_stats *stats);
+/* One served stream over the blocks of several plans (several meshes,
+ * operators or wavenumbers in one device queue): block i is block
+ * blocks[i] of plans[plan_index[i]], available arrival[i] seconds after the
+ * call (NULL: at once; non-decreasing); n_workers host threads, each with up
+ * to blocks_per_worker blocks in flight, take the blocks in arrival order
+ * whatever plan they belong to, so one pool of ACA workers serves every plan
+ * (the plans' own n_workers and blocks_per_worker are not used).  Each
+ * block is approximated with its plan's operator, mesh, wavenumber,
+ * tolerance and rank bound, entries of precision prec; its factors replace
+ * those of the plan's previous run (a plan's blocks not in this run have
+ * none afterwards).  The plans must share the value type (all Laplace or all
+ * Helmholtz) and no other run may use them meanwhile.  stats: totals over
+ * all blocks.  Errors: BEM_E_ARG (bad arguments, an index out of range,
+ * mixed value types), BEM_E_OOM, BEM_E_DEVICE. */
+int bem_aca_plans_run(bem_aca_plan *const *plans, int64_t nplans, const int64_t *plan_index, const int64_t *blocks,
+                      const double *arrival, int64_t n, bem_prec prec, int32_t n_workers, int32_t blocks_per_worker,
+                      bem_aca_run_stats *stats);
 /* Factors of plan block b from the last run: *rank, and when U, V are not
  * NULL, U column-major m x rank and V column-major n x rank (double or
  * complex double), block ~= U V^T.  BEM_E_ARG if b was not in the last run. */

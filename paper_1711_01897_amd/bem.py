@@ -34,7 +34,7 @@ EXPORTS = [
     "bem_server_stats", "bem_server_kernel_stats", "bem_aca_block", "bem_aca_callback", "bem_partition", "bem_hmat_assemble",
     "bem_hmat_matvec", "bem_hmat_stats_get", "bem_hmat_block_info", "bem_hmat_block_dense", "bem_hmat_destroy",
     "bem_aca_plan_create", "bem_aca_plan_info", "bem_aca_plan_block", "bem_aca_plan_run", "bem_aca_plan_factors",
-    "bem_aca_plan_destroy", "bem_eval_dense", "bem_eval_entries_async_noalloc",
+    "bem_aca_plan_destroy", "bem_eval_dense", "bem_eval_entries_async_noalloc", "bem_aca_plans_run",
 ]
 
 
@@ -168,6 +168,8 @@ def lib():
     L.bem_aca_plan_info.argtypes = [_p, _i64p, _i64p, _dp]
     L.bem_aca_plan_block.argtypes = [_p, ctypes.c_int64, _i64p, _i64p, ctypes.POINTER(_i32p), ctypes.POINTER(_i32p)]
     L.bem_aca_plan_run.argtypes = [_p, _i64p, _dp, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(AcaRunStats)]
+    L.bem_aca_plans_run.argtypes = [ctypes.POINTER(_p), ctypes.c_int64, _i64p, _i64p, _dp, ctypes.c_int64,
+                                    ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(AcaRunStats)]
     L.bem_aca_plan_factors.argtypes = [_p, ctypes.c_int64, _i32p, _p, _p]
     L.bem_aca_plan_destroy.argtypes = [_p]
     L.bem_eval_dense.argtypes = entry_args + [_p, ctypes.POINTER(DenseStats)]
@@ -510,6 +512,26 @@ class AcaPlan:
             self.destroy()
         except Exception:
             pass
+
+
+def aca_plans_run(plans, plan_index, blocks, arrival=None, prec=FP32, n_workers=32, blocks_per_worker=128) -> dict:
+    """bem_aca_plans_run: one served stream over blocks of several plans
+    (block i is blocks[i] of plans[plan_index[i]])."""
+    pidx = np.ascontiguousarray(np.asarray(plan_index, dtype=np.int64).ravel())
+    blocks = np.ascontiguousarray(np.asarray(blocks, dtype=np.int64).ravel())
+    if pidx.size != blocks.size:
+        raise ValueError("one plan index per block")
+    arr = None
+    if arrival is not None:
+        arr = np.ascontiguousarray(np.asarray(arrival, dtype=np.float64).ravel())
+        if arr.size != blocks.size:
+            raise ValueError("one arrival time per block")
+    handles = (_p * len(plans))(*[pl.handle for pl in plans])
+    st = AcaRunStats()
+    _check(lib().bem_aca_plans_run(handles, len(plans), pidx.ctypes.data_as(_i64p), blocks.ctypes.data_as(_i64p),
+                                   arr.ctypes.data_as(_dp) if arr is not None else None, blocks.size, prec,
+                                   int(n_workers), int(blocks_per_worker), ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in AcaRunStats._fields_}
 
 
 def aca_plan_create(mesh: Mesh, op, space, k, leaf_size=100, eta=1.0, aca_tol=1e-5, max_rank=200, n_workers=8,

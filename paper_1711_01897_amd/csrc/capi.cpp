@@ -28,6 +28,8 @@ int plan_create(bem_mesh *, int, int, double, const bem_hmat_params *, bem_aca_p
 int plan_info(const bem_aca_plan *, int64_t *, int64_t *, double *);
 int plan_block(const bem_aca_plan *, int64_t, int64_t *, int64_t *, const int32_t **, const int32_t **);
 int plan_run(bem_aca_plan *, const int64_t *, const double *, int64_t, int, bem_aca_run_stats *);
+int plans_run(bem_aca_plan *const *, int64_t, const int64_t *, const int64_t *, const double *, int64_t, int, int,
+              int, bem_aca_run_stats *);
 int plan_factors(const bem_aca_plan *, int64_t, int32_t *, void *, void *);
 int plan_destroy(bem_aca_plan *);
 int eval_dense(bem_mesh *, int, int, double, const int32_t *, int64_t, const int32_t *, int64_t, int, int, void *,
@@ -469,6 +471,13 @@ int bem_aca_plan_run(bem_aca_plan *plan, const int64_t *blocks, const double *ar
                      bem_aca_run_stats *stats)
 {
     return plan_run(plan, blocks, arrival, n, prec, stats);
+}
+
+int bem_aca_plans_run(bem_aca_plan *const *plans, int64_t nplans, const int64_t *plan_index, const int64_t *blocks,
+                      const double *arrival, int64_t n, bem_prec prec, int32_t n_workers, int32_t blocks_per_worker,
+                      bem_aca_run_stats *stats)
+{
+    return plans_run(plans, nplans, plan_index, blocks, arrival, n, prec, n_workers, blocks_per_worker, stats);
 }
 
 int bem_aca_plan_factors(const bem_aca_plan *plan, int64_t b, int32_t *rank, void *U, void *V)

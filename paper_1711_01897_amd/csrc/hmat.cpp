@@ -17,6 +17,7 @@
 #include <deque>
 #include <type_traits>
 #include <thread>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <sys/mman.h>
@@ -419,15 +420,20 @@ struct DoneQueue {
     }
 };
 
+struct AssemblyCtx;
+
 struct Job {
     int64_t leaf;
     int adm;
+    AssemblyCtx *plan = nullptr;   // the block's plan context (null: the run's own context)
 };
 
 template <typename T>
 struct Slot {
     int64_t leaf = -1;
     bool adm = false;
+    AssemblyCtx *P = nullptr;   // context of the block's plan (operator, mesh, H-matrix, lane sets)
+    int arena = 0;              // the worker's value arena for that plan
     double t_start = 0.0;
     AcaCore<T> core;
     Request req;
@@ -552,7 +558,15 @@ void worker(AssemblyCtx &C, int per_worker)
     // noticeable share of a request's host work): only with BEM_DEBUG_TIMING
     static const bool fine = std::getenv("BEM_DEBUG_TIMING") != nullptr;
     WorkerTally tally;
-    ValueArena arena;   // values of the blocks this worker finishes
+    // values of the blocks this worker finishes, one arena per plan (a run
+    // over several plans hands each plan's values to its own H-matrix)
+    std::vector<std::pair<AssemblyCtx *, ValueArena>> arenas;
+    auto arena_of = [&](AssemblyCtx *P) -> int {
+        for (size_t i = 0; i < arenas.size(); ++i)
+            if (arenas[i].first == P) return (int)i;
+        arenas.emplace_back(P, ValueArena());
+        return (int)arenas.size() - 1;
+    };
     std::vector<Slot<T>> slots(per_worker);
     std::vector<Request *> submit, done;
     int active = 0;
@@ -589,16 +603,19 @@ void worker(AssemblyCtx &C, int per_worker)
         if (C.arrival) start_delay += t - (C.t0 + C.arrival[j]);
         s.leaf = C.jobs[j].leaf;
         s.adm = C.jobs[j].adm != 0;
+        s.P = C.jobs[j].plan ? C.jobs[j].plan : &C;
+        s.arena = arena_of(s.P);
         s.t_start = now_seconds();
         if (s.adm) {
-            const bem_hmat::Leaf &L = C.h->leaves[s.leaf];
-            const Block &bk = C.h->part.blocks[s.leaf];
-            const Cluster &a = C.h->part.nodes[bk.tau];
-            const Cluster &b = C.h->part.nodes[bk.sigma];
-            s.core.init(L.m, L.n, C.tol, C.max_rank,
-                        default_zero_abs(*C.mesh, C.op, C.space, C.k, C.prec, support_distance(a, b)));
+            const AssemblyCtx &P = *s.P;
+            const bem_hmat::Leaf &L = P.h->leaves[s.leaf];
+            const Block &bk = P.h->part.blocks[s.leaf];
+            const Cluster &a = P.h->part.nodes[bk.tau];
+            const Cluster &b = P.h->part.nodes[bk.sigma];
+            s.core.init(L.m, L.n, P.tol, P.max_rank,
+                        default_zero_abs(*P.mesh, P.op, P.space, P.k, P.prec, support_distance(a, b)));
         }
-        const int rc = prepare_slot(C, s, dq, si, tally);
+        const int rc = prepare_slot(*s.P, s, dq, si, tally);
         if (rc != BEM_OK) {
             C.set_error(rc, std::string("request: ") + bem_last_error());
             return -1;
@@ -688,12 +705,14 @@ void worker(AssemblyCtx &C, int per_worker)
                                                         : "device request failed");
                 finished = true;
             } else {
-                bem_hmat::Leaf &L = C.h->leaves[s.leaf];
+                AssemblyCtx &P = *s.P;
+                ValueArena &arena = arenas[s.arena].second;
+                bem_hmat::Leaf &L = P.h->leaves[s.leaf];
                 const int64_t cnt = r->entries();
                 if (!s.adm) {
                     const double c0 = fine ? now_seconds() : 0.0;
                     s.buf.resize(cnt);
-                    to_scalar<T>(r->result, C.prec, cnt, s.buf.data());
+                    to_scalar<T>(r->result, P.prec, cnt, s.buf.data());
                     if (fine) tc += now_seconds() - c0;
                     double *D = arena.take((size_t)cnt * (sizeof(T) / sizeof(double)));
                     std::memcpy(D, s.buf.data(), sizeof(T) * cnt);
@@ -701,7 +720,7 @@ void worker(AssemblyCtx &C, int per_worker)
                     finished = true;
                 } else {
                     const double a0 = fine ? now_seconds() : 0.0;
-                    aca_consume(s.core, r->result, C.prec);
+                    aca_consume(s.core, r->result, P.prec);
                     if (fine) ta += now_seconds() - a0;
                     if (s.core.phase == AcaCore<T>::DONE) {
                         L.rank = s.core.k;
@@ -737,7 +756,7 @@ void worker(AssemblyCtx &C, int per_worker)
                 continue;
             }
             const double p0 = fine ? now_seconds() : 0.0;
-            const int rc = prepare_slot(C, s, dq, r->tag, tally);
+            const int rc = prepare_slot(*s.P, s, dq, r->tag, tally);
             if (fine) tp += now_seconds() - p0;
             if (rc != BEM_OK) {
                 C.set_error(rc, std::string("request: ") + bem_last_error());
@@ -766,7 +785,8 @@ void worker(AssemblyCtx &C, int per_worker)
     C.dense_entries.fetch_add(tally.dense_entries);
     C.requests.fetch_add(tally.requests);
     std::lock_guard<std::mutex> g(C.busy_mu);
-    C.h->store.insert(C.h->store.end(), arena.blocks.begin(), arena.blocks.end());
+    for (auto &pa : arenas) pa.first->h->store.insert(pa.first->h->store.end(), pa.second.blocks.begin(),
+                                                      pa.second.blocks.end());
     C.busy += busy;
     C.qdelay += qd;
     C.proc += pr;
@@ -1259,6 +1279,106 @@ int plan_run(bem_aca_plan *pl, const int64_t *blocks, const double *arrival, int
                 1e6 * C.busy / np, 1e6 * C.t_conv / np, 1e6 * C.t_aca / np, 1e6 * C.t_rel / np, 1e6 * C.t_prep / np,
                 1e6 * C.t_flush / np);
         server_print_phases();
+    }
+    return BEM_OK;
+}
+
+// One served stream over the blocks of several plans (the served mixed
+// workload): one pool of workers takes the blocks in arrival order whatever
+// plan they belong to, each block with its own plan's operator, mesh,
+// wavenumber, H-matrix and lane sets.
+int plans_run(bem_aca_plan *const *plans, int64_t np, const int64_t *pidx, const int64_t *blocks,
+              const double *arrival, int64_t n, int prec, int n_workers, int per_worker, bem_aca_run_stats *st)
+{
+    if (!plans || np < 1 || n < 0 || (n > 0 && (!pidx || !blocks)) || n_workers < 1 || per_worker < 1)
+        return fail(BEM_E_ARG, "bad run arguments");
+    if (prec != BEM_FP32 && prec != BEM_FP64) return fail(BEM_E_ARG, "unknown precision");
+    for (int64_t p = 0; p < np; ++p)
+        if (!plans[p]) return fail(BEM_E_ARG, "null plan");
+    const bool cplx = plans[0]->h->cplx;
+    for (int64_t p = 0; p < np; ++p)
+        if (plans[p]->h->cplx != cplx) return fail(BEM_E_ARG, "the plans of one run must share the value type");
+    for (int64_t i = 0; i < n; ++i) {
+        if (pidx[i] < 0 || pidx[i] >= np) return fail(BEM_E_ARG, "plan index out of range");
+        if (blocks[i] < 0 || blocks[i] >= (int64_t)plans[pidx[i]]->adm.size())
+            return fail(BEM_E_ARG, "plan block out of range");
+        if (arrival && (!std::isfinite(arrival[i]) || arrival[i] < 0.0 || (i > 0 && arrival[i] < arrival[i - 1])))
+            return fail(BEM_E_ARG, "arrival times must be finite, >= 0 and non-decreasing");
+    }
+    // every distinct plan, locked in address order (one run per plan at a time)
+    std::vector<bem_aca_plan *> distinct(plans, plans + np);
+    std::sort(distinct.begin(), distinct.end());
+    distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+    std::vector<std::unique_lock<std::mutex>> locks;
+    for (bem_aca_plan *pl : distinct) locks.emplace_back(pl->run_mu);
+    std::vector<std::unique_ptr<AssemblyCtx>> ctx(distinct.size());
+    for (size_t d = 0; d < distinct.size(); ++d) {
+        bem_aca_plan *pl = distinct[d];
+        bem_hmat *h = pl->h;
+        for (int64_t leaf : pl->last) {   // the previous run's factors go back to the pool
+            auto &L = h->leaves[leaf];
+            L.rank = 0;
+            L.U = L.V = nullptr;
+        }
+        pl->last.clear();
+        value_pool().give(h->store);
+        ctx[d].reset(new AssemblyCtx());
+        AssemblyCtx &c = *ctx[d];
+        c.mesh = pl->mesh;
+        c.op = pl->op;
+        c.space = pl->space;
+        c.prec = prec;
+        c.k = pl->k;
+        c.tol = pl->p.aca_tol;
+        c.max_rank = pl->p.max_rank;
+        c.h = h;
+        c.lanes = &pl->lanes.refs;
+    }
+    auto ctx_of = [&](bem_aca_plan *pl) {
+        return ctx[std::lower_bound(distinct.begin(), distinct.end(), pl) - distinct.begin()].get();
+    };
+    AssemblyCtx M;   // the run: jobs, arrivals, counters; per-block fields come from the jobs' plans
+    M.mesh = plans[0]->mesh;
+    M.prec = prec;
+    M.jobs.reserve((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        bem_aca_plan *pl = plans[pidx[i]];
+        Job j{pl->adm[blocks[i]], 1};
+        j.plan = ctx_of(pl);
+        M.jobs.push_back(j);
+    }
+    M.arrival = arrival;
+    M.t0 = now_seconds();
+    std::vector<std::thread> th;
+    for (int w = 0; w < n_workers; ++w) {
+        if (cplx)
+            th.emplace_back([&] { worker<cd>(M, per_worker); });
+        else
+            th.emplace_back([&] { worker<double>(M, per_worker); });
+    }
+    for (auto &t : th) t.join();
+    const double t1 = now_seconds();
+    for (const Job &j : M.jobs)
+        for (bem_aca_plan *pl : distinct)
+            if (ctx_of(pl) == j.plan) {
+                pl->last.push_back(j.leaf);
+                break;
+            }
+    if (M.error.load() != 0) return fail(M.error.load(), "ACA run: " + M.err_msg);
+    if (st) {
+        *st = bem_aca_run_stats{};
+        st->blocks = n;
+        st->entries = M.aca_entries.load();
+        st->requests = M.requests.load();
+        for (const Job &j : M.jobs) {
+            const auto &L = j.plan->h->leaves[j.leaf];
+            st->rank_sum += L.rank;
+            st->rank_max = std::max(st->rank_max, (int32_t)L.rank);
+        }
+        st->seconds = t1 - M.t0;
+        const double nd = (double)std::max<int64_t>(1, M.blocks_done);
+        st->mean_start_delay = M.start_delay / nd;
+        st->mean_block_seconds = M.block_time / nd;
     }
     return BEM_OK;
 }

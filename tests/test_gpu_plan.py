@@ -85,3 +85,59 @@ def test_plan_fp32_requests_close_to_fp64(sphere4):
         assert s32["requests"] <= 1.05 * s64["requests"], (op, s32["requests"], s64["requests"])
         assert s32["rank_sum"] <= 1.2 * s64["rank_sum"]
         plan.destroy()
+
+
+def test_plans_run_serves_several_plans_in_one_stream():
+    """One pool of workers over the blocks of four plans (two meshes x two
+    wavenumbers, Helmholtz single layer P0): every block's factors equal those
+    of its plan run alone (bit for bit: the pivots depend only on the block's
+    entries, and a request's entries do not depend on the batch it lands in),
+    sampled blocks match the dense oracle block, and mixed value types or bad
+    indices are refused."""
+    meshes = []
+    for xyz, tri in (inputs.icosphere(3), inputs.spheroid(10.0, 1.0, 4000)):
+        meshes.append((xyz, tri, bem.mesh_create(xyz, tri, 4), O.OracleMesh(xyz, tri, 4)))
+    plans, ks, oms = [], [], []
+    for xyz, tri, mesh, om in meshes:
+        for epw in (5.0, 10.0):
+            k = inputs.wavenumber(xyz, tri, epw)
+            plans.append(bem.aca_plan_create(mesh, bem.HELMHOLTZ_SLP, bem.P0, k, leaf_size=16, eta=1.0,
+                                             aca_tol=1e-4, max_rank=100, n_workers=1, blocks_per_worker=8,
+                                             prec=bem.FP32))
+            ks.append(k)
+            oms.append(om)
+    rng = inputs.rng(inputs.SEED_REQUESTS)
+    pidx, blocks = [], []
+    for p, pl in enumerate(plans):
+        sel = rng.choice(pl.info()["blocks"], size=60, replace=False)
+        pidx += [p] * sel.size
+        blocks += list(sel)
+    order = rng.permutation(len(blocks))
+    pidx, blocks = np.array(pidx)[order], np.array(blocks)[order]
+    arr = np.cumsum(rng.exponential(1e-5, size=blocks.size))
+    st = bem.aca_plans_run(plans, pidx, blocks, arr, bem.FP32, n_workers=6, blocks_per_worker=16)
+    assert st["blocks"] == blocks.size and st["entries"] > 0
+    together = {(int(p), int(b)): plans[p].factors(b) for p, b in zip(pidx, blocks)}
+    for p, pl in enumerate(plans):
+        mine = blocks[pidx == p]
+        pl.run(mine, None, bem.FP32)
+        for b in mine:
+            U, V = pl.factors(b)
+            U2, V2 = together[(p, int(b))]
+            assert np.array_equal(U, U2) and np.array_equal(V, V2)
+        for b in mine[:5]:
+            rows, cols = pl.block(b)
+            D = oms[p].entries(O.HELMHOLTZ_SLP, O.P0, ks[p], rows, cols, near=O.NEAR_ERROR)
+            U, V = pl.factors(b)
+            assert np.linalg.norm(D - U @ V.T) / np.linalg.norm(D) <= 10 * 1e-4
+    lap = bem.aca_plan_create(meshes[0][2], bem.LAPLACE_SLP, bem.P0, 0.0, leaf_size=16, eta=1.0, aca_tol=1e-4,
+                              max_rank=100, n_workers=1, blocks_per_worker=8, prec=bem.FP32)
+    with pytest.raises(bem.BemError):
+        bem.aca_plans_run([plans[0], lap], [0, 1], [0, 0])
+    with pytest.raises(bem.BemError):
+        bem.aca_plans_run(plans, [0, 9], [0, 0])
+    lap.destroy()
+    for pl in plans:
+        pl.destroy()
+    for xyz, tri, mesh, om in meshes:
+        mesh.destroy()
