@@ -177,9 +177,10 @@ public:
         size_t out = 0;                 // output bytes reserved (from off_out0)
         int64_t entries = 0, evals = 0, loads = 0;
         double t_first = 0.0;
+        bool closed = false;            // taken by the dispatcher; the last writer launches it
+        double t_close = 0.0;
     };
     Open *open = nullptr;              // guarded by mu
-    std::condition_variable wcv;       // dispatcher: reservations of a closed batch written
     bool fast_enabled = true;          // BEM_SERVER_FAST (default 1)
     int fast_min = 256;                // BEM_SERVER_FAST_MIN: close at this many requests ...
     double fast_wait_s = 30e-6;        // BEM_SERVER_FAST_WAIT_US: ... or when the first has waited this long
@@ -517,12 +518,41 @@ public:
         }
         rs[0]->mesh->inflight.fetch_add((int64_t)n);
         _mm_sfence();   // the streamed records are in memory before the batch can be launched
+        bool last = false;
         {
             std::lock_guard<std::mutex> g(mu);
-            if (--o->writers == 0) wcv.notify_all();
+            last = --o->writers == 0 && o->closed;
         }
+        // a batch closed while its reservations were being written is
+        // launched by the writer that finishes last
+        if (last) launch_closed(o);
         if (wake) cv.notify_one();
         return true;
+    }
+
+    // Launches a closed fast batch whose reservations are all written and
+    // hands it to the completion thread.
+    void launch_closed(Open *fo)
+    {
+        launch_fast(fo);
+        Batch *b = fo->b;
+        const double t1 = now_seconds();
+        double qs = 0.0;
+        for (const FastGroup &g : b->groups) qs += g.n * (fo->t_close - g.t_submit);
+        b->t_take = fo->t_close;
+        b->t_enq = t1;
+        b->q_sum = qs;
+        delete fo;
+        {
+            std::lock_guard<std::mutex> g(stat_mu);
+            dispatch_s += t1 - b->t_take;
+            dispatch_hip_s += b->t_hip;
+        }
+        {
+            std::lock_guard<std::mutex> g(mu);
+            inflight.push_back(b);
+        }
+        cvc.notify_one();
     }
 
     Batch *new_fast_batch(int slot)
@@ -627,28 +657,12 @@ public:
                         open->b = new_fast_batch(fs);
                         slot_busy[fs] = true;
                     }
-                    const double t0 = now_seconds();
-                    wcv.wait(lk, [&] { return fo->writers == 0; });
+                    fo->t_close = now_seconds();
+                    fo->closed = true;
+                    const bool ready = fo->writers == 0;
                     lk.unlock();
-                    launch_fast(fo);
-                    Batch *b = fo->b;
-                    const double t1 = now_seconds();
-                    double qs = 0.0;
-                    for (const FastGroup &g : b->groups) qs += g.n * (t0 - g.t_submit);
-                    b->t_take = t0;
-                    b->t_enq = t1;
-                    b->q_sum = qs;
-                    delete fo;
-                    {
-                        std::lock_guard<std::mutex> g(stat_mu);
-                        dispatch_s += t1 - t0;
-                        dispatch_hip_s += b->t_hip;
-                    }
-                    {
-                        std::lock_guard<std::mutex> g(mu);
-                        inflight.push_back(b);
-                    }
-                    cvc.notify_one();
+                    // reservations still being written: their last writer launches the batch
+                    if (ready) launch_closed(fo);
                     continue;
                 }
                 while (!stop && min_batch > 1 && (int)pending.size() < min_batch) {
