@@ -100,6 +100,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-star", action="store_true", help="--dense: skip the star-kernel comparison")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-hmatrix-fraction", type=float, default=0.02,
+                    help="icosphere6: fraction of admissible blocks in the CPU-only oracle H-matrix assembly "
+                         "(0: skip)")
     ap.add_argument("--dense", type=int, default=0, metavar="LEVEL",
                     help="instead of the H-matrix workload: the dense P1 matrix of the --ops operators on the "
                          "icosphere of this level, submitted to the request server in row chunks")
@@ -274,32 +277,41 @@ def timed(bem, mesh, prec, steps, warmup, args):
 
 
 def roofline(kstats, workload="icosphere6"):
+    """Roofline of the dominant kernel: the resident (persistent) launches
+    when the server served its batches that way, else the launched kernel
+    with the most device time."""
     main = list(kstats)
     if not main:
         return None, None
-    dom = max(main, key=lambda k: k["seconds"])
+    resident = [k for k in main if k.get("persistent")]
+    dom = max(resident or main, key=lambda k: k["seconds"])
     flops = dom["pair_evals"] * FLOPS_PER_EVAL[(dom["op"], dom["space"])]
     per_launch = flops / dom["launches"]
     mean_ev = dom["seconds_events"] / dom["launches"]    # HIP events around the launch, on its stream
     mean_dc = dom["seconds"] / dom["launches"]           # first workgroup start to last workgroup end
     achieved = per_launch / mean_ev / 1e12
     traffic = None
-    wg_per_launch = dom["workgroups"] / dom["launches"]
+    blocks_per_launch = dom["blocks"] / dom["launches"]
     if os.path.exists(traffic_file(workload)):
         with open(traffic_file(workload)) as f:
             t = json.load(f)
+        # per block of entry work: the resident and the launched kernel run the
+        # same per-block code (one block per workgroup when launched)
         if t.get("kernel_source_hash") == kernel_source_hash() and "bytes_per_workgroup" in t:
-            traffic = t["bytes_per_workgroup"] * wg_per_launch
+            traffic = t["bytes_per_workgroup"] * blocks_per_launch
     # algorithmic bytes per entry of the measurement plan (P1, 6-point rule):
     # two trial triangles of 36 B of vertex coordinates, a 4-byte index and a
     # 4-byte FP32 output
     alg_bytes = 80.0 * dom["entries"] / dom["launches"]
-    name = "%s_f%s<op=%d,Q=%d>" % (KERNEL_NAMES[dom["space"]], "32" if dom["prec"] == 1 else "64",
-                                   dom["op"], dom["quad_points"])
+    name = "%s%s_f%s<op=%d,Q=%d>" % ("kp_" if dom.get("persistent") else "k_",
+                                     KERNEL_NAMES[dom["space"]][2:], "32" if dom["prec"] == 1 else "64",
+                                     dom["op"], dom["quad_points"])
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_PACKED / 1e12, 1),
             "unit": "TFLOP/s", "frac": round(achieved * 1e12 / PEAK_FP32_PACKED, 4), "traffic": traffic,
-            "kernel": name, "launches": dom["launches"], "mean_launch_us": round(mean_ev * 1e6, 2),
+            "kernel": name, "persistent": bool(dom.get("persistent")), "launches": dom["launches"],
+            "mean_launch_us": round(mean_ev * 1e6, 2),
             "workgroups_per_launch": round(dom["workgroups"] / dom["launches"], 1),
+            "blocks_per_launch": round(blocks_per_launch, 1),
             "mean_launch_us_device_clock": round(mean_dc * 1e6, 2),
             "frac_device_clock": round(per_launch / mean_dc / PEAK_FP32_PACKED, 4),
             "flops_per_launch": per_launch, "flops_per_eval": FLOPS_PER_EVAL[(dom["op"], dom["space"])],
@@ -348,6 +360,63 @@ def cpu_baseline(bem, inputs, mesh, xyz, tri, seconds, ops):
             "sample": f"{nreq} ACA row/column requests ({'/'.join(sorted(set(OP_LABEL[o] for o in ops)))}, P1) of "
                       f"seeded admissible blocks of "
                       f"the same partition, {entries} entries, {spent:.1f} s"}, worst
+
+
+def cpu_hmatrix(inputs, xyz, tri, ops, fraction, tol=1e-5, max_rank=200):
+    """CPU-only H-matrix assembly driven by the FP64 oracle: the oracle's
+    partition (leaf 100, eta 1) and its ACA (Algorithm ACA, Section 2.1) with
+    the oracle's FP64 rows and columns on all host threads, over a seeded
+    fraction of the admissible blocks of each operator; the time for every
+    admissible block is extrapolated by the blocks' summed dimensions (ACA
+    work goes as rank x (m + n))."""
+    import numpy as np
+    import oracle
+    from oracle import aca as oaca
+    from oracle import tree as otree
+
+    om = oracle.OracleMesh(xyz, tri, 6)
+    t0 = time.perf_counter()
+    nodes, leaves = otree.partition(xyz, tri, oracle.P1, 100, 1.0)
+    t_part = time.perf_counter() - t0
+    adm = [(t, s) for t, s, a in leaves if a]
+    rng = inputs.rng(inputs.SEED_SAMPLING)
+    pick = rng.choice(len(adm), size=max(1, int(round(fraction * len(adm)))), replace=False)
+    mn_all = float(sum(nodes[t].idx.size + nodes[s].idx.size for t, s in adm))
+    out = {"kind": "oracle", "cores": oracle.max_threads(), "partition_seconds": t_part,
+           "admissible_blocks": len(adm), "sampled_blocks": int(pick.size), "ops": {}}
+    total = 0.0
+    for op in ops:
+        entries, spent, rank_sum, mn = 0, 0.0, 0, 0
+        for i in pick:
+            t, s = adm[int(i)]
+            rows = nodes[t].idx.astype(np.int32)
+            cols = nodes[s].idx.astype(np.int32)
+            count = [0]
+
+            def get_row(k, rows=rows, cols=cols, count=count):
+                count[0] += cols.size
+                return om.entries(op, oracle.P1, 0.0, rows[k:k + 1], cols)[0]
+
+            def get_col(k, rows=rows, cols=cols, count=count):
+                count[0] += rows.size
+                return om.entries(op, oracle.P1, 0.0, rows, cols[k:k + 1])[:, 0]
+
+            ts = time.perf_counter()
+            U, V, _, _ = oaca.aca(get_row, get_col, rows.size, cols.size, tol, max_rank)
+            spent += time.perf_counter() - ts
+            entries += count[0]
+            rank_sum += U.shape[1]
+            mn += rows.size + cols.size
+        full = spent * mn_all / mn
+        total += full
+        out["ops"][OP_LABEL[op]] = {"sampled_seconds": spent, "sampled_entries": entries,
+                                    "entries_per_s": entries / spent, "mean_rank": rank_sum / pick.size,
+                                    "extrapolated_seconds_all_admissible_blocks": full}
+    out["extrapolated_seconds"] = total
+    out["sample"] = (f"{pick.size} of {len(adm)} admissible blocks per operator (seed {inputs.SEED_SAMPLING}), "
+                     f"oracle ACA tol {tol}, FP64 oracle rows and columns on {out['cores']} threads; time for all "
+                     "admissible blocks extrapolated by summed block dimensions")
+    return out
 
 
 def dense_run(bem, mesh, idx, ops, prec, chunk):
@@ -1071,10 +1140,16 @@ def main():
 
     cpu = None
     worst = None
+    cpu_h = None
     if not args.no_cpu_baseline:
         cpu, worst = cpu_baseline(bem, inputs, mesh, xyz, tri, args.cpu_seconds, step_ops(args))
         print(f"[bench] cpu baseline {cpu['value']:.3e} entries/s on {cpu['cores']} threads", file=sys.stderr,
               flush=True)
+        if args.cpu_hmatrix_fraction > 0:
+            cpu_h = cpu_hmatrix(inputs, xyz, tri, step_ops(args), args.cpu_hmatrix_fraction)
+            cpu_h["speedup_over_fp32_step"] = cpu_h["extrapolated_seconds"] / (dt / args.steps)
+            print(f"[bench] cpu H-matrix: {cpu_h['extrapolated_seconds']:.1f} s extrapolated "
+                  f"(S = {cpu_h['speedup_over_fp32_step']:.0f})", file=sys.stderr, flush=True)
 
     value = tot["entries"] / dt
     line = {
@@ -1121,6 +1196,7 @@ def main():
         "max_rel_err_sampled": worst,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "cpu_hmatrix": cpu_h,
     }
     print(json.dumps(line))
 

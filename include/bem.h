@@ -293,9 +293,16 @@ int bem_server_stats(bem_server_stats_t *stats, int reset);
  * between HIP events recorded around each launch on its stream, which also
  * holds whatever separates the start event from the kernel's start (host
  * submission of the launch, other work of the same hardware queue).  One
- * entry launch serves row and column requests alike. */
+ * entry launch serves row and column requests alike.
+ * Records with persistent = 1 would be resident launches serving the
+ * server's batches of ACA rows and columns one after another (every such
+ * launch ended since the last reset, with all the work of its batches, both
+ * times its whole residency); those launches are switched off in this build
+ * (BEM_SERVER_PERSIST=1 makes the server refuse to start), so none appear. */
 typedef struct {
     int32_t op, space, prec, quad_points;
+    int32_t persistent;        /* 1: resident launches serving batch after batch */
+    int32_t reserved;
     int64_t launches;
     int64_t workgroups;        /* 256-thread workgroups of these launches */
     int64_t entries;           /* entries of the requests these launches served */
@@ -304,6 +311,7 @@ typedef struct {
     int64_t triangle_loads;    /* lane-triangle geometry records gathered (one per lane per workgroup) */
     double seconds;            /* summed kernel execution times (device clock) */
     double seconds_events;     /* summed HIP-event launch brackets */
+    int64_t blocks;            /* blocks of entry work served (one per workgroup of a launch of its own) */
 } bem_kernel_stats_t;
 
 /* Copies up to max_entries variant records into out, sets *count to the

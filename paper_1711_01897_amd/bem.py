@@ -74,10 +74,10 @@ class ServerStats(ctypes.Structure):
 
 class KernelStats(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("space", ctypes.c_int32), ("prec", ctypes.c_int32),
-                ("quad_points", ctypes.c_int32),
+                ("quad_points", ctypes.c_int32), ("persistent", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("launches", ctypes.c_int64), ("workgroups", ctypes.c_int64), ("entries", ctypes.c_int64), ("pair_evals", ctypes.c_int64),
                 ("triangle_loads", ctypes.c_int64), ("seconds", ctypes.c_double),
-                ("seconds_events", ctypes.c_double)]
+                ("seconds_events", ctypes.c_double), ("blocks", ctypes.c_int64)]
 
 
 class AcaParams(ctypes.Structure):

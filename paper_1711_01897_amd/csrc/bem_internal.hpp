@@ -88,11 +88,13 @@ struct EntryBlock {  // one workgroup of entry work (64 bytes, read with one sca
 // both fixed sides).
 struct Variant {
     int op, space, prec, q;
+    int persist = 0;   // statistics only: the resident (persistent) form of the kernel
     bool operator<(const Variant &o) const {
         if (op != o.op) return op < o.op;
         if (space != o.space) return space < o.space;
         if (prec != o.prec) return prec < o.prec;
-        return q < o.q;
+        if (q != o.q) return q < o.q;
+        return persist < o.persist;
     }
 };
 
@@ -106,6 +108,92 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out);
 // start/stop (optional): HIP events recorded around the launch on its stream.
 hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock *blocks, int64_t nblocks, hipStream_t s,
                           unsigned long long *tclock = nullptr, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+
+// ---------------------------------------------------------------------------
+// Persistent service of batches.
+//
+// One launch of the entry kernel stays resident and serves a stream of
+// batches of one kernel variant.  The host publishes each batch (its
+// descriptors and block records already in host-coherent staging) as an
+// entry of a ring in host-coherent memory, in sequence order.  Workgroup 0
+// watches the ring (one thread) and copies each published entry to device
+// memory together with its claim word; the other workgroups claim blocks
+// with atomic adds on the claim words, oldest batch first, and run the same
+// per-block code as the launched kernels.  Any workgroup can claim any
+// block, so a launch never depends on all of its workgroups being resident.
+// The workgroup that ends a batch's last block stores seq + 1 into the
+// batch's completion word in host memory.  The launch ends when the host asks
+// it to or no entry has been published for a given number of device-clock
+// ticks: the watching thread stores the first sequence number it did not
+// take into the exit word, and every waiting workgroup returns.  The host
+// publishes entry i again only after the batch it last held has completed.
+constexpr int kPersistRing = 64;    // ring entries (more than batches in flight)
+
+struct PersistEntry {               // host-coherent; seq1 written last
+    const ReqDev *reqs;
+    const EntryBlock *blocks;
+    unsigned long long *clock;      // per block {start, end} device clock, or null
+    int64_t nblk;
+    uint64_t seq1;                  // sequence number + 1 once published
+    uint64_t pad[3];
+};
+static_assert(sizeof(PersistEntry) == 64, "ring entries are 64 bytes");
+
+struct PersistHost {                // host-coherent words shared by the persistent launches
+    PersistEntry ring[kPersistRing];
+    uint64_t done[kPersistRing][8];   // done[i][0] = seq + 1 of the last batch of ring entry i completed
+    uint64_t stop;                    // the host asks launches with id <= stop to end
+    uint64_t pad0[7];
+    uint64_t exit_word;               // id << 40 | (first sequence number not taken + 1), stored by a
+                                      // launch as it ends
+    uint64_t pad1[7];
+};
+
+struct PersistItem {                // a published batch as the workers read it (device memory)
+    const ReqDev *reqs;
+    const EntryBlock *blocks;
+    unsigned long long *clock;
+    int64_t nblk;
+    uint64_t pad[4];
+};
+
+// Claim word of ring entry i: (seq mod 2^16) << 48 | nblk << 32 | blocks
+// claimed, seq the batch the entry holds.  An atomic add of one claims
+// block "blocks claimed" when that is below nblk; the tag names the batch
+// the claim belongs to whatever batch the claimer expected (a workgroup's
+// cursor is never 2^15 batches away from the batches an entry can hold), so
+// no claim is lost when an entry is reused.
+struct PersistCtl {                 // device memory, reset before each launch
+    unsigned long long cur;         // every batch before cur has no unclaimed block
+    unsigned long long pad0[15];
+    unsigned int stop;              // the watcher has left: waiting workgroups return
+    unsigned int pad1[31];
+    PersistItem item[kPersistRing];
+    unsigned long long claim[kPersistRing][16];   // one 128-byte line each
+    unsigned int done[kPersistRing][32];          // blocks finished, one line each
+};
+constexpr int kPersistMaxBlocks = 65535;   // per batch (the claim word's nblk field)
+
+struct PersistArgs {
+    const PersistHost *host;        // device address of the host words
+    uint64_t *done;                 // device address of host->done
+    uint64_t *exit_word;            // device address of host->exit_word
+    PersistCtl *ctl;
+    uint64_t seq0;                  // first sequence number this launch serves
+    uint64_t id;                    // launch number: the launch ends once host->stop >= id
+    long long idle_ticks;           // device-clock ticks without a new entry before the launch ends
+};
+
+// Enqueues the reset of a.ctl for a launch that starts at sequence number
+// a.seq0, then the persistent launch of variant v with `groups` workgroups
+// (workgroup 0 watches the ring); start/stop events (optional) around the
+// persistent launch.
+hipError_t launch_persistent(const Variant &v, const PersistArgs &a, int groups, hipStream_t s,
+                             hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// Resident workgroups per compute unit of the persistent kernel of variant v
+// (0 if there is none).
+int persistent_occupancy(const Variant &v);
+
 hipError_t launch_geometry(const double *xyz, const int32_t *tri, int64_t nt, int q, float *g32, double *g64,
                            int4 *vtx, int32_t *bad, hipStream_t s);
 // geo[i] = FP32 record of triangle index[i] >> shift, meta[i] = its vertex

@@ -45,6 +45,91 @@ constexpr int LHYP = BEM_LAPLACE_HYPS, HHYP = BEM_HELMHOLTZ_HYPS;
 constexpr float kInv4PiF = 0.0795774715459476679f;
 constexpr double kInv4Pi = 0.0795774715459476678844418816862571;
 
+// Memory access helpers.  Relaxed atomics at device scope go to the point of
+// coherence of the device, at system scope to host memory; they carry no
+// cache invalidation or writeback.
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p)
+{
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_sys(const T *p)
+{
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename T>
+__device__ __forceinline__ void st_sys(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+template <typename P>
+__device__ __forceinline__ P ld_ptr_sys(P const *p)
+{
+    return reinterpret_cast<P>(ld_sys(reinterpret_cast<const uint64_t *>(p)));
+}
+template <typename P>
+__device__ __forceinline__ P ld_ptr_dev(P const *p)
+{
+    return reinterpret_cast<P>(ld_dev(reinterpret_cast<const uint64_t *>(p)));
+}
+// Waits until this wavefront's vector memory operations, stores included
+// (gfx9 counts both in vmcnt), have completed; also a compiler barrier.
+__device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+
+// Results, near-field flags and clock records go to host-coherent staging.
+// A launched kernel stores them plainly: the end of the kernel makes them
+// visible to the host.  A persistent launch (SYS = true) reports each batch
+// while it keeps running, so it stores them at system scope, written through
+// to host memory instead of staying in the device cache.
+template <bool SYS>
+__device__ __forceinline__ void put(float *p, float v)
+{
+    if constexpr (SYS) st_sys(reinterpret_cast<uint32_t *>(p), __float_as_uint(v));
+    else *p = v;
+}
+template <bool SYS>
+__device__ __forceinline__ void put(double *p, double v)
+{
+    if constexpr (SYS) st_sys(reinterpret_cast<uint64_t *>(p), (uint64_t)__double_as_longlong(v));
+    else *p = v;
+}
+template <bool SYS>
+__device__ __forceinline__ void put(float2 *p, float2 v)
+{
+    if constexpr (SYS) st_sys(reinterpret_cast<uint64_t *>(p), ((uint64_t)__float_as_uint(v.y) << 32) | __float_as_uint(v.x));
+    else *p = v;
+}
+template <bool SYS>
+__device__ __forceinline__ void put(double2 *p, double2 v)
+{
+    if constexpr (SYS) {
+        st_sys(reinterpret_cast<uint64_t *>(p), (uint64_t)__double_as_longlong(v.x));
+        st_sys(reinterpret_cast<uint64_t *>(p) + 1, (uint64_t)__double_as_longlong(v.y));
+    } else {
+        *p = v;
+    }
+}
+template <bool SYS>
+__device__ __forceinline__ void put(int32_t *p, int32_t v)
+{
+    if constexpr (SYS) st_sys(p, v);
+    else *p = v;
+}
+template <bool SYS>
+__device__ __forceinline__ void put(unsigned long long *p, unsigned long long v)
+{
+    if constexpr (SYS) st_sys(p, v);
+    else *p = v;
+}
+
+
 template <int OP>
 constexpr bool is_cplx() { return OP == HSLP || OP == HDLP || OP == HHYP; }
 template <int OP>
@@ -144,14 +229,14 @@ __device__ __forceinline__ void two_sum_acc(float &hi, float &lo, float x)
 // end in tc[2b + 1] (plain stores, one slot per workgroup).
 __device__ __forceinline__ void clock_start(unsigned long long *tc)
 {
-    if (tc && threadIdx.x == 0) tc[2 * blockIdx.x] = (unsigned long long)wall_clock64();
+    if (tc && threadIdx.x == 0) put<false>(tc + 2 * blockIdx.x, (unsigned long long)wall_clock64());
 }
 
 __device__ __forceinline__ void clock_end(unsigned long long *tc)
 {
     if (tc) {   // workgroup-uniform
         __syncthreads();
-        if (threadIdx.x == 0) tc[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
+        if (threadIdx.x == 0) put<false>(tc + 2 * blockIdx.x + 1, (unsigned long long)wall_clock64());
     }
 }
 
@@ -722,7 +807,7 @@ __device__ __forceinline__ void pair_p1_f64(const double *T, const double *S, in
 // chunk repeat its first lane (valid loads) and store nothing; a wavefront
 // with no valid lane skips the arithmetic.
 
-template <int OP, int Q, bool ROWFIX>
+template <int OP, int Q, bool ROWFIX, bool SYS = false>
 __device__ __forceinline__ void p0_body_f32(const ReqDev &R, const EntryBlock &B)
 {
     const int4 ch = B.chunk;   // first lane, lanes, first dof, dofs
@@ -744,14 +829,14 @@ __device__ __forceinline__ void p0_body_f32(const ReqDev &R, const EntryBlock &B
         vr *= sc;
         vi *= sc;
     } else if (act && R.near_error) {
-        *R.status = 1;
+        put<SYS>(R.status, 1);
     }
     if (act) {
         const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)(ch.z + t) * R.sl;
         if constexpr (is_cplx<OP>())
-            reinterpret_cast<float2 *>(R.out)[o] = make_float2(vr, vi);
+            put<SYS>(reinterpret_cast<float2 *>(R.out) + o, make_float2(vr, vi));
         else
-            reinterpret_cast<float *>(R.out)[o] = vr;
+            put<SYS>(reinterpret_cast<float *>(R.out) + o, vr);
     }
 }
 
@@ -771,7 +856,7 @@ __global__ __launch_bounds__(kBlockLanes) void k_p0_f32(const ReqDev *__restrict
     clock_end(tclock);
 }
 
-template <int OP, int Q, bool ROWFIX>
+template <int OP, int Q, bool ROWFIX, bool SYS = false>
 __device__ __forceinline__ void p0_body_f64(const ReqDev &R, const EntryBlock &B)
 {
     const int4 ch = B.chunk;
@@ -793,14 +878,14 @@ __device__ __forceinline__ void p0_body_f64(const ReqDev &R, const EntryBlock &B
         vr *= sc;
         vi *= sc;
     } else if (act && R.near_error) {
-        *R.status = 1;
+        put<SYS>(R.status, 1);
     }
     if (act) {
         const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)(ch.z + t) * R.sl;
         if constexpr (is_cplx<OP>())
-            reinterpret_cast<double2 *>(R.out)[o] = make_double2(vr, vi);
+            put<SYS>(reinterpret_cast<double2 *>(R.out) + o, make_double2(vr, vi));
         else
-            reinterpret_cast<double *>(R.out)[o] = vr;
+            put<SYS>(reinterpret_cast<double *>(R.out) + o, vr);
     }
 }
 
@@ -950,7 +1035,7 @@ __device__ __forceinline__ void combine_groups_f32(const LaneGroups &G, int lane
     __syncthreads();
 }
 
-template <int OP, int Q, bool ROWFIX>
+template <int OP, int Q, bool ROWFIX, bool SYS = false>
 __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B, float (*sG)[nstar32<Q>()], int4 *sV,
                                             int *sL, float4 (*sP)[3])
 {
@@ -999,7 +1084,7 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
         if (!wact) continue;
         for (int s = grp; s < ns; s += G.count) {
             if (share_vertex(sV[s], vn)) {
-                if (act && R.near_error) *R.status = 1;
+                if (act && R.near_error) put<SYS>(R.status, 1);
                 continue;
             }
             constexpr int FW = ROWFIX ? n32<Q>() : nstar32<Q>();
@@ -1064,9 +1149,9 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
         const int32_t dp = R.lpos ? R.lpos[d] : d;   // lane-side output position
         const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)dp * R.sl;
         if constexpr (is_cplx<OP>())
-            reinterpret_cast<float2 *>(R.out)[o] = make_float2(ar + br, ai + bi);
+            put<SYS>(reinterpret_cast<float2 *>(R.out) + o, make_float2(ar + br, ai + bi));
         else
-            reinterpret_cast<float *>(R.out)[o] = ar + br;
+            put<SYS>(reinterpret_cast<float *>(R.out) + o, ar + br);
     }
 }
 
@@ -1091,7 +1176,7 @@ __global__ __launch_bounds__(kBlockLanes) void k_p1_f32(const ReqDev *__restrict
 }
 
 // P1, FP64: the same two phases with plain FP64 sums.
-template <int OP, int Q, bool ROWFIX>
+template <int OP, int Q, bool ROWFIX, bool SYS = false>
 __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B, double (*sG)[n64<Q>()], int4 *sV,
                                             int *sL, double2 (*sP)[3])
 {
@@ -1116,7 +1201,7 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
         if (!wact) continue;
         for (int s = grp; s < ns; s += G.count) {
             if (share_vertex(sV[s], vn)) {
-                if (act && R.near_error) *R.status = 1;
+                if (act && R.near_error) put<SYS>(R.status, 1);
                 continue;
             }
             double F[n64<Q>()];
@@ -1196,9 +1281,9 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
         const int32_t dp = R.lpos ? R.lpos[d] : d;   // lane-side output position
         const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)dp * R.sl;
         if constexpr (is_cplx<OP>())
-            reinterpret_cast<double2 *>(R.out)[o] = make_double2(xr, xi);
+            put<SYS>(reinterpret_cast<double2 *>(R.out) + o, make_double2(xr, xi));
         else
-            reinterpret_cast<double *>(R.out)[o] = xr;
+            put<SYS>(reinterpret_cast<double *>(R.out) + o, xr);
     }
 }
 
@@ -1220,6 +1305,332 @@ __global__ __launch_bounds__(kBlockLanes) void k_p1_f64(const ReqDev *__restrict
     else
         p1_body_f64<OP, Q, false>(R, B, sG, sV, sL, sP);
     clock_end(tclock);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent launches (layout and protocol in bem_internal.hpp).
+//
+// Words shared between workgroups are read and written with relaxed atomics
+// at device scope, host words at system scope: those accesses go to the
+// point of coherence instead of a cache that may hold an older copy, and
+// they carry no cache invalidation or writeback, which would cost the
+// geometry its L2 residency.  Order comes from two rules: a load that
+// depends on another is issued only after that one has returned (its value
+// decides whether it is issued), and a word that publishes data is stored
+// only after the stores of that data have completed (wait_memory).  Results
+// reach host memory through put<true>(), so a batch's completion word can follow
+// its entries while the launch runs on.
+
+__device__ __forceinline__ uint64_t claim_word(uint64_t seq, int64_t nblk)
+{
+    return ((seq & 0xffffull) << 48) | ((uint64_t)nblk << 32);
+}
+
+// The watching thread: copies each published ring entry to device memory,
+// then makes its blocks claimable; ends on the host's stop word or after
+// idle_ticks without a new entry.
+__device__ void persist_watch(const PersistArgs &a)
+{
+    uint64_t seq = a.seq0;
+    uint64_t last = wall_clock64();
+    for (;;) {
+        const PersistEntry *e = &a.host->ring[seq % kPersistRing];
+        if (ld_sys(&e->seq1) == seq + 1) {
+            PersistItem *d = &a.ctl->item[seq % kPersistRing];
+            const int64_t nb = ld_sys(&e->nblk);
+            st_dev(reinterpret_cast<uint64_t *>(&d->reqs), reinterpret_cast<uint64_t>(ld_ptr_sys(&e->reqs)));
+            st_dev(reinterpret_cast<uint64_t *>(&d->blocks), reinterpret_cast<uint64_t>(ld_ptr_sys(&e->blocks)));
+            st_dev(reinterpret_cast<uint64_t *>(&d->clock), reinterpret_cast<uint64_t>(ld_ptr_sys(&e->clock)));
+            st_dev(&d->nblk, nb);
+            wait_memory();   // the entry is in place before its blocks can be claimed
+            st_dev(&a.ctl->claim[seq % kPersistRing][0], (unsigned long long)claim_word(seq, nb));
+            ++seq;
+            last = wall_clock64();
+            continue;
+        }
+        if (ld_sys(&a.host->stop) >= a.id || (long long)(wall_clock64() - last) > a.idle_ticks) break;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    st_dev(&a.ctl->stop, 1u);
+    wait_memory();
+    st_sys(a.exit_word, (a.id << 40) | (seq + 1));
+}
+
+// What a workgroup works on (LDS, written by thread 0).  The records are
+// kept as 64-bit words, the form they are read in, and decoded with memcpy.
+struct PersistBlock {
+    uint64_t R[sizeof(ReqDev) / 8];
+    uint64_t B[sizeof(EntryBlock) / 8];
+    unsigned long long *clock;
+    int64_t idx, nblk;
+    uint64_t seq;
+    int go;
+};
+static_assert(sizeof(ReqDev) % 8 == 0 && sizeof(EntryBlock) % 8 == 0, "records are read in 8-byte words");
+static_assert(offsetof(EntryBlock, req) == 0, "the request index is the block record's first word");
+
+// Workgroup-uniform copy of a record held in LDS words (32-bit halves
+// through readfirstlane, so the per-block code keeps its scalar addressing).
+template <typename T>
+__device__ __forceinline__ T uniform_copy(const uint64_t *src)
+{
+    constexpr int n = (int)(sizeof(T) / 4);
+    int u[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        const uint64_t wv = src[i / 2];
+        u[i] = __builtin_amdgcn_readfirstlane((int)(uint32_t)((i & 1) ? (wv >> 32) : wv));
+    }
+    T out;
+    __builtin_memcpy(&out, u, sizeof(T));
+    return out;
+}
+
+// Claims the next block for the workgroup, oldest batch first from the
+// workgroup's cursor *c (LDS, thread 0's), and reads its block record and
+// request descriptor from the host-coherent staging into w.  False (for the
+// whole workgroup) once the launch is ending.
+__device__ bool persist_claim(const PersistArgs &a, uint64_t *cp, PersistBlock &w)
+{
+    if (threadIdx.x == 0) {
+        int go = 1;
+        uint64_t c = *cp, s = 0;
+        int64_t idx = 0, nb = 0;
+        for (;;) {
+            unsigned long long *cw = &a.ctl->claim[c % kPersistRing][0];
+            const uint64_t v = __hip_atomic_fetch_add(cw, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // the batch this claim belongs to: c + ds (ds < 0: an earlier batch
+            // still holds the entry, batch c is not published yet)
+            const int64_t ds = (int16_t)(uint16_t)((v >> 48) - (c & 0xffff));
+            idx = (int64_t)(v & 0xffffffffull);
+            nb = (int64_t)((v >> 32) & 0xffff);
+            if (ds >= 0) {
+                s = c + (uint64_t)ds;
+                if (idx < nb) break;   // block idx of batch s
+                // batch s has no unclaimed block: step on (an entry that holds a
+                // later batch than c means batch c ended long ago)
+                if (s == c) {
+                    unsigned long long cur = c;
+                    __hip_atomic_compare_exchange_strong(&a.ctl->cur, &cur, (unsigned long long)(c + 1),
+                                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                }
+                ++c;
+                const uint64_t cur = ld_dev(&a.ctl->cur);
+                if (cur > c) c = cur;
+                continue;
+            }
+            // batch c is not published yet: wait for it, for the cursor to pass
+            // it or for the end of the launch (the claim word every round, the
+            // other two every eighth)
+            for (int round = 1;; ++round) {
+                if ((uint16_t)(ld_dev(cw) >> 48) == (uint16_t)(c & 0xffff)) break;
+                if ((round & 7) == 0) {
+                    const uint64_t cur = ld_dev(&a.ctl->cur);
+                    if (cur > c) {
+                        c = cur;
+                        break;
+                    }
+                    if (ld_dev(&a.ctl->stop) != 0u) {
+                        go = 0;
+                        break;
+                    }
+                }
+                __builtin_amdgcn_s_sleep(24);
+            }
+            if (!go) break;
+        }
+        *cp = c;
+        w.go = go;
+        if (go) {
+            const PersistItem *it = &a.ctl->item[s % kPersistRing];
+            const EntryBlock *blocks = ld_ptr_dev(&it->blocks);
+            const ReqDev *reqs = ld_ptr_dev(&it->reqs);
+            w.clock = ld_ptr_dev(&it->clock);
+            w.idx = idx;
+            w.nblk = nb;
+            w.seq = s;
+            // the block record, then its request's descriptor: all words of a
+            // record in flight together, stored to LDS once they have arrived
+            constexpr int nb8 = (int)(sizeof(EntryBlock) / 8), nr8 = (int)(sizeof(ReqDev) / 8);
+            const uint64_t *bs = reinterpret_cast<const uint64_t *>(blocks + idx);
+            uint64_t bw[nb8], rw[nr8];
+#pragma unroll
+            for (int i = 0; i < nb8; ++i) bw[i] = ld_sys(bs + i);
+            const int32_t req = (int32_t)(uint32_t)bw[0];   // EntryBlock::req, the record's first word
+            const uint64_t *rs = reinterpret_cast<const uint64_t *>(reqs + (req >> 1));
+#pragma unroll
+            for (int i = 0; i < nr8; ++i) rw[i] = ld_sys(rs + i);
+#pragma unroll
+            for (int i = 0; i < nb8; ++i) w.B[i] = bw[i];
+#pragma unroll
+            for (int i = 0; i < nr8; ++i) w.R[i] = rw[i];
+            if (w.clock) put<true>(w.clock + 2 * idx, (unsigned long long)wall_clock64());
+        }
+    }
+    __syncthreads();
+    return w.go != 0;
+}
+
+// After a block: once every thread's entries and status words are written,
+// the block counts as finished; the last block of a batch stores the
+// batch's completion word.
+__device__ void persist_finish(const PersistArgs &a, PersistBlock &w)
+{
+    wait_memory();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t s = w.seq;
+        if (w.clock) put<true>(w.clock + 2 * w.idx + 1, (unsigned long long)wall_clock64());
+        wait_memory();
+        unsigned int *cnt = &a.ctl->done[s % kPersistRing][0];
+        const unsigned int n = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int64_t)n + 1 == w.nblk) {
+            st_dev(cnt, 0u);
+            wait_memory();
+            st_sys(&a.done[8 * (s % kPersistRing)], s + 1);
+        }
+    }
+}
+
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void kp_p0_f32(PersistArgs a)
+{
+    __shared__ PersistBlock w;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) persist_watch(a);
+        return;
+    }
+    __shared__ uint64_t cursor;   // thread 0's, kept out of registers across the block's code
+    if (threadIdx.x == 0) cursor = a.seq0;
+    while (persist_claim(a, &cursor, w)) {
+        const EntryBlock B = uniform_copy<EntryBlock>(w.B);
+        const ReqDev R = uniform_copy<ReqDev>(w.R);
+        if (B.req & 1)
+            p0_body_f32<OP, Q, true, true>(R, B);
+        else
+            p0_body_f32<OP, Q, false, true>(R, B);
+        persist_finish(a, w);
+    }
+}
+
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void kp_p0_f64(PersistArgs a)
+{
+    __shared__ PersistBlock w;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) persist_watch(a);
+        return;
+    }
+    __shared__ uint64_t cursor;   // thread 0's, kept out of registers across the block's code
+    if (threadIdx.x == 0) cursor = a.seq0;
+    while (persist_claim(a, &cursor, w)) {
+        const EntryBlock B = uniform_copy<EntryBlock>(w.B);
+        const ReqDev R = uniform_copy<ReqDev>(w.R);
+        if (B.req & 1)
+            p0_body_f64<OP, Q, true, true>(R, B);
+        else
+            p0_body_f64<OP, Q, false, true>(R, B);
+        persist_finish(a, w);
+    }
+}
+
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void kp_p1_f32(PersistArgs a)
+{
+    __shared__ float sG[kStage][nstar32<Q>()];
+    __shared__ int4 sV[kStage];
+    __shared__ int sL[kStage];
+    __shared__ float4 sP[kBlockLanes][3];
+    __shared__ PersistBlock w;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) persist_watch(a);
+        return;
+    }
+    __shared__ uint64_t cursor;   // thread 0's, kept out of registers across the block's code
+    if (threadIdx.x == 0) cursor = a.seq0;
+    while (persist_claim(a, &cursor, w)) {
+        const EntryBlock B = uniform_copy<EntryBlock>(w.B);
+        const ReqDev R = uniform_copy<ReqDev>(w.R);
+        if (B.req & 1)
+            p1_body_f32<OP, Q, true, true>(R, B, sG, sV, sL, sP);
+        else
+            p1_body_f32<OP, Q, false, true>(R, B, sG, sV, sL, sP);
+        persist_finish(a, w);
+    }
+}
+
+template <int OP, int Q>
+__global__ __launch_bounds__(kBlockLanes) void kp_p1_f64(PersistArgs a)
+{
+    __shared__ double sG[kStage][n64<Q>()];
+    __shared__ int4 sV[kStage];
+    __shared__ int sL[kStage];
+    __shared__ double2 sP[kBlockLanes][3];
+    __shared__ PersistBlock w;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) persist_watch(a);
+        return;
+    }
+    __shared__ uint64_t cursor;   // thread 0's, kept out of registers across the block's code
+    if (threadIdx.x == 0) cursor = a.seq0;
+    while (persist_claim(a, &cursor, w)) {
+        const EntryBlock B = uniform_copy<EntryBlock>(w.B);
+        const ReqDev R = uniform_copy<ReqDev>(w.R);
+        if (B.req & 1)
+            p1_body_f64<OP, Q, true, true>(R, B, sG, sV, sL, sP);
+        else
+            p1_body_f64<OP, Q, false, true>(R, B, sG, sV, sL, sP);
+        persist_finish(a, w);
+    }
+}
+
+// Resets the control block of a launch that starts at sequence number seq0:
+// no batch claimable (every entry tagged with an earlier batch), nothing
+// finished.  One workgroup of kPersistRing threads.
+__global__ void k_persist_reset(PersistCtl *ctl, uint64_t seq0)
+{
+    const int i = threadIdx.x;
+    if (i == 0) {
+        ctl->cur = seq0;
+        ctl->stop = 0u;
+    }
+    if (i < kPersistRing) {
+        ctl->claim[i][0] = claim_word(seq0 - 1, 0);
+        ctl->done[i][0] = 0u;
+    }
+}
+
+typedef void (*PersistKernel)(PersistArgs);
+
+template <int OP, int Q>
+PersistKernel pick_persist(int space, int prec)
+{
+    if constexpr (is_hyp<OP>()) {
+        if (space == BEM_P0) return nullptr;
+    } else {
+        if (space == BEM_P0) return prec == BEM_FP32 ? kp_p0_f32<OP, Q> : kp_p0_f64<OP, Q>;
+    }
+    return prec == BEM_FP32 ? kp_p1_f32<OP, Q> : kp_p1_f64<OP, Q>;
+}
+
+template <int OP>
+PersistKernel pick_persist_q(int space, int prec, int q)
+{
+    return q == 6 ? pick_persist<OP, 6>(space, prec) : pick_persist<OP, 4>(space, prec);
+}
+
+PersistKernel select_persist(const Variant &v)
+{
+    switch (v.op) {
+    case LSLP: return pick_persist_q<LSLP>(v.space, v.prec, v.q);
+    case LDLP: return pick_persist_q<LDLP>(v.space, v.prec, v.q);
+    case HSLP: return pick_persist_q<HSLP>(v.space, v.prec, v.q);
+    case HDLP: return pick_persist_q<HDLP>(v.space, v.prec, v.q);
+    case LHYP: return pick_persist_q<LHYP>(v.space, v.prec, v.q);
+    case HHYP: return pick_persist_q<HHYP>(v.space, v.prec, v.q);
+    default: return nullptr;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1600,6 +2011,30 @@ hipError_t launch_entries(const Variant &v, const ReqDev *reqs, const EntryBlock
     else
         hipLaunchKernelGGL(k, dim3((unsigned)nblocks), dim3(kBlockLanes), 0, s, reqs, blocks, nblocks, tclock);
     return hipGetLastError();
+}
+
+hipError_t launch_persistent(const Variant &v, const PersistArgs &a, int groups, hipStream_t s, hipEvent_t start,
+                             hipEvent_t stop)
+{
+    const PersistKernel k = select_persist(v);
+    if (!k || groups < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_persist_reset, dim3(1), dim3(kPersistRing), 0, s, a.ctl, a.seq0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (start || stop)
+        hipExtLaunchKernelGGL(k, dim3((unsigned)groups), dim3(kBlockLanes), 0, s, start, stop, 0, a);
+    else
+        hipLaunchKernelGGL(k, dim3((unsigned)groups), dim3(kBlockLanes), 0, s, a);
+    return hipGetLastError();
+}
+
+int persistent_occupancy(const Variant &v)
+{
+    const PersistKernel k = select_persist(v);
+    if (!k) return 0;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, kBlockLanes, 0) != hipSuccess) return 0;
+    return n;
 }
 
 }  // namespace bem
