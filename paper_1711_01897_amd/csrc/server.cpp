@@ -765,6 +765,22 @@ public:
         return true;
     }
 
+    // Closes the open batch o (mu held): the next submissions go to a new
+    // open batch if a slot is free and nothing is queued; if reservations of
+    // o are still being written, the last writer launches it.
+    void close_open_locked(Open *o, double t)
+    {
+        open = nullptr;
+        o->t_close = t;
+        o->closed = true;
+        const int fs = free_slot();
+        if (fs >= 0 && pending.empty()) {
+            open = new Open();
+            open->b = new_fast_batch(fs);
+            slot_busy[fs] = true;
+        }
+    }
+
     // Launches a closed fast batch whose reservations are all written and
     // hands it to the completion thread.
     void launch_closed(Open *fo)
@@ -890,14 +906,7 @@ public:
                 }
                 if (fo && !stop) {
                     // the next open batch, if a slot is free and nothing is queued
-                    const int fs = free_slot();
-                    if (fs >= 0 && pending.empty()) {
-                        open = new Open();
-                        open->b = new_fast_batch(fs);
-                        slot_busy[fs] = true;
-                    }
-                    fo->t_close = now_seconds();
-                    fo->closed = true;
+                    close_open_locked(fo, now_seconds());
                     const bool ready = fo->writers == 0;
                     lk.unlock();
                     // reservations still being written: their last writer launches the batch
