@@ -26,6 +26,9 @@
 #include <cmath>
 #include <complex>
 #include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
 #include <vector>
 
 namespace bem {
@@ -38,6 +41,47 @@ double aca_dot(const double *x, const double *y, int64_t n);
 std::complex<double> aca_dot(const std::complex<double> *x, const std::complex<double> *y, int64_t n);
 double aca_norm2(const double *x, int64_t n);
 double aca_norm2(const std::complex<double> *x, int64_t n);
+
+// Growable column store for U or V: the residual row or column of each step
+// is formed in place as the next column, without a copy (a std::vector would
+// zero or copy it), and growth does not initialise.  Elements are trivially
+// copyable (double, std::complex<double>).
+template <typename T>
+class AcaBuf {
+public:
+    AcaBuf() = default;
+    AcaBuf(const AcaBuf &) = delete;
+    AcaBuf &operator=(const AcaBuf &) = delete;
+    ~AcaBuf() { std::free(p_); }
+    void clear() { n_ = 0; }
+    void reserve(size_t c)
+    {
+        if (c <= cap_) return;
+        // a new block and a copy of the elements held (realloc would copy the
+        // whole old block)
+        T *q = static_cast<T *>(std::malloc(c * sizeof(T)));
+        if (!q) throw std::bad_alloc();
+        if (n_) std::memcpy(q, p_, n_ * sizeof(T));
+        std::free(p_);
+        p_ = q;
+        cap_ = c;
+    }
+    // size n, new elements uninitialised
+    void resize_uninit(size_t n)
+    {
+        if (n > cap_) reserve(std::max(n, 2 * cap_));
+        n_ = n;
+    }
+    size_t size() const { return n_; }
+    T *data() { return p_; }
+    const T *data() const { return p_; }
+    T &operator[](size_t i) { return p_[i]; }
+    const T &operator[](size_t i) const { return p_[i]; }
+
+private:
+    T *p_ = nullptr;
+    size_t n_ = 0, cap_ = 0;
+};
 
 inline double abs2(double x) { return x * x; }
 inline double abs2(const std::complex<double> &x) { return x.real() * x.real() + x.imag() * x.imag(); }
@@ -52,9 +96,8 @@ struct AcaCore {
     int64_t m = 0, n = 0;
     double tol = 1e-5, zero_abs = 0.0;
     int max_rank = 0, limit = 0;
-    std::vector<T> U, V;   // column l of U at U[l*m], of V at V[l*n]
-    std::vector<T> v;      // current residual row
-    std::vector<T> u;      // current residual column
+    AcaBuf<T> U, V;        // column l of U at U[l*m], of V at V[l*n]; the current residual
+                           // row is formed as column k of V, the residual column as column k of U
     std::vector<char> used;
     int64_t nused = 0;
     int k = 0;
@@ -87,8 +130,11 @@ struct AcaCore {
     template <typename In>
     void consume_row(const In *row)
     {
-        v.assign(row, row + n);
-        for (int l = 0; l < k; ++l) aca_axpy(v.data(), &V[(size_t)l * n], U[(size_t)l * m + i], n);
+        const size_t base = (size_t)k * (size_t)n;
+        V.resize_uninit(base + (size_t)n);
+        T *v = V.data() + base;
+        for (int64_t c = 0; c < n; ++c) v[c] = T(row[c]);
+        for (int l = 0; l < k; ++l) aca_axpy(v, V.data() + (size_t)l * n, U[(size_t)l * m + i], n);
         if (!used[i]) {
             used[i] = 1;
             ++nused;
@@ -103,6 +149,7 @@ struct AcaCore {
             }
         }
         if (!(std::sqrt(amax2) > zero_abs)) {
+            V.resize_uninit(base);   // the row is not kept
             if (nused == m || k > 0) {
                 phase = DONE;
                 return;
@@ -125,20 +172,22 @@ struct AcaCore {
     template <typename In>
     void consume_col(const In *col)
     {
-        u.assign(col, col + m);
-        for (int l = 0; l < k; ++l) aca_axpy(u.data(), &U[(size_t)l * m], V[(size_t)l * n + j], m);
+        const size_t base = (size_t)k * (size_t)m;
+        U.resize_uninit(base + (size_t)m);
+        T *u = U.data() + base;
+        const T *v = V.data() + (size_t)k * n;   // the scaled residual row of this step
+        for (int64_t r = 0; r < m; ++r) u[r] = T(col[r]);
+        for (int l = 0; l < k; ++l) aca_axpy(u, U.data() + (size_t)l * m, V[(size_t)l * n + j], m);
         double cross = 0.0;
         for (int l = 0; l < k; ++l) {
-            const T du = aca_dot(&U[(size_t)l * m], u.data(), m);
-            const T dv = aca_dot(&V[(size_t)l * n], v.data(), n);
+            const T du = aca_dot(U.data() + (size_t)l * m, u, m);
+            const T dv = aca_dot(V.data() + (size_t)l * n, v, n);
             cross += re_of(du * dv);
         }
-        const double su = aca_norm2(u.data(), m), sv = aca_norm2(v.data(), n);
+        const double su = aca_norm2(u, m), sv = aca_norm2(v, n);
         const double nu = std::sqrt(su), nv = std::sqrt(sv);
         norm2 = norm2 + 2.0 * cross + (nu * nv) * (nu * nv);
-        U.insert(U.end(), u.begin(), u.end());
-        V.insert(V.end(), v.begin(), v.end());
-        ++k;
+        ++k;   // u and v are column k - 1 of U and V
         if (nu * nv <= tol * std::sqrt(std::max(norm2, 0.0))) {
             phase = DONE;
             return;

@@ -225,17 +225,17 @@ void to_scalar<cd>(const void *src, int prec, int64_t n, cd *dst)
 }
 
 template <typename T>
-void store_cols(const std::vector<T> &src, int k, int64_t len, int64_t cap, void *dst);
+void store_cols(const AcaBuf<T> &src, int k, int64_t len, int64_t cap, void *dst);
 
 template <>
-void store_cols<double>(const std::vector<double> &src, int k, int64_t len, int64_t cap, void *dst)
+void store_cols<double>(const AcaBuf<double> &src, int k, int64_t len, int64_t cap, void *dst)
 {
     (void)cap;
     std::memcpy(dst, src.data(), sizeof(double) * len * k);
 }
 
 template <>
-void store_cols<cd>(const std::vector<cd> &src, int k, int64_t len, int64_t cap, void *dst)
+void store_cols<cd>(const AcaBuf<cd> &src, int k, int64_t len, int64_t cap, void *dst)
 {
     (void)cap;
     std::memcpy(dst, src.data(), sizeof(cd) * len * k);

@@ -33,6 +33,7 @@
 #include <cstdlib>
 #include <deque>
 #include <map>
+#include <new>
 #include <thread>
 
 #include <immintrin.h>
@@ -114,6 +115,29 @@ struct Batch {
     int64_t entries = 0, evals = 0;
     std::atomic<int> refs{1};     // completion thread + borrowed results
     bool timed = false;           // per-launch events recorded
+
+    // Back to a fresh batch, keeping the vectors' capacity.
+    void reset()
+    {
+        std::vector<Request *> r;
+        std::vector<FastGroup> g;
+        std::vector<Launch> l;
+        std::vector<hipEvent_t> e;
+        r.swap(reqs);
+        g.swap(groups);
+        l.swap(launches);
+        e.swap(ev);
+        this->~Batch();
+        new (this) Batch();
+        r.clear();
+        g.clear();
+        l.clear();
+        e.clear();
+        reqs.swap(r);
+        groups.swap(g);
+        launches.swap(l);
+        ev.swap(e);
+    }
 };
 
 // Per dispatcher thread: group member lists, reused across batches.
@@ -227,6 +251,8 @@ public:
     int p_occ[kKeys] = {};             // resident workgroups per compute unit (-1: none)
 
     std::deque<Batch *> inflight;
+    std::mutex pool_mu;
+    std::vector<Batch *> batch_pool;   // reset batch records for reuse
     bool slot_busy[kMaxSlots] = {};
     bool started = false, stop = false;
     int device = 0;
@@ -806,9 +832,33 @@ public:
         cvc.notify_one();
     }
 
+    // Batch records are reused.  A fast batch reserves room for up to 8,192
+    // request pointers; allocating that per batch and freeing it on another
+    // thread made the allocator grow and shrink its heaps with mprotect and
+    // munmap, system calls that interrupt every core the process runs on.
+    Batch *take_batch()
+    {
+        {
+            std::lock_guard<std::mutex> g(pool_mu);
+            if (!batch_pool.empty()) {
+                Batch *b = batch_pool.back();
+                batch_pool.pop_back();
+                return b;
+            }
+        }
+        return new Batch();
+    }
+
+    void give_batch(Batch *b)
+    {
+        b->reset();
+        std::lock_guard<std::mutex> g(pool_mu);
+        batch_pool.push_back(b);
+    }
+
     Batch *new_fast_batch(int slot)
     {
-        Batch *b = new Batch();
+        Batch *b = take_batch();
         b->slot = slot;
         b->fast = true;
         b->hb = h_stage + (size_t)slot * slot_bytes;
@@ -964,7 +1014,7 @@ public:
 
     Batch *build_and_launch(int slot, std::vector<Request *> &take, Scratch &sc)
     {
-        Batch *b = new Batch();
+        Batch *b = take_batch();
         b->slot = slot;
         b->reqs = take;
         char *hb = h_stage + (size_t)slot * slot_bytes;
@@ -1202,7 +1252,7 @@ public:
             slot_busy[b->slot] = false;
         }
         cv.notify_one();
-        delete b;
+        give_batch(b);
     }
 
     void complete_loop()
@@ -1409,7 +1459,7 @@ public:
                 if (streams[i]) (void)hipStreamDestroy(streams[i]);
             for (int i = 0; i < kMaxSlots; ++i) streams[i] = nullptr;
             if (open) {   // empty (checked above)
-                delete open->b;
+                give_batch(open->b);
                 delete open;
                 open = nullptr;
             }
