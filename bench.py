@@ -379,6 +379,8 @@ def cpu_hmatrix(inputs, xyz, tri, ops, fraction, tol=1e-5, max_rank=200):
     nodes, leaves = otree.partition(xyz, tri, oracle.P1, 100, 1.0)
     t_part = time.perf_counter() - t0
     adm = [(t, s) for t, s, a in leaves if a]
+    if not adm:
+        raise ValueError("the partition has no admissible block")
     rng = inputs.rng(inputs.SEED_SAMPLING)
     pick = rng.choice(len(adm), size=max(1, int(round(fraction * len(adm)))), replace=False)
     mn_all = float(sum(nodes[t].idx.size + nodes[s].idx.size for t, s in adm))
@@ -804,6 +806,17 @@ def cylinder_cpu_baseline(bem, inputs, plan, mesh, xyz, tri, seconds):
             "one_core_value": one_rate, "host": cores}, worst
 
 
+def kernel_entries_rate(kstats):
+    """Entries per second of entry-kernel time (HIP-event launch brackets) of
+    the variant with the most device time: the GPU path's own rate, apart
+    from the host loop around it."""
+    main = [k for k in kstats if not k.get("persistent")]
+    if not main:
+        return None
+    dom = max(main, key=lambda k: k["seconds"])
+    return dom["entries"] / dom["seconds_events"] if dom["seconds_events"] > 0 else None
+
+
 def cylinder_main(args):
     import numpy as np
     from paper_1711_01897_amd import bem, inputs
@@ -831,6 +844,10 @@ def cylinder_main(args):
                                     "latency_p50_ms", "latency_p99_ms", "capacity_entries_per_s",
                                     "arrival_rate_blocks_per_s", "latency_vs_load")}
         fp64["unit"] = "entries/s"
+        fp64["kernel_entries_per_s"] = kernel_entries_rate(f64["kst"])
+    kernel_rate = {"fp32": kernel_entries_rate(f32["kst"]), "fp64": fp64["kernel_entries_per_s"] if fp64 else None}
+    if kernel_rate["fp32"] and kernel_rate["fp64"]:
+        kernel_rate["fp32_over_fp64"] = kernel_rate["fp32"] / kernel_rate["fp64"]
     cpu, worst = (None, None)
     if not args.no_cpu_baseline:
         cpu, worst = cylinder_cpu_baseline(bem, inputs, plan, mesh, xyz, tri, args.cpu_seconds)
@@ -867,6 +884,7 @@ def cylinder_main(args):
                                     for k in ("queue", "stage", "device", "complete")},
         "kernel_busy_fraction": sst["kernel_seconds"] / f32["wall"] if f32["wall"] > 0 else None,
         "fp64": fp64, "fp32_over_fp64": (f32["value"] / fp64["value"]) if fp64 else None,
+        "kernel_entries_per_s": kernel_rate,
         "max_rel_err_sampled": worst, "gpu_telemetry": f32["telemetry"],
         "host_cpu": dict(f32["host_cpu"], **host_cores()),
         "roofline": roof, "cpu_baseline": cpu,
@@ -919,6 +937,8 @@ def spheroid_main(args):
                      "latency_p50_ms": sst["latency_p50"] * 1e3, "latency_p99_ms": sst["latency_p99"] * 1e3,
                      "kst": bem.server_kernel_stats()}
         print(f"[bench] spheroid prec {prec}: median {res[prec]['seconds_median']:.3f} s", file=sys.stderr, flush=True)
+    for prec in (bem.FP32, bem.FP64):
+        res[prec]["kernel_entries_per_s"] = kernel_entries_rate(res[prec]["kst"])
     roof, _ = roofline(res[bem.FP32].pop("kst"), "spheroid")
     res[bem.FP64].pop("kst")
     f32, f64 = res[bem.FP32], res[bem.FP64]
@@ -1135,7 +1155,7 @@ def main():
                 "aca_entries_per_step": tot64["entries"] // args.steps,
                 "aca_requests_per_step": tot64["requests"] // args.steps,
                 "latency_p50_ms": sst64["latency_p50"] * 1e3, "latency_p99_ms": sst64["latency_p99"] * 1e3,
-                "rank_sum": tot64["rank_sum"] // args.steps}
+                "rank_sum": tot64["rank_sum"] // args.steps, "kernel_entries_per_s": kernel_entries_rate(kst64)}
         print(f"[bench] fp64: {args.steps} steps in {dt64:.3f} s", file=sys.stderr, flush=True)
 
     cpu = None
@@ -1193,6 +1213,7 @@ def main():
         "kernel_busy_fraction": sst["kernel_seconds"] / dt if dt > 0 else None,
         "fp64": fp64,
         "fp32_over_fp64": (value / fp64["value"]) if fp64 else None,
+        "kernel_entries_per_s": kernel_entries_rate(kst),
         "max_rel_err_sampled": worst,
         "roofline": roof,
         "cpu_baseline": cpu,
