@@ -78,6 +78,36 @@ __device__ __forceinline__ P ld_ptr_dev(P const *p)
 {
     return reinterpret_cast<P>(ld_dev(reinterpret_cast<const uint64_t *>(p)));
 }
+// Loads and stores through global rather than generic pointers.  The
+// records, tables and outputs these kernels touch are device or
+// host-coherent memory reached through generic pointers, which compile to
+// flat accesses; a flat access also counts against the LDS wait counter, so
+// every wait for an LDS access (or for a scalar load) would wait for it too.
+// The vector types keep the accesses in the global address space (a struct
+// copy would go back through a generic reference).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ldg(const float4 *p)
+{
+    const f32x4 v = *(const __attribute__((address_space(1))) f32x4 *)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int4 ldg(const int4 *p)
+{
+    const i32x4 v = *(const __attribute__((address_space(1))) i32x4 *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int32_t ldg(const int32_t *p) { return *(const __attribute__((address_space(1))) int32_t *)p; }
+__device__ __forceinline__ void stg(float *p, float v) { *(__attribute__((address_space(1))) float *)p = v; }
+__device__ __forceinline__ void stg(float2 *p, float2 v)
+{
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    f32x2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *(__attribute__((address_space(1))) f32x2 *)p = w;
+}
+
 // Waits until this wavefront's vector memory operations, stores included
 // (gfx9 counts both in vmcnt), have completed; also a compiler barrier.
 __device__ __forceinline__ void wait_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
@@ -92,7 +122,7 @@ template <bool SYS>
 __device__ __forceinline__ void put(float *p, float v)
 {
     if constexpr (SYS) st_sys(reinterpret_cast<uint32_t *>(p), __float_as_uint(v));
-    else *p = v;
+    else stg(p, v);
 }
 template <bool SYS>
 __device__ __forceinline__ void put(double *p, double v)
@@ -104,7 +134,7 @@ template <bool SYS>
 __device__ __forceinline__ void put(float2 *p, float2 v)
 {
     if constexpr (SYS) st_sys(reinterpret_cast<uint64_t *>(p), ((uint64_t)__float_as_uint(v.y) << 32) | __float_as_uint(v.x));
-    else *p = v;
+    else stg(p, v);
 }
 template <bool SYS>
 __device__ __forceinline__ void put(double2 *p, double2 v)
@@ -193,7 +223,7 @@ template <int Q>
 __device__ __forceinline__ void load32(const float *__restrict__ g, int t, float *v)
 {
     const float4 *p = reinterpret_cast<const float4 *>(g + (size_t)t * kGeo32Stride);
-    expand32<Q>(p[0], p[1], p[2], p[3], v);
+    expand32<Q>(ldg(p), ldg(p + 1), ldg(p + 2), ldg(p + 3), v);
 }
 
 template <int Q>
@@ -929,39 +959,65 @@ __device__ __forceinline__ int stage_star(const ReqDev &R, const R_T *__restrict
     return ns;
 }
 
+// The request fields that phase 2 of a P1 block uses: segment lists, output
+// positions, output address and strides.  A block reads them all at its
+// start, together with its first loads: the descriptor of a direct batch
+// sits in host memory, and a read at each point of use would add a host-link
+// round trip to the path of every workgroup.
+struct Phase2Req {
+    const int32_t *seg_ptr, *seg, *lpos;
+    void *out;
+    int64_t sf, sl;
+    __device__ __forceinline__ explicit Phase2Req(const ReqDev &R)
+        : seg_ptr(R.seg_ptr), seg(R.seg), lpos(R.lpos), out(R.out), sf(R.sf), sl(R.sl)
+    {
+    }
+};
+
 // The first kN segments of thread t's first entry (dof ch.z + t of the
 // chunk), loaded ahead of use.
 struct SegPrefetch {
     static constexpr int kN = 8;
     int g0 = 0, g1 = 0;
     int seg[kN];
-    __device__ __forceinline__ void fetch(const ReqDev &R, const int4 &ch, int t)
+    __device__ __forceinline__ void fetch(const Phase2Req &P, const int4 &ch, int t)
     {
         if (t >= ch.w) return;
         const int d = ch.z + t;
-        g0 = R.seg_ptr[d];
-        g1 = R.seg_ptr[d + 1];
+        g0 = ldg(P.seg_ptr + d);
+        g1 = ldg(P.seg_ptr + d + 1);
 #pragma unroll
-        for (int i = 0; i < kN; ++i) seg[i] = g0 + i < g1 ? R.seg[g0 + i] : 0;
+        for (int i = 0; i < kN; ++i) seg[i] = g0 + i < g1 ? ldg(P.seg + g0 + i) : 0;
     }
 };
 
-// Stages up to kStage star entries [sb, ...) of the mesh star table into LDS
-// from the gathered star records of block B (FP32).  A trial-side star
-// (TRIAL) is staged in the nstar32 layout: offsets scaled by -2 (exact) and
-// |o_q|^2 appended; a test-side star as the plain record.
+// Star records of the fixed side, staged kStage entries at a time: thread
+// t < ns loads entry sb + t of block B's star table into registers
+// (load_star), then, once the previous stage has been read, expands it into
+// LDS (put_star).  A trial-side star (TRIAL) is staged in the nstar32 layout:
+// offsets scaled by -2 (exact) and |o_q|^2 appended; a test-side star as the
+// plain record.  Loading apart from storing lets the first stage's loads be
+// issued together with the lane records.
+struct StarRec {
+    float4 r0, r1, r2, r3;
+    int4 m;
+};
+
+__device__ __forceinline__ StarRec load_star(const EntryBlock &B, int e)
+{
+    const float4 *p = reinterpret_cast<const float4 *>(B.sgeo + (size_t)e * kGeo32Stride);
+    return StarRec{ldg(p), ldg(p + 1), ldg(p + 2), ldg(p + 3), ldg(B.smeta + e)};
+}
+
 template <int Q, bool TRIAL>
-__device__ __forceinline__ int stage_star_tab(const EntryBlock &B, int sb, int s1, float (*sG)[nstar32<Q>()], int4 *sV,
-                                              int *sL)
+__device__ __forceinline__ void put_star(const StarRec &x, int ns, float (*sG)[nstar32<Q>()], int4 *sV, int *sL)
 {
     constexpr int W = n32<Q>();
     const int t = threadIdx.x;
-    const int ns = min(kStage, s1 - sb);
     __syncthreads();   // the previous stage has been read
     if (t < ns) {
-        // one thread per staged triangle expands its record
         float v[W];
-        load32<Q>(B.sgeo, sb + t, v);
+        expand32<Q>(x.r0, x.r1, x.r2, x.r3, v);
         if constexpr (TRIAL) {
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
@@ -974,12 +1030,10 @@ __device__ __forceinline__ int stage_star_tab(const EntryBlock &B, int sb, int s
         }
 #pragma unroll
         for (int w = 0; w < W; ++w) sG[t][w] = v[w];
-        const int4 m = B.smeta[sb + t];
-        sV[t] = m;
-        sL[t] = m.w;
+        sV[t] = x.m;
+        sL[t] = x.m.w;
     }
     __syncthreads();
-    return ns;
 }
 
 // P1, FP32.  Phase 1: lane triangle against the fixed vertex star; the three
@@ -1047,17 +1101,28 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     const bool wact = (lt & ~63) < ch.y;   // wave-uniform
     const bool act = lt < ch.y;
     const int li = ch.x + (act ? lt : 0);
-    float L[n32<Q>()];
+    const float4 *lrec;
     int4 vn;
     if (B.lgeo && ch.y > 0) {
         // lane records gathered per lane position
-        vn = B.lmeta[li];
-        load32<Q>(B.lgeo, li, L);
+        vn = ldg(B.lmeta + li);
+        lrec = reinterpret_cast<const float4 *>(B.lgeo + (size_t)li * kGeo32Stride);
     } else {
-        const int tn = ch.y > 0 ? R.lane[li] : 0;   // a chunk of dofs without triangles has no lanes
-        vn = R.vtx[tn];
-        load32<Q>(R.g32, tn, L);
+        const int tn = ch.y > 0 ? ldg(R.lane + li) : 0;   // a chunk of dofs without triangles has no lanes
+        vn = ldg(R.vtx + tn);
+        lrec = reinterpret_cast<const float4 *>(R.g32 + (size_t)tn * kGeo32Stride);
     }
+    const float4 r0 = ldg(lrec), r1 = ldg(lrec + 1), r2 = ldg(lrec + 2), r3 = ldg(lrec + 3);
+    const int s0 = B.s0, s1 = B.s1;
+    StarRec first{};
+    if (t < min(kStage, s1 - s0)) first = load_star(B, s0 + t);   // the first stage
+    // the request's phase-2 fields are read once the lane and star loads are
+    // issued: waiting for them (a host-link round trip in direct batches)
+    // then overlaps those loads instead of holding them back
+    asm volatile("" ::: "memory");
+    const Phase2Req P(R);
+    float L[n32<Q>()];
+    expand32<Q>(r0, r1, r2, r3, L);
     // row requests: the lane is the trial side; its offsets scaled by -2 and
     // |o_q|^2 serve every star triangle
     float Bq[ROWFIX ? Q : 1];
@@ -1072,16 +1137,14 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
         }
     }
     float hr[3] = {0.f, 0.f, 0.f}, lr[3] = {0.f, 0.f, 0.f}, hi[3] = {0.f, 0.f, 0.f}, lo[3] = {0.f, 0.f, 0.f};
-    const int s0 = B.s0, s1 = B.s1;
     // phase 2 of this thread's first entry: its segment list, fetched while
     // phase 1 computes (after the first stage, so the stage barrier does not
     // wait for it)
     SegPrefetch pf;
     static_assert(kStage % 4 == 0, "every stage starts a new round of the lane groups");
-    for (int sb = s0; sb < s1; sb += kStage) {
-        const int ns = stage_star_tab<Q, !ROWFIX>(B, sb, s1, sG, sV, sL);
-        if (sb == s0) pf.fetch(R, ch, t);
-        if (!wact) continue;
+    // this thread's pairs with the ns staged star triangles
+    auto pairs = [&](int ns) {
+        if (!wact) return;
         for (int s = grp; s < ns; s += G.count) {
             if (share_vertex(sV[s], vn)) {
                 if (act && R.near_error) put<SYS>(R.status, 1);
@@ -1110,12 +1173,26 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
                 if constexpr (is_cplx<OP>()) two_sum_acc(hi[e], lo[e], sc * vi[e]);
             }
         }
+    };
+    if (s0 < s1) {
+        // the first stage, loaded above (its registers are free after this)
+        const int ns = min(kStage, s1 - s0);
+        put_star<Q, !ROWFIX>(first, ns, sG, sV, sL);
+        pf.fetch(P, ch, t);
+        pairs(ns);
+    }
+    for (int sb = s0 + kStage; sb < s1; sb += kStage) {
+        const int ns = min(kStage, s1 - sb);
+        StarRec x{};
+        if (t < ns) x = load_star(B, sb + t);
+        put_star<Q, !ROWFIX>(x, ns, sG, sV, sL);
+        pairs(ns);
     }
     if (act) {
 #pragma unroll
         for (int e = 0; e < 3; ++e) sP[t][e] = make_float4(hr[e], lr[e], hi[e], lo[e]);
     }
-    if (s0 == s1) pf.fetch(R, ch, t);
+    if (s0 == s1) pf.fetch(P, ch, t);
     __syncthreads();
     combine_groups_f32<is_cplx<OP>()>(G, ch.y, sP);
     for (int j = t; j < ch.w; j += kBlockLanes) {
@@ -1125,8 +1202,8 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
             g0 = pf.g0;
             g1 = pf.g1;
         } else {
-            g0 = R.seg_ptr[d];
-            g1 = R.seg_ptr[d + 1];
+            g0 = ldg(P.seg_ptr + d);
+            g1 = ldg(P.seg_ptr + d + 1);
         }
         float ar = 0.f, br = 0.f, ai = 0.f, bi = 0.f;
         auto add = [&](int pk) {
@@ -1145,13 +1222,13 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
                 if (g0 + i < g1) add(pf.seg[i]);
             g = g0 + SegPrefetch::kN;
         }
-        for (; g < g1; ++g) add(R.seg[g]);
-        const int32_t dp = R.lpos ? R.lpos[d] : d;   // lane-side output position
-        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)dp * R.sl;
+        for (; g < g1; ++g) add(ldg(P.seg + g));
+        const int32_t dp = P.lpos ? ldg(P.lpos + d) : d;   // lane-side output position
+        const int64_t o = (int64_t)B.fixed * P.sf + (int64_t)dp * P.sl;
         if constexpr (is_cplx<OP>())
-            put<SYS>(reinterpret_cast<float2 *>(R.out) + o, make_float2(ar + br, ai + bi));
+            put<SYS>(reinterpret_cast<float2 *>(P.out) + o, make_float2(ar + br, ai + bi));
         else
-            put<SYS>(reinterpret_cast<float *>(R.out) + o, ar + br);
+            put<SYS>(reinterpret_cast<float *>(P.out) + o, ar + br);
     }
 }
 
@@ -1188,6 +1265,7 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
     const bool wact = (lt & ~63) < ch.y;
     const bool act = lt < ch.y;
     const int li = ch.x + (act ? lt : 0);
+    const Phase2Req P(R);
     const int tn = ch.y > 0 ? R.lane[li] : 0;
     const int4 vn = R.vtx[tn];
     double L[n64<Q>()];
@@ -1197,7 +1275,7 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
     SegPrefetch pf;
     for (int sb = s0; sb < s1; sb += kStage) {
         const int ns = stage_star<double, n64<Q>()>(R, R.g64, kGeo64Stride, sb, s1, sG, sV, sL);
-        if (sb == s0) pf.fetch(R, ch, t);
+        if (sb == s0) pf.fetch(P, ch, t);
         if (!wact) continue;
         for (int s = grp; s < ns; s += G.count) {
             if (share_vertex(sV[s], vn)) {
@@ -1231,7 +1309,7 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
 #pragma unroll
         for (int e = 0; e < 3; ++e) sP[t][e] = make_double2(ar[e], ai[e]);
     }
-    if (s0 == s1) pf.fetch(R, ch, t);
+    if (s0 == s1) pf.fetch(P, ch, t);
     __syncthreads();
     if (G.count > 1) {
         // the groups' partials of lane t, added in group order
@@ -1261,8 +1339,8 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
             g0 = pf.g0;
             g1 = pf.g1;
         } else {
-            g0 = R.seg_ptr[d];
-            g1 = R.seg_ptr[d + 1];
+            g0 = ldg(P.seg_ptr + d);
+            g1 = ldg(P.seg_ptr + d + 1);
         }
         double xr = 0.0, xi = 0.0;
         auto add = [&](int pk) {
@@ -1277,13 +1355,13 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
                 if (g0 + i < g1) add(pf.seg[i]);
             g = g0 + SegPrefetch::kN;
         }
-        for (; g < g1; ++g) add(R.seg[g]);
-        const int32_t dp = R.lpos ? R.lpos[d] : d;   // lane-side output position
-        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)dp * R.sl;
+        for (; g < g1; ++g) add(ldg(P.seg + g));
+        const int32_t dp = P.lpos ? ldg(P.lpos + d) : d;   // lane-side output position
+        const int64_t o = (int64_t)B.fixed * P.sf + (int64_t)dp * P.sl;
         if constexpr (is_cplx<OP>())
-            put<SYS>(reinterpret_cast<double2 *>(R.out) + o, make_double2(xr, xi));
+            put<SYS>(reinterpret_cast<double2 *>(P.out) + o, make_double2(xr, xi));
         else
-            put<SYS>(reinterpret_cast<double *>(R.out) + o, xr);
+            put<SYS>(reinterpret_cast<double *>(P.out) + o, xr);
     }
 }
 
