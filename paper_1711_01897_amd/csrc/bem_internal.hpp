@@ -80,8 +80,8 @@ struct EntryBlock {  // one workgroup of entry work (64 bytes, read with one sca
     int4 chunk;            // lane side: first lane, lanes, first dof, dofs
     const float *lgeo;     // lane records gathered per lane position (or null: gather through R.lane)
     const int4 *lmeta;     // their vertex ids
-    const float *sgeo;     // P1: the mesh's star records (FP32), indexed by star entry
-    const int4 *smeta;     // their vertex ids, w = local vertex of the star's dof
+    const float *sgeo;     // P1: the mesh's star records (FP32), indexed by star entry; P0: its triangle records
+    const int4 *smeta;     // their vertex ids (P1: w = local vertex of the star's dof)
 };
 
 // Kernel variant: one compiled instantiation of the entry kernel (it serves

@@ -845,28 +845,54 @@ __device__ __forceinline__ void p0_body_f32(const ReqDev &R, const EntryBlock &B
     if ((t & ~63) >= ch.y) return;
     const bool act = t < ch.y;
     const int li = ch.x + (act ? t : 0);
+    // the lane's record: gathered per lane position for resident lane sets,
+    // else through its triangle index; the fixed triangle's from the mesh
+    // records the block names (no request field on the way)
     const int tf = B.s0;
-    const int tn = R.lane[li];
-    const int test = ROWFIX ? tf : tn, trial = ROWFIX ? tn : tf;
-    const bool adj = share_vertex(R.vtx[test], R.vtx[trial]);
+    const float *lg;
+    int4 vl;
+    if (B.lgeo) {
+        vl = ldg(B.lmeta + li);
+        lg = B.lgeo + (size_t)li * kGeo32Stride;
+    } else {
+        const int tn = ldg(R.lane + li);
+        vl = ldg(R.vtx + tn);
+        lg = R.g32 + (size_t)tn * kGeo32Stride;
+    }
+    const int4 vf = ldg(B.smeta + tf);
+    const float4 *fp = reinterpret_cast<const float4 *>(B.sgeo + (size_t)tf * kGeo32Stride);
+    const float4 *lp = reinterpret_cast<const float4 *>(lg);
+    // both records are loaded before the adjacency test (a vertex-sharing
+    // pair is rare and its records are valid), and the request's fields
+    // after them: the host-link round trip for those overlaps the loads
+    const float4 f0 = ldg(fp), f1 = ldg(fp + 1), f2 = ldg(fp + 2), f3 = ldg(fp + 3);
+    const float4 l0 = ldg(lp), l1 = ldg(lp + 1), l2 = ldg(lp + 2), l3 = ldg(lp + 3);
+    asm volatile("" ::: "memory");
+    const float kf = (float)R.k;
+    const double kk = R.kk;
+    void *const out = R.out;
+    const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)(ch.z + t) * R.sl;
+    const bool adj = share_vertex(vf, vl);
     float vr = 0.f, vi = 0.f;
     if (!adj) {
-        float T[n32<Q>()], S[n32<Q>()];
-        load32<Q>(R.g32, test, T);
-        load32<Q>(R.g32, trial, S);
-        pair_p0_f32<OP, Q>(T, S, (float)R.k, R.kk, vr, vi);
-        const float sc = T[3] * S[3] * kInv4PiF;
+        float F[n32<Q>()], L[n32<Q>()];
+        expand32<Q>(f0, f1, f2, f3, F);
+        expand32<Q>(l0, l1, l2, l3, L);
+        if constexpr (ROWFIX)
+            pair_p0_f32<OP, Q>(F, L, kf, kk, vr, vi);
+        else
+            pair_p0_f32<OP, Q>(L, F, kf, kk, vr, vi);
+        const float sc = F[3] * L[3] * kInv4PiF;
         vr *= sc;
         vi *= sc;
     } else if (act && R.near_error) {
         put<SYS>(R.status, 1);
     }
     if (act) {
-        const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)(ch.z + t) * R.sl;
         if constexpr (is_cplx<OP>())
-            put<SYS>(reinterpret_cast<float2 *>(R.out) + o, make_float2(vr, vi));
+            put<SYS>(reinterpret_cast<float2 *>(out) + o, make_float2(vr, vi));
         else
-            put<SYS>(reinterpret_cast<float *>(R.out) + o, vr);
+            put<SYS>(reinterpret_cast<float *>(out) + o, vr);
     }
 }
 
