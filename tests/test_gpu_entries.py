@@ -310,3 +310,45 @@ def test_p1_chunk_edge_cases():
     single = bem.eval_entries(mesh, bem.LAPLACE_SLP, bem.P1, 0.0, [3], [120], prec=bem.FP32)
     assert np.all(got == single[0, 0])
     mesh.destroy()
+
+
+def _bipyramid(n, height=3.0):
+    """Closed double cone: n rim vertices on the unit circle and two apexes at
+    z = +-height, so both apex stars hold n triangles (outward winding)."""
+    phi = 2.0 * np.pi * np.arange(n) / n
+    xyz = np.vstack([np.stack([np.cos(phi), np.sin(phi), np.zeros(n)], axis=1), [[0.0, 0.0, height]],
+                     [[0.0, 0.0, -height]]])
+    top, bot = n, n + 1
+    tri = []
+    for i in range(n):
+        j = (i + 1) % n
+        tri.append([i, j, top])
+        tri.append([j, i, bot])
+    return xyz, np.array(tri, dtype=np.int32)
+
+
+@pytest.mark.parametrize("n", [9, 20])
+def test_p1_high_valence_stars_span_stages(n):
+    """A P1 dof whose star has more triangles than one staging round holds
+    (8): the apexes of a double cone with 9 and 20 rim vertices.  The row
+    request stages the apex star on the test side, the transposed request on
+    the trial side; both precisions, four operators, against the oracle with
+    vertex-sharing pairs skipped on both sides."""
+    xyz, tri = _bipyramid(n)
+    mesh = bem.mesh_create(xyz, tri, 6)
+    om = O.OracleMesh(xyz, tri, 6)
+    apex = np.array([n, n + 1], dtype=np.int32)
+    cols = np.arange(n + 2, dtype=np.int32)
+    try:
+        for op in (bem.LAPLACE_SLP, bem.LAPLACE_DLP, bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP):
+            k = 2.0 if op in (bem.HELMHOLTZ_SLP, bem.HELMHOLTZ_DLP) else 0.0
+            ref = om.entries(op, O.P1, k, apex, cols, near=O.NEAR_SKIP)
+            refT = om.entries(op, O.P1, k, cols, apex, near=O.NEAR_SKIP)
+            assert np.max(np.abs(ref)) > 0 and np.max(np.abs(refT)) > 0
+            for prec in (bem.FP64, bem.FP32):
+                got = bem.eval_entries(mesh, op, bem.P1, k, apex, cols, prec=prec, near=bem.NEAR_SKIP)
+                gotT = bem.eval_entries(mesh, op, bem.P1, k, cols, apex, prec=prec, near=bem.NEAR_SKIP)
+                assert normwise(got.astype(ref.dtype), ref) <= tol(op, prec), (n, op, prec)
+                assert normwise(gotT.astype(refT.dtype), refT) <= tol(op, prec), (n, op, prec)
+    finally:
+        mesh.destroy()
