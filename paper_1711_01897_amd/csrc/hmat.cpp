@@ -21,6 +21,7 @@
 #include <mutex>
 #include <new>
 #include <sys/mman.h>
+#include <unistd.h>
 
 #include "aca.hpp"
 #include <unordered_map>
@@ -33,11 +34,23 @@ namespace bem {
 
 // Factor and dense-block values live in large blocks bump-allocated per
 // worker instead of three heap vectors per leaf: assembly makes no
-// allocator call per block, and destroying an H-matrix hands a few blocks
-// back to a process-wide pool (up to kPoolKeep of them are kept, so
-// repeated assemblies reuse memory that is already mapped).
+// allocator call per block, and destroying an H-matrix (or running a plan
+// again) hands its blocks back to a process-wide pool, which keeps them up
+// to an eighth of physical memory (at least 1 GiB): repeated assemblies and
+// plan runs then reuse memory that is already mapped instead of faulting in
+// and zeroing new pages (a run over a quarter of the 1M-triangle cylinder's
+// blocks holds ~6 GB of FP64 factors).
 constexpr size_t kPoolDoubles = size_t(1) << 19;   // 4 MiB per block
-constexpr size_t kPoolKeep = 256;                  // at most 1 GiB retained
+
+size_t pool_keep_blocks()
+{
+    static const size_t keep = [] {
+        const long pages = sysconf(_SC_PHYS_PAGES), psz = sysconf(_SC_PAGE_SIZE);
+        const double eighth = pages > 0 && psz > 0 ? (double)pages * (double)psz / 8.0 : 0.0;
+        return std::max<size_t>(256, (size_t)(eighth / (double)(kPoolDoubles * sizeof(double))));
+    }();
+    return keep;
+}
 
 struct ValueBlock {
     double *p = nullptr;
@@ -68,7 +81,7 @@ public:
     {
         std::lock_guard<std::mutex> g(mu_);
         for (const ValueBlock &b : v) {
-            if (b.n == kPoolDoubles && free_.size() < kPoolKeep)
+            if (b.n == kPoolDoubles && free_.size() < pool_keep_blocks())
                 free_.push_back(b.p);
             else if (b.n == kPoolDoubles)
                 std::free(b.p);
