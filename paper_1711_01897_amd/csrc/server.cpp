@@ -528,9 +528,10 @@ public:
     }
 
     // Events skip the system-scope fence (a device cache writeback and
-    // invalidation per event): results reach the host through uncached
-    // stores to coherent memory, which precede the batch event's signal, and
-    // timing events must not charge such cache work to the timed kernel.
+    // invalidation per event): results are stored into host-coherent
+    // (fine-grained) staging, which the device keeps coherent with the host
+    // without that flush once the storing kernel has completed, and timing
+    // events must not charge such cache work to the timed kernel.
     hipEvent_t get_event()
     {
         std::lock_guard<std::mutex> g(ev_mu);
