@@ -79,7 +79,8 @@ struct EntryBlock {  // one workgroup of entry work (64 bytes, read with one sca
     int32_t s0, s1;        // P1: the fixed dof's star, entries [s0, s1) of the mesh star table; P0: s0 = the fixed triangle
     int4 chunk;            // lane side: first lane, lanes, first dof, dofs
     const float *lgeo;     // lane records gathered per lane position (or null: gather through R.lane)
-    const int4 *lmeta;     // their vertex ids
+    const int4 *lmeta;     // their vertex ids; null with lgeo set: the sides are separated (no vertex-sharing
+                           // pair can occur, the kernels skip the test)
     const float *sgeo;     // P1: the mesh's star records (FP32), indexed by star entry; P0: its triangle records
     const int4 *smeta;     // their vertex ids (P1: w = local vertex of the star's dof)
 };
@@ -392,6 +393,10 @@ struct Request {
     std::vector<int32_t> fix;   // fixed side: P0 triangles; P1 star ranges [s0, s1) per fixed dof (2 each)
     LaneSet own;                       // lane side, when not external
     const LaneRef *ext = nullptr;      // device-resident lane side
+    // the supports of the fixed and lane sides have a positive distance (the
+    // blocks of an admissible partition): no pair can share a vertex, so the
+    // kernels neither load vertex ids for the lanes nor test for sharing
+    bool separated = false;
     int64_t nfix = 0, nlane = 0, nchunk = 0, ndistinct = 0;
     int64_t nstar = 0;          // P1: triangles over the fixed dofs' stars
     size_t elem_bytes = 0;

@@ -849,17 +849,18 @@ __device__ __forceinline__ void p0_body_f32(const ReqDev &R, const EntryBlock &B
     // else through its triangle index; the fixed triangle's from the mesh
     // records the block names (no request field on the way)
     const int tf = B.s0;
+    const bool sep = B.lgeo && !B.lmeta;   // separated sides: no vertex-sharing pair (workgroup-uniform)
     const float *lg;
-    int4 vl;
+    int4 vl = make_int4(-1, -1, -1, -1);
     if (B.lgeo) {
-        vl = ldg(B.lmeta + li);
+        if (!sep) vl = ldg(B.lmeta + li);
         lg = B.lgeo + (size_t)li * kGeo32Stride;
     } else {
         const int tn = ldg(R.lane + li);
         vl = ldg(R.vtx + tn);
         lg = R.g32 + (size_t)tn * kGeo32Stride;
     }
-    const int4 vf = ldg(B.smeta + tf);
+    const int4 vf = sep ? make_int4(-2, -2, -2, -2) : ldg(B.smeta + tf);
     const float4 *fp = reinterpret_cast<const float4 *>(B.sgeo + (size_t)tf * kGeo32Stride);
     const float4 *lp = reinterpret_cast<const float4 *>(lg);
     // both records are loaded before the adjacency test (a vertex-sharing
@@ -872,7 +873,7 @@ __device__ __forceinline__ void p0_body_f32(const ReqDev &R, const EntryBlock &B
     const double kk = R.kk;
     void *const out = R.out;
     const int64_t o = (int64_t)B.fixed * R.sf + (int64_t)(ch.z + t) * R.sl;
-    const bool adj = share_vertex(vf, vl);
+    const bool adj = !sep && share_vertex(vf, vl);
     float vr = 0.f, vi = 0.f;
     if (!adj) {
         float F[n32<Q>()], L[n32<Q>()];
@@ -923,7 +924,8 @@ __device__ __forceinline__ void p0_body_f64(const ReqDev &R, const EntryBlock &B
     const int tf = B.s0;
     const int tn = R.lane[li];
     const int test = ROWFIX ? tf : tn, trial = ROWFIX ? tn : tf;
-    const bool adj = share_vertex(R.vtx[test], R.vtx[trial]);
+    const bool sep = B.lgeo && !B.lmeta;   // separated sides: no vertex-sharing pair (workgroup-uniform)
+    const bool adj = !sep && share_vertex(R.vtx[test], R.vtx[trial]);
     double vr = 0.0, vi = 0.0;
     if (!adj) {
         double T[n64<Q>()], S[n64<Q>()];
@@ -1127,11 +1129,12 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     const bool wact = (lt & ~63) < ch.y;   // wave-uniform
     const bool act = lt < ch.y;
     const int li = ch.x + (act ? lt : 0);
+    const bool sep = B.lgeo && !B.lmeta;   // separated sides: no vertex-sharing pair (workgroup-uniform)
     const float4 *lrec;
-    int4 vn;
+    int4 vn = make_int4(-1, -1, -1, -1);
     if (B.lgeo && ch.y > 0) {
         // lane records gathered per lane position
-        vn = ldg(B.lmeta + li);
+        if (!sep) vn = ldg(B.lmeta + li);
         lrec = reinterpret_cast<const float4 *>(B.lgeo + (size_t)li * kGeo32Stride);
     } else {
         const int tn = ch.y > 0 ? ldg(R.lane + li) : 0;   // a chunk of dofs without triangles has no lanes
@@ -1172,7 +1175,7 @@ __device__ __forceinline__ void p1_body_f32(const ReqDev &R, const EntryBlock &B
     auto pairs = [&](int ns) {
         if (!wact) return;
         for (int s = grp; s < ns; s += G.count) {
-            if (share_vertex(sV[s], vn)) {
+            if (!sep && share_vertex(sV[s], vn)) {
                 if (act && R.near_error) put<SYS>(R.status, 1);
                 continue;
             }
@@ -1292,8 +1295,9 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
     const bool act = lt < ch.y;
     const int li = ch.x + (act ? lt : 0);
     const Phase2Req P(R);
+    const bool sep = B.lgeo && !B.lmeta;   // separated sides: no vertex-sharing pair (workgroup-uniform)
     const int tn = ch.y > 0 ? R.lane[li] : 0;
-    const int4 vn = R.vtx[tn];
+    const int4 vn = sep ? make_int4(-1, -1, -1, -1) : R.vtx[tn];
     double L[n64<Q>()];
     load64<Q>(R.g64, tn, L);
     double ar[3] = {0.0, 0.0, 0.0}, ai[3] = {0.0, 0.0, 0.0};
@@ -1304,7 +1308,7 @@ __device__ __forceinline__ void p1_body_f64(const ReqDev &R, const EntryBlock &B
         if (sb == s0) pf.fetch(P, ch, t);
         if (!wact) continue;
         for (int s = grp; s < ns; s += G.count) {
-            if (share_vertex(sV[s], vn)) {
+            if (!sep && share_vertex(sV[s], vn)) {
                 if (act && R.near_error) put<SYS>(R.status, 1);
                 continue;
             }

@@ -532,6 +532,7 @@ int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag, WorkerT
     r.tag = tag;
     if (!s.adm) {
         r.near = C.dense_near;
+        r.separated = false;
         r.rows.assign(C.h->rows(L), C.h->rows(L) + L.m);
         r.cols.assign(C.h->cols(L), C.h->cols(L) + L.n);
         r.nrows = (int64_t)r.rows.size();
@@ -549,6 +550,9 @@ int prepare_slot(AssemblyCtx &C, Slot<T> &s, DoneQueue &dq, int64_t tag, WorkerT
         w.dense_entries += r.entries();
     } else {
         r.near = BEM_NEAR_ERROR;
+        // admissible: the support boxes of the two clusters are apart, so no
+        // triangle of one shares a vertex with a triangle of the other
+        r.separated = true;
         const Block &bk = C.h->part.blocks[s.leaf];
         if (s.core.phase == AcaCore<T>::NEED_ROW)
             expand_single_fixed(r, C.h->rows(L)[s.core.i], 1, &(*C.lanes)[bk.sigma]);

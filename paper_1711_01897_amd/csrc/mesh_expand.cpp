@@ -832,7 +832,7 @@ int64_t write_blocks(const Request &r, int32_t ri, EntryBlock *out)
             b.s1 = s1;
             b.chunk = make_int4(ch[4 * c], ch[4 * c + 1], ch[4 * c + 2], ch[4 * c + 3]);
             b.lgeo = lgeo;
-            b.lmeta = lmeta;
+            b.lmeta = r.separated ? nullptr : lmeta;
             // the fixed side's records: P1 star records per star entry, P0
             // the mesh's triangle records
             b.sgeo = r.space != BEM_P0 ? m.d_sgeo : m.d_g32;
