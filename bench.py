@@ -86,7 +86,7 @@ def parse():
                          "H-matrix of the Helmholtz single layer, P0, on the 262,186-triangle 10:1:1 spheroid, "
                          "complex64 vs complex128; mix: served Helmholtz single layer on 8 meshes x 4 wavenumbers; "
                          "sphere3: the dense P0 Laplace single layer of the level-3 icosphere, FP64")
-    ap.add_argument("--workers", type=int, default=None, help="host ACA workers (cylinder 32, icosphere6 10)")
+    ap.add_argument("--workers", type=int, default=None, help="host ACA workers (cylinder and mix 32, icosphere6 12, others 10)")
     ap.add_argument("--blocks-per-worker", type=int, default=None,
                     help="ACA blocks each worker keeps in flight (cylinder 128, icosphere6 180)")
     ap.add_argument("--load", type=float, default=1.25,
@@ -132,7 +132,7 @@ def parse():
     ap.add_argument("--traffic-copy-bytes", type=int, default=256 << 20)
     a = ap.parse_args()
     if a.workers is None:
-        a.workers = 32 if a.workload in ("cylinder", "mix") else 10
+        a.workers = {"cylinder": 32, "mix": 32, "icosphere6": 12}.get(a.workload, 10)
     if a.blocks_per_worker is None:
         a.blocks_per_worker = 128 if a.workload in ("cylinder", "mix") else 180
     return a
